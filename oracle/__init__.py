@@ -1,0 +1,330 @@
+"""FP64 CPU oracle for the NVGS per-frame path (test infrastructure only).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  It never imports the product package
+and the product never imports it; the two share only the seeded inputs of
+``synth``.
+
+The heavy loops live in ``nvgs_oracle.cpp`` (plain C++17, FP64, no FMA
+contraction, OpenMP over independent outputs).  This file marshals the
+``synth`` containers into flat arrays and strings the steps together in the
+order of the method (Sec. 3.3): frustum cull -> MLP query -> compaction of the
+survivors -> projection -> (tile, depth, id) ordering -> compositing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+import subprocess
+from typing import List, Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "nvgs_oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+REC = 16  # doubles per projected splat record (see nvgs_oracle.cpp)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with g++ (no fast-math, no FMA contraction)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-fopenmp", "-ffp-contract=off",
+                               "-shared", "-fPIC", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = C.CDLL(_LIB)
+        dp = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+        fp = np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS")
+        u8 = np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")
+        i32 = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+        i64 = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
+        vp = C.c_void_p
+        L.orc_encode.argtypes = [dp, C.c_int, C.c_int, dp]
+        L.orc_encode_batch.argtypes = [dp, C.c_int64, C.c_int, C.c_int, dp]
+        L.orc_mlp_forward.argtypes = [dp, C.c_int, C.c_int, dp, C.c_int64, dp, vp, vp]
+        L.orc_sh_basis.argtypes = [dp, C.c_int, dp]
+        L.orc_local_camera.argtypes = [dp, dp, C.c_double, C.c_double, dp]
+        L.orc_query.argtypes = [C.c_int64, fp, dp, dp, dp, C.c_int, C.c_int, C.c_double, C.c_double,
+                                C.c_double, C.c_double, C.c_double, C.c_int, u8, dp, vp]
+        L.orc_project.argtypes = [C.c_int64, i64, C.c_int64, fp, fp, fp, fp, fp, C.c_int, dp, dp, dp, i32]
+        L.orc_render.argtypes = [C.c_int64, dp, i32, dp, C.c_int, dp, dp, vp, vp, vp, vp, vp, C.c_int64]
+        L.orc_render.restype = C.c_int64
+        L.orc_render_brute.argtypes = [C.c_int64, dp, dp, dp, dp, vp]
+        L.orc_bce_backward.argtypes = [dp, C.c_int, C.c_int, dp, dp, vp, C.c_int64, dp, vp]
+        L.orc_bce_backward.restype = C.c_double
+        L.orc_adam_step.argtypes = [C.c_int64, dp, dp, dp, dp, C.c_int64, C.c_double, C.c_double,
+                                    C.c_double, C.c_double]
+        L.orc_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
+        L.orc_splitmix64.restype = C.c_uint64
+        _lib = L
+    return _lib
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+# ----------------------------------------------------------------------------
+# records
+# ----------------------------------------------------------------------------
+def inst_array(inst) -> np.ndarray:
+    """Instance record; every field passes through float32, the precision in
+    which instances are handed over, then is widened exactly to FP64."""
+    return _f64(np.concatenate([np.asarray(inst.R, np.float32).ravel(), np.float32([inst.s]),
+                                np.asarray(inst.t, np.float32).ravel()]).astype(np.float32))
+
+
+def cam_array(cam) -> np.ndarray:
+    """Camera record (float32 fields widened exactly to FP64)."""
+    return _f64(np.concatenate([np.asarray(cam.pos, np.float32).ravel(),
+                                np.asarray(cam.R, np.float32).ravel(),
+                                np.float32([cam.fovy, cam.width, cam.height, cam.near])]).astype(np.float32))
+
+
+# ----------------------------------------------------------------------------
+# single steps
+# ----------------------------------------------------------------------------
+def encode(x: np.ndarray, bands: int = 6) -> np.ndarray:
+    x = _f64(x).ravel()
+    out = np.zeros(x.size * bands * 2)
+    lib().orc_encode(x, x.size, bands, out)
+    return out
+
+
+def mlp_forward(params, width: int, X: np.ndarray, want_pre: bool = False):
+    """Logits of the packed MLP for inputs X [B, in_dim] (FP64)."""
+    X = _f64(X)
+    B, in_dim = X.shape
+    z = np.zeros(B)
+    sc = np.zeros(B)
+    pre = np.zeros((B, 3 * width)) if want_pre else None
+    lib().orc_mlp_forward(_f64(params), width, in_dim, X, B, z, _ptr(pre), _ptr(sc))
+    return (z, sc, pre) if want_pre else (z, sc)
+
+
+def sh_basis(d, degree: int = 3) -> np.ndarray:
+    Y = np.zeros(16)
+    lib().orc_sh_basis(_f64(d), degree, Y)
+    return Y[: (degree + 1) ** 2]
+
+
+def local_camera(inst, cam, train_focal: float, d_max: float = 0.0) -> np.ndarray:
+    out = np.zeros(3)
+    lib().orc_local_camera(inst_array(inst), cam_array(cam), train_focal, d_max, out)
+    return out
+
+
+def mlp_inputs(asset, gidx: np.ndarray, cam_local: np.ndarray) -> np.ndarray:
+    """Encoded MLP inputs (FP64) for Gaussians gidx seen from cam_local [.., 3]."""
+    spec = asset.mlp
+    mu = asset.mean[:, gidx].T.astype(np.float64) * spec.mean_scale
+    cl = np.broadcast_to(np.asarray(cam_local, np.float64) * spec.cam_scale, mu.shape)
+    x = np.ascontiguousarray(np.concatenate([mu, cl], axis=1))
+    out = np.zeros((len(x), 12 * spec.bands))
+    if len(x):
+        lib().orc_encode_batch(x, len(x), 6, spec.bands, out)
+    return out
+
+
+def bce_backward(params, width: int, X, y, w=None, want_dx: bool = False):
+    P = _f64(params)
+    X = _f64(X)
+    B, in_dim = X.shape
+    dP = np.zeros_like(P)
+    dX = np.zeros_like(X) if want_dx else None
+    loss = lib().orc_bce_backward(P, width, in_dim, X, _f64(y), _ptr(None if w is None else _f64(w)),
+                                  B, dP, _ptr(dX))
+    return (loss, dP, dX) if want_dx else (loss, dP)
+
+
+def adam_step(p, g, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """In-place Adam step on float64 arrays p, m, v with gradient g."""
+    lib().orc_adam_step(p.size, p, _f64(g), m, v, t, lr, b1, b2, eps)
+
+
+def splitmix64(seed: int, i: int) -> int:
+    return int(lib().orc_splitmix64(seed, i))
+
+
+# ----------------------------------------------------------------------------
+# the per-frame path
+# ----------------------------------------------------------------------------
+def query(scene, use_mlp: bool = True, cams=None, want_margin: bool = False):
+    """Cull + MLP query for every (camera, instance, Gaussian).
+
+    Returns state [C, P] (0 frustum-culled, 1 MLP-culled, 2 kept),
+    logits [C, P] (NaN where not queried) and optionally margins [C, P]."""
+    cams = scene.cameras if cams is None else cams
+    off = scene.pair_offsets()
+    P = int(off[-1])
+    state = np.zeros((len(cams), P), np.uint8)
+    logit = np.full((len(cams), P), np.nan)
+    margin = np.zeros((len(cams), P)) if want_margin else None
+    params64 = [_f64(a.mlp.params) for a in scene.assets]
+    L = lib()
+    for k, cam in enumerate(cams):
+        ca = cam_array(cam)
+        for i, inst in enumerate(scene.instances):
+            a = scene.assets[inst.asset]
+            sp = a.mlp
+            n = a.n
+            st = np.zeros(n, np.uint8)
+            lg = np.zeros(n)
+            mg = np.zeros(n) if want_margin else None
+            L.orc_query(n, np.ascontiguousarray(a.mean), inst_array(inst), ca, params64[inst.asset],
+                        sp.width, sp.bands, sp.mean_scale, sp.cam_scale, sp.train_focal, sp.d_min,
+                        sp.d_max, int(use_mlp), st, lg, _ptr(mg))
+            state[k, off[i]:off[i + 1]] = st
+            logit[k, off[i]:off[i + 1]] = lg
+            if want_margin:
+                margin[k, off[i]:off[i + 1]] = mg
+    return (state, logit, margin) if want_margin else (state, logit)
+
+
+def compact(state: np.ndarray) -> List[np.ndarray]:
+    """Compaction: per camera, the kept pair indices in increasing (instance, Gaussian)
+    order; the splat id is the running index over cameras."""
+    return [np.flatnonzero(state[k] == 2).astype(np.int64) for k in range(state.shape[0])]
+
+
+def pair_to_instance(scene, pairs: np.ndarray):
+    off = scene.pair_offsets()
+    inst = np.searchsorted(off, pairs, side="right") - 1
+    return inst.astype(np.int64), (pairs - off[inst]).astype(np.int64)
+
+
+def project(scene, cam, pairs: np.ndarray):
+    """Projection + footprint for the kept pairs of one camera, in the given order."""
+    inst_of, g_of = pair_to_instance(scene, pairs)
+    m = len(pairs)
+    rec = np.zeros((m, REC))
+    prect = np.zeros((m, 4), np.int32)
+    L = lib()
+    ca = cam_array(cam)
+    for i in np.unique(inst_of):
+        sel = np.flatnonzero(inst_of == i)
+        inst = scene.instances[int(i)]
+        a = scene.assets[inst.asset]
+        r = np.zeros((len(sel), REC))
+        pr = np.zeros((len(sel), 4), np.int32)
+        L.orc_project(len(sel), np.ascontiguousarray(g_of[sel]), a.n, np.ascontiguousarray(a.mean),
+                      np.ascontiguousarray(a.scale), np.ascontiguousarray(a.quat),
+                      np.ascontiguousarray(a.opacity), np.ascontiguousarray(a.sh), a.sh_degree,
+                      inst_array(inst), ca, r, pr)
+        rec[sel] = r
+        prect[sel] = pr
+    return rec, prect
+
+
+def render_camera(rec, prect, cam, tile: int, bg=(0.0, 0.0, 0.0), contrib=None, reached=None,
+                  want_margin: bool = True, want_order: bool = False):
+    """Binning + compositing for one camera.  contrib/reached arrays (length m) are updated
+    in place when given."""
+    m = rec.shape[0]
+    H, W = cam.height, cam.width
+    img = np.zeros((H, W, 3))
+    tf = np.zeros((H, W))
+    mg = np.zeros((H, W, 2)) if want_margin else None
+    cap = 0
+    order = None
+    if want_order:
+        cap = int(np.sum(_tiles_per_rect(prect, tile))) if m else 0
+        order = np.zeros((max(cap, 1), 2), np.int64)
+    n = lib().orc_render(m, _f64(rec), np.ascontiguousarray(prect, np.int32), cam_array(cam), tile,
+                         _f64(bg), img, _ptr(tf), _ptr(contrib), _ptr(reached), _ptr(mg), _ptr(order), cap)
+    out = {"image": img, "T": tf, "entries": int(n)}
+    if want_margin:
+        out["margin"] = mg
+    if want_order:
+        out["order"] = order[:n]
+    return out
+
+
+def render_brute(rec, cam, bg=(0.0, 0.0, 0.0)):
+    H, W = cam.height, cam.width
+    img = np.zeros((H, W, 3))
+    tf = np.zeros((H, W))
+    lib().orc_render_brute(rec.shape[0], _f64(rec), cam_array(cam), _f64(bg), img, _ptr(tf))
+    return img, tf
+
+
+def _tiles_per_rect(prect, tile):
+    pr = np.asarray(prect, np.int64)
+    empty = (pr[:, 0] > pr[:, 1]) | (pr[:, 2] > pr[:, 3])
+    nx = pr[:, 1] // tile - pr[:, 0] // tile + 1
+    ny = pr[:, 3] // tile - pr[:, 2] // tile + 1
+    return np.where(empty, 0, nx * ny)
+
+
+def frame(scene, use_mlp: bool = True, tile: Optional[int] = None, record: bool = False,
+          want_margin: bool = True):
+    """The whole per-frame path for every camera of the scene."""
+    tile = scene.tile if tile is None else tile
+    state, logit = query(scene, use_mlp=use_mlp)
+    kept = compact(state)
+    out = {"state": state, "logit": logit, "kept": kept, "images": [], "T": [], "margin": [],
+           "rec": [], "prect": [], "contrib": [], "reached": [], "entries": []}
+    for k, cam in enumerate(scene.cameras):
+        rec, prect = project(scene, cam, kept[k])
+        cb = np.zeros(len(kept[k])) if record else None
+        rc = np.zeros(len(kept[k]), np.uint8) if record else None
+        r = render_camera(rec, prect, cam, tile, scene.bg, cb, rc, want_margin=want_margin)
+        out["images"].append(r["image"])
+        out["T"].append(r["T"])
+        out["margin"].append(r.get("margin"))
+        out["rec"].append(rec)
+        out["prect"].append(prect)
+        out["contrib"].append(cb)
+        out["reached"].append(rc)
+        out["entries"].append(r["entries"])
+    return out
+
+
+def labels(asset, views, threshold: float = 1.0 / 255.0, tile: int = 16) -> np.ndarray:
+    """Labels (Sec. 3.1): label[v, g] = 1 iff Gaussian g's largest contribution alpha*T over
+    the pixels of view v exceeds the threshold (single identity instance,
+    frustum culling only)."""
+    from synth import Scene, identity_instance  # inputs only
+    sc = Scene(assets=[asset], instances=[identity_instance(0)], cameras=list(views), tile=tile)
+    state, _ = query(sc, use_mlp=False)
+    kept = compact(state)
+    lab = np.zeros((len(views), asset.n), np.uint8)
+    for k, cam in enumerate(views):
+        rec, prect = project(sc, cam, kept[k])
+        cb = np.zeros(len(kept[k]))
+        render_camera(rec, prect, cam, tile, (0.0, 0.0, 0.0), cb, None, want_margin=False)
+        lab[k, kept[k]] = (cb > threshold).astype(np.uint8)
+    return lab
+
+
+# ----------------------------------------------------------------------------
+# metrics
+# ----------------------------------------------------------------------------
+def psnr(a: np.ndarray, b: np.ndarray, cap: float = 100.0) -> float:
+    mse = float(np.mean((np.asarray(a, np.float64) - np.asarray(b, np.float64)) ** 2))
+    if mse == 0.0:
+        return cap
+    return min(cap, 10.0 * math.log10(1.0 / mse))
+
+
+def flip_rate(keep_a: np.ndarray, keep_b: np.ndarray, in_frustum: np.ndarray) -> float:
+    n = int(np.sum(in_frustum))
+    if n == 0:
+        return 0.0
+    return float(np.sum((keep_a != keep_b) & in_frustum)) / n

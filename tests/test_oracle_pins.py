@@ -1,0 +1,603 @@
+"""Pins of the FP64 oracle against things other than itself: closed forms,
+library routines, invariants and brute force.  CPU only."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from synth import Camera, Instance, Scene
+
+pytestmark = pytest.mark.filterwarnings("ignore::DeprecationWarning")
+
+
+def axis_camera(W=64, H=64, fovy_deg=60.0, near=0.2):
+    """Camera at the origin looking along +z with x right and y down."""
+    return Camera(pos=np.zeros(3, np.float32), R=np.eye(3, dtype=np.float32),
+                  fovy=math.radians(fovy_deg), width=W, height=H, near=near)
+
+
+def one_gaussian_asset(mean, scale, quat=(1, 0, 0, 0), opacity=0.8, rgb=(0.2, 0.5, 0.9), degree=0):
+    n = 1
+    a = synth.Asset(mean=np.asarray(mean, np.float32).reshape(3, n),
+                    scale=np.asarray(scale, np.float32).reshape(3, n),
+                    quat=np.asarray(quat, np.float32).reshape(4, n),
+                    opacity=np.asarray([opacity], np.float32),
+                    sh=((np.asarray(rgb, np.float64) - 0.5) / (0.5 / math.sqrt(math.pi))).astype(np.float32).reshape(3, n),
+                    sh_degree=degree, mlp=synth.MLPSpec(params=synth.mlp_params(8, synth.rng(0)), width=8))
+    return a
+
+
+def project_one(orc, asset, cam, inst=None):
+    inst = inst or synth.identity_instance(0)
+    sc = Scene(assets=[asset], instances=[inst], cameras=[cam])
+    rec, prect = orc.project(sc, cam, np.zeros(1, np.int64))
+    return rec[0], prect[0]
+
+
+# ---------------------------------------------------------------------------
+# encoding (Sec. 3.2 counting) and MLP
+# ---------------------------------------------------------------------------
+def test_encoding_count_matches_paper(orc):
+    # the paper counts five bands over the six scalars as sixty values
+    assert orc.encode(np.zeros(6), bands=5).size == 60
+    assert orc.encode(np.zeros(6), bands=6).size == 72
+
+
+def test_encoding_angle_doubling(orc):
+    x = np.random.default_rng(1).uniform(-1.3, 1.3, 6)
+    e = orc.encode(x, bands=6).reshape(6, 6, 2)
+    # sin(2a) = 2 sin a cos a, cos(2a) = 1 - 2 sin^2 a, band 0 is sin/cos(pi x)
+    np.testing.assert_allclose(e[:, 0, 0], np.sin(np.pi * x), atol=1e-15)
+    np.testing.assert_allclose(e[:, 0, 1], np.cos(np.pi * x), atol=1e-15)
+    for k in range(5):
+        np.testing.assert_allclose(e[:, k + 1, 0], 2 * e[:, k, 0] * e[:, k, 1], atol=1e-12)
+        np.testing.assert_allclose(e[:, k + 1, 1], 1 - 2 * e[:, k, 0] ** 2, atol=1e-12)
+    z = orc.encode(np.zeros(2), bands=3).reshape(2, 3, 2)
+    assert np.all(z[..., 0] == 0) and np.all(z[..., 1] == 1)
+
+
+def _numpy_mlp(params, W, X):
+    off = 0
+    h = X
+    fan = X.shape[1]
+    for _ in range(3):
+        Wl = params[off:off + W * fan].reshape(W, fan); off += W * fan
+        bl = params[off:off + W]; off += W
+        h = np.maximum(h @ Wl.T + bl, 0.0)
+        fan = W
+    wo = params[off:off + W]; bo = params[off + W]
+    return h @ wo + bo
+
+
+@pytest.mark.parametrize("W", [64, 128])
+def test_mlp_equals_numpy_matmul_chain(orc, W):
+    g = np.random.default_rng(W)
+    p = synth.mlp_params(W, synth.rng(W)).astype(np.float64)
+    assert p.size == synth.mlp_param_count(W) == {64: 13057, 128: 42497}[W]
+    X = g.uniform(-1, 1, (300, 72))
+    z, _ = orc.mlp_forward(p, W, X)
+    ref = _numpy_mlp(p, W, X)
+    np.testing.assert_allclose(z, ref, rtol=1e-12, atol=1e-12)
+
+
+def test_mlp_bias_only_is_constant(orc):
+    W = 16
+    p = synth.mlp_params(W, synth.rng(3)).astype(np.float64)
+    n1 = 72 * W
+    p[:n1] = 0
+    p[n1 + W:n1 + W + W * W] = 0
+    o = n1 + W + W * W + W
+    p[o:o + W * W] = 0
+    b3 = p[o + W * W:o + W * W + W]
+    wo = p[-W - 1:-1]
+    X = np.random.default_rng(0).uniform(-1, 1, (50, 72))
+    z, _ = orc.mlp_forward(p, W, X)
+    np.testing.assert_allclose(z, np.dot(wo, np.maximum(b3, 0)) + p[-1], rtol=0, atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# scene transform, Eq. 2 and the frustum
+# ---------------------------------------------------------------------------
+def test_local_camera_eq2_fov_and_scale(orc):
+    inst = Instance(asset=0, R=synth.yaw(0.7), s=2.0, t=np.array([3.0, -1.0, 0.5], np.float32))
+    cam = synth.camera((10.0, 4.0, 6.0), fovy_deg=20.0)
+    f_t = 1.0 / math.tan(math.radians(30.0))  # trained at 60 deg
+    cl = orc.local_camera(inst, cam, f_t)
+    d_r = np.linalg.norm(np.asarray(cam.pos, np.float64) - inst.t)
+    # Eq. 2: d_t = d_r (f_t / f_r) / s with f = 1 / tan(fov / 2)
+    d_t = d_r * (f_t * math.tan(math.radians(10.0))) / 2.0
+    # (the float32 rotation is orthonormal to ~1e-7)
+    assert abs(np.linalg.norm(cl) - d_t) < 2e-7 * d_t
+    # direction: R^T (c - t) / |c - t|
+    dir_ = inst.R.astype(np.float64).T @ (np.asarray(cam.pos, np.float64) - inst.t)
+    np.testing.assert_allclose(cl / np.linalg.norm(cl), dir_ / np.linalg.norm(dir_), atol=1e-12)
+    # FoV 60 -> 20 shrinks the distance by tan 10 / tan 30
+    assert abs(d_t * 2.0 / d_r - math.tan(math.radians(10)) / math.tan(math.radians(30))) < 1e-12
+    # the far clamp keeps the direction and caps the length
+    clc = orc.local_camera(inst, cam, f_t, d_max=0.5 * d_t)
+    assert abs(np.linalg.norm(clc) - 0.5 * d_t) < 1e-12
+    np.testing.assert_allclose(clc / np.linalg.norm(clc), dir_ / np.linalg.norm(dir_), atol=1e-12)
+
+
+def test_eq1_distance_range():
+    # Eq. 1: d = r / (tan(theta/2) p) for the torus (half-diagonal 1.941) at 50 deg
+    r = synth.SHAPE_HALF_DIAG["torus"]
+    assert abs(r - 1.9411) < 1e-3
+    d_near = r / (math.tan(math.radians(25)) * 0.9)
+    d_far = r / (math.tan(math.radians(25)) * 0.05)
+    assert abs(d_near - 4.625) < 5e-3 and abs(d_far - 83.25) < 0.1
+
+
+def test_frustum_special_points(orc):
+    cam = axis_camera(W=64, H=32, fovy_deg=60.0)
+    ty = math.tan(math.radians(30))
+    tx = ty * 2.0
+    pts = {
+        (0.0, 0.0, 1.0): 2,              # on the axis
+        (0.0, 0.0, 0.1): 0,              # before the near plane
+        (0.0, 0.0, 0.2): 0,              # exactly at near: p_z > near is strict
+        (1.29 * tx * 5, 0.0, 5.0): 2,    # inside the 1.3 guard band in x
+        (1.31 * tx * 5, 0.0, 5.0): 0,
+        (0.0, -1.29 * ty * 5, 5.0): 2,
+        (0.0, 1.31 * ty * 5, 5.0): 0,
+        (0.0, 0.0, -3.0): 0,             # behind
+        (0.0, 0.0, 1e6): 2,              # no far plane
+    }
+    means = np.array(list(pts.keys()), np.float32).T.copy()
+    a = synth.Asset(mean=means, scale=np.ones_like(means) * 0.01, quat=np.tile([[1], [0], [0], [0]], means.shape[1]).astype(np.float32),
+                    opacity=np.ones(means.shape[1], np.float32), sh=np.zeros((3, means.shape[1]), np.float32),
+                    sh_degree=0, mlp=synth.MLPSpec(params=synth.mlp_params(8, synth.rng(0)), width=8))
+    sc = Scene(assets=[a], instances=[synth.identity_instance()], cameras=[cam])
+    st, lg = orc.query(sc, use_mlp=False)
+    assert st[0].tolist() == list(pts.values())
+    assert np.all(np.isnan(lg))
+
+
+def _random_scene(n=3000, seed=5, W=48, H=40, degree=3, width=16):
+    a = synth.make_asset("torus", n, degree, seed, width=width)
+    inst = Instance(asset=0, R=synth.yaw(1.1) @ np.array([[1, 0, 0], [0, 0.6, -0.8], [0, 0.8, 0.6]], np.float32),
+                    s=1.7, t=np.array([0.4, -0.3, 0.2], np.float32))
+    cam = synth.camera((0.5, -5.0, 2.5), target=(0.4, -0.3, 0.2), fovy_deg=45.0, width=W, height=H)
+    return Scene(assets=[a], instances=[inst], cameras=[cam], tile=8)
+
+
+def _mapped_identity_scene(sc):
+    """The same view with an identity instance and the camera mapped by the
+    inverse instance transform (near plane scaled with it)."""
+    inst, cam = sc.instances[0], sc.cameras[0]
+    R = inst.R.astype(np.float64)
+    pos = R.T @ (np.asarray(cam.pos, np.float64) - inst.t) / inst.s
+    cam2 = Camera(pos=pos, R=cam.R.astype(np.float64) @ R, fovy=cam.fovy, width=cam.width,
+                  height=cam.height, near=cam.near / inst.s)
+    return Scene(assets=sc.assets, instances=[synth.identity_instance()], cameras=[cam2], tile=sc.tile)
+
+
+@pytest.mark.parametrize("exact", [True, False])
+def test_instancing_invariance(orc, exact):
+    sc = _random_scene()
+    tol = 1e-9
+    if exact:
+        # signed-permutation rotation, power-of-two scale and dyadic offsets:
+        # the inverse-mapped camera is exactly representable in float32
+        sc.instances[0] = Instance(asset=0, R=np.array([[0, 0, 1], [-1, 0, 0], [0, -1, 0]], np.float32),
+                                   s=2.0, t=np.array([0.5, -0.25, 0.125], np.float32))
+        sc.cameras[0] = Camera(pos=np.array([1.0, -6.0, 3.0], np.float32),
+                               R=np.array([[1, 0, 0], [0, 0, -1], [0, 1, 0]], np.float32),
+                               fovy=sc.cameras[0].fovy, width=48, height=40, near=0.25)
+    else:
+        tol = 1e-5  # float32 rounding of the mapped camera
+    sc2 = _mapped_identity_scene(sc)
+    st1, lg1 = orc.query(sc)
+    st2, lg2 = orc.query(sc2)
+    assert np.array_equal(st1, st2)
+    q = ~np.isnan(lg1)
+    assert q.sum() > 100 and np.array_equal(q, ~np.isnan(lg2))
+    np.testing.assert_allclose(lg1[q], lg2[q], rtol=tol, atol=tol)
+    f1 = orc.frame(sc)
+    f2 = orc.frame(sc2)
+    r1, r2 = f1["rec"][0], f2["rec"][0]
+    np.testing.assert_allclose(r1[:, [0, 1, 2, 3, 4, 9, 10, 11, 12]], r2[:, [0, 1, 2, 3, 4, 9, 10, 11, 12]],
+                               rtol=tol, atol=tol)
+    np.testing.assert_allclose(r1[:, 8], r2[:, 8] * sc.instances[0].s, rtol=tol)
+    np.testing.assert_allclose(f1["images"][0], f2["images"][0], atol=100 * tol)
+
+
+# ---------------------------------------------------------------------------
+# EWA projection closed forms
+# ---------------------------------------------------------------------------
+def test_projection_on_axis_closed_form(orc):
+    cam = axis_camera(W=64, H=48, fovy_deg=60.0)
+    f = 0.5 * 48 / math.tan(float(np.float32(math.radians(60))) / 2)
+    z, sx, sy, sz = 4.0, *map(float, np.float32([0.05, 0.11, 0.3]))
+    rec, _ = project_one(orc, one_gaussian_asset((0, 0, z), (sx, sy, sz)), cam)
+    assert abs(rec[0] - 32.0) < 1e-12 and abs(rec[1] - 24.0) < 1e-12 and rec[8] == z
+    assert abs(rec[2] - (f * f * sx * sx / z ** 2 + 0.3)) < 1e-12
+    assert abs(rec[4] - (f * f * sy * sy / z ** 2 + 0.3)) < 1e-12
+    assert abs(rec[3]) < 1e-15
+    # conic is the inverse of Sigma2D
+    S = np.array([[rec[2], rec[3]], [rec[3], rec[4]]])
+    Ci = np.array([[rec[5], rec[6]], [rec[6], rec[7]]])
+    np.testing.assert_allclose(S @ Ci, np.eye(2), atol=1e-12)
+
+
+def test_projection_off_axis_closed_form(orc):
+    cam = axis_camera(W=64, H=48, fovy_deg=60.0)
+    f = 0.5 * 48 / math.tan(float(np.float32(math.radians(60))) / 2)
+    tx, z, sx, sy, sz = 1.25, 5.0, *map(float, np.float32([0.07, 0.02, 0.2]))
+    rec, _ = project_one(orc, one_gaussian_asset((tx, 0, z), (sx, sy, sz)), cam)
+    assert abs(rec[2] - (f * f * (sx * sx / z ** 2 + tx * tx * sz * sz / z ** 4) + 0.3)) < 1e-11
+    assert abs(rec[3]) < 1e-15
+    assert abs(rec[4] - (f * f * sy * sy / z ** 2 + 0.3)) < 1e-11
+    assert abs(rec[0] - (f * tx / z + 32.0)) < 1e-12
+    # off-axis in both x and y: the depth variance couples u and v
+    ty = -0.75
+    rec, _ = project_one(orc, one_gaussian_asset((tx, ty, z), (sx, sy, sz)), cam)
+    assert abs(rec[3] - f * f * tx * ty * sz * sz / z ** 4) < 1e-11
+    assert abs(rec[4] - (f * f * (sy * sy / z ** 2 + ty * ty * sz * sz / z ** 4) + 0.3)) < 1e-11
+
+
+def test_projection_is_first_order_pushforward(orc):
+    """EWA: Sigma2D - 0.3 I = J Sigma_c J^T with J the derivative of the
+    perspective map (u, v)(p) at the mean; J is taken here by central
+    differences of the map itself, for a rotated, off-axis Gaussian under a
+    rotated, scaled instance and a tilted camera."""
+    cam = synth.camera((0.3, -4.0, 1.5), target=(0.5, 0.2, 0.1), fovy_deg=55.0, width=80, height=60)
+    inst = Instance(asset=0, R=synth.yaw(0.4), s=1.5, t=np.array([0.2, 0.1, -0.1], np.float32))
+    q = np.array([0.8, 0.3, -0.4, 0.34], np.float64); q /= np.linalg.norm(q)
+    a = one_gaussian_asset((0.6, 0.4, 0.3), (0.3, 0.05, 0.12), quat=q)
+    rec, _ = project_one(orc, a, cam, inst)
+    ca = orc.cam_array(cam); ia = orc.inst_array(inst)
+    Rc = ca[3:12].reshape(3, 3); pos = ca[:3]; Ri = ia[:9].reshape(3, 3); s = ia[9]; t = ia[10:13]
+    f = 0.5 * 60 / math.tan(0.5 * ca[12])
+    uv = lambda pp: np.array([f * pp[0] / pp[2] + 40, f * pp[1] / pp[2] + 30])
+    mu = a.mean[:, 0].astype(np.float64)
+    p = Rc @ (s * Ri @ mu + t - pos)
+    h = 1e-5
+    J = np.stack([(uv(p + h * e) - uv(p - h * e)) / (2 * h) for e in np.eye(3)], axis=1)
+    qq = a.quat[:, 0].astype(np.float64); qq /= np.linalg.norm(qq)
+    w, x, y, z = qq
+    Rq = np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                   [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                   [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+    # the rotation maps the first scale axis onto its first column
+    Sl = Rq @ np.diag(a.scale[:, 0].astype(np.float64) ** 2) @ Rq.T
+    M = Rc @ Ri
+    Sc = s * s * M @ Sl @ M.T
+    S2 = J @ Sc @ J.T
+    np.testing.assert_allclose([rec[2] - 0.3, rec[3], rec[4] - 0.3], [S2[0, 0], S2[0, 1], S2[1, 1]], rtol=1e-7)
+    np.testing.assert_allclose(rec[:2], uv(p), rtol=1e-12)
+
+
+def test_quaternion_orientation(orc):
+    # 30 deg about the view axis turns the long axis towards +x+y: the screen
+    # covariance xy term is positive and equals (s1^2 - s2^2) cos30 sin30 f^2/z^2
+    cam = axis_camera(64, 64, fovy_deg=60.0)
+    f = 0.5 * 64 / math.tan(float(np.float32(math.radians(60))) / 2)
+    c, sn = math.cos(math.radians(15)), math.sin(math.radians(15))
+    s1, s2 = map(float, np.float32([0.2, 0.02]))
+    rec, _ = project_one(orc, one_gaussian_asset((0, 0, 4.0), (s1, s2, 0.02), quat=(c, 0, 0, sn)), cam)
+    expect = (s1 * s1 - s2 * s2) * math.cos(math.radians(30)) * math.sin(math.radians(30)) * f * f / 16.0
+    assert rec[3] > 0 and abs(rec[3] - expect) < 1e-6 * expect
+
+
+def test_sh_view_direction_is_camera_to_gaussian(orc):
+    # only the (l=1, m=0) coefficient is set: colour = 0.5 + c Y_10(d) with d
+    # the unit vector from the camera to the Gaussian in the asset frame
+    cam = axis_camera(32, 32)  # at the origin looking along +z
+    a = one_gaussian_asset((0, 0, 3.0), (0.05, 0.05, 0.05))
+    a.sh_degree = 1
+    a.sh = np.zeros((12, 1), np.float32)
+    a.sh[3 * 2 + 0, 0] = 0.4  # coefficient 2 = (l=1, m=0), red channel
+    rec, _ = project_one(orc, a, cam)
+    y10 = math.sqrt(3 / (4 * math.pi))
+    assert abs(rec[10] - (0.5 + 0.4 * y10)) < 1e-7 and abs(rec[11] - 0.5) < 1e-12
+
+
+def test_projection_rotation_about_view_axis_swaps(orc):
+    cam = axis_camera()
+    a = one_gaussian_asset((0, 0, 3.0), (0.09, 0.03, 0.05))
+    r0, _ = project_one(orc, a, cam)
+    h = math.sqrt(0.5)
+    b = one_gaussian_asset((0, 0, 3.0), (0.09, 0.03, 0.05), quat=(h, 0, 0, h))  # 90 deg about z
+    r1, _ = project_one(orc, b, cam)
+    assert abs(r0[2] - r1[4]) < 1e-12 and abs(r0[4] - r1[2]) < 1e-12
+    # an unnormalised quaternion is normalised on use
+    c = one_gaussian_asset((0, 0, 3.0), (0.09, 0.03, 0.05), quat=(3 * h, 0, 0, 3 * h))
+    r2, _ = project_one(orc, c, cam)
+    np.testing.assert_allclose(r1, r2, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# spherical harmonics
+# ---------------------------------------------------------------------------
+def _real_sh_scipy(l, m, theta, phi):
+    from scipy import special
+    try:
+        Y = lambda mm: special.sph_harm_y(l, mm, theta, phi)
+    except AttributeError:  # older scipy
+        Y = lambda mm: special.sph_harm(mm, l, phi, theta)
+    if m == 0:
+        return Y(0).real
+    # real form without Condon-Shortley phase: the (-1)^m cancels scipy's phase
+    if m > 0:
+        return math.sqrt(2) * (-1) ** m * Y(m).real
+    return math.sqrt(2) * (-1) ** m * Y(-m).imag
+
+
+def test_sh_basis_matches_scipy_real_form(orc):
+    g = np.random.default_rng(2)
+    for _ in range(20):
+        d = g.standard_normal(3)
+        d /= np.linalg.norm(d)
+        theta = math.acos(d[2])
+        phi = math.atan2(d[1], d[0])
+        Y = orc.sh_basis(d, 3)
+        k = 0
+        for l in range(4):
+            for m in range(-l, l + 1):
+                assert abs(Y[k] - _real_sh_scipy(l, m, theta, phi)) < 1e-12, (l, m)
+                k += 1
+
+
+def test_sh_orthonormal_by_quadrature(orc):
+    # Gauss-Legendre in cos(theta) x uniform phi integrates degree <= 6 exactly
+    xs, ws = np.polynomial.legendre.leggauss(12)
+    nphi = 16
+    G = np.zeros((16, 16))
+    for x, w in zip(xs, ws):
+        st = math.sqrt(1 - x * x)
+        for j in range(nphi):
+            ph = 2 * math.pi * j / nphi
+            Y = orc.sh_basis(np.array([st * math.cos(ph), st * math.sin(ph), x]), 3)
+            G += w * (2 * math.pi / nphi) * np.outer(Y, Y)
+    np.testing.assert_allclose(G, np.eye(16), atol=1e-12)
+
+
+def test_sh0_colour_is_sampled_rgb(orc):
+    cam = axis_camera()
+    a = one_gaussian_asset((0.1, -0.2, 3.0), (0.05, 0.05, 0.05), rgb=(0.25, 0.5, 0.75))
+    rec, _ = project_one(orc, a, cam)
+    np.testing.assert_allclose(rec[10:13], [0.25, 0.5, 0.75], atol=1e-7)
+
+
+# ---------------------------------------------------------------------------
+# compositing
+# ---------------------------------------------------------------------------
+def _rec(u, v, sxx, sxy, syy, depth, o, rgb):
+    det = sxx * syy - sxy * sxy
+    r = np.zeros(16)
+    r[0], r[1], r[2], r[3], r[4] = u, v, sxx, sxy, syy
+    r[5], r[6], r[7] = syy / det, -sxy / det, sxx / det
+    r[8], r[9] = depth, o
+    r[10:13] = rgb
+    return r
+
+
+def _full_rect(m, W, H):
+    return np.tile(np.array([[0, W - 1, 0, H - 1]], np.int32), (m, 1))
+
+
+def test_single_splat_alpha_falloff(orc):
+    W = H = 16
+    cam = axis_camera(W, H)
+    for o in (0.5, 1.0):
+        rec = _rec(7.5, 8.5, 4.0, 0.0, 1.0, 2.0, o, (0.3, 0.6, 0.9))[None]
+        out = orc.render_camera(rec, _full_rect(1, W, H), cam, 16)
+        img = out["image"]
+        a0 = min(0.99, o)
+        np.testing.assert_allclose(img[8, 7], a0 * np.array([0.3, 0.6, 0.9]), rtol=1e-14)
+        # one sigma along the major (x) axis: dx = 2 -> alpha = o e^(-1/2)
+        a1 = min(0.99, o * math.exp(-0.5))
+        np.testing.assert_allclose(img[8, 9], a1 * np.array([0.3, 0.6, 0.9]), rtol=1e-14)
+        # outside the kappa ellipse nothing is blended
+        k2 = 2 * math.log(255 * o)
+        for px in range(W):
+            q = (px + 0.5 - 7.5) ** 2 / 4.0
+            if q > k2 + 1e-9:
+                assert np.all(img[8, px] == 0)
+
+
+def test_two_splat_closed_form(orc):
+    cam = axis_camera(8, 8)
+    c1, c2 = np.array([1.0, 0.2, 0.1]), np.array([0.1, 0.3, 1.0])
+    rec = np.stack([_rec(3.5, 3.5, 1e4, 0, 1e4, 1.0, 0.6, c1), _rec(3.5, 3.5, 1e4, 0, 1e4, 2.0, 0.7, c2)])
+    img = orc.render_camera(rec, _full_rect(2, 8, 8), cam, 8, bg=(0.0, 0.0, 0.0))["image"]
+    a1, a2 = 0.6, 0.7
+    np.testing.assert_allclose(img[3, 3], a1 * c1 + (1 - a1) * a2 * c2, rtol=1e-12)
+    # order is by depth, not by id
+    rec2 = rec[::-1].copy()
+    img2 = orc.render_camera(rec2, _full_rect(2, 8, 8), cam, 8)["image"]
+    np.testing.assert_allclose(img2[3, 3], img[3, 3], rtol=1e-14)
+    # equal depths: ties break by id
+    rec3 = rec.copy(); rec3[1, 8] = 1.0
+    img3 = orc.render_camera(rec3, _full_rect(2, 8, 8), cam, 8)["image"]
+    np.testing.assert_allclose(img3[3, 3], a1 * c1 + (1 - a1) * a2 * c2, rtol=1e-12)
+
+
+def test_stop_rule_three_opaque_splats(orc):
+    cam = axis_camera(4, 4)
+    recs = [_rec(1.5, 1.5, 1e6, 0, 1e6, 1.0 + k, 1.0, (1.0, 1.0, 1.0)) for k in range(4)]
+    rec = np.stack(recs)
+    cb = np.zeros(4)
+    rc = np.zeros(4, np.uint8)
+    out = orc.render_camera(rec, _full_rect(4, 4, 4), cam, 4, contrib=cb, reached=rc)
+    T = out["T"][1, 1]
+    # two splats of alpha 0.99 bring T to 1e-4 (not below): both blended;
+    # the third would push T below 1e-4 and is not blended; the fourth is never reached
+    assert abs(T - 0.01 * 0.01) < 1e-15 and T >= 1e-4
+    assert abs(out["image"][1, 1, 0] - (0.99 + 0.01 * 0.99)) < 1e-14
+    assert rc.tolist() == [1, 1, 1, 0]
+    assert cb[2] == 0 and cb[3] == 0 and abs(cb[1] - 0.99 * 0.01) < 1e-15
+
+
+def test_partition_of_unity_and_T_bounds(orc):
+    sc = _random_scene(n=4000, degree=0)
+    st, _ = orc.query(sc, use_mlp=False)
+    kept = orc.compact(st)[0]
+    rec, prect = orc.project(sc, sc.cameras[0], kept)
+    rec[:, 10:13] = 1.0  # white splats, black background: C + T_final = 1
+    out = orc.render_camera(rec, prect, sc.cameras[0], 8)
+    np.testing.assert_allclose(out["image"][..., 0] + out["T"], 1.0, atol=1e-12)
+    assert np.all(out["T"] >= 1e-4) and np.all(out["T"] <= 1.0)
+    assert np.any(out["T"] < 0.5)
+
+
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_tiled_equals_tile_free_bruteforce(orc, tile):
+    sc = _random_scene(n=200, seed=9, W=32, H=32)
+    sc.instances[0].s = 3.0
+    st, _ = orc.query(sc, use_mlp=False)
+    kept = orc.compact(st)[0]
+    assert 50 < len(kept) <= 200
+    rec, prect = orc.project(sc, sc.cameras[0], kept)
+    tiled = orc.render_camera(rec, prect, sc.cameras[0], tile)
+    brute, tf = orc.render_brute(rec, sc.cameras[0])
+    assert np.array_equal(tiled["image"], brute)
+    assert np.array_equal(tiled["T"], tf)
+
+
+def test_footprint_is_conservative(orc):
+    sc = _random_scene(n=400, seed=13, W=40, H=32)
+    sc.instances[0].s = 4.0
+    st, _ = orc.query(sc, use_mlp=False)
+    kept = orc.compact(st)[0]
+    rec, prect = orc.project(sc, sc.cameras[0], kept)
+    W, H = 40, 32
+    px, py = np.meshgrid(np.arange(W) + 0.5, np.arange(H) + 0.5)
+    for r, pr in zip(rec, prect):
+        dx, dy = px - r[0], py - r[1]
+        q = r[5] * dx * dx + 2 * r[6] * dx * dy + r[7] * dy * dy
+        alpha = np.minimum(0.99, r[9] * np.exp(-0.5 * q))
+        ys, xs = np.nonzero(alpha >= 1 / 255)
+        if len(xs):
+            assert pr[0] <= xs.min() and xs.max() <= pr[1] and pr[2] <= ys.min() and ys.max() <= pr[3]
+
+
+def test_sort_order_is_tile_depth_id(orc):
+    sc = _random_scene(n=500, seed=21, W=48, H=40)
+    sc.instances[0].s = 2.5
+    st, _ = orc.query(sc, use_mlp=False)
+    kept = orc.compact(st)[0]
+    rec, prect = orc.project(sc, sc.cameras[0], kept)
+    rec[::7, 8] = rec[1, 8]  # force depth ties
+    out = orc.render_camera(rec, prect, sc.cameras[0], 8, want_order=True)
+    tw = (48 + 7) // 8
+    ent = []
+    for j, pr in enumerate(prect):
+        if pr[0] > pr[1]:
+            continue
+        for ty in range(pr[2] // 8, pr[3] // 8 + 1):
+            for tx in range(pr[0] // 8, pr[1] // 8 + 1):
+                ent.append((ty * tw + tx, rec[j, 8], j))
+    ref = sorted(ent)
+    assert [(t, j) for t, _, j in ref] == [tuple(x) for x in out["order"].tolist()]
+
+
+def test_ground_truth_visibility_invariant(orc):
+    sc = _random_scene(n=6000, seed=31, W=48, H=40, degree=3)
+    sc.instances[0].s = 2.0
+    f = orc.frame(sc, use_mlp=False, record=True)
+    rec, prect = f["rec"][0], f["prect"][0]
+    reached, contrib = f["reached"][0], f["contrib"][0]
+    assert 0 < reached.sum() < len(reached)
+    img = f["images"][0]
+    keep = reached == 1
+    img2 = orc.render_camera(rec[keep], prect[keep], sc.cameras[0], 8)["image"]
+    assert np.array_equal(img, img2)  # removing never-reached splats changes nothing
+    keep = contrib > 0
+    img3 = orc.render_camera(rec[keep], prect[keep], sc.cameras[0], 8)["image"]
+    # removing never-blended splats changes no pixel by more than T_min * max colour
+    assert np.max(np.abs(img3 - img)) <= 1e-4 * max(1.0, rec[:, 10:13].max())
+
+
+def test_labels_on_a_stack(orc):
+    # 3 layers of wide opaque splats in front of a layer of small ones: the
+    # small ones behind saturated pixels never contribute.
+    n_front, n_back = 3, 40
+    g = np.random.default_rng(4)
+    back = np.stack([g.uniform(-0.3, 0.3, n_back), g.uniform(-0.3, 0.3, n_back), np.full(n_back, 5.0)])
+    front = np.stack([np.zeros(n_front), np.zeros(n_front), 2.0 + 0.1 * np.arange(n_front)])
+    side = np.array([[3.0], [0.0], [5.0]])  # visible, off to the side
+    means = np.concatenate([front, back, side], axis=1).astype(np.float32)
+    n = means.shape[1]
+    scale = np.full((3, n), 0.01, np.float32)
+    scale[:, :n_front] = 1.0
+    quat = np.tile([[1], [0], [0], [0]], n).astype(np.float32)
+    op = np.full(n, 0.8, np.float32)
+    op[:n_front] = 1.0
+    a = synth.Asset(mean=means, scale=scale, quat=quat, opacity=op, sh=np.zeros((3, n), np.float32),
+                    sh_degree=0, mlp=synth.MLPSpec(params=synth.mlp_params(8, synth.rng(0)), width=8))
+    cam = axis_camera(64, 64, fovy_deg=90.0)
+    lab = orc.labels(a, [cam])[0]
+    assert lab[:n_front].tolist() == [1, 1, 1]  # the front layers contribute
+    assert np.all(lab[n_front:n_front + n_back] == 0)
+    assert lab[-1] == 1
+
+
+# ---------------------------------------------------------------------------
+# loss, backward, Adam, RNG, metrics
+# ---------------------------------------------------------------------------
+def test_backward_matches_central_differences_all_params(orc):
+    W = 8
+    g = np.random.default_rng(7)
+    p = synth.mlp_params(W, synth.rng(11)).astype(np.float64)
+    X = g.uniform(-1, 1, (64, 72))
+    y = (g.uniform(0, 1, 64) > 0.5).astype(np.float64)
+    loss, dP, dX = orc.bce_backward(p, W, X, y, want_dx=True)
+    eps = 1e-3
+    fd = np.zeros_like(p)
+    for k in range(p.size):
+        pp = p.copy(); pp[k] += eps
+        pm = p.copy(); pm[k] -= eps
+        fd[k] = (orc.bce_backward(pp, W, X, y)[0] - orc.bce_backward(pm, W, X, y)[0]) / (2 * eps)
+    # a central difference across a ReLU kink is not the derivative: leave out
+    # the parameters whose +-eps step flips any hidden unit of any sample
+    _, _, pre0 = orc.mlp_forward(p, W, X, want_pre=True)
+    smooth = np.ones(p.size, bool)
+    for k in range(p.size):
+        for sgn in (1, -1):
+            pp = p.copy(); pp[k] += sgn * eps
+            if np.any((orc.mlp_forward(pp, W, X, want_pre=True)[2] > 0) != (pre0 > 0)):
+                smooth[k] = False
+    assert smooth.mean() > 0.9
+    floor = 1e-6 * np.max(np.abs(fd))
+    rel = np.abs(dP - fd) / np.maximum(np.abs(fd), floor)
+    assert np.linalg.norm((dP - fd)[smooth]) <= 1e-3 * np.linalg.norm(fd[smooth])
+    assert np.all(rel[smooth] < 1e-3)
+    # input gradient
+    k = 5
+    Xp = X.copy(); Xp[3, k] += eps
+    Xm = X.copy(); Xm[3, k] -= eps
+    fdx = (orc.bce_backward(p, W, Xp, y)[0] - orc.bce_backward(p, W, Xm, y)[0]) / (2 * eps)
+    assert abs(dX[3, k] - fdx) <= 1e-3 * abs(fdx) + 1e-9
+    # the loss itself: mean of max(z,0) - z y + log(1 + e^-|z|)
+    z, _ = orc.mlp_forward(p, W, X)
+    ref = np.mean(np.logaddexp(0, z) - z * y)
+    assert abs(loss - ref) < 1e-12
+
+
+def test_adam_one_step_closed_form(orc):
+    for gval in (0.3, -2.0):
+        p = np.array([1.5]); m = np.zeros(1); v = np.zeros(1)
+        orc.adam_step(p, np.array([gval]), m, v, 1, lr=1e-3)
+        assert abs(p[0] - (1.5 - 1e-3 * gval / (abs(gval) + 1e-8))) < 1e-15
+    # second step with the same gradient: m_hat = g, v_hat = g^2 again
+    p = np.array([0.0]); m = np.zeros(1); v = np.zeros(1)
+    orc.adam_step(p, np.array([0.5]), m, v, 1)
+    orc.adam_step(p, np.array([0.5]), m, v, 2)
+    assert abs(p[0] + 2e-3 * 0.5 / (0.5 + 1e-8)) < 1e-15
+
+
+def test_splitmix64_published_values(orc):
+    # first outputs of SplitMix64 seeded with 0 and with 1234567
+    assert orc.splitmix64(0, 0) == 0xE220A8397B1DCDAF
+    assert orc.splitmix64(0, 1) == 0x6E789E6AA1B965F4
+    assert orc.splitmix64(1234567, 0) == 6457827717110365317
+    assert orc.splitmix64(1234567, 1) == 3203168211198807973
+
+
+def test_psnr(orc):
+    a = np.random.default_rng(0).uniform(0, 1, (8, 8, 3))
+    assert orc.psnr(a, a) == 100.0
+    assert abs(orc.psnr(a, a + 0.01) - 40.0) < 1e-9
