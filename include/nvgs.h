@@ -1,0 +1,216 @@
+/*
+ * nvgs.h -- C ABI of the NVGS per-frame renderer for composed 3D Gaussian
+ * Splatting scenes on AMD Instinct MI355X (gfx950).
+ *
+ * The method ("NVGS: Neural Visibility for Occlusion Culling in 3D Gaussian
+ * Splatting", Sec. 3.3) stores every asset once together with a list of
+ * instance transforms.  Per frame and per camera it
+ *   1. frustum-culls every Gaussian of every instance on its mean,
+ *   2. queries a small per-asset visibility MLP for every in-frustum
+ *      (instance, Gaussian) pair, with the camera moved into the asset frame
+ *      and corrected for FoV and instance scale (Eq. 2),
+ *   3. instantiates only the surviving pairs,
+ *   4. projects them to 2D (EWA splatting, as in original 3DGS),
+ *   5. bins them into screen tiles ordered by (tile, depth, id), and
+ *   6. composites front to back, skipping alpha < 1/255 and stopping before
+ *      transmittance would fall below 1e-4 (Sec. 4.1).
+ * The MLP is trained per asset on visibility labels, where a Gaussian is
+ * visible from a view if its contribution alpha*T to some pixel is non-zero
+ * (Sec. 3.1, 3.2).
+ *
+ * Conventions
+ *  - All entry points return nvgs_status and never throw.  On a non-OK
+ *    status nvgs_last_error() describes the failure.
+ *  - "device" pointers are HIP device memory of the context's device,
+ *    "host" pointers are ordinary host memory.  Device inputs are borrowed:
+ *    asset arrays until the next nvgs_load_assets / nvgs_destroy, per-call
+ *    inputs and outputs until the call's work on the context stream is done.
+ *  - Work is enqueued on the context stream; a call synchronises only where
+ *    its comment says so.
+ *  - A context is not thread-safe; use one context per stream.
+ *  - Cameras: world -> camera rotation R with rows (right, down, forward),
+ *    the camera looks along +z_cam, fovy is the vertical field of view in
+ *    radians, square pixels, principal point (W/2, H/2), pixel centres at
+ *    integer + 0.5.
+ */
+#ifndef NVGS_H_
+#define NVGS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t nvgs_status;
+#define NVGS_OK 0
+#define NVGS_E_INVALID 1  /* bad argument: null pointer, n <= 0, bad enum, non-finite value ... */
+#define NVGS_E_STATE 2    /* call order: render before load_assets / set_instances, ... */
+#define NVGS_E_NOMEM 3    /* device allocation failed */
+#define NVGS_E_CAPACITY 4 /* a planned capacity was exceeded; outputs undefined; call again */
+#define NVGS_E_DEVICE 5   /* HIP runtime error (text in nvgs_last_error) */
+
+#define NVGS_PREC_FP32 0 /* MLP operands in FP32, FP32 accumulation */
+#define NVGS_PREC_BF16 1 /* MLP operands in BF16 (round to nearest even), FP32 accumulation */
+#define NVGS_PREC_FP8 2  /* MLP operands in OCP FP8 E4M3 with per-layer scales, FP32 accumulation */
+
+#define NVGS_RENDER_RECORD_CONTRIB 1u /* write per-pair max alpha*T into opts->contrib */
+#define NVGS_RENDER_KEEP_DEBUG 2u     /* keep per-splat debug arrays (nvgs_debug_buffers) */
+
+typedef struct nvgs_ctx nvgs_ctx;
+
+/* Device memory provider.  alloc returns device memory (>= 256-byte aligned)
+ * or NULL; free releases it.  With alloc == NULL the library uses hipMalloc. */
+typedef struct nvgs_allocator {
+  void* (*alloc)(size_t bytes, void* user);
+  void (*free)(void* ptr, void* user);
+  void* user;
+} nvgs_allocator;
+
+typedef struct nvgs_create_info {
+  int32_t device;           /* HIP device ordinal */
+  void* stream;             /* hipStream_t the context enqueues on (NULL = null stream) */
+  nvgs_allocator allocator; /* scratch memory provider */
+} nvgs_create_info;
+
+/* Visibility MLP of one asset (Sec. 3.2; hidden layers fixed at 3 here).
+ * params: device, FP32, packed row-major W1[width][12*bands], b1[width],
+ * W2[width][width], b2, W3[width][width], b3, wo[width], bo[1].
+ * Input x = (mean_scale * mu, cam_scale * c_local) with c_local the camera
+ * position in the asset frame, scaled by train_focal / f_render (Eq. 2,
+ * f = 1 / tan(fovy / 2)) and clamped to length d_max when d_max > 0;
+ * features sin(2^k pi x_j), cos(2^k pi x_j), k < bands, for the six scalars
+ * in order.  A pair is kept iff the logit is >= 0.  If |c_local| < d_min
+ * the MLP is not queried and every in-frustum Gaussian is kept (Sec. 3.3). */
+typedef struct nvgs_mlp {
+  int32_t width; /* 64 or 128 */
+  int32_t bands; /* 6 */
+  const float* params;
+  float mean_scale, cam_scale, train_focal, d_min, d_max;
+} nvgs_mlp;
+
+/* One asset, float32 structure-of-arrays in device memory (borrowed). */
+typedef struct nvgs_asset {
+  int64_t n;            /* Gaussians, 1 <= n < 2^31 */
+  int32_t sh_degree;    /* 0..3 */
+  const float* mean;    /* [3][n] asset frame */
+  const float* scale;   /* [3][n] linear standard deviations */
+  const float* quat;    /* [4][n] (w, x, y, z), normalised on use */
+  const float* opacity; /* [n] activated, in (0, 1] */
+  const float* sh;      /* [(sh_degree+1)^2 * 3][n], plane c*3 + channel,
+                           real SH (l-major, m = -l..l); colour =
+                           max(0, 0.5 + sum_c Y_c(dir) sh_c), dir = unit
+                           vector from camera to Gaussian in the asset frame */
+  nvgs_mlp mlp;
+} nvgs_asset;
+
+/* Instance: world = s * R * mu + t (R row-major, asset -> world). */
+typedef struct nvgs_instance {
+  int32_t asset;
+  float R[9];
+  float s;
+  float t[3];
+} nvgs_instance;
+
+typedef struct nvgs_camera {
+  float pos[3];
+  float R[9]; /* world -> camera, rows right, down, forward */
+  float fovy;
+  int32_t width, height;
+  float near_plane; /* frustum: z > near, |x| <= 1.3 tan(fovx/2) z, |y| <= 1.3 tan(fovy/2) z */
+} nvgs_camera;
+
+typedef struct nvgs_render_opts {
+  int32_t tile;      /* screen tile edge: 8, 16 or 32 (the image does not depend on it) */
+  int32_t use_mlp;   /* 0: frustum culling only (the unculled reference) */
+  int32_t precision; /* NVGS_PREC_* for the MLP */
+  float bg[3];       /* background colour */
+  uint32_t flags;    /* NVGS_RENDER_* */
+  float* contrib;    /* device [C][P] (P = pairs per camera, instance-major) or NULL;
+                        with RECORD_CONTRIB the max alpha*T of every blended fragment
+                        of each pair is max-accumulated into it (caller zero-fills) */
+} nvgs_render_opts;
+
+/* Stages timed with HIP events on the context stream (ms_stage index). */
+#define NVGS_STAGE_SETUP 0      /* per (camera, instance) transforms and MLP layer-1 camera half */
+#define NVGS_STAGE_CULL_MLP 1   /* frustum cull + visibility MLP */
+#define NVGS_STAGE_COMPACT 2    /* scan of the per-chunk keep counts */
+#define NVGS_STAGE_PROJECT 3    /* compaction + EWA projection + SH + footprint */
+#define NVGS_STAGE_DEPTH_SORT 4 /* radix sort of the splats by depth */
+#define NVGS_STAGE_BIN 5        /* tile counts in depth order + scan + emission */
+#define NVGS_STAGE_TILE_SORT 6  /* stable radix sort by tile + tile ranges */
+#define NVGS_STAGE_BLEND 7      /* front-to-back compositing */
+#define NVGS_NUM_STAGES 8
+
+typedef struct nvgs_frame_stats {
+  int64_t pairs;      /* C * P */
+  int64_t in_frustum; /* pairs inside the frustum */
+  int64_t queried;    /* pairs the MLP was evaluated for */
+  int64_t kept;       /* instantiated splats (survived frustum + MLP) */
+  int64_t duplicates; /* (splat, tile) entries sorted */
+  int64_t workspace_bytes;
+  float ms_total;     /* frame wall time on the stream (first to last event) */
+  float ms_stage[NVGS_NUM_STAGES]; /* per-stage kernel time (HIP events) */
+} nvgs_frame_stats;
+
+/* Borrowed views of the last frame's device buffers (valid until the next
+ * render / destroy); arrays are indexed by splat id = position in the
+ * (camera, instance, Gaussian)-ordered list of survivors. */
+typedef struct nvgs_debug_view {
+  int64_t n_splats, n_dup;
+  const uint32_t* pair;    /* [n_splats] index into [C][P] of the splat's pair (KEEP_DEBUG only) */
+  const float* rec_a;      /* [n_splats][4]: u, v, conic xx, conic xy (pixels) */
+  const float* rec_b;      /* [n_splats][4]: conic yy, opacity, r, g */
+  const float* rec_c;      /* [n_splats][4]: b, depth, ex, ey (footprint half extents, pixels) */
+  const uint32_t* rect;    /* [n_splats][4]: x0 | y0 << 16, x1 | y1 << 16 (tile coords), cam, tiles */
+  const uint32_t* sorted_key; /* [n_dup] cam * n_tiles + tile, ascending */
+  const uint32_t* sorted_id;  /* [n_dup] splat id, (depth, id) order within a tile */
+  const uint32_t* ranges;  /* [C * n_tiles][2] start, end into the sorted arrays */
+  int32_t tiles_x, tiles_y;
+} nvgs_debug_view;
+
+typedef struct nvgs_train_opts {
+  int64_t batch;      /* (Gaussian, view) pairs per step */
+  int32_t steps;
+  int32_t precision;  /* NVGS_PREC_FP32 or NVGS_PREC_BF16 */
+  float lr, beta1, beta2, eps;
+  uint64_t seed;      /* SplitMix64 seed for the batch draws */
+  float threshold;    /* label = max alpha*T > threshold (1/255) */
+  int32_t tile;
+} nvgs_train_opts;
+
+/* Create a context on a device / stream.  Host call, no GPU work. */
+nvgs_status nvgs_create(const nvgs_create_info* info, nvgs_ctx** out);
+/* Destroy a context, releasing its scratch memory (synchronises its stream). */
+void nvgs_destroy(nvgs_ctx* ctx);
+/* Message of the last non-OK status of this context ("" if none). */
+const char* nvgs_last_error(const nvgs_ctx* ctx);
+
+/* Register the asset store (each asset stored once, Sec. 3.3).  Arrays are
+ * borrowed.  Validates shapes; copies MLP weights into the kernels' operand
+ * layouts (asynchronous).  Invalidates the instance list. */
+nvgs_status nvgs_load_assets(nvgs_ctx* ctx, const nvgs_asset* assets, int32_t n);
+
+/* Copy the instance list (host array).  Synchronous host->device copy.
+ * E_INVALID for an asset index out of range, s <= 0 or non-finite values. */
+nvgs_status nvgs_set_instances(nvgs_ctx* ctx, const nvgs_instance* inst, int32_t n);
+
+/* Steps 1-2 only.  state: device [C][P] bytes (0 frustum-culled, 1 culled by
+ * the MLP, 2 kept); logits: device [C][P] float or NULL (NaN where the MLP was
+ * not queried).  P = sum over instances of their asset's n. */
+nvgs_status nvgs_query_visibility(nvgs_ctx* ctx, const nvgs_camera* cams, int32_t C, int32_t precision,
+                                  uint8_t* state, float* logits);
+
+/* The whole frame for C cameras of equal size.  rgb: device [C][H][W][3].
+ * stats (host, nullable): filled after a stream synchronisation. */
+nvgs_status nvgs_render(nvgs_ctx* ctx, const nvgs_camera* cams, int32_t C, const nvgs_render_opts* opts,
+                        float* rgb, nvgs_frame_stats* stats);
+
+/* Views of the last frame's intermediate buffers (for tests and tools). */
+nvgs_status nvgs_debug_buffers(nvgs_ctx* ctx, nvgs_debug_view* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NVGS_H_ */

@@ -1,0 +1,313 @@
+"""Python binding of libnvgs.so, the NVGS per-frame renderer for MI355X.
+
+Argument marshalling only: every step of the frame runs in the library's HIP
+kernels.  PyTorch supplies device memory (the library's scratch comes from
+torch's caching allocator through the allocator callback) and the stream.
+The names follow the C ABI in include/nvgs.h.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Iterable, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnvgs.so")
+
+OK, E_INVALID, E_STATE, E_NOMEM, E_CAPACITY, E_DEVICE = range(6)
+PREC_FP32, PREC_BF16, PREC_FP8 = 0, 1, 2
+RENDER_RECORD_CONTRIB, RENDER_KEEP_DEBUG = 1, 2
+_PREC = {"fp32": PREC_FP32, "bf16": PREC_BF16, "fp8": PREC_FP8}
+
+
+class NvgsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"nvgs status {status}: {msg}")
+        self.status = status
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class Allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", C.c_void_p)]
+
+
+class CreateInfo(C.Structure):
+    _fields_ = [("device", C.c_int32), ("stream", C.c_void_p), ("allocator", Allocator)]
+
+
+class MLP(C.Structure):
+    _fields_ = [("width", C.c_int32), ("bands", C.c_int32), ("params", C.c_void_p),
+                ("mean_scale", C.c_float), ("cam_scale", C.c_float), ("train_focal", C.c_float),
+                ("d_min", C.c_float), ("d_max", C.c_float)]
+
+
+class Asset(C.Structure):
+    _fields_ = [("n", C.c_int64), ("sh_degree", C.c_int32), ("mean", C.c_void_p), ("scale", C.c_void_p),
+                ("quat", C.c_void_p), ("opacity", C.c_void_p), ("sh", C.c_void_p), ("mlp", MLP)]
+
+
+class Instance(C.Structure):
+    _fields_ = [("asset", C.c_int32), ("R", C.c_float * 9), ("s", C.c_float), ("t", C.c_float * 3)]
+
+
+class Camera(C.Structure):
+    _fields_ = [("pos", C.c_float * 3), ("R", C.c_float * 9), ("fovy", C.c_float), ("width", C.c_int32),
+                ("height", C.c_int32), ("near_plane", C.c_float)]
+
+
+class RenderOpts(C.Structure):
+    _fields_ = [("tile", C.c_int32), ("use_mlp", C.c_int32), ("precision", C.c_int32), ("bg", C.c_float * 3),
+                ("flags", C.c_uint32), ("contrib", C.c_void_p)]
+
+
+NUM_STAGES = 8
+STAGES = ["setup", "cull_mlp", "compact", "project", "depth_sort", "bin", "tile_sort", "blend"]
+
+
+class FrameStats(C.Structure):
+    _fields_ = [("pairs", C.c_int64), ("in_frustum", C.c_int64), ("queried", C.c_int64), ("kept", C.c_int64),
+                ("duplicates", C.c_int64), ("workspace_bytes", C.c_int64), ("ms_total", C.c_float),
+                ("ms_stage", C.c_float * NUM_STAGES)]
+
+
+class DebugView(C.Structure):
+    _fields_ = [("n_splats", C.c_int64), ("n_dup", C.c_int64), ("pair", C.c_void_p), ("rec_a", C.c_void_p),
+                ("rec_b", C.c_void_p), ("rec_c", C.c_void_p), ("rect", C.c_void_p), ("sorted_key", C.c_void_p),
+                ("sorted_id", C.c_void_p), ("ranges", C.c_void_p), ("tiles_x", C.c_int32), ("tiles_y", C.c_int32)]
+
+
+class TrainOpts(C.Structure):
+    _fields_ = [("batch", C.c_int64), ("steps", C.c_int32), ("precision", C.c_int32), ("lr", C.c_float),
+                ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float), ("seed", C.c_uint64),
+                ("threshold", C.c_float), ("tile", C.c_int32)]
+
+
+# exported symbols of the C ABI and their signatures
+_SIGS = {
+    "nvgs_create": ([C.POINTER(CreateInfo), C.POINTER(C.c_void_p)], C.c_int32),
+    "nvgs_destroy": ([C.c_void_p], None),
+    "nvgs_last_error": ([C.c_void_p], C.c_char_p),
+    "nvgs_load_assets": ([C.c_void_p, C.POINTER(Asset), C.c_int32], C.c_int32),
+    "nvgs_set_instances": ([C.c_void_p, C.POINTER(Instance), C.c_int32], C.c_int32),
+    "nvgs_query_visibility": ([C.c_void_p, C.POINTER(Camera), C.c_int32, C.c_int32, C.c_void_p, C.c_void_p],
+                              C.c_int32),
+    "nvgs_render": ([C.c_void_p, C.POINTER(Camera), C.c_int32, C.POINTER(RenderOpts), C.c_void_p,
+                     C.POINTER(FrameStats)], C.c_int32),
+    "nvgs_debug_buffers": ([C.c_void_p, C.POINTER(DebugView)], C.c_int32),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libnvgs.so; raises if it has not been built (no fallback path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                              "(python -m paper_2511_19202_amd.build)")
+        L = C.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+_hip = None
+
+
+def _hiprt():
+    global _hip
+    if _hip is None:
+        _hip = C.CDLL("libamdhip64.so")
+        _hip.hipMemcpyAsync.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p]
+        _hip.hipMemcpyAsync.restype = C.c_int
+        _hip.hipStreamSynchronize.argtypes = [C.c_void_p]
+        _hip.hipStreamSynchronize.restype = C.c_int
+    return _hip
+
+
+def _torch():
+    import torch
+    return torch
+
+
+# ----------------------------------------------------------------------------
+# marshalling helpers
+# ----------------------------------------------------------------------------
+def camera_struct(cam) -> Camera:
+    c = Camera()
+    c.pos[:] = [float(v) for v in np.asarray(cam.pos, np.float32).ravel()]
+    c.R[:] = [float(v) for v in np.asarray(cam.R, np.float32).ravel()]
+    c.fovy = float(cam.fovy)
+    c.width = int(cam.width)
+    c.height = int(cam.height)
+    c.near_plane = float(cam.near)
+    return c
+
+
+def instance_struct(inst) -> Instance:
+    h = Instance()
+    h.asset = int(inst.asset)
+    h.R[:] = [float(v) for v in np.asarray(inst.R, np.float32).ravel()]
+    h.s = float(inst.s)
+    h.t[:] = [float(v) for v in np.asarray(inst.t, np.float32).ravel()]
+    return h
+
+
+class DeviceAsset:
+    """Device copies (torch tensors) of one asset's arrays; owned by the caller."""
+
+    def __init__(self, asset, device):
+        torch = _torch()
+        f = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float32)).to(device)
+        self.mean, self.scale, self.quat = f(asset.mean), f(asset.scale), f(asset.quat)
+        self.opacity, self.sh = f(asset.opacity), f(asset.sh)
+        self.params = f(asset.mlp.params)
+        self.n = int(asset.mean.shape[1])
+        self.sh_degree = int(asset.sh_degree)
+        self.spec = asset.mlp
+
+    def struct(self) -> Asset:
+        a = Asset()
+        a.n = self.n
+        a.sh_degree = self.sh_degree
+        a.mean, a.scale, a.quat = self.mean.data_ptr(), self.scale.data_ptr(), self.quat.data_ptr()
+        a.opacity, a.sh = self.opacity.data_ptr(), self.sh.data_ptr()
+        sp = self.spec
+        a.mlp = MLP(int(sp.width), int(sp.bands), self.params.data_ptr(), float(sp.mean_scale), float(sp.cam_scale),
+                    float(sp.train_focal), float(sp.d_min), float(sp.d_max))
+        return a
+
+
+class Context:
+    """One renderer context on a device and torch stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible to torch")
+        self.L = lib()
+        self.device = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._blocks = {}
+
+        def _alloc(nbytes, user):
+            t = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+            p = t.data_ptr()
+            self._blocks[p] = t
+            return p
+
+        def _free(ptr, user):
+            self._blocks.pop(int(ptr or 0), None)
+
+        self._alloc_cb = ALLOC_FN(_alloc)
+        self._free_cb = FREE_FN(_free)
+        info = CreateInfo(device, C.c_void_p(self.stream.cuda_stream), Allocator(self._alloc_cb, self._free_cb, None))
+        h = C.c_void_p()
+        st = self.L.nvgs_create(C.byref(info), C.byref(h))
+        if st != OK:
+            raise NvgsError(st, "nvgs_create failed")
+        self.h = h
+        self.assets = []
+        self.instances = []
+        self.P = 0
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.nvgs_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int):
+        if st != OK:
+            raise NvgsError(st, self.L.nvgs_last_error(self.h).decode())
+
+    # -- asset store and instances ------------------------------------------
+    def load_assets(self, assets: Sequence):
+        self.assets = [a if isinstance(a, DeviceAsset) else DeviceAsset(a, self.device) for a in assets]
+        arr = (Asset * len(self.assets))(*[a.struct() for a in self.assets])
+        self._check(self.L.nvgs_load_assets(self.h, arr, len(self.assets)))
+
+    def set_instances(self, instances: Sequence):
+        arr = (Instance * len(instances))(*[instance_struct(i) for i in instances])
+        self._check(self.L.nvgs_set_instances(self.h, arr, len(instances)))
+        self.instances = list(instances)
+        self.P = sum(self.assets[i.asset].n for i in instances)
+
+    # -- per frame -----------------------------------------------------------
+    def _cams(self, cams):
+        cams = list(cams)
+        return (Camera * len(cams))(*[camera_struct(c) for c in cams]), len(cams)
+
+    def query_visibility(self, cams: Iterable, precision="fp32", want_logits: bool = True):
+        torch = _torch()
+        arr, n = self._cams(cams)
+        state = torch.empty((n, self.P), dtype=torch.uint8, device=self.device)
+        logits = torch.empty((n, self.P), dtype=torch.float32, device=self.device) if want_logits else None
+        self._check(self.L.nvgs_query_visibility(self.h, arr, n, _PREC.get(precision, precision), state.data_ptr(),
+                                                 logits.data_ptr() if logits is not None else None))
+        return state, logits
+
+    def render(self, cams: Iterable, tile: int = 16, use_mlp: bool = True, precision="fp32", bg=(0.0, 0.0, 0.0),
+               contrib=None, keep_debug: bool = False, stats: bool = False, out=None):
+        torch = _torch()
+        arr, n = self._cams(cams)
+        W, H = arr[0].width, arr[0].height
+        rgb = out if out is not None else torch.empty((n, H, W, 3), dtype=torch.float32, device=self.device)
+        flags = (RENDER_RECORD_CONTRIB if contrib is not None else 0) | (RENDER_KEEP_DEBUG if keep_debug else 0)
+        opts = RenderOpts(int(tile), int(bool(use_mlp)), _PREC.get(precision, precision), (C.c_float * 3)(*bg), flags,
+                          contrib.data_ptr() if contrib is not None else None)
+        fs = FrameStats() if stats else None
+        self._check(self.L.nvgs_render(self.h, arr, n, C.byref(opts), rgb.data_ptr(),
+                                       C.byref(fs) if fs is not None else None))
+        if stats:
+            return rgb, {"pairs": fs.pairs, "in_frustum": fs.in_frustum, "queried": fs.queried, "kept": fs.kept,
+                         "duplicates": fs.duplicates, "workspace_bytes": fs.workspace_bytes, "ms": fs.ms_total,
+                         "ms_stage": dict(zip(STAGES, list(fs.ms_stage)))}
+        return rgb
+
+    def debug_buffers(self) -> dict:
+        """Copies of the last frame's intermediate buffers as torch tensors."""
+        torch = _torch()
+        v = DebugView()
+        self._check(self.L.nvgs_debug_buffers(self.h, C.byref(v)))
+        hip = _hiprt()
+        ns, nd = int(v.n_splats), int(v.n_dup)
+
+        def grab(ptr, shape, dtype):
+            t = torch.empty(shape, dtype=dtype, device=self.device)
+            nbytes = t.numel() * t.element_size()
+            if ptr and nbytes:
+                hip.hipMemcpyAsync(t.data_ptr(), ptr, nbytes, 3, self.stream.cuda_stream)  # device to device
+            return t
+
+        out = {
+            "n_splats": ns, "n_dup": nd, "tiles_x": int(v.tiles_x), "tiles_y": int(v.tiles_y),
+            "rec_a": grab(v.rec_a, (ns, 4), torch.float32),
+            "rec_b": grab(v.rec_b, (ns, 4), torch.float32),
+            "rec_c": grab(v.rec_c, (ns, 4), torch.float32),
+            "rect": grab(v.rect, (ns, 4), torch.int32),
+            "sorted_key": grab(v.sorted_key, (nd,), torch.int32),
+            "sorted_id": grab(v.sorted_id, (nd,), torch.int32),
+        }
+        if v.pair:
+            out["pair"] = grab(v.pair, (ns,), torch.int32)
+        hip.hipStreamSynchronize(self.stream.cuda_stream)
+        return out
+
+
+def exported_symbols() -> list:
+    return list(_SIGS)

@@ -1,0 +1,567 @@
+// C ABI of the NVGS renderer: context, asset store, instance list, and the
+// per-frame launch sequence (declared in include/nvgs.h).
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace nvgs;
+
+namespace {
+
+struct Buf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct nvgs_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  nvgs_allocator alloc{};
+  std::string err;
+  size_t workspace = 0;
+
+  // asset store
+  std::vector<nvgs_asset> assets;
+  std::vector<AssetDev> adev;
+  std::vector<Buf> op_bufs;
+  Buf assets_dev;
+  int width = 0;
+
+  // instances
+  std::vector<nvgs_instance> inst;
+  std::vector<int64_t> inst_off;
+  int64_t P = 0;
+  Buf inst_dev, inst_off_dev;
+
+  // plan (depends on the camera count)
+  int planC = -1;
+  int64_t n_words = 0, n_chunks = 0;
+  std::vector<int64_t> seg_word_base, seg_chunk_base;
+  std::vector<WorkItem> items;
+  std::vector<int32_t> seglist;
+  Buf seg_word_dev, seg_chunk_dev, items_dev, seglist_dev, segs_dev, c1_dev;
+  Buf mask, chunk_cnt, chunk_off, scan_part;
+
+  // cameras
+  nvgs_camera* cam_host = nullptr;  // pinned staging
+  int cam_host_cap = 0;
+  Buf cam_dev;
+
+  // splats and sort buffers
+  int64_t cap_splats = 0, cap_dup = 0;
+  Buf rec_a, rec_b, rec_c, rect, depth_key, ids, ids_tmp, keys_tmp2, pair_of, cnt, dup_off;
+  Buf keys, vals, keys_tmp, vals_tmp, hist, hist_part, ranges;
+  Buf counters;          // u32 [0] n_splats, [1] n_dup, [2] overflow flags; u64 at [4] in-frustum, [6] queried
+  uint32_t* counters_host = nullptr;
+
+  // last frame (debug view)
+  int64_t last_splats = 0, last_dup = 0;
+  const uint32_t* last_sorted_key = nullptr;
+  const uint32_t* last_sorted_id = nullptr;
+  int last_tiles_x = 0, last_tiles_y = 0;
+  bool last_debug = false;
+
+  hipEvent_t ev[2 * NVGS_NUM_STAGES] = {};
+};
+
+namespace {
+
+nvgs_status fail(nvgs_ctx* c, nvgs_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+#define CK(call)                                                                         \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(ctx, NVGS_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+void* dev_alloc(nvgs_ctx* ctx, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  if (ctx->alloc.alloc) return ctx->alloc.alloc(bytes, ctx->alloc.user);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+  return p;
+}
+
+void dev_free(nvgs_ctx* ctx, void* p) {
+  if (!p) return;
+  if (ctx->alloc.alloc) {
+    if (ctx->alloc.free) ctx->alloc.free(p, ctx->alloc.user);
+  } else {
+    (void)hipFree(p);
+  }
+}
+
+void release(nvgs_ctx* ctx, Buf& b) {
+  if (b.p) {
+    dev_free(ctx, b.p);
+    ctx->workspace -= b.bytes;
+  }
+  b.p = nullptr;
+  b.bytes = 0;
+}
+
+// grow-only device buffer
+bool ensure(nvgs_ctx* ctx, Buf& b, size_t bytes) {
+  if (b.p && b.bytes >= bytes) return true;
+  if (b.p) {
+    (void)hipStreamSynchronize(ctx->stream);  // the old buffer may still be in use
+    release(ctx, b);
+  }
+  size_t want = std::max<size_t>(bytes, 256);
+  b.p = dev_alloc(ctx, want);
+  if (!b.p) return false;
+  b.bytes = want;
+  ctx->workspace += want;
+  return true;
+}
+
+template <class T>
+T* P_(Buf& b) {
+  return reinterpret_cast<T*>(b.p);
+}
+
+bool finite_f(float x) { return std::isfinite(x); }
+
+nvgs_status check_cams(nvgs_ctx* ctx, const nvgs_camera* cams, int32_t C) {
+  if (!cams || C <= 0) return fail(ctx, NVGS_E_INVALID, "cameras: null pointer or C <= 0");
+  for (int k = 0; k < C; ++k) {
+    const nvgs_camera& c = cams[k];
+    if (c.width <= 0 || c.height <= 0 || c.width > 32768 || c.height > 32768)
+      return fail(ctx, NVGS_E_INVALID, "camera: width/height out of range");
+    if (c.width != cams[0].width || c.height != cams[0].height)
+      return fail(ctx, NVGS_E_INVALID, "cameras of one call must share width and height");
+    if (!(c.fovy > 0.f && c.fovy < 3.1f) || !(c.near_plane > 0.f))
+      return fail(ctx, NVGS_E_INVALID, "camera: fovy must be in (0, pi) and near > 0");
+    for (int q = 0; q < 3; ++q)
+      if (!finite_f(c.pos[q])) return fail(ctx, NVGS_E_INVALID, "camera: non-finite position");
+    for (int q = 0; q < 9; ++q)
+      if (!finite_f(c.R[q])) return fail(ctx, NVGS_E_INVALID, "camera: non-finite rotation");
+  }
+  return NVGS_OK;
+}
+
+// Build the per-camera-count plan: segment bases, work items, buffers.
+nvgs_status plan(nvgs_ctx* ctx, int C) {
+  if (ctx->planC == C) return NVGS_OK;
+  const int NI = (int)ctx->inst.size();
+  const int S = C * NI;
+  ctx->seg_word_base.assign(S + 1, 0);
+  ctx->seg_chunk_base.assign(S + 1, 0);
+  int64_t w = 0, ch = 0;
+  for (int s = 0; s < S; ++s) {
+    const int64_t n = ctx->assets[ctx->inst[s % NI].asset].n;
+    ctx->seg_word_base[s] = w;
+    ctx->seg_chunk_base[s] = ch;
+    w += (n + 31) / 32;
+    ch += (n + kChunk - 1) / kChunk;
+  }
+  ctx->seg_word_base[S] = w;
+  ctx->seg_chunk_base[S] = ch;
+  ctx->n_words = w;
+  ctx->n_chunks = ch;
+  if (ch >= (int64_t)1 << 31) return fail(ctx, NVGS_E_INVALID, "too many pairs for one frame");
+  // work items: chunk x run of up to G segments of the same asset
+  ctx->items.clear();
+  ctx->seglist.clear();
+  const int G = 16;
+  for (int a = 0; a < (int)ctx->assets.size(); ++a) {
+    const int base = (int)ctx->seglist.size();
+    for (int s = 0; s < S; ++s)
+      if (ctx->inst[s % NI].asset == a) ctx->seglist.push_back(s);
+    const int ns = (int)ctx->seglist.size() - base;
+    if (ns == 0) continue;
+    const int64_t chunks = (ctx->assets[a].n + kChunk - 1) / kChunk;
+    for (int64_t c = 0; c < chunks; ++c)
+      for (int sb = 0; sb < ns; sb += G) ctx->items.push_back({a, (int32_t)c, base + sb, base + std::min(ns, sb + G)});
+  }
+  if (!ensure(ctx, ctx->seg_word_dev, sizeof(int64_t) * (S + 1)) ||
+      !ensure(ctx, ctx->seg_chunk_dev, sizeof(int64_t) * (S + 1)) ||
+      !ensure(ctx, ctx->items_dev, sizeof(WorkItem) * std::max<size_t>(1, ctx->items.size())) ||
+      !ensure(ctx, ctx->seglist_dev, sizeof(int32_t) * std::max<size_t>(1, ctx->seglist.size())) ||
+      !ensure(ctx, ctx->segs_dev, sizeof(SegRec) * S) || !ensure(ctx, ctx->c1_dev, sizeof(float) * 128 * S) ||
+      !ensure(ctx, ctx->mask, sizeof(uint32_t) * (w + 1)) || !ensure(ctx, ctx->chunk_cnt, sizeof(uint32_t) * (ch + 1)) ||
+      !ensure(ctx, ctx->chunk_off, sizeof(uint32_t) * (ch + 1)) ||
+      !ensure(ctx, ctx->scan_part, sizeof(uint32_t) * scan_partials_needed(ch + 1)) ||
+      !ensure(ctx, ctx->cam_dev, sizeof(nvgs_camera) * C) || !ensure(ctx, ctx->counters, sizeof(uint32_t) * 8))
+    return fail(ctx, NVGS_E_NOMEM, "device allocation failed (plan)");
+  CK(hipMemcpy(ctx->seg_word_dev.p, ctx->seg_word_base.data(), sizeof(int64_t) * (S + 1), hipMemcpyHostToDevice));
+  CK(hipMemcpy(ctx->seg_chunk_dev.p, ctx->seg_chunk_base.data(), sizeof(int64_t) * (S + 1), hipMemcpyHostToDevice));
+  if (!ctx->items.empty())
+    CK(hipMemcpy(ctx->items_dev.p, ctx->items.data(), sizeof(WorkItem) * ctx->items.size(), hipMemcpyHostToDevice));
+  if (!ctx->seglist.empty())
+    CK(hipMemcpy(ctx->seglist_dev.p, ctx->seglist.data(), sizeof(int32_t) * ctx->seglist.size(),
+                 hipMemcpyHostToDevice));
+  if (ctx->cam_host_cap < C) {
+    if (ctx->cam_host) (void)hipHostFree(ctx->cam_host);
+    CK(hipHostMalloc(reinterpret_cast<void**>(&ctx->cam_host), sizeof(nvgs_camera) * C, hipHostMallocDefault));
+    ctx->cam_host_cap = C;
+  }
+  ctx->planC = C;
+  return NVGS_OK;
+}
+
+nvgs_status upload_cams(nvgs_ctx* ctx, const nvgs_camera* cams, int C) {
+  CK(hipStreamSynchronize(ctx->stream));  // the staging buffer may still be read by a previous copy
+  std::memcpy(ctx->cam_host, cams, sizeof(nvgs_camera) * C);
+  CK(hipMemcpyAsync(ctx->cam_dev.p, ctx->cam_host, sizeof(nvgs_camera) * C, hipMemcpyHostToDevice, ctx->stream));
+  return NVGS_OK;
+}
+
+nvgs_status read_counters(nvgs_ctx* ctx) {
+  CK(hipMemcpyAsync(ctx->counters_host, ctx->counters.p, sizeof(uint32_t) * 8, hipMemcpyDeviceToHost, ctx->stream));
+  CK(hipStreamSynchronize(ctx->stream));
+  return NVGS_OK;
+}
+
+nvgs_status ready(nvgs_ctx* ctx) {
+  if (ctx->assets.empty()) return fail(ctx, NVGS_E_STATE, "no assets loaded");
+  if (ctx->inst.empty()) return fail(ctx, NVGS_E_STATE, "no instances set");
+  return NVGS_OK;
+}
+
+int bits_for(int64_t v) {
+  int b = 0;
+  while (((int64_t)1 << b) < v) ++b;
+  return b;
+}
+
+}  // namespace
+
+extern "C" {
+
+nvgs_status nvgs_create(const nvgs_create_info* info, nvgs_ctx** out) {
+  if (!info || !out) return NVGS_E_INVALID;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return NVGS_E_DEVICE;
+  if (info->device < 0 || info->device >= ndev) return NVGS_E_INVALID;
+  if ((info->allocator.alloc == nullptr) != (info->allocator.free == nullptr)) return NVGS_E_INVALID;
+  if (hipSetDevice(info->device) != hipSuccess) return NVGS_E_DEVICE;
+  nvgs_ctx* ctx = new nvgs_ctx();
+  ctx->device = info->device;
+  ctx->stream = reinterpret_cast<hipStream_t>(info->stream);
+  ctx->alloc = info->allocator;
+  bool ok = hipHostMalloc(reinterpret_cast<void**>(&ctx->counters_host), 8 * sizeof(uint32_t),
+                          hipHostMallocDefault) == hipSuccess;
+  for (int e = 0; e < 2 * NVGS_NUM_STAGES && ok; ++e) ok = hipEventCreate(&ctx->ev[e]) == hipSuccess;
+  if (!ok) {
+    nvgs_destroy(ctx);
+    return NVGS_E_DEVICE;
+  }
+  *out = ctx;
+  return NVGS_OK;
+}
+
+void nvgs_destroy(nvgs_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  Buf* all[] = {&ctx->assets_dev, &ctx->inst_dev, &ctx->inst_off_dev, &ctx->seg_word_dev, &ctx->seg_chunk_dev,
+                &ctx->items_dev, &ctx->seglist_dev, &ctx->segs_dev, &ctx->c1_dev, &ctx->mask, &ctx->chunk_cnt,
+                &ctx->chunk_off, &ctx->scan_part, &ctx->cam_dev, &ctx->rec_a, &ctx->rec_b, &ctx->rec_c, &ctx->rect,
+                &ctx->depth_key, &ctx->ids, &ctx->ids_tmp, &ctx->keys_tmp2, &ctx->pair_of, &ctx->cnt, &ctx->dup_off,
+                &ctx->keys, &ctx->vals, &ctx->keys_tmp, &ctx->vals_tmp, &ctx->hist, &ctx->hist_part, &ctx->ranges,
+                &ctx->counters};
+  for (Buf* b : all) release(ctx, *b);
+  for (Buf& b : ctx->op_bufs) release(ctx, b);
+  if (ctx->cam_host) (void)hipHostFree(ctx->cam_host);
+  if (ctx->counters_host) (void)hipHostFree(ctx->counters_host);
+  for (hipEvent_t e : ctx->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete ctx;
+}
+
+const char* nvgs_last_error(const nvgs_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+nvgs_status nvgs_load_assets(nvgs_ctx* ctx, const nvgs_asset* a, int32_t n) {
+  if (!ctx) return NVGS_E_INVALID;
+  if (!a || n <= 0) return fail(ctx, NVGS_E_INVALID, "assets: null pointer or n <= 0");
+  int width = a[0].mlp.width;
+  for (int j = 0; j < n; ++j) {
+    const nvgs_asset& x = a[j];
+    if (x.n <= 0 || x.n >= ((int64_t)1 << 31)) return fail(ctx, NVGS_E_INVALID, "asset: n out of range");
+    if (x.sh_degree < 0 || x.sh_degree > 3) return fail(ctx, NVGS_E_INVALID, "asset: sh_degree must be 0..3");
+    if (!x.mean || !x.scale || !x.quat || !x.opacity || !x.sh || !x.mlp.params)
+      return fail(ctx, NVGS_E_INVALID, "asset: null array");
+    if (x.mlp.width != 64 && x.mlp.width != 128) return fail(ctx, NVGS_E_INVALID, "asset: MLP width must be 64 or 128");
+    if (x.mlp.width != width) return fail(ctx, NVGS_E_INVALID, "assets of one context must share the MLP width");
+    if (x.mlp.bands != 6) return fail(ctx, NVGS_E_INVALID, "asset: MLP bands must be 6");
+    if (!finite_f(x.mlp.mean_scale) || !finite_f(x.mlp.cam_scale) || !finite_f(x.mlp.train_focal) ||
+        !finite_f(x.mlp.d_min) || !finite_f(x.mlp.d_max) || x.mlp.train_focal <= 0.f)
+      return fail(ctx, NVGS_E_INVALID, "asset: non-finite MLP metadata");
+  }
+  CK(hipSetDevice(ctx->device));
+  CK(hipStreamSynchronize(ctx->stream));
+  for (Buf& b : ctx->op_bufs) release(ctx, b);
+  ctx->op_bufs.assign(n, Buf{});
+  ctx->assets.assign(a, a + n);
+  ctx->adev.assign(n, AssetDev{});
+  for (int j = 0; j < n; ++j) {
+    const nvgs_asset& x = a[j];
+    AssetDev& d = ctx->adev[j];
+    d.mean = x.mean; d.scale = x.scale; d.quat = x.quat; d.opacity = x.opacity; d.sh = x.sh;
+    d.n = x.n; d.sh_degree = x.sh_degree; d.width = x.mlp.width;
+    d.mean_scale = x.mlp.mean_scale; d.cam_scale = x.mlp.cam_scale; d.train_focal = x.mlp.train_focal;
+    d.d_min = x.mlp.d_min; d.d_max = x.mlp.d_max;
+    d.params = x.mlp.params;
+    const size_t nf = mlp_op_f32_floats(width);
+    if (!ensure(ctx, ctx->op_bufs[j], nf * sizeof(float))) return fail(ctx, NVGS_E_NOMEM, "operand image");
+    d.op_f32 = P_<float>(ctx->op_bufs[j]);
+    d.op_bf16 = nullptr; d.op_fp8 = nullptr; d.fp8_scale = nullptr;
+    CK(launch_prepare_mlp(x.mlp.params, width, P_<float>(ctx->op_bufs[j]), nullptr, nullptr, nullptr, ctx->stream));
+  }
+  if (!ensure(ctx, ctx->assets_dev, sizeof(AssetDev) * n)) return fail(ctx, NVGS_E_NOMEM, "asset table");
+  CK(hipMemcpyAsync(ctx->assets_dev.p, ctx->adev.data(), sizeof(AssetDev) * n, hipMemcpyHostToDevice, ctx->stream));
+  CK(hipStreamSynchronize(ctx->stream));
+  ctx->width = width;
+  ctx->inst.clear();
+  ctx->planC = -1;
+  return NVGS_OK;
+}
+
+nvgs_status nvgs_set_instances(nvgs_ctx* ctx, const nvgs_instance* h, int32_t n) {
+  if (!ctx) return NVGS_E_INVALID;
+  if (ctx->assets.empty()) return fail(ctx, NVGS_E_STATE, "set_instances before load_assets");
+  if (!h || n <= 0) return fail(ctx, NVGS_E_INVALID, "instances: null pointer or n <= 0");
+  std::vector<int64_t> off(n + 1, 0);
+  for (int i = 0; i < n; ++i) {
+    if (h[i].asset < 0 || h[i].asset >= (int)ctx->assets.size())
+      return fail(ctx, NVGS_E_INVALID, "instance: asset index out of range");
+    if (!(h[i].s > 0.f) || !finite_f(h[i].s)) return fail(ctx, NVGS_E_INVALID, "instance: scale must be > 0");
+    for (int q = 0; q < 9; ++q)
+      if (!finite_f(h[i].R[q])) return fail(ctx, NVGS_E_INVALID, "instance: non-finite rotation");
+    for (int q = 0; q < 3; ++q)
+      if (!finite_f(h[i].t[q])) return fail(ctx, NVGS_E_INVALID, "instance: non-finite translation");
+    off[i + 1] = off[i] + ctx->assets[h[i].asset].n;
+  }
+  if (off[n] >= ((int64_t)1 << 32)) return fail(ctx, NVGS_E_INVALID, "more than 2^32 pairs per camera");
+  CK(hipSetDevice(ctx->device));
+  CK(hipStreamSynchronize(ctx->stream));
+  ctx->inst.assign(h, h + n);
+  ctx->inst_off = off;
+  ctx->P = off[n];
+  if (!ensure(ctx, ctx->inst_dev, sizeof(nvgs_instance) * n) ||
+      !ensure(ctx, ctx->inst_off_dev, sizeof(int64_t) * (n + 1)))
+    return fail(ctx, NVGS_E_NOMEM, "instance table");
+  CK(hipMemcpy(ctx->inst_dev.p, h, sizeof(nvgs_instance) * n, hipMemcpyHostToDevice));
+  CK(hipMemcpy(ctx->inst_off_dev.p, off.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice));
+  ctx->planC = -1;
+  return NVGS_OK;
+}
+
+nvgs_status nvgs_query_visibility(nvgs_ctx* ctx, const nvgs_camera* cams, int32_t C, int32_t precision,
+                                  uint8_t* state, float* logits) {
+  if (!ctx) return NVGS_E_INVALID;
+  nvgs_status s = ready(ctx);
+  if (s) return s;
+  if ((s = check_cams(ctx, cams, C))) return s;
+  if (!state) return fail(ctx, NVGS_E_INVALID, "state: null pointer");
+  if (precision != NVGS_PREC_FP32) return fail(ctx, NVGS_E_INVALID, "precision not supported");
+  CK(hipSetDevice(ctx->device));
+  if ((s = plan(ctx, C))) return s;
+  if ((s = upload_cams(ctx, cams, C))) return s;
+  const int NI = (int)ctx->inst.size();
+  CK(launch_segment_setup(P_<nvgs_camera>(ctx->cam_dev), P_<nvgs_instance>(ctx->inst_dev),
+                          P_<AssetDev>(ctx->assets_dev), P_<int64_t>(ctx->inst_off_dev), NI, C, ctx->P, 1,
+                          P_<int64_t>(ctx->seg_word_dev), P_<int64_t>(ctx->seg_chunk_dev), P_<SegRec>(ctx->segs_dev),
+                          P_<float>(ctx->c1_dev), 128, ctx->stream));
+  // logits may be NULL: write them into a scratch buffer then
+  Buf scratch;
+  float* lg = logits;
+  if (!lg) {
+    if (!ensure(ctx, scratch, sizeof(float) * (size_t)C * ctx->P)) return fail(ctx, NVGS_E_NOMEM, "logit scratch");
+    lg = P_<float>(scratch);
+  }
+  CK(launch_cull_mlp(P_<AssetDev>(ctx->assets_dev), ctx->adev.data(), (int)ctx->adev.size(),
+                     P_<WorkItem>(ctx->items_dev), (int64_t)ctx->items.size(), P_<int32_t>(ctx->seglist_dev),
+                     P_<SegRec>(ctx->segs_dev), P_<float>(ctx->c1_dev), 128, ctx->width, precision, 1,
+                     P_<uint32_t>(ctx->mask), P_<uint32_t>(ctx->chunk_cnt), state, lg, nullptr, ctx->stream));
+  if (scratch.p) {
+    CK(hipStreamSynchronize(ctx->stream));
+    release(ctx, scratch);
+  }
+  return NVGS_OK;
+}
+
+nvgs_status nvgs_render(nvgs_ctx* ctx, const nvgs_camera* cams, int32_t C, const nvgs_render_opts* opts, float* rgb,
+                        nvgs_frame_stats* stats) {
+  if (!ctx) return NVGS_E_INVALID;
+  nvgs_status s = ready(ctx);
+  if (s) return s;
+  if ((s = check_cams(ctx, cams, C))) return s;
+  if (!opts || !rgb) return fail(ctx, NVGS_E_INVALID, "render: null opts or rgb");
+  const int T = opts->tile;
+  if (T != 8 && T != 16 && T != 32) return fail(ctx, NVGS_E_INVALID, "tile must be 8, 16 or 32");
+  if (opts->precision != NVGS_PREC_FP32) return fail(ctx, NVGS_E_INVALID, "precision not supported");
+  const bool record = (opts->flags & NVGS_RENDER_RECORD_CONTRIB) != 0;
+  if (record && !opts->contrib) return fail(ctx, NVGS_E_INVALID, "RECORD_CONTRIB needs opts->contrib");
+  const bool debug = record || (opts->flags & NVGS_RENDER_KEEP_DEBUG);
+  for (int q = 0; q < 3; ++q)
+    if (!finite_f(opts->bg[q])) return fail(ctx, NVGS_E_INVALID, "non-finite background");
+  CK(hipSetDevice(ctx->device));
+  if ((s = plan(ctx, C))) return s;
+  const int W = cams[0].width, H = cams[0].height;
+  const int tiles_x = (W + T - 1) / T, tiles_y = (H + T - 1) / T, n_tiles = tiles_x * tiles_y;
+  if ((int64_t)C * n_tiles >= ((int64_t)1 << 31)) return fail(ctx, NVGS_E_INVALID, "too many tiles");
+  if ((s = upload_cams(ctx, cams, C))) return s;
+  hipStream_t st = ctx->stream;
+  hipEvent_t* ev = ctx->ev;
+#define STAGE_BEGIN(k) CK(hipEventRecord(ev[2 * (k)], st))
+#define STAGE_END(k) CK(hipEventRecord(ev[2 * (k) + 1], st))
+  const int NI = (int)ctx->inst.size();
+  uint32_t* counters = P_<uint32_t>(ctx->counters);
+  unsigned long long* counts64 = reinterpret_cast<unsigned long long*>(counters + 4);
+  STAGE_BEGIN(NVGS_STAGE_SETUP);
+  CK(launch_fill_u32(counters, 0u, 8, st));
+  CK(launch_segment_setup(P_<nvgs_camera>(ctx->cam_dev), P_<nvgs_instance>(ctx->inst_dev),
+                          P_<AssetDev>(ctx->assets_dev), P_<int64_t>(ctx->inst_off_dev), NI, C, ctx->P,
+                          opts->use_mlp ? 1 : 0, P_<int64_t>(ctx->seg_word_dev), P_<int64_t>(ctx->seg_chunk_dev),
+                          P_<SegRec>(ctx->segs_dev), P_<float>(ctx->c1_dev), 128, st));
+  STAGE_END(NVGS_STAGE_SETUP);
+  STAGE_BEGIN(NVGS_STAGE_CULL_MLP);
+  CK(launch_cull_mlp(P_<AssetDev>(ctx->assets_dev), ctx->adev.data(), (int)ctx->adev.size(),
+                     P_<WorkItem>(ctx->items_dev), (int64_t)ctx->items.size(), P_<int32_t>(ctx->seglist_dev),
+                     P_<SegRec>(ctx->segs_dev), P_<float>(ctx->c1_dev), 128, ctx->width, opts->precision, 0,
+                     P_<uint32_t>(ctx->mask), P_<uint32_t>(ctx->chunk_cnt), nullptr, nullptr, counts64, st));
+  STAGE_END(NVGS_STAGE_CULL_MLP);
+  STAGE_BEGIN(NVGS_STAGE_COMPACT);
+  CK(launch_scan_u32(P_<uint32_t>(ctx->chunk_cnt), P_<uint32_t>(ctx->chunk_off), ctx->n_chunks, counters + 0,
+                     P_<uint32_t>(ctx->scan_part), st));
+  STAGE_END(NVGS_STAGE_COMPACT);
+  if ((s = read_counters(ctx))) return s;
+  const int64_t ns = ctx->counters_host[0];
+  // splat buffers
+  if (ns > ctx->cap_splats || !ctx->rec_a.p) {
+    const int64_t cap = std::max<int64_t>(ns + ns / 8, 4096);
+    bool ok = ensure(ctx, ctx->rec_a, 16 * cap) && ensure(ctx, ctx->rec_b, 16 * cap) &&
+              ensure(ctx, ctx->rec_c, 16 * cap) && ensure(ctx, ctx->rect, 16 * cap) &&
+              ensure(ctx, ctx->depth_key, 4 * cap) && ensure(ctx, ctx->ids, 4 * cap) &&
+              ensure(ctx, ctx->ids_tmp, 4 * cap) && ensure(ctx, ctx->keys_tmp2, 4 * cap) &&
+              ensure(ctx, ctx->pair_of, 4 * cap) && ensure(ctx, ctx->cnt, 4 * cap) &&
+              ensure(ctx, ctx->dup_off, 4 * cap) &&
+              ensure(ctx, ctx->hist, 4 * radix_hist_words(cap)) &&
+              ensure(ctx, ctx->hist_part, 4 * scan_partials_needed(radix_hist_words(cap)) + 4 * scan_partials_needed(cap));
+    if (!ok) return fail(ctx, NVGS_E_NOMEM, "splat buffers");
+    ctx->cap_splats = cap;
+  }
+  const uint32_t* n_splats_dev = counters + 0;
+  STAGE_BEGIN(NVGS_STAGE_PROJECT);
+  CK(launch_project(P_<AssetDev>(ctx->assets_dev), P_<SegRec>(ctx->segs_dev), C * NI, P_<int64_t>(ctx->seg_chunk_dev),
+                    ctx->n_chunks, P_<uint32_t>(ctx->mask), P_<uint32_t>(ctx->chunk_off), n_splats_dev,
+                    ctx->cap_splats, T, tiles_x, tiles_y, debug ? 1 : 0, P_<float4>(ctx->rec_a),
+                    P_<float4>(ctx->rec_b), P_<float4>(ctx->rec_c), P_<uint4>(ctx->rect), P_<uint32_t>(ctx->depth_key),
+                    P_<uint32_t>(ctx->pair_of), counters + 2, st));
+  STAGE_END(NVGS_STAGE_PROJECT);
+  // depth order of the splats (stable: equal depths keep id order)
+  STAGE_BEGIN(NVGS_STAGE_DEPTH_SORT);
+  bool in_tmp = false;
+  CK(launch_radix_sort(P_<uint32_t>(ctx->depth_key), P_<uint32_t>(ctx->ids), P_<uint32_t>(ctx->keys_tmp2),
+                       P_<uint32_t>(ctx->ids_tmp), n_splats_dev, ns, 0, 32, 1, P_<uint32_t>(ctx->hist),
+                       P_<uint32_t>(ctx->hist_part), &in_tmp, st));
+  const uint32_t* depth_ids = in_tmp ? P_<uint32_t>(ctx->ids_tmp) : P_<uint32_t>(ctx->ids);
+  STAGE_END(NVGS_STAGE_DEPTH_SORT);
+  STAGE_BEGIN(NVGS_STAGE_BIN);
+  CK(launch_gather_tiles(depth_ids, P_<uint4>(ctx->rect), n_splats_dev, ns, P_<uint32_t>(ctx->cnt), st));
+  CK(launch_scan_u32_dev(P_<uint32_t>(ctx->cnt), P_<uint32_t>(ctx->dup_off), ns, n_splats_dev, counters + 1,
+                         P_<uint32_t>(ctx->hist_part), st));
+  STAGE_END(NVGS_STAGE_BIN);
+  if ((s = read_counters(ctx))) return s;
+  const int64_t nd = ctx->counters_host[1];
+  float ms_bin_count = 0.f;  // first half of the binning stage (counts + scan)
+  CK(hipEventElapsedTime(&ms_bin_count, ev[2 * NVGS_STAGE_BIN], ev[2 * NVGS_STAGE_BIN + 1]));
+  if (nd > ctx->cap_dup || !ctx->keys.p) {
+    const int64_t cap = std::max<int64_t>(nd + nd / 8, 4096);
+    bool ok = ensure(ctx, ctx->keys, 4 * cap) && ensure(ctx, ctx->vals, 4 * cap) &&
+              ensure(ctx, ctx->keys_tmp, 4 * cap) && ensure(ctx, ctx->vals_tmp, 4 * cap) &&
+              ensure(ctx, ctx->hist, 4 * radix_hist_words(std::max(cap, ctx->cap_splats))) &&
+              ensure(ctx, ctx->hist_part, 4 * scan_partials_needed(radix_hist_words(std::max(cap, ctx->cap_splats))) +
+                                              4 * scan_partials_needed(std::max(cap, ctx->cap_splats)));
+    if (!ok) return fail(ctx, NVGS_E_NOMEM, "duplicate buffers");
+    ctx->cap_dup = cap;
+  }
+  if (!ensure(ctx, ctx->ranges, sizeof(uint32_t) * 2 * (size_t)C * n_tiles))
+    return fail(ctx, NVGS_E_NOMEM, "tile ranges");
+  const uint32_t* n_dup_dev = counters + 1;
+  STAGE_BEGIN(NVGS_STAGE_BIN);
+  CK(launch_emit(depth_ids, P_<uint4>(ctx->rect), P_<uint32_t>(ctx->dup_off), n_splats_dev, ns, n_dup_dev,
+                 ctx->cap_dup, tiles_x, n_tiles, P_<uint32_t>(ctx->keys), P_<uint32_t>(ctx->vals), counters + 2, st));
+  STAGE_END(NVGS_STAGE_BIN);
+  STAGE_BEGIN(NVGS_STAGE_TILE_SORT);
+  bool in_tmp2 = false;
+  CK(launch_radix_sort(P_<uint32_t>(ctx->keys), P_<uint32_t>(ctx->vals), P_<uint32_t>(ctx->keys_tmp),
+                       P_<uint32_t>(ctx->vals_tmp), n_dup_dev, nd, 0, bits_for((int64_t)C * n_tiles), 0,
+                       P_<uint32_t>(ctx->hist), P_<uint32_t>(ctx->hist_part), &in_tmp2, st));
+  const uint32_t* skeys = in_tmp2 ? P_<uint32_t>(ctx->keys_tmp) : P_<uint32_t>(ctx->keys);
+  const uint32_t* sids = in_tmp2 ? P_<uint32_t>(ctx->vals_tmp) : P_<uint32_t>(ctx->vals);
+  CK(launch_fill_u32(P_<uint32_t>(ctx->ranges), 0u, 2 * (int64_t)C * n_tiles, st));
+  CK(launch_ranges(skeys, n_dup_dev, nd, P_<uint32_t>(ctx->ranges), st));
+  STAGE_END(NVGS_STAGE_TILE_SORT);
+  STAGE_BEGIN(NVGS_STAGE_BLEND);
+  CK(launch_blend(P_<uint32_t>(ctx->ranges), sids, P_<float4>(ctx->rec_a), P_<float4>(ctx->rec_b),
+                  P_<float4>(ctx->rec_c), P_<uint32_t>(ctx->pair_of), C, W, H, T, tiles_x, tiles_y, opts->bg[0],
+                  opts->bg[1], opts->bg[2], rgb, record ? opts->contrib : nullptr, ctx->P, P_<uint4>(ctx->rect), st));
+  STAGE_END(NVGS_STAGE_BLEND);
+#undef STAGE_BEGIN
+#undef STAGE_END
+  ctx->last_splats = ns;
+  ctx->last_dup = nd;
+  ctx->last_sorted_key = skeys;
+  ctx->last_sorted_id = sids;
+  ctx->last_tiles_x = tiles_x;
+  ctx->last_tiles_y = tiles_y;
+  ctx->last_debug = debug;
+  if (stats) {
+    if ((s = read_counters(ctx))) return s;
+    float ms = 0.f;
+    CK(hipEventElapsedTime(&ms, ev[2 * NVGS_STAGE_SETUP], ev[2 * NVGS_STAGE_BLEND + 1]));
+    for (int k = 0; k < NVGS_NUM_STAGES; ++k) {
+      float m = 0.f;
+      CK(hipEventElapsedTime(&m, ev[2 * k], ev[2 * k + 1]));
+      stats->ms_stage[k] = m;
+    }
+    stats->ms_stage[NVGS_STAGE_BIN] += ms_bin_count;
+    const unsigned long long* c64 = reinterpret_cast<const unsigned long long*>(ctx->counters_host + 4);
+    stats->pairs = (int64_t)C * ctx->P;
+    stats->in_frustum = (int64_t)c64[0];
+    stats->queried = (int64_t)c64[1];
+    stats->kept = ns;
+    stats->duplicates = nd;
+    stats->workspace_bytes = (int64_t)ctx->workspace;
+    stats->ms_total = ms;
+    if (ctx->counters_host[2]) return fail(ctx, NVGS_E_CAPACITY, "capacity exceeded");
+  }
+  return NVGS_OK;
+}
+
+nvgs_status nvgs_debug_buffers(nvgs_ctx* ctx, nvgs_debug_view* out) {
+  if (!ctx) return NVGS_E_INVALID;
+  if (!out) return fail(ctx, NVGS_E_INVALID, "null output");
+  std::memset(out, 0, sizeof(*out));
+  if (!ctx->last_sorted_key) return fail(ctx, NVGS_E_STATE, "no frame rendered yet");
+  out->n_splats = ctx->last_splats;
+  out->n_dup = ctx->last_dup;
+  out->pair = ctx->last_debug ? P_<uint32_t>(ctx->pair_of) : nullptr;
+  out->rec_a = P_<float>(ctx->rec_a);
+  out->rec_b = P_<float>(ctx->rec_b);
+  out->rec_c = P_<float>(ctx->rec_c);
+  out->rect = P_<uint32_t>(ctx->rect);
+  out->sorted_key = ctx->last_sorted_key;
+  out->sorted_id = ctx->last_sorted_id;
+  out->ranges = P_<uint32_t>(ctx->ranges);
+  out->tiles_x = ctx->last_tiles_x;
+  out->tiles_y = ctx->last_tiles_y;
+  return NVGS_OK;
+}
+
+}  // extern "C"

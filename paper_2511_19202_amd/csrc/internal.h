@@ -1,0 +1,126 @@
+// Internal declarations of the NVGS gfx950 library (not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "../../include/nvgs.h"
+
+namespace nvgs {
+
+// Compositing constants of original 3DGS (Sec. 4.1): fragments below 1/255
+// are skipped, alpha is clamped to 0.99, and the pixel stops before its
+// transmittance would drop below 1e-4.
+constexpr float kAlphaMin = 1.0f / 255.0f;
+constexpr float kAlphaMax = 0.99f;
+constexpr float kTMin = 1e-4f;
+constexpr float kGuard = 1.3f;   // frustum / Jacobian side guard band
+constexpr float kDilate = 0.3f;  // screen-space low-pass added to the 2D covariance
+
+constexpr int kChunk = 256;           // pairs per compaction chunk (one cull/MLP work-group)
+constexpr int kSortBlock = 4096;      // keys per radix-sort block
+constexpr int kScanBlock = 4096;      // items per scan block
+
+// Per-asset device record (library-owned copy of the borrowed pointers and
+// the MLP operands in MFMA register order).
+struct AssetDev {
+  const float* mean;
+  const float* scale;
+  const float* quat;
+  const float* opacity;
+  const float* sh;
+  int64_t n;
+  int32_t sh_degree;
+  int32_t width;
+  float mean_scale, cam_scale, train_focal, d_min, d_max;
+  const float* params;   // packed FP32 (borrowed)
+  const float* op_f32;   // FP32 operand image (library-owned)
+  const uint16_t* op_bf16;
+  const uint8_t* op_fp8;
+  const float* fp8_scale; // per-layer dequantisation scales
+};
+
+// Per (camera, instance) segment, built on the device every frame.
+struct SegRec {
+  float M[12];       // camera-space p = M[:, 0:3] mu + M[:, 3]  (row-major 3x4)
+  float cl[3];       // camera position in the asset frame (undoes R, t, s)
+  float near_plane;
+  float tanx_g, tany_g;  // 1.3 * tan(fov/2) in x and y
+  float focal;           // pixels
+  float half_w, half_h;
+  int32_t asset, inst, cam, n;
+  int32_t query;     // 1 = the MLP decides, 0 = every in-frustum Gaussian is kept
+  int32_t pad0;
+  int64_t pair_base;   // cam * P + instance offset  (index into [C][P] outputs)
+  int64_t word_base;   // first 32-pair mask word of the segment
+  int64_t chunk_base;  // first compaction chunk of the segment
+};
+
+// One cull/MLP work item: a 256-Gaussian chunk of an asset against a run of
+// that asset's segments (indices into the per-asset segment list).
+struct WorkItem {
+  int32_t asset;
+  int32_t chunk;
+  int32_t seg_begin;
+  int32_t seg_end;
+};
+
+// float bits are monotone for non-negative floats
+__device__ __forceinline__ uint32_t fbits(float x) { return __float_as_uint(x); }
+
+// feature held by MFMA lane group g in its q-th accumulator value after a
+// 32x32 output tile sequence (row = 8*(r/4) + 4*g + r%4 of tile q/16)
+__host__ __device__ constexpr int hid_feature(int q, int g) {
+  return 32 * (q / 16) + 8 * ((q % 16) / 4) + 4 * g + (q % 4);
+}
+
+// ---- launchers (defined in the .hip files) --------------------------------
+// operand images of the MLP weights for one asset
+hipError_t launch_prepare_mlp(const float* params, int width, float* op_f32, uint16_t* op_bf16, uint8_t* op_fp8,
+                              float* fp8_scale, hipStream_t st);
+size_t mlp_op_f32_floats(int width);
+size_t mlp_op_bf16_elems(int width);
+size_t mlp_op_fp8_bytes(int width);
+
+hipError_t launch_segment_setup(const nvgs_camera* cams_dev, const nvgs_instance* inst_dev, const AssetDev* assets,
+                                const int64_t* inst_offset, int32_t n_inst, int32_t C, int64_t P, int use_mlp,
+                                const int64_t* seg_word_base, const int64_t* seg_chunk_base, SegRec* segs,
+                                float* c1perm, int max_width, hipStream_t st);
+
+// mode: 0 = render (mask + chunk counts), 1 = query (state + logits as well)
+hipError_t launch_cull_mlp(const AssetDev* assets_dev, const AssetDev* assets_host, int32_t n_assets,
+                           const WorkItem* items, int64_t n_items, const int32_t* seglist, const SegRec* segs,
+                           const float* c1perm, int max_width, int width, int precision, int mode,
+                           uint32_t* mask, uint32_t* chunk_count, uint8_t* state, float* logits,
+                           unsigned long long* counts, hipStream_t st);
+
+hipError_t launch_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, uint32_t* partials,
+                           hipStream_t st);
+hipError_t launch_scan_u32_dev(const uint32_t* in, uint32_t* out, int64_t n, const uint32_t* n_dev, uint32_t* total,
+                               uint32_t* partials, hipStream_t st);
+size_t scan_partials_needed(int64_t n);
+
+hipError_t launch_project(const AssetDev* assets, const SegRec* segs, int32_t n_segs, const int64_t* seg_chunk_base,
+                          int64_t n_chunks, const uint32_t* mask, const uint32_t* chunk_off, const uint32_t* n_splats,
+                          int64_t cap_splats, int tile, int tiles_x, int tiles_y, int keep_debug, float4* rec_a,
+                          float4* rec_b, float4* rec_c, uint4* rect, uint32_t* depth_key, uint32_t* pair_of,
+                          uint32_t* overflow, hipStream_t st);
+
+hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint32_t* vals_tmp,
+                             const uint32_t* n_dev, int64_t cap, int begin_bit, int end_bit, int iota_vals,
+                             uint32_t* hist, uint32_t* partials, bool* result_in_tmp, hipStream_t st);
+size_t radix_hist_words(int64_t cap);
+
+hipError_t launch_gather_tiles(const uint32_t* sorted_ids, const uint4* rect, const uint32_t* n_dev, int64_t cap,
+                               uint32_t* out, hipStream_t st);
+hipError_t launch_emit(const uint32_t* sorted_ids, const uint4* rect, const uint32_t* dup_off, const uint32_t* n_dev,
+                       int64_t cap, const uint32_t* n_dup_dev, int64_t cap_dup, int tiles_x, int n_tiles,
+                       uint32_t* keys, uint32_t* vals, uint32_t* overflow, hipStream_t st);
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
+hipError_t launch_ranges(const uint32_t* keys, const uint32_t* n_dev, int64_t cap, uint32_t* ranges, hipStream_t st);
+hipError_t launch_blend(const uint32_t* ranges, const uint32_t* ids, const float4* rec_a, const float4* rec_b,
+                        const float4* rec_c, const uint32_t* pair_of, int C, int W, int H, int tile, int tiles_x,
+                        int tiles_y, float bg0, float bg1, float bg2, float* rgb, float* contrib, int64_t P,
+                        const uint4* rect, hipStream_t st);
+
+}  // namespace nvgs

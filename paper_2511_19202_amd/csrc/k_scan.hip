@@ -1,0 +1,121 @@
+// Device-wide exclusive prefix sum of uint32 counts (reduce-then-scan).
+// Used for the ordered compaction of kept pairs and for the placement of
+// (splat, tile) entries; each block owns 4096 consecutive items.
+#include "internal.h"
+
+namespace nvgs {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = kScanBlock / kScanThreads;  // 16 per thread
+
+// exclusive scan of one value per thread across a 256-thread block
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s_wave, uint32_t* block_total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint32_t y = __shfl_up(x, d);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) s_wave[wave] = x;
+  __syncthreads();
+  uint32_t base = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kScanThreads / 64; ++w) {
+    uint32_t t = s_wave[w];
+    base += (w < wave) ? t : 0u;
+    tot += t;
+  }
+  __syncthreads();
+  if (block_total) *block_total = tot;
+  return base + x - v;
+}
+
+__device__ __forceinline__ int64_t scan_n(int64_t n, const uint32_t* n_dev) {
+  return n_dev ? (int64_t)min((uint64_t)*n_dev, (uint64_t)n) : n;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* __restrict__ in, int64_t n_cap,
+                                                              const uint32_t* __restrict__ n_dev,
+                                                              uint32_t* __restrict__ partials) {
+  __shared__ uint32_t s_wave[kScanThreads / 64];
+  const int64_t n = scan_n(n_cap, n_dev);
+  const int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * kScanItems;
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k)
+    if (base + k < n) s += in[base + k];
+  uint32_t tot;
+  block_exclusive_scan(s, s_wave, &tot);
+  if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+// single work-group: exclusive scan of the block partials, total to *total
+__global__ __launch_bounds__(kScanThreads) void k_scan_partials(uint32_t* __restrict__ partials, int64_t nb,
+                                                                uint32_t* __restrict__ total) {
+  __shared__ uint32_t s_wave[kScanThreads / 64];
+  uint32_t carry = 0;
+  for (int64_t off = 0; off < nb; off += kScanBlock) {
+    const int64_t base = off + threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      v[k] = base + k < nb ? partials[base + k] : 0u;
+      s += v[k];
+    }
+    uint32_t tot;
+    uint32_t pre = block_exclusive_scan(s, s_wave, &tot) + carry;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      if (base + k < nb) partials[base + k] = pre;
+      pre += v[k];
+    }
+    carry += tot;
+  }
+  if (threadIdx.x == 0 && total) *total = carry;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* in, uint32_t* out,  // may alias
+                                                            int64_t n_cap, const uint32_t* __restrict__ n_dev,
+                                                            const uint32_t* __restrict__ partials) {
+  __shared__ uint32_t s_wave[kScanThreads / 64];
+  const int64_t n = scan_n(n_cap, n_dev);
+  const int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * kScanItems;
+  uint32_t v[kScanItems];
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    v[k] = base + k < n ? in[base + k] : 0u;
+    s += v[k];
+  }
+  uint32_t pre = block_exclusive_scan(s, s_wave, nullptr) + partials[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    if (base + k < n) out[base + k] = pre;
+    pre += v[k];
+  }
+}
+
+size_t scan_partials_needed(int64_t n) { return (size_t)((n + kScanBlock - 1) / kScanBlock) + 1; }
+
+// n: capacity (grid size); if n_dev is given the live count is min(*n_dev, n)
+hipError_t launch_scan_u32_dev(const uint32_t* in, uint32_t* out, int64_t n, const uint32_t* n_dev, uint32_t* total,
+                               uint32_t* partials, hipStream_t st) {
+  int64_t nb = (n + kScanBlock - 1) / kScanBlock;
+  if (nb == 0) {  // empty input: the partials kernel alone writes total = 0
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanThreads), 0, st, partials, (int64_t)0, total);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, st, in, n, n_dev, partials);
+  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanThreads), 0, st, partials, nb, total);
+  hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kScanThreads), 0, st, in, out, n, n_dev, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, uint32_t* partials,
+                           hipStream_t st) {
+  return launch_scan_u32_dev(in, out, n, nullptr, total, partials, st);
+}
+
+}  // namespace nvgs

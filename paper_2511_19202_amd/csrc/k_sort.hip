@@ -1,0 +1,140 @@
+// Stable LSD radix sort of (uint32 key, uint32 value) pairs, 8-bit digits,
+// for the (tile, depth, id) ordering of splats (Sec. 3.3, original 3DGS
+// binning).  Stability is what makes the id the final tie-break: values
+// enter in id order and equal keys never swap.
+//
+// Per pass: a histogram kernel (per-block digit counts, digit-major), one
+// exclusive scan over all (digit, block) counts, and a scatter kernel.  The
+// scatter ranks keys inside a block with 64-lane ballots (eight ballots give
+// the set of lanes sharing a digit), so the rank is exact and in input order
+// without atomics deciding the order.
+#include <algorithm>
+#include <utility>
+
+#include "internal.h"
+
+namespace nvgs {
+
+constexpr int kSortThreads = 256;
+constexpr int kSortWaves = kSortThreads / 64;
+constexpr int kPerWave = kSortBlock / kSortWaves;  // 1024 keys per wave
+constexpr int kRounds = kPerWave / 64;             // 16 rounds of 64
+
+__device__ __forceinline__ int64_t live_n(const uint32_t* n_dev, int64_t cap) {
+  return n_dev ? (int64_t)min((uint64_t)*n_dev, (uint64_t)cap) : cap;
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t* __restrict__ keys,
+                                                             const uint32_t* __restrict__ n_dev, int64_t cap, int shift,
+                                                             uint32_t dmask, uint32_t* __restrict__ hist, int64_t nblocks) {
+  __shared__ uint32_t s_h[kSortWaves][256];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int d = threadIdx.x; d < kSortWaves * 256; d += kSortThreads) (&s_h[0][0])[d] = 0;
+  __syncthreads();
+  const int64_t n = live_n(n_dev, cap);
+  const int64_t base = (int64_t)blockIdx.x * kSortBlock + wave * kPerWave;
+  for (int r = 0; r < kRounds; ++r) {
+    int64_t idx = base + r * 64 + lane;
+    if (idx < n) atomicAdd(&s_h[wave][(keys[idx] >> shift) & dmask], 1u);
+  }
+  __syncthreads();
+  for (int d = threadIdx.x; d < 256; d += kSortThreads) {
+    uint32_t s = 0;
+    for (int w = 0; w < kSortWaves; ++w) s += s_h[w][d];
+    hist[(int64_t)d * nblocks + blockIdx.x] = s;
+  }
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
+    const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, uint32_t* __restrict__ keys_out,
+    uint32_t* __restrict__ vals_out, const uint32_t* __restrict__ n_dev, int64_t cap, int shift, uint32_t dmask,
+    int nbits, const uint32_t* __restrict__ offs, int64_t nblocks, int iota_vals) {
+  __shared__ uint32_t s_cnt[kSortWaves][256];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int d = threadIdx.x; d < kSortWaves * 256; d += kSortThreads) (&s_cnt[0][0])[d] = 0;
+  __syncthreads();
+  const int64_t n = live_n(n_dev, cap);
+  const int64_t base = (int64_t)blockIdx.x * kSortBlock + wave * kPerWave;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  uint32_t key[kRounds], local[kRounds];
+  // phase 1: rank every key among the equal digits of this wave, in order
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    const int64_t idx = base + r * 64 + lane;
+    const bool ok = idx < n;
+    key[r] = ok ? keys_in[idx] : 0u;
+    const uint32_t d = (key[r] >> shift) & dmask;
+    uint64_t peers = __ballot(ok);
+    for (int b = 0; b < nbits; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t m = __ballot(bit);
+      peers &= bit ? m : ~m;
+    }
+    const uint32_t before = s_cnt[wave][d];
+    local[r] = before + (uint32_t)__popcll(peers & lt);
+    // the highest peer publishes the new running count (one writer per digit)
+    if (ok && (peers >> lane) == 1ull) s_cnt[wave][d] = before + (uint32_t)__popcll(peers);
+  }
+  __syncthreads();
+  // phase 2: per digit, global block offset plus the counts of earlier waves
+  for (int d = threadIdx.x; d < 256; d += kSortThreads) {
+    uint32_t run = offs[(int64_t)d * nblocks + blockIdx.x];
+    for (int w = 0; w < kSortWaves; ++w) {
+      uint32_t c = s_cnt[w][d];
+      s_cnt[w][d] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    const int64_t idx = base + r * 64 + lane;
+    if (idx < n) {
+      const uint32_t d = (key[r] >> shift) & dmask;
+      const uint32_t pos = s_cnt[wave][d] + local[r];
+      keys_out[pos] = key[r];
+      vals_out[pos] = iota_vals ? (uint32_t)idx : vals_in[idx];
+    }
+  }
+}
+
+size_t radix_hist_words(int64_t cap) {
+  int64_t nb = (cap + kSortBlock - 1) / kSortBlock;
+  return (size_t)(256 * (nb > 0 ? nb : 1));
+}
+
+// Sorts keys[0..n) (n = *n_dev, at most cap) by bits [begin_bit, end_bit).
+// Buffers ping-pong between (keys, vals) and (keys_tmp, vals_tmp); the result
+// ends in the tmp pair when the number of passes is odd (*result_in_tmp).
+hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint32_t* vals_tmp,
+                             const uint32_t* n_dev, int64_t cap, int begin_bit, int end_bit, int iota_vals,
+                             uint32_t* hist, uint32_t* partials, bool* result_in_tmp, hipStream_t st) {
+  const int64_t nb = (cap + kSortBlock - 1) / kSortBlock;
+  bool in_tmp = false;
+  if (nb == 0 || end_bit <= begin_bit) {
+    *result_in_tmp = false;
+    return hipSuccess;
+  }
+  uint32_t* kin = keys;
+  uint32_t* vin = vals;
+  uint32_t* kout = keys_tmp;
+  uint32_t* vout = vals_tmp;
+  bool first = true;
+  for (int shift = begin_bit; shift < end_bit; shift += 8) {
+    const int nbits = min(8, end_bit - shift);
+    const uint32_t dmask = (1u << nbits) - 1u;
+    hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kSortThreads), 0, st, kin, n_dev, cap, shift, dmask,
+                       hist, nb);
+    (void)launch_scan_u32_dev(hist, hist, 256 * nb, nullptr, nullptr, partials, st);
+    hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(kSortThreads), 0, st, kin, vin, kout, vout, n_dev,
+                       cap, shift, dmask, nbits, hist, nb, (first && iota_vals) ? 1 : 0);
+    first = false;
+    std::swap(kin, kout);
+    std::swap(vin, vout);
+    in_tmp = !in_tmp;
+  }
+  *result_in_tmp = in_tmp;
+  return hipGetLastError();
+}
+
+}  // namespace nvgs

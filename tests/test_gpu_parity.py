@@ -1,0 +1,245 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Protocol for discrete decisions (FP32 kernels vs FP64 oracle):
+ (i) same input: the oracle's decision rule applied to the kernel's own FP32
+     upstream values must reproduce the kernel's output exactly;
+ (ii) from scratch: decisions must agree except where the FP64 decision margin
+     is below a small relative threshold (counted and bounded).
+Pixels must be within 1e-4 unless a decision on that pixel was within margin.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests import scenes
+
+pytestmark = pytest.mark.gpu
+
+MARGIN = 1e-5  # relative FP64 margin of frustum / keep decisions below which FP32 may differ
+# Alpha and transmittance decisions at a pixel: the FP32 quadratic form
+# q = d^T conic d of an elongated splat carries a relative error of about
+# kappa * 2^-24 (kappa = condition number of Sigma2D, up to ~1e3 here) and
+# alpha = o e^(-q/2) near 1/255 has q ~ 11, so alpha's relative error reaches
+# ~1e-3 / 2; decisions closer than this to the 1/255 or 1e-4 thresholds may
+# flip.  Depth-order ties: FP32 depth keys resolve ~1e-7 relative.
+MARGIN_ALPHA = 1e-3
+MARGIN_DEPTH = 1e-6
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def nvgs():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2511_19202_amd as m
+    m.lib()
+    return m
+
+
+def make_ctx(nvgs, sc):
+    ctx = nvgs.Context(0)
+    ctx.load_assets(sc.assets)
+    ctx.set_instances(sc.instances)
+    return ctx
+
+
+def logit_tol(z64, scale):
+    return 1e-5 * np.maximum(np.abs(z64), scale)
+
+
+SCENES = {
+    "tiny": lambda: scenes.tiny(),
+    "tiny_w128": lambda: scenes.tiny(n=5000, res=128, width=128),
+    "composed_small": lambda: scenes.composed_small(),
+}
+
+
+@pytest.mark.parametrize("name", list(SCENES))
+def test_query_state_and_logits(nvgs, name):
+    sc = SCENES[name]()
+    log(f"[query] scene={name}")
+    ctx = make_ctx(nvgs, sc)
+    st, lg = ctx.query_visibility(sc.cameras)
+    st = st.cpu().numpy()
+    lg = lg.cpu().numpy().astype(np.float64)
+    ost, olg, omg = oracle.query(sc, want_margin=True)
+    # logits: every pair the oracle queried and the GPU queried
+    both = ~np.isnan(olg) & ~np.isnan(lg)
+    assert both.sum() > 0.3 * (ost > 0).sum()
+    # tolerance with the scale term |wo h3| + |bo| from the oracle's own MLP
+    z64 = olg[both]
+    scale = np.zeros_like(z64)
+    off = sc.pair_offsets()
+    idx = np.flatnonzero(both.ravel())
+    k_of = idx // st.shape[1]
+    p_of = idx % st.shape[1]
+    inst_of = np.searchsorted(off, p_of, side="right") - 1
+    for i in np.unique(inst_of):
+        sel = inst_of == i
+        inst = sc.instances[int(i)]
+        a = sc.assets[inst.asset]
+        cl = oracle.local_camera(inst, sc.cameras[int(k_of[sel][0])], a.mlp.train_focal, a.mlp.d_max)
+        X = oracle.mlp_inputs(a, p_of[sel] - off[i], cl)
+        _, sc_i = oracle.mlp_forward(a.mlp.params, a.mlp.width, X)
+        scale[sel] = sc_i
+    err = np.abs(lg[both] - z64)
+    tol = logit_tol(z64, scale)
+    log(f"[query] {name}: queried {both.sum()}, max |dz| {err.max():.3e}, max err/tol {np.max(err / tol):.3f}")
+    assert np.all(err <= tol)
+    # same input: the keep rule applied to the GPU's logits reproduces its state
+    gq = ~np.isnan(lg)
+    assert np.array_equal(st[gq] == 2, lg[gq] >= 0)
+    assert np.all(st[gq] >= 1)
+    # from scratch: states agree except near-threshold pairs
+    diff = st != ost
+    excused = omg < MARGIN
+    log(f"[query] {name}: state mismatches {diff.sum()} (excused by margin {np.sum(diff & excused)})")
+    assert np.sum(diff & ~excused) == 0
+    assert diff.sum() <= max(2, 1e-5 * st.size)
+    ctx.close()
+
+
+def _render_debug(nvgs, sc, tile, use_mlp=True):
+    ctx = make_ctx(nvgs, sc)
+    img, stats = ctx.render(sc.cameras, tile=tile, use_mlp=use_mlp, keep_debug=True, stats=True)
+    dbg = ctx.debug_buffers()
+    st, lg = ctx.query_visibility(sc.cameras)
+    out = {"img": img.cpu().numpy().astype(np.float64), "stats": stats, "state": st.cpu().numpy(),
+           "logit": lg.cpu().numpy()}
+    for k, v in dbg.items():
+        out[k] = v.cpu().numpy() if hasattr(v, "cpu") else v
+    ctx.close()
+    return out
+
+
+def _same_input_rect(u, v, ex, ey, W, H, T):
+    """Footprint rectangle rule applied in float32 to the kernel's own values."""
+    f = np.float32
+    u, v, ex, ey = (np.asarray(a, np.float32) for a in (u, v, ex, ey))
+    wx = f(1e-4) * ex + f(1e-3)
+    wy = f(1e-4) * ey + f(1e-3)
+    x0 = np.maximum(np.ceil(((u - ex) - f(0.5)) - wx), f(0))
+    x1 = np.minimum(np.floor(((u + ex) - f(0.5)) + wx), f(W - 1))
+    y0 = np.maximum(np.ceil(((v - ey) - f(0.5)) - wy), f(0))
+    y1 = np.minimum(np.floor(((v + ey) - f(0.5)) + wy), f(H - 1))
+    empty = (x0 > x1) | (y0 > y1)
+    return x0.astype(np.int64) // T, x1.astype(np.int64) // T, y0.astype(np.int64) // T, y1.astype(np.int64) // T, empty
+
+
+@pytest.mark.parametrize("name,tile", [("tiny", 16), ("tiny", 8), ("composed_small", 16), ("composed_small", 32)])
+def test_frame_stages_against_oracle(nvgs, name, tile):
+    sc = SCENES[name]()
+    log(f"[frame] scene={name} tile={tile}")
+    r = _render_debug(nvgs, sc, tile)
+    cam = sc.cameras[0]
+    W, H = cam.width, cam.height
+    ns = r["n_splats"]
+    # --- compaction: kept list equals the ordered survivors of the GPU state
+    kept_gpu = r["pair"].astype(np.int64) & 0xFFFFFFFF
+    kept_ref = np.flatnonzero(r["state"][0] == 2)
+    assert ns == len(kept_ref) and np.array_equal(kept_gpu, kept_ref)
+    log(f"[frame] {name}: {ns} splats, {r['n_dup']} tile entries")
+    # --- projection vs FP64 oracle on the same kept list
+    rec, prect = oracle.project(sc, cam, kept_ref)
+    ra, rb, rc = r["rec_a"].astype(np.float64), r["rec_b"].astype(np.float64), r["rec_c"].astype(np.float64)
+    np.testing.assert_allclose(ra[:, 0], rec[:, 0], rtol=0, atol=2e-3)       # u (pixels)
+    np.testing.assert_allclose(ra[:, 1], rec[:, 1], rtol=0, atol=2e-3)       # v
+    np.testing.assert_allclose(rc[:, 1], rec[:, 8], rtol=2e-6)               # depth
+    np.testing.assert_allclose(rb[:, 1], rec[:, 9], rtol=0, atol=0)          # opacity
+    for gi, oi in [(ra[:, 2], 5), (ra[:, 3], 6), (rb[:, 0], 7)]:             # conic
+        scale = np.maximum(np.abs(rec[:, 5]), np.abs(rec[:, 7]))
+        assert np.max(np.abs(gi - rec[:, oi]) / scale) < 5e-5
+    rgb_g = np.stack([rb[:, 2], rb[:, 3], rc[:, 0]], 1)
+    np.testing.assert_allclose(rgb_g, rec[:, 10:13], rtol=0, atol=2e-5)
+    # --- footprint rectangles: same input exactly, from scratch up to margins
+    rect = r["rect"].astype(np.int64) & 0xFFFFFFFF
+    gx0, gy0 = rect[:, 0] & 0xFFFF, rect[:, 0] >> 16
+    gx1, gy1 = rect[:, 1] & 0xFFFF, rect[:, 1] >> 16
+    gn = rect[:, 3]
+    sx0, sx1, sy0, sy1, sempty = _same_input_rect(ra[:, 0], ra[:, 1], rc[:, 2], rc[:, 3], W, H, tile)
+    assert np.array_equal(sempty, gn == 0)
+    ne = ~sempty
+    assert np.array_equal(sx0[ne], gx0[ne]) and np.array_equal(sx1[ne], gx1[ne])
+    assert np.array_equal(sy0[ne], gy0[ne]) and np.array_equal(sy1[ne], gy1[ne])
+    assert np.array_equal(gn[ne], (gx1 - gx0 + 1)[ne] * (gy1 - gy0 + 1)[ne])
+    oempty = (prect[:, 0] > prect[:, 1]) | (prect[:, 2] > prect[:, 3])
+    mism = (oempty != (gn == 0))
+    both = ~oempty & (gn > 0)
+    mism[both] |= (prect[both, 0] // tile != gx0[both]) | (prect[both, 1] // tile != gx1[both]) | \
+                   (prect[both, 2] // tile != gy0[both]) | (prect[both, 3] // tile != gy1[both])
+    log(f"[frame] {name}: rect mismatches vs FP64 {mism.sum()} of {ns}")
+    assert mism.sum() <= max(3, 1e-3 * ns)
+    # --- sort order: the (tile, depth, id) order of the kernel's own keys
+    sk = r["sorted_key"].astype(np.int64) & 0xFFFFFFFF
+    sid = r["sorted_id"].astype(np.int64) & 0xFFFFFFFF
+    tiles_x = r["tiles_x"]
+    ent_t, ent_i = [], []
+    for j in np.flatnonzero(gn > 0):
+        for ty in range(gy0[j], gy1[j] + 1):
+            for tx in range(gx0[j], gx1[j] + 1):
+                ent_t.append(ty * tiles_x + tx)
+                ent_i.append(j)
+    ent_t = np.asarray(ent_t, np.int64)
+    ent_i = np.asarray(ent_i, np.int64)
+    dkey = r["rec_c"][:, 1].view(np.uint32).astype(np.int64)[ent_i]
+    order = np.lexsort((ent_i, dkey, ent_t))
+    assert len(sk) == len(ent_t)
+    assert np.array_equal(sk, ent_t[order]) and np.array_equal(sid, ent_i[order])
+    # --- pixels vs the FP64 oracle from scratch
+    ref = oracle.render_camera(rec, prect, cam, tile, sc.bg)
+    dimg = np.abs(r["img"][0] - ref["image"]).max(axis=2)
+    bad = dimg > 1e-4
+    excused = bad & ((ref["margin"][..., 0] < MARGIN_ALPHA) | (ref["margin"][..., 1] < MARGIN_DEPTH))
+    log(f"[frame] {name}: max pixel err {dimg.max():.3e}, >1e-4: {bad.sum()} (excused {excused.sum()})")
+    assert np.sum(bad & ~excused) == 0
+    assert bad.sum() <= max(4, 1e-3 * dimg.size)
+
+
+def test_image_independent_of_tile_size_and_deterministic(nvgs):
+    sc = SCENES["composed_small"]()
+    ctx = make_ctx(nvgs, sc)
+    imgs = [ctx.render(sc.cameras, tile=t).cpu().numpy() for t in (8, 16, 32)]
+    again = ctx.render(sc.cameras, tile=16).cpu().numpy()
+    ctx.close()
+    assert np.array_equal(imgs[0], imgs[1]) and np.array_equal(imgs[1], imgs[2])
+    assert np.array_equal(imgs[1], again)
+
+
+def test_unculled_render_matches_oracle(nvgs):
+    sc = SCENES["tiny"]()
+    ctx = make_ctx(nvgs, sc)
+    img = ctx.render(sc.cameras, tile=16, use_mlp=False).cpu().numpy()[0].astype(np.float64)
+    ctx.close()
+    ref = oracle.frame(sc, use_mlp=False)
+    d = np.abs(img - ref["images"][0]).max(axis=2)
+    m = ref["margin"][0]
+    bad = d > 1e-4
+    excused = bad & ((m[..., 0] < MARGIN_ALPHA) | (m[..., 1] < MARGIN_DEPTH))
+    log(f"[unculled] max err {d.max():.3e}, bad {bad.sum()} excused {excused.sum()}")
+    assert np.sum(bad & ~excused) == 0
+
+
+def test_empty_frame_and_invalid_arguments(nvgs):
+    sc = SCENES["tiny"]()
+    ctx = make_ctx(nvgs, sc)
+    back = synth.camera((0.0, 3.0, 0.0), target=(0.0, 6.0, 0.0), width=64, height=48)  # looks away
+    img, stats = ctx.render([back], tile=16, bg=(0.25, 0.5, 0.75), stats=True)
+    assert stats["kept"] == 0 and stats["duplicates"] == 0
+    assert np.allclose(img.cpu().numpy(), np.array([0.25, 0.5, 0.75], np.float32))
+    with pytest.raises(nvgs.NvgsError) as e:
+        ctx.render([back], tile=12)
+    assert e.value.status == nvgs.E_INVALID
+    bad = synth.camera((0.0, 3.0, 0.0), width=64, height=48)
+    bad.fovy = float("nan")
+    with pytest.raises(nvgs.NvgsError):
+        ctx.render([bad])
+    ctx.close()
