@@ -30,6 +30,9 @@ sys.path.insert(0, ROOT)
 FLOP_PER_QUERY = {64: 2 * (72 * 64 + 2 * 64 * 64 + 64), 128: 2 * (72 * 128 + 2 * 128 * 128 + 128)}
 MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0}
 HBM_PEAK_GBS = 8000.0
+VALU_LANE_OPS = 256 * 64 * 2.4e9          # non-packed FP32 lane-ops per second
+BLEND_SLOTS_PER_TEST = 20
+BLEND_PEAK_GTESTS = VALU_LANE_OPS / BLEND_SLOTS_PER_TEST / 1e9
 
 
 def calibrate_keep(ctx, sc, frac, precision):
@@ -92,8 +95,11 @@ def roofline(stage_ms, st, width, precision, sh_degree):
         a = n * per / sec / 1e9
         return dom, {"bound": "hbm", "achieved": a, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": a / HBM_PEAK_GBS,
                      "traffic": None}
-    # blend: bounded by exp + FMA issue; work counted as duplicates x tile pixels is an upper bound
-    return dom, {"bound": "alu", "achieved": None, "peak": None, "unit": None, "frac": None, "traffic": None}
+    # blend: one (pixel, tile-list entry) test costs ~20 VALU lane-slots (exp at 4),
+    # so the chip's 256 CU x 64 lanes x 2.4 GHz non-packed issue rate bounds it
+    a = st["blend_tests"] / sec / 1e9
+    p = BLEND_PEAK_GTESTS
+    return dom, {"bound": "alu", "achieved": a, "peak": p, "unit": "Gtests/s", "frac": a / p, "traffic": None}
 
 
 def cpu_baseline(sc, every=16):
@@ -123,7 +129,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--tile", type=int, default=16)
+    ap.add_argument("--tile", type=int, default=0, help="8, 16, 32, or 0 to autotune")
     ap.add_argument("--precision", default="fp32")
     ap.add_argument("--keep", type=float, default=0.65)
     ap.add_argument("--n", type=int, default=250000)
@@ -143,7 +149,15 @@ def main():
     ctx.load_assets(sc.assets)
     ctx.set_instances(sc.instances)
     calibrate_keep(ctx, sc, args.keep, args.precision)
-    kw = dict(tile=args.tile, precision=args.precision)
+    tile = args.tile
+    tune = {}
+    if tile == 0:  # autotune the tile edge on this scene (the image does not depend on it)
+        for T in (8, 16, 32):
+            ctx.render(sc.cameras, tile=T, precision=args.precision)
+            ms = [ctx.render(sc.cameras, tile=T, precision=args.precision, stats=True)[1]["ms"] for _ in range(3)]
+            tune[T] = float(np.median(ms))
+        tile = min(tune, key=tune.get)
+    kw = dict(tile=tile, precision=args.precision)
     t_c, stage_c, st_c, img_c = time_frames(ctx, sc, args.steps, args.warmup, use_mlp=True, **kw)
     img_c = img_c.cpu().numpy()
     t_u, stage_u, st_u, img_u = time_frames(ctx, sc, args.steps, args.warmup, use_mlp=False, **kw)
@@ -153,7 +167,7 @@ def main():
     extra = {}
     for prec in [p for p in args.extra_precisions.split(",") if p]:
         try:
-            t_p, stage_p, st_p, img_p = time_frames(ctx, sc, args.steps, args.warmup, use_mlp=True, tile=args.tile,
+            t_p, stage_p, st_p, img_p = time_frames(ctx, sc, args.steps, args.warmup, use_mlp=True, tile=tile,
                                                     precision=prec)
             extra[prec] = {"fps": 1.0 / t_p, "ms_cull_mlp": stage_p["cull_mlp"],
                            "psnr_vs_fp32_culled_db": psnr(img_p.cpu().numpy(), img_c),
@@ -175,16 +189,17 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "composed-1080p: 4 assets x 250k SH3 Gaussians, 64 instances, 1 camera, "
-                               "width-64 MLP per asset, tile 16",
+                               "width-64 MLP per asset",
                    "gaussians_stored": sum(a.n for a in sc.assets), "instances": len(sc.instances),
                    "pairs": st_c["pairs"], "resolution": "1920x1080", "mlp_precision": args.precision,
-                   "tile": args.tile, "keep_target": args.keep},
+                   "tile": tile, "tile_autotune_ms": tune, "keep_target": args.keep},
         "fps_unculled": 1.0 / t_u,
         "mlp_queries_per_s": st_c["queried"] / (stage_c["cull_mlp"] * 1e-3),
         "gaussians_per_s": st_c["pairs"] / t_c,
         "psnr_culled_vs_unculled_db": psnr(img_c, img_u),
         "in_frustum": st_c["in_frustum"], "queried": st_c["queried"], "kept": st_c["kept"],
         "duplicates": st_c["duplicates"], "duplicates_unculled": st_u["duplicates"],
+        "blend_tests": st_c["blend_tests"], "blend_tests_unculled": st_u["blend_tests"],
         "ms_stage": stage_c, "ms_stage_unculled": stage_u,
         "dominant_kernel": dom,
         "roofline": roof,

@@ -149,6 +149,7 @@ typedef struct nvgs_frame_stats {
   int64_t queried;    /* pairs the MLP was evaluated for */
   int64_t kept;       /* instantiated splats (survived frustum + MLP) */
   int64_t duplicates; /* (splat, tile) entries sorted */
+  int64_t blend_tests; /* (pixel, tile-list entry) pairs examined before each pixel stopped */
   int64_t workspace_bytes;
   float ms_total;     /* frame wall time on the stream (first to last event) */
   float ms_stage[NVGS_NUM_STAGES]; /* per-stage kernel time (HIP events) */

@@ -66,6 +66,8 @@ def lib():
         L.orc_bce_backward.restype = C.c_double
         L.orc_adam_step.argtypes = [C.c_int64, dp, dp, dp, dp, C.c_int64, C.c_double, C.c_double,
                                     C.c_double, C.c_double]
+        L.orc_fp8_scales.argtypes = [dp, C.c_int, dp]
+        L.orc_mlp_forward_q.argtypes = [dp, C.c_int, dp, C.c_int64, C.c_int, dp]
         L.orc_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
         L.orc_splitmix64.restype = C.c_uint64
         _lib = L
@@ -116,6 +118,23 @@ def mlp_forward(params, width: int, X: np.ndarray, want_pre: bool = False):
     pre = np.zeros((B, 3 * width)) if want_pre else None
     lib().orc_mlp_forward(_f64(params), width, in_dim, X, B, z, _ptr(pre), _ptr(sc))
     return (z, sc, pre) if want_pre else (z, sc)
+
+
+PREC = {"bf16": 1, "fp8": 2}
+
+
+def mlp_forward_q(params, width: int, X: np.ndarray, prec: str) -> np.ndarray:
+    """Logits of the MLP with its GEMM operands rounded to BF16 or FP8 E4M3."""
+    X = _f64(X)
+    z = np.zeros(X.shape[0])
+    lib().orc_mlp_forward_q(_f64(params), width, X, X.shape[0], PREC[prec], z)
+    return z
+
+
+def fp8_scales(params, width: int) -> np.ndarray:
+    out = np.zeros(9)
+    lib().orc_fp8_scales(_f64(params), width, out)
+    return out
 
 
 def sh_basis(d, degree: int = 3) -> np.ndarray:

@@ -610,6 +610,122 @@ void orc_adam_step(int64_t n, double* p, const double* g, double* m, double* v, 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Reduced-precision forms of the visibility MLP: operands rounded to BF16 or
+// to OCP FP8 E4M3 where the GEMM chain consumes them, everything else in
+// FP64 (FP32 where the value is stored as FP32).  prec: 1 = BF16, 2 = FP8.
+//   BF16: round-to-nearest-even to 8 significant bits of the float32 value.
+//   E4M3: 4 exponent bits (bias 7), 3 mantissa bits, largest finite 448,
+//         subnormal spacing 2^-9, round-to-nearest-even.
+// FP8 per-layer scales are powers of two: weights by 448 / max|W| of each
+// GEMM, inputs by 448 over an interval bound of the activations
+// (|gamma| <= 1; |h1| <= max_r sum_k |W1[r,k]| + |b1[r]|;
+//  |h2| <= max_r sum_k |W2[r,k]| |h1|max + |b2[r]|).
+static double to_f32(double x) { return (double)(float)x; }
+
+static double to_bf16(double x) {
+  float f = (float)x;
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  uint32_t lsb = (u >> 16) & 1u;
+  u = (u + 0x7FFFu + lsb) & 0xFFFF0000u;
+  std::memcpy(&f, &u, 4);
+  return (double)f;
+}
+
+static double to_e4m3(double x) {
+  double a = std::fabs(x);
+  if (a == 0.0) return 0.0;
+  int e = (int)std::floor(std::log2(a));
+  if (e < -6) e = -6;                       // subnormal range: fixed spacing 2^-9
+  double q = std::ldexp(1.0, e - 3);         // spacing of representable values
+  double m = a / q;
+  double r = std::nearbyint(m);              // ties to even (default rounding mode)
+  double v = std::min(r * q, 448.0);
+  return x < 0 ? -v : v;
+}
+
+static double pow2_floor(double x) { return std::ldexp(1.0, (int)std::floor(std::log2(x))); }
+
+}  // extern "C" (reopened below)
+extern "C" {
+
+// scales[9]: invU, inv2, inv3, saH1, saH2, saG, sw1, sw2, sw3
+void orc_fp8_scales(const double* P, int W, double* scales) {
+  const double* W1 = P;
+  const double* b1 = W1 + (size_t)W * 72;
+  const double* W2 = b1 + W;
+  const double* b2 = W2 + (size_t)W * W;
+  const double* W3 = b2 + W;
+  double m1 = 0, m2 = 0, m3 = 0, B1 = 0, B2 = 0;
+  for (int r = 0; r < W; ++r)
+    for (int k = 0; k < 36; ++k) m1 = std::max(m1, std::fabs(W1[(size_t)r * 72 + k]));
+  for (size_t i = 0; i < (size_t)W * W; ++i) {
+    m2 = std::max(m2, std::fabs(W2[i]));
+    m3 = std::max(m3, std::fabs(W3[i]));
+  }
+  for (int r = 0; r < W; ++r) {
+    double s = std::fabs(b1[r]);
+    for (int k = 0; k < 72; ++k) s += std::fabs(W1[(size_t)r * 72 + k]);
+    B1 = std::max(B1, s);
+  }
+  for (int r = 0; r < W; ++r) {
+    double s = 0;
+    for (int k = 0; k < W; ++k) s += std::fabs(W2[(size_t)r * W + k]);
+    B2 = std::max(B2, s * B1 + std::fabs(b2[r]));
+  }
+  double sw1 = pow2_floor(448.0 / m1), sw2 = pow2_floor(448.0 / m2), sw3 = pow2_floor(448.0 / m3);
+  double sag = pow2_floor(448.0), sa1 = pow2_floor(448.0 / B1), sa2 = pow2_floor(448.0 / B2);
+  double out[9] = {1.0 / (sw1 * sag), 1.0 / (sw2 * sa1), 1.0 / (sw3 * sa2), sa1, sa2, sag, sw1, sw2, sw3};
+  for (int k = 0; k < 9; ++k) scales[k] = out[k];
+}
+
+// X [B][72] encoded inputs (Gaussian half first), z [B]
+void orc_mlp_forward_q(const double* P, int W, const double* X, int64_t B, int prec, double* z) {
+  double sc[9] = {1, 1, 1, 1, 1, 1, 1, 1, 1};
+  if (prec == 2) orc_fp8_scales(P, W, sc);
+  auto q = [&](double v) { return prec == 1 ? to_bf16(v) : to_e4m3(v); };
+  const double* W1 = P;
+  const double* b1 = W1 + (size_t)W * 72;
+  const double* W2 = b1 + W;
+  const double* b2 = W2 + (size_t)W * W;
+  const double* W3 = b2 + W;
+  const double* b3 = W3 + (size_t)W * W;
+  const double* wo = b3 + W;
+  std::vector<double> W1q((size_t)W * 36), W2q((size_t)W * W), W3q((size_t)W * W);
+  for (int r = 0; r < W; ++r)
+    for (int k = 0; k < 36; ++k) W1q[(size_t)r * 36 + k] = q(W1[(size_t)r * 72 + k] * sc[6]);
+  for (size_t i = 0; i < (size_t)W * W; ++i) {
+    W2q[i] = q(W2[i] * sc[7]);
+    W3q[i] = q(W3[i] * sc[8]);
+  }
+#pragma omp parallel for schedule(static)
+  for (int64_t b = 0; b < B; ++b) {
+    const double* x = X + b * 72;
+    std::vector<double> g(36), h1(W), h2(W);
+    for (int k = 0; k < 36; ++k) g[k] = q(to_f32(x[k]) * sc[5]);
+    for (int r = 0; r < W; ++r) {
+      double u = 0, c = b1[r];
+      for (int k = 0; k < 36; ++k) u += W1q[(size_t)r * 36 + k] * g[k];
+      for (int k = 36; k < 72; ++k) c += W1[(size_t)r * 72 + k] * x[k];
+      double h = to_f32(to_f32(u) * sc[0] + to_f32(c));
+      h1[r] = q(to_f32(std::max(h, 0.0)) * sc[3]);
+    }
+    for (int r = 0; r < W; ++r) {
+      double a = 0;
+      for (int k = 0; k < W; ++k) a += W2q[(size_t)r * W + k] * h1[k];
+      h2[r] = q(to_f32(std::max(to_f32(a) * sc[1] + b2[r], 0.0)) * sc[4]);
+    }
+    double zz = wo[W];
+    for (int r = 0; r < W; ++r) {
+      double a = 0;
+      for (int k = 0; k < W; ++k) a += W3q[(size_t)r * W + k] * h2[k];
+      zz += wo[r] * std::max(to_f32(a) * sc[2] + b3[r], 0.0);
+    }
+    z[b] = zz;
+  }
+}
+
 // SplitMix64 (Steele, Lea and Flood, OOPSLA 2014) evaluated at counter i:
 // the i-th output of the generator seeded with `seed`.
 uint64_t orc_splitmix64(uint64_t seed, uint64_t i) {

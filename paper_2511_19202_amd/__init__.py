@@ -71,7 +71,8 @@ STAGES = ["setup", "cull_mlp", "compact", "project", "depth_sort", "bin", "tile_
 
 class FrameStats(C.Structure):
     _fields_ = [("pairs", C.c_int64), ("in_frustum", C.c_int64), ("queried", C.c_int64), ("kept", C.c_int64),
-                ("duplicates", C.c_int64), ("workspace_bytes", C.c_int64), ("ms_total", C.c_float),
+                ("duplicates", C.c_int64), ("blend_tests", C.c_int64), ("workspace_bytes", C.c_int64),
+                ("ms_total", C.c_float),
                 ("ms_stage", C.c_float * NUM_STAGES)]
 
 
@@ -275,7 +276,8 @@ class Context:
                                        C.byref(fs) if fs is not None else None))
         if stats:
             return rgb, {"pairs": fs.pairs, "in_frustum": fs.in_frustum, "queried": fs.queried, "kept": fs.kept,
-                         "duplicates": fs.duplicates, "workspace_bytes": fs.workspace_bytes, "ms": fs.ms_total,
+                         "duplicates": fs.duplicates, "blend_tests": fs.blend_tests,
+                         "workspace_bytes": fs.workspace_bytes, "ms": fs.ms_total,
                          "ms_stage": dict(zip(STAGES, list(fs.ms_stage)))}
         return rgb
 

@@ -57,8 +57,8 @@ struct nvgs_ctx {
   // splats and sort buffers
   int64_t cap_splats = 0, cap_dup = 0;
   Buf rec_a, rec_b, rec_c, rect, depth_key, ids, ids_tmp, keys_tmp2, pair_of, cnt, dup_off;
-  Buf keys, vals, keys_tmp, vals_tmp, hist, hist_part, ranges;
-  Buf counters;          // u32 [0] n_splats, [1] n_dup, [2] overflow flags; u64 at [4] in-frustum, [6] queried
+  Buf keys, vals, keys_tmp, vals_tmp, hist, hist_part, ranges, tord;  // tord: tile order (4 arrays)
+  Buf counters;          // u32 [0] n_splats, [1] n_dup, [2] overflow flags; u64 at [4] in-frustum, [6] queried, [8] blend tests
   uint32_t* counters_host = nullptr;
 
   // last frame (debug view)
@@ -193,7 +193,7 @@ nvgs_status plan(nvgs_ctx* ctx, int C) {
       !ensure(ctx, ctx->mask, sizeof(uint32_t) * (w + 1)) || !ensure(ctx, ctx->chunk_cnt, sizeof(uint32_t) * (ch + 1)) ||
       !ensure(ctx, ctx->chunk_off, sizeof(uint32_t) * (ch + 1)) ||
       !ensure(ctx, ctx->scan_part, sizeof(uint32_t) * scan_partials_needed(ch + 1)) ||
-      !ensure(ctx, ctx->cam_dev, sizeof(nvgs_camera) * C) || !ensure(ctx, ctx->counters, sizeof(uint32_t) * 8))
+      !ensure(ctx, ctx->cam_dev, sizeof(nvgs_camera) * C) || !ensure(ctx, ctx->counters, sizeof(uint32_t) * 12))
     return fail(ctx, NVGS_E_NOMEM, "device allocation failed (plan)");
   CK(hipMemcpy(ctx->seg_word_dev.p, ctx->seg_word_base.data(), sizeof(int64_t) * (S + 1), hipMemcpyHostToDevice));
   CK(hipMemcpy(ctx->seg_chunk_dev.p, ctx->seg_chunk_base.data(), sizeof(int64_t) * (S + 1), hipMemcpyHostToDevice));
@@ -219,7 +219,7 @@ nvgs_status upload_cams(nvgs_ctx* ctx, const nvgs_camera* cams, int C) {
 }
 
 nvgs_status read_counters(nvgs_ctx* ctx) {
-  CK(hipMemcpyAsync(ctx->counters_host, ctx->counters.p, sizeof(uint32_t) * 8, hipMemcpyDeviceToHost, ctx->stream));
+  CK(hipMemcpyAsync(ctx->counters_host, ctx->counters.p, sizeof(uint32_t) * 12, hipMemcpyDeviceToHost, ctx->stream));
   CK(hipStreamSynchronize(ctx->stream));
   return NVGS_OK;
 }
@@ -252,7 +252,7 @@ nvgs_status nvgs_create(const nvgs_create_info* info, nvgs_ctx** out) {
   ctx->device = info->device;
   ctx->stream = reinterpret_cast<hipStream_t>(info->stream);
   ctx->alloc = info->allocator;
-  bool ok = hipHostMalloc(reinterpret_cast<void**>(&ctx->counters_host), 8 * sizeof(uint32_t),
+  bool ok = hipHostMalloc(reinterpret_cast<void**>(&ctx->counters_host), 12 * sizeof(uint32_t),
                           hipHostMallocDefault) == hipSuccess;
   for (int e = 0; e < 2 * NVGS_NUM_STAGES && ok; ++e) ok = hipEventCreate(&ctx->ev[e]) == hipSuccess;
   if (!ok) {
@@ -271,7 +271,7 @@ void nvgs_destroy(nvgs_ctx* ctx) {
                 &ctx->items_dev, &ctx->seglist_dev, &ctx->segs_dev, &ctx->c1_dev, &ctx->mask, &ctx->chunk_cnt,
                 &ctx->chunk_off, &ctx->scan_part, &ctx->cam_dev, &ctx->rec_a, &ctx->rec_b, &ctx->rec_c, &ctx->rect,
                 &ctx->depth_key, &ctx->ids, &ctx->ids_tmp, &ctx->keys_tmp2, &ctx->pair_of, &ctx->cnt, &ctx->dup_off,
-                &ctx->keys, &ctx->vals, &ctx->keys_tmp, &ctx->vals_tmp, &ctx->hist, &ctx->hist_part, &ctx->ranges,
+                &ctx->keys, &ctx->vals, &ctx->keys_tmp, &ctx->vals_tmp, &ctx->hist, &ctx->hist_part, &ctx->ranges, &ctx->tord,
                 &ctx->counters};
   for (Buf* b : all) release(ctx, *b);
   for (Buf& b : ctx->op_bufs) release(ctx, b);
@@ -304,7 +304,7 @@ nvgs_status nvgs_load_assets(nvgs_ctx* ctx, const nvgs_asset* a, int32_t n) {
   CK(hipSetDevice(ctx->device));
   CK(hipStreamSynchronize(ctx->stream));
   for (Buf& b : ctx->op_bufs) release(ctx, b);
-  ctx->op_bufs.assign(n, Buf{});
+  ctx->op_bufs.assign(4 * (size_t)n, Buf{});  // per asset: FP32, BF16, FP8 images, FP8 scales
   ctx->assets.assign(a, a + n);
   ctx->adev.assign(n, AssetDev{});
   for (int j = 0; j < n; ++j) {
@@ -315,11 +315,17 @@ nvgs_status nvgs_load_assets(nvgs_ctx* ctx, const nvgs_asset* a, int32_t n) {
     d.mean_scale = x.mlp.mean_scale; d.cam_scale = x.mlp.cam_scale; d.train_focal = x.mlp.train_focal;
     d.d_min = x.mlp.d_min; d.d_max = x.mlp.d_max;
     d.params = x.mlp.params;
-    const size_t nf = mlp_op_f32_floats(width);
-    if (!ensure(ctx, ctx->op_bufs[j], nf * sizeof(float))) return fail(ctx, NVGS_E_NOMEM, "operand image");
-    d.op_f32 = P_<float>(ctx->op_bufs[j]);
-    d.op_bf16 = nullptr; d.op_fp8 = nullptr; d.fp8_scale = nullptr;
-    CK(launch_prepare_mlp(x.mlp.params, width, P_<float>(ctx->op_bufs[j]), nullptr, nullptr, nullptr, ctx->stream));
+    Buf* ob = &ctx->op_bufs[4 * (size_t)j];
+    if (!ensure(ctx, ob[0], mlp_op_f32_floats(width) * sizeof(float)) ||
+        !ensure(ctx, ob[1], mlp_op_bf16_elems(width) * sizeof(uint16_t)) ||
+        !ensure(ctx, ob[2], mlp_op_fp8_bytes(width)) || !ensure(ctx, ob[3], 16 * sizeof(float)))
+      return fail(ctx, NVGS_E_NOMEM, "operand images");
+    d.op_f32 = P_<float>(ob[0]);
+    d.op_bf16 = P_<uint16_t>(ob[1]);
+    d.op_fp8 = P_<uint8_t>(ob[2]);
+    d.fp8_scale = P_<float>(ob[3]);
+    CK(launch_prepare_mlp(x.mlp.params, width, P_<float>(ob[0]), P_<uint16_t>(ob[1]), P_<uint8_t>(ob[2]),
+                          P_<float>(ob[3]), ctx->stream));
   }
   if (!ensure(ctx, ctx->assets_dev, sizeof(AssetDev) * n)) return fail(ctx, NVGS_E_NOMEM, "asset table");
   CK(hipMemcpyAsync(ctx->assets_dev.p, ctx->adev.data(), sizeof(AssetDev) * n, hipMemcpyHostToDevice, ctx->stream));
@@ -367,7 +373,7 @@ nvgs_status nvgs_query_visibility(nvgs_ctx* ctx, const nvgs_camera* cams, int32_
   if (s) return s;
   if ((s = check_cams(ctx, cams, C))) return s;
   if (!state) return fail(ctx, NVGS_E_INVALID, "state: null pointer");
-  if (precision != NVGS_PREC_FP32) return fail(ctx, NVGS_E_INVALID, "precision not supported");
+  if (precision < NVGS_PREC_FP32 || precision > NVGS_PREC_FP8) return fail(ctx, NVGS_E_INVALID, "bad precision");
   CK(hipSetDevice(ctx->device));
   if ((s = plan(ctx, C))) return s;
   if ((s = upload_cams(ctx, cams, C))) return s;
@@ -403,7 +409,8 @@ nvgs_status nvgs_render(nvgs_ctx* ctx, const nvgs_camera* cams, int32_t C, const
   if (!opts || !rgb) return fail(ctx, NVGS_E_INVALID, "render: null opts or rgb");
   const int T = opts->tile;
   if (T != 8 && T != 16 && T != 32) return fail(ctx, NVGS_E_INVALID, "tile must be 8, 16 or 32");
-  if (opts->precision != NVGS_PREC_FP32) return fail(ctx, NVGS_E_INVALID, "precision not supported");
+  if (opts->precision < NVGS_PREC_FP32 || opts->precision > NVGS_PREC_FP8)
+    return fail(ctx, NVGS_E_INVALID, "bad precision");
   const bool record = (opts->flags & NVGS_RENDER_RECORD_CONTRIB) != 0;
   if (record && !opts->contrib) return fail(ctx, NVGS_E_INVALID, "RECORD_CONTRIB needs opts->contrib");
   const bool debug = record || (opts->flags & NVGS_RENDER_KEEP_DEBUG);
@@ -423,7 +430,7 @@ nvgs_status nvgs_render(nvgs_ctx* ctx, const nvgs_camera* cams, int32_t C, const
   uint32_t* counters = P_<uint32_t>(ctx->counters);
   unsigned long long* counts64 = reinterpret_cast<unsigned long long*>(counters + 4);
   STAGE_BEGIN(NVGS_STAGE_SETUP);
-  CK(launch_fill_u32(counters, 0u, 8, st));
+  CK(launch_fill_u32(counters, 0u, 12, st));
   CK(launch_segment_setup(P_<nvgs_camera>(ctx->cam_dev), P_<nvgs_instance>(ctx->inst_dev),
                           P_<AssetDev>(ctx->assets_dev), P_<int64_t>(ctx->inst_off_dev), NI, C, ctx->P,
                           opts->use_mlp ? 1 : 0, P_<int64_t>(ctx->seg_word_dev), P_<int64_t>(ctx->seg_chunk_dev),
@@ -490,7 +497,13 @@ nvgs_status nvgs_render(nvgs_ctx* ctx, const nvgs_camera* cams, int32_t C, const
     if (!ok) return fail(ctx, NVGS_E_NOMEM, "duplicate buffers");
     ctx->cap_dup = cap;
   }
-  if (!ensure(ctx, ctx->ranges, sizeof(uint32_t) * 2 * (size_t)C * n_tiles))
+  const int64_t nkeys = (int64_t)C * n_tiles;
+  if (!ensure(ctx, ctx->ranges, sizeof(uint32_t) * 2 * (size_t)nkeys) ||
+      !ensure(ctx, ctx->tord, sizeof(uint32_t) * 4 * (size_t)nkeys) ||
+      !ensure(ctx, ctx->hist, 4 * radix_hist_words(std::max({ctx->cap_dup, ctx->cap_splats, nkeys}))) ||
+      !ensure(ctx, ctx->hist_part,
+              4 * scan_partials_needed(radix_hist_words(std::max({ctx->cap_dup, ctx->cap_splats, nkeys}))) +
+                  4 * scan_partials_needed(std::max({ctx->cap_dup, ctx->cap_splats, nkeys}))))
     return fail(ctx, NVGS_E_NOMEM, "tile ranges");
   const uint32_t* n_dup_dev = counters + 1;
   STAGE_BEGIN(NVGS_STAGE_BIN);
@@ -506,11 +519,19 @@ nvgs_status nvgs_render(nvgs_ctx* ctx, const nvgs_camera* cams, int32_t C, const
   const uint32_t* sids = in_tmp2 ? P_<uint32_t>(ctx->vals_tmp) : P_<uint32_t>(ctx->vals);
   CK(launch_fill_u32(P_<uint32_t>(ctx->ranges), 0u, 2 * (int64_t)C * n_tiles, st));
   CK(launch_ranges(skeys, n_dup_dev, nd, P_<uint32_t>(ctx->ranges), st));
+  // launch order of the tiles: longest lists first
+  uint32_t* tk = P_<uint32_t>(ctx->tord);
+  CK(launch_tile_keys(P_<uint32_t>(ctx->ranges), nkeys, tk, tk + nkeys, st));
+  bool in_tmp3 = false;
+  CK(launch_radix_sort(tk, tk + nkeys, tk + 2 * nkeys, tk + 3 * nkeys, nullptr, nkeys, 0, 5, 0,
+                       P_<uint32_t>(ctx->hist), P_<uint32_t>(ctx->hist_part), &in_tmp3, st));
+  const uint32_t* tile_order = in_tmp3 ? tk + 3 * nkeys : tk + nkeys;
   STAGE_END(NVGS_STAGE_TILE_SORT);
   STAGE_BEGIN(NVGS_STAGE_BLEND);
-  CK(launch_blend(P_<uint32_t>(ctx->ranges), sids, P_<float4>(ctx->rec_a), P_<float4>(ctx->rec_b),
+  CK(launch_blend(P_<uint32_t>(ctx->ranges), tile_order, sids, P_<float4>(ctx->rec_a), P_<float4>(ctx->rec_b),
                   P_<float4>(ctx->rec_c), P_<uint32_t>(ctx->pair_of), C, W, H, T, tiles_x, tiles_y, opts->bg[0],
-                  opts->bg[1], opts->bg[2], rgb, record ? opts->contrib : nullptr, ctx->P, P_<uint4>(ctx->rect), st));
+                  opts->bg[1], opts->bg[2], rgb, record ? opts->contrib : nullptr,
+                  stats ? reinterpret_cast<unsigned long long*>(counters + 8) : nullptr, st));
   STAGE_END(NVGS_STAGE_BLEND);
 #undef STAGE_BEGIN
 #undef STAGE_END
@@ -535,6 +556,7 @@ nvgs_status nvgs_render(nvgs_ctx* ctx, const nvgs_camera* cams, int32_t C, const
     stats->pairs = (int64_t)C * ctx->P;
     stats->in_frustum = (int64_t)c64[0];
     stats->queried = (int64_t)c64[1];
+    stats->blend_tests = (int64_t)c64[2];
     stats->kept = ns;
     stats->duplicates = nd;
     stats->workspace_bytes = (int64_t)ctx->workspace;

@@ -118,9 +118,10 @@ hipError_t launch_emit(const uint32_t* sorted_ids, const uint4* rect, const uint
                        uint32_t* keys, uint32_t* vals, uint32_t* overflow, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
 hipError_t launch_ranges(const uint32_t* keys, const uint32_t* n_dev, int64_t cap, uint32_t* ranges, hipStream_t st);
-hipError_t launch_blend(const uint32_t* ranges, const uint32_t* ids, const float4* rec_a, const float4* rec_b,
-                        const float4* rec_c, const uint32_t* pair_of, int C, int W, int H, int tile, int tiles_x,
-                        int tiles_y, float bg0, float bg1, float bg2, float* rgb, float* contrib, int64_t P,
-                        const uint4* rect, hipStream_t st);
+hipError_t launch_tile_keys(const uint32_t* ranges, int64_t n, uint32_t* keys, uint32_t* vals, hipStream_t st);
+hipError_t launch_blend(const uint32_t* ranges, const uint32_t* order, const uint32_t* ids, const float4* rec_a,
+                        const float4* rec_b, const float4* rec_c, const uint32_t* pair_of, int C, int W, int H,
+                        int tile, int tiles_x, int tiles_y, float bg0, float bg1, float bg2, float* rgb,
+                        float* contrib, unsigned long long* work, hipStream_t st);
 
 }  // namespace nvgs

@@ -1,6 +1,7 @@
 // Per-frame steps 1-2 of the NVGS renderer (Sec. 3.3): frustum culling of
 // every (camera, instance, Gaussian) pair on the Gaussian mean, and the
-// visibility-MLP query for the in-frustum pairs, on gfx950 MFMA.
+// visibility-MLP query for the in-frustum pairs, on gfx950 MFMA, with FP32,
+// BF16 or FP8 (OCP E4M3) operands and FP32 accumulation.
 //
 // Design (MI355X-first):
 //  * Layer 1 is linear in the 72 encoded inputs, which split into the 36
@@ -10,12 +11,16 @@
 //    segment (in FP64).  The Gaussian half U = W1u gamma(mu) does not depend
 //    on the instance, so one work-group computes it once for a chunk of 256
 //    Gaussians and reuses it, in registers, for every segment of that asset.
-//  * Hidden layers run on v_mfma_f32_32x32x2_f32 with the pairs as the N
+//  * Hidden layers run on 32x32 MFMA tiles with the pairs as the N
 //    dimension.  The accumulator of one layer is used directly as the B
 //    operand of the next: the contraction index is permuted to follow the
 //    accumulator register order and the weights are stored pre-permuted in
-//    LDS (operand image built once per asset), so activations never leave
+//    LDS (an operand image built once per asset), so activations never leave
 //    registers.
+//  * FP8 uses power-of-two per-layer scales: weights by their maximum,
+//    activations by a rigorous interval bound derived from the weights
+//    (|gamma| <= 1 propagates through |W| row sums), so no value saturates;
+//    dequantisation is one multiply in the epilogue.
 //  * Per 32 pairs a wave-uniform ballot skips the MLP when no pair is in the
 //    frustum.  The keep decisions are written as 32-pair bit words plus one
 //    count per 256-pair chunk for the ordered compaction that follows.
@@ -24,57 +29,206 @@
 namespace nvgs {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
-
-constexpr int kK1 = 18;  // K=2 steps over the 36 Gaussian features of layer 1
-
-// floats in the FP32 operand image of a width-W MLP
-__host__ __device__ constexpr int op_f32_size(int W) { return ((36 * W + 2 * W * W + 3 * W + 1) + 3) / 4 * 4; }
-
-size_t mlp_op_f32_floats(int width) { return (size_t)op_f32_size(width); }
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
 
 // ---------------------------------------------------------------------------
-// operand image: W1u [NT][18][64], W2p [NT][KS][64], W3p [NT][KS][64],
-// b2p [2][KS], b3p [2][KS], wop [2][KS], bo
+// operand image of a width-W MLP for precision P (bytes):
+//   W1u  [NT][KS1][64 lanes][EPL]  Gaussian half of layer 1 (36 of 72 inputs)
+//   W2p  [NT][KSH][64][EPL], W3p   hidden layers, contraction index permuted
+//   vec  f32: b2p [2][W/2], b3p [2][W/2], wop [2][W/2], bo, scales[8]
+// EPL = operand elements per lane per MFMA (1 FP32, 8 BF16, 32 FP8).
 // ---------------------------------------------------------------------------
-__global__ void k_prepare_f32(const float* __restrict__ P, int W, float* __restrict__ op) {
-  const int NT = W / 32, KS = W / 2, in1 = 72;
+template <int P>
+struct Prec;
+template <>
+struct Prec<NVGS_PREC_FP32> {
+  static constexpr int EPL = 1, ESZ = 4, K = 2;
+};
+template <>
+struct Prec<NVGS_PREC_BF16> {
+  static constexpr int EPL = 8, ESZ = 2, K = 16;
+};
+template <>
+struct Prec<NVGS_PREC_FP8> {
+  static constexpr int EPL = 32, ESZ = 1, K = 64;
+};
+
+// scale slots of the vec section (FP8 only)
+enum { kInvU = 0, kInv2 = 1, kInv3 = 2, kSaH1 = 3, kSaH2 = 4, kSaG = 5, kSw1 = 6, kSw2 = 7, kSw3 = 8, kNumScales = 9 };
+
+__host__ __device__ constexpr int img_ks1(int K) { return (36 + K - 1) / K; }
+__host__ __device__ constexpr int img_w1_bytes(int W, int K, int EPL, int ESZ) {
+  return (W / 32) * img_ks1(K) * 64 * EPL * ESZ;
+}
+__host__ __device__ constexpr int img_wh_bytes(int W, int K, int EPL, int ESZ) { return (W / 32) * (W / K) * 64 * EPL * ESZ; }
+__host__ __device__ constexpr int img_vec_floats(int W) { return (3 * W + 1 + kNumScales + 3) / 4 * 4; }
+__host__ __device__ constexpr int img_bytes(int W, int K, int EPL, int ESZ) {
+  return img_w1_bytes(W, K, EPL, ESZ) + 2 * img_wh_bytes(W, K, EPL, ESZ) + 4 * img_vec_floats(W);
+}
+template <int P, int W>
+struct Img {
+  using T = Prec<P>;
+  static constexpr int NT = W / 32, KS1 = img_ks1(T::K), KSH = W / T::K;
+  static constexpr int W1 = 0;
+  static constexpr int W2 = img_w1_bytes(W, T::K, T::EPL, T::ESZ);
+  static constexpr int W3 = W2 + img_wh_bytes(W, T::K, T::EPL, T::ESZ);
+  static constexpr int VEC = W3 + img_wh_bytes(W, T::K, T::EPL, T::ESZ);
+  static constexpr int BYTES = img_bytes(W, T::K, T::EPL, T::ESZ);
+};
+
+static size_t img_size(int P, int W) {
+  if (P == NVGS_PREC_FP32) return img_bytes(W, 2, 1, 4);
+  if (P == NVGS_PREC_BF16) return img_bytes(W, 16, 8, 2);
+  return img_bytes(W, 64, 32, 1);
+}
+size_t mlp_op_f32_floats(int width) { return img_size(NVGS_PREC_FP32, width) / 4; }
+size_t mlp_op_bf16_elems(int width) { return img_size(NVGS_PREC_BF16, width) / 2; }
+size_t mlp_op_fp8_bytes(int width) { return img_size(NVGS_PREC_FP8, width); }
+
+__host__ __device__ inline float pow2_floor(float x) {  // largest power of two <= x (x > 0)
+  int e;
+  frexpf(x, &e);
+  return ldexpf(1.f, e - 1);
+}
+
+// FP8 scales: weights by max |W| of each MFMA layer, activations by interval
+// bounds: |gamma| <= 1, |h1| <= max_r (sum_k |W1[r,k]| + |b1[r]|),
+// |h2| <= max_r (sum_k |W2[r,k]| B1 + |b2[r]|).  One 256-thread group.
+__global__ void k_mlp_scales(const float* __restrict__ P, int W, float* __restrict__ scales) {
+  __shared__ float s_red[256];
   const float* W1 = P;
+  const float* b1 = W1 + W * 72;
+  const float* W2 = b1 + W;
+  const float* b2 = W2 + W * W;
+  const float* W3 = b2 + W;
+  auto block_max = [&](float v) {
+    s_red[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if ((int)threadIdx.x < o) s_red[threadIdx.x] = fmaxf(s_red[threadIdx.x], s_red[threadIdx.x + o]);
+      __syncthreads();
+    }
+    float r = s_red[0];
+    __syncthreads();
+    return r;
+  };
+  float m1 = 0.f, m2 = 0.f, m3 = 0.f, r1 = 0.f;
+  for (int i = threadIdx.x; i < W * 36; i += blockDim.x) m1 = fmaxf(m1, fabsf(W1[(i / 36) * 72 + i % 36]));
+  for (int i = threadIdx.x; i < W * W; i += blockDim.x) {
+    m2 = fmaxf(m2, fabsf(W2[i]));
+    m3 = fmaxf(m3, fabsf(W3[i]));
+  }
+  for (int r = threadIdx.x; r < W; r += blockDim.x) {
+    float s = fabsf(b1[r]);
+    for (int k = 0; k < 72; ++k) s += fabsf(W1[r * 72 + k]);
+    r1 = fmaxf(r1, s);
+  }
+  m1 = block_max(m1);
+  m2 = block_max(m2);
+  m3 = block_max(m3);
+  const float B1 = block_max(r1);
+  float r2 = 0.f;
+  for (int r = threadIdx.x; r < W; r += blockDim.x) {
+    float s = 0.f;
+    for (int k = 0; k < W; ++k) s += fabsf(W2[r * W + k]);
+    r2 = fmaxf(r2, s * B1 + fabsf(b2[r]));
+  }
+  const float B2 = block_max(r2);
+  if (threadIdx.x == 0) {
+    const float sw1 = pow2_floor(448.f / fmaxf(m1, 1e-30f)), sw2 = pow2_floor(448.f / fmaxf(m2, 1e-30f));
+    const float sw3 = pow2_floor(448.f / fmaxf(m3, 1e-30f));
+    const float sag = pow2_floor(448.f), sa1 = pow2_floor(448.f / fmaxf(B1, 1e-30f));
+    const float sa2 = pow2_floor(448.f / fmaxf(B2, 1e-30f));
+    scales[kInvU] = 1.f / (sw1 * sag);
+    scales[kInv2] = 1.f / (sw2 * sa1);
+    scales[kInv3] = 1.f / (sw3 * sa2);
+    scales[kSaH1] = sa1;
+    scales[kSaH2] = sa2;
+    scales[kSaG] = sag;
+    scales[kSw1] = sw1;
+    scales[kSw2] = sw2;
+    scales[kSw3] = sw3;
+  }
+}
+
+__device__ inline uint8_t to_fp8(float v) {
+  return (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(v, 0.f, 0, false) & 0xff);
+}
+
+template <int P>
+__global__ void k_prepare(const float* __restrict__ Pm, int W, const float* __restrict__ scales,
+                          uint8_t* __restrict__ img) {
+  using T = Prec<P>;
+  constexpr int EPL = T::EPL, ESZ = T::ESZ, K = T::K;
+  const int NT = W / 32, KS1 = img_ks1(K), KSH = W / K;
+  const int in1 = 72;
+  const float* W1 = Pm;
   const float* b1 = W1 + W * in1;
   const float* W2 = b1 + W;
   const float* b2 = W2 + W * W;
   const float* W3 = b2 + W;
   const float* b3 = W3 + W * W;
   const float* wo = b3 + W;
-  const float bo = wo[W];
-  (void)b1;
-  const int total = op_f32_size(W);
+  const int n1 = NT * KS1 * 64 * EPL, nh = NT * KSH * 64 * EPL;
+  const int nvec = img_vec_floats(W);
+  const int total = n1 + 2 * nh + nvec;
+  const float sw1 = P == NVGS_PREC_FP8 ? scales[kSw1] : 1.f;
+  const float sw2 = P == NVGS_PREC_FP8 ? scales[kSw2] : 1.f;
+  const float sw3 = P == NVGS_PREC_FP8 ? scales[kSw3] : 1.f;
   for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += gridDim.x * blockDim.x) {
-    float v = 0.f;
-    int o = idx;
-    if (o < NT * kK1 * 64) {
-      int lane = o % 64, s = (o / 64) % kK1, t = o / (64 * kK1);
-      v = W1[(32 * t + lane % 32) * in1 + 2 * s + lane / 32];
-    } else if ((o -= NT * kK1 * 64) < 2 * NT * KS * 64) {
-      const float* Wl = o < NT * KS * 64 ? W2 : W3;
-      o %= NT * KS * 64;
-      int lane = o % 64, s = (o / 64) % KS, t = o / (64 * KS);
-      v = Wl[(32 * t + lane % 32) * W + hid_feature(s, lane / 32)];
-    } else if ((o -= 2 * NT * KS * 64) < 6 * KS) {
-      int which = o / (2 * KS), r = o % (2 * KS), g = r / KS, q = r % KS;
-      const float* vec = which == 0 ? b2 : which == 1 ? b3 : wo;
-      v = vec[hid_feature(q, g)];
-    } else if (o == 6 * KS) {
-      v = bo;
+    if (idx < n1 + 2 * nh) {
+      float v;
+      int o = idx, base = 0;
+      if (o < n1) {
+        const int j = o % EPL, lane = (o / EPL) % 64, s = (o / (EPL * 64)) % KS1, t = o / (EPL * 64 * KS1);
+        const int k = s * 2 * EPL + (lane / 32) * EPL + j;  // Gaussian feature (natural order)
+        v = k < 36 ? W1[(32 * t + lane % 32) * in1 + k] * sw1 : 0.f;
+      } else {
+        o -= n1;
+        const bool third = o >= nh;
+        o %= nh;
+        base = n1 + (third ? nh : 0);
+        const int j = o % EPL, lane = (o / EPL) % 64, s = (o / (EPL * 64)) % KSH, t = o / (EPL * 64 * KSH);
+        v = (third ? W3 : W2)[(32 * t + lane % 32) * W + hid_feature(s * EPL + j, lane / 32)] * (third ? sw3 : sw2);
+      }
+      (void)base;
+      if (P == NVGS_PREC_FP32) reinterpret_cast<float*>(img)[idx] = v;
+      if (P == NVGS_PREC_BF16) reinterpret_cast<__bf16*>(img)[idx] = (__bf16)v;
+      if (P == NVGS_PREC_FP8) img[idx] = to_fp8(v);
+    } else {
+      const int e = idx - (n1 + 2 * nh);
+      float v = 0.f;
+      const int KQ = W / 2;
+      if (e < 6 * KQ) {
+        const int which = e / (2 * KQ), r = e % (2 * KQ), g = r / KQ, q = r % KQ;
+        const float* vec = which == 0 ? b2 : which == 1 ? b3 : wo;
+        v = vec[hid_feature(q, g)];
+      } else if (e == 6 * KQ) {
+        v = wo[W];
+      } else if (e - 6 * KQ - 1 < kNumScales) {
+        v = P == NVGS_PREC_FP8 ? scales[e - 6 * KQ - 1] : 1.f;
+      }
+      reinterpret_cast<float*>(img + (size_t)(n1 + 2 * nh) * ESZ)[e] = v;
     }
-    op[idx] = v;
   }
 }
 
 hipError_t launch_prepare_mlp(const float* params, int width, float* op_f32, uint16_t* op_bf16, uint8_t* op_fp8,
                               float* fp8_scale, hipStream_t st) {
-  (void)op_bf16; (void)op_fp8; (void)fp8_scale;
-  int total = op_f32_size(width);
-  hipLaunchKernelGGL(k_prepare_f32, dim3((total + 255) / 256), dim3(256), 0, st, params, width, op_f32);
+  const int W = width;
+  auto grid = [](size_t n) { return dim3((unsigned)((n + 255) / 256)); };
+  if (op_f32)
+    hipLaunchKernelGGL(k_prepare<NVGS_PREC_FP32>, grid(img_size(NVGS_PREC_FP32, W) / 4), dim3(256), 0, st, params, W,
+                       (const float*)nullptr, reinterpret_cast<uint8_t*>(op_f32));
+  if (op_bf16)
+    hipLaunchKernelGGL(k_prepare<NVGS_PREC_BF16>, grid(img_size(NVGS_PREC_BF16, W) / 2), dim3(256), 0, st, params, W,
+                       (const float*)nullptr, reinterpret_cast<uint8_t*>(op_bf16));
+  if (op_fp8 && fp8_scale) {
+    hipLaunchKernelGGL(k_mlp_scales, dim3(1), dim3(256), 0, st, params, W, fp8_scale);
+    hipLaunchKernelGGL(k_prepare<NVGS_PREC_FP8>, grid(img_size(NVGS_PREC_FP8, W)), dim3(256), 0, st, params, W,
+                       (const float*)fp8_scale, op_fp8);
+  }
   return hipGetLastError();
 }
 
@@ -175,68 +329,134 @@ hipError_t launch_segment_setup(const nvgs_camera* cams_dev, const nvgs_instance
   return hipGetLastError();
 }
 
+
 // ---------------------------------------------------------------------------
-// FP32 cull + MLP kernel
+// cull + MLP kernel
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ bool frustum(const SegRec& R, const float mu[3], float* pz_out) {
-  float px = fmaf(R.M[0], mu[0], fmaf(R.M[1], mu[1], fmaf(R.M[2], mu[2], R.M[3])));
-  float py = fmaf(R.M[4], mu[0], fmaf(R.M[5], mu[1], fmaf(R.M[6], mu[2], R.M[7])));
-  float pz = fmaf(R.M[8], mu[0], fmaf(R.M[9], mu[1], fmaf(R.M[10], mu[2], R.M[11])));
-  if (pz_out) *pz_out = pz;
+__device__ __forceinline__ bool frustum(const SegRec& R, const float mu[3]) {
+  const float px = fmaf(R.M[0], mu[0], fmaf(R.M[1], mu[1], fmaf(R.M[2], mu[2], R.M[3])));
+  const float py = fmaf(R.M[4], mu[0], fmaf(R.M[5], mu[1], fmaf(R.M[6], mu[2], R.M[7])));
+  const float pz = fmaf(R.M[8], mu[0], fmaf(R.M[9], mu[1], fmaf(R.M[10], mu[2], R.M[11])));
   return pz > R.near_plane && fabsf(px) <= R.tanx_g * pz && fabsf(py) <= R.tany_g * pz;
 }
 
-template <int W, int NB>
-__device__ __forceinline__ void hidden_f32(const float* __restrict__ Wp, const float* __restrict__ bp,
-                                           const float (&h)[NB][W / 2], float (&o)[NB][W / 2], int lane, int grp) {
-  constexpr int NT = W / 32, KS = W / 2;
+// MFMA operand of one lane for precision P: load from the LDS image, pack
+// from FP32 values, multiply-accumulate a 32x32 tile.
+template <int P>
+struct Mfma;
+template <>
+struct Mfma<NVGS_PREC_FP32> {
+  using Op = float;
+  static __device__ __forceinline__ Op load(const uint8_t* p, int idx) {
+    return reinterpret_cast<const float*>(p)[idx];
+  }
+  static __device__ __forceinline__ Op pack(const float* v) { return v[0]; }
+  static __device__ __forceinline__ f32x16 mma(Op a, Op b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Mfma<NVGS_PREC_BF16> {
+  using Op = bf16x8;
+  static __device__ __forceinline__ Op load(const uint8_t* p, int idx) {
+    return reinterpret_cast<const bf16x8*>(p)[idx];
+  }
+  static __device__ __forceinline__ Op pack(const float* v) {
+    Op r;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) r[j] = (__bf16)v[j];
+    return r;
+  }
+  static __device__ __forceinline__ f32x16 mma(Op a, Op b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Mfma<NVGS_PREC_FP8> {
+  using Op = i32x8;
+  static __device__ __forceinline__ Op load(const uint8_t* p, int idx) {
+    return reinterpret_cast<const i32x8*>(p)[idx];
+  }
+  static __device__ __forceinline__ Op pack(const float* v) {
+    Op r;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      int w = __builtin_amdgcn_cvt_pk_fp8_f32(v[4 * q], v[4 * q + 1], 0, false);
+      r[q] = __builtin_amdgcn_cvt_pk_fp8_f32(v[4 * q + 2], v[4 * q + 3], w, true);
+    }
+    return r;
+  }
+  static __device__ __forceinline__ f32x16 mma(Op a, Op b, f32x16 c) {
+    // E4M3 x E4M3, block scales 2^0 (the per-layer scales are applied in the epilogue)
+    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, 127, 0, 127);
+  }
+};
+
+// one hidden layer: o = relu(inv * (Wp h) + b), h and o in accumulator order
+template <int P, int W, int NB>
+__device__ __forceinline__ void hidden(const uint8_t* __restrict__ Wp, const float* __restrict__ bp, float inv,
+                                       float in_scale, const float (&h)[NB][W / 2], float (&o)[NB][W / 2], int lane,
+                                       int grp) {
+  using M = Mfma<P>;
+  constexpr int EPL = Prec<P>::EPL, NT = W / 32, KSH = W / Prec<P>::K, KQ = W / 2;
   f32x16 acc[NB][NT];
 #pragma unroll
   for (int b = 0; b < NB; ++b)
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[b][t] = (f32x16){0};
 #pragma unroll
-  for (int s = 0; s < KS; ++s) {
-    float a[NT];
+  for (int s = 0; s < KSH; ++s) {
+    typename M::Op a[NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) a[t] = Wp[(t * KS + s) * 64 + lane];
+    for (int t = 0; t < NT; ++t) a[t] = M::load(Wp, (t * KSH + s) * 64 + lane);
 #pragma unroll
-    for (int b = 0; b < NB; ++b)
+    for (int b = 0; b < NB; ++b) {
+      float v[EPL];
 #pragma unroll
-      for (int t = 0; t < NT; ++t) acc[b][t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[t], h[b][s], acc[b][t], 0, 0, 0);
+      for (int j = 0; j < EPL; ++j) v[j] = h[b][s * EPL + j] * in_scale;
+      const typename M::Op hb = M::pack(v);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[b][t] = M::mma(a[t], hb, acc[b][t]);
+    }
   }
-  const float* bg = bp + grp * KS;
+  const float* bg = bp + grp * KQ;
 #pragma unroll
   for (int b = 0; b < NB; ++b)
 #pragma unroll
-    for (int q = 0; q < KS; ++q) o[b][q] = fmaxf(acc[b][q / 16][q % 16] + bg[q], 0.f);
+    for (int q = 0; q < KQ; ++q) o[b][q] = fmaxf(fmaf(acc[b][q / 16][q % 16], inv, bg[q]), 0.f);
 }
 
-template <int W, int NB, int WAVES, int MODE>
-__global__ __launch_bounds__(64 * WAVES) void k_cull_mlp_f32(
+template <int P, int W, int NB, int WAVES, int MODE>
+__global__ __launch_bounds__(64 * WAVES) void k_cull_mlp(
     const AssetDev* __restrict__ assets, const WorkItem* __restrict__ items, const int32_t* __restrict__ seglist,
     const SegRec* __restrict__ segs, const float* __restrict__ c1perm, int c1_stride, uint32_t* __restrict__ mask,
     uint32_t* __restrict__ chunk_count, uint8_t* __restrict__ state, float* __restrict__ logits,
     unsigned long long* __restrict__ frame_counts) {
   static_assert(WAVES * NB * 32 == kChunk, "a work-group covers one compaction chunk");
-  constexpr int NT = W / 32, KS = W / 2;
-  constexpr int OPN = op_f32_size(W);
-  __shared__ __attribute__((aligned(16))) float lds[OPN];
+  using M = Mfma<P>;
+  using I = Img<P, W>;
+  constexpr int EPL = Prec<P>::EPL, NT = W / 32, KQ = W / 2, KS1 = I::KS1;
+  __shared__ __attribute__((aligned(16))) uint8_t lds[I::BYTES];
   __shared__ uint32_t s_cnt[2];
   __shared__ uint32_t s_tot[2];
   const WorkItem it = items[blockIdx.x];
   const AssetDev* A = assets + it.asset;
   {
-    const float4* src = reinterpret_cast<const float4*>(A->op_f32);
-    for (int k = threadIdx.x; k < OPN / 4; k += 64 * WAVES) reinterpret_cast<float4*>(lds)[k] = src[k];
+    const uint8_t* img = P == NVGS_PREC_FP32 ? reinterpret_cast<const uint8_t*>(A->op_f32)
+                         : P == NVGS_PREC_BF16 ? reinterpret_cast<const uint8_t*>(A->op_bf16)
+                                               : A->op_fp8;
+    const uint4* src = reinterpret_cast<const uint4*>(img);
+    for (int k = threadIdx.x; k < I::BYTES / 16; k += 64 * WAVES) reinterpret_cast<uint4*>(lds)[k] = src[k];
   }
   if (threadIdx.x < 2) s_cnt[threadIdx.x] = s_tot[threadIdx.x] = 0;
-  const float* W1u = lds;
-  const float* W2p = W1u + NT * kK1 * 64;
-  const float* W3p = W2p + NT * KS * 64;
-  const float* b2p = W3p + NT * KS * 64;
-  const float* b3p = b2p + 2 * KS;
-  const float* wop = b3p + 2 * KS;
+  const uint8_t* W1u = lds + I::W1;
+  const uint8_t* W2p = lds + I::W2;
+  const uint8_t* W3p = lds + I::W3;
+  const float* vec = reinterpret_cast<const float*>(lds + I::VEC);
+  const float* b2p = vec;
+  const float* b3p = vec + 2 * KQ;
+  const float* wop = vec + 4 * KQ;
+  const float* scl = vec + 6 * KQ + 1;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int ncol = lane & 31, grp = lane >> 5;
   const int64_t n = A->n;
@@ -246,30 +466,44 @@ __global__ __launch_bounds__(64 * WAVES) void k_cull_mlp_f32(
   bool valid[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
-    int64_t g = g0 + 32 * b + ncol;
+    const int64_t g = g0 + 32 * b + ncol;
     valid[b] = g < n;
     for (int j = 0; j < 3; ++j) mu[b][j] = valid[b] ? A->mean[j * n + g] : 0.f;
   }
   __syncthreads();
-  const float bo = wop[2 * KS];
-  // layer 1, Gaussian half: U = W1u gamma(mean_scale * mu)
+  const float bo = wop[2 * KQ];
+  const float invU = P == NVGS_PREC_FP8 ? scl[kInvU] : 1.f;
+  const float inv2 = P == NVGS_PREC_FP8 ? scl[kInv2] : 1.f;
+  const float inv3 = P == NVGS_PREC_FP8 ? scl[kInv3] : 1.f;
+  const float saG = P == NVGS_PREC_FP8 ? scl[kSaG] : 1.f;
+  const float saH1 = P == NVGS_PREC_FP8 ? scl[kSaH1] : 1.f;
+  const float saH2 = P == NVGS_PREC_FP8 ? scl[kSaH2] : 1.f;
+  // layer 1, Gaussian half: U = W1u gamma(mean_scale * mu), features in the
+  // natural order k = s*2*EPL + grp*EPL + j (zero beyond 36)
   f32x16 U[NB][NT];
 #pragma unroll
   for (int b = 0; b < NB; ++b)
 #pragma unroll
     for (int t = 0; t < NT; ++t) U[b][t] = (f32x16){0};
 #pragma unroll
-  for (int s = 0; s < kK1; ++s) {
-    const int j = s / 6, band = s % 6;
-    float a[NT];
+  for (int s = 0; s < KS1; ++s) {
+    typename M::Op a[NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) a[t] = W1u[(t * kK1 + s) * 64 + lane];
+    for (int t = 0; t < NT; ++t) a[t] = M::load(W1u, (t * KS1 + s) * 64 + lane);
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-      float x = ldexpf(msc * mu[b][j], band);
-      float e = grp ? cospif(x) : sinpif(x);
+      float e[EPL];
 #pragma unroll
-      for (int t = 0; t < NT; ++t) U[b][t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[t], e, U[b][t], 0, 0, 0);
+      for (int j = 0; j < EPL; ++j) {
+        const int k = s * 2 * EPL + grp * EPL + j;  // grp is 0/1: the compiler keeps both paths cheap
+        const int coord = k / 12, band = (k % 12) / 2;
+        const float x = ldexpf(msc * mu[b][min(coord, 2)], band);
+        const float v = (k % 2) ? cospif(x) : sinpif(x);
+        e[j] = k < 36 ? v * saG : 0.f;
+      }
+      const typename M::Op eb = M::pack(e);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) U[b][t] = M::mma(a[t], eb, U[b][t]);
     }
   }
   int parity = 0;
@@ -281,7 +515,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_cull_mlp_f32(
     bool any = false;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-      in[b] = valid[b] && frustum(R, mu[b], nullptr);
+      in[b] = valid[b] && frustum(R, mu[b]);
       any |= in[b];
     }
     const bool wave_any = __ballot(any) != 0;
@@ -296,20 +530,20 @@ __global__ __launch_bounds__(64 * WAVES) void k_cull_mlp_f32(
     float z[NB];
     bool keep[NB];
     if (query && wave_any) {
-      const float* c1 = c1perm + (size_t)seg * c1_stride + grp * KS;
-      float h[NB][KS], h2[NB][KS];
+      const float* c1 = c1perm + (size_t)seg * c1_stride + grp * KQ;
+      float h[NB][KQ], h2[NB][KQ];
 #pragma unroll
       for (int b = 0; b < NB; ++b)
 #pragma unroll
-        for (int q = 0; q < KS; ++q) h[b][q] = fmaxf(U[b][q / 16][q % 16] + c1[q], 0.f);
-      hidden_f32<W, NB>(W2p, b2p, h, h2, lane, grp);
-      hidden_f32<W, NB>(W3p, b3p, h2, h, lane, grp);
-      const float* wg = wop + grp * KS;
+        for (int q = 0; q < KQ; ++q) h[b][q] = fmaxf(fmaf(U[b][q / 16][q % 16], invU, c1[q]), 0.f);
+      hidden<P, W, NB>(W2p, b2p, inv2, saH1, h, h2, lane, grp);
+      hidden<P, W, NB>(W3p, b3p, inv3, saH2, h2, h, lane, grp);
+      const float* wg = wop + grp * KQ;
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         float part = 0.f;
 #pragma unroll
-        for (int q = 0; q < KS; ++q) part = fmaf(wg[q], h[b][q], part);
+        for (int q = 0; q < KQ; ++q) part = fmaf(wg[q], h[b][q], part);
         z[b] = part + __shfl_xor(part, 32) + bo;
         keep[b] = in[b] && z[b] >= 0.f;
       }
@@ -323,7 +557,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_cull_mlp_f32(
     uint32_t cnt = 0;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-      uint32_t word = (uint32_t)__ballot(keep[b]);
+      const uint32_t word = (uint32_t)__ballot(keep[b]);
       cnt += __popc(word);
       if (lane == 0 && g0 + 32 * b < n) mask[R.word_base + (g0 >> 5) + b] = word;
     }
@@ -332,7 +566,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_cull_mlp_f32(
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         if (valid[b]) {
-          int64_t idx = R.pair_base + g0 + 32 * b + ncol;
+          const int64_t idx = R.pair_base + g0 + 32 * b + ncol;
           state[idx] = keep[b] ? 2 : (in[b] ? 1 : 0);
           logits[idx] = (in[b] && query) ? z[b] : __builtin_nanf("");
         }
@@ -357,16 +591,16 @@ __global__ __launch_bounds__(64 * WAVES) void k_cull_mlp_f32(
   }
 }
 
-template <int W, int NB, int WAVES>
-static hipError_t launch_f32(const AssetDev* assets, const WorkItem* items, int64_t n_items, const int32_t* seglist,
-                             const SegRec* segs, const float* c1perm, int c1_stride, int mode, uint32_t* mask,
-                             uint32_t* chunk_count, uint8_t* state, float* logits, unsigned long long* counts,
-                             hipStream_t st) {
+template <int P, int W, int NB, int WAVES>
+static hipError_t launch_t(const AssetDev* assets, const WorkItem* items, int64_t n_items, const int32_t* seglist,
+                           const SegRec* segs, const float* c1perm, int c1_stride, int mode, uint32_t* mask,
+                           uint32_t* chunk_count, uint8_t* state, float* logits, unsigned long long* counts,
+                           hipStream_t st) {
   if (mode == 1)
-    hipLaunchKernelGGL((k_cull_mlp_f32<W, NB, WAVES, 1>), dim3((unsigned)n_items), dim3(64 * WAVES), 0, st, assets,
+    hipLaunchKernelGGL((k_cull_mlp<P, W, NB, WAVES, 1>), dim3((unsigned)n_items), dim3(64 * WAVES), 0, st, assets,
                        items, seglist, segs, c1perm, c1_stride, mask, chunk_count, state, logits, counts);
   else
-    hipLaunchKernelGGL((k_cull_mlp_f32<W, NB, WAVES, 0>), dim3((unsigned)n_items), dim3(64 * WAVES), 0, st, assets,
+    hipLaunchKernelGGL((k_cull_mlp<P, W, NB, WAVES, 0>), dim3((unsigned)n_items), dim3(64 * WAVES), 0, st, assets,
                        items, seglist, segs, c1perm, c1_stride, mask, chunk_count, state, logits, counts);
   return hipGetLastError();
 }
@@ -376,14 +610,22 @@ hipError_t launch_cull_mlp(const AssetDev* assets_dev, const AssetDev* assets_ho
                            const float* c1perm, int max_width, int width, int precision, int mode, uint32_t* mask,
                            uint32_t* chunk_count, uint8_t* state, float* logits, unsigned long long* counts,
                            hipStream_t st) {
-  (void)assets_host; (void)n_assets; (void)precision;
+  (void)assets_host; (void)n_assets;
   if (n_items == 0) return hipSuccess;
-  if (width == 64)
-    return launch_f32<64, 2, 4>(assets_dev, items, n_items, seglist, segs, c1perm, max_width, mode, mask,
-                                chunk_count, state, logits, counts, st);
-  if (width == 128)
-    return launch_f32<128, 1, 8>(assets_dev, items, n_items, seglist, segs, c1perm, max_width, mode, mask,
-                                 chunk_count, state, logits, counts, st);
+#define NVGS_LAUNCH(P, W, NB, WV)                                                                                   \
+  return launch_t<P, W, NB, WV>(assets_dev, items, n_items, seglist, segs, c1perm, max_width, mode, mask,          \
+                                chunk_count, state, logits, counts, st)
+  if (precision == NVGS_PREC_FP32) {
+    if (width == 64) NVGS_LAUNCH(NVGS_PREC_FP32, 64, 2, 4);
+    if (width == 128) NVGS_LAUNCH(NVGS_PREC_FP32, 128, 1, 8);
+  } else if (precision == NVGS_PREC_BF16) {
+    if (width == 64) NVGS_LAUNCH(NVGS_PREC_BF16, 64, 2, 4);
+    if (width == 128) NVGS_LAUNCH(NVGS_PREC_BF16, 128, 1, 8);
+  } else if (precision == NVGS_PREC_FP8) {
+    if (width == 64) NVGS_LAUNCH(NVGS_PREC_FP8, 64, 2, 4);
+    if (width == 128) NVGS_LAUNCH(NVGS_PREC_FP8, 128, 1, 8);
+  }
+#undef NVGS_LAUNCH
   return hipErrorInvalidValue;
 }
 

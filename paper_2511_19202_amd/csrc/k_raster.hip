@@ -323,33 +323,69 @@ hipError_t launch_ranges(const uint32_t* keys, const uint32_t* n_dev, int64_t ca
 }
 
 // ---------------------------------------------------------------------------
+// tile order: longest tile lists first (one stable radix pass on a 5-bit
+// log2 bucket of the list length), so the heaviest tiles do not start last
+// ---------------------------------------------------------------------------
+__global__ void k_tile_keys(const uint32_t* __restrict__ ranges, int64_t n, uint32_t* __restrict__ keys,
+                            uint32_t* __restrict__ vals) {
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t len = ranges[2 * j + 1] - ranges[2 * j];
+    keys[j] = 31u - (uint32_t)(32 - __clz(len));  // 31 - bit length: longer lists get smaller keys
+    vals[j] = (uint32_t)j;
+  }
+}
+
+hipError_t launch_tile_keys(const uint32_t* ranges, int64_t n, uint32_t* keys, uint32_t* vals, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_tile_keys, dim3(grid), dim3(256), 0, st, ranges, n, keys, vals);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // front-to-back compositing, one work-group per (camera, tile)
+//
+// Each wave owns an 8x8 block of pixels (one lane per pixel; the 32-pixel
+// tile gives every lane four blocks).  Splats are staged in LDS 256 at a
+// time; the next batch is fetched into registers while the current one is
+// composited.  Per (pixel, splat) the quadratic form is compared against a
+// conservative per-splat bound log2(1/(255 o)) - 0.01 before the exponential:
+// below it alpha is certainly under 1/255, so the skip decision is the same
+// as evaluating alpha.  A wave skips splats whose alpha footprint box misses
+// its pixel block.
 // ---------------------------------------------------------------------------
 template <int T, bool RECORD>
 __global__ __launch_bounds__(T == 8 ? 64 : 256) void k_blend(
-    const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ ids, const float4* __restrict__ rec_a,
-    const float4* __restrict__ rec_b, const float4* __restrict__ rec_c, const uint32_t* __restrict__ pair_of, int W,
-    int H, int tiles_x, int n_tiles, float bg0, float bg1, float bg2, float* __restrict__ rgb,
-    uint32_t* __restrict__ contrib) {
-  constexpr int NT = T == 8 ? 64 : 256;   // threads
-  constexpr int PPT = T * T / NT;         // pixels per thread
-  constexpr int BATCH = NT;
+    const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ order, const uint32_t* __restrict__ ids,
+    const float4* __restrict__ rec_a, const float4* __restrict__ rec_b, const float4* __restrict__ rec_c,
+    const uint32_t* __restrict__ pair_of, int W, int H, int tiles_x, int n_tiles, float bg0, float bg1, float bg2,
+    float* __restrict__ rgb, uint32_t* __restrict__ contrib, unsigned long long* __restrict__ work) {
+  constexpr int NT = T == 8 ? 64 : 256;  // threads
+  constexpr int NB = T * T / 64;         // 8x8 pixel blocks per tile
+  constexpr int BPW = NB / (NT / 64);    // blocks per wave (1, 1, 4)
+  constexpr int BATCH = 256;
+  constexpr int LPT = BATCH / NT;        // splats each thread stages per batch
   constexpr float kLog2e = 1.4426950408889634f;
-  __shared__ float s_u[BATCH], s_v[BATCH], s_A[BATCH], s_B[BATCH], s_C[BATCH], s_o[BATCH];
-  __shared__ float s_r[BATCH], s_g[BATCH], s_b[BATCH];
+  __shared__ float4 s_g[BATCH];  // u, v, A, B   (A, B, C: conic scaled by -log2(e)/2, -log2(e), -log2(e)/2)
+  __shared__ float4 s_h[BATCH];  // C, opacity, log2 bound, -
+  __shared__ float4 s_c[BATCH];  // r, g, b, -
+  __shared__ uint32_t s_ov[T == 8 ? 1 : BATCH];  // bit b: the footprint box touches 8x8 block b
   __shared__ uint32_t s_p[RECORD ? BATCH : 1];
-  const int key = blockIdx.x;
+  const int key = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
   const int cam = key / n_tiles, tile = key % n_tiles;
   const int tx = tile % tiles_x, ty = tile / tiles_x;
   const uint32_t start = ranges[2 * (int64_t)key], end = ranges[2 * (int64_t)key + 1];
-  const int t = threadIdx.x;
-  float px[PPT], py[PPT], Tr[PPT], cr[PPT], cg[PPT], cb[PPT];
-  bool done[PPT];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  float px[BPW], py[BPW], Tr[BPW], cr[BPW], cg[BPW], cb[BPW];
+  bool done[BPW];
+  uint32_t stop[BPW];  // list position at which the pixel stopped (end if it never did)
+  uint32_t b0k = start;  // list position of the current batch
   int alive = 0;
 #pragma unroll
-  for (int j = 0; j < PPT; ++j) {
-    const int lp = t + j * NT;
-    const int x = tx * T + lp % T, y = ty * T + lp / T;
+  for (int j = 0; j < BPW; ++j) {
+    stop[j] = end;
+    const int blk = wave * BPW + j;
+    const int x = tx * T + (blk % (T / 8)) * 8 + (lane & 7), y = ty * T + (blk / (T / 8)) * 8 + (lane >> 3);
     px[j] = (float)x + 0.5f;
     py[j] = (float)y + 0.5f;
     Tr[j] = 1.f;
@@ -357,54 +393,165 @@ __global__ __launch_bounds__(T == 8 ? 64 : 256) void k_blend(
     done[j] = !(x < W && y < H);
     alive += done[j] ? 0 : 1;
   }
-  for (uint32_t b0 = start; b0 < end; b0 += BATCH) {
-    if (__syncthreads_count(alive > 0) == 0) break;
-    const uint32_t cnt = min((uint32_t)BATCH, end - b0);
-    if (t < (int)cnt) {
-      const uint32_t id = ids[b0 + t];
-      const float4 A = rec_a[id], B = rec_b[id];
-      const float C = rec_c[id].x;
-      s_u[t] = A.x;
-      s_v[t] = A.y;
-      // exponent in base 2: -q/2 * log2(e) with q = d^T conic d
-      s_A[t] = -0.5f * kLog2e * A.z;
-      s_B[t] = -kLog2e * A.w;
-      s_C[t] = -0.5f * kLog2e * B.x;
-      s_o[t] = B.y;
-      s_r[t] = B.z;
-      s_g[t] = B.w;
-      s_b[t] = C;
-      if (RECORD) s_p[t] = pair_of[id];
-    }
-    __syncthreads();
+  float4 pa[LPT], pb[LPT], pc[LPT];
+  uint32_t pp[LPT];
+  auto fetch = [&](uint32_t b0) {
 #pragma unroll
-    for (int j = 0; j < PPT; ++j) {
-      if (done[j]) continue;
-      for (uint32_t k = 0; k < cnt; ++k) {
-        const float dx = px[j] - s_u[k], dy = py[j] - s_v[k];
-        const float pw = s_A[k] * dx * dx + s_B[k] * dx * dy + s_C[k] * dy * dy;
-        if (pw > 0.f) continue;
-        const float al = fminf(kAlphaMax, s_o[k] * __builtin_amdgcn_exp2f(pw));
-        if (al < kAlphaMin) continue;
-        const float Tn = Tr[j] * (1.f - al);
+    for (int i = 0; i < LPT; ++i) {
+      const uint32_t idx = b0 + t + i * NT;
+      if (idx < end) {
+        const uint32_t id = ids[idx];
+        pa[i] = rec_a[id];
+        pb[i] = rec_b[id];
+        pc[i] = rec_c[id];
+        if (RECORD) pp[i] = pair_of[id];
+      }
+    }
+  };
+  // composite up to 4 splats (batch slots ks[0..ng), wave-uniform) into pixel
+  // block j: the four alphas are independent of the transmittance and are
+  // evaluated together; only the short T / colour update is sequential.
+  auto blend_group = [&](int j, const int (&ks)[4], int ng) {
+    float al[4];
+    bool ok[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const float4 g = s_g[ks[u]];
+      const float4 h = s_h[ks[u]];
+      const float dx = px[j] - g.x, dy = py[j] - g.y;
+      const float pw = dx * fmaf(g.z, dx, g.w * dy) + h.x * dy * dy;
+      al[u] = fminf(kAlphaMax, h.y * __builtin_amdgcn_exp2f(pw));
+      ok[u] = u < ng && pw >= h.z && pw <= 0.f && al[u] >= kAlphaMin;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (ok[u] && !done[j]) {
+        const float Tn = Tr[j] * (1.f - al[u]);
         if (Tn < kTMin) {
           done[j] = true;
           --alive;
-          break;
+          stop[j] = b0k + ks[u];
+        } else {
+          const float4 c = s_c[ks[u]];
+          const float w = al[u] * Tr[j];
+          cr[j] = fmaf(w, c.x, cr[j]);
+          cg[j] = fmaf(w, c.y, cg[j]);
+          cb[j] = fmaf(w, c.z, cb[j]);
+          if (RECORD) atomicMax(contrib + s_p[ks[u]], __float_as_uint(w));
+          Tr[j] = Tn;
         }
-        const float w = al * Tr[j];
-        cr[j] = fmaf(w, s_r[k], cr[j]);
-        cg[j] = fmaf(w, s_g[k], cg[j]);
-        cb[j] = fmaf(w, s_b[k], cb[j]);
-        if (RECORD) atomicMax(contrib + s_p[k], __float_as_uint(w));
-        Tr[j] = Tn;
+      }
+    }
+  };
+  // composite splat k of the batch into pixel block j (per-lane predication)
+  auto blend_one = [&](int j, int k, const float4& g, const float4& h) {
+    const float dx = px[j] - g.x, dy = py[j] - g.y;
+    const float pw = dx * fmaf(g.z, dx, g.w * dy) + h.x * dy * dy;
+    if (done[j] || pw < h.z || pw > 0.f) return;
+    const float al = fminf(kAlphaMax, h.y * __builtin_amdgcn_exp2f(pw));
+    if (al < kAlphaMin) return;
+    const float Tn = Tr[j] * (1.f - al);
+    if (Tn < kTMin) {
+      done[j] = true;
+      --alive;
+      stop[j] = b0k + k;
+      return;
+    }
+    const float4 c = s_c[k];
+    const float w = al * Tr[j];
+    cr[j] = fmaf(w, c.x, cr[j]);
+    cg[j] = fmaf(w, c.y, cg[j]);
+    cb[j] = fmaf(w, c.z, cb[j]);
+    if (RECORD) atomicMax(contrib + s_p[k], __float_as_uint(w));
+    Tr[j] = Tn;
+  };
+  if (start < end) fetch(start);
+  for (uint32_t b0 = start; b0 < end; b0 += BATCH) {
+    if (__syncthreads_count(alive > 0) == 0) break;  // also: the previous batch is consumed
+    const uint32_t cnt = min((uint32_t)BATCH, end - b0);
+    b0k = b0;
+#pragma unroll
+    for (int i = 0; i < LPT; ++i) {
+      const int k = t + i * NT;
+      if (k < (int)cnt) {
+        s_g[k] = make_float4(pa[i].x, pa[i].y, -0.5f * kLog2e * pa[i].z, -kLog2e * pa[i].w);
+        s_h[k] = make_float4(-0.5f * kLog2e * pb[i].x, pb[i].y, -__log2f(255.f * pb[i].y) - 0.01f, 0.f);
+        s_c[k] = make_float4(pb[i].z, pb[i].w, pc[i].x, 0.f);
+        if (T != 8) {
+          // blocks touched by the footprint box (same widening as the tile rectangle)
+          const float wx = 1e-4f * pc[i].z + 1e-3f, wy = 1e-4f * pc[i].w + 1e-3f;
+          const float x0 = pa[i].x - pc[i].z - wx - (float)(tx * T) - 0.5f;
+          const float x1 = pa[i].x + pc[i].z + wx - (float)(tx * T) - 0.5f;
+          const float y0 = pa[i].y - pc[i].w - wy - (float)(ty * T) - 0.5f;
+          const float y1 = pa[i].y + pc[i].w + wy - (float)(ty * T) - 0.5f;
+          const int bx0 = max(0, (int)floorf(x0 * 0.125f)), bx1 = min(T / 8 - 1, (int)floorf(x1 * 0.125f));
+          const int by0 = max(0, (int)floorf(y0 * 0.125f)), by1 = min(T / 8 - 1, (int)floorf(y1 * 0.125f));
+          uint32_t m = 0;
+          for (int by = by0; by <= by1; ++by)
+            for (int bx = bx0; bx <= bx1; ++bx) m |= 1u << (by * (T / 8) + bx);
+          s_ov[k] = m;
+        }
+        if (RECORD) s_p[k] = pp[i];
+      }
+    }
+    __syncthreads();
+    if (b0 + BATCH < end) fetch(b0 + BATCH);  // overlaps the compositing below
+#pragma unroll
+    for (int j = 0; j < BPW; ++j) {
+      if (__ballot(!done[j]) == 0) continue;
+      if (T == 8) {
+        // every listed splat touches the tile
+        for (int k = 0; k < (int)cnt; k += 4) {
+          const int ks[4] = {k, min(k + 1, (int)cnt - 1), min(k + 2, (int)cnt - 1), min(k + 3, (int)cnt - 1)};
+          blend_group(j, ks, min(4, (int)cnt - k));
+          if ((k & 15) == 12 && __ballot(!done[j]) == 0) break;
+        }
+      } else {
+        // splats whose box touches this wave's block, as 64-bit ballot sets
+        const int blk = wave * BPW + j;
+        uint64_t set[BATCH / 64];
+#pragma unroll
+        for (int c = 0; c < BATCH / 64; ++c) {
+          const int k = c * 64 + lane;
+          set[c] = __ballot(k < (int)cnt && ((s_ov[k] >> blk) & 1u));
+        }
+#pragma unroll
+        for (int c = 0; c < BATCH / 64; ++c) {
+          uint64_t m = set[c];
+          if (!m) continue;
+          int k = c * 64 + __builtin_ctzll(m);
+          m &= m - 1;
+          float4 g = s_g[k], h = s_h[k];
+          while (true) {
+            const bool more = m != 0;
+            const int kn = more ? c * 64 + __builtin_ctzll(m) : k;
+            m &= m - 1;
+            const float4 gn = s_g[kn], hn = s_h[kn];
+            blend_one(j, k, g, h);
+            if (!more) break;
+            k = kn;
+            g = gn;
+            h = hn;
+          }
+          if (__ballot(!done[j]) == 0) break;
+        }
       }
     }
   }
+  if (work) {
+    // entries of the tile list each pixel examined: up to and including its stop
+    uint32_t wk = 0;
 #pragma unroll
-  for (int j = 0; j < PPT; ++j) {
-    const int lp = t + j * NT;
-    const int x = tx * T + lp % T, y = ty * T + lp / T;
+    for (int j = 0; j < BPW; ++j) {
+      const int x = (int)px[j], y = (int)py[j];
+      if (x < W && y < H) wk += (stop[j] < end ? stop[j] + 1 : end) - start;
+    }
+    for (int o = 32; o > 0; o >>= 1) wk += __shfl_xor(wk, o);
+    if (lane == 0) atomicAdd(work, (unsigned long long)wk);
+  }
+#pragma unroll
+  for (int j = 0; j < BPW; ++j) {
+    const int x = (int)px[j], y = (int)py[j];
     if (x < W && y < H) {
       float* o = rgb + (((int64_t)cam * H + y) * W + x) * 3;
       o[0] = fmaf(Tr[j], bg0, cr[j]);
@@ -415,35 +562,35 @@ __global__ __launch_bounds__(T == 8 ? 64 : 256) void k_blend(
 }
 
 template <int T>
-static void launch_blend_t(bool record, dim3 grid, hipStream_t st, const uint32_t* ranges, const uint32_t* ids,
-                           const float4* ra, const float4* rb, const float4* rc, const uint32_t* pair_of, int W, int H,
-                           int tiles_x, int n_tiles, float b0, float b1, float b2, float* rgb, float* contrib) {
+static void launch_blend_t(bool record, dim3 grid, hipStream_t st, const uint32_t* ranges, const uint32_t* order,
+                           const uint32_t* ids, const float4* ra, const float4* rb, const float4* rc,
+                           const uint32_t* pair_of, int W, int H, int tiles_x, int n_tiles, float b0, float b1,
+                           float b2, float* rgb, float* contrib, unsigned long long* work) {
   constexpr int NT = T == 8 ? 64 : 256;
   if (record)
-    hipLaunchKernelGGL((k_blend<T, true>), grid, dim3(NT), 0, st, ranges, ids, ra, rb, rc, pair_of, W, H, tiles_x,
-                       n_tiles, b0, b1, b2, rgb, reinterpret_cast<uint32_t*>(contrib));
+    hipLaunchKernelGGL((k_blend<T, true>), grid, dim3(NT), 0, st, ranges, order, ids, ra, rb, rc, pair_of, W, H,
+                       tiles_x, n_tiles, b0, b1, b2, rgb, reinterpret_cast<uint32_t*>(contrib), work);
   else
-    hipLaunchKernelGGL((k_blend<T, false>), grid, dim3(NT), 0, st, ranges, ids, ra, rb, rc, pair_of, W, H, tiles_x,
-                       n_tiles, b0, b1, b2, rgb, reinterpret_cast<uint32_t*>(contrib));
+    hipLaunchKernelGGL((k_blend<T, false>), grid, dim3(NT), 0, st, ranges, order, ids, ra, rb, rc, pair_of, W, H,
+                       tiles_x, n_tiles, b0, b1, b2, rgb, reinterpret_cast<uint32_t*>(contrib), work);
 }
 
-hipError_t launch_blend(const uint32_t* ranges, const uint32_t* ids, const float4* rec_a, const float4* rec_b,
-                        const float4* rec_c, const uint32_t* pair_of, int C, int W, int H, int tile, int tiles_x,
-                        int tiles_y, float bg0, float bg1, float bg2, float* rgb, float* contrib, int64_t P,
-                        const uint4* rect, hipStream_t st) {
-  (void)P; (void)rect;
+hipError_t launch_blend(const uint32_t* ranges, const uint32_t* order, const uint32_t* ids, const float4* rec_a,
+                        const float4* rec_b, const float4* rec_c, const uint32_t* pair_of, int C, int W, int H,
+                        int tile, int tiles_x, int tiles_y, float bg0, float bg1, float bg2, float* rgb,
+                        float* contrib, unsigned long long* work, hipStream_t st) {
   const int n_tiles = tiles_x * tiles_y;
   dim3 grid((unsigned)(C * n_tiles));
   const bool record = contrib != nullptr;
   if (tile == 8)
-    launch_blend_t<8>(record, grid, st, ranges, ids, rec_a, rec_b, rec_c, pair_of, W, H, tiles_x, n_tiles, bg0, bg1,
-                      bg2, rgb, contrib);
+    launch_blend_t<8>(record, grid, st, ranges, order, ids, rec_a, rec_b, rec_c, pair_of, W, H, tiles_x, n_tiles,
+                      bg0, bg1, bg2, rgb, contrib, work);
   else if (tile == 16)
-    launch_blend_t<16>(record, grid, st, ranges, ids, rec_a, rec_b, rec_c, pair_of, W, H, tiles_x, n_tiles, bg0, bg1,
-                       bg2, rgb, contrib);
+    launch_blend_t<16>(record, grid, st, ranges, order, ids, rec_a, rec_b, rec_c, pair_of, W, H, tiles_x, n_tiles,
+                       bg0, bg1, bg2, rgb, contrib, work);
   else if (tile == 32)
-    launch_blend_t<32>(record, grid, st, ranges, ids, rec_a, rec_b, rec_c, pair_of, W, H, tiles_x, n_tiles, bg0, bg1,
-                       bg2, rgb, contrib);
+    launch_blend_t<32>(record, grid, st, ranges, order, ids, rec_a, rec_b, rec_c, pair_of, W, H, tiles_x, n_tiles,
+                       bg0, bg1, bg2, rgb, contrib, work);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

@@ -243,3 +243,39 @@ def test_empty_frame_and_invalid_arguments(nvgs):
     with pytest.raises(nvgs.NvgsError):
         ctx.render([bad])
     ctx.close()
+
+
+@pytest.mark.parametrize("prec,width", [("bf16", 64), ("bf16", 128), ("fp8", 64), ("fp8", 128)])
+def test_reduced_precision_mlp(nvgs, prec, width):
+    """BF16 / FP8 E4M3 MLP forms: the kernel's logits equal the oracle's
+    emulation of the same operand rounding (FP64 otherwise) up to FP32
+    accumulation order; the keep flip rate against the FP64 MLP is reported."""
+    sc = scenes.tiny(n=6000, res=128, width=width)
+    log(f"[prec] {prec} W={width}")
+    ctx = make_ctx(nvgs, sc)
+    st, lg = ctx.query_visibility(sc.cameras, precision=prec)
+    st, lg = st.cpu().numpy()[0], lg.cpu().numpy()[0].astype(np.float64)
+    ctx.close()
+    ost, olg = oracle.query(sc)
+    ost, olg = ost[0], olg[0]
+    q = ~np.isnan(olg)
+    a = sc.assets[0]
+    cl = oracle.local_camera(sc.instances[0], sc.cameras[0], a.mlp.train_focal, a.mlp.d_max)
+    X = oracle.mlp_inputs(a, np.flatnonzero(q), cl)
+    zq = oracle.mlp_forward_q(a.mlp.params, width, X, prec)
+    _, scale = oracle.mlp_forward(a.mlp.params, width, X)
+    zg = lg[q]
+    err = np.abs(zg - zq)
+    rel = err / np.maximum(np.abs(zq), scale)
+    flips = np.mean((zg >= 0) != (olg[q] >= 0))
+    log(f"[prec] {prec} W={width}: max |z-zq| {err.max():.3e}, max rel {rel.max():.3e}, "
+        f"p99.9 rel {np.quantile(rel, 0.999):.3e}, flip rate vs FP64 {flips:.4f}")
+    # Most pairs agree to FP32 accumulation order.  An activation whose FP32
+    # value (kernel) and FP64 value (emulation) straddle a rounding boundary
+    # rounds one unit apart: 2^-8 (BF16) or up to 2^-3 (E4M3) of one of the W
+    # terms, i.e. ~2^-3/W of the logit scale for FP8; such pairs are rare.
+    assert np.median(rel) < 1e-5
+    assert np.quantile(rel, 0.999) < (1e-3 if prec == "bf16" else 5e-3)
+    assert rel.max() < (1e-2 if prec == "bf16" else 5e-2)
+    assert np.array_equal(st[q] == 2, zg >= 0)
+    assert flips < (0.02 if prec == "bf16" else 0.08)
