@@ -27,7 +27,9 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-FLOP_PER_QUERY = {64: 2 * (72 * 64 + 2 * 64 * 64 + 64), 128: 2 * (72 * 128 + 2 * 128 * 128 + 128)}
+# per queried pair: the two hidden layers and the output layer (layer 1 is
+# computed once per Gaussian chunk and once per (camera, instance) segment)
+FLOP_PER_QUERY = {64: 2 * (2 * 64 * 64 + 64), 128: 2 * (2 * 128 * 128 + 128)}
 MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0}
 HBM_PEAK_GBS = 8000.0
 VALU_LANE_OPS = 256 * 64 * 2.4e9          # non-packed FP32 lane-ops per second
@@ -82,12 +84,13 @@ def roofline(stage_ms, st, width, precision, sh_degree):
         flop = st["queried"] * FLOP_PER_QUERY[width]
         a = flop / sec / 1e12
         p = MFMA_PEAK_TFLOPS[precision]
-        return dom, {"bound": "mfma", "achieved": a, "peak": p, "unit": "TFLOP/s", "frac": a / p, "traffic": None}
+        return dom, {"bound": "mfma", "achieved": a, "peak": p, "unit": "TFLOP/s", "frac": a / p,
+                     "traffic": measured_traffic(dom)}
     if dom == "project":
         per = (12 + 12 + 16 + 4 + 12 * (sh_degree + 1) ** 2) + 68
         a = st["kept"] * per / sec / 1e9
         return dom, {"bound": "hbm", "achieved": a, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": a / HBM_PEAK_GBS,
-                     "traffic": None}
+                     "traffic": measured_traffic(dom)}
     if dom in ("depth_sort", "tile_sort", "bin"):
         n = st["kept"] if dom == "depth_sort" else st["duplicates"]
         passes = 4 if dom == "depth_sort" else 2
@@ -99,12 +102,25 @@ def roofline(stage_ms, st, width, precision, sh_degree):
     # so the chip's 256 CU x 64 lanes x 2.4 GHz non-packed issue rate bounds it
     a = st["blend_tests"] / sec / 1e9
     p = BLEND_PEAK_GTESTS
-    return dom, {"bound": "alu", "achieved": a, "peak": p, "unit": "Gtests/s", "frac": a / p, "traffic": None}
+    return dom, {"bound": "alu", "achieved": a, "peak": p, "unit": "Gtests/s", "frac": a / p,
+                 "traffic": measured_traffic(dom)}
 
 
-def cpu_baseline(sc, every=16):
-    """The FP64 oracle on a bounded sample: every `every`-th instance of the
-    scene, one full frame; the time is scaled by the pair-count ratio."""
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when the kernel source changed since it was measured."""
+    import hashlib
+    try:
+        t = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))[kernel]
+        cur = hashlib.sha256(open(os.path.join(ROOT, t["source"]), "rb").read()).hexdigest()
+        return t["fetch_bytes"] + t["write_bytes"] if cur == t["source_sha256"] else None
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(sc, every=1):
+    """The FP64 oracle on one full frame of the scene (every `every`-th
+    instance if `every` > 1, the time then scaled by the pair-count ratio)."""
     import oracle
     import synth
     sub = synth.Scene(assets=sc.assets, instances=sc.instances[::every], cameras=sc.cameras, tile=sc.tile)
@@ -114,9 +130,9 @@ def cpu_baseline(sc, every=16):
     scale = sc.pairs_per_camera / sub.pairs_per_camera
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": 1.0 / (dt * scale), "unit": "frames/s", "cores": threads, "kind": "oracle",
-            "sample": f"every {every}th instance ({len(sub.instances)} of {len(sc.instances)}), one full "
-                      f"{sc.cameras[0].width}x{sc.cameras[0].height} frame in {dt:.1f} s, scaled x{scale:.1f} "
-                      f"by pair count"}
+            "sample": f"{len(sub.instances)} of {len(sc.instances)} instances, one full "
+                      f"{sc.cameras[0].width}x{sc.cameras[0].height} frame in {dt:.1f} s"
+                      + (f", scaled x{scale:.1f} by pair count" if every > 1 else "")}
 
 
 def psnr(a, b):
@@ -135,7 +151,18 @@ def main():
     ap.add_argument("--n", type=int, default=250000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--extra-precisions", default="", help="comma list, e.g. bf16,fp8")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="only run a plain device copy of this many bytes (calibrates HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        a = torch.empty(args.copy_probe // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": args.copy_probe, "launches": 3}))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the renderer shards across GPUs only by design, see the design notes)", file=sys.stderr)
