@@ -172,13 +172,13 @@ typedef struct nvgs_debug_view {
 } nvgs_debug_view;
 
 typedef struct nvgs_train_opts {
-  int64_t batch;      /* (Gaussian, view) pairs per step */
-  int32_t steps;
+  int64_t batch;      /* (Gaussian, view) pairs per step, >= 1 */
+  int32_t steps;      /* >= 1 */
   int32_t precision;  /* NVGS_PREC_FP32 or NVGS_PREC_BF16 */
-  float lr, beta1, beta2, eps;
-  uint64_t seed;      /* SplitMix64 seed for the batch draws */
-  float threshold;    /* label = max alpha*T > threshold (1/255) */
-  int32_t tile;
+  float lr, beta1, beta2, eps; /* Adam */
+  uint64_t seed;      /* SplitMix64 seed of the batch draws */
+  float threshold;    /* labels made internally: contribution > threshold */
+  int32_t tile;       /* labels made internally: tile edge of the label renders */
 } nvgs_train_opts;
 
 /* Create a context on a device / stream.  Host call, no GPU work. */
@@ -210,6 +210,43 @@ nvgs_status nvgs_render(nvgs_ctx* ctx, const nvgs_camera* cams, int32_t C, const
 
 /* Views of the last frame's intermediate buffers (for tests and tools). */
 nvgs_status nvgs_debug_buffers(nvgs_ctx* ctx, nvgs_debug_view* out);
+
+/* Visibility labels of one asset from the renderer itself (Sec. 3.1): each
+ * view renders a single identity instance of the asset with frustum culling
+ * only and records, per Gaussian, the largest contribution alpha*T of its
+ * blended fragments; the label is contribution > threshold (1/255 for a
+ * non-zero 8-bit contribution).  views: host [V], equal sizes.
+ * labels: device [V][ceil(n/32)] bit words (bit g%32 of word g/32), written.
+ * The instance list is restored afterwards.  Synchronises. */
+nvgs_status nvgs_make_labels(nvgs_ctx* ctx, int32_t asset, const nvgs_camera* views, int32_t V, float threshold,
+                             int32_t tile, uint32_t* labels);
+
+/* Train the width-64 visibility MLP of one asset (Sec. 3.2) on (Gaussian,
+ * view) pairs drawn uniformly with replacement: pair i of step s comes from
+ * r = SplitMix64(opts->seed, s * batch + i), Gaussian ((r mod 2^32) n) >> 32,
+ * view ((r >> 32) V) >> 32.  Loss: mean BCE with logits against the labels
+ * (labels == NULL: made here with opts->threshold and opts->tile).  Adam
+ * (beta1, beta2, eps, bias-corrected, constant lr) on FP32 master weights.
+ * precision NVGS_PREC_BF16 rounds every GEMM operand of the forward and
+ * backward pass to BF16 (FP32 accumulation); NVGS_PREC_FP32 keeps FP32.
+ * params: device FP32 packed parameters (layout of nvgs_mlp.params), read as
+ * the initial weights and updated in place (reload the asset to render with
+ * them).  loss_curve: host [steps] (mean batch loss before each update) or
+ * NULL.  Synchronises. */
+nvgs_status nvgs_train_visibility(nvgs_ctx* ctx, int32_t asset, const nvgs_camera* views, int32_t V,
+                                  const uint32_t* labels, const nvgs_train_opts* opts, float* params,
+                                  float* loss_curve);
+
+/* MLP on encoded inputs, for automatic differentiation frameworks (width 64).
+ * X: device [B][72] encoded inputs; logits: device [B].  precision as in
+ * nvgs_train_visibility. */
+nvgs_status nvgs_mlp_forward(nvgs_ctx* ctx, const float* params, int32_t width, const float* X, int64_t B,
+                             int32_t precision, float* logits);
+/* Vector-Jacobian product: dparams[p] = sum_b dlogits[b] dz_b/dparams[p]
+ * (device [13057], overwritten) and, if dX != NULL, dX[b][k] = dlogits[b]
+ * dz_b/dX[b][k] (device [B][72]).  The sum over b runs in a fixed order. */
+nvgs_status nvgs_mlp_backward(nvgs_ctx* ctx, const float* params, int32_t width, const float* X, int64_t B,
+                              const float* dlogits, int32_t precision, float* dparams, float* dX);
 
 #ifdef __cplusplus
 }

@@ -315,21 +315,40 @@ def frame(scene, use_mlp: bool = True, tile: Optional[int] = None, record: bool 
     return out
 
 
-def labels(asset, views, threshold: float = 1.0 / 255.0, tile: int = 16) -> np.ndarray:
-    """Labels (Sec. 3.1): label[v, g] = 1 iff Gaussian g's largest contribution alpha*T over
-    the pixels of view v exceeds the threshold (single identity instance,
-    frustum culling only)."""
+def contributions(asset, views, tile: int = 16) -> np.ndarray:
+    """Largest contribution alpha*T of each Gaussian's blended fragments in
+    each view (Sec. 3.1), single identity instance, frustum culling only:
+    [V, n] (0 where outside the frustum or never blended)."""
     from synth import Scene, identity_instance  # inputs only
     sc = Scene(assets=[asset], instances=[identity_instance(0)], cameras=list(views), tile=tile)
     state, _ = query(sc, use_mlp=False)
     kept = compact(state)
-    lab = np.zeros((len(views), asset.n), np.uint8)
+    out = np.zeros((len(views), asset.n))
     for k, cam in enumerate(views):
         rec, prect = project(sc, cam, kept[k])
         cb = np.zeros(len(kept[k]))
         render_camera(rec, prect, cam, tile, (0.0, 0.0, 0.0), cb, None, want_margin=False)
-        lab[k, kept[k]] = (cb > threshold).astype(np.uint8)
-    return lab
+        out[k, kept[k]] = cb
+    return out
+
+
+def labels(asset, views, threshold: float = 1.0 / 255.0, tile: int = 16) -> np.ndarray:
+    """Labels (Sec. 3.1): label[v, g] = 1 iff Gaussian g's largest contribution
+    alpha*T over the pixels of view v exceeds the threshold."""
+    return (contributions(asset, views, tile) > threshold).astype(np.uint8)
+
+
+def sample_pairs(seed: int, step: int, batch: int, n: int, V: int):
+    """(Gaussian, view) pairs of one training step, drawn with SplitMix64 at
+    counter step * batch + i: g = (low32(r) n) >> 32, v = (high32(r) V) >> 32."""
+    L = lib()
+    g = np.zeros(batch, np.int64)
+    v = np.zeros(batch, np.int64)
+    for i in range(batch):
+        r = int(L.orc_splitmix64(seed, step * batch + i))
+        g[i] = ((r & 0xFFFFFFFF) * n) >> 32
+        v[i] = ((r >> 32) * V) >> 32
+    return g, v
 
 
 # ----------------------------------------------------------------------------

@@ -100,7 +100,17 @@ _SIGS = {
     "nvgs_render": ([C.c_void_p, C.POINTER(Camera), C.c_int32, C.POINTER(RenderOpts), C.c_void_p,
                      C.POINTER(FrameStats)], C.c_int32),
     "nvgs_debug_buffers": ([C.c_void_p, C.POINTER(DebugView)], C.c_int32),
+    "nvgs_make_labels": ([C.c_void_p, C.c_int32, C.POINTER(Camera), C.c_int32, C.c_float, C.c_int32, C.c_void_p],
+                         C.c_int32),
+    "nvgs_train_visibility": ([C.c_void_p, C.c_int32, C.POINTER(Camera), C.c_int32, C.c_void_p,
+                               C.POINTER(TrainOpts), C.c_void_p, C.c_void_p], C.c_int32),
+    "nvgs_mlp_forward": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p],
+                         C.c_int32),
+    "nvgs_mlp_backward": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p, C.c_int32,
+                           C.c_void_p, C.c_void_p], C.c_int32),
 }
+
+NUM_PARAMS_W64 = 72 * 64 + 64 + 2 * (64 * 64 + 64) + 64 + 1
 
 _lib = None
 
@@ -192,6 +202,10 @@ class Context:
     """One renderer context on a device and torch stream."""
 
     def __init__(self, device: int = 0, stream=None):
+        global _train_methods_installed
+        if not _train_methods_installed:
+            _train_methods()
+            _train_methods_installed = True
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device visible to torch")
@@ -309,6 +323,81 @@ class Context:
             out["pair"] = grab(v.pair, (ns,), torch.int32)
         hip.hipStreamSynchronize(self.stream.cuda_stream)
         return out
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _train_methods():
+    torch = _torch()
+
+    def make_labels(self, asset: int, views, threshold: float = 1.0 / 255.0, tile: int = 16):
+        """Label bits [V][ceil(n/32)] (int32 view of uint32) rendered by the library."""
+        arr, V = self._cams(views)
+        words = (self.assets[asset].n + 31) // 32
+        lab = torch.empty((V, words), dtype=torch.int32, device=self.device)
+        self._check(self.L.nvgs_make_labels(self.h, asset, arr, V, float(threshold), int(tile), lab.data_ptr()))
+        return lab
+
+    def train_visibility(self, asset: int, views, params, labels=None, batch: int = 65536, steps: int = 5000,
+                         precision="bf16", lr: float = 1e-3, betas=(0.9, 0.999), eps: float = 1e-8, seed: int = 1,
+                         threshold: float = 1.0 / 255.0, tile: int = 16):
+        """Train in place; params is a device float32 tensor [13057]; returns the loss curve."""
+        arr, V = self._cams(views)
+        opts = TrainOpts(int(batch), int(steps), _PREC.get(precision, precision), float(lr), float(betas[0]),
+                         float(betas[1]), float(eps), int(seed), float(threshold), int(tile))
+        curve = (C.c_float * int(steps))()
+        self._check(self.L.nvgs_train_visibility(self.h, asset, arr, V, _ptr(labels), C.byref(opts),
+                                                 params.data_ptr(), curve))
+        return np.frombuffer(curve, dtype=np.float32).copy()
+
+    def mlp_forward(self, params, X, precision="fp32"):
+        z = torch.empty(X.shape[0], dtype=torch.float32, device=self.device)
+        self._check(self.L.nvgs_mlp_forward(self.h, params.data_ptr(), 64, X.data_ptr(), X.shape[0],
+                                            _PREC.get(precision, precision), z.data_ptr()))
+        return z
+
+    def mlp_backward(self, params, X, dlogits, precision="fp32", want_dx=True):
+        dp = torch.empty(NUM_PARAMS_W64, dtype=torch.float32, device=self.device)
+        dx = torch.empty_like(X) if want_dx else None
+        self._check(self.L.nvgs_mlp_backward(self.h, params.data_ptr(), 64, X.data_ptr(), X.shape[0],
+                                             dlogits.data_ptr(), _PREC.get(precision, precision), dp.data_ptr(),
+                                             _ptr(dx)))
+        return dp, dx
+
+    Context.make_labels = make_labels
+    Context.train_visibility = train_visibility
+    Context.mlp_forward = mlp_forward
+    Context.mlp_backward = mlp_backward
+
+
+_train_methods_installed = False
+
+
+def visibility_mlp_function():
+    """torch.autograd.Function over the library's MLP forward and hand-written
+    backward: apply(X [B, 72], params [13057], ctx, precision) -> logits [B]."""
+    torch = _torch()
+
+    class VisibilityMLPFunction(torch.autograd.Function):
+        @staticmethod
+        def forward(fctx, X, params, nctx, precision="fp32"):
+            X = X.contiguous()
+            params = params.contiguous()
+            fctx.save_for_backward(X, params)
+            fctx.nctx = nctx
+            fctx.precision = precision
+            return nctx.mlp_forward(params, X, precision)
+
+        @staticmethod
+        def backward(fctx, grad):
+            X, params = fctx.saved_tensors
+            dp, dx = fctx.nctx.mlp_backward(params, X, grad.contiguous().float(), fctx.precision,
+                                            want_dx=fctx.needs_input_grad[0])
+            return dx, dp, None, None
+
+    return VisibilityMLPFunction
 
 
 def exported_symbols() -> list:

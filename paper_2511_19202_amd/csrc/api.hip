@@ -587,3 +587,178 @@ nvgs_status nvgs_debug_buffers(nvgs_ctx* ctx, nvgs_debug_view* out) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// labels, training and the MLP forward / backward
+// ---------------------------------------------------------------------------
+namespace {
+
+// temporary device buffer owned by one call
+struct Tmp {
+  nvgs_ctx* ctx;
+  Buf b;
+  explicit Tmp(nvgs_ctx* c) : ctx(c) {}
+  ~Tmp() {
+    if (b.p) {
+      (void)hipStreamSynchronize(ctx->stream);
+      release(ctx, b);
+    }
+  }
+  template <class T>
+  T* get(size_t count) {
+    return ensure(ctx, b, count * sizeof(T)) ? reinterpret_cast<T*>(b.p) : nullptr;
+  }
+};
+
+nvgs_status check_train_prec(nvgs_ctx* ctx, int32_t precision, int32_t width) {
+  if (precision != NVGS_PREC_FP32 && precision != NVGS_PREC_BF16)
+    return fail(ctx, NVGS_E_INVALID, "training precision must be FP32 or BF16");
+  if (width != 64) return fail(ctx, NVGS_E_INVALID, "training supports width 64");
+  return NVGS_OK;
+}
+
+constexpr int kTrainChunksPerWG = 4;  // 4 x 64 pairs per work-group
+constexpr int kPairsPerWG = 64 * kTrainChunksPerWG;
+
+}  // namespace
+
+extern "C" {
+
+nvgs_status nvgs_make_labels(nvgs_ctx* ctx, int32_t asset, const nvgs_camera* views, int32_t V, float threshold,
+                             int32_t tile, uint32_t* labels) {
+  if (!ctx) return NVGS_E_INVALID;
+  if (ctx->assets.empty()) return fail(ctx, NVGS_E_STATE, "no assets loaded");
+  if (asset < 0 || asset >= (int)ctx->assets.size()) return fail(ctx, NVGS_E_INVALID, "asset index out of range");
+  if (!labels) return fail(ctx, NVGS_E_INVALID, "labels: null pointer");
+  if (!std::isfinite(threshold)) return fail(ctx, NVGS_E_INVALID, "non-finite threshold");
+  nvgs_status s = check_cams(ctx, views, V);
+  if (s) return s;
+  CK(hipSetDevice(ctx->device));
+  const int64_t n = ctx->assets[asset].n;
+  const int64_t words = (n + 31) / 32;
+  // a single identity instance of the asset; the caller's list is restored
+  std::vector<nvgs_instance> saved = ctx->inst;
+  nvgs_instance id{};
+  id.asset = asset;
+  id.R[0] = id.R[4] = id.R[8] = 1.f;
+  id.s = 1.f;
+  if ((s = nvgs_set_instances(ctx, &id, 1))) return s;
+  const int VB = std::min(V, 16);
+  const int Wd = views[0].width, Ht = views[0].height;
+  Tmp contrib(ctx), rgb(ctx);
+  float* cb = contrib.get<float>((size_t)VB * n);
+  float* img = rgb.get<float>((size_t)VB * Wd * Ht * 3);
+  if (!cb || !img) s = fail(ctx, NVGS_E_NOMEM, "label buffers");
+  for (int v0 = 0; v0 < V && !s; v0 += VB) {
+    const int nb = std::min(VB, V - v0);
+    if (hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(cb), 0u, (int64_t)nb * n, ctx->stream)) {
+      s = fail(ctx, NVGS_E_DEVICE, hipGetErrorString(e));
+      break;
+    }
+    nvgs_render_opts ro{};
+    ro.tile = tile;
+    ro.use_mlp = 0;
+    ro.precision = NVGS_PREC_FP32;
+    ro.flags = NVGS_RENDER_RECORD_CONTRIB;
+    ro.contrib = cb;
+    if ((s = nvgs_render(ctx, views + v0, nb, &ro, img, nullptr))) break;
+    if (hipError_t e = launch_label_bits(cb, n, nb, threshold, labels + (int64_t)v0 * words, ctx->stream))
+      s = fail(ctx, NVGS_E_DEVICE, hipGetErrorString(e));
+  }
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess && !s) s = fail(ctx, NVGS_E_DEVICE, "label renders failed");
+  const std::string err = ctx->err;
+  nvgs_status s2 = saved.empty() ? NVGS_OK : nvgs_set_instances(ctx, saved.data(), (int)saved.size());
+  if (saved.empty()) ctx->inst.clear(), ctx->planC = -1;
+  if (s) {
+    ctx->err = err;
+    return s;
+  }
+  return s2;
+}
+
+nvgs_status nvgs_train_visibility(nvgs_ctx* ctx, int32_t asset, const nvgs_camera* views, int32_t V,
+                                  const uint32_t* labels, const nvgs_train_opts* opts, float* params,
+                                  float* loss_curve) {
+  if (!ctx) return NVGS_E_INVALID;
+  if (ctx->assets.empty()) return fail(ctx, NVGS_E_STATE, "no assets loaded");
+  if (asset < 0 || asset >= (int)ctx->assets.size()) return fail(ctx, NVGS_E_INVALID, "asset index out of range");
+  if (!opts || !params) return fail(ctx, NVGS_E_INVALID, "null opts or params");
+  if (opts->batch < 1 || opts->steps < 1) return fail(ctx, NVGS_E_INVALID, "batch and steps must be >= 1");
+  if (!(opts->lr > 0.f) || !(opts->beta1 >= 0.f && opts->beta1 < 1.f) || !(opts->beta2 >= 0.f && opts->beta2 < 1.f) ||
+      !(opts->eps > 0.f))
+    return fail(ctx, NVGS_E_INVALID, "bad Adam hyper-parameters");
+  nvgs_status s = check_train_prec(ctx, opts->precision, ctx->assets[asset].mlp.width);
+  if (s) return s;
+  if ((s = check_cams(ctx, views, V))) return s;
+  CK(hipSetDevice(ctx->device));
+  const nvgs_asset& A = ctx->assets[asset];
+  const int64_t n = A.n, words = (n + 31) / 32;
+  Tmp lab_tmp(ctx);
+  if (!labels) {
+    uint32_t* lb = lab_tmp.get<uint32_t>((size_t)V * words);
+    if (!lb) return fail(ctx, NVGS_E_NOMEM, "labels");
+    if ((s = nvgs_make_labels(ctx, asset, views, V, opts->threshold, opts->tile, lb))) return s;
+    labels = lb;
+  }
+  const int np = train_num_params();
+  const int nwg = (int)((opts->batch + kPairsPerWG - 1) / kPairsPerWG);
+  Tmp cams_t(ctx), gam_t(ctx), part_t(ctx), lp_t(ctx), m_t(ctx), v_t(ctx), loss_t(ctx);
+  nvgs_camera* cams_d = cams_t.get<nvgs_camera>(V);
+  float* gam = gam_t.get<float>((size_t)V * 36);
+  float* part = part_t.get<float>((size_t)nwg * np);
+  float* lp = lp_t.get<float>(nwg);
+  float* m = m_t.get<float>(np);
+  float* v = v_t.get<float>(np);
+  float* loss = loss_t.get<float>(opts->steps);
+  if (!cams_d || !gam || !part || !lp || !m || !v || !loss) return fail(ctx, NVGS_E_NOMEM, "training buffers");
+  CK(hipMemcpy(cams_d, views, sizeof(nvgs_camera) * V, hipMemcpyHostToDevice));
+  CK(launch_fill_u32(reinterpret_cast<uint32_t*>(m), 0u, np, ctx->stream));
+  CK(launch_fill_u32(reinterpret_cast<uint32_t*>(v), 0u, np, ctx->stream));
+  CK(launch_view_gam(cams_d, V, A.mlp.cam_scale, A.mlp.train_focal, A.mlp.d_max, gam, ctx->stream));
+  const bool bf16 = opts->precision == NVGS_PREC_BF16;
+  const float inv_b = 1.f / (float)opts->batch;
+  for (int step = 0; step < opts->steps; ++step) {
+    CK(launch_mlp_train(0, bf16, nwg, kTrainChunksPerWG, ctx->stream, params, opts->batch, inv_b, A.mean, n,
+                        A.mlp.mean_scale, gam, V, labels, opts->seed, step, nullptr, nullptr, nullptr, part, lp,
+                        nullptr));
+    CK(launch_reduce_adam(part, nwg, params, m, v, nullptr, opts->lr, opts->beta1, opts->beta2, opts->eps, step + 1,
+                          lp, inv_b, loss + step, ctx->stream));
+  }
+  CK(hipStreamSynchronize(ctx->stream));
+  if (loss_curve) CK(hipMemcpy(loss_curve, loss, sizeof(float) * opts->steps, hipMemcpyDeviceToHost));
+  return NVGS_OK;
+}
+
+nvgs_status nvgs_mlp_forward(nvgs_ctx* ctx, const float* params, int32_t width, const float* X, int64_t B,
+                             int32_t precision, float* logits) {
+  if (!ctx) return NVGS_E_INVALID;
+  if (!params || !X || !logits || B < 1) return fail(ctx, NVGS_E_INVALID, "mlp_forward: null pointer or B < 1");
+  nvgs_status s = check_train_prec(ctx, precision, width);
+  if (s) return s;
+  CK(hipSetDevice(ctx->device));
+  const int nwg = (int)((B + kPairsPerWG - 1) / kPairsPerWG);
+  CK(launch_mlp_train(1, precision == NVGS_PREC_BF16, nwg, kTrainChunksPerWG, ctx->stream, params, B, 1.f, nullptr,
+                      1, 0.f, nullptr, 1, nullptr, 0, 0, X, nullptr, logits, nullptr, nullptr, nullptr));
+  return NVGS_OK;
+}
+
+nvgs_status nvgs_mlp_backward(nvgs_ctx* ctx, const float* params, int32_t width, const float* X, int64_t B,
+                              const float* dlogits, int32_t precision, float* dparams, float* dX) {
+  if (!ctx) return NVGS_E_INVALID;
+  if (!params || !X || !dlogits || !dparams || B < 1)
+    return fail(ctx, NVGS_E_INVALID, "mlp_backward: null pointer or B < 1");
+  nvgs_status s = check_train_prec(ctx, precision, width);
+  if (s) return s;
+  CK(hipSetDevice(ctx->device));
+  const int nwg = (int)((B + kPairsPerWG - 1) / kPairsPerWG);
+  Tmp part_t(ctx);
+  float* part = part_t.get<float>((size_t)nwg * train_num_params());
+  if (!part) return fail(ctx, NVGS_E_NOMEM, "gradient partials");
+  CK(launch_mlp_train(2, precision == NVGS_PREC_BF16, nwg, kTrainChunksPerWG, ctx->stream, params, B, 1.f, nullptr,
+                      1, 0.f, nullptr, 1, nullptr, 0, 0, X, dlogits, nullptr, part, nullptr, dX));
+  CK(launch_reduce_adam(part, nwg, nullptr, nullptr, nullptr, dparams, 0.f, 0.f, 0.f, 1.f, 1, nullptr, 0.f, nullptr,
+                        ctx->stream));
+  return NVGS_OK;
+}
+
+}  // extern "C"

@@ -125,3 +125,20 @@ hipError_t launch_blend(const uint32_t* ranges, const uint32_t* order, const uin
                         float* contrib, unsigned long long* work, hipStream_t st);
 
 }  // namespace nvgs
+
+namespace nvgs {
+// training (k_train.hip)
+size_t train_smem_bytes();
+int train_num_params();
+hipError_t launch_view_gam(const nvgs_camera* views, int V, float cam_scale, float train_focal, float d_max,
+                           float* gam, hipStream_t st);
+hipError_t launch_label_bits(const float* contrib, int64_t n, int V, float thr, uint32_t* bits, hipStream_t st);
+hipError_t launch_mlp_train(int mode, bool bf16, int nwg, int chunks_per_wg, hipStream_t st, const float* params,
+                            int64_t batch, float inv_batch, const float* mean, int64_t n, float mean_scale,
+                            const float* view_gam, int V, const uint32_t* labels, uint64_t seed, int64_t step,
+                            const float* X, const float* dlogits, float* logits, float* partial, float* loss_part,
+                            float* dX);
+hipError_t launch_reduce_adam(const float* partial, int nwg, float* params, float* m, float* v, float* grad_out,
+                              float lr, float b1, float b2, float eps, int64_t t, const float* loss_part,
+                              float inv_batch, float* loss_out, hipStream_t st);
+}  // namespace nvgs
