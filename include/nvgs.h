@@ -78,8 +78,10 @@ typedef struct nvgs_create_info {
  * params: device, FP32, packed row-major W1[width][12*bands], b1[width],
  * W2[width][width], b2, W3[width][width], b3, wo[width], bo[1].
  * Input x = (mean_scale * mu, cam_scale * c_local) with c_local the camera
- * position in the asset frame, scaled by train_focal / f_render (Eq. 2,
- * f = 1 / tan(fovy / 2)) and clamped to length d_max when d_max > 0;
+ * position in the asset frame, scaled by train_focal / f_render (Eq. 2 with
+ * focal lengths in pixels, f = (height / 2) / tan(fovy / 2), so a render at
+ * another resolution or field of view maps onto the training views) and
+ * clamped to length d_max when d_max > 0;
  * features sin(2^k pi x_j), cos(2^k pi x_j), k < bands, for the six scalars
  * in order.  A pair is kept iff the logit is >= 0.  If |c_local| < d_min
  * the MLP is not queried and every in-frustum Gaussian is kept (Sec. 3.3). */
@@ -179,6 +181,8 @@ typedef struct nvgs_train_opts {
   uint64_t seed;      /* SplitMix64 seed of the batch draws */
   float threshold;    /* labels made internally: contribution > threshold */
   int32_t tile;       /* labels made internally: tile edge of the label renders */
+  int32_t weighting;  /* 0: mean BCE; 1: each sample weighted by B / (2 n_class), n_class the
+                         count of its label in the batch (Sec. 4.1 frequency weighting) */
 } nvgs_train_opts;
 
 /* Create a context on a device / stream.  Host call, no GPU work. */
@@ -217,9 +221,17 @@ nvgs_status nvgs_debug_buffers(nvgs_ctx* ctx, nvgs_debug_view* out);
  * blended fragments; the label is contribution > threshold (1/255 for a
  * non-zero 8-bit contribution).  views: host [V], equal sizes.
  * labels: device [V][ceil(n/32)] bit words (bit g%32 of word g/32), written.
+ * With aux > 0 (at most 64) each view also renders `aux` auxiliary views:
+ * the view rotated rigidly about the asset centre by aux_angle (radians)
+ * around the axes k_j = cos(phi_j) e1 + sin(phi_j) e2, phi_j = 2 pi j / aux,
+ * with d the unit direction from the centre to the view, e1 its right axis
+ * made orthogonal to d and e2 = d x e1.  The auxiliary cameras lie at the
+ * view's distance on the cone of half-angle aux_angle around d (Sec. 3.1,
+ * robustness against popping); a Gaussian is labelled visible for the view
+ * if it is visible in any of its 1 + aux renders.
  * The instance list is restored afterwards.  Synchronises. */
 nvgs_status nvgs_make_labels(nvgs_ctx* ctx, int32_t asset, const nvgs_camera* views, int32_t V, float threshold,
-                             int32_t tile, uint32_t* labels);
+                             int32_t tile, int32_t aux, float aux_angle, uint32_t* labels);
 
 /* Train the width-64 visibility MLP of one asset (Sec. 3.2) on (Gaussian,
  * view) pairs drawn uniformly with replacement: pair i of step s comes from

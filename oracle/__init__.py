@@ -332,10 +332,42 @@ def contributions(asset, views, tile: int = 16) -> np.ndarray:
     return out
 
 
-def labels(asset, views, threshold: float = 1.0 / 255.0, tile: int = 16) -> np.ndarray:
+def aux_views(view, aux: int, angle: float):
+    """Auxiliary views (Sec. 3.1): the camera turned rigidly about the asset
+    centre by `angle` so that it stays at its distance on the cone around its
+    direction d, at `aux` evenly spaced azimuths phi_j = 2 pi j / aux measured
+    from e1 = the camera's right axis made orthogonal to d (e2 = d x e1).
+    Position and orientation are rotated by the same rotation matrix."""
+    from synth import Camera  # inputs only
+    if aux == 0:
+        return []
+    pos = np.asarray(view.pos, np.float64)
+    d = pos / np.linalg.norm(pos)
+    Rc = np.asarray(view.R, np.float64).reshape(3, 3)
+    e1 = Rc[0] - np.dot(Rc[0], d) * d
+    e1 /= np.linalg.norm(e1)
+    e2 = np.cross(d, e1)
+    out = []
+    for j in range(aux):
+        phi = 2.0 * math.pi * j / aux
+        k = math.cos(phi) * e1 + math.sin(phi) * e2
+        K = np.array([[0.0, -k[2], k[1]], [k[2], 0.0, -k[0]], [-k[1], k[0], 0.0]])
+        M = np.eye(3) + math.sin(angle) * K + (1.0 - math.cos(angle)) * (K @ K)  # rotation by angle about k
+        out.append(Camera(pos=(M @ pos).astype(np.float32), R=(Rc @ M.T).astype(np.float32), fovy=view.fovy,
+                          width=view.width, height=view.height, near=view.near))
+    return out
+
+
+def labels(asset, views, threshold: float = 1.0 / 255.0, tile: int = 16, aux: int = 0,
+           aux_angle: float = 0.0) -> np.ndarray:
     """Labels (Sec. 3.1): label[v, g] = 1 iff Gaussian g's largest contribution
-    alpha*T over the pixels of view v exceeds the threshold."""
-    return (contributions(asset, views, tile) > threshold).astype(np.uint8)
+    alpha*T over the pixels of view v, or of one of its auxiliary views,
+    exceeds the threshold."""
+    out = np.zeros((len(views), asset.n), np.uint8)
+    for k, v in enumerate(views):
+        group = [v] + aux_views(v, aux, aux_angle)
+        out[k] = np.any(contributions(asset, group, tile) > threshold, axis=0)
+    return out
 
 
 def sample_pairs(seed: int, step: int, batch: int, n: int, V: int):

@@ -115,17 +115,16 @@ bool in_frustum(const Cam& c, const double* p, double* margin) {
 }
 
 // Camera position in the asset frame.  The global->local transform undoes
-// the instance rotation, translation and scale; the FoV factor f_t / f_r
-// (Eq. 2, applied to the position so that its length is the corrected
-// distance) maps the render camera onto the training camera.  If a far
-// bound d_max is set, the local distance is clamped to it (the distance
-// input is normalised to a fixed range).
+// the instance rotation, translation and scale; the factor f_t / f_r of
+// Eq. 2, with focal lengths in pixels (so it accounts for both field of view
+// and resolution), is applied to the position so that its length is the
+// corrected distance.  If a far bound d_max is set, the local distance is
+// clamped to it (the distance input is normalised to a fixed range).
 void local_camera(const Inst& in, const Cam& c, double train_focal, double d_max, double* cl) {
   double d[3] = {c.pos[0] - in.t[0], c.pos[1] - in.t[1], c.pos[2] - in.t[2]};
   double r[3];
   mat3t_vec(in.R, d, r);
-  double fr = 1.0 / std::tan(0.5 * c.fovy);
-  double f = train_focal / fr;
+  double f = train_focal / c.focal();
   for (int k = 0; k < 3; ++k) cl[k] = r[k] / in.s * f;
   if (d_max > 0) {
     double len = std::sqrt(cl[0] * cl[0] + cl[1] * cl[1] + cl[2] * cl[2]);

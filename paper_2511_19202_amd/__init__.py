@@ -85,7 +85,7 @@ class DebugView(C.Structure):
 class TrainOpts(C.Structure):
     _fields_ = [("batch", C.c_int64), ("steps", C.c_int32), ("precision", C.c_int32), ("lr", C.c_float),
                 ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float), ("seed", C.c_uint64),
-                ("threshold", C.c_float), ("tile", C.c_int32)]
+                ("threshold", C.c_float), ("tile", C.c_int32), ("weighting", C.c_int32)]
 
 
 # exported symbols of the C ABI and their signatures
@@ -100,8 +100,8 @@ _SIGS = {
     "nvgs_render": ([C.c_void_p, C.POINTER(Camera), C.c_int32, C.POINTER(RenderOpts), C.c_void_p,
                      C.POINTER(FrameStats)], C.c_int32),
     "nvgs_debug_buffers": ([C.c_void_p, C.POINTER(DebugView)], C.c_int32),
-    "nvgs_make_labels": ([C.c_void_p, C.c_int32, C.POINTER(Camera), C.c_int32, C.c_float, C.c_int32, C.c_void_p],
-                         C.c_int32),
+    "nvgs_make_labels": ([C.c_void_p, C.c_int32, C.POINTER(Camera), C.c_int32, C.c_float, C.c_int32, C.c_int32,
+                          C.c_float, C.c_void_p], C.c_int32),
     "nvgs_train_visibility": ([C.c_void_p, C.c_int32, C.POINTER(Camera), C.c_int32, C.c_void_p,
                                C.POINTER(TrainOpts), C.c_void_p, C.c_void_p], C.c_int32),
     "nvgs_mlp_forward": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p],
@@ -332,21 +332,23 @@ def _ptr(t):
 def _train_methods():
     torch = _torch()
 
-    def make_labels(self, asset: int, views, threshold: float = 1.0 / 255.0, tile: int = 16):
+    def make_labels(self, asset: int, views, threshold: float = 1.0 / 255.0, tile: int = 16, aux: int = 0,
+                    aux_angle: float = 0.0):
         """Label bits [V][ceil(n/32)] (int32 view of uint32) rendered by the library."""
         arr, V = self._cams(views)
         words = (self.assets[asset].n + 31) // 32
         lab = torch.empty((V, words), dtype=torch.int32, device=self.device)
-        self._check(self.L.nvgs_make_labels(self.h, asset, arr, V, float(threshold), int(tile), lab.data_ptr()))
+        self._check(self.L.nvgs_make_labels(self.h, asset, arr, V, float(threshold), int(tile), int(aux),
+                                            float(aux_angle), lab.data_ptr()))
         return lab
 
     def train_visibility(self, asset: int, views, params, labels=None, batch: int = 65536, steps: int = 5000,
                          precision="bf16", lr: float = 1e-3, betas=(0.9, 0.999), eps: float = 1e-8, seed: int = 1,
-                         threshold: float = 1.0 / 255.0, tile: int = 16):
+                         threshold: float = 1.0 / 255.0, tile: int = 16, weighting: int = 0):
         """Train in place; params is a device float32 tensor [13057]; returns the loss curve."""
         arr, V = self._cams(views)
         opts = TrainOpts(int(batch), int(steps), _PREC.get(precision, precision), float(lr), float(betas[0]),
-                         float(betas[1]), float(eps), int(seed), float(threshold), int(tile))
+                         float(betas[1]), float(eps), int(seed), float(threshold), int(tile), int(weighting))
         curve = (C.c_float * int(steps))()
         self._check(self.L.nvgs_train_visibility(self.h, asset, arr, V, _ptr(labels), C.byref(opts),
                                                  params.data_ptr(), curve))

@@ -624,9 +624,62 @@ constexpr int kPairsPerWG = 64 * kTrainChunksPerWG;
 
 extern "C" {
 
-nvgs_status nvgs_make_labels(nvgs_ctx* ctx, int32_t asset, const nvgs_camera* views, int32_t V, float threshold,
-                             int32_t tile, uint32_t* labels) {
+// Auxiliary label views of view v: v rotated rigidly (position and
+// orientation) about the asset centre, the origin of the asset frame, by
+// `angle` around the axes k_j = cos(phi_j) e1 + sin(phi_j) e2, phi_j = 2 pi j / aux,
+// where d = pos/|pos|, e1 = v's right axis made orthogonal to d, e2 = d x e1.
+// Each auxiliary camera stays at v's distance, on the cone of half-angle
+// `angle` around d, and keeps v's framing of the asset.
+static std::vector<nvgs_camera> aux_views(const nvgs_camera& v, int aux, double angle) {
+  std::vector<nvgs_camera> out;
+  double d[3] = {v.pos[0], v.pos[1], v.pos[2]};
+  const double dist = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+  if (dist <= 0) return out;
+  for (double& x : d) x /= dist;
+  double e1[3] = {v.R[0], v.R[1], v.R[2]};
+  const double rd = e1[0] * d[0] + e1[1] * d[1] + e1[2] * d[2];
+  for (int k = 0; k < 3; ++k) e1[k] -= rd * d[k];
+  const double l1 = std::sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+  if (!(l1 > 1e-9)) return out;
+  for (double& x : e1) x /= l1;
+  const double e2[3] = {d[1] * e1[2] - d[2] * e1[1], d[2] * e1[0] - d[0] * e1[2], d[0] * e1[1] - d[1] * e1[0]};
+  const double ca = std::cos(angle), sa = std::sin(angle);
+  for (int j = 0; j < aux; ++j) {
+    const double ph = 2.0 * M_PI * j / aux;
+    double k[3];
+    for (int q = 0; q < 3; ++q) k[q] = std::cos(ph) * e1[q] + std::sin(ph) * e2[q];
+    // Rodrigues: rot(x) = x cos a + (k x x) sin a + k (k.x)(1 - cos a)
+    auto rot = [&](const double* x, float* y) {
+      const double kx[3] = {k[1] * x[2] - k[2] * x[1], k[2] * x[0] - k[0] * x[2], k[0] * x[1] - k[1] * x[0]};
+      const double kd = k[0] * x[0] + k[1] * x[1] + k[2] * x[2];
+      for (int q = 0; q < 3; ++q) y[q] = (float)(x[q] * ca + kx[q] * sa + k[q] * kd * (1.0 - ca));
+    };
+    nvgs_camera cam = v;
+    const double p[3] = {v.pos[0], v.pos[1], v.pos[2]};
+    rot(p, cam.pos);
+    for (int r = 0; r < 3; ++r) {
+      const double row[3] = {v.R[3 * r], v.R[3 * r + 1], v.R[3 * r + 2]};
+      rot(row, cam.R + 3 * r);
+    }
+    out.push_back(cam);
+  }
+  return out;
+}
+
+nvgs_status nvgs_make_labels(nvgs_ctx* ctx, int32_t asset, const nvgs_camera* views_in, int32_t V_in, float threshold,
+                             int32_t tile, int32_t aux, float aux_angle, uint32_t* labels) {
   if (!ctx) return NVGS_E_INVALID;
+  if (aux < 0 || aux > 64 || !std::isfinite(aux_angle)) return fail(ctx, NVGS_E_INVALID, "bad auxiliary views");
+  if (!views_in || V_in <= 0) return fail(ctx, NVGS_E_INVALID, "views: null pointer or V <= 0");
+  // main views followed, per view, by its auxiliary views: label rows are OR-ed per group
+  std::vector<nvgs_camera> all;
+  for (int v = 0; v < V_in; ++v) {
+    all.push_back(views_in[v]);
+    for (const nvgs_camera& c : aux_views(views_in[v], aux, aux_angle)) all.push_back(c);
+  }
+  const nvgs_camera* views = all.data();
+  const int32_t V = (int32_t)all.size();
+  const int group = 1 + aux;
   if (ctx->assets.empty()) return fail(ctx, NVGS_E_STATE, "no assets loaded");
   if (asset < 0 || asset >= (int)ctx->assets.size()) return fail(ctx, NVGS_E_INVALID, "asset index out of range");
   if (!labels) return fail(ctx, NVGS_E_INVALID, "labels: null pointer");
@@ -645,10 +698,11 @@ nvgs_status nvgs_make_labels(nvgs_ctx* ctx, int32_t asset, const nvgs_camera* vi
   if ((s = nvgs_set_instances(ctx, &id, 1))) return s;
   const int VB = std::min(V, 16);
   const int Wd = views[0].width, Ht = views[0].height;
-  Tmp contrib(ctx), rgb(ctx);
+  Tmp contrib(ctx), rgb(ctx), rows(ctx);
   float* cb = contrib.get<float>((size_t)VB * n);
   float* img = rgb.get<float>((size_t)VB * Wd * Ht * 3);
-  if (!cb || !img) s = fail(ctx, NVGS_E_NOMEM, "label buffers");
+  uint32_t* lab_all = group == 1 ? labels : rows.get<uint32_t>((size_t)V * words);
+  if (!cb || !img || !lab_all) s = fail(ctx, NVGS_E_NOMEM, "label buffers");
   for (int v0 = 0; v0 < V && !s; v0 += VB) {
     const int nb = std::min(VB, V - v0);
     if (hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(cb), 0u, (int64_t)nb * n, ctx->stream)) {
@@ -662,9 +716,12 @@ nvgs_status nvgs_make_labels(nvgs_ctx* ctx, int32_t asset, const nvgs_camera* vi
     ro.flags = NVGS_RENDER_RECORD_CONTRIB;
     ro.contrib = cb;
     if ((s = nvgs_render(ctx, views + v0, nb, &ro, img, nullptr))) break;
-    if (hipError_t e = launch_label_bits(cb, n, nb, threshold, labels + (int64_t)v0 * words, ctx->stream))
+    if (hipError_t e = launch_label_bits(cb, n, nb, threshold, lab_all + (int64_t)v0 * words, ctx->stream))
       s = fail(ctx, NVGS_E_DEVICE, hipGetErrorString(e));
   }
+  if (!s && group > 1)
+    if (hipError_t e = launch_or_groups(lab_all, V_in, group, words, labels, ctx->stream))
+      s = fail(ctx, NVGS_E_DEVICE, hipGetErrorString(e));
   if (hipStreamSynchronize(ctx->stream) != hipSuccess && !s) s = fail(ctx, NVGS_E_DEVICE, "label renders failed");
   const std::string err = ctx->err;
   nvgs_status s2 = saved.empty() ? NVGS_OK : nvgs_set_instances(ctx, saved.data(), (int)saved.size());
@@ -697,12 +754,13 @@ nvgs_status nvgs_train_visibility(nvgs_ctx* ctx, int32_t asset, const nvgs_camer
   if (!labels) {
     uint32_t* lb = lab_tmp.get<uint32_t>((size_t)V * words);
     if (!lb) return fail(ctx, NVGS_E_NOMEM, "labels");
-    if ((s = nvgs_make_labels(ctx, asset, views, V, opts->threshold, opts->tile, lb))) return s;
+    if ((s = nvgs_make_labels(ctx, asset, views, V, opts->threshold, opts->tile, 0, 0.f, lb))) return s;
     labels = lb;
   }
   const int np = train_num_params();
   const int nwg = (int)((opts->batch + kPairsPerWG - 1) / kPairsPerWG);
-  Tmp cams_t(ctx), gam_t(ctx), part_t(ctx), lp_t(ctx), m_t(ctx), v_t(ctx), loss_t(ctx);
+  if (opts->weighting != 0 && opts->weighting != 1) return fail(ctx, NVGS_E_INVALID, "weighting must be 0 or 1");
+  Tmp cams_t(ctx), gam_t(ctx), part_t(ctx), lp_t(ctx), m_t(ctx), v_t(ctx), loss_t(ctx), cnt_t(ctx);
   nvgs_camera* cams_d = cams_t.get<nvgs_camera>(V);
   float* gam = gam_t.get<float>((size_t)V * 36);
   float* part = part_t.get<float>((size_t)nwg * np);
@@ -710,17 +768,23 @@ nvgs_status nvgs_train_visibility(nvgs_ctx* ctx, int32_t asset, const nvgs_camer
   float* m = m_t.get<float>(np);
   float* v = v_t.get<float>(np);
   float* loss = loss_t.get<float>(opts->steps);
-  if (!cams_d || !gam || !part || !lp || !m || !v || !loss) return fail(ctx, NVGS_E_NOMEM, "training buffers");
+  uint32_t* npos = cnt_t.get<uint32_t>(opts->steps);
+  if (!cams_d || !gam || !part || !lp || !m || !v || !loss || !npos)
+    return fail(ctx, NVGS_E_NOMEM, "training buffers");
   CK(hipMemcpy(cams_d, views, sizeof(nvgs_camera) * V, hipMemcpyHostToDevice));
   CK(launch_fill_u32(reinterpret_cast<uint32_t*>(m), 0u, np, ctx->stream));
   CK(launch_fill_u32(reinterpret_cast<uint32_t*>(v), 0u, np, ctx->stream));
   CK(launch_view_gam(cams_d, V, A.mlp.cam_scale, A.mlp.train_focal, A.mlp.d_max, gam, ctx->stream));
   const bool bf16 = opts->precision == NVGS_PREC_BF16;
   const float inv_b = 1.f / (float)opts->batch;
+  const bool weighted = opts->weighting == 1;
+  if (weighted) CK(launch_fill_u32(npos, 0u, opts->steps, ctx->stream));
   for (int step = 0; step < opts->steps; ++step) {
+    if (weighted)
+      CK(launch_count_pos(opts->batch, n, V, labels, opts->seed, step, npos + step, ctx->stream));
     CK(launch_mlp_train(0, bf16, nwg, kTrainChunksPerWG, ctx->stream, params, opts->batch, inv_b, A.mean, n,
-                        A.mlp.mean_scale, gam, V, labels, opts->seed, step, nullptr, nullptr, nullptr, part, lp,
-                        nullptr));
+                        A.mlp.mean_scale, gam, V, labels, opts->seed, step, weighted ? npos + step : nullptr, nullptr,
+                        nullptr, nullptr, part, lp, nullptr));
     CK(launch_reduce_adam(part, nwg, params, m, v, nullptr, opts->lr, opts->beta1, opts->beta2, opts->eps, step + 1,
                           lp, inv_b, loss + step, ctx->stream));
   }
@@ -738,7 +802,7 @@ nvgs_status nvgs_mlp_forward(nvgs_ctx* ctx, const float* params, int32_t width, 
   CK(hipSetDevice(ctx->device));
   const int nwg = (int)((B + kPairsPerWG - 1) / kPairsPerWG);
   CK(launch_mlp_train(1, precision == NVGS_PREC_BF16, nwg, kTrainChunksPerWG, ctx->stream, params, B, 1.f, nullptr,
-                      1, 0.f, nullptr, 1, nullptr, 0, 0, X, nullptr, logits, nullptr, nullptr, nullptr));
+                      1, 0.f, nullptr, 1, nullptr, 0, 0, nullptr, X, nullptr, logits, nullptr, nullptr, nullptr));
   return NVGS_OK;
 }
 
@@ -755,7 +819,7 @@ nvgs_status nvgs_mlp_backward(nvgs_ctx* ctx, const float* params, int32_t width,
   float* part = part_t.get<float>((size_t)nwg * train_num_params());
   if (!part) return fail(ctx, NVGS_E_NOMEM, "gradient partials");
   CK(launch_mlp_train(2, precision == NVGS_PREC_BF16, nwg, kTrainChunksPerWG, ctx->stream, params, B, 1.f, nullptr,
-                      1, 0.f, nullptr, 1, nullptr, 0, 0, X, dlogits, nullptr, part, nullptr, dX));
+                      1, 0.f, nullptr, 1, nullptr, 0, 0, nullptr, X, dlogits, nullptr, part, nullptr, dX));
   CK(launch_reduce_adam(part, nwg, nullptr, nullptr, nullptr, dparams, 0.f, 0.f, 0.f, 1.f, 1, nullptr, 0.f, nullptr,
                         ctx->stream));
   return NVGS_OK;

@@ -136,8 +136,11 @@ hipError_t launch_label_bits(const float* contrib, int64_t n, int V, float thr, 
 hipError_t launch_mlp_train(int mode, bool bf16, int nwg, int chunks_per_wg, hipStream_t st, const float* params,
                             int64_t batch, float inv_batch, const float* mean, int64_t n, float mean_scale,
                             const float* view_gam, int V, const uint32_t* labels, uint64_t seed, int64_t step,
-                            const float* X, const float* dlogits, float* logits, float* partial, float* loss_part,
-                            float* dX);
+                            const uint32_t* n_pos, const float* X, const float* dlogits, float* logits,
+                            float* partial, float* loss_part, float* dX);
+hipError_t launch_or_groups(const uint32_t* rows, int V, int group, int64_t words, uint32_t* out, hipStream_t st);
+hipError_t launch_count_pos(int64_t batch, int64_t n, int V, const uint32_t* labels, uint64_t seed, int64_t step,
+                            uint32_t* count, hipStream_t st);
 hipError_t launch_reduce_adam(const float* partial, int nwg, float* params, float* m, float* v, float* grad_out,
                               float lr, float b1, float b2, float eps, int64_t t, const float* loss_part,
                               float inv_batch, float* loss_out, hipStream_t st);

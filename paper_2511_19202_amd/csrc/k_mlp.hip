@@ -254,7 +254,8 @@ __global__ void k_segment_setup(const nvgs_camera* __restrict__ cams, const nvgs
   for (int r = 0; r < 3; ++r)
     cl[r] = ((double)in.R[r] * d[0] + (double)in.R[3 + r] * d[1] + (double)in.R[6 + r] * d[2]) / (double)in.s;
   // FoV correction (Eq. 2) and far clamp of the MLP's camera input
-  double f_r = 1.0 / tan(0.5 * (double)cam.fovy);
+  // Eq. 2 with focal lengths in pixels: f_r = (H / 2) / tan(fovy / 2)
+  double f_r = 0.5 * (double)cam.height / tan(0.5 * (double)cam.fovy);
   double fac = (double)A.train_focal / f_r;
   double cm[3] = {cl[0] * fac, cl[1] * fac, cl[2] * fac};
   double len = sqrt(cm[0] * cm[0] + cm[1] * cm[1] + cm[2] * cm[2]);

@@ -76,7 +76,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     const float* __restrict__ params, int64_t batch, int chunks_per_wg, float inv_batch,
     // training inputs
     const float* __restrict__ mean, int64_t n, float mean_scale, const float* __restrict__ view_gam, int V,
-    const uint32_t* __restrict__ labels, uint64_t seed, int64_t step,
+    const uint32_t* __restrict__ labels, uint64_t seed, int64_t step, const uint32_t* __restrict__ n_pos,
     // forward / backward inputs
     const float* __restrict__ X, const float* __restrict__ dlogits,
     // outputs
@@ -186,9 +186,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
       float d = 0.f;
       if (MODE == kModeTrain && live) {
         const float y = S.dz[t];
+        float w = 1.f;  // frequency weighting: B / (2 n_class)
+        if (n_pos) {
+          const float np_ = (float)*n_pos, nn_ = (float)batch - np_;
+          const float wc = y > 0.5f ? np_ : nn_;
+          w = wc > 0.f ? 0.5f * (float)batch / wc : 0.f;
+        }
         const float sig = 1.f / (1.f + expf(-z));
-        loss += fmaxf(z, 0.f) - z * y + log1pf(expf(-fabsf(z)));
-        d = (sig - y) * inv_batch;
+        loss += w * (fmaxf(z, 0.f) - z * y + log1pf(expf(-fabsf(z))));
+        d = w * (sig - y) * inv_batch;
       } else if (MODE == kModeBackward) {
         d = live ? dlogits[gi] : 0.f;
       } else if (live) {
@@ -364,7 +370,7 @@ __global__ void k_view_gam(const nvgs_camera* __restrict__ views, int V, float c
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= V) return;
   const nvgs_camera& c = views[v];
-  const double f_r = 1.0 / tan(0.5 * (double)c.fovy);
+  const double f_r = 0.5 * (double)c.height / tan(0.5 * (double)c.fovy);  // pixels
   const double fac = (double)train_focal / f_r;
   double cm[3] = {c.pos[0] * fac, c.pos[1] * fac, c.pos[2] * fac};
   const double len = sqrt(cm[0] * cm[0] + cm[1] * cm[1] + cm[2] * cm[2]);
@@ -392,6 +398,46 @@ __global__ void k_label_bits(const float* __restrict__ contrib, int64_t n, int V
   }
 }
 
+// number of positive labels among the pairs of one training step
+__global__ void k_count_pos(int64_t batch, int64_t n, int V, const uint32_t* __restrict__ labels, uint64_t seed,
+                            int64_t step, uint32_t* __restrict__ count) {
+  const int64_t words = (n + 31) / 32;
+  uint32_t c = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < batch; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t r = splitmix64(seed, (uint64_t)step * (uint64_t)batch + (uint64_t)i);
+    const int64_t g = (int64_t)(((r & 0xffffffffull) * (uint64_t)n) >> 32);
+    const int64_t v = (int64_t)(((r >> 32) * (uint64_t)V) >> 32);
+    c += (labels[v * words + (g >> 5)] >> (g & 31)) & 1u;
+  }
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+  if ((threadIdx.x & 63) == 0) atomicAdd(count, c);
+}
+
+hipError_t launch_count_pos(int64_t batch, int64_t n, int V, const uint32_t* labels, uint64_t seed, int64_t step,
+                            uint32_t* count, hipStream_t st) {
+  const unsigned grid = (unsigned)std::min<int64_t>((batch + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_count_pos, dim3(grid), dim3(256), 0, st, batch, n, V, labels, seed, step, count);
+  return hipGetLastError();
+}
+
+// labels[v][w] = OR over the `group` rows v*group .. v*group+group-1 of rows
+__global__ void k_or_groups(const uint32_t* __restrict__ rows, int V, int group, int64_t words,
+                            uint32_t* __restrict__ out) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < (int64_t)V * words;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t v = e / words, w = e % words;
+    uint32_t b = 0;
+    for (int k = 0; k < group; ++k) b |= rows[((int64_t)v * group + k) * words + w];
+    out[e] = b;
+  }
+}
+
+hipError_t launch_or_groups(const uint32_t* rows, int V, int group, int64_t words, uint32_t* out, hipStream_t st) {
+  const unsigned grid = (unsigned)std::min<int64_t>(((int64_t)V * words + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_or_groups, dim3(grid), dim3(256), 0, st, rows, V, group, words, out);
+  return hipGetLastError();
+}
+
 size_t train_smem_bytes() { return sizeof(TrainSmem); }
 int train_num_params() { return kNumParams; }
 
@@ -411,8 +457,8 @@ hipError_t launch_label_bits(const float* contrib, int64_t n, int V, float thr, 
 template <bool BF16R, int MODE>
 static hipError_t launch_mlp_t(int nwg, int cpw, hipStream_t st, const float* params, int64_t batch, float inv_batch,
                                const float* mean, int64_t n, float msc, const float* gam, int V, const uint32_t* labels,
-                               uint64_t seed, int64_t step, const float* X, const float* dlogits, float* logits,
-                               float* partial, float* loss_part, float* dX) {
+                               uint64_t seed, int64_t step, const uint32_t* n_pos, const float* X,
+                               const float* dlogits, float* logits, float* partial, float* loss_part, float* dX) {
   auto kern = k_mlp_train<BF16R, MODE>;
   static bool attr = false;
   if (!attr) {
@@ -422,7 +468,7 @@ static hipError_t launch_mlp_t(int nwg, int cpw, hipStream_t st, const float* pa
     attr = true;
   }
   hipLaunchKernelGGL(kern, dim3(nwg), dim3(256), sizeof(TrainSmem), st, params, batch, cpw, inv_batch, mean, n, msc,
-                     gam, V, labels, seed, step, X, dlogits, logits, partial, loss_part, dX);
+                     gam, V, labels, seed, step, n_pos, X, dlogits, logits, partial, loss_part, dX);
   return hipGetLastError();
 }
 
@@ -430,11 +476,11 @@ static hipError_t launch_mlp_t(int nwg, int cpw, hipStream_t st, const float* pa
 hipError_t launch_mlp_train(int mode, bool bf16, int nwg, int chunks_per_wg, hipStream_t st, const float* params,
                             int64_t batch, float inv_batch, const float* mean, int64_t n, float mean_scale,
                             const float* view_gam, int V, const uint32_t* labels, uint64_t seed, int64_t step,
-                            const float* X, const float* dlogits, float* logits, float* partial, float* loss_part,
-                            float* dX) {
+                            const uint32_t* n_pos, const float* X, const float* dlogits, float* logits,
+                            float* partial, float* loss_part, float* dX) {
 #define NVGS_MLPT(B, M)                                                                                             \
   return launch_mlp_t<B, M>(nwg, chunks_per_wg, st, params, batch, inv_batch, mean, n, mean_scale, view_gam, V,   \
-                            labels, seed, step, X, dlogits, logits, partial, loss_part, dX)
+                            labels, seed, step, n_pos, X, dlogits, logits, partial, loss_part, dX)
   if (bf16) {
     if (mode == 0) NVGS_MLPT(true, 0);
     if (mode == 1) NVGS_MLPT(true, 1);

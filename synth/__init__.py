@@ -52,7 +52,7 @@ class MLPSpec:
     bands: int = 6
     mean_scale: float = 0.5     # sigma_mu
     cam_scale: float = 0.05     # sigma_c
-    train_focal: float = 1.0    # 1 / tan(fov_train / 2)
+    train_focal: float = 548.9  # focal length (pixels) of the training views: (H/2) / tan(fovy/2)
     d_min: float = 0.0          # minimum-distance gate (0 = off)
     d_max: float = 0.0          # far clamp of the local camera distance (0 = off)
 
@@ -230,15 +230,16 @@ def pow2_scale(r: float) -> float:
 
 
 def make_asset(shape: str, n: int, sh_degree: int, seed: int, width: int = 64,
-               cam_scale: float = 0.05, fov_train: float = math.radians(50.0),
-               d_max: float = 0.0) -> Asset:
+               cam_scale: float = 0.05, fov_train: float = math.radians(50.0), res_train: int = 512,
+               d_max: float = 20.0) -> Asset:
     g = rng(seed)
     means = SHAPES[shape](n, g)
     scale, quat, opacity, sh = gaussian_params(means, g, sh_degree)
     params = mlp_params(width, g)
     spec = MLPSpec(params=params, width=width, bands=6,
                    mean_scale=pow2_scale(SHAPE_HALF_DIAG[shape]), cam_scale=cam_scale,
-                   train_focal=1.0 / math.tan(fov_train / 2.0), d_min=0.0, d_max=d_max)
+                   train_focal=float(np.float32(0.5 * res_train / math.tan(float(np.float32(fov_train)) / 2.0))),
+                   d_min=0.0, d_max=d_max)
     return Asset(mean=means, scale=scale, quat=quat, opacity=opacity, sh=sh,
                  sh_degree=sh_degree, mlp=spec, name=shape)
 
@@ -343,17 +344,31 @@ def scene_batched(n_assets: int = 16, n_inst: int = 1024, n_cams: int = 8,
                  extra={"instances_per_asset": per_asset.tolist(), "sizes": sizes.tolist()})
 
 
+def fibonacci_sphere(n: int) -> np.ndarray:
+    """n unit directions on the Fibonacci (golden-angle) spiral, [n, 3]."""
+    k = np.arange(n, dtype=np.float64) + 0.5
+    z = 1.0 - 2.0 * k / n
+    rho = np.sqrt(np.maximum(0.0, 1.0 - z * z))
+    phi = k * math.pi * (3.0 - math.sqrt(5.0))
+    return np.stack([rho * np.cos(phi), rho * np.sin(phi), z], axis=1)
+
+
 def label_views(n_views: int, seed: int, d_lo: float = 1.5, d_hi: float = 20.0,
-                res: int = 512, fovy_deg: float = 50.0) -> List[Camera]:
-    """Random training views: uniform directions on the sphere, distance
-    U(d_lo, d_hi), looking at the asset centre."""
+                res: int = 512, fovy_deg: float = 50.0, offset: float = 0.0) -> List[Camera]:
+    """Training views (Sec. 3.1 recipe): Fibonacci-sphere directions, distance
+    U(d_lo, d_hi) per view, looking at the asset centre displaced by a random
+    offset of at most `offset` * distance * tan(fovy / 2) per axis (so the
+    asset stays in the frustum while leaving the image centre)."""
     g = rng(seed)
-    d = g.standard_normal((n_views, 3))
-    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    d = fibonacci_sphere(n_views)
     r = g.uniform(d_lo, d_hi, n_views)
-    return [camera(d[k] * r[k], fovy_deg=fovy_deg, width=res, height=res) for k in range(n_views)]
+    off = g.uniform(-1.0, 1.0, (n_views, 3))
+    t = math.tan(math.radians(fovy_deg) / 2)
+    return [camera(d[k] * r[k], target=tuple(off[k] * offset * r[k] * t), fovy_deg=fovy_deg, width=res, height=res)
+            for k in range(n_views)]
 
 
 def scene_train(n: int = 500000, seed: int = SEED_BASE + 5, width: int = 64, sh_degree: int = 3) -> Scene:
-    a = make_asset("torus", n, sh_degree, seed * 100 + 0, width=width, cam_scale=1.0 / 20.0, d_max=20.0)
+    a = make_asset("torus", n, sh_degree, seed * 100 + 0, width=width, cam_scale=1.0 / 20.0, d_max=20.0,
+                   res_train=512)
     return Scene(assets=[a], instances=[identity_instance(0)], cameras=[], tile=16, name="train")

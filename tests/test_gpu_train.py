@@ -97,23 +97,28 @@ def _small_asset(n=3000, seed=4):
     return a
 
 
-def test_labels_match_oracle(env):
+@pytest.mark.parametrize("aux", [0, 6])
+def test_labels_match_oracle(env, aux):
+    """Labels rendered by the library equal the oracle's (largest alpha*T over
+    the view and its auxiliary views above 1/255) away from the threshold."""
     nvgs, ctx, torch = env
     a = _small_asset()
-    views = synth.label_views(6, seed=3, d_lo=2.0, d_hi=4.0, res=96)
+    views = synth.label_views(6, seed=3, d_lo=2.0, d_hi=4.0, res=96, offset=0.2)
+    ang = math.radians(5.0)
     ctx.load_assets([a])
-    lab = ctx.make_labels(0, views).cpu().numpy().view(np.uint32)
+    lab = ctx.make_labels(0, views, aux=aux, aux_angle=ang).cpu().numpy().view(np.uint32)
     bits = np.unpackbits(lab.view(np.uint8).reshape(len(views), -1), axis=1, bitorder="little")[:, :a.n]
-    cb = oracle.contributions(a, views)
+    cb = np.stack([oracle.contributions(a, [v] + oracle.aux_views(v, aux, ang)).max(axis=0) for v in views])
     ref = cb > 1 / 255
     diff = bits.astype(bool) != ref
     near = np.abs(cb - 1 / 255) < 2e-3 / 255
-    log(f"[labels] {ref.mean():.3f} visible; mismatches {diff.sum()} (near threshold {np.sum(diff & near)})")
+    log(f"[labels aux={aux}] {ref.mean():.3f} visible; mismatches {diff.sum()} (near threshold {np.sum(diff & near)})")
     assert 0.1 < ref.mean() < 0.95
     assert np.sum(diff & ~near) <= max(2, 1e-4 * diff.size)
 
 
-def test_training_step_matches_oracle(env):
+@pytest.mark.parametrize("weighting", [0, 1])
+def test_training_step_matches_oracle(env, weighting):
     """One FP32 Adam step on oracle labels: the GPU's batch loss equals the
     oracle's on the same SplitMix64-drawn pairs, and the first Adam update
     (lr * sign(g) where |g| >> eps) agrees."""
@@ -130,7 +135,7 @@ def test_training_step_matches_oracle(env):
     pt = torch.from_numpy(p0.copy()).cuda()
     B, seed, lr = 1000, 77, 1e-3
     curve = ctx.train_visibility(0, views, pt, labels=torch.from_numpy(lab_words.view(np.int32)).cuda(), batch=B,
-                                 steps=1, precision="fp32", lr=lr, seed=seed)
+                                 steps=1, precision="fp32", lr=lr, seed=seed, weighting=weighting)
     g_idx, v_idx = oracle.sample_pairs(seed, 0, B, a.n, len(views))
     X = np.zeros((B, 72))
     for v in np.unique(v_idx):
@@ -138,7 +143,11 @@ def test_training_step_matches_oracle(env):
         cl = oracle.local_camera(synth.identity_instance(), views[v], a.mlp.train_focal, a.mlp.d_max)
         X[sel] = oracle.mlp_inputs(a, g_idx[sel], cl)
     y = lab[v_idx, g_idx].astype(np.float64)
-    loss, dP = oracle.bce_backward(p0, 64, X, y)
+    w = None
+    if weighting:  # each sample weighted by B / (2 n_class)
+        npos = y.sum()
+        w = np.where(y > 0.5, B / (2 * npos), B / (2 * (B - npos)))
+    loss, dP = oracle.bce_backward(p0, 64, X, y, w=w)
     log(f"[train] loss gpu {curve[0]:.6f} oracle {loss:.6f}")
     assert abs(curve[0] - loss) < 1e-5 * max(1.0, loss)
     p64 = p0.astype(np.float64)

@@ -101,19 +101,27 @@ def test_mlp_bias_only_is_constant(orc):
 # ---------------------------------------------------------------------------
 def test_local_camera_eq2_fov_and_scale(orc):
     inst = Instance(asset=0, R=synth.yaw(0.7), s=2.0, t=np.array([3.0, -1.0, 0.5], np.float32))
-    cam = synth.camera((10.0, 4.0, 6.0), fovy_deg=20.0)
-    f_t = 1.0 / math.tan(math.radians(30.0))  # trained at 60 deg
+    cam = synth.camera((10.0, 4.0, 6.0), fovy_deg=20.0, width=300, height=200)
+    f_t = 256.0 / math.tan(math.radians(30.0))  # trained at 60 deg, 512 px tall
     cl = orc.local_camera(inst, cam, f_t)
     d_r = np.linalg.norm(np.asarray(cam.pos, np.float64) - inst.t)
-    # Eq. 2: d_t = d_r (f_t / f_r) / s with f = 1 / tan(fov / 2)
-    d_t = d_r * (f_t * math.tan(math.radians(10.0))) / 2.0
+    # Eq. 2: d_t = d_r (f_t / f_r) / s with focal lengths in pixels (H/2) / tan(fovy/2)
+    f_r = 100.0 / math.tan(float(np.float32(math.radians(20.0))) / 2)
+    d_t = d_r * (f_t / f_r) / 2.0
     # (the float32 rotation is orthonormal to ~1e-7)
     assert abs(np.linalg.norm(cl) - d_t) < 2e-7 * d_t
     # direction: R^T (c - t) / |c - t|
     dir_ = inst.R.astype(np.float64).T @ (np.asarray(cam.pos, np.float64) - inst.t)
     np.testing.assert_allclose(cl / np.linalg.norm(cl), dir_ / np.linalg.norm(dir_), atol=1e-12)
-    # FoV 60 -> 20 shrinks the distance by tan 10 / tan 30
-    assert abs(d_t * 2.0 / d_r - math.tan(math.radians(10)) / math.tan(math.radians(30))) < 1e-12
+    # same resolution, FoV 60 -> 20: the distance shrinks by tan 10 / tan 30
+    cam2 = synth.camera((10.0, 4.0, 6.0), fovy_deg=20.0, width=512, height=512)
+    cl2 = orc.local_camera(inst, cam2, f_t)
+    ratio = np.linalg.norm(cl2) * 2.0 / d_r
+    assert abs(ratio - math.tan(float(np.float32(math.radians(20.0))) / 2) / math.tan(math.radians(30))) < 2e-7
+    # same FoV, twice the resolution: half the distance
+    cam3 = synth.camera((10.0, 4.0, 6.0), fovy_deg=60.0, width=1024, height=1024)
+    cl3 = orc.local_camera(inst, cam3, f_t)
+    assert abs(np.linalg.norm(cl3) * 2.0 / d_r - 0.5) < 2e-7
     # the far clamp keeps the direction and caps the length
     clc = orc.local_camera(inst, cam, f_t, d_max=0.5 * d_t)
     assert abs(np.linalg.norm(clc) - 0.5 * d_t) < 1e-12
@@ -601,3 +609,38 @@ def test_psnr(orc):
     a = np.random.default_rng(0).uniform(0, 1, (8, 8, 3))
     assert orc.psnr(a, a) == 100.0
     assert abs(orc.psnr(a, a + 0.01) - 40.0) < 1e-9
+
+
+def test_aux_views_lie_on_the_cone_and_keep_framing(orc):
+    """Auxiliary views (Sec. 3.1): same distance, at the cone angle from the
+    main direction, evenly spaced around it, orthonormal orientation, and the
+    asset centre stays where the main view sees it."""
+    main = synth.camera((1.0, -3.0, 2.0), target=(0.2, 0.1, -0.1), width=64, height=48)
+    ang = math.radians(5.0)
+    aux = orc.aux_views(main, 6, ang)
+    p0 = main.pos.astype(np.float64)
+    d = p0 / np.linalg.norm(p0)
+    ring = []
+    for cam in aux:
+        p = cam.pos.astype(np.float64)
+        assert abs(np.linalg.norm(p) - np.linalg.norm(p0)) < 1e-5
+        assert abs(math.acos(np.clip(np.dot(p, d) / np.linalg.norm(p), -1, 1)) - ang) < 1e-5
+        R = cam.R.astype(np.float64)
+        assert np.allclose(R @ R.T, np.eye(3), atol=1e-6)
+        # the centre (origin) in camera coordinates is unchanged by a rigid turn about it
+        assert np.allclose(R @ (-p), main.R.astype(np.float64) @ (-p0), atol=1e-5)
+        ring.append(p - np.dot(p, d) * d)
+    gaps = [np.linalg.norm(ring[j] - ring[(j + 1) % 6]) for j in range(6)]
+    assert max(gaps) - min(gaps) < 1e-5
+    # zero angle: the auxiliary views coincide with the main view
+    for cam in orc.aux_views(main, 3, 0.0):
+        assert np.allclose(cam.pos, main.pos) and np.allclose(cam.R, main.R)
+
+
+def test_labels_with_aux_views_are_a_superset(orc):
+    a = synth.make_asset("sphere", 600, 0, 4242, width=16)
+    views = synth.label_views(2, seed=11, d_lo=2.0, d_hi=3.0, res=48)
+    base = orc.labels(a, views)
+    wide = orc.labels(a, views, aux=4, aux_angle=math.radians(10.0))
+    assert np.all(wide >= base)
+    assert wide.sum() > base.sum()
