@@ -2,17 +2,28 @@
 """Frame benchmark of the NVGS renderer on one MI355X.
 
 One step is one full frame of the per-frame path (cull -> visibility MLP ->
-compaction -> projection -> tile binning and sort -> compositing) over the
-composed 1080p scene: 4 assets (torus, sphere shell, box shell, helix tube)
-of 250,000 SH-degree-3 Gaussians each, 64 instances with random yaw, scale
-U(0.5, 2) and positions on a 40 x 40 ground plane, one camera, one width-64
-FP32 visibility MLP per asset.  Inputs are seeded synthetic stand-ins for the
-paper's composed scenes and are resident in HBM before timing starts.
+compaction -> projection -> tile binning and sort -> compositing), run as the
+library's persistent frame (one captured HIP graph replayed per frame, the
+cameras uploaded before each replay).
 
-Before timing, each asset's MLP is trained by the library (renderer-made
-visibility labels from 512 random views at 512x512, batches of 65,536 pairs,
-BF16 forward/backward, Adam 1e-3, 5000 steps); `--mlp random` instead uses
-seeded weights with the output bias set to keep 65% of the in-frustum pairs.
+--workload composed (default): the composed 1080p scene, 4 assets (torus,
+sphere shell, box shell, helix tube) of 250,000 SH-degree-3 Gaussians each,
+64 instances with random yaw, scale U(0.5, 2) and positions on a 40 x 40
+ground plane, one camera, one width-64 FP32 visibility MLP per asset.
+
+--workload batched: 16 assets of log-uniform sizes in [50k, 1M] (SH 3),
+1,024 instances with Zipf counts per asset on a 160 x 160 plane, 8 cameras at
+1080p on a ring of radius 60 at height 15; the ring turns 1 degree per frame
+over 360 frames for the p50 / p99 frame times.
+
+Inputs are seeded synthetic stand-ins for the paper's scenes and are resident
+in HBM before timing starts.  Before timing, each asset's MLP is trained by
+the library on renderer-made labels (Sec. 3.1 recipe: Fibonacci views at
+distances U(1.5, 20) with a random offset, 6 auxiliary views on a 5 degree
+cone, class-frequency weighted BCE, BF16 forward/backward, Adam 1e-3,
+batches of 65,536 pairs); `--mlp random` instead uses seeded weights with the
+output bias set to keep 65% of the in-frustum pairs.  Tile size and MLP block
+shape come from the library's autotuner unless --tile is given.
 
 Prints one JSON line.
 """
@@ -177,24 +188,76 @@ def psnr(a, b):
     return 100.0 if mse == 0 else min(100.0, 10 * math.log10(1.0 / mse))
 
 
-def main():
+def time_graph(ctx, cam_sets, steps, warmup, **kw):
+    """Persistent frames: `warmup` untimed, then `steps` timed replays cycling
+    through `cam_sets`; returns (wall seconds per frame, per-frame ms from
+    HIP events on the context stream)."""
+    import torch
+    for i in range(warmup):
+        ctx.render(cam_sets[i % len(cam_sets)], graph=True, **kw)
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for i in range(steps):
+        evs[i][0].record(s)
+        ctx.render(cam_sets[i % len(cam_sets)], graph=True, **kw)
+        evs[i][1].record(s)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    per = [a.elapsed_time(b) for a, b in evs]
+    return (t1 - t0) / steps, per
+
+
+def prepare(ctx, cam_sets, tile_arg, precision, reps=3, use_mlp_modes=(True, False)):
+    """Autotune (unless a tile is given), then size the persistent frame's
+    capacities from eager frames over the camera sets (10% headroom)."""
+    tune = None
+    if tile_arg == 0:
+        tile, shape, table = ctx.autotune(cam_sets[0], precision=precision, reps=reps)
+        tune = {"tile": tile, "mlp_shape": list(shape), "table": table}
+    else:
+        tile = tile_arg
+    ctx.watermarks(reset=True)
+    for cams in cam_sets:
+        for um in use_mlp_modes:
+            ctx.render(cams, tile=tile, precision=precision, use_mlp=um)
+    wm = ctx.watermarks(reset=True)
+    ctx.reserve(int(wm["max_splats"] * 1.1) + 4096, int(wm["max_duplicates"] * 1.1) + 4096)
+    return tile, tune
+
+
+def check_no_overflow(ctx):
+    wm = ctx.watermarks(reset=True)
+    if wm["overflowed"]:
+        raise RuntimeError(f"a timed frame exceeded the reserved capacities: {wm}")
+
+
+def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--tile", type=int, default=0, help="8, 16, 32, or 0 to autotune")
-    ap.add_argument("--precision", default="fp32")
+    ap.add_argument("--workload", default="composed", choices=["composed", "batched"])
+    ap.add_argument("--tile", type=int, default=0, help="8, 16, 32, or 0 to autotune (tile and MLP block shape)")
+    ap.add_argument("--precision", default=None, help="MLP precision (default fp32 composed, bf16 batched)")
     ap.add_argument("--mlp", default="trained", choices=["trained", "random"],
                     help="trained: per-asset MLPs trained on renderer labels; random: seeded weights with the "
                          "output bias set to keep --keep of the in-frustum pairs")
     ap.add_argument("--train-steps", type=int, default=5000)
+    ap.add_argument("--views", type=int, default=2000, help="label views per asset")
     ap.add_argument("--keep", type=float, default=0.65)
     ap.add_argument("--n", type=int, default=250000)
+    ap.add_argument("--frames", type=int, default=360, help="batched: ring positions (1 degree apart)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--extra-precisions", default="", help="comma list, e.g. bf16,fp8")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many bytes (calibrates HBM byte counters)")
-    args = ap.parse_args()
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
     if args.copy_probe:
         import torch
         a = torch.empty(args.copy_probe // 4, dtype=torch.float32, device="cuda")
@@ -205,49 +268,53 @@ def main():
         print(json.dumps({"copy_probe_bytes": args.copy_probe, "launches": 3}))
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the renderer shards across GPUs only by design, see the design notes)", file=sys.stderr)
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported: splitting a frame across "
+              "GPUs (by camera, or by screen band after projection) is designed but not built", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batched":
+        return main_batched(args)
     import torch
     import paper_2511_19202_amd as nvgs
     import synth
 
+    prec = args.precision or "fp32"
     sc = synth.scene_composed(n_per_asset=args.n)
     ctx = nvgs.Context(0)
     ctx.load_assets(sc.assets)
     ctx.set_instances(sc.instances)
     training = None
     if args.mlp == "trained":
-        training = train_assets(ctx, sc, steps=args.train_steps)
+        training = train_assets(ctx, sc, views=args.views, steps=args.train_steps)
     else:
-        calibrate_keep(ctx, sc, args.keep, args.precision)
-    tile = args.tile
-    tune = {}
-    if tile == 0:  # autotune the tile edge on this scene (the image does not depend on it)
-        for T in (8, 16, 32):
-            ctx.render(sc.cameras, tile=T, precision=args.precision)
-            ms = [ctx.render(sc.cameras, tile=T, precision=args.precision, stats=True)[1]["ms"] for _ in range(3)]
-            tune[T] = float(np.median(ms))
-        tile = min(tune, key=tune.get)
-    kw = dict(tile=tile, precision=args.precision)
-    t_c, stage_c, st_c, img_c = time_frames(ctx, sc, args.steps, args.warmup, use_mlp=True, **kw)
+        calibrate_keep(ctx, sc, args.keep, prec)
+    tile, tune = prepare(ctx, [sc.cameras], args.tile, prec)
+    kw = dict(tile=tile, precision=prec)
+    # headline: persistent frames, culled and unculled
+    t_c, per_c = time_graph(ctx, [sc.cameras], args.steps, args.warmup, use_mlp=True, **kw)
+    t_u, per_u = time_graph(ctx, [sc.cameras], args.steps, args.warmup, use_mlp=False, **kw)
+    check_no_overflow(ctx)
+    # per-stage kernel times and counts: eager frames with HIP stage events
+    _, stage_c, st_c, img_c = time_frames(ctx, sc, max(5, args.steps // 5), 2, use_mlp=True, **kw)
     img_c = img_c.cpu().numpy()
-    t_u, stage_u, st_u, img_u = time_frames(ctx, sc, args.steps, args.warmup, use_mlp=False, **kw)
+    _, stage_u, st_u, img_u = time_frames(ctx, sc, max(5, args.steps // 5), 2, use_mlp=False, **kw)
     img_u = img_u.cpu().numpy()
+    g_c = ctx.render(sc.cameras, graph=True, use_mlp=True, **kw).cpu().numpy()
+    graph_equals_eager = bool(np.array_equal(g_c, img_c))
 
     width = sc.assets[0].mlp.width
-    dom, roof = roofline(stage_c, st_c, width, args.precision, sc.assets[0].sh_degree)
+    dom, roof = roofline(stage_c, st_c, width, prec, sc.assets[0].sh_degree)
     extra = {}
-    for prec in [p for p in args.extra_precisions.split(",") if p]:
+    for p2 in [p for p in args.extra_precisions.split(",") if p]:
         try:
-            t_p, stage_p, st_p, img_p = time_frames(ctx, sc, args.steps, args.warmup, use_mlp=True, tile=tile,
-                                                    precision=prec)
-            extra[prec] = {"fps": 1.0 / t_p, "ms_cull_mlp": stage_p["cull_mlp"],
-                           "psnr_vs_fp32_culled_db": psnr(img_p.cpu().numpy(), img_c),
-                           "psnr_vs_unculled_db": psnr(img_p.cpu().numpy(), img_u),
-                           "kept": st_p["kept"]}
+            t_p, _ = time_graph(ctx, [sc.cameras], args.steps, args.warmup, use_mlp=True, tile=tile, precision=p2)
+            check_no_overflow(ctx)
+            _, stage_p, st_p, img_p = time_frames(ctx, sc, 5, 1, use_mlp=True, tile=tile, precision=p2)
+            extra[p2] = {"fps": 1.0 / t_p, "ms_cull_mlp": stage_p["cull_mlp"],
+                         "psnr_vs_fp32_culled_db": psnr(img_p.cpu().numpy(), img_c),
+                         "psnr_vs_unculled_db": psnr(img_p.cpu().numpy(), img_u),
+                         "kept": st_p["kept"]}
         except Exception as e:  # report, do not hide
-            extra[prec] = {"error": str(e)}
+            extra[p2] = {"error": str(e)}
     fps = 1.0 / t_c
     out = {
         "metric": "1080p FPS + visibility-MLP queries/s, culled vs unculled, PSNR vs FP64 oracle",
@@ -265,13 +332,16 @@ def main():
         "config": {"workload": "composed-1080p: 4 assets x 250k SH3 Gaussians, 64 instances, 1 camera, "
                                "width-64 MLP per asset",
                    "gaussians_stored": sum(a.n for a in sc.assets), "instances": len(sc.instances),
-                   "pairs": st_c["pairs"], "resolution": "1920x1080", "mlp_precision": args.precision,
-                   "tile": tile, "tile_autotune_ms": tune, "mlp": args.mlp,
-                   "keep_target": args.keep if args.mlp == "random" else None},
+                   "pairs": st_c["pairs"], "resolution": "1920x1080", "mlp_precision": prec,
+                   "tile": tile, "mlp_shape": list(ctx.mlp_shape), "autotune": tune, "mlp": args.mlp,
+                   "keep_target": args.keep if args.mlp == "random" else None, "frame": "persistent (HIP graph)"},
         "fps_unculled": 1.0 / t_u,
+        "frame_ms_p50": float(np.percentile(per_c, 50)), "frame_ms_p99": float(np.percentile(per_c, 99)),
+        "frame_ms_p50_unculled": float(np.percentile(per_u, 50)),
         "mlp_queries_per_s": st_c["queried"] / (stage_c["cull_mlp"] * 1e-3),
         "gaussians_per_s": st_c["pairs"] / t_c,
         "psnr_culled_vs_unculled_db": psnr(img_c, img_u),
+        "graph_frame_equals_eager_frame": graph_equals_eager,
         "in_frustum": st_c["in_frustum"], "queried": st_c["queried"], "kept": st_c["kept"],
         "duplicates": st_c["duplicates"], "duplicates_unculled": st_u["duplicates"],
         "blend_tests": st_c["blend_tests"], "blend_tests_unculled": st_u["blend_tests"],
@@ -287,6 +357,96 @@ def main():
         out["cpu_baseline"] = cpu_baseline(sc, img_c)
     print(json.dumps(out), flush=True)
     ctx.close()
+
+
+def main_batched(args):
+    """8 cameras x 1080p in one persistent frame; the ring turns 1 degree per
+    frame; p50 / p99 over the timed frames."""
+    import torch
+    import paper_2511_19202_amd as nvgs
+    import synth
+
+    prec = args.precision or "bf16"
+    sc = synth.scene_batched()
+    ctx = nvgs.Context(0)
+    ctx.load_assets(sc.assets)
+    ctx.set_instances(sc.instances)
+    print(f"[batched] {len(sc.assets)} assets, {sum(a.n for a in sc.assets)} Gaussians stored, "
+          f"{len(sc.instances)} instances, {sc.pairs_per_camera} pairs per camera", file=sys.stderr, flush=True)
+    training = None
+    if args.mlp == "trained":
+        training = train_assets(ctx, sc, views=args.views, steps=args.train_steps)
+        print("[batched] trained", file=sys.stderr, flush=True)
+    else:
+        calibrate_keep(ctx, sc, args.keep, prec)
+    c0 = sc.cameras[0]
+    rings = [synth.ring_cameras(len(sc.cameras), f, res=(c0.width, c0.height)) for f in range(args.frames)]
+    # the ring repeats every 360 / 8 = 45 degrees: size from eager frames over one period
+    period = [rings[f] for f in range(0, min(45, args.frames), 5)]
+    tile, tune = prepare(ctx, period, args.tile, prec, use_mlp_modes=(True,))
+    print(f"[batched] tile {tile}, MLP shape {ctx.mlp_shape}", file=sys.stderr, flush=True)
+    kw = dict(tile=tile, precision=prec, use_mlp=True)
+    steps = max(args.steps, args.frames)
+    t_f, per = time_graph(ctx, rings, steps, args.warmup, **kw)
+    check_no_overflow(ctx)
+    _, stage, st, img = time_frames(ctx, sc, 3, 1, **kw)
+    # culled vs unculled on the first ring position (GPU images)
+    iu = ctx.render(sc.cameras, tile=tile, precision=prec, use_mlp=False).cpu().numpy()
+    ic = img.cpu().numpy()
+    psnrs = [psnr(ic[k], iu[k]) for k in range(len(sc.cameras))]
+    width = sc.assets[0].mlp.width
+    dom, roof = roofline(stage, st, width, prec, sc.assets[0].sh_degree)
+    C = len(sc.cameras)
+    out = {
+        "metric": "1080p FPS + visibility-MLP queries/s, culled vs unculled, PSNR vs FP64 oracle",
+        "value": C / t_f,
+        "unit": "1080p camera frames/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * t_f,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "batched-8cam-1080p: 16 assets (50k-1M log-uniform, SH3), 1024 Zipf instances, "
+                               "8 ring cameras turning 1 deg per frame",
+                   "gaussians_stored": sum(a.n for a in sc.assets), "instances": len(sc.instances),
+                   "pairs": st["pairs"], "cameras": C, "resolution": "1920x1080", "mlp_precision": prec,
+                   "tile": tile, "mlp_shape": list(ctx.mlp_shape), "autotune": tune, "mlp": args.mlp,
+                   "frame": "persistent (HIP graph)"},
+        "frame_ms_p50": float(np.percentile(per, 50)), "frame_ms_p99": float(np.percentile(per, 99)),
+        "frame_ms_mean": float(np.mean(per)),
+        "mlp_queries_per_s": st["queried"] / (stage["cull_mlp"] * 1e-3),
+        "gaussians_per_s": st["pairs"] / t_f,
+        "psnr_culled_vs_unculled_db_per_camera": psnrs,
+        "in_frustum": st["in_frustum"], "queried": st["queried"], "kept": st["kept"],
+        "duplicates": st["duplicates"], "blend_tests": st["blend_tests"], "ms_stage": stage,
+        "dominant_kernel": dom, "roofline": roof, "workspace_bytes": st["workspace_bytes"],
+        "training": training,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_batched(sc)
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+def cpu_baseline_batched(sc, every=16):
+    """The FP64 oracle on a deterministic subsample (camera 0, every 16th
+    instance), its time scaled by the pair-count ratio to the whole frame."""
+    import oracle
+    import synth
+    sub = synth.Scene(assets=sc.assets, instances=sc.instances[::every], cameras=sc.cameras[:1], tile=sc.tile)
+    t0 = time.perf_counter()
+    oracle.frame(sub, use_mlp=True, want_margin=False)
+    dt = time.perf_counter() - t0
+    scale = len(sc.cameras) * sc.pairs_per_camera / sub.pairs_per_camera
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": len(sc.cameras) / (dt * scale), "unit": "1080p camera frames/s", "cores": threads,
+            "kind": "oracle", "extrapolated": True,
+            "sample": f"camera 0 and {len(sub.instances)} of {len(sc.instances)} instances in {dt:.1f} s, "
+                      f"scaled x{scale:.1f} by pair count to the 8-camera frame"}
 
 
 if __name__ == "__main__":

@@ -57,6 +57,7 @@ typedef int32_t nvgs_status;
 
 #define NVGS_RENDER_RECORD_CONTRIB 1u /* write per-pair max alpha*T into opts->contrib */
 #define NVGS_RENDER_KEEP_DEBUG 2u     /* keep per-splat debug arrays (nvgs_debug_buffers) */
+#define NVGS_RENDER_GRAPH 4u          /* persistent frame: see nvgs_render */
 
 typedef struct nvgs_ctx nvgs_ctx;
 
@@ -173,6 +174,25 @@ typedef struct nvgs_debug_view {
   int32_t tiles_x, tiles_y;
 } nvgs_debug_view;
 
+/* Block shape of the cull + visibility-MLP kernel.  A work-group covers 256
+ * consecutive Gaussians of one asset (256 / gaussians_per_wave waves) and
+ * loops over up to segments_per_group (camera, instance) pairs of that asset,
+ * reusing the Gaussian half of layer 1 (Sec. 3.3 factorisation of the camera
+ * and Gaussian inputs). */
+typedef struct nvgs_mlp_shape {
+  int32_t gaussians_per_wave; /* 32, 64 or 128 (128 not with FP8 operands: falls back to 64) */
+  int32_t segments_per_group; /* 1 .. 1024 */
+} nvgs_mlp_shape;
+
+/* One autotuner measurement: median milliseconds of the culling + MLP stage
+ * (shape sweep) or of the whole frame (tile sweep). */
+typedef struct nvgs_tune_entry {
+  int32_t tile;
+  int32_t gaussians_per_wave;
+  int32_t segments_per_group;
+  float ms;
+} nvgs_tune_entry;
+
 typedef struct nvgs_train_opts {
   int64_t batch;      /* (Gaussian, view) pairs per step, >= 1 */
   int32_t steps;      /* >= 1 */
@@ -207,10 +227,50 @@ nvgs_status nvgs_set_instances(nvgs_ctx* ctx, const nvgs_instance* inst, int32_t
 nvgs_status nvgs_query_visibility(nvgs_ctx* ctx, const nvgs_camera* cams, int32_t C, int32_t precision,
                                   uint8_t* state, float* logits);
 
-/* The whole frame for C cameras of equal size.  rgb: device [C][H][W][3].
- * stats (host, nullable): filled after a stream synchronisation. */
+/* The whole frame (steps 1-6, Sec. 3.3 and 4.1) for C cameras of equal size,
+ * all cameras in one launch sequence: the tile key is camera * n_tiles + tile.
+ * rgb: device [C][H][W][3].  stats (host, nullable): filled after a stream
+ * synchronisation; E_CAPACITY if a capacity was exceeded (then the image is
+ * undefined and stats hold the sizes needed).
+ * Without NVGS_RENDER_GRAPH the call reads the splat and entry counts back
+ * to size its buffers (two synchronisations) and times every stage.
+ * With NVGS_RENDER_GRAPH (persistent frame) the call never synchronises
+ * unless stats is given: every launch is bounded by the capacities from
+ * nvgs_reserve or earlier frames (E_STATE if there are none), kernels clamp
+ * to them and raise an overflow flag, and the launch sequence is captured
+ * once into a HIP graph that later calls replay after uploading the cameras.
+ * It is captured again when anything it was captured for changes (camera
+ * count, image size, options, output pointers, buffers, MLP shape, assets,
+ * instances).  ms_stage is zero for graph frames. */
 nvgs_status nvgs_render(nvgs_ctx* ctx, const nvgs_camera* cams, int32_t C, const nvgs_render_opts* opts,
                         float* rgb, nvgs_frame_stats* stats);
+
+/* Capacities for persistent frames: at least max_splats splats and
+ * max_duplicates (splat, tile) entries per frame (both < 2^32).  Grow-only;
+ * allocates (synchronises if a buffer moves). */
+nvgs_status nvgs_reserve(nvgs_ctx* ctx, int64_t max_splats, int64_t max_duplicates);
+
+/* Largest splat and entry counts of any frame since creation or the last
+ * reset, and whether any frame overflowed its capacities.  Synchronises.
+ * reset != 0 clears them afterwards.  A frame whose splats overflowed counts
+ * the entries of the splats that fit only: grow and render again. */
+nvgs_status nvgs_frame_watermarks(nvgs_ctx* ctx, int64_t* max_splats, int64_t* max_duplicates, int32_t* overflowed,
+                                  int32_t reset);
+
+/* Set / read the cull + MLP block shape used by later frames and queries
+ * (default 64 Gaussians per wave, 16 segments per work-group). */
+nvgs_status nvgs_set_mlp_shape(nvgs_ctx* ctx, const nvgs_mlp_shape* shape);
+nvgs_status nvgs_get_mlp_shape(nvgs_ctx* ctx, nvgs_mlp_shape* shape);
+
+/* Autotuner.  Renders the given cameras without NVGS_RENDER_GRAPH: first every
+ * supported MLP block shape (gaussians_per_wave 32/64/128 x segments_per_group
+ * 4/8/16/32/64) at opts->tile, scored by the median culling + MLP stage time
+ * over `reps` frames; then tiles 8, 16 and 32 with the best shape, scored by
+ * the median frame time.  Keeps the best shape in the context and writes the
+ * best tile into opts->tile.  table (host, nullable, table_cap entries)
+ * receives the measurements, n_entries their count.  Synchronises. */
+nvgs_status nvgs_autotune(nvgs_ctx* ctx, const nvgs_camera* cams, int32_t C, nvgs_render_opts* opts, float* rgb,
+                          int32_t reps, nvgs_tune_entry* table, int32_t table_cap, int32_t* n_entries);
 
 /* Views of the last frame's intermediate buffers (for tests and tools). */
 nvgs_status nvgs_debug_buffers(nvgs_ctx* ctx, nvgs_debug_view* out);

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libnvgs.so")
 
 OK, E_INVALID, E_STATE, E_NOMEM, E_CAPACITY, E_DEVICE = range(6)
 PREC_FP32, PREC_BF16, PREC_FP8 = 0, 1, 2
-RENDER_RECORD_CONTRIB, RENDER_KEEP_DEBUG = 1, 2
+RENDER_RECORD_CONTRIB, RENDER_KEEP_DEBUG, RENDER_GRAPH = 1, 2, 4
 _PREC = {"fp32": PREC_FP32, "bf16": PREC_BF16, "fp8": PREC_FP8}
 
 
@@ -82,6 +82,15 @@ class DebugView(C.Structure):
                 ("sorted_id", C.c_void_p), ("ranges", C.c_void_p), ("tiles_x", C.c_int32), ("tiles_y", C.c_int32)]
 
 
+class MlpShape(C.Structure):
+    _fields_ = [("gaussians_per_wave", C.c_int32), ("segments_per_group", C.c_int32)]
+
+
+class TuneEntry(C.Structure):
+    _fields_ = [("tile", C.c_int32), ("gaussians_per_wave", C.c_int32), ("segments_per_group", C.c_int32),
+                ("ms", C.c_float)]
+
+
 class TrainOpts(C.Structure):
     _fields_ = [("batch", C.c_int64), ("steps", C.c_int32), ("precision", C.c_int32), ("lr", C.c_float),
                 ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float), ("seed", C.c_uint64),
@@ -100,6 +109,13 @@ _SIGS = {
     "nvgs_render": ([C.c_void_p, C.POINTER(Camera), C.c_int32, C.POINTER(RenderOpts), C.c_void_p,
                      C.POINTER(FrameStats)], C.c_int32),
     "nvgs_debug_buffers": ([C.c_void_p, C.POINTER(DebugView)], C.c_int32),
+    "nvgs_reserve": ([C.c_void_p, C.c_int64, C.c_int64], C.c_int32),
+    "nvgs_frame_watermarks": ([C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int32),
+                               C.c_int32], C.c_int32),
+    "nvgs_set_mlp_shape": ([C.c_void_p, C.POINTER(MlpShape)], C.c_int32),
+    "nvgs_get_mlp_shape": ([C.c_void_p, C.POINTER(MlpShape)], C.c_int32),
+    "nvgs_autotune": ([C.c_void_p, C.POINTER(Camera), C.c_int32, C.POINTER(RenderOpts), C.c_void_p, C.c_int32,
+                       C.POINTER(TuneEntry), C.c_int32, C.POINTER(C.c_int32)], C.c_int32),
     "nvgs_make_labels": ([C.c_void_p, C.c_int32, C.POINTER(Camera), C.c_int32, C.c_float, C.c_int32, C.c_int32,
                           C.c_float, C.c_void_p], C.c_int32),
     "nvgs_train_visibility": ([C.c_void_p, C.c_int32, C.POINTER(Camera), C.c_int32, C.c_void_p,
@@ -277,12 +293,25 @@ class Context:
         return state, logits
 
     def render(self, cams: Iterable, tile: int = 16, use_mlp: bool = True, precision="fp32", bg=(0.0, 0.0, 0.0),
-               contrib=None, keep_debug: bool = False, stats: bool = False, out=None):
+               contrib=None, keep_debug: bool = False, stats: bool = False, out=None, graph: bool = False):
+        """One frame for all cameras.  graph=True: persistent frame (captured
+        HIP graph, no synchronisation unless stats); without `out` the image
+        goes to a context-owned tensor that the next graph frame overwrites."""
         torch = _torch()
         arr, n = self._cams(cams)
         W, H = arr[0].width, arr[0].height
-        rgb = out if out is not None else torch.empty((n, H, W, 3), dtype=torch.float32, device=self.device)
-        flags = (RENDER_RECORD_CONTRIB if contrib is not None else 0) | (RENDER_KEEP_DEBUG if keep_debug else 0)
+        if out is not None:
+            rgb = out
+        elif graph:
+            key = (n, H, W)
+            if getattr(self, "_graph_out_key", None) != key:
+                self._graph_out = torch.empty((n, H, W, 3), dtype=torch.float32, device=self.device)
+                self._graph_out_key = key
+            rgb = self._graph_out
+        else:
+            rgb = torch.empty((n, H, W, 3), dtype=torch.float32, device=self.device)
+        flags = (RENDER_RECORD_CONTRIB if contrib is not None else 0) | (RENDER_KEEP_DEBUG if keep_debug else 0) | \
+            (RENDER_GRAPH if graph else 0)
         opts = RenderOpts(int(tile), int(bool(use_mlp)), _PREC.get(precision, precision), (C.c_float * 3)(*bg), flags,
                           contrib.data_ptr() if contrib is not None else None)
         fs = FrameStats() if stats else None
@@ -294,6 +323,42 @@ class Context:
                          "workspace_bytes": fs.workspace_bytes, "ms": fs.ms_total,
                          "ms_stage": dict(zip(STAGES, list(fs.ms_stage)))}
         return rgb
+
+    def reserve(self, max_splats: int, max_duplicates: int):
+        self._check(self.L.nvgs_reserve(self.h, int(max_splats), int(max_duplicates)))
+
+    def watermarks(self, reset: bool = False) -> dict:
+        a, b, o = C.c_int64(), C.c_int64(), C.c_int32()
+        self._check(self.L.nvgs_frame_watermarks(self.h, C.byref(a), C.byref(b), C.byref(o), int(bool(reset))))
+        return {"max_splats": a.value, "max_duplicates": b.value, "overflowed": bool(o.value)}
+
+    @property
+    def mlp_shape(self):
+        s = MlpShape()
+        self._check(self.L.nvgs_get_mlp_shape(self.h, C.byref(s)))
+        return (s.gaussians_per_wave, s.segments_per_group)
+
+    @mlp_shape.setter
+    def mlp_shape(self, shape):
+        s = MlpShape(int(shape[0]), int(shape[1]))
+        self._check(self.L.nvgs_set_mlp_shape(self.h, C.byref(s)))
+
+    def autotune(self, cams: Iterable, tile: int = 16, use_mlp: bool = True, precision="fp32", bg=(0.0, 0.0, 0.0),
+                 reps: int = 3):
+        """Library autotuner: returns (best tile, best MLP shape, table)."""
+        torch = _torch()
+        arr, n = self._cams(cams)
+        rgb = torch.empty((n, arr[0].height, arr[0].width, 3), dtype=torch.float32, device=self.device)
+        opts = RenderOpts(int(tile), int(bool(use_mlp)), _PREC.get(precision, precision), (C.c_float * 3)(*bg), 0,
+                          None)
+        cap = 64
+        table = (TuneEntry * cap)()
+        cnt = C.c_int32()
+        self._check(self.L.nvgs_autotune(self.h, arr, n, C.byref(opts), rgb.data_ptr(), int(reps), table, cap,
+                                         C.byref(cnt)))
+        rows = [{"tile": e.tile, "gaussians_per_wave": e.gaussians_per_wave,
+                 "segments_per_group": e.segments_per_group, "ms": e.ms} for e in table[:min(cnt.value, cap)]]
+        return opts.tile, self.mlp_shape, rows
 
     def debug_buffers(self) -> dict:
         """Copies of the last frame's intermediate buffers as torch tensors."""

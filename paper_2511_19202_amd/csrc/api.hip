@@ -40,8 +40,10 @@ struct nvgs_ctx {
   int64_t P = 0;
   Buf inst_dev, inst_off_dev;
 
-  // plan (depends on the camera count)
-  int planC = -1;
+  // plan (depends on the camera count and the MLP block shape)
+  int planC = -1, plan_segs = -1;
+  int mlp_nb = 2, mlp_segs = 16;  // Gaussians per wave / 32, (camera, instance) segments per work-group
+  uint64_t gen = 1;               // changes whenever a device buffer moves or the plan is rebuilt
   int64_t n_words = 0, n_chunks = 0;
   std::vector<int64_t> seg_word_base, seg_chunk_base;
   std::vector<WorkItem> items;
@@ -49,17 +51,29 @@ struct nvgs_ctx {
   Buf seg_word_dev, seg_chunk_dev, items_dev, seglist_dev, segs_dev, c1_dev;
   Buf mask, chunk_cnt, chunk_off, scan_part;
 
-  // cameras
-  nvgs_camera* cam_host = nullptr;  // pinned staging
-  int cam_host_cap = 0;
+  // cameras: pinned staging ring, one completion event per slot
+  static constexpr int kRing = 4;
+  nvgs_camera* ring[kRing] = {};
+  hipEvent_t ring_ev[kRing] = {};
+  bool ring_used[kRing] = {};
+  int ring_cap = 0, ring_next = 0;
   Buf cam_dev;
 
   // splats and sort buffers
   int64_t cap_splats = 0, cap_dup = 0;
   Buf rec_a, rec_b, rec_c, rect, depth_key, ids, ids_tmp, keys_tmp2, pair_of, cnt, dup_off;
   Buf keys, vals, keys_tmp, vals_tmp, hist, hist_part, ranges, tord;  // tord: tile order (4 arrays)
-  Buf counters;          // u32 [0] n_splats, [1] n_dup, [2] overflow flags; u64 at [4] in-frustum, [6] queried, [8] blend tests
+  int64_t cap_keys = 0;  // tile keys (cameras x tiles) the range buffers hold
+  // u32 [0] n_splats, [1] n_dup, [2] overflow flags; u64 at [4] in-frustum, [6] queried, [8] blend tests
+  // (reset by every frame); across frames: [12] max splats, [13] max tile entries, [14] OR of overflow flags
+  Buf counters;
   uint32_t* counters_host = nullptr;
+
+  // persistent frame: captured launch sequence and what it was captured for
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<uint64_t> gkey;
+  hipEvent_t gev[2] = {};
 
   // last frame (debug view)
   int64_t last_splats = 0, last_dup = 0;
@@ -118,6 +132,7 @@ bool ensure(nvgs_ctx* ctx, Buf& b, size_t bytes) {
     (void)hipStreamSynchronize(ctx->stream);  // the old buffer may still be in use
     release(ctx, b);
   }
+  ++ctx->gen;
   size_t want = std::max<size_t>(bytes, 256);
   b.p = dev_alloc(ctx, want);
   if (!b.p) return false;
@@ -153,7 +168,8 @@ nvgs_status check_cams(nvgs_ctx* ctx, const nvgs_camera* cams, int32_t C) {
 
 // Build the per-camera-count plan: segment bases, work items, buffers.
 nvgs_status plan(nvgs_ctx* ctx, int C) {
-  if (ctx->planC == C) return NVGS_OK;
+  if (ctx->planC == C && ctx->plan_segs == ctx->mlp_segs) return NVGS_OK;
+  ++ctx->gen;
   const int NI = (int)ctx->inst.size();
   const int S = C * NI;
   ctx->seg_word_base.assign(S + 1, 0);
@@ -170,11 +186,12 @@ nvgs_status plan(nvgs_ctx* ctx, int C) {
   ctx->seg_chunk_base[S] = ch;
   ctx->n_words = w;
   ctx->n_chunks = ch;
-  if (ch >= (int64_t)1 << 31) return fail(ctx, NVGS_E_INVALID, "too many pairs for one frame");
+  if (ch >= (int64_t)1 << 31 || (int64_t)C * ctx->P >= ((int64_t)1 << 32))
+    return fail(ctx, NVGS_E_INVALID, "more than 2^32 (camera, instance, Gaussian) pairs in one frame");
   // work items: chunk x run of up to G segments of the same asset
   ctx->items.clear();
   ctx->seglist.clear();
-  const int G = 16;
+  const int G = ctx->mlp_segs;
   for (int a = 0; a < (int)ctx->assets.size(); ++a) {
     const int base = (int)ctx->seglist.size();
     for (int s = 0; s < S; ++s)
@@ -193,7 +210,7 @@ nvgs_status plan(nvgs_ctx* ctx, int C) {
       !ensure(ctx, ctx->mask, sizeof(uint32_t) * (w + 1)) || !ensure(ctx, ctx->chunk_cnt, sizeof(uint32_t) * (ch + 1)) ||
       !ensure(ctx, ctx->chunk_off, sizeof(uint32_t) * (ch + 1)) ||
       !ensure(ctx, ctx->scan_part, sizeof(uint32_t) * scan_partials_needed(ch + 1)) ||
-      !ensure(ctx, ctx->cam_dev, sizeof(nvgs_camera) * C) || !ensure(ctx, ctx->counters, sizeof(uint32_t) * 12))
+      !ensure(ctx, ctx->cam_dev, sizeof(nvgs_camera) * C))
     return fail(ctx, NVGS_E_NOMEM, "device allocation failed (plan)");
   CK(hipMemcpy(ctx->seg_word_dev.p, ctx->seg_word_base.data(), sizeof(int64_t) * (S + 1), hipMemcpyHostToDevice));
   CK(hipMemcpy(ctx->seg_chunk_dev.p, ctx->seg_chunk_base.data(), sizeof(int64_t) * (S + 1), hipMemcpyHostToDevice));
@@ -202,24 +219,38 @@ nvgs_status plan(nvgs_ctx* ctx, int C) {
   if (!ctx->seglist.empty())
     CK(hipMemcpy(ctx->seglist_dev.p, ctx->seglist.data(), sizeof(int32_t) * ctx->seglist.size(),
                  hipMemcpyHostToDevice));
-  if (ctx->cam_host_cap < C) {
-    if (ctx->cam_host) (void)hipHostFree(ctx->cam_host);
-    CK(hipHostMalloc(reinterpret_cast<void**>(&ctx->cam_host), sizeof(nvgs_camera) * C, hipHostMallocDefault));
-    ctx->cam_host_cap = C;
-  }
   ctx->planC = C;
+  ctx->plan_segs = ctx->mlp_segs;
   return NVGS_OK;
 }
 
+// Copy the cameras through the next slot of the pinned ring; a slot is only
+// rewritten once the copy that last read it has completed.
 nvgs_status upload_cams(nvgs_ctx* ctx, const nvgs_camera* cams, int C) {
-  CK(hipStreamSynchronize(ctx->stream));  // the staging buffer may still be read by a previous copy
-  std::memcpy(ctx->cam_host, cams, sizeof(nvgs_camera) * C);
-  CK(hipMemcpyAsync(ctx->cam_dev.p, ctx->cam_host, sizeof(nvgs_camera) * C, hipMemcpyHostToDevice, ctx->stream));
+  if (ctx->ring_cap < C) {
+    CK(hipStreamSynchronize(ctx->stream));
+    for (int j = 0; j < nvgs_ctx::kRing; ++j) {
+      if (ctx->ring[j]) (void)hipHostFree(ctx->ring[j]);
+      ctx->ring[j] = nullptr;
+      ctx->ring_used[j] = false;
+    }
+    ctx->ring_cap = 0;
+    for (int j = 0; j < nvgs_ctx::kRing; ++j)
+      CK(hipHostMalloc(reinterpret_cast<void**>(&ctx->ring[j]), sizeof(nvgs_camera) * C, hipHostMallocDefault));
+    ctx->ring_cap = C;
+  }
+  const int j = ctx->ring_next;
+  ctx->ring_next = (j + 1) % nvgs_ctx::kRing;
+  if (ctx->ring_used[j]) CK(hipEventSynchronize(ctx->ring_ev[j]));
+  std::memcpy(ctx->ring[j], cams, sizeof(nvgs_camera) * C);
+  CK(hipMemcpyAsync(ctx->cam_dev.p, ctx->ring[j], sizeof(nvgs_camera) * C, hipMemcpyHostToDevice, ctx->stream));
+  CK(hipEventRecord(ctx->ring_ev[j], ctx->stream));
+  ctx->ring_used[j] = true;
   return NVGS_OK;
 }
 
 nvgs_status read_counters(nvgs_ctx* ctx) {
-  CK(hipMemcpyAsync(ctx->counters_host, ctx->counters.p, sizeof(uint32_t) * 12, hipMemcpyDeviceToHost, ctx->stream));
+  CK(hipMemcpyAsync(ctx->counters_host, ctx->counters.p, sizeof(uint32_t) * 16, hipMemcpyDeviceToHost, ctx->stream));
   CK(hipStreamSynchronize(ctx->stream));
   return NVGS_OK;
 }
@@ -228,6 +259,11 @@ nvgs_status ready(nvgs_ctx* ctx) {
   if (ctx->assets.empty()) return fail(ctx, NVGS_E_STATE, "no assets loaded");
   if (ctx->inst.empty()) return fail(ctx, NVGS_E_STATE, "no instances set");
   return NVGS_OK;
+}
+
+// the configured Gaussians-per-wave, or 2 where that shape is not built for this precision
+int shape_nb(const nvgs_ctx* ctx, int precision) {
+  return mlp_shape_supported(ctx->width, precision, ctx->mlp_nb) ? ctx->mlp_nb : 2;
 }
 
 int bits_for(int64_t v) {
@@ -252,9 +288,15 @@ nvgs_status nvgs_create(const nvgs_create_info* info, nvgs_ctx** out) {
   ctx->device = info->device;
   ctx->stream = reinterpret_cast<hipStream_t>(info->stream);
   ctx->alloc = info->allocator;
-  bool ok = hipHostMalloc(reinterpret_cast<void**>(&ctx->counters_host), 12 * sizeof(uint32_t),
+  bool ok = hipHostMalloc(reinterpret_cast<void**>(&ctx->counters_host), 16 * sizeof(uint32_t),
                           hipHostMallocDefault) == hipSuccess;
   for (int e = 0; e < 2 * NVGS_NUM_STAGES && ok; ++e) ok = hipEventCreate(&ctx->ev[e]) == hipSuccess;
+  for (int e = 0; e < 2 && ok; ++e) ok = hipEventCreate(&ctx->gev[e]) == hipSuccess;
+  for (int e = 0; e < nvgs_ctx::kRing && ok; ++e)
+    ok = hipEventCreateWithFlags(&ctx->ring_ev[e], hipEventDisableTiming) == hipSuccess;
+  ok = ok && hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) == hipSuccess;
+  ok = ok && ensure(ctx, ctx->counters, 16 * sizeof(uint32_t)) &&
+       launch_fill_u32(P_<uint32_t>(ctx->counters), 0u, 16, ctx->stream) == hipSuccess;
   if (!ok) {
     nvgs_destroy(ctx);
     return NVGS_E_DEVICE;
@@ -275,9 +317,16 @@ void nvgs_destroy(nvgs_ctx* ctx) {
                 &ctx->counters};
   for (Buf* b : all) release(ctx, *b);
   for (Buf& b : ctx->op_bufs) release(ctx, b);
-  if (ctx->cam_host) (void)hipHostFree(ctx->cam_host);
+  if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+  for (nvgs_camera* r : ctx->ring)
+    if (r) (void)hipHostFree(r);
   if (ctx->counters_host) (void)hipHostFree(ctx->counters_host);
   for (hipEvent_t e : ctx->ev)
+    if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : ctx->gev)
+    if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : ctx->ring_ev)
     if (e) (void)hipEventDestroy(e);
   delete ctx;
 }
@@ -333,6 +382,7 @@ nvgs_status nvgs_load_assets(nvgs_ctx* ctx, const nvgs_asset* a, int32_t n) {
   ctx->width = width;
   ctx->inst.clear();
   ctx->planC = -1;
+  ++ctx->gen;
   return NVGS_OK;
 }
 
@@ -363,6 +413,7 @@ nvgs_status nvgs_set_instances(nvgs_ctx* ctx, const nvgs_instance* h, int32_t n)
   CK(hipMemcpy(ctx->inst_dev.p, h, sizeof(nvgs_instance) * n, hipMemcpyHostToDevice));
   CK(hipMemcpy(ctx->inst_off_dev.p, off.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice));
   ctx->planC = -1;
+  ++ctx->gen;
   return NVGS_OK;
 }
 
@@ -389,16 +440,198 @@ nvgs_status nvgs_query_visibility(nvgs_ctx* ctx, const nvgs_camera* cams, int32_
     if (!ensure(ctx, scratch, sizeof(float) * (size_t)C * ctx->P)) return fail(ctx, NVGS_E_NOMEM, "logit scratch");
     lg = P_<float>(scratch);
   }
-  CK(launch_cull_mlp(P_<AssetDev>(ctx->assets_dev), ctx->adev.data(), (int)ctx->adev.size(),
-                     P_<WorkItem>(ctx->items_dev), (int64_t)ctx->items.size(), P_<int32_t>(ctx->seglist_dev),
-                     P_<SegRec>(ctx->segs_dev), P_<float>(ctx->c1_dev), 128, ctx->width, precision, 1,
-                     P_<uint32_t>(ctx->mask), P_<uint32_t>(ctx->chunk_cnt), state, lg, nullptr, ctx->stream));
+  CK(launch_cull_mlp(P_<AssetDev>(ctx->assets_dev), P_<WorkItem>(ctx->items_dev), (int64_t)ctx->items.size(),
+                     P_<int32_t>(ctx->seglist_dev), P_<SegRec>(ctx->segs_dev), P_<float>(ctx->c1_dev), 128, ctx->width,
+                     precision, shape_nb(ctx, precision), 1, P_<uint32_t>(ctx->mask), P_<uint32_t>(ctx->chunk_cnt),
+                     state, lg, nullptr, ctx->stream));
   if (scratch.p) {
     CK(hipStreamSynchronize(ctx->stream));
     release(ctx, scratch);
   }
   return NVGS_OK;
 }
+
+}  // extern "C"
+
+namespace {
+
+// Radix histograms and scan partials for the largest sorted or scanned list.
+nvgs_status size_hist(nvgs_ctx* ctx) {
+  const int64_t m = std::max({ctx->cap_dup, ctx->cap_splats, ctx->cap_keys, (int64_t)4096});
+  if (!ensure(ctx, ctx->hist, 4 * radix_hist_words(m)) ||
+      !ensure(ctx, ctx->hist_part, 4 * scan_partials_needed(radix_hist_words(m)) + 4 * scan_partials_needed(m)))
+    return fail(ctx, NVGS_E_NOMEM, "sort histograms");
+  return NVGS_OK;
+}
+
+// Grow-only splat buffers for `need` splats (1/8 headroom when `slack`).
+nvgs_status size_splats(nvgs_ctx* ctx, int64_t need, bool slack) {
+  if (need <= ctx->cap_splats && ctx->rec_a.p) return NVGS_OK;
+  const int64_t cap = std::max<int64_t>(slack ? need + need / 8 : need, 4096);
+  const bool ok = ensure(ctx, ctx->rec_a, 16 * cap) && ensure(ctx, ctx->rec_b, 16 * cap) &&
+                  ensure(ctx, ctx->rec_c, 16 * cap) && ensure(ctx, ctx->rect, 16 * cap) &&
+                  ensure(ctx, ctx->depth_key, 4 * cap) && ensure(ctx, ctx->ids, 4 * cap) &&
+                  ensure(ctx, ctx->ids_tmp, 4 * cap) && ensure(ctx, ctx->keys_tmp2, 4 * cap) &&
+                  ensure(ctx, ctx->pair_of, 4 * cap) && ensure(ctx, ctx->cnt, 4 * cap) &&
+                  ensure(ctx, ctx->dup_off, 4 * cap);
+  if (!ok) return fail(ctx, NVGS_E_NOMEM, "splat buffers");
+  ctx->cap_splats = cap;
+  return size_hist(ctx);
+}
+
+// Grow-only (tile, splat) entry buffers for `need` entries.
+nvgs_status size_dups(nvgs_ctx* ctx, int64_t need, bool slack) {
+  if (need <= ctx->cap_dup && ctx->keys.p) return NVGS_OK;
+  const int64_t cap = std::max<int64_t>(slack ? need + need / 8 : need, 4096);
+  const bool ok = ensure(ctx, ctx->keys, 4 * cap) && ensure(ctx, ctx->vals, 4 * cap) &&
+                  ensure(ctx, ctx->keys_tmp, 4 * cap) && ensure(ctx, ctx->vals_tmp, 4 * cap);
+  if (!ok) return fail(ctx, NVGS_E_NOMEM, "tile entry buffers");
+  ctx->cap_dup = cap;
+  return size_hist(ctx);
+}
+
+// Tile ranges and launch-order buffers for `nkeys` (camera, tile) keys.
+nvgs_status size_tiles(nvgs_ctx* ctx, int64_t nkeys) {
+  if (nkeys <= ctx->cap_keys) return NVGS_OK;
+  if (!ensure(ctx, ctx->ranges, sizeof(uint32_t) * 2 * (size_t)nkeys) ||
+      !ensure(ctx, ctx->tord, sizeof(uint32_t) * 4 * (size_t)nkeys))
+    return fail(ctx, NVGS_E_NOMEM, "tile ranges");
+  ctx->cap_keys = nkeys;
+  return size_hist(ctx);
+}
+
+struct Frame {
+  int C, W, H, T, tiles_x, tiles_y, n_tiles;
+  int64_t nkeys;
+  bool record, debug, count_tests;
+  const nvgs_render_opts* opts;
+  float* rgb;
+};
+
+// Enqueue one frame on `st`.  eager: the splat and entry counts are read back
+// to size the buffers (two host synchronisations) and stage events are
+// recorded.  Otherwise the reserved capacities bound every launch, nothing
+// is read back and no buffer is allocated, so the sequence can be captured;
+// kernels clamp to the capacities and raise overflow flags.
+nvgs_status enqueue_frame(nvgs_ctx* ctx, hipStream_t st, const Frame& f, bool eager, float* ms_bin_count) {
+  hipEvent_t* ev = ctx->ev;
+#define STAGE_BEGIN(k) \
+  if (eager) CK(hipEventRecord(ev[2 * (k)], st))
+#define STAGE_END(k) \
+  if (eager) CK(hipEventRecord(ev[2 * (k) + 1], st))
+  nvgs_status s = NVGS_OK;
+  const nvgs_render_opts* opts = f.opts;
+  const int C = f.C, NI = (int)ctx->inst.size();
+  uint32_t* counters = P_<uint32_t>(ctx->counters);
+  unsigned long long* counts64 = reinterpret_cast<unsigned long long*>(counters + 4);
+  STAGE_BEGIN(NVGS_STAGE_SETUP);
+  CK(launch_fill_u32(counters, 0u, 12, st));
+  CK(launch_segment_setup(P_<nvgs_camera>(ctx->cam_dev), P_<nvgs_instance>(ctx->inst_dev),
+                          P_<AssetDev>(ctx->assets_dev), P_<int64_t>(ctx->inst_off_dev), NI, C, ctx->P,
+                          opts->use_mlp ? 1 : 0, P_<int64_t>(ctx->seg_word_dev), P_<int64_t>(ctx->seg_chunk_dev),
+                          P_<SegRec>(ctx->segs_dev), P_<float>(ctx->c1_dev), 128, st));
+  STAGE_END(NVGS_STAGE_SETUP);
+  STAGE_BEGIN(NVGS_STAGE_CULL_MLP);
+  CK(launch_cull_mlp(P_<AssetDev>(ctx->assets_dev), P_<WorkItem>(ctx->items_dev), (int64_t)ctx->items.size(),
+                     P_<int32_t>(ctx->seglist_dev), P_<SegRec>(ctx->segs_dev), P_<float>(ctx->c1_dev), 128, ctx->width,
+                     opts->precision, shape_nb(ctx, opts->precision), 0, P_<uint32_t>(ctx->mask),
+                     P_<uint32_t>(ctx->chunk_cnt), nullptr, nullptr, counts64, st));
+  STAGE_END(NVGS_STAGE_CULL_MLP);
+  STAGE_BEGIN(NVGS_STAGE_COMPACT);
+  CK(launch_scan_u32(P_<uint32_t>(ctx->chunk_cnt), P_<uint32_t>(ctx->chunk_off), ctx->n_chunks, counters + 0,
+                     P_<uint32_t>(ctx->scan_part), st));
+  STAGE_END(NVGS_STAGE_COMPACT);
+  int64_t ns_bound = ctx->cap_splats;  // grid bound of the splat-indexed launches
+  if (eager) {
+    if ((s = read_counters(ctx))) return s;
+    ns_bound = ctx->counters_host[0];
+    if ((s = size_splats(ctx, ns_bound, true))) return s;
+  }
+  const uint32_t* n_splats_dev = counters + 0;
+  STAGE_BEGIN(NVGS_STAGE_PROJECT);
+  CK(launch_project(P_<AssetDev>(ctx->assets_dev), P_<SegRec>(ctx->segs_dev), C * NI, P_<int64_t>(ctx->seg_chunk_dev),
+                    ctx->n_chunks, P_<uint32_t>(ctx->mask), P_<uint32_t>(ctx->chunk_off), n_splats_dev,
+                    ctx->cap_splats, f.T, f.tiles_x, f.tiles_y, f.debug ? 1 : 0, P_<float4>(ctx->rec_a),
+                    P_<float4>(ctx->rec_b), P_<float4>(ctx->rec_c), P_<uint4>(ctx->rect), P_<uint32_t>(ctx->depth_key),
+                    P_<uint32_t>(ctx->pair_of), counters + 2, st));
+  STAGE_END(NVGS_STAGE_PROJECT);
+  // depth order of the splats (stable: equal depths keep id order)
+  STAGE_BEGIN(NVGS_STAGE_DEPTH_SORT);
+  bool in_tmp = false;
+  CK(launch_radix_sort(P_<uint32_t>(ctx->depth_key), P_<uint32_t>(ctx->ids), P_<uint32_t>(ctx->keys_tmp2),
+                       P_<uint32_t>(ctx->ids_tmp), n_splats_dev, ns_bound, 0, 32, 1, P_<uint32_t>(ctx->hist),
+                       P_<uint32_t>(ctx->hist_part), &in_tmp, st));
+  const uint32_t* depth_ids = in_tmp ? P_<uint32_t>(ctx->ids_tmp) : P_<uint32_t>(ctx->ids);
+  STAGE_END(NVGS_STAGE_DEPTH_SORT);
+  STAGE_BEGIN(NVGS_STAGE_BIN);
+  CK(launch_gather_tiles(depth_ids, P_<uint4>(ctx->rect), n_splats_dev, ns_bound, P_<uint32_t>(ctx->cnt), st));
+  CK(launch_scan_u32_dev(P_<uint32_t>(ctx->cnt), P_<uint32_t>(ctx->dup_off), ns_bound, n_splats_dev, counters + 1,
+                         P_<uint32_t>(ctx->hist_part), st));
+  STAGE_END(NVGS_STAGE_BIN);
+  int64_t nd_bound = ctx->cap_dup;
+  if (eager) {
+    if ((s = read_counters(ctx))) return s;
+    nd_bound = ctx->counters_host[1];
+    if (ms_bin_count) CK(hipEventElapsedTime(ms_bin_count, ev[2 * NVGS_STAGE_BIN], ev[2 * NVGS_STAGE_BIN + 1]));
+    if ((s = size_dups(ctx, nd_bound, true))) return s;
+    if ((s = size_tiles(ctx, f.nkeys))) return s;
+  }
+  const uint32_t* n_dup_dev = counters + 1;
+  STAGE_BEGIN(NVGS_STAGE_BIN);
+  CK(launch_emit(depth_ids, P_<uint4>(ctx->rect), P_<uint32_t>(ctx->dup_off), n_splats_dev, ns_bound, n_dup_dev,
+                 ctx->cap_dup, f.tiles_x, f.n_tiles, P_<uint32_t>(ctx->keys), P_<uint32_t>(ctx->vals), counters + 2, st));
+  STAGE_END(NVGS_STAGE_BIN);
+  STAGE_BEGIN(NVGS_STAGE_TILE_SORT);
+  bool in_tmp2 = false;
+  CK(launch_radix_sort(P_<uint32_t>(ctx->keys), P_<uint32_t>(ctx->vals), P_<uint32_t>(ctx->keys_tmp),
+                       P_<uint32_t>(ctx->vals_tmp), n_dup_dev, nd_bound, 0, bits_for(f.nkeys), 0,
+                       P_<uint32_t>(ctx->hist), P_<uint32_t>(ctx->hist_part), &in_tmp2, st));
+  const uint32_t* skeys = in_tmp2 ? P_<uint32_t>(ctx->keys_tmp) : P_<uint32_t>(ctx->keys);
+  const uint32_t* sids = in_tmp2 ? P_<uint32_t>(ctx->vals_tmp) : P_<uint32_t>(ctx->vals);
+  CK(launch_fill_u32(P_<uint32_t>(ctx->ranges), 0u, 2 * f.nkeys, st));
+  CK(launch_ranges(skeys, n_dup_dev, nd_bound, f.nkeys, P_<uint32_t>(ctx->ranges), st));
+  // launch order of the tiles: longest lists first
+  uint32_t* tk = P_<uint32_t>(ctx->tord);
+  const int64_t nk = f.nkeys;
+  CK(launch_tile_keys(P_<uint32_t>(ctx->ranges), nk, tk, tk + nk, st));
+  bool in_tmp3 = false;
+  CK(launch_radix_sort(tk, tk + nk, tk + 2 * nk, tk + 3 * nk, nullptr, nk, 0, 5, 0, P_<uint32_t>(ctx->hist),
+                       P_<uint32_t>(ctx->hist_part), &in_tmp3, st));
+  const uint32_t* tile_order = in_tmp3 ? tk + 3 * nk : tk + nk;
+  STAGE_END(NVGS_STAGE_TILE_SORT);
+  STAGE_BEGIN(NVGS_STAGE_BLEND);
+  CK(launch_blend(P_<uint32_t>(ctx->ranges), tile_order, sids, P_<float4>(ctx->rec_a), P_<float4>(ctx->rec_b),
+                  P_<float4>(ctx->rec_c), P_<uint32_t>(ctx->pair_of), C, f.W, f.H, f.T, f.tiles_x, f.tiles_y,
+                  opts->bg[0], opts->bg[1], opts->bg[2], f.rgb, f.record ? opts->contrib : nullptr,
+                  f.count_tests ? reinterpret_cast<unsigned long long*>(counters + 8) : nullptr, st));
+  STAGE_END(NVGS_STAGE_BLEND);
+  CK(launch_watermark(counters, st));
+#undef STAGE_BEGIN
+#undef STAGE_END
+  ctx->last_splats = eager ? ns_bound : -1;
+  ctx->last_dup = eager ? nd_bound : -1;
+  ctx->last_sorted_key = skeys;
+  ctx->last_sorted_id = sids;
+  ctx->last_tiles_x = f.tiles_x;
+  ctx->last_tiles_y = f.tiles_y;
+  ctx->last_debug = f.debug;
+  return NVGS_OK;
+}
+
+void fill_stats(nvgs_ctx* ctx, const Frame& f, nvgs_frame_stats* stats) {
+  const unsigned long long* c64 = reinterpret_cast<const unsigned long long*>(ctx->counters_host + 4);
+  stats->pairs = (int64_t)f.C * ctx->P;
+  stats->in_frustum = (int64_t)c64[0];
+  stats->queried = (int64_t)c64[1];
+  stats->blend_tests = (int64_t)c64[2];
+  stats->kept = ctx->counters_host[0];
+  stats->duplicates = ctx->counters_host[1];
+  stats->workspace_bytes = (int64_t)ctx->workspace;
+}
+
+}  // namespace
+
+extern "C" {
 
 nvgs_status nvgs_render(nvgs_ctx* ctx, const nvgs_camera* cams, int32_t C, const nvgs_render_opts* opts, float* rgb,
                         nvgs_frame_stats* stats) {
@@ -413,156 +646,211 @@ nvgs_status nvgs_render(nvgs_ctx* ctx, const nvgs_camera* cams, int32_t C, const
     return fail(ctx, NVGS_E_INVALID, "bad precision");
   const bool record = (opts->flags & NVGS_RENDER_RECORD_CONTRIB) != 0;
   if (record && !opts->contrib) return fail(ctx, NVGS_E_INVALID, "RECORD_CONTRIB needs opts->contrib");
-  const bool debug = record || (opts->flags & NVGS_RENDER_KEEP_DEBUG);
+  const bool graph = (opts->flags & NVGS_RENDER_GRAPH) != 0;
   for (int q = 0; q < 3; ++q)
     if (!finite_f(opts->bg[q])) return fail(ctx, NVGS_E_INVALID, "non-finite background");
   CK(hipSetDevice(ctx->device));
   if ((s = plan(ctx, C))) return s;
-  const int W = cams[0].width, H = cams[0].height;
-  const int tiles_x = (W + T - 1) / T, tiles_y = (H + T - 1) / T, n_tiles = tiles_x * tiles_y;
-  if ((int64_t)C * n_tiles >= ((int64_t)1 << 31)) return fail(ctx, NVGS_E_INVALID, "too many tiles");
-  if ((s = upload_cams(ctx, cams, C))) return s;
+  Frame f{};
+  f.C = C;
+  f.W = cams[0].width;
+  f.H = cams[0].height;
+  f.T = T;
+  f.tiles_x = (f.W + T - 1) / T;
+  f.tiles_y = (f.H + T - 1) / T;
+  f.n_tiles = f.tiles_x * f.tiles_y;
+  f.nkeys = (int64_t)C * f.n_tiles;
+  if (f.nkeys >= ((int64_t)1 << 31)) return fail(ctx, NVGS_E_INVALID, "too many tiles");
+  f.record = record;
+  f.debug = record || (opts->flags & NVGS_RENDER_KEEP_DEBUG);
+  f.count_tests = stats != nullptr;
+  f.opts = opts;
+  f.rgb = rgb;
   hipStream_t st = ctx->stream;
-  hipEvent_t* ev = ctx->ev;
-#define STAGE_BEGIN(k) CK(hipEventRecord(ev[2 * (k)], st))
-#define STAGE_END(k) CK(hipEventRecord(ev[2 * (k) + 1], st))
-  const int NI = (int)ctx->inst.size();
-  uint32_t* counters = P_<uint32_t>(ctx->counters);
-  unsigned long long* counts64 = reinterpret_cast<unsigned long long*>(counters + 4);
-  STAGE_BEGIN(NVGS_STAGE_SETUP);
-  CK(launch_fill_u32(counters, 0u, 12, st));
-  CK(launch_segment_setup(P_<nvgs_camera>(ctx->cam_dev), P_<nvgs_instance>(ctx->inst_dev),
-                          P_<AssetDev>(ctx->assets_dev), P_<int64_t>(ctx->inst_off_dev), NI, C, ctx->P,
-                          opts->use_mlp ? 1 : 0, P_<int64_t>(ctx->seg_word_dev), P_<int64_t>(ctx->seg_chunk_dev),
-                          P_<SegRec>(ctx->segs_dev), P_<float>(ctx->c1_dev), 128, st));
-  STAGE_END(NVGS_STAGE_SETUP);
-  STAGE_BEGIN(NVGS_STAGE_CULL_MLP);
-  CK(launch_cull_mlp(P_<AssetDev>(ctx->assets_dev), ctx->adev.data(), (int)ctx->adev.size(),
-                     P_<WorkItem>(ctx->items_dev), (int64_t)ctx->items.size(), P_<int32_t>(ctx->seglist_dev),
-                     P_<SegRec>(ctx->segs_dev), P_<float>(ctx->c1_dev), 128, ctx->width, opts->precision, 0,
-                     P_<uint32_t>(ctx->mask), P_<uint32_t>(ctx->chunk_cnt), nullptr, nullptr, counts64, st));
-  STAGE_END(NVGS_STAGE_CULL_MLP);
-  STAGE_BEGIN(NVGS_STAGE_COMPACT);
-  CK(launch_scan_u32(P_<uint32_t>(ctx->chunk_cnt), P_<uint32_t>(ctx->chunk_off), ctx->n_chunks, counters + 0,
-                     P_<uint32_t>(ctx->scan_part), st));
-  STAGE_END(NVGS_STAGE_COMPACT);
-  if ((s = read_counters(ctx))) return s;
-  const int64_t ns = ctx->counters_host[0];
-  // splat buffers
-  if (ns > ctx->cap_splats || !ctx->rec_a.p) {
-    const int64_t cap = std::max<int64_t>(ns + ns / 8, 4096);
-    bool ok = ensure(ctx, ctx->rec_a, 16 * cap) && ensure(ctx, ctx->rec_b, 16 * cap) &&
-              ensure(ctx, ctx->rec_c, 16 * cap) && ensure(ctx, ctx->rect, 16 * cap) &&
-              ensure(ctx, ctx->depth_key, 4 * cap) && ensure(ctx, ctx->ids, 4 * cap) &&
-              ensure(ctx, ctx->ids_tmp, 4 * cap) && ensure(ctx, ctx->keys_tmp2, 4 * cap) &&
-              ensure(ctx, ctx->pair_of, 4 * cap) && ensure(ctx, ctx->cnt, 4 * cap) &&
-              ensure(ctx, ctx->dup_off, 4 * cap) &&
-              ensure(ctx, ctx->hist, 4 * radix_hist_words(cap)) &&
-              ensure(ctx, ctx->hist_part, 4 * scan_partials_needed(radix_hist_words(cap)) + 4 * scan_partials_needed(cap));
-    if (!ok) return fail(ctx, NVGS_E_NOMEM, "splat buffers");
-    ctx->cap_splats = cap;
+  if (!graph) {
+    if ((s = upload_cams(ctx, cams, C))) return s;
+    float ms_bin_count = 0.f;
+    if ((s = enqueue_frame(ctx, st, f, true, &ms_bin_count))) return s;
+    if (stats) {
+      if ((s = read_counters(ctx))) return s;
+      float ms = 0.f;
+      CK(hipEventElapsedTime(&ms, ctx->ev[2 * NVGS_STAGE_SETUP], ctx->ev[2 * NVGS_STAGE_BLEND + 1]));
+      for (int k = 0; k < NVGS_NUM_STAGES; ++k) {
+        float m = 0.f;
+        CK(hipEventElapsedTime(&m, ctx->ev[2 * k], ctx->ev[2 * k + 1]));
+        stats->ms_stage[k] = m;
+      }
+      stats->ms_stage[NVGS_STAGE_BIN] += ms_bin_count;
+      stats->ms_total = ms;
+      fill_stats(ctx, f, stats);
+      if (ctx->counters_host[2]) return fail(ctx, NVGS_E_CAPACITY, "capacity exceeded");
+    }
+    return NVGS_OK;
   }
-  const uint32_t* n_splats_dev = counters + 0;
-  STAGE_BEGIN(NVGS_STAGE_PROJECT);
-  CK(launch_project(P_<AssetDev>(ctx->assets_dev), P_<SegRec>(ctx->segs_dev), C * NI, P_<int64_t>(ctx->seg_chunk_dev),
-                    ctx->n_chunks, P_<uint32_t>(ctx->mask), P_<uint32_t>(ctx->chunk_off), n_splats_dev,
-                    ctx->cap_splats, T, tiles_x, tiles_y, debug ? 1 : 0, P_<float4>(ctx->rec_a),
-                    P_<float4>(ctx->rec_b), P_<float4>(ctx->rec_c), P_<uint4>(ctx->rect), P_<uint32_t>(ctx->depth_key),
-                    P_<uint32_t>(ctx->pair_of), counters + 2, st));
-  STAGE_END(NVGS_STAGE_PROJECT);
-  // depth order of the splats (stable: equal depths keep id order)
-  STAGE_BEGIN(NVGS_STAGE_DEPTH_SORT);
-  bool in_tmp = false;
-  CK(launch_radix_sort(P_<uint32_t>(ctx->depth_key), P_<uint32_t>(ctx->ids), P_<uint32_t>(ctx->keys_tmp2),
-                       P_<uint32_t>(ctx->ids_tmp), n_splats_dev, ns, 0, 32, 1, P_<uint32_t>(ctx->hist),
-                       P_<uint32_t>(ctx->hist_part), &in_tmp, st));
-  const uint32_t* depth_ids = in_tmp ? P_<uint32_t>(ctx->ids_tmp) : P_<uint32_t>(ctx->ids);
-  STAGE_END(NVGS_STAGE_DEPTH_SORT);
-  STAGE_BEGIN(NVGS_STAGE_BIN);
-  CK(launch_gather_tiles(depth_ids, P_<uint4>(ctx->rect), n_splats_dev, ns, P_<uint32_t>(ctx->cnt), st));
-  CK(launch_scan_u32_dev(P_<uint32_t>(ctx->cnt), P_<uint32_t>(ctx->dup_off), ns, n_splats_dev, counters + 1,
-                         P_<uint32_t>(ctx->hist_part), st));
-  STAGE_END(NVGS_STAGE_BIN);
-  if ((s = read_counters(ctx))) return s;
-  const int64_t nd = ctx->counters_host[1];
-  float ms_bin_count = 0.f;  // first half of the binning stage (counts + scan)
-  CK(hipEventElapsedTime(&ms_bin_count, ev[2 * NVGS_STAGE_BIN], ev[2 * NVGS_STAGE_BIN + 1]));
-  if (nd > ctx->cap_dup || !ctx->keys.p) {
-    const int64_t cap = std::max<int64_t>(nd + nd / 8, 4096);
-    bool ok = ensure(ctx, ctx->keys, 4 * cap) && ensure(ctx, ctx->vals, 4 * cap) &&
-              ensure(ctx, ctx->keys_tmp, 4 * cap) && ensure(ctx, ctx->vals_tmp, 4 * cap) &&
-              ensure(ctx, ctx->hist, 4 * radix_hist_words(std::max(cap, ctx->cap_splats))) &&
-              ensure(ctx, ctx->hist_part, 4 * scan_partials_needed(radix_hist_words(std::max(cap, ctx->cap_splats))) +
-                                              4 * scan_partials_needed(std::max(cap, ctx->cap_splats)));
-    if (!ok) return fail(ctx, NVGS_E_NOMEM, "duplicate buffers");
-    ctx->cap_dup = cap;
+  // persistent frame
+  if (ctx->cap_splats <= 0 || ctx->cap_dup <= 0 || !ctx->rec_a.p || !ctx->keys.p)
+    return fail(ctx, NVGS_E_STATE, "GRAPH frames need capacities: nvgs_reserve, or one frame without NVGS_RENDER_GRAPH");
+  if ((s = size_tiles(ctx, f.nkeys)) || (s = size_hist(ctx))) return s;
+  const std::vector<uint64_t> key = {
+      (uint64_t)C, (uint64_t)f.W, (uint64_t)f.H, (uint64_t)T, (uint64_t)opts->use_mlp, (uint64_t)opts->precision,
+      (uint64_t)opts->flags, (uint64_t)reinterpret_cast<uintptr_t>(rgb),
+      (uint64_t)reinterpret_cast<uintptr_t>(record ? opts->contrib : nullptr), (uint64_t)(stats != nullptr),
+      ctx->gen, (uint64_t)shape_nb(ctx, opts->precision), (uint64_t)ctx->mlp_segs,
+      (uint64_t)ctx->cap_splats, (uint64_t)ctx->cap_dup,
+      ((uint64_t)__builtin_bit_cast(uint32_t, opts->bg[0]) << 32) | __builtin_bit_cast(uint32_t, opts->bg[1]),
+      (uint64_t)__builtin_bit_cast(uint32_t, opts->bg[2])};
+  if (!ctx->gexec || key != ctx->gkey) {
+    if (ctx->gexec) {
+      CK(hipStreamSynchronize(st));
+      (void)hipGraphExecDestroy(ctx->gexec);
+      ctx->gexec = nullptr;
+    }
+    CK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+    s = enqueue_frame(ctx, ctx->cap_stream, f, false, nullptr);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(ctx->cap_stream, &g);
+    if (s || e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return s ? s : fail(ctx, NVGS_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    }
+    const hipError_t ei = hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+      ctx->gexec = nullptr;
+      return fail(ctx, NVGS_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+    }
+    ctx->gkey = key;
   }
-  const int64_t nkeys = (int64_t)C * n_tiles;
-  if (!ensure(ctx, ctx->ranges, sizeof(uint32_t) * 2 * (size_t)nkeys) ||
-      !ensure(ctx, ctx->tord, sizeof(uint32_t) * 4 * (size_t)nkeys) ||
-      !ensure(ctx, ctx->hist, 4 * radix_hist_words(std::max({ctx->cap_dup, ctx->cap_splats, nkeys}))) ||
-      !ensure(ctx, ctx->hist_part,
-              4 * scan_partials_needed(radix_hist_words(std::max({ctx->cap_dup, ctx->cap_splats, nkeys}))) +
-                  4 * scan_partials_needed(std::max({ctx->cap_dup, ctx->cap_splats, nkeys}))))
-    return fail(ctx, NVGS_E_NOMEM, "tile ranges");
-  const uint32_t* n_dup_dev = counters + 1;
-  STAGE_BEGIN(NVGS_STAGE_BIN);
-  CK(launch_emit(depth_ids, P_<uint4>(ctx->rect), P_<uint32_t>(ctx->dup_off), n_splats_dev, ns, n_dup_dev,
-                 ctx->cap_dup, tiles_x, n_tiles, P_<uint32_t>(ctx->keys), P_<uint32_t>(ctx->vals), counters + 2, st));
-  STAGE_END(NVGS_STAGE_BIN);
-  STAGE_BEGIN(NVGS_STAGE_TILE_SORT);
-  bool in_tmp2 = false;
-  CK(launch_radix_sort(P_<uint32_t>(ctx->keys), P_<uint32_t>(ctx->vals), P_<uint32_t>(ctx->keys_tmp),
-                       P_<uint32_t>(ctx->vals_tmp), n_dup_dev, nd, 0, bits_for((int64_t)C * n_tiles), 0,
-                       P_<uint32_t>(ctx->hist), P_<uint32_t>(ctx->hist_part), &in_tmp2, st));
-  const uint32_t* skeys = in_tmp2 ? P_<uint32_t>(ctx->keys_tmp) : P_<uint32_t>(ctx->keys);
-  const uint32_t* sids = in_tmp2 ? P_<uint32_t>(ctx->vals_tmp) : P_<uint32_t>(ctx->vals);
-  CK(launch_fill_u32(P_<uint32_t>(ctx->ranges), 0u, 2 * (int64_t)C * n_tiles, st));
-  CK(launch_ranges(skeys, n_dup_dev, nd, P_<uint32_t>(ctx->ranges), st));
-  // launch order of the tiles: longest lists first
-  uint32_t* tk = P_<uint32_t>(ctx->tord);
-  CK(launch_tile_keys(P_<uint32_t>(ctx->ranges), nkeys, tk, tk + nkeys, st));
-  bool in_tmp3 = false;
-  CK(launch_radix_sort(tk, tk + nkeys, tk + 2 * nkeys, tk + 3 * nkeys, nullptr, nkeys, 0, 5, 0,
-                       P_<uint32_t>(ctx->hist), P_<uint32_t>(ctx->hist_part), &in_tmp3, st));
-  const uint32_t* tile_order = in_tmp3 ? tk + 3 * nkeys : tk + nkeys;
-  STAGE_END(NVGS_STAGE_TILE_SORT);
-  STAGE_BEGIN(NVGS_STAGE_BLEND);
-  CK(launch_blend(P_<uint32_t>(ctx->ranges), tile_order, sids, P_<float4>(ctx->rec_a), P_<float4>(ctx->rec_b),
-                  P_<float4>(ctx->rec_c), P_<uint32_t>(ctx->pair_of), C, W, H, T, tiles_x, tiles_y, opts->bg[0],
-                  opts->bg[1], opts->bg[2], rgb, record ? opts->contrib : nullptr,
-                  stats ? reinterpret_cast<unsigned long long*>(counters + 8) : nullptr, st));
-  STAGE_END(NVGS_STAGE_BLEND);
-#undef STAGE_BEGIN
-#undef STAGE_END
-  ctx->last_splats = ns;
-  ctx->last_dup = nd;
-  ctx->last_sorted_key = skeys;
-  ctx->last_sorted_id = sids;
-  ctx->last_tiles_x = tiles_x;
-  ctx->last_tiles_y = tiles_y;
-  ctx->last_debug = debug;
+  if ((s = upload_cams(ctx, cams, C))) return s;
+  if (stats) CK(hipEventRecord(ctx->gev[0], st));
+  CK(hipGraphLaunch(ctx->gexec, st));
   if (stats) {
+    CK(hipEventRecord(ctx->gev[1], st));
     if ((s = read_counters(ctx))) return s;
     float ms = 0.f;
-    CK(hipEventElapsedTime(&ms, ev[2 * NVGS_STAGE_SETUP], ev[2 * NVGS_STAGE_BLEND + 1]));
-    for (int k = 0; k < NVGS_NUM_STAGES; ++k) {
-      float m = 0.f;
-      CK(hipEventElapsedTime(&m, ev[2 * k], ev[2 * k + 1]));
-      stats->ms_stage[k] = m;
-    }
-    stats->ms_stage[NVGS_STAGE_BIN] += ms_bin_count;
-    const unsigned long long* c64 = reinterpret_cast<const unsigned long long*>(ctx->counters_host + 4);
-    stats->pairs = (int64_t)C * ctx->P;
-    stats->in_frustum = (int64_t)c64[0];
-    stats->queried = (int64_t)c64[1];
-    stats->blend_tests = (int64_t)c64[2];
-    stats->kept = ns;
-    stats->duplicates = nd;
-    stats->workspace_bytes = (int64_t)ctx->workspace;
+    CK(hipEventElapsedTime(&ms, ctx->gev[0], ctx->gev[1]));
+    for (int k = 0; k < NVGS_NUM_STAGES; ++k) stats->ms_stage[k] = 0.f;
     stats->ms_total = ms;
+    fill_stats(ctx, f, stats);
     if (ctx->counters_host[2]) return fail(ctx, NVGS_E_CAPACITY, "capacity exceeded");
   }
+  return NVGS_OK;
+}
+
+nvgs_status nvgs_reserve(nvgs_ctx* ctx, int64_t max_splats, int64_t max_duplicates) {
+  if (!ctx) return NVGS_E_INVALID;
+  if (max_splats < 0 || max_duplicates < 0 || max_splats >= ((int64_t)1 << 32) ||
+      max_duplicates >= ((int64_t)1 << 32))
+    return fail(ctx, NVGS_E_INVALID, "reserve: sizes must be in [0, 2^32)");
+  CK(hipSetDevice(ctx->device));
+  nvgs_status s = size_splats(ctx, max_splats, false);
+  if (!s) s = size_dups(ctx, max_duplicates, false);
+  return s;
+}
+
+nvgs_status nvgs_frame_watermarks(nvgs_ctx* ctx, int64_t* max_splats, int64_t* max_duplicates, int32_t* overflowed,
+                                  int32_t reset) {
+  if (!ctx) return NVGS_E_INVALID;
+  CK(hipSetDevice(ctx->device));
+  nvgs_status s = read_counters(ctx);
+  if (s) return s;
+  if (max_splats) *max_splats = ctx->counters_host[12];
+  if (max_duplicates) *max_duplicates = ctx->counters_host[13];
+  if (overflowed) *overflowed = ctx->counters_host[14] != 0;
+  if (reset) {
+    CK(launch_fill_u32(P_<uint32_t>(ctx->counters) + 12, 0u, 3, ctx->stream));
+    CK(hipStreamSynchronize(ctx->stream));
+  }
+  return NVGS_OK;
+}
+
+nvgs_status nvgs_set_mlp_shape(nvgs_ctx* ctx, const nvgs_mlp_shape* shape) {
+  if (!ctx) return NVGS_E_INVALID;
+  if (!shape) return fail(ctx, NVGS_E_INVALID, "null shape");
+  if (shape->gaussians_per_wave != 32 && shape->gaussians_per_wave != 64 && shape->gaussians_per_wave != 128)
+    return fail(ctx, NVGS_E_INVALID, "gaussians_per_wave must be 32, 64 or 128");
+  if (shape->segments_per_group < 1 || shape->segments_per_group > 1024)
+    return fail(ctx, NVGS_E_INVALID, "segments_per_group must be in [1, 1024]");
+  ctx->mlp_nb = shape->gaussians_per_wave / 32;
+  ctx->mlp_segs = shape->segments_per_group;
+  return NVGS_OK;
+}
+
+nvgs_status nvgs_get_mlp_shape(nvgs_ctx* ctx, nvgs_mlp_shape* shape) {
+  if (!ctx) return NVGS_E_INVALID;
+  if (!shape) return fail(ctx, NVGS_E_INVALID, "null shape");
+  shape->gaussians_per_wave = 32 * ctx->mlp_nb;
+  shape->segments_per_group = ctx->mlp_segs;
+  return NVGS_OK;
+}
+
+nvgs_status nvgs_autotune(nvgs_ctx* ctx, const nvgs_camera* cams, int32_t C, nvgs_render_opts* opts, float* rgb,
+                          int32_t reps, nvgs_tune_entry* table, int32_t table_cap, int32_t* n_entries) {
+  if (!ctx) return NVGS_E_INVALID;
+  if (!opts || !rgb) return fail(ctx, NVGS_E_INVALID, "autotune: null opts or rgb");
+  if (reps < 1 || reps > 1000) return fail(ctx, NVGS_E_INVALID, "autotune: reps must be in [1, 1000]");
+  if (table_cap < 0 || (table_cap > 0 && !table)) return fail(ctx, NVGS_E_INVALID, "autotune: bad table");
+  nvgs_status s = ready(ctx);
+  if (s) return s;
+  nvgs_render_opts o = *opts;
+  o.flags &= ~(int32_t)NVGS_RENDER_GRAPH;
+  if (o.tile != 8 && o.tile != 16 && o.tile != 32) o.tile = 16;
+  const int saved_nb = ctx->mlp_nb, saved_segs = ctx->mlp_segs;
+  int n = 0;
+  auto record = [&](int tile, int nb, int segs, float ms) {
+    if (n < table_cap) table[n] = nvgs_tune_entry{tile, 32 * nb, segs, ms};
+    ++n;
+  };
+  // median over `reps` timed frames after one untimed frame; returns the
+  // culling + MLP stage time and the whole-frame time
+  auto measure = [&](float* cull_ms, float* total_ms) -> nvgs_status {
+    nvgs_frame_stats st{};
+    nvgs_status r = nvgs_render(ctx, cams, C, &o, rgb, &st);
+    if (r) return r;
+    std::vector<float> a, b;
+    for (int k = 0; k < reps; ++k) {
+      if ((r = nvgs_render(ctx, cams, C, &o, rgb, &st))) return r;
+      a.push_back(st.ms_stage[NVGS_STAGE_CULL_MLP]);
+      b.push_back(st.ms_total);
+    }
+    std::nth_element(a.begin(), a.begin() + a.size() / 2, a.end());
+    std::nth_element(b.begin(), b.begin() + b.size() / 2, b.end());
+    *cull_ms = a[a.size() / 2];
+    *total_ms = b[b.size() / 2];
+    return NVGS_OK;
+  };
+  // 1. MLP block shape, by the culling + MLP stage time
+  int best_nb = saved_nb, best_segs = saved_segs;
+  float best_cull = INFINITY;
+  for (int nb : {1, 2, 4}) {
+    if (!mlp_shape_supported(ctx->width, o.precision, nb)) continue;
+    for (int segs : {4, 8, 16, 32, 64}) {
+      ctx->mlp_nb = nb;
+      ctx->mlp_segs = segs;
+      float cm = 0.f, tm = 0.f;
+      if ((s = measure(&cm, &tm))) {
+        ctx->mlp_nb = saved_nb;
+        ctx->mlp_segs = saved_segs;
+        return s;
+      }
+      record(o.tile, nb, segs, cm);
+      if (cm < best_cull) best_cull = cm, best_nb = nb, best_segs = segs;
+    }
+  }
+  ctx->mlp_nb = best_nb;
+  ctx->mlp_segs = best_segs;
+  // 2. tile size, by the whole-frame time with that shape
+  int best_tile = o.tile;
+  float best_total = INFINITY;
+  for (int tile : {8, 16, 32}) {
+    o.tile = tile;
+    float cm = 0.f, tm = 0.f;
+    if ((s = measure(&cm, &tm))) return s;
+    record(tile, best_nb, best_segs, tm);
+    if (tm < best_total) best_total = tm, best_tile = tile;
+  }
+  opts->tile = best_tile;
+  if (n_entries) *n_entries = n;
   return NVGS_OK;
 }
 
@@ -571,8 +859,15 @@ nvgs_status nvgs_debug_buffers(nvgs_ctx* ctx, nvgs_debug_view* out) {
   if (!out) return fail(ctx, NVGS_E_INVALID, "null output");
   std::memset(out, 0, sizeof(*out));
   if (!ctx->last_sorted_key) return fail(ctx, NVGS_E_STATE, "no frame rendered yet");
-  out->n_splats = ctx->last_splats;
-  out->n_dup = ctx->last_dup;
+  if (ctx->last_splats < 0) {  // graph frame: counts are on the device
+    nvgs_status s = read_counters(ctx);
+    if (s) return s;
+    out->n_splats = std::min<int64_t>(ctx->counters_host[0], ctx->cap_splats);
+    out->n_dup = std::min<int64_t>(ctx->counters_host[1], ctx->cap_dup);
+  } else {
+    out->n_splats = ctx->last_splats;
+    out->n_dup = ctx->last_dup;
+  }
   out->pair = ctx->last_debug ? P_<uint32_t>(ctx->pair_of) : nullptr;
   out->rec_a = P_<float>(ctx->rec_a);
   out->rec_b = P_<float>(ctx->rec_b);

@@ -87,11 +87,13 @@ hipError_t launch_segment_setup(const nvgs_camera* cams_dev, const nvgs_instance
                                 const int64_t* seg_word_base, const int64_t* seg_chunk_base, SegRec* segs,
                                 float* c1perm, int max_width, hipStream_t st);
 
-// mode: 0 = render (mask + chunk counts), 1 = query (state + logits as well)
-hipError_t launch_cull_mlp(const AssetDev* assets_dev, const AssetDev* assets_host, int32_t n_assets,
-                           const WorkItem* items, int64_t n_items, const int32_t* seglist, const SegRec* segs,
-                           const float* c1perm, int max_width, int width, int precision, int mode,
-                           uint32_t* mask, uint32_t* chunk_count, uint8_t* state, float* logits,
+// mode: 0 = render (mask + chunk counts), 1 = query (state + logits as well).
+// nb: Gaussians per wave in units of 32 (the work-group has kChunk / (32 nb)
+// waves); supported shapes: mlp_shape_supported().
+bool mlp_shape_supported(int width, int precision, int nb);
+hipError_t launch_cull_mlp(const AssetDev* assets_dev, const WorkItem* items, int64_t n_items, const int32_t* seglist,
+                           const SegRec* segs, const float* c1perm, int max_width, int width, int precision, int nb,
+                           int mode, uint32_t* mask, uint32_t* chunk_count, uint8_t* state, float* logits,
                            unsigned long long* counts, hipStream_t st);
 
 hipError_t launch_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, uint32_t* partials,
@@ -116,8 +118,10 @@ hipError_t launch_gather_tiles(const uint32_t* sorted_ids, const uint4* rect, co
 hipError_t launch_emit(const uint32_t* sorted_ids, const uint4* rect, const uint32_t* dup_off, const uint32_t* n_dev,
                        int64_t cap, const uint32_t* n_dup_dev, int64_t cap_dup, int tiles_x, int n_tiles,
                        uint32_t* keys, uint32_t* vals, uint32_t* overflow, hipStream_t st);
+hipError_t launch_watermark(uint32_t* counters, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
-hipError_t launch_ranges(const uint32_t* keys, const uint32_t* n_dev, int64_t cap, uint32_t* ranges, hipStream_t st);
+hipError_t launch_ranges(const uint32_t* keys, const uint32_t* n_dev, int64_t cap, int64_t nkeys, uint32_t* ranges,
+                         hipStream_t st);
 hipError_t launch_tile_keys(const uint32_t* ranges, int64_t n, uint32_t* keys, uint32_t* vals, hipStream_t st);
 hipError_t launch_blend(const uint32_t* ranges, const uint32_t* order, const uint32_t* ids, const float4* rec_a,
                         const float4* rec_b, const float4* rec_c, const uint32_t* pair_of, int C, int W, int H,

@@ -606,26 +606,38 @@ static hipError_t launch_t(const AssetDev* assets, const WorkItem* items, int64_
   return hipGetLastError();
 }
 
-hipError_t launch_cull_mlp(const AssetDev* assets_dev, const AssetDev* assets_host, int32_t n_assets,
-                           const WorkItem* items, int64_t n_items, const int32_t* seglist, const SegRec* segs,
-                           const float* c1perm, int max_width, int width, int precision, int mode, uint32_t* mask,
-                           uint32_t* chunk_count, uint8_t* state, float* logits, unsigned long long* counts,
-                           hipStream_t st) {
-  (void)assets_host; (void)n_assets;
+bool mlp_shape_supported(int width, int precision, int nb) {
+  if (width != 64 && width != 128) return false;
+  return nb == 1 || nb == 2 || (nb == 4 && width == 64 && precision != NVGS_PREC_FP8);
+}
+
+hipError_t launch_cull_mlp(const AssetDev* assets_dev, const WorkItem* items, int64_t n_items, const int32_t* seglist,
+                           const SegRec* segs, const float* c1perm, int max_width, int width, int precision, int nb,
+                           int mode, uint32_t* mask, uint32_t* chunk_count, uint8_t* state, float* logits,
+                           unsigned long long* counts, hipStream_t st) {
   if (n_items == 0) return hipSuccess;
-#define NVGS_LAUNCH(P, W, NB, WV)                                                                                   \
-  return launch_t<P, W, NB, WV>(assets_dev, items, n_items, seglist, segs, c1perm, max_width, mode, mask,          \
-                                chunk_count, state, logits, counts, st)
-  if (precision == NVGS_PREC_FP32) {
-    if (width == 64) NVGS_LAUNCH(NVGS_PREC_FP32, 64, 2, 4);
-    if (width == 128) NVGS_LAUNCH(NVGS_PREC_FP32, 128, 1, 8);
-  } else if (precision == NVGS_PREC_BF16) {
-    if (width == 64) NVGS_LAUNCH(NVGS_PREC_BF16, 64, 2, 4);
-    if (width == 128) NVGS_LAUNCH(NVGS_PREC_BF16, 128, 1, 8);
-  } else if (precision == NVGS_PREC_FP8) {
-    if (width == 64) NVGS_LAUNCH(NVGS_PREC_FP8, 64, 2, 4);
-    if (width == 128) NVGS_LAUNCH(NVGS_PREC_FP8, 128, 1, 8);
+#define NVGS_LAUNCH(P, W, NB)                                                                                  \
+  return launch_t<P, W, NB, kChunk / (32 * NB)>(assets_dev, items, n_items, seglist, segs, c1perm, max_width, \
+                                                mode, mask, chunk_count, state, logits, counts, st)
+#define NVGS_SHAPES(P)                          \
+  if (width == 64) {                            \
+    if (nb == 1) NVGS_LAUNCH(P, 64, 1);         \
+    if (nb == 2) NVGS_LAUNCH(P, 64, 2);         \
+  } else if (width == 128) {                    \
+    if (nb == 1) NVGS_LAUNCH(P, 128, 1);        \
+    if (nb == 2) NVGS_LAUNCH(P, 128, 2);        \
   }
+  // four blocks per wave spill with the FP8 operand packing: FP32 and BF16 only
+  if (precision == NVGS_PREC_FP32) {
+    NVGS_SHAPES(NVGS_PREC_FP32)
+    if (width == 64 && nb == 4) NVGS_LAUNCH(NVGS_PREC_FP32, 64, 4);
+  } else if (precision == NVGS_PREC_BF16) {
+    NVGS_SHAPES(NVGS_PREC_BF16)
+    if (width == 64 && nb == 4) NVGS_LAUNCH(NVGS_PREC_BF16, 64, 4);
+  } else if (precision == NVGS_PREC_FP8) {
+    NVGS_SHAPES(NVGS_PREC_FP8)
+  }
+#undef NVGS_SHAPES
 #undef NVGS_LAUNCH
   return hipErrorInvalidValue;
 }

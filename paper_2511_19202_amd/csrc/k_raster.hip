@@ -255,7 +255,10 @@ hipError_t launch_gather_tiles(const uint32_t* sorted_ids, const uint4* rect, co
 }
 
 // one thread per splat in depth order: one (tile key, splat id) entry per
-// overlapped tile, written at the splat's exclusive offset
+// overlapped tile, written at the splat's exclusive offset.  Past the entry
+// capacity the overflow flag is raised and only the entries below it are
+// written, so every position of [0, cap_dup) still holds an entry of this
+// frame (a clipped frame, never stale keys).
 __global__ void k_emit(const uint32_t* __restrict__ ids, const uint4* __restrict__ rect,
                        const uint32_t* __restrict__ off, const uint32_t* __restrict__ n_dev, int64_t cap,
                        const uint32_t* __restrict__ n_dup_dev, int64_t cap_dup, int tiles_x, int n_tiles,
@@ -266,16 +269,19 @@ __global__ void k_emit(const uint32_t* __restrict__ ids, const uint4* __restrict
     const uint4 r = rect[s];
     if (r.w == 0) continue;
     int64_t o = off[j];
-    if (o + r.w > cap_dup) {
+    if (o >= cap_dup) {
       atomicOr(overflow, 2u);
       continue;
     }
+    if (o + r.w > cap_dup) atomicOr(overflow, 2u);
     const int tx0 = r.x & 0xffff, ty0 = r.x >> 16, tx1 = r.y & 0xffff, ty1 = r.y >> 16;
     const uint32_t kb = r.z * (uint32_t)n_tiles;
     for (int ty = ty0; ty <= ty1; ++ty)
       for (int tx = tx0; tx <= tx1; ++tx) {
-        keys[o] = kb + (uint32_t)(ty * tiles_x + tx);
-        vals[o] = s;
+        if (o < cap_dup) {
+          keys[o] = kb + (uint32_t)(ty * tiles_x + tx);
+          vals[o] = s;
+        }
         ++o;
       }
   }
@@ -304,21 +310,38 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st) {
   return hipGetLastError();
 }
 
+// High-water marks across frames: [12] max splats, [13] max tile entries,
+// [14] OR of the overflow flags (word [2] of the per-frame counters).
+__global__ void k_watermark(uint32_t* __restrict__ c) {
+  if (threadIdx.x == 0) {
+    c[12] = max(c[12], c[0]);
+    c[13] = max(c[13], c[1]);
+    c[14] |= c[2];
+  }
+}
+
+hipError_t launch_watermark(uint32_t* counters, hipStream_t st) {
+  hipLaunchKernelGGL(k_watermark, dim3(1), dim3(64), 0, st, counters);
+  return hipGetLastError();
+}
+
 // [start, end) of every tile key in the sorted list (ranges pre-filled with 0)
 __global__ void k_ranges(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_dev, int64_t cap,
-                         uint32_t* __restrict__ ranges) {
+                         int64_t nkeys, uint32_t* __restrict__ ranges) {
   const int64_t n = live(n_dev, cap);
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
     const uint32_t k = keys[j];
+    if (k >= nkeys) continue;
     if (j == 0 || keys[j - 1] != k) ranges[2 * (int64_t)k] = (uint32_t)j;
     if (j == n - 1 || keys[j + 1] != k) ranges[2 * (int64_t)k + 1] = (uint32_t)(j + 1);
   }
 }
 
-hipError_t launch_ranges(const uint32_t* keys, const uint32_t* n_dev, int64_t cap, uint32_t* ranges, hipStream_t st) {
+hipError_t launch_ranges(const uint32_t* keys, const uint32_t* n_dev, int64_t cap, int64_t nkeys, uint32_t* ranges,
+                         hipStream_t st) {
   if (cap == 0) return hipSuccess;
   unsigned grid = (unsigned)std::min<int64_t>((cap + 255) / 256, 65536);
-  hipLaunchKernelGGL(k_ranges, dim3(grid), dim3(256), 0, st, keys, n_dev, cap, ranges);
+  hipLaunchKernelGGL(k_ranges, dim3(grid), dim3(256), 0, st, keys, n_dev, cap, nkeys, ranges);
   return hipGetLastError();
 }
 

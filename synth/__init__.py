@@ -311,8 +311,10 @@ def scene_composed(n_per_asset: int = 250000, n_inst: int = 64, seed: int = SEED
 def scene_batched(n_assets: int = 16, n_inst: int = 1024, n_cams: int = 8,
                   seed: int = SEED_BASE + 4, width: int = 64, res=(1920, 1080),
                   tile: int = 16, sh_degree: int = 3, n_lo: float = 5e4, n_hi: float = 1e6,
-                  half_extent: float = 80.0, frame: int = 0, size_scale: float = 1.0) -> Scene:
-    """Uneven assets (log-uniform sizes), Zipf instance counts, a ring of cameras."""
+                  half_extent: float = 80.0, frame: int = 0, size_scale: float = 1.0,
+                  ring_radius: float = 60.0, ring_height: float = 15.0) -> Scene:
+    """Uneven assets (log-uniform sizes), Zipf instance counts, a ring of
+    cameras looking at the centre, turned by `frame` degrees."""
     names = ["torus", "sphere", "box", "helix"]
     g = rng(seed)
     sizes = np.round(np.exp(g.uniform(math.log(n_lo), math.log(n_hi), n_assets)) * size_scale).astype(np.int64)
@@ -335,13 +337,21 @@ def scene_batched(n_assets: int = 16, n_inst: int = 1024, n_cams: int = 8,
                                   t=np.array([xy[0], xy[1], 0.0], np.float32)))
     order = g.permutation(len(insts))
     insts = [insts[k] for k in order]
+    cams = ring_cameras(n_cams, frame, ring_radius, ring_height, res)
+    return Scene(assets=assets, instances=insts, cameras=cams, tile=tile, name="batched",
+                 extra={"instances_per_asset": per_asset.tolist(), "sizes": sizes.tolist()})
+
+
+def ring_cameras(n_cams: int = 8, frame: float = 0.0, radius: float = 60.0, height: float = 15.0,
+                 res=(1920, 1080), fovy_deg: float = 50.0) -> List[Camera]:
+    """n_cams cameras evenly spaced on a horizontal circle, looking at the
+    origin, the ring turned by `frame` degrees."""
     cams = []
     for k in range(n_cams):
         ang = 2 * np.pi * k / n_cams + math.radians(frame)
-        cams.append(camera((60 * math.cos(ang), 60 * math.sin(ang), 15.0), fovy_deg=50.0,
+        cams.append(camera((radius * math.cos(ang), radius * math.sin(ang), height), fovy_deg=fovy_deg,
                            width=res[0], height=res[1]))
-    return Scene(assets=assets, instances=insts, cameras=cams, tile=tile, name="batched",
-                 extra={"instances_per_asset": per_asset.tolist(), "sizes": sizes.tolist()})
+    return cams
 
 
 def fibonacci_sphere(n: int) -> np.ndarray:

@@ -42,3 +42,14 @@ def tiny(n=20000, res=256, width=64):
 
 def composed_small(**kw):
     return calibrate_keep(small_composed(**kw))
+
+
+def small_batched(frame=0, n_cams=3, res=(160, 96), width=64):
+    """The batching workload's recipe at test size: 5 uneven assets, 40
+    Zipf-distributed instances, a ring of cameras turned by `frame` degrees."""
+    return synth.scene_batched(n_assets=5, n_inst=40, n_cams=n_cams, res=res, n_lo=500, n_hi=4000,
+                               half_extent=6.0, frame=frame, ring_radius=8.0, ring_height=2.5, width=width)
+
+
+def batched_small(**kw):
+    return calibrate_keep(small_batched(**kw))

@@ -28,7 +28,9 @@ def so():
 def test_header_declares_the_entry_points():
     names = declared_functions()
     for must in ["nvgs_create", "nvgs_destroy", "nvgs_last_error", "nvgs_load_assets", "nvgs_set_instances",
-                 "nvgs_query_visibility", "nvgs_render", "nvgs_debug_buffers"]:
+                 "nvgs_query_visibility", "nvgs_render", "nvgs_debug_buffers", "nvgs_reserve",
+                 "nvgs_frame_watermarks", "nvgs_set_mlp_shape", "nvgs_autotune", "nvgs_make_labels",
+                 "nvgs_train_visibility", "nvgs_mlp_forward", "nvgs_mlp_backward"]:
         assert must in names
 
 
@@ -50,7 +52,8 @@ def test_struct_layouts_match_the_header():
     structs = {"nvgs_create_info": nvgs.CreateInfo, "nvgs_mlp": nvgs.MLP, "nvgs_asset": nvgs.Asset,
                "nvgs_instance": nvgs.Instance, "nvgs_camera": nvgs.Camera, "nvgs_render_opts": nvgs.RenderOpts,
                "nvgs_frame_stats": nvgs.FrameStats, "nvgs_debug_view": nvgs.DebugView,
-               "nvgs_train_opts": nvgs.TrainOpts}
+               "nvgs_train_opts": nvgs.TrainOpts, "nvgs_mlp_shape": nvgs.MlpShape,
+               "nvgs_tune_entry": nvgs.TuneEntry}
     body = "\n".join(f'printf("%zu\\n", sizeof({k}));' for k in structs)
     with tempfile.TemporaryDirectory() as d:
         c = os.path.join(d, "s.c")

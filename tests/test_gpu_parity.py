@@ -60,6 +60,7 @@ SCENES = {
     "tiny": lambda: scenes.tiny(),
     "tiny_w128": lambda: scenes.tiny(n=5000, res=128, width=128),
     "composed_small": lambda: scenes.composed_small(),
+    "batched_small": lambda: scenes.batched_small(),
 }
 
 
