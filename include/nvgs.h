@@ -164,9 +164,9 @@ typedef struct nvgs_frame_stats {
 typedef struct nvgs_debug_view {
   int64_t n_splats, n_dup;
   const uint32_t* pair;    /* [n_splats] index into [C][P] of the splat's pair (KEEP_DEBUG only) */
-  const float* rec_a;      /* [n_splats][4]: u, v, conic xx, conic xy (pixels) */
-  const float* rec_b;      /* [n_splats][4]: conic yy, opacity, r, g */
-  const float* rec_c;      /* [n_splats][4]: b, depth, ex, ey (footprint half extents, pixels) */
+  const float* rec_a;      /* [n_splats][4]: u, v, conic xx, conic xy (pixels; KEEP_DEBUG only) */
+  const float* rec_b;      /* [n_splats][4]: conic yy, opacity, r, g (KEEP_DEBUG only) */
+  const float* rec_c;      /* [n_splats][4]: b, depth, ex, ey (footprint half extents, pixels; KEEP_DEBUG only) */
   const uint32_t* rect;    /* [n_splats][4]: x0 | y0 << 16, x1 | y1 << 16 (tile coords), cam, tiles */
   const uint32_t* sorted_key; /* [n_dup] cam * n_tiles + tile, ascending */
   const uint32_t* sorted_id;  /* [n_dup] splat id, (depth, id) order within a tile */
@@ -213,8 +213,11 @@ void nvgs_destroy(nvgs_ctx* ctx);
 const char* nvgs_last_error(const nvgs_ctx* ctx);
 
 /* Register the asset store (each asset stored once, Sec. 3.3).  Arrays are
- * borrowed.  Validates shapes; copies MLP weights into the kernels' operand
- * layouts (asynchronous).  Invalidates the instance list. */
+ * borrowed (the means are read by every frame's culling).  Validates shapes;
+ * copies the MLP weights into the kernels' operand layouts and the Gaussians
+ * into library-owned per-Gaussian projection records (48 bytes of geometry
+ * plus 3 (d+1)^2 SH floats rounded up to a multiple of 4, i.e. 240 bytes per
+ * SH-3 Gaussian), asynchronously.  Invalidates the instance list. */
 nvgs_status nvgs_load_assets(nvgs_ctx* ctx, const nvgs_asset* assets, int32_t n);
 
 /* Copy the instance list (host array).  Synchronous host->device copy.

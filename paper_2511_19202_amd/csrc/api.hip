@@ -61,7 +61,7 @@ struct nvgs_ctx {
 
   // splats and sort buffers
   int64_t cap_splats = 0, cap_dup = 0;
-  Buf rec_a, rec_b, rec_c, rect, depth_key, ids, ids_tmp, keys_tmp2, pair_of, cnt, dup_off;
+  Buf splat, rec_a, rec_b, rec_c, rect, depth_key, ids, ids_tmp, keys_tmp2, pair_of, cnt, dup_off;
   Buf keys, vals, keys_tmp, vals_tmp, hist, hist_part, ranges, tord;  // tord: tile order (4 arrays)
   int64_t cap_keys = 0;  // tile keys (cameras x tiles) the range buffers hold
   // u32 [0] n_splats, [1] n_dup, [2] overflow flags; u64 at [4] in-frustum, [6] queried, [8] blend tests
@@ -311,7 +311,7 @@ void nvgs_destroy(nvgs_ctx* ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   Buf* all[] = {&ctx->assets_dev, &ctx->inst_dev, &ctx->inst_off_dev, &ctx->seg_word_dev, &ctx->seg_chunk_dev,
                 &ctx->items_dev, &ctx->seglist_dev, &ctx->segs_dev, &ctx->c1_dev, &ctx->mask, &ctx->chunk_cnt,
-                &ctx->chunk_off, &ctx->scan_part, &ctx->cam_dev, &ctx->rec_a, &ctx->rec_b, &ctx->rec_c, &ctx->rect,
+                &ctx->chunk_off, &ctx->scan_part, &ctx->cam_dev, &ctx->splat, &ctx->rec_a, &ctx->rec_b, &ctx->rec_c, &ctx->rect,
                 &ctx->depth_key, &ctx->ids, &ctx->ids_tmp, &ctx->keys_tmp2, &ctx->pair_of, &ctx->cnt, &ctx->dup_off,
                 &ctx->keys, &ctx->vals, &ctx->keys_tmp, &ctx->vals_tmp, &ctx->hist, &ctx->hist_part, &ctx->ranges, &ctx->tord,
                 &ctx->counters};
@@ -353,7 +353,8 @@ nvgs_status nvgs_load_assets(nvgs_ctx* ctx, const nvgs_asset* a, int32_t n) {
   CK(hipSetDevice(ctx->device));
   CK(hipStreamSynchronize(ctx->stream));
   for (Buf& b : ctx->op_bufs) release(ctx, b);
-  ctx->op_bufs.assign(4 * (size_t)n, Buf{});  // per asset: FP32, BF16, FP8 images, FP8 scales
+  // per asset: FP32, BF16, FP8 operand images, FP8 scales, projection geometry and SH records
+  ctx->op_bufs.assign(6 * (size_t)n, Buf{});
   ctx->assets.assign(a, a + n);
   ctx->adev.assign(n, AssetDev{});
   for (int j = 0; j < n; ++j) {
@@ -364,11 +365,18 @@ nvgs_status nvgs_load_assets(nvgs_ctx* ctx, const nvgs_asset* a, int32_t n) {
     d.mean_scale = x.mlp.mean_scale; d.cam_scale = x.mlp.cam_scale; d.train_focal = x.mlp.train_focal;
     d.d_min = x.mlp.d_min; d.d_max = x.mlp.d_max;
     d.params = x.mlp.params;
-    Buf* ob = &ctx->op_bufs[4 * (size_t)j];
+    Buf* ob = &ctx->op_bufs[6 * (size_t)j];
     if (!ensure(ctx, ob[0], mlp_op_f32_floats(width) * sizeof(float)) ||
         !ensure(ctx, ob[1], mlp_op_bf16_elems(width) * sizeof(uint16_t)) ||
-        !ensure(ctx, ob[2], mlp_op_fp8_bytes(width)) || !ensure(ctx, ob[3], 16 * sizeof(float)))
+        !ensure(ctx, ob[2], mlp_op_fp8_bytes(width)) || !ensure(ctx, ob[3], 16 * sizeof(float)) ||
+        !ensure(ctx, ob[4], 3 * sizeof(float4) * (size_t)x.n) ||
+        !ensure(ctx, ob[5], sizeof(float) * (size_t)sh_stride_for(x.sh_degree) * (size_t)x.n))
       return fail(ctx, NVGS_E_NOMEM, "operand images");
+    d.geo = P_<float4>(ob[4]);
+    d.shp = P_<float>(ob[5]);
+    d.sh_stride = sh_stride_for(x.sh_degree);
+    CK(launch_pack_asset(x.mean, x.scale, x.quat, x.opacity, x.sh, x.n, x.sh_degree, P_<float4>(ob[4]),
+                         P_<float>(ob[5]), ctx->stream));
     d.op_f32 = P_<float>(ob[0]);
     d.op_bf16 = P_<uint16_t>(ob[1]);
     d.op_fp8 = P_<uint8_t>(ob[2]);
@@ -468,7 +476,7 @@ nvgs_status size_hist(nvgs_ctx* ctx) {
 nvgs_status size_splats(nvgs_ctx* ctx, int64_t need, bool slack) {
   if (need <= ctx->cap_splats && ctx->rec_a.p) return NVGS_OK;
   const int64_t cap = std::max<int64_t>(slack ? need + need / 8 : need, 4096);
-  const bool ok = ensure(ctx, ctx->rec_a, 16 * cap) && ensure(ctx, ctx->rec_b, 16 * cap) &&
+  const bool ok = ensure(ctx, ctx->splat, 64 * cap) && ensure(ctx, ctx->rec_a, 16 * cap) && ensure(ctx, ctx->rec_b, 16 * cap) &&
                   ensure(ctx, ctx->rec_c, 16 * cap) && ensure(ctx, ctx->rect, 16 * cap) &&
                   ensure(ctx, ctx->depth_key, 4 * cap) && ensure(ctx, ctx->ids, 4 * cap) &&
                   ensure(ctx, ctx->ids_tmp, 4 * cap) && ensure(ctx, ctx->keys_tmp2, 4 * cap) &&
@@ -551,9 +559,9 @@ nvgs_status enqueue_frame(nvgs_ctx* ctx, hipStream_t st, const Frame& f, bool ea
   STAGE_BEGIN(NVGS_STAGE_PROJECT);
   CK(launch_project(P_<AssetDev>(ctx->assets_dev), P_<SegRec>(ctx->segs_dev), C * NI, P_<int64_t>(ctx->seg_chunk_dev),
                     ctx->n_chunks, P_<uint32_t>(ctx->mask), P_<uint32_t>(ctx->chunk_off), n_splats_dev,
-                    ctx->cap_splats, f.T, f.tiles_x, f.tiles_y, f.debug ? 1 : 0, P_<float4>(ctx->rec_a),
-                    P_<float4>(ctx->rec_b), P_<float4>(ctx->rec_c), P_<uint4>(ctx->rect), P_<uint32_t>(ctx->depth_key),
-                    P_<uint32_t>(ctx->pair_of), counters + 2, st));
+                    ctx->cap_splats, f.T, f.tiles_x, f.tiles_y, f.debug ? 1 : 0, P_<float4>(ctx->splat),
+                    P_<float4>(ctx->rec_a), P_<float4>(ctx->rec_b), P_<float4>(ctx->rec_c), P_<uint4>(ctx->rect),
+                    P_<uint32_t>(ctx->depth_key), P_<uint32_t>(ctx->pair_of), counters + 2, st));
   STAGE_END(NVGS_STAGE_PROJECT);
   // depth order of the splats (stable: equal depths keep id order)
   STAGE_BEGIN(NVGS_STAGE_DEPTH_SORT);
@@ -600,9 +608,8 @@ nvgs_status enqueue_frame(nvgs_ctx* ctx, hipStream_t st, const Frame& f, bool ea
   const uint32_t* tile_order = in_tmp3 ? tk + 3 * nk : tk + nk;
   STAGE_END(NVGS_STAGE_TILE_SORT);
   STAGE_BEGIN(NVGS_STAGE_BLEND);
-  CK(launch_blend(P_<uint32_t>(ctx->ranges), tile_order, sids, P_<float4>(ctx->rec_a), P_<float4>(ctx->rec_b),
-                  P_<float4>(ctx->rec_c), P_<uint32_t>(ctx->pair_of), C, f.W, f.H, f.T, f.tiles_x, f.tiles_y,
-                  opts->bg[0], opts->bg[1], opts->bg[2], f.rgb, f.record ? opts->contrib : nullptr,
+  CK(launch_blend(P_<uint32_t>(ctx->ranges), tile_order, sids, P_<float4>(ctx->splat), C, f.W, f.H, f.T, f.tiles_x,
+                  f.tiles_y, opts->bg[0], opts->bg[1], opts->bg[2], f.rgb, f.record ? opts->contrib : nullptr,
                   f.count_tests ? reinterpret_cast<unsigned long long*>(counters + 8) : nullptr, st));
   STAGE_END(NVGS_STAGE_BLEND);
   CK(launch_watermark(counters, st));
@@ -869,9 +876,9 @@ nvgs_status nvgs_debug_buffers(nvgs_ctx* ctx, nvgs_debug_view* out) {
     out->n_dup = ctx->last_dup;
   }
   out->pair = ctx->last_debug ? P_<uint32_t>(ctx->pair_of) : nullptr;
-  out->rec_a = P_<float>(ctx->rec_a);
-  out->rec_b = P_<float>(ctx->rec_b);
-  out->rec_c = P_<float>(ctx->rec_c);
+  out->rec_a = ctx->last_debug ? P_<float>(ctx->rec_a) : nullptr;
+  out->rec_b = ctx->last_debug ? P_<float>(ctx->rec_b) : nullptr;
+  out->rec_c = ctx->last_debug ? P_<float>(ctx->rec_c) : nullptr;
   out->rect = P_<uint32_t>(ctx->rect);
   out->sorted_key = ctx->last_sorted_key;
   out->sorted_id = ctx->last_sorted_id;

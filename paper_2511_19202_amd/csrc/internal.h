@@ -38,7 +38,17 @@ struct AssetDev {
   const uint16_t* op_bf16;
   const uint8_t* op_fp8;
   const float* fp8_scale; // per-layer dequantisation scales
+  // projection image (library-owned, one record per Gaussian so that the
+  // gathers of sparse survivors read whole lines): geo[3g..3g+2] =
+  // (mean, opacity), (scale, 0), (qw, qx, qy, qz); shp[g * sh_stride + 3c + ch]
+  const float4* geo;
+  const float* shp;
+  int32_t sh_stride;     // 3 (d+1)^2 rounded up to a multiple of 4
 };
+
+int32_t sh_stride_for(int sh_degree);
+hipError_t launch_pack_asset(const float* mean, const float* scale, const float* quat, const float* opacity,
+                             const float* sh, int64_t n, int sh_degree, float4* geo, float* shp, hipStream_t st);
 
 // Per (camera, instance) segment, built on the device every frame.
 struct SegRec {
@@ -104,9 +114,9 @@ size_t scan_partials_needed(int64_t n);
 
 hipError_t launch_project(const AssetDev* assets, const SegRec* segs, int32_t n_segs, const int64_t* seg_chunk_base,
                           int64_t n_chunks, const uint32_t* mask, const uint32_t* chunk_off, const uint32_t* n_splats,
-                          int64_t cap_splats, int tile, int tiles_x, int tiles_y, int keep_debug, float4* rec_a,
-                          float4* rec_b, float4* rec_c, uint4* rect, uint32_t* depth_key, uint32_t* pair_of,
-                          uint32_t* overflow, hipStream_t st);
+                          int64_t cap_splats, int tile, int tiles_x, int tiles_y, int keep_debug, float4* splat,
+                          float4* rec_a, float4* rec_b, float4* rec_c, uint4* rect, uint32_t* depth_key,
+                          uint32_t* pair_of, uint32_t* overflow, hipStream_t st);
 
 hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint32_t* vals_tmp,
                              const uint32_t* n_dev, int64_t cap, int begin_bit, int end_bit, int iota_vals,
@@ -123,9 +133,9 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
 hipError_t launch_ranges(const uint32_t* keys, const uint32_t* n_dev, int64_t cap, int64_t nkeys, uint32_t* ranges,
                          hipStream_t st);
 hipError_t launch_tile_keys(const uint32_t* ranges, int64_t n, uint32_t* keys, uint32_t* vals, hipStream_t st);
-hipError_t launch_blend(const uint32_t* ranges, const uint32_t* order, const uint32_t* ids, const float4* rec_a,
-                        const float4* rec_b, const float4* rec_c, const uint32_t* pair_of, int C, int W, int H,
-                        int tile, int tiles_x, int tiles_y, float bg0, float bg1, float bg2, float* rgb,
+// splat: [n][4] float4 compositing records written by launch_project
+hipError_t launch_blend(const uint32_t* ranges, const uint32_t* order, const uint32_t* ids, const float4* splat, int C,
+                        int W, int H, int tile, int tiles_x, int tiles_y, float bg0, float bg1, float bg2, float* rgb,
                         float* contrib, unsigned long long* work, hipStream_t st);
 
 }  // namespace nvgs

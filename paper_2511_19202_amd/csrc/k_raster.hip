@@ -23,8 +23,8 @@ namespace nvgs {
 // real spherical harmonics (l <= 3, order l-major, m = -l..l, no Condon-
 // Shortley phase) evaluated on a unit direction, accumulated into rgb
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void sh_color(const float* __restrict__ sh, int64_t n, int64_t g, int degree, float x,
-                                         float y, float z, float rgb[3]) {
+__device__ __forceinline__ void sh_color(const float* __restrict__ p, int degree, float x, float y, float z,
+                                         float rgb[3]) {
   // normalisation constants sqrt((2l+1)/(4pi) (l-m)!/(l+m)!) (x sqrt2 for m != 0)
   constexpr float c0 = 0.28209479177387814f;
   constexpr float c1 = 0.48860251190291992f;
@@ -64,14 +64,41 @@ __device__ __forceinline__ void sh_color(const float* __restrict__ sh, int64_t n
   }
   float r = 0.5f, gg = 0.5f, b = 0.5f;
   for (int k = 0; k < K; ++k) {
-    const float* p = sh + (int64_t)(3 * k) * n + g;
-    r = fmaf(Y[k], p[0], r);
-    gg = fmaf(Y[k], p[n], gg);
-    b = fmaf(Y[k], p[2 * n], b);
+    r = fmaf(Y[k], p[3 * k], r);
+    gg = fmaf(Y[k], p[3 * k + 1], gg);
+    b = fmaf(Y[k], p[3 * k + 2], b);
   }
   rgb[0] = fmaxf(r, 0.f);
   rgb[1] = fmaxf(gg, 0.f);
   rgb[2] = fmaxf(b, 0.f);
+}
+
+int32_t sh_stride_for(int sh_degree) {
+  const int k = 3 * (sh_degree + 1) * (sh_degree + 1);
+  return (k + 3) & ~3;
+}
+
+// SoA asset arrays -> one geometry record and one SH row per Gaussian
+__global__ void k_pack_asset(const float* __restrict__ mean, const float* __restrict__ scale,
+                             const float* __restrict__ quat, const float* __restrict__ opacity,
+                             const float* __restrict__ sh, int64_t n, int K, int stride, float4* __restrict__ geo,
+                             float* __restrict__ shp) {
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x) {
+    geo[3 * g] = make_float4(mean[g], mean[n + g], mean[2 * n + g], opacity[g]);
+    geo[3 * g + 1] = make_float4(scale[g], scale[n + g], scale[2 * n + g], 0.f);
+    geo[3 * g + 2] = make_float4(quat[g], quat[n + g], quat[2 * n + g], quat[3 * n + g]);
+    float* row = shp + g * stride;
+    for (int c = 0; c < stride; ++c) row[c] = c < K ? sh[(int64_t)c * n + g] : 0.f;
+  }
+}
+
+hipError_t launch_pack_asset(const float* mean, const float* scale, const float* quat, const float* opacity,
+                             const float* sh, int64_t n, int sh_degree, float4* geo, float* shp, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_pack_asset, dim3(grid), dim3(256), 0, st, mean, scale, quat, opacity, sh, n,
+                     3 * (sh_degree + 1) * (sh_degree + 1), sh_stride_for(sh_degree), geo, shp);
+  return hipGetLastError();
 }
 
 // pixel-rectangle bound of the alpha >= 1/255 set: centres x + 0.5 within
@@ -91,8 +118,9 @@ __global__ __launch_bounds__(kChunk) void k_project(
     const AssetDev* __restrict__ assets, const SegRec* __restrict__ segs, int32_t n_segs,
     const int64_t* __restrict__ seg_chunk_base, const uint32_t* __restrict__ mask,
     const uint32_t* __restrict__ chunk_off, int64_t cap, int tile, int tiles_x, int tiles_y, int keep_debug,
-    float4* __restrict__ rec_a, float4* __restrict__ rec_b, float4* __restrict__ rec_c, uint4* __restrict__ rect,
-    uint32_t* __restrict__ depth_key, uint32_t* __restrict__ pair_of, uint32_t* __restrict__ overflow) {
+    float4* __restrict__ splat, float4* __restrict__ rec_a, float4* __restrict__ rec_b, float4* __restrict__ rec_c,
+    uint4* __restrict__ rect, uint32_t* __restrict__ depth_key, uint32_t* __restrict__ pair_of,
+    uint32_t* __restrict__ overflow) {
   const int64_t chunk = blockIdx.x;
   // segment of this chunk: last s with seg_chunk_base[s] <= chunk
   int lo = 0, hi = n_segs - 1;
@@ -122,10 +150,11 @@ __global__ __launch_bounds__(kChunk) void k_project(
     return;
   }
   const AssetDev& A = assets[R.asset];
-  const float mu[3] = {A.mean[g], A.mean[n + g], A.mean[2 * n + g]};
-  const float s3[3] = {A.scale[g], A.scale[n + g], A.scale[2 * n + g]};
-  float qw = A.quat[g], qx = A.quat[n + g], qy = A.quat[2 * n + g], qz = A.quat[3 * n + g];
-  const float o = A.opacity[g];
+  const float4 g0 = A.geo[3 * g], g1 = A.geo[3 * g + 1], g2 = A.geo[3 * g + 2];
+  const float mu[3] = {g0.x, g0.y, g0.z};
+  const float s3[3] = {g1.x, g1.y, g1.z};
+  float qw = g2.x, qx = g2.y, qy = g2.z, qz = g2.w;
+  const float o = g0.w;
   // camera space
   const float* M = R.M;
   const float px = fmaf(M[0], mu[0], fmaf(M[1], mu[1], fmaf(M[2], mu[2], M[3])));
@@ -191,7 +220,7 @@ __global__ __launch_bounds__(kChunk) void k_project(
   float dx = mu[0] - R.cl[0], dy = mu[1] - R.cl[1], dz = mu[2] - R.cl[2];
   const float dn = rsqrtf(dx * dx + dy * dy + dz * dz);
   float rgb[3];
-  sh_color(A.sh, n, g, A.sh_degree, dx * dn, dy * dn, dz * dn, rgb);
+  sh_color(A.shp + g * A.sh_stride, A.sh_degree, dx * dn, dy * dn, dz * dn, rgb);
   // footprint
   const float k2 = 2.f * logf(255.f * o);
   const int W = (int)(2.f * R.half_w), H = (int)(2.f * R.half_h);
@@ -210,25 +239,35 @@ __global__ __launch_bounds__(kChunk) void k_project(
       ntiles = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
     }
   }
-  rec_a[slot] = make_float4(u, v, ca, cb);
-  rec_b[slot] = make_float4(cc2, o, rgb[0], rgb[1]);
-  rec_c[slot] = make_float4(rgb[2], pz, ex, ey);
+  // the compositing record: one 64-byte line per splat, the conic scaled so
+  // that the exponent is base 2, and the log2 pre-test bound precomputed
+  constexpr float kLog2e = 1.4426950408889634f;
+  float4* sp = splat + 4 * (int64_t)slot;
+  sp[0] = make_float4(u, v, -0.5f * kLog2e * ca, -kLog2e * cb);
+  sp[1] = make_float4(-0.5f * kLog2e * cc2, o, -__log2f(255.f * o) - 0.01f, rgb[0]);
+  sp[2] = make_float4(rgb[1], rgb[2], ex, ey);
+  sp[3] = make_float4(__uint_as_float((uint32_t)(R.pair_base + g)), pz, 0.f, 0.f);
   rect[slot] = make_uint4(r0, r1, (uint32_t)R.cam, ntiles);
   depth_key[slot] = fbits(pz);
-  if (keep_debug) pair_of[slot] = (uint32_t)(R.pair_base + g);
+  if (keep_debug) {
+    rec_a[slot] = make_float4(u, v, ca, cb);
+    rec_b[slot] = make_float4(cc2, o, rgb[0], rgb[1]);
+    rec_c[slot] = make_float4(rgb[2], pz, ex, ey);
+    pair_of[slot] = (uint32_t)(R.pair_base + g);
+  }
   (void)tiles_x; (void)tiles_y;
 }
 
 hipError_t launch_project(const AssetDev* assets, const SegRec* segs, int32_t n_segs, const int64_t* seg_chunk_base,
                           int64_t n_chunks, const uint32_t* mask, const uint32_t* chunk_off, const uint32_t* n_splats,
-                          int64_t cap_splats, int tile, int tiles_x, int tiles_y, int keep_debug, float4* rec_a,
-                          float4* rec_b, float4* rec_c, uint4* rect, uint32_t* depth_key, uint32_t* pair_of,
-                          uint32_t* overflow, hipStream_t st) {
+                          int64_t cap_splats, int tile, int tiles_x, int tiles_y, int keep_debug, float4* splat,
+                          float4* rec_a, float4* rec_b, float4* rec_c, uint4* rect, uint32_t* depth_key,
+                          uint32_t* pair_of, uint32_t* overflow, hipStream_t st) {
   (void)n_splats;
   if (n_chunks == 0) return hipSuccess;
   hipLaunchKernelGGL(k_project, dim3((unsigned)n_chunks), dim3(kChunk), 0, st, assets, segs, n_segs, seg_chunk_base,
-                     mask, chunk_off, cap_splats, tile, tiles_x, tiles_y, keep_debug, rec_a, rec_b, rec_c, rect,
-                     depth_key, pair_of, overflow);
+                     mask, chunk_off, cap_splats, tile, tiles_x, tiles_y, keep_debug, splat, rec_a, rec_b, rec_c,
+                     rect, depth_key, pair_of, overflow);
   return hipGetLastError();
 }
 
@@ -380,18 +419,16 @@ hipError_t launch_tile_keys(const uint32_t* ranges, int64_t n, uint32_t* keys, u
 template <int T, bool RECORD>
 __global__ __launch_bounds__(T == 8 ? 64 : 256) void k_blend(
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ order, const uint32_t* __restrict__ ids,
-    const float4* __restrict__ rec_a, const float4* __restrict__ rec_b, const float4* __restrict__ rec_c,
-    const uint32_t* __restrict__ pair_of, int W, int H, int tiles_x, int n_tiles, float bg0, float bg1, float bg2,
+    const float4* __restrict__ splat, int W, int H, int tiles_x, int n_tiles, float bg0, float bg1, float bg2,
     float* __restrict__ rgb, uint32_t* __restrict__ contrib, unsigned long long* __restrict__ work) {
   constexpr int NT = T == 8 ? 64 : 256;  // threads
   constexpr int NB = T * T / 64;         // 8x8 pixel blocks per tile
   constexpr int BPW = NB / (NT / 64);    // blocks per wave (1, 1, 4)
   constexpr int BATCH = 256;
   constexpr int LPT = BATCH / NT;        // splats each thread stages per batch
-  constexpr float kLog2e = 1.4426950408889634f;
   __shared__ float4 s_g[BATCH];  // u, v, A, B   (A, B, C: conic scaled by -log2(e)/2, -log2(e), -log2(e)/2)
-  __shared__ float4 s_h[BATCH];  // C, opacity, log2 bound, -
-  __shared__ float4 s_c[BATCH];  // r, g, b, -
+  __shared__ float4 s_h[BATCH];  // C, opacity, log2 bound, r
+  __shared__ float2 s_c[BATCH];  // g, b
   __shared__ uint32_t s_ov[T == 8 ? 1 : BATCH];  // bit b: the footprint box touches 8x8 block b
   __shared__ uint32_t s_p[RECORD ? BATCH : 1];
   const int key = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
@@ -423,11 +460,11 @@ __global__ __launch_bounds__(T == 8 ? 64 : 256) void k_blend(
     for (int i = 0; i < LPT; ++i) {
       const uint32_t idx = b0 + t + i * NT;
       if (idx < end) {
-        const uint32_t id = ids[idx];
-        pa[i] = rec_a[id];
-        pb[i] = rec_b[id];
-        pc[i] = rec_c[id];
-        if (RECORD) pp[i] = pair_of[id];
+        const float4* r = splat + 4 * (int64_t)ids[idx];
+        pa[i] = r[0];
+        pb[i] = r[1];
+        pc[i] = r[2];
+        if (RECORD) pp[i] = __float_as_uint(r[3].x);
       }
     }
   };
@@ -455,11 +492,11 @@ __global__ __launch_bounds__(T == 8 ? 64 : 256) void k_blend(
           --alive;
           stop[j] = b0k + ks[u];
         } else {
-          const float4 c = s_c[ks[u]];
+          const float2 c = s_c[ks[u]];
           const float w = al[u] * Tr[j];
-          cr[j] = fmaf(w, c.x, cr[j]);
-          cg[j] = fmaf(w, c.y, cg[j]);
-          cb[j] = fmaf(w, c.z, cb[j]);
+          cr[j] = fmaf(w, s_h[ks[u]].w, cr[j]);
+          cg[j] = fmaf(w, c.x, cg[j]);
+          cb[j] = fmaf(w, c.y, cb[j]);
           if (RECORD) atomicMax(contrib + s_p[ks[u]], __float_as_uint(w));
           Tr[j] = Tn;
         }
@@ -480,11 +517,11 @@ __global__ __launch_bounds__(T == 8 ? 64 : 256) void k_blend(
       stop[j] = b0k + k;
       return;
     }
-    const float4 c = s_c[k];
+    const float2 c = s_c[k];
     const float w = al * Tr[j];
-    cr[j] = fmaf(w, c.x, cr[j]);
-    cg[j] = fmaf(w, c.y, cg[j]);
-    cb[j] = fmaf(w, c.z, cb[j]);
+    cr[j] = fmaf(w, h.w, cr[j]);
+    cg[j] = fmaf(w, c.x, cg[j]);
+    cb[j] = fmaf(w, c.y, cb[j]);
     if (RECORD) atomicMax(contrib + s_p[k], __float_as_uint(w));
     Tr[j] = Tn;
   };
@@ -497,13 +534,13 @@ __global__ __launch_bounds__(T == 8 ? 64 : 256) void k_blend(
     for (int i = 0; i < LPT; ++i) {
       const int k = t + i * NT;
       if (k < (int)cnt) {
-        s_g[k] = make_float4(pa[i].x, pa[i].y, -0.5f * kLog2e * pa[i].z, -kLog2e * pa[i].w);
-        s_h[k] = make_float4(-0.5f * kLog2e * pb[i].x, pb[i].y, -__log2f(255.f * pb[i].y) - 0.01f, 0.f);
-        s_c[k] = make_float4(pb[i].z, pb[i].w, pc[i].x, 0.f);
+        s_g[k] = pa[i];
+        s_h[k] = pb[i];
+        s_c[k] = make_float2(pc[i].x, pc[i].y);
         if (T != 8) {
           // blocks touched by the footprint box (same widening as the tile rectangle)
           const float wx = 1e-4f * pc[i].z + 1e-3f, wy = 1e-4f * pc[i].w + 1e-3f;
-          const float x0 = pa[i].x - pc[i].z - wx - (float)(tx * T) - 0.5f;
+          const float x0 = pa[i].x - pc[i].z - wx - (float)(tx * T) - 0.5f;  // pc: g, b, ex, ey
           const float x1 = pa[i].x + pc[i].z + wx - (float)(tx * T) - 0.5f;
           const float y0 = pa[i].y - pc[i].w - wy - (float)(ty * T) - 0.5f;
           const float y1 = pa[i].y + pc[i].w + wy - (float)(ty * T) - 0.5f;
@@ -586,34 +623,32 @@ __global__ __launch_bounds__(T == 8 ? 64 : 256) void k_blend(
 
 template <int T>
 static void launch_blend_t(bool record, dim3 grid, hipStream_t st, const uint32_t* ranges, const uint32_t* order,
-                           const uint32_t* ids, const float4* ra, const float4* rb, const float4* rc,
-                           const uint32_t* pair_of, int W, int H, int tiles_x, int n_tiles, float b0, float b1,
-                           float b2, float* rgb, float* contrib, unsigned long long* work) {
+                           const uint32_t* ids, const float4* splat, int W, int H, int tiles_x, int n_tiles, float b0,
+                           float b1, float b2, float* rgb, float* contrib, unsigned long long* work) {
   constexpr int NT = T == 8 ? 64 : 256;
   if (record)
-    hipLaunchKernelGGL((k_blend<T, true>), grid, dim3(NT), 0, st, ranges, order, ids, ra, rb, rc, pair_of, W, H,
-                       tiles_x, n_tiles, b0, b1, b2, rgb, reinterpret_cast<uint32_t*>(contrib), work);
+    hipLaunchKernelGGL((k_blend<T, true>), grid, dim3(NT), 0, st, ranges, order, ids, splat, W, H, tiles_x, n_tiles,
+                       b0, b1, b2, rgb, reinterpret_cast<uint32_t*>(contrib), work);
   else
-    hipLaunchKernelGGL((k_blend<T, false>), grid, dim3(NT), 0, st, ranges, order, ids, ra, rb, rc, pair_of, W, H,
-                       tiles_x, n_tiles, b0, b1, b2, rgb, reinterpret_cast<uint32_t*>(contrib), work);
+    hipLaunchKernelGGL((k_blend<T, false>), grid, dim3(NT), 0, st, ranges, order, ids, splat, W, H, tiles_x, n_tiles,
+                       b0, b1, b2, rgb, reinterpret_cast<uint32_t*>(contrib), work);
 }
 
-hipError_t launch_blend(const uint32_t* ranges, const uint32_t* order, const uint32_t* ids, const float4* rec_a,
-                        const float4* rec_b, const float4* rec_c, const uint32_t* pair_of, int C, int W, int H,
-                        int tile, int tiles_x, int tiles_y, float bg0, float bg1, float bg2, float* rgb,
+hipError_t launch_blend(const uint32_t* ranges, const uint32_t* order, const uint32_t* ids, const float4* splat, int C,
+                        int W, int H, int tile, int tiles_x, int tiles_y, float bg0, float bg1, float bg2, float* rgb,
                         float* contrib, unsigned long long* work, hipStream_t st) {
   const int n_tiles = tiles_x * tiles_y;
   dim3 grid((unsigned)(C * n_tiles));
   const bool record = contrib != nullptr;
   if (tile == 8)
-    launch_blend_t<8>(record, grid, st, ranges, order, ids, rec_a, rec_b, rec_c, pair_of, W, H, tiles_x, n_tiles,
-                      bg0, bg1, bg2, rgb, contrib, work);
+    launch_blend_t<8>(record, grid, st, ranges, order, ids, splat, W, H, tiles_x, n_tiles, bg0, bg1, bg2, rgb,
+                      contrib, work);
   else if (tile == 16)
-    launch_blend_t<16>(record, grid, st, ranges, order, ids, rec_a, rec_b, rec_c, pair_of, W, H, tiles_x, n_tiles,
-                       bg0, bg1, bg2, rgb, contrib, work);
+    launch_blend_t<16>(record, grid, st, ranges, order, ids, splat, W, H, tiles_x, n_tiles, bg0, bg1, bg2, rgb,
+                       contrib, work);
   else if (tile == 32)
-    launch_blend_t<32>(record, grid, st, ranges, order, ids, rec_a, rec_b, rec_c, pair_of, W, H, tiles_x, n_tiles,
-                       bg0, bg1, bg2, rgb, contrib, work);
+    launch_blend_t<32>(record, grid, st, ranges, order, ids, splat, W, H, tiles_x, n_tiles, bg0, bg1, bg2, rgb,
+                       contrib, work);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
