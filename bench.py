@@ -390,10 +390,11 @@ def main_batched(args):
     t_f, per = time_graph(ctx, rings, steps, args.warmup, **kw)
     check_no_overflow(ctx)
     _, stage, st, img = time_frames(ctx, sc, 3, 1, **kw)
-    # culled vs unculled on the first ring position (GPU images)
-    iu = ctx.render(sc.cameras, tile=tile, precision=prec, use_mlp=False).cpu().numpy()
-    ic = img.cpu().numpy()
-    psnrs = [psnr(ic[k], iu[k]) for k in range(len(sc.cameras))]
+    # culled vs unculled on two cameras of the first ring position (GPU images;
+    # the unculled 8-camera frame would hold ~2.5e9 tile entries)
+    ic = img.cpu().numpy()[:2]
+    iu = ctx.render(sc.cameras[:2], tile=tile, precision=prec, use_mlp=False).cpu().numpy()
+    psnrs = [psnr(ic[k], iu[k]) for k in range(2)]
     width = sc.assets[0].mlp.width
     dom, roof = roofline(stage, st, width, prec, sc.assets[0].sh_degree)
     C = len(sc.cameras)
@@ -420,7 +421,7 @@ def main_batched(args):
         "frame_ms_mean": float(np.mean(per)),
         "mlp_queries_per_s": st["queried"] / (stage["cull_mlp"] * 1e-3),
         "gaussians_per_s": st["pairs"] / t_f,
-        "psnr_culled_vs_unculled_db_per_camera": psnrs,
+        "psnr_culled_vs_unculled_db_cameras_0_1": psnrs,
         "in_frustum": st["in_frustum"], "queried": st["queried"], "kept": st["kept"],
         "duplicates": st["duplicates"], "blend_tests": st["blend_tests"], "ms_stage": stage,
         "dominant_kernel": dom, "roofline": roof, "workspace_bytes": st["workspace_bytes"],

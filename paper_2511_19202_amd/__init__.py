@@ -214,6 +214,40 @@ class DeviceAsset:
         return a
 
 
+def torch_allocator(device, blocks: dict):
+    """Allocator callbacks backed by torch's caching allocator; `blocks` keeps
+    the tensors alive by address.  They never raise: ctypes leaves a raising
+    callback's return value undefined, which the library would take for
+    memory.  A failed allocation returns NULL (the library reports E_NOMEM)."""
+    torch = _torch()
+
+    def _alloc(nbytes, user):
+        for attempt in range(2):
+            try:
+                t = torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+                p = t.data_ptr()
+                blocks[p] = t
+                return p
+            except Exception:
+                if attempt == 0 and getattr(device, "type", str(device)) == "cuda":
+                    try:
+                        torch.cuda.empty_cache()
+                    except Exception:
+                        return None
+        return None
+
+    def _free(ptr, user):
+        try:
+            t = blocks.pop(int(ptr or 0), None)
+            if t is not None and t.numel() >= (1 << 30) and t.is_cuda:
+                del t
+                torch.cuda.empty_cache()  # hand large blocks back so a larger buffer can take their place
+        except Exception:
+            pass
+
+    return ALLOC_FN(_alloc), FREE_FN(_free)
+
+
 class Context:
     """One renderer context on a device and torch stream."""
 
@@ -229,18 +263,7 @@ class Context:
         self.device = torch.device("cuda", device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self._blocks = {}
-
-        def _alloc(nbytes, user):
-            t = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
-            p = t.data_ptr()
-            self._blocks[p] = t
-            return p
-
-        def _free(ptr, user):
-            self._blocks.pop(int(ptr or 0), None)
-
-        self._alloc_cb = ALLOC_FN(_alloc)
-        self._free_cb = FREE_FN(_free)
+        self._alloc_cb, self._free_cb = torch_allocator(self.device, self._blocks)
         info = CreateInfo(device, C.c_void_p(self.stream.cuda_stream), Allocator(self._alloc_cb, self._free_cb, None))
         h = C.c_void_p()
         st = self.L.nvgs_create(C.byref(info), C.byref(h))

@@ -64,7 +64,12 @@ struct nvgs_ctx {
   Buf splat, rec_a, rec_b, rec_c, rect, depth_key, ids, ids_tmp, keys_tmp2, pair_of, cnt, dup_off;
   Buf keys, vals, keys_tmp, vals_tmp, hist, hist_part, ranges, tord;  // tord: tile order (4 arrays)
   int64_t cap_keys = 0;  // tile keys (cameras x tiles) the range buffers hold
-  // u32 [0] n_splats, [1] n_dup, [2] overflow flags; u64 at [4] in-frustum, [6] queried, [8] blend tests
+  int64_t cap_hist = 0;  // longest list the sort histograms and scan partials cover
+  int64_t cap_debug = 0; // splats the debug arrays hold
+  // every cap_* is set only once all of its buffers exist at that size and is
+  // reset to 0 when an allocation fails, so no launch sees a missing buffer
+  // u32 [0] n_splats, [1] n_dup, [2] overflow flags; u64 at [4] in-frustum, [6] queried, [8] blend tests,
+  // [10] (splat, tile) entries summed in 64 bits
   // (reset by every frame); across frames: [12] max splats, [13] max tile entries, [14] OR of overflow flags
   Buf counters;
   uint32_t* counters_host = nullptr;
@@ -466,22 +471,38 @@ namespace {
 // Radix histograms and scan partials for the largest sorted or scanned list.
 nvgs_status size_hist(nvgs_ctx* ctx) {
   const int64_t m = std::max({ctx->cap_dup, ctx->cap_splats, ctx->cap_keys, (int64_t)4096});
+  if (m <= ctx->cap_hist) return NVGS_OK;
   if (!ensure(ctx, ctx->hist, 4 * radix_hist_words(m)) ||
-      !ensure(ctx, ctx->hist_part, 4 * scan_partials_needed(radix_hist_words(m)) + 4 * scan_partials_needed(m)))
+      !ensure(ctx, ctx->hist_part, 4 * scan_partials_needed(radix_hist_words(m)) + 4 * scan_partials_needed(m))) {
+    ctx->cap_hist = 0;
     return fail(ctx, NVGS_E_NOMEM, "sort histograms");
+  }
+  ctx->cap_hist = m;
+  return NVGS_OK;
+}
+
+// Debug arrays (KEEP_DEBUG / RECORD_CONTRIB frames) for cap_splats splats.
+nvgs_status size_debug(nvgs_ctx* ctx) {
+  if (ctx->cap_debug >= ctx->cap_splats && ctx->cap_debug > 0) return NVGS_OK;
+  const int64_t cap = ctx->cap_splats;
+  if (!ensure(ctx, ctx->rec_a, 16 * cap) || !ensure(ctx, ctx->rec_b, 16 * cap) ||
+      !ensure(ctx, ctx->rec_c, 16 * cap) || !ensure(ctx, ctx->pair_of, 4 * cap)) {
+    ctx->cap_debug = 0;
+    return fail(ctx, NVGS_E_NOMEM, "debug buffers");
+  }
+  ctx->cap_debug = cap;
   return NVGS_OK;
 }
 
 // Grow-only splat buffers for `need` splats (1/8 headroom when `slack`).
 nvgs_status size_splats(nvgs_ctx* ctx, int64_t need, bool slack) {
-  if (need <= ctx->cap_splats && ctx->rec_a.p) return NVGS_OK;
+  if (need <= ctx->cap_splats && ctx->cap_splats > 0) return NVGS_OK;
   const int64_t cap = std::max<int64_t>(slack ? need + need / 8 : need, 4096);
-  const bool ok = ensure(ctx, ctx->splat, 64 * cap) && ensure(ctx, ctx->rec_a, 16 * cap) && ensure(ctx, ctx->rec_b, 16 * cap) &&
-                  ensure(ctx, ctx->rec_c, 16 * cap) && ensure(ctx, ctx->rect, 16 * cap) &&
+  ctx->cap_splats = 0;
+  const bool ok = ensure(ctx, ctx->splat, 64 * cap) && ensure(ctx, ctx->rect, 16 * cap) &&
                   ensure(ctx, ctx->depth_key, 4 * cap) && ensure(ctx, ctx->ids, 4 * cap) &&
                   ensure(ctx, ctx->ids_tmp, 4 * cap) && ensure(ctx, ctx->keys_tmp2, 4 * cap) &&
-                  ensure(ctx, ctx->pair_of, 4 * cap) && ensure(ctx, ctx->cnt, 4 * cap) &&
-                  ensure(ctx, ctx->dup_off, 4 * cap);
+                  ensure(ctx, ctx->cnt, 4 * cap) && ensure(ctx, ctx->dup_off, 4 * cap);
   if (!ok) return fail(ctx, NVGS_E_NOMEM, "splat buffers");
   ctx->cap_splats = cap;
   return size_hist(ctx);
@@ -489,8 +510,9 @@ nvgs_status size_splats(nvgs_ctx* ctx, int64_t need, bool slack) {
 
 // Grow-only (tile, splat) entry buffers for `need` entries.
 nvgs_status size_dups(nvgs_ctx* ctx, int64_t need, bool slack) {
-  if (need <= ctx->cap_dup && ctx->keys.p) return NVGS_OK;
-  const int64_t cap = std::max<int64_t>(slack ? need + need / 8 : need, 4096);
+  if (need <= ctx->cap_dup && ctx->cap_dup > 0) return NVGS_OK;
+  const int64_t cap = std::min<int64_t>(std::max<int64_t>(slack ? need + need / 8 : need, 4096), UINT32_MAX);
+  ctx->cap_dup = 0;
   const bool ok = ensure(ctx, ctx->keys, 4 * cap) && ensure(ctx, ctx->vals, 4 * cap) &&
                   ensure(ctx, ctx->keys_tmp, 4 * cap) && ensure(ctx, ctx->vals_tmp, 4 * cap);
   if (!ok) return fail(ctx, NVGS_E_NOMEM, "tile entry buffers");
@@ -501,6 +523,7 @@ nvgs_status size_dups(nvgs_ctx* ctx, int64_t need, bool slack) {
 // Tile ranges and launch-order buffers for `nkeys` (camera, tile) keys.
 nvgs_status size_tiles(nvgs_ctx* ctx, int64_t nkeys) {
   if (nkeys <= ctx->cap_keys) return NVGS_OK;
+  ctx->cap_keys = 0;
   if (!ensure(ctx, ctx->ranges, sizeof(uint32_t) * 2 * (size_t)nkeys) ||
       !ensure(ctx, ctx->tord, sizeof(uint32_t) * 4 * (size_t)nkeys))
     return fail(ctx, NVGS_E_NOMEM, "tile ranges");
@@ -554,6 +577,7 @@ nvgs_status enqueue_frame(nvgs_ctx* ctx, hipStream_t st, const Frame& f, bool ea
     if ((s = read_counters(ctx))) return s;
     ns_bound = ctx->counters_host[0];
     if ((s = size_splats(ctx, ns_bound, true))) return s;
+    if (f.debug && (s = size_debug(ctx))) return s;
   }
   const uint32_t* n_splats_dev = counters + 0;
   STAGE_BEGIN(NVGS_STAGE_PROJECT);
@@ -572,7 +596,8 @@ nvgs_status enqueue_frame(nvgs_ctx* ctx, hipStream_t st, const Frame& f, bool ea
   const uint32_t* depth_ids = in_tmp ? P_<uint32_t>(ctx->ids_tmp) : P_<uint32_t>(ctx->ids);
   STAGE_END(NVGS_STAGE_DEPTH_SORT);
   STAGE_BEGIN(NVGS_STAGE_BIN);
-  CK(launch_gather_tiles(depth_ids, P_<uint4>(ctx->rect), n_splats_dev, ns_bound, P_<uint32_t>(ctx->cnt), st));
+  CK(launch_gather_tiles(depth_ids, P_<uint4>(ctx->rect), n_splats_dev, ns_bound, P_<uint32_t>(ctx->cnt),
+                         reinterpret_cast<unsigned long long*>(counters + 10), st));
   CK(launch_scan_u32_dev(P_<uint32_t>(ctx->cnt), P_<uint32_t>(ctx->dup_off), ns_bound, n_splats_dev, counters + 1,
                          P_<uint32_t>(ctx->hist_part), st));
   STAGE_END(NVGS_STAGE_BIN);
@@ -580,6 +605,8 @@ nvgs_status enqueue_frame(nvgs_ctx* ctx, hipStream_t st, const Frame& f, bool ea
   if (eager) {
     if ((s = read_counters(ctx))) return s;
     nd_bound = ctx->counters_host[1];
+    if (reinterpret_cast<const unsigned long long*>(ctx->counters_host + 10)[0] != (unsigned long long)nd_bound)
+      return fail(ctx, NVGS_E_CAPACITY, "more than 2^32 - 1 (splat, tile) entries in one frame");
     if (ms_bin_count) CK(hipEventElapsedTime(ms_bin_count, ev[2 * NVGS_STAGE_BIN], ev[2 * NVGS_STAGE_BIN + 1]));
     if ((s = size_dups(ctx, nd_bound, true))) return s;
     if ((s = size_tiles(ctx, f.nkeys))) return s;
@@ -695,9 +722,13 @@ nvgs_status nvgs_render(nvgs_ctx* ctx, const nvgs_camera* cams, int32_t C, const
     return NVGS_OK;
   }
   // persistent frame
-  if (ctx->cap_splats <= 0 || ctx->cap_dup <= 0 || !ctx->rec_a.p || !ctx->keys.p)
+  if (ctx->cap_splats <= 0 || ctx->cap_dup <= 0)
     return fail(ctx, NVGS_E_STATE, "GRAPH frames need capacities: nvgs_reserve, or one frame without NVGS_RENDER_GRAPH");
   if ((s = size_tiles(ctx, f.nkeys)) || (s = size_hist(ctx))) return s;
+  if (f.debug && (s = size_debug(ctx))) return s;
+  if (ctx->cap_keys < f.nkeys || ctx->cap_hist < std::max({ctx->cap_dup, ctx->cap_splats, ctx->cap_keys}) ||
+      (f.debug && ctx->cap_debug < ctx->cap_splats))
+    return fail(ctx, NVGS_E_STATE, "frame buffers are incomplete after a failed allocation");
   const std::vector<uint64_t> key = {
       (uint64_t)C, (uint64_t)f.W, (uint64_t)f.H, (uint64_t)T, (uint64_t)opts->use_mlp, (uint64_t)opts->precision,
       (uint64_t)opts->flags, (uint64_t)reinterpret_cast<uintptr_t>(rgb),
@@ -875,7 +906,7 @@ nvgs_status nvgs_debug_buffers(nvgs_ctx* ctx, nvgs_debug_view* out) {
     out->n_splats = ctx->last_splats;
     out->n_dup = ctx->last_dup;
   }
-  out->pair = ctx->last_debug ? P_<uint32_t>(ctx->pair_of) : nullptr;
+  out->pair = ctx->last_debug ? P_<uint32_t>(ctx->pair_of) : nullptr;  // debug arrays exist only then
   out->rec_a = ctx->last_debug ? P_<float>(ctx->rec_a) : nullptr;
   out->rec_b = ctx->last_debug ? P_<float>(ctx->rec_b) : nullptr;
   out->rec_c = ctx->last_debug ? P_<float>(ctx->rec_c) : nullptr;

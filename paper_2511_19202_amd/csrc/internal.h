@@ -124,7 +124,7 @@ hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp,
 size_t radix_hist_words(int64_t cap);
 
 hipError_t launch_gather_tiles(const uint32_t* sorted_ids, const uint4* rect, const uint32_t* n_dev, int64_t cap,
-                               uint32_t* out, hipStream_t st);
+                               uint32_t* out, unsigned long long* total, hipStream_t st);
 hipError_t launch_emit(const uint32_t* sorted_ids, const uint4* rect, const uint32_t* dup_off, const uint32_t* n_dev,
                        int64_t cap, const uint32_t* n_dup_dev, int64_t cap_dup, int tiles_x, int n_tiles,
                        uint32_t* keys, uint32_t* vals, uint32_t* overflow, hipStream_t st);

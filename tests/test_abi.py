@@ -76,3 +76,21 @@ def test_null_and_invalid_arguments_are_rejected(so):
     so.nvgs_last_error.restype = ctypes.c_char_p
     so.nvgs_last_error.argtypes = [ctypes.c_void_p]
     assert so.nvgs_last_error(None) == b"null context"
+
+
+def test_allocator_callbacks_return_null_instead_of_raising():
+    """A failed torch allocation inside the allocator callback must reach the
+    library as NULL (a raising ctypes callback returns an undefined value)."""
+    import torch
+    import paper_2511_19202_amd as nvgs
+    blocks = {}
+    alloc, free = nvgs.torch_allocator(torch.device("cpu"), blocks)
+    call_alloc = ctypes.cast(alloc, ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p))
+    call_free = ctypes.cast(free, ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p))
+    p = call_alloc(1024, None)
+    assert p and p in blocks
+    call_free(p, None)
+    assert p not in blocks
+    for _ in range(3):  # far beyond any memory: torch raises, the callback returns NULL
+        assert call_alloc(1 << 62, None) is None
+    call_free(12345, None)  # unknown pointers are ignored
