@@ -68,8 +68,8 @@ struct nvgs_ctx {
   int64_t cap_debug = 0; // splats the debug arrays hold
   // every cap_* is set only once all of its buffers exist at that size and is
   // reset to 0 when an allocation fails, so no launch sees a missing buffer
-  // u32 [0] n_splats, [1] n_dup, [2] overflow flags; u64 at [4] in-frustum, [6] queried, [8] blend tests,
-  // [10] (splat, tile) entries summed in 64 bits
+  // u32 [0] n_splats, [1] n_dup, [2] overflow flags (1 splats, 2 entries, 4 entry offsets wrapped);
+  // u64 at [4] in-frustum, [6] queried, [8] blend tests
   // (reset by every frame); across frames: [12] max splats, [13] max tile entries, [14] OR of overflow flags
   Buf counters;
   uint32_t* counters_host = nullptr;
@@ -596,16 +596,15 @@ nvgs_status enqueue_frame(nvgs_ctx* ctx, hipStream_t st, const Frame& f, bool ea
   const uint32_t* depth_ids = in_tmp ? P_<uint32_t>(ctx->ids_tmp) : P_<uint32_t>(ctx->ids);
   STAGE_END(NVGS_STAGE_DEPTH_SORT);
   STAGE_BEGIN(NVGS_STAGE_BIN);
-  CK(launch_gather_tiles(depth_ids, P_<uint4>(ctx->rect), n_splats_dev, ns_bound, P_<uint32_t>(ctx->cnt),
-                         reinterpret_cast<unsigned long long*>(counters + 10), st));
+  CK(launch_gather_tiles(depth_ids, P_<uint4>(ctx->rect), n_splats_dev, ns_bound, P_<uint32_t>(ctx->cnt), st));
   CK(launch_scan_u32_dev(P_<uint32_t>(ctx->cnt), P_<uint32_t>(ctx->dup_off), ns_bound, n_splats_dev, counters + 1,
-                         P_<uint32_t>(ctx->hist_part), st));
+                         P_<uint32_t>(ctx->hist_part), st, counters + 2));
   STAGE_END(NVGS_STAGE_BIN);
   int64_t nd_bound = ctx->cap_dup;
   if (eager) {
     if ((s = read_counters(ctx))) return s;
     nd_bound = ctx->counters_host[1];
-    if (reinterpret_cast<const unsigned long long*>(ctx->counters_host + 10)[0] != (unsigned long long)nd_bound)
+    if (ctx->counters_host[2] & 4u)
       return fail(ctx, NVGS_E_CAPACITY, "more than 2^32 - 1 (splat, tile) entries in one frame");
     if (ms_bin_count) CK(hipEventElapsedTime(ms_bin_count, ev[2 * NVGS_STAGE_BIN], ev[2 * NVGS_STAGE_BIN + 1]));
     if ((s = size_dups(ctx, nd_bound, true))) return s;

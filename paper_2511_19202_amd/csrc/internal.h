@@ -108,8 +108,9 @@ hipError_t launch_cull_mlp(const AssetDev* assets_dev, const WorkItem* items, in
 
 hipError_t launch_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, uint32_t* partials,
                            hipStream_t st);
+// wrap (nullable): bit value 4 is OR-ed in when the total reaches 2^32
 hipError_t launch_scan_u32_dev(const uint32_t* in, uint32_t* out, int64_t n, const uint32_t* n_dev, uint32_t* total,
-                               uint32_t* partials, hipStream_t st);
+                               uint32_t* partials, hipStream_t st, uint32_t* wrap);
 size_t scan_partials_needed(int64_t n);
 
 hipError_t launch_project(const AssetDev* assets, const SegRec* segs, int32_t n_segs, const int64_t* seg_chunk_base,
@@ -124,7 +125,7 @@ hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp,
 size_t radix_hist_words(int64_t cap);
 
 hipError_t launch_gather_tiles(const uint32_t* sorted_ids, const uint4* rect, const uint32_t* n_dev, int64_t cap,
-                               uint32_t* out, unsigned long long* total, hipStream_t st);
+                               uint32_t* out, hipStream_t st);
 hipError_t launch_emit(const uint32_t* sorted_ids, const uint4* rect, const uint32_t* dup_off, const uint32_t* n_dev,
                        int64_t cap, const uint32_t* n_dup_dev, int64_t cap_dup, int tiles_x, int n_tiles,
                        uint32_t* keys, uint32_t* vals, uint32_t* overflow, hipStream_t st);

@@ -278,27 +278,19 @@ __device__ __forceinline__ int64_t live(const uint32_t* n_dev, int64_t cap) {
   return n_dev ? (int64_t)min((uint64_t)*n_dev, (uint64_t)cap) : cap;
 }
 
-// tile counts in depth order; their sum is also accumulated in 64 bits so a
-// frame with more than 2^32 - 1 entries is detected rather than wrapped
+// tile counts of the splats in depth order
 __global__ void k_gather_tiles(const uint32_t* __restrict__ ids, const uint4* __restrict__ rect,
-                               const uint32_t* __restrict__ n_dev, int64_t cap, uint32_t* __restrict__ out,
-                               unsigned long long* __restrict__ total) {
+                               const uint32_t* __restrict__ n_dev, int64_t cap, uint32_t* __restrict__ out) {
   const int64_t n = live(n_dev, cap);
-  unsigned long long sum = 0;
-  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t c = rect[ids[j]].w;
-    out[j] = c;
-    sum += c;
-  }
-  for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o);
-  if ((threadIdx.x & 63) == 0 && sum) atomicAdd(total, sum);
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
+    out[j] = rect[ids[j]].w;
 }
 
 hipError_t launch_gather_tiles(const uint32_t* sorted_ids, const uint4* rect, const uint32_t* n_dev, int64_t cap,
-                               uint32_t* out, unsigned long long* total, hipStream_t st) {
+                               uint32_t* out, hipStream_t st) {
   if (cap == 0) return hipSuccess;
   unsigned grid = (unsigned)std::min<int64_t>((cap + 255) / 256, 65536);
-  hipLaunchKernelGGL(k_gather_tiles, dim3(grid), dim3(256), 0, st, sorted_ids, rect, n_dev, cap, out, total);
+  hipLaunchKernelGGL(k_gather_tiles, dim3(grid), dim3(256), 0, st, sorted_ids, rect, n_dev, cap, out);
   return hipGetLastError();
 }
 
@@ -362,10 +354,8 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st) {
 // [14] OR of the overflow flags (word [2] of the per-frame counters).
 __global__ void k_watermark(uint32_t* __restrict__ c) {
   if (threadIdx.x == 0) {
-    const unsigned long long entries = reinterpret_cast<const unsigned long long*>(c + 10)[0];
-    if (entries >> 32) c[2] |= 4u;  // the 32-bit entry offsets wrapped
     c[12] = max(c[12], c[0]);
-    c[13] = (uint32_t)max((unsigned long long)c[13], min(entries, 0xffffffffull));
+    c[13] = (c[2] & 4u) ? 0xffffffffu : max(c[13], c[1]);  // 4: the 32-bit entry offsets wrapped
     c[14] |= c[2];
   }
 }

@@ -35,26 +35,43 @@ __device__ __forceinline__ int64_t scan_n(int64_t n, const uint32_t* n_dev) {
   return n_dev ? (int64_t)min((uint64_t)*n_dev, (uint64_t)n) : n;
 }
 
+// wrap: if given, bit 2 (value 4) is set when a sum reaches 2^32 (the
+// 32-bit offsets would wrap)
 __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* __restrict__ in, int64_t n_cap,
                                                               const uint32_t* __restrict__ n_dev,
-                                                              uint32_t* __restrict__ partials) {
+                                                              uint32_t* __restrict__ partials,
+                                                              uint32_t* __restrict__ wrap) {
   __shared__ uint32_t s_wave[kScanThreads / 64];
+  __shared__ unsigned long long s_wide[kScanThreads / 64];
   const int64_t n = scan_n(n_cap, n_dev);
   const int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * kScanItems;
-  uint32_t s = 0;
+  unsigned long long s = 0;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k)
     if (base + k < n) s += in[base + k];
   uint32_t tot;
-  block_exclusive_scan(s, s_wave, &tot);
+  block_exclusive_scan((uint32_t)s, s_wave, &tot);
+  if (wrap) {
+    unsigned long long w = s;
+    for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o);
+    if ((threadIdx.x & 63) == 0) s_wide[threadIdx.x >> 6] = w;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned long long b = 0;
+      for (int q = 0; q < kScanThreads / 64; ++q) b += s_wide[q];
+      if (b >> 32) atomicOr(wrap, 4u);
+    }
+  }
   if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
 
 // single work-group: exclusive scan of the block partials, total to *total
 __global__ __launch_bounds__(kScanThreads) void k_scan_partials(uint32_t* __restrict__ partials, int64_t nb,
-                                                                uint32_t* __restrict__ total) {
+                                                                uint32_t* __restrict__ total,
+                                                                uint32_t* __restrict__ wrap) {
   __shared__ uint32_t s_wave[kScanThreads / 64];
   uint32_t carry = 0;
+  unsigned long long wide = 0;
   for (int64_t off = 0; off < nb; off += kScanBlock) {
     const int64_t base = off + threadIdx.x * kScanItems;
     uint32_t v[kScanItems];
@@ -72,8 +89,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_partials(uint32_t* __rest
       pre += v[k];
     }
     carry += tot;
+    wide += tot;
   }
   if (threadIdx.x == 0 && total) *total = carry;
+  if (threadIdx.x == 0 && wrap && (wide >> 32)) atomicOr(wrap, 4u);
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* in, uint32_t* out,  // may alias
@@ -101,21 +120,21 @@ size_t scan_partials_needed(int64_t n) { return (size_t)((n + kScanBlock - 1) / 
 
 // n: capacity (grid size); if n_dev is given the live count is min(*n_dev, n)
 hipError_t launch_scan_u32_dev(const uint32_t* in, uint32_t* out, int64_t n, const uint32_t* n_dev, uint32_t* total,
-                               uint32_t* partials, hipStream_t st) {
+                               uint32_t* partials, hipStream_t st, uint32_t* wrap) {
   int64_t nb = (n + kScanBlock - 1) / kScanBlock;
   if (nb == 0) {  // empty input: the partials kernel alone writes total = 0
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanThreads), 0, st, partials, (int64_t)0, total);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanThreads), 0, st, partials, (int64_t)0, total, wrap);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, st, in, n, n_dev, partials);
-  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanThreads), 0, st, partials, nb, total);
+  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, st, in, n, n_dev, partials, wrap);
+  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanThreads), 0, st, partials, nb, total, wrap);
   hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kScanThreads), 0, st, in, out, n, n_dev, partials);
   return hipGetLastError();
 }
 
 hipError_t launch_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, uint32_t* partials,
                            hipStream_t st) {
-  return launch_scan_u32_dev(in, out, n, nullptr, total, partials, st);
+  return launch_scan_u32_dev(in, out, n, nullptr, total, partials, st, nullptr);
 }
 
 }  // namespace nvgs

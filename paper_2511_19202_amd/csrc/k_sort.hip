@@ -7,7 +7,9 @@
 // exclusive scan over all (digit, block) counts, and a scatter kernel.  The
 // scatter ranks keys inside a block with 64-lane ballots (eight ballots give
 // the set of lanes sharing a digit), so the rank is exact and in input order
-// without atomics deciding the order.
+// without atomics deciding the order; the block's keys are then reordered by
+// digit in LDS so that consecutive threads write consecutive addresses of
+// each digit's output run.
 #include <algorithm>
 #include <utility>
 
@@ -19,6 +21,7 @@ constexpr int kSortThreads = 256;
 constexpr int kSortWaves = kSortThreads / 64;
 constexpr int kPerWave = kSortBlock / kSortWaves;  // 1024 keys per wave
 constexpr int kRounds = kPerWave / 64;             // 16 rounds of 64
+static_assert(kSortThreads == 256, "the scatter gives one thread to each of the 256 digits");
 
 __device__ __forceinline__ int64_t live_n(const uint32_t* n_dev, int64_t cap) {
   return n_dev ? (int64_t)min((uint64_t)*n_dev, (uint64_t)cap) : cap;
@@ -49,12 +52,18 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, uint32_t* __restrict__ keys_out,
     uint32_t* __restrict__ vals_out, const uint32_t* __restrict__ n_dev, int64_t cap, int shift, uint32_t dmask,
     int nbits, const uint32_t* __restrict__ offs, int64_t nblocks, int iota_vals) {
-  __shared__ uint32_t s_cnt[kSortWaves][256];
+  __shared__ uint32_t s_cnt[kSortWaves][256];  // per-wave digit counts, then per-wave digit bases in the block
+  __shared__ uint32_t s_start[256];            // first block-local position of each digit
+  __shared__ uint32_t s_glob[256];             // global position of each digit's first key of this block
+  __shared__ uint32_t s_wsum[kSortWaves];
+  __shared__ uint32_t s_k[kSortBlock];
+  __shared__ uint32_t s_v[kSortBlock];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int d = threadIdx.x; d < kSortWaves * 256; d += kSortThreads) (&s_cnt[0][0])[d] = 0;
   __syncthreads();
   const int64_t n = live_n(n_dev, cap);
-  const int64_t base = (int64_t)blockIdx.x * kSortBlock + wave * kPerWave;
+  const int64_t block0 = (int64_t)blockIdx.x * kSortBlock;
+  const int64_t base = block0 + wave * kPerWave;
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   uint32_t key[kRounds], local[kRounds];
   // phase 1: rank every key among the equal digits of this wave, in order
@@ -76,25 +85,50 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     if (ok && (peers >> lane) == 1ull) s_cnt[wave][d] = before + (uint32_t)__popcll(peers);
   }
   __syncthreads();
-  // phase 2: per digit, global block offset plus the counts of earlier waves
-  for (int d = threadIdx.x; d < 256; d += kSortThreads) {
-    uint32_t run = offs[(int64_t)d * nblocks + blockIdx.x];
-    for (int w = 0; w < kSortWaves; ++w) {
-      uint32_t c = s_cnt[w][d];
-      s_cnt[w][d] = run;
-      run += c;
-    }
+  // phase 2: one thread per digit: block total, per-wave bases, global base;
+  // then an exclusive scan of the digit totals gives each digit's block start
+  const int d = threadIdx.x;  // kSortThreads == 256 digits
+  uint32_t tot = 0;
+#pragma unroll
+  for (int w = 0; w < kSortWaves; ++w) {
+    const uint32_t c = s_cnt[w][d];
+    s_cnt[w][d] = tot;
+    tot += c;
   }
+  s_glob[d] = offs[(int64_t)d * nblocks + blockIdx.x];
+  uint32_t x = tot;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) s_wsum[wave] = x;
   __syncthreads();
+  uint32_t wbase = 0;
+#pragma unroll
+  for (int w = 0; w < kSortWaves; ++w) wbase += (w < wave) ? s_wsum[w] : 0u;
+  s_start[d] = wbase + x - tot;
+  __syncthreads();
+  // phase 3: keys and values into LDS in (digit, input) order
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
     const int64_t idx = base + r * 64 + lane;
     if (idx < n) {
-      const uint32_t d = (key[r] >> shift) & dmask;
-      const uint32_t pos = s_cnt[wave][d] + local[r];
-      keys_out[pos] = key[r];
-      vals_out[pos] = iota_vals ? (uint32_t)idx : vals_in[idx];
+      const uint32_t dg = (key[r] >> shift) & dmask;
+      const uint32_t p = s_start[dg] + s_cnt[wave][dg] + local[r];
+      s_k[p] = key[r];
+      s_v[p] = iota_vals ? (uint32_t)idx : vals_in[idx];
     }
+  }
+  __syncthreads();
+  // phase 4: consecutive threads write consecutive positions of each digit run
+  const int cnt = (int)min<int64_t>(kSortBlock, n - block0);
+  for (int p = threadIdx.x; p < cnt; p += kSortThreads) {
+    const uint32_t k = s_k[p];
+    const uint32_t dg = (k >> shift) & dmask;
+    const uint32_t pos = s_glob[dg] + (uint32_t)p - s_start[dg];
+    keys_out[pos] = k;
+    vals_out[pos] = s_v[p];
   }
 }
 
@@ -125,7 +159,7 @@ hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp,
     const uint32_t dmask = (1u << nbits) - 1u;
     hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kSortThreads), 0, st, kin, n_dev, cap, shift, dmask,
                        hist, nb);
-    (void)launch_scan_u32_dev(hist, hist, 256 * nb, nullptr, nullptr, partials, st);
+    (void)launch_scan_u32_dev(hist, hist, 256 * nb, nullptr, nullptr, partials, st, nullptr);
     hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(kSortThreads), 0, st, kin, vin, kout, vout, n_dev,
                        cap, shift, dmask, nbits, hist, nb, (first && iota_vals) ? 1 : 0);
     first = false;
