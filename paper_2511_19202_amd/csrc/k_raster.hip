@@ -10,8 +10,9 @@
 //  * Footprints are the exact AABB of the alpha = 1/255 level set of the
 //    splat (not a 3-sigma box), widened slightly, so the image does not
 //    depend on the tile size.
-//  * k_blend stages batches of 256 splats in LDS and stops a tile as soon as
-//    every pixel of it has stopped.
+//  * k_blend stages batches of splats (one per thread) in LDS, fetching the
+//    next batch while compositing the current one, and stops a tile as soon
+//    as every pixel of it has stopped.
 #include <algorithm>
 #include <utility>
 
@@ -425,8 +426,7 @@ __global__ __launch_bounds__(T == 8 ? 64 : 256) void k_blend(
   constexpr int NT = T == 8 ? 64 : 256;  // threads
   constexpr int NB = T * T / 64;         // 8x8 pixel blocks per tile
   constexpr int BPW = NB / (NT / 64);    // blocks per wave (1, 1, 4)
-  constexpr int BATCH = 256;
-  constexpr int LPT = BATCH / NT;        // splats each thread stages per batch
+  constexpr int BATCH = NT;              // one staged splat per thread per batch
   __shared__ float4 s_g[BATCH];  // u, v, A, B   (A, B, C: conic scaled by -log2(e)/2, -log2(e), -log2(e)/2)
   __shared__ float4 s_h[BATCH];  // C, opacity, log2 bound, r
   __shared__ float2 s_c[BATCH];  // g, b
@@ -440,8 +440,6 @@ __global__ __launch_bounds__(T == 8 ? 64 : 256) void k_blend(
   float px[BPW], py[BPW], Tr[BPW], cr[BPW], cg[BPW], cb[BPW];
   bool done[BPW];
   uint32_t stop[BPW];  // list position at which the pixel stopped (end if it never did)
-  uint32_t b0k = start;  // list position of the current batch
-  int alive = 0;
 #pragma unroll
   for (int j = 0; j < BPW; ++j) {
     stop[j] = end;
@@ -452,120 +450,87 @@ __global__ __launch_bounds__(T == 8 ? 64 : 256) void k_blend(
     Tr[j] = 1.f;
     cr[j] = cg[j] = cb[j] = 0.f;
     done[j] = !(x < W && y < H);
-    alive += done[j] ? 0 : 1;
   }
-  float4 pa[LPT], pb[LPT], pc[LPT];
-  uint32_t pp[LPT];
-  auto fetch = [&](uint32_t b0) {
-#pragma unroll
-    for (int i = 0; i < LPT; ++i) {
-      const uint32_t idx = b0 + t + i * NT;
-      if (idx < end) {
-        const float4* r = splat + 4 * (int64_t)ids[idx];
-        pa[i] = r[0];
-        pb[i] = r[1];
-        pc[i] = r[2];
-        if (RECORD) pp[i] = __float_as_uint(r[3].x);
-      }
-    }
-  };
-  // composite up to 4 splats (batch slots ks[0..ng), wave-uniform) into pixel
-  // block j: the four alphas are independent of the transmittance and are
-  // evaluated together; only the short T / colour update is sequential.
-  auto blend_group = [&](int j, const int (&ks)[4], int ng) {
-    float al[4];
-    bool ok[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const float4 g = s_g[ks[u]];
-      const float4 h = s_h[ks[u]];
-      const float dx = px[j] - g.x, dy = py[j] - g.y;
-      const float pw = dx * fmaf(g.z, dx, g.w * dy) + h.x * dy * dy;
-      al[u] = fminf(kAlphaMax, h.y * __builtin_amdgcn_exp2f(pw));
-      ok[u] = u < ng && pw >= h.z && pw <= 0.f && al[u] >= kAlphaMin;
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      if (ok[u] && !done[j]) {
-        const float Tn = Tr[j] * (1.f - al[u]);
-        if (Tn < kTMin) {
-          done[j] = true;
-          --alive;
-          stop[j] = b0k + ks[u];
-        } else {
-          const float2 c = s_c[ks[u]];
-          const float w = al[u] * Tr[j];
-          cr[j] = fmaf(w, s_h[ks[u]].w, cr[j]);
-          cg[j] = fmaf(w, c.x, cg[j]);
-          cb[j] = fmaf(w, c.y, cb[j]);
-          if (RECORD) atomicMax(contrib + s_p[ks[u]], __float_as_uint(w));
-          Tr[j] = Tn;
-        }
-      }
-    }
-  };
-  // composite splat k of the batch into pixel block j (per-lane predication)
-  auto blend_one = [&](int j, int k, const float4& g, const float4& h) {
+  // the next batch's record of this thread, fetched while the current one is composited
+  float4 qa = make_float4(0.f, 0.f, 0.f, 0.f), qb = qa, qc = qa;
+  uint32_t qp = 0;
+  if (start + t < end) {
+    const float4* r = splat + 4 * (int64_t)ids[start + t];
+    qa = r[0];
+    qb = r[1];
+    qc = r[2];
+    if (RECORD) qp = __float_as_uint(r[3].x);
+  }
+  uint32_t b0k = start;
+  // composite staged splat k into pixel block j.  Branch-free: a fragment that
+  // is skipped (outside the 1/255 level set, alpha < 1/255, pixel stopped)
+  // contributes weight 0; one whose blend would take T below 1e-4 stops the
+  // pixel instead (Sec. 4.1).
+  auto step = [&](int j, int k) {
+    const float4 g = s_g[k];
+    const float4 h = s_h[k];
+    const float2 c = s_c[k];
     const float dx = px[j] - g.x, dy = py[j] - g.y;
     const float pw = dx * fmaf(g.z, dx, g.w * dy) + h.x * dy * dy;
-    if (done[j] || pw < h.z || pw > 0.f) return;
     const float al = fminf(kAlphaMax, h.y * __builtin_amdgcn_exp2f(pw));
-    if (al < kAlphaMin) return;
+    const bool ok = !done[j] && pw >= h.z && pw <= 0.f && al >= kAlphaMin;
     const float Tn = Tr[j] * (1.f - al);
-    if (Tn < kTMin) {
-      done[j] = true;
-      --alive;
-      stop[j] = b0k + k;
-      return;
-    }
-    const float2 c = s_c[k];
-    const float w = al * Tr[j];
+    const bool halt = ok && Tn < kTMin;
+    const bool take = ok && !halt;
+    const float w = take ? al * Tr[j] : 0.f;
     cr[j] = fmaf(w, h.w, cr[j]);
     cg[j] = fmaf(w, c.x, cg[j]);
     cb[j] = fmaf(w, c.y, cb[j]);
-    if (RECORD) atomicMax(contrib + s_p[k], __float_as_uint(w));
-    Tr[j] = Tn;
+    Tr[j] = take ? Tn : Tr[j];
+    stop[j] = halt ? b0k + (uint32_t)k : stop[j];
+    done[j] = done[j] || halt;
+    if (RECORD && take) atomicMax(contrib + s_p[k], __float_as_uint(w));
   };
-  if (start < end) fetch(start);
   for (uint32_t b0 = start; b0 < end; b0 += BATCH) {
-    if (__syncthreads_count(alive > 0) == 0) break;  // also: the previous batch is consumed
-    const uint32_t cnt = min((uint32_t)BATCH, end - b0);
-    b0k = b0;
+    bool any = false;
 #pragma unroll
-    for (int i = 0; i < LPT; ++i) {
-      const int k = t + i * NT;
-      if (k < (int)cnt) {
-        s_g[k] = pa[i];
-        s_h[k] = pb[i];
-        s_c[k] = make_float2(pc[i].x, pc[i].y);
-        if (T != 8) {
-          // blocks touched by the footprint box (same widening as the tile rectangle)
-          const float wx = 1e-4f * pc[i].z + 1e-3f, wy = 1e-4f * pc[i].w + 1e-3f;
-          const float x0 = pa[i].x - pc[i].z - wx - (float)(tx * T) - 0.5f;  // pc: g, b, ex, ey
-          const float x1 = pa[i].x + pc[i].z + wx - (float)(tx * T) - 0.5f;
-          const float y0 = pa[i].y - pc[i].w - wy - (float)(ty * T) - 0.5f;
-          const float y1 = pa[i].y + pc[i].w + wy - (float)(ty * T) - 0.5f;
-          const int bx0 = max(0, (int)floorf(x0 * 0.125f)), bx1 = min(T / 8 - 1, (int)floorf(x1 * 0.125f));
-          const int by0 = max(0, (int)floorf(y0 * 0.125f)), by1 = min(T / 8 - 1, (int)floorf(y1 * 0.125f));
-          uint32_t m = 0;
-          for (int by = by0; by <= by1; ++by)
-            for (int bx = bx0; bx <= bx1; ++bx) m |= 1u << (by * (T / 8) + bx);
-          s_ov[k] = m;
-        }
-        if (RECORD) s_p[k] = pp[i];
+    for (int j = 0; j < BPW; ++j) any |= !done[j];
+    if (__syncthreads_count(any) == 0) break;  // also: the previous batch is consumed
+    const int cnt = (int)min((uint32_t)BATCH, end - b0);
+    b0k = b0;
+    if (t < cnt) {
+      s_g[t] = qa;
+      s_h[t] = qb;
+      s_c[t] = make_float2(qc.x, qc.y);
+      if (T != 8) {
+        // blocks touched by the footprint box (same widening as the tile rectangle); qc = g, b, ex, ey
+        const float wx = 1e-4f * qc.z + 1e-3f, wy = 1e-4f * qc.w + 1e-3f;
+        const float x0 = qa.x - qc.z - wx - (float)(tx * T) - 0.5f;
+        const float x1 = qa.x + qc.z + wx - (float)(tx * T) - 0.5f;
+        const float y0 = qa.y - qc.w - wy - (float)(ty * T) - 0.5f;
+        const float y1 = qa.y + qc.w + wy - (float)(ty * T) - 0.5f;
+        const int bx0 = max(0, (int)floorf(x0 * 0.125f)), bx1 = min(T / 8 - 1, (int)floorf(x1 * 0.125f));
+        const int by0 = max(0, (int)floorf(y0 * 0.125f)), by1 = min(T / 8 - 1, (int)floorf(y1 * 0.125f));
+        uint32_t m = 0;
+        for (int by = by0; by <= by1; ++by)
+          for (int bx = bx0; bx <= bx1; ++bx) m |= 1u << (by * (T / 8) + bx);
+        s_ov[t] = m;
       }
+      if (RECORD) s_p[t] = qp;
     }
     __syncthreads();
-    if (b0 + BATCH < end) fetch(b0 + BATCH);  // overlaps the compositing below
+    if (b0 + BATCH + t < end) {  // overlaps the compositing below
+      const float4* r = splat + 4 * (int64_t)ids[b0 + BATCH + t];
+      qa = r[0];
+      qb = r[1];
+      qc = r[2];
+      if (RECORD) qp = __float_as_uint(r[3].x);
+    }
 #pragma unroll
     for (int j = 0; j < BPW; ++j) {
       if (__ballot(!done[j]) == 0) continue;
       if (T == 8) {
         // every listed splat touches the tile
-        for (int k = 0; k < (int)cnt; k += 4) {
-          const int ks[4] = {k, min(k + 1, (int)cnt - 1), min(k + 2, (int)cnt - 1), min(k + 3, (int)cnt - 1)};
-          blend_group(j, ks, min(4, (int)cnt - k));
-          if ((k & 15) == 12 && __ballot(!done[j]) == 0) break;
+        for (int k = 0; k < cnt; k += 8) {
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (k + u < cnt) step(j, k + u);
+          if (__ballot(!done[j]) == 0) break;
         }
       } else {
         // splats whose box touches this wave's block, as 64-bit ballot sets
@@ -574,25 +539,15 @@ __global__ __launch_bounds__(T == 8 ? 64 : 256) void k_blend(
 #pragma unroll
         for (int c = 0; c < BATCH / 64; ++c) {
           const int k = c * 64 + lane;
-          set[c] = __ballot(k < (int)cnt && ((s_ov[k] >> blk) & 1u));
+          set[c] = __ballot(k < cnt && ((s_ov[k] >> blk) & 1u));
         }
 #pragma unroll
         for (int c = 0; c < BATCH / 64; ++c) {
           uint64_t m = set[c];
-          if (!m) continue;
-          int k = c * 64 + __builtin_ctzll(m);
-          m &= m - 1;
-          float4 g = s_g[k], h = s_h[k];
-          while (true) {
-            const bool more = m != 0;
-            const int kn = more ? c * 64 + __builtin_ctzll(m) : k;
+          while (m) {
+            const int k = c * 64 + __builtin_ctzll(m);
             m &= m - 1;
-            const float4 gn = s_g[kn], hn = s_h[kn];
-            blend_one(j, k, g, h);
-            if (!more) break;
-            k = kn;
-            g = gn;
-            h = hn;
+            step(j, k);
           }
           if (__ballot(!done[j]) == 0) break;
         }
