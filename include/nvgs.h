@@ -133,6 +133,11 @@ typedef struct nvgs_render_opts {
   float* contrib;    /* device [C][P] (P = pairs per camera, instance-major) or NULL;
                         with RECORD_CONTRIB the max alpha*T of every blended fragment
                         of each pair is max-accumulated into it (caller zero-fills) */
+  int32_t split_len; /* tile lists longer than this are composited in chunks of at most
+                        this many entries by separate work-groups, which equals the
+                        sequential composite up to rounding (the association of the
+                        transmittance products and colour sums); 0: default 2048;
+                        < 0: never split (bit-identical across tile sizes); else >= 64 */
 } nvgs_render_opts;
 
 /* Stages timed with HIP events on the context stream (ms_stage index). */

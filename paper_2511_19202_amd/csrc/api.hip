@@ -18,6 +18,9 @@ struct Buf {
   size_t bytes = 0;
 };
 
+constexpr int kCounters = 24;       // u32 words of the frame counters
+constexpr int kSplitDefault = 2048; // tile-list entries per compositing chunk
+
 }  // namespace
 
 struct nvgs_ctx {
@@ -63,13 +66,16 @@ struct nvgs_ctx {
   int64_t cap_splats = 0, cap_dup = 0;
   Buf splat, rec_a, rec_b, rec_c, rect, depth_key, ids, ids_tmp, keys_tmp2, pair_of, cnt, dup_off;
   Buf keys, vals, keys_tmp, vals_tmp, hist, hist_part, ranges, tord;  // tord: tile order (4 arrays)
+  Buf tsplit, citems, prodb, partb;  // long-list split: per-position counts and offsets, items, chunk products / records
+  int64_t cap_items = 0, cap_split_px = 0;  // items; split slots x pixels per tile
   int64_t cap_keys = 0;  // tile keys (cameras x tiles) the range buffers hold
   int64_t cap_hist = 0;  // longest list the sort histograms and scan partials cover
   int64_t cap_debug = 0; // splats the debug arrays hold
   // every cap_* is set only once all of its buffers exist at that size and is
   // reset to 0 when an allocation fails, so no launch sees a missing buffer
-  // u32 [0] n_splats, [1] n_dup, [2] overflow flags (1 splats, 2 entries, 4 entry offsets wrapped);
-  // u64 at [4] in-frustum, [6] queried, [8] blend tests
+  // u32 [0] n_splats, [1] n_dup, [2] overflow flags (1 splats, 2 entries, 4 entry offsets wrapped,
+  // 8 compositing items); u64 at [4] in-frustum, [6] queried, [8] blend tests; [16] compositing items,
+  // [17] split-chunk slots (written by their scans every frame)
   // (reset by every frame); across frames: [12] max splats, [13] max tile entries, [14] OR of overflow flags
   Buf counters;
   uint32_t* counters_host = nullptr;
@@ -255,7 +261,8 @@ nvgs_status upload_cams(nvgs_ctx* ctx, const nvgs_camera* cams, int C) {
 }
 
 nvgs_status read_counters(nvgs_ctx* ctx) {
-  CK(hipMemcpyAsync(ctx->counters_host, ctx->counters.p, sizeof(uint32_t) * 16, hipMemcpyDeviceToHost, ctx->stream));
+  CK(hipMemcpyAsync(ctx->counters_host, ctx->counters.p, sizeof(uint32_t) * kCounters, hipMemcpyDeviceToHost,
+                    ctx->stream));
   CK(hipStreamSynchronize(ctx->stream));
   return NVGS_OK;
 }
@@ -293,15 +300,15 @@ nvgs_status nvgs_create(const nvgs_create_info* info, nvgs_ctx** out) {
   ctx->device = info->device;
   ctx->stream = reinterpret_cast<hipStream_t>(info->stream);
   ctx->alloc = info->allocator;
-  bool ok = hipHostMalloc(reinterpret_cast<void**>(&ctx->counters_host), 16 * sizeof(uint32_t),
+  bool ok = hipHostMalloc(reinterpret_cast<void**>(&ctx->counters_host), kCounters * sizeof(uint32_t),
                           hipHostMallocDefault) == hipSuccess;
   for (int e = 0; e < 2 * NVGS_NUM_STAGES && ok; ++e) ok = hipEventCreate(&ctx->ev[e]) == hipSuccess;
   for (int e = 0; e < 2 && ok; ++e) ok = hipEventCreate(&ctx->gev[e]) == hipSuccess;
   for (int e = 0; e < nvgs_ctx::kRing && ok; ++e)
     ok = hipEventCreateWithFlags(&ctx->ring_ev[e], hipEventDisableTiming) == hipSuccess;
   ok = ok && hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) == hipSuccess;
-  ok = ok && ensure(ctx, ctx->counters, 16 * sizeof(uint32_t)) &&
-       launch_fill_u32(P_<uint32_t>(ctx->counters), 0u, 16, ctx->stream) == hipSuccess;
+  ok = ok && ensure(ctx, ctx->counters, kCounters * sizeof(uint32_t)) &&
+       launch_fill_u32(P_<uint32_t>(ctx->counters), 0u, kCounters, ctx->stream) == hipSuccess;
   if (!ok) {
     nvgs_destroy(ctx);
     return NVGS_E_DEVICE;
@@ -319,6 +326,7 @@ void nvgs_destroy(nvgs_ctx* ctx) {
                 &ctx->chunk_off, &ctx->scan_part, &ctx->cam_dev, &ctx->splat, &ctx->rec_a, &ctx->rec_b, &ctx->rec_c, &ctx->rect,
                 &ctx->depth_key, &ctx->ids, &ctx->ids_tmp, &ctx->keys_tmp2, &ctx->pair_of, &ctx->cnt, &ctx->dup_off,
                 &ctx->keys, &ctx->vals, &ctx->keys_tmp, &ctx->vals_tmp, &ctx->hist, &ctx->hist_part, &ctx->ranges, &ctx->tord,
+                &ctx->tsplit, &ctx->citems, &ctx->prodb, &ctx->partb,
                 &ctx->counters};
   for (Buf* b : all) release(ctx, *b);
   for (Buf& b : ctx->op_bufs) release(ctx, b);
@@ -531,8 +539,28 @@ nvgs_status size_tiles(nvgs_ctx* ctx, int64_t nkeys) {
   return size_hist(ctx);
 }
 
+// Compositing items and split-chunk buffers for nkeys tiles of T x T pixels
+// and the current entry capacity.
+nvgs_status size_items(nvgs_ctx* ctx, int64_t nkeys, int T, int split_len) {
+  const int64_t per = split_len > 0 ? ctx->cap_dup / split_len : 0;
+  const int64_t cap_items = nkeys + per + 1;
+  const int64_t cap_split_px = split_len > 0 ? (2 * per + 2) * (int64_t)T * T : 0;
+  if (cap_items <= ctx->cap_items && cap_split_px <= ctx->cap_split_px && ctx->tsplit.bytes >= 16 * (size_t)nkeys)
+    return NVGS_OK;
+  ctx->cap_items = 0;
+  ctx->cap_split_px = 0;
+  if (!ensure(ctx, ctx->tsplit, 16 * (size_t)nkeys) || !ensure(ctx, ctx->citems, 8 * (size_t)cap_items) ||
+      !ensure(ctx, ctx->prodb, 4 * (size_t)std::max<int64_t>(cap_split_px, 1)) ||
+      !ensure(ctx, ctx->partb, 16 * (size_t)std::max<int64_t>(cap_split_px, 1)))
+    return fail(ctx, NVGS_E_NOMEM, "compositing items");
+  ctx->cap_items = cap_items;
+  ctx->cap_split_px = cap_split_px;
+  return NVGS_OK;
+}
+
 struct Frame {
   int C, W, H, T, tiles_x, tiles_y, n_tiles;
+  int split_len;  // <= 0: no split
   int64_t nkeys;
   bool record, debug, count_tests;
   const nvgs_render_opts* opts;
@@ -609,6 +637,7 @@ nvgs_status enqueue_frame(nvgs_ctx* ctx, hipStream_t st, const Frame& f, bool ea
     if (ms_bin_count) CK(hipEventElapsedTime(ms_bin_count, ev[2 * NVGS_STAGE_BIN], ev[2 * NVGS_STAGE_BIN + 1]));
     if ((s = size_dups(ctx, nd_bound, true))) return s;
     if ((s = size_tiles(ctx, f.nkeys))) return s;
+    if ((s = size_items(ctx, f.nkeys, f.T, f.split_len))) return s;
   }
   const uint32_t* n_dup_dev = counters + 1;
   STAGE_BEGIN(NVGS_STAGE_BIN);
@@ -632,9 +661,25 @@ nvgs_status enqueue_frame(nvgs_ctx* ctx, hipStream_t st, const Frame& f, bool ea
   CK(launch_radix_sort(tk, tk + nk, tk + 2 * nk, tk + 3 * nk, nullptr, nk, 0, 5, 0, P_<uint32_t>(ctx->hist),
                        P_<uint32_t>(ctx->hist_part), &in_tmp3, st));
   const uint32_t* tile_order = in_tmp3 ? tk + 3 * nk : tk + nk;
+  // compositing items: long lists split into chunks
+  uint32_t* ts = P_<uint32_t>(ctx->tsplit);
+  CK(launch_split_items(P_<uint32_t>(ctx->ranges), tile_order, nk, f.split_len, ts, ts + nk, ts + 2 * nk, ts + 3 * nk,
+                        counters + 16, counters + 17, P_<uint2>(ctx->citems), ctx->cap_items,
+                        P_<uint32_t>(ctx->hist_part), counters + 2, st));
   STAGE_END(NVGS_STAGE_TILE_SORT);
   STAGE_BEGIN(NVGS_STAGE_BLEND);
-  CK(launch_blend(P_<uint32_t>(ctx->ranges), tile_order, sids, P_<float4>(ctx->splat), C, f.W, f.H, f.T, f.tiles_x,
+  BlendItems bi{};
+  bi.split_len = f.split_len;
+  bi.order = tile_order;
+  bi.nch = ts;
+  bi.split_off = ts + 3 * nk;
+  bi.items = P_<uint2>(ctx->citems);
+  bi.n_items = counters + 16;
+  bi.cap_items = ctx->cap_items;
+  bi.cap_split = f.split_len > 0 ? ctx->cap_split_px / ((int64_t)f.T * f.T) : 0;
+  bi.prod = P_<float>(ctx->prodb);
+  bi.part = P_<float4>(ctx->partb);
+  CK(launch_blend(bi, P_<uint32_t>(ctx->ranges), sids, P_<float4>(ctx->splat), f.W, f.H, f.T, f.tiles_x,
                   f.tiles_y, opts->bg[0], opts->bg[1], opts->bg[2], f.rgb, f.record ? opts->contrib : nullptr,
                   f.count_tests ? reinterpret_cast<unsigned long long*>(counters + 8) : nullptr, st));
   STAGE_END(NVGS_STAGE_BLEND);
@@ -677,6 +722,7 @@ nvgs_status nvgs_render(nvgs_ctx* ctx, const nvgs_camera* cams, int32_t C, const
   if (T != 8 && T != 16 && T != 32) return fail(ctx, NVGS_E_INVALID, "tile must be 8, 16 or 32");
   if (opts->precision < NVGS_PREC_FP32 || opts->precision > NVGS_PREC_FP8)
     return fail(ctx, NVGS_E_INVALID, "bad precision");
+  if (opts->split_len > 0 && opts->split_len < 64) return fail(ctx, NVGS_E_INVALID, "split_len must be 0, < 0 or >= 64");
   const bool record = (opts->flags & NVGS_RENDER_RECORD_CONTRIB) != 0;
   if (record && !opts->contrib) return fail(ctx, NVGS_E_INVALID, "RECORD_CONTRIB needs opts->contrib");
   const bool graph = (opts->flags & NVGS_RENDER_GRAPH) != 0;
@@ -695,6 +741,7 @@ nvgs_status nvgs_render(nvgs_ctx* ctx, const nvgs_camera* cams, int32_t C, const
   f.nkeys = (int64_t)C * f.n_tiles;
   if (f.nkeys >= ((int64_t)1 << 31)) return fail(ctx, NVGS_E_INVALID, "too many tiles");
   f.record = record;
+  f.split_len = opts->split_len == 0 ? kSplitDefault : (opts->split_len < 0 ? 0 : opts->split_len);
   f.debug = record || (opts->flags & NVGS_RENDER_KEEP_DEBUG);
   f.count_tests = stats != nullptr;
   f.opts = opts;
@@ -723,7 +770,8 @@ nvgs_status nvgs_render(nvgs_ctx* ctx, const nvgs_camera* cams, int32_t C, const
   // persistent frame
   if (ctx->cap_splats <= 0 || ctx->cap_dup <= 0)
     return fail(ctx, NVGS_E_STATE, "GRAPH frames need capacities: nvgs_reserve, or one frame without NVGS_RENDER_GRAPH");
-  if ((s = size_tiles(ctx, f.nkeys)) || (s = size_hist(ctx))) return s;
+  if ((s = size_tiles(ctx, f.nkeys)) || (s = size_hist(ctx)) || (s = size_items(ctx, f.nkeys, f.T, f.split_len)))
+    return s;
   if (f.debug && (s = size_debug(ctx))) return s;
   if (ctx->cap_keys < f.nkeys || ctx->cap_hist < std::max({ctx->cap_dup, ctx->cap_splats, ctx->cap_keys}) ||
       (f.debug && ctx->cap_debug < ctx->cap_splats))
@@ -733,7 +781,7 @@ nvgs_status nvgs_render(nvgs_ctx* ctx, const nvgs_camera* cams, int32_t C, const
       (uint64_t)opts->flags, (uint64_t)reinterpret_cast<uintptr_t>(rgb),
       (uint64_t)reinterpret_cast<uintptr_t>(record ? opts->contrib : nullptr), (uint64_t)(stats != nullptr),
       ctx->gen, (uint64_t)shape_nb(ctx, opts->precision), (uint64_t)ctx->mlp_segs,
-      (uint64_t)ctx->cap_splats, (uint64_t)ctx->cap_dup,
+      (uint64_t)ctx->cap_splats, (uint64_t)ctx->cap_dup, (uint64_t)(int64_t)f.split_len,
       ((uint64_t)__builtin_bit_cast(uint32_t, opts->bg[0]) << 32) | __builtin_bit_cast(uint32_t, opts->bg[1]),
       (uint64_t)__builtin_bit_cast(uint32_t, opts->bg[2])};
   if (!ctx->gexec || key != ctx->gkey) {

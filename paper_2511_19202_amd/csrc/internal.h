@@ -134,9 +134,29 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
 hipError_t launch_ranges(const uint32_t* keys, const uint32_t* n_dev, int64_t cap, int64_t nkeys, uint32_t* ranges,
                          hipStream_t st);
 hipError_t launch_tile_keys(const uint32_t* ranges, int64_t n, uint32_t* keys, uint32_t* vals, hipStream_t st);
+// Compositing work items (tile lists longer than split_len entries are cut
+// into chunks composited by separate work-groups; split_len <= 0: never).
+struct BlendItems {
+  int split_len;
+  const uint32_t* order;    // tile launch order (positions -> tile keys)
+  const uint32_t* nch;      // [nkeys] chunks per position
+  const uint32_t* split_off;// [nkeys] first split-chunk slot per position
+  const uint2* items;       // [cap_items] (position, chunk)
+  const uint32_t* n_items;  // device count of items
+  int64_t cap_items;
+  int64_t cap_split;        // split-chunk slots (at most 2 cap_dup / split_len + 2 are used)
+  float* prod;              // [split slots][T*T]
+  float4* part;             // [split slots][T*T]
+};
+// Builds nch / item_off / split_off and the item list; n_items and n_split
+// receive the totals; overflow bit value 8 when cap_items is exceeded.
+hipError_t launch_split_items(const uint32_t* ranges, const uint32_t* order, int64_t nkeys, int split_len,
+                              uint32_t* nch, uint32_t* nsp, uint32_t* item_off, uint32_t* split_off, uint32_t* n_items,
+                              uint32_t* n_split, uint2* items, int64_t cap_items, uint32_t* partials,
+                              uint32_t* overflow, hipStream_t st);
 // splat: [n][4] float4 compositing records written by launch_project
-hipError_t launch_blend(const uint32_t* ranges, const uint32_t* order, const uint32_t* ids, const float4* splat, int C,
-                        int W, int H, int tile, int tiles_x, int tiles_y, float bg0, float bg1, float bg2, float* rgb,
+hipError_t launch_blend(const BlendItems& bi, const uint32_t* ranges, const uint32_t* ids, const float4* splat, int W,
+                        int H, int tile, int tiles_x, int tiles_y, float bg0, float bg1, float bg2, float* rgb,
                         float* contrib, unsigned long long* work, hipStream_t st);
 
 }  // namespace nvgs

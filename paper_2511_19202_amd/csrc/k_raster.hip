@@ -418,11 +418,60 @@ hipError_t launch_tile_keys(const uint32_t* ranges, int64_t n, uint32_t* keys, u
 // as evaluating alpha.  A wave skips splats whose alpha footprint box misses
 // its pixel block.
 // ---------------------------------------------------------------------------
-template <int T, bool RECORD>
+// ---------------------------------------------------------------------------
+// compositing work items.  A tile list longer than split_len entries is cut
+// into nch equal chunks composited by nch work-groups: a product pass gives
+// each chunk's per-pixel product of (1 - alpha) over its passing fragments
+// (no stop rule); chunk j then starts from the product of the chunks before
+// it.  Transmittance only falls, so a pixel stopped before chunk j exactly
+// when that product is below 1e-4, and chunk j applies the stop rule from
+// there.  A combine pass sums the chunks' colours in list order.  The result
+// equals the sequential composite up to the association of the products and
+// sums (rounding).  Items are (position in the tile launch order, chunk).
+// ---------------------------------------------------------------------------
+__global__ void k_split_count(const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ order, int64_t nkeys,
+                              int split_len, uint32_t* __restrict__ nch, uint32_t* __restrict__ nsp) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < nkeys; p += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t key = order[p];
+    const uint32_t len = ranges[2 * (int64_t)key + 1] - ranges[2 * (int64_t)key];
+    const uint32_t c = (split_len > 0 && len > (uint32_t)split_len) ? (len + split_len - 1) / split_len : 1u;
+    nch[p] = c;
+    nsp[p] = c > 1 ? c : 0u;
+  }
+}
+
+__global__ void k_split_expand(const uint32_t* __restrict__ nch, const uint32_t* __restrict__ item_off, int64_t nkeys,
+                               int64_t cap_items, uint2* __restrict__ items, uint32_t* __restrict__ overflow) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < nkeys; p += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t c = nch[p], o = item_off[p];
+    for (uint32_t j = 0; j < c; ++j) {
+      if ((int64_t)o + j < cap_items)
+        items[o + j] = make_uint2((uint32_t)p, j);
+      else
+        atomicOr(overflow, 8u);
+    }
+  }
+}
+
+struct ItemCtx {
+  const uint2* items;
+  const uint32_t* n_items;  // device count
+  int64_t cap_items;
+  int64_t cap_split;        // split-chunk slots of prod / part
+  const uint32_t* order;
+  const uint32_t* nch;
+  const uint32_t* split_off;
+  float* prod;              // [split chunk][T*T]
+  float4* part;             // [split chunk][T*T]: r, g, b, flag
+};
+
+// MODE 0: composite; 1: composite and record contributions; 2: product pass
+template <int T, int MODE>
 __global__ __launch_bounds__(T == 8 ? 64 : 256) void k_blend(
-    const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ order, const uint32_t* __restrict__ ids,
+    ItemCtx ic, const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ ids,
     const float4* __restrict__ splat, int W, int H, int tiles_x, int n_tiles, float bg0, float bg1, float bg2,
     float* __restrict__ rgb, uint32_t* __restrict__ contrib, unsigned long long* __restrict__ work) {
+  constexpr bool RECORD = MODE == 1, PROD = MODE == 2;
   constexpr int NT = T == 8 ? 64 : 256;  // threads
   constexpr int NB = T * T / 64;         // 8x8 pixel blocks per tile
   constexpr int BPW = NB / (NT / 64);    // blocks per wave (1, 1, 4)
@@ -432,13 +481,26 @@ __global__ __launch_bounds__(T == 8 ? 64 : 256) void k_blend(
   __shared__ float2 s_c[BATCH];  // g, b
   __shared__ uint32_t s_ov[T == 8 ? 1 : BATCH];  // bit b: the footprint box touches 8x8 block b
   __shared__ uint32_t s_p[RECORD ? BATCH : 1];
-  const int key = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
+  const int64_t item = blockIdx.x;
+  if (item >= min((int64_t)*ic.n_items, ic.cap_items)) return;
+  const uint2 it = ic.items[item];
+  const uint32_t nch = ic.nch[it.x];
+  const bool split = nch > 1;
+  if (PROD && (!split || it.y + 1 == nch)) return;  // products are needed for all but the last chunk
+  if (split && (int64_t)ic.split_off[it.x] + nch > ic.cap_split) return;  // cannot happen within the sizing bound
+  const int key = (int)ic.order[it.x];
   const int cam = key / n_tiles, tile = key % n_tiles;
   const int tx = tile % tiles_x, ty = tile / tiles_x;
-  const uint32_t start = ranges[2 * (int64_t)key], end = ranges[2 * (int64_t)key + 1];
+  uint32_t start = ranges[2 * (int64_t)key], end = ranges[2 * (int64_t)key + 1];
+  if (split) {
+    const uint32_t clen = (end - start + nch - 1) / nch;
+    start = min(end, start + it.y * clen);
+    end = min(end, start + clen);
+  }
+  const int64_t sbase = split ? ((int64_t)ic.split_off[it.x] + it.y) * (T * T) : 0;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   float px[BPW], py[BPW], Tr[BPW], cr[BPW], cg[BPW], cb[BPW];
-  bool done[BPW];
+  bool done[BPW], before[BPW];
   uint32_t stop[BPW];  // list position at which the pixel stopped (end if it never did)
 #pragma unroll
   for (int j = 0; j < BPW; ++j) {
@@ -450,6 +512,17 @@ __global__ __launch_bounds__(T == 8 ? 64 : 256) void k_blend(
     Tr[j] = 1.f;
     cr[j] = cg[j] = cb[j] = 0.f;
     done[j] = !(x < W && y < H);
+    before[j] = false;
+    if (split && !PROD && it.y > 0) {
+      // transmittance entering this chunk: product of the earlier chunks' products
+      const int64_t pix = blk * 64 + lane;
+      const int64_t b0 = (int64_t)ic.split_off[it.x] * (T * T) + pix;
+      float tin = 1.f;
+      for (uint32_t q = 0; q < it.y; ++q) tin *= ic.prod[b0 + (int64_t)q * (T * T)];
+      Tr[j] = tin;
+      before[j] = tin < kTMin;
+      done[j] = done[j] || before[j];
+    }
   }
   // the next batch's record of this thread, fetched while the current one is composited
   float4 qa = make_float4(0.f, 0.f, 0.f, 0.f), qb = qa, qc = qa;
@@ -465,16 +538,22 @@ __global__ __launch_bounds__(T == 8 ? 64 : 256) void k_blend(
   // composite staged splat k into pixel block j.  Branch-free: a fragment that
   // is skipped (outside the 1/255 level set, alpha < 1/255, pixel stopped)
   // contributes weight 0; one whose blend would take T below 1e-4 stops the
-  // pixel instead (Sec. 4.1).
+  // pixel instead (Sec. 4.1).  The product pass multiplies (1 - alpha) of the
+  // passing fragments, stopping once below 1e-4 (later chunks only test that).
   auto step = [&](int j, int k) {
     const float4 g = s_g[k];
     const float4 h = s_h[k];
-    const float2 c = s_c[k];
     const float dx = px[j] - g.x, dy = py[j] - g.y;
     const float pw = dx * fmaf(g.z, dx, g.w * dy) + h.x * dy * dy;
     const float al = fminf(kAlphaMax, h.y * __builtin_amdgcn_exp2f(pw));
     const bool ok = !done[j] && pw >= h.z && pw <= 0.f && al >= kAlphaMin;
     const float Tn = Tr[j] * (1.f - al);
+    if (PROD) {
+      Tr[j] = ok ? Tn : Tr[j];
+      done[j] = done[j] || Tr[j] < kTMin;
+      return;
+    }
+    const float2 c = s_c[k];
     const bool halt = ok && Tn < kTMin;
     const bool take = ok && !halt;
     const float w = take ? al * Tr[j] : 0.f;
@@ -554,19 +633,31 @@ __global__ __launch_bounds__(T == 8 ? 64 : 256) void k_blend(
       }
     }
   }
+  if (PROD) {
+#pragma unroll
+    for (int j = 0; j < BPW; ++j) ic.prod[sbase + (wave * BPW + j) * 64 + lane] = Tr[j];
+    return;
+  }
   if (work) {
     // entries of the tile list each pixel examined: up to and including its stop
     uint32_t wk = 0;
 #pragma unroll
     for (int j = 0; j < BPW; ++j) {
       const int x = (int)px[j], y = (int)py[j];
-      if (x < W && y < H) wk += (stop[j] < end ? stop[j] + 1 : end) - start;
+      if (x < W && y < H && !before[j]) wk += (stop[j] < end ? stop[j] + 1 : end) - start;
     }
     for (int o = 32; o > 0; o >>= 1) wk += __shfl_xor(wk, o);
     if (lane == 0) atomicAdd(work, (unsigned long long)wk);
   }
 #pragma unroll
   for (int j = 0; j < BPW; ++j) {
+    if (split) {
+      // chunk record: colour and a flag: 0 if the pixel stopped in an earlier
+      // chunk, -T if it stopped in this one, else the transmittance leaving it
+      const float flag = before[j] ? 0.f : (stop[j] < end ? -Tr[j] : Tr[j]);
+      ic.part[sbase + (wave * BPW + j) * 64 + lane] = make_float4(cr[j], cg[j], cb[j], flag);
+      continue;
+    }
     const int x = (int)px[j], y = (int)py[j];
     if (x < W && y < H) {
       float* o = rgb + (((int64_t)cam * H + y) * W + x) * 3;
@@ -577,33 +668,96 @@ __global__ __launch_bounds__(T == 8 ? 64 : 256) void k_blend(
   }
 }
 
+// pixels of split tiles: chunk colours summed in list order, the final
+// transmittance from the chunk where the pixel stopped (or the last one)
 template <int T>
-static void launch_blend_t(bool record, dim3 grid, hipStream_t st, const uint32_t* ranges, const uint32_t* order,
+__global__ __launch_bounds__(256) void k_blend_combine(ItemCtx ic, int W, int H, int tiles_x, int n_tiles, float bg0,
+                                                       float bg1, float bg2, float* __restrict__ rgb) {
+  const int64_t item = blockIdx.x;
+  if (item >= min((int64_t)*ic.n_items, ic.cap_items)) return;
+  const uint2 it = ic.items[item];
+  const uint32_t nch = ic.nch[it.x];
+  if (nch <= 1 || it.y != 0) return;
+  if ((int64_t)ic.split_off[it.x] + nch > ic.cap_split) return;
+  const int key = (int)ic.order[it.x];
+  const int cam = key / n_tiles, tile = key % n_tiles;
+  const int tx = tile % tiles_x, ty = tile / tiles_x;
+  const int64_t base = (int64_t)ic.split_off[it.x] * (T * T);
+  for (int pix = threadIdx.x; pix < T * T; pix += 256) {
+    const int blk = pix / 64, lane = pix % 64;
+    const int x = tx * T + (blk % (T / 8)) * 8 + (lane & 7), y = ty * T + (blk / (T / 8)) * 8 + (lane >> 3);
+    if (!(x < W && y < H)) continue;
+    float r = 0.f, g = 0.f, b = 0.f, tf = 1.f;
+    for (uint32_t q = 0; q < nch; ++q) {
+      const float4 v = ic.part[base + (int64_t)q * (T * T) + pix];
+      if (v.w == 0.f) break;  // stopped before this chunk: tf is the last chunk's exit value
+      r += v.x;
+      g += v.y;
+      b += v.z;
+      if (v.w < 0.f) {
+        tf = -v.w;
+        break;
+      }
+      tf = v.w;
+    }
+    float* o = rgb + (((int64_t)cam * H + y) * W + x) * 3;
+    o[0] = fmaf(tf, bg0, r);
+    o[1] = fmaf(tf, bg1, g);
+    o[2] = fmaf(tf, bg2, b);
+  }
+}
+
+template <int T>
+static void launch_blend_t(bool record, const ItemCtx& ic, bool any_split, hipStream_t st, const uint32_t* ranges,
                            const uint32_t* ids, const float4* splat, int W, int H, int tiles_x, int n_tiles, float b0,
                            float b1, float b2, float* rgb, float* contrib, unsigned long long* work) {
   constexpr int NT = T == 8 ? 64 : 256;
+  const dim3 grid((unsigned)ic.cap_items);
+  uint32_t* cu = reinterpret_cast<uint32_t*>(contrib);
+  if (any_split)
+    hipLaunchKernelGGL((k_blend<T, 2>), grid, dim3(NT), 0, st, ic, ranges, ids, splat, W, H, tiles_x, n_tiles, b0,
+                       b1, b2, rgb, cu, nullptr);
   if (record)
-    hipLaunchKernelGGL((k_blend<T, true>), grid, dim3(NT), 0, st, ranges, order, ids, splat, W, H, tiles_x, n_tiles,
-                       b0, b1, b2, rgb, reinterpret_cast<uint32_t*>(contrib), work);
+    hipLaunchKernelGGL((k_blend<T, 1>), grid, dim3(NT), 0, st, ic, ranges, ids, splat, W, H, tiles_x, n_tiles, b0,
+                       b1, b2, rgb, cu, work);
   else
-    hipLaunchKernelGGL((k_blend<T, false>), grid, dim3(NT), 0, st, ranges, order, ids, splat, W, H, tiles_x, n_tiles,
-                       b0, b1, b2, rgb, reinterpret_cast<uint32_t*>(contrib), work);
+    hipLaunchKernelGGL((k_blend<T, 0>), grid, dim3(NT), 0, st, ic, ranges, ids, splat, W, H, tiles_x, n_tiles, b0,
+                       b1, b2, rgb, cu, work);
+  if (any_split)
+    hipLaunchKernelGGL((k_blend_combine<T>), grid, dim3(256), 0, st, ic, W, H, tiles_x, n_tiles, b0, b1, b2, rgb);
 }
 
-hipError_t launch_blend(const uint32_t* ranges, const uint32_t* order, const uint32_t* ids, const float4* splat, int C,
-                        int W, int H, int tile, int tiles_x, int tiles_y, float bg0, float bg1, float bg2, float* rgb,
+hipError_t launch_split_items(const uint32_t* ranges, const uint32_t* order, int64_t nkeys, int split_len,
+                              uint32_t* nch, uint32_t* nsp, uint32_t* item_off, uint32_t* split_off, uint32_t* n_items,
+                              uint32_t* n_split, uint2* items, int64_t cap_items, uint32_t* partials,
+                              uint32_t* overflow, hipStream_t st) {
+  if (nkeys == 0) return hipSuccess;
+  const unsigned grid = (unsigned)std::min<int64_t>((nkeys + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_split_count, dim3(grid), dim3(256), 0, st, ranges, order, nkeys, split_len, nch, nsp);
+  hipError_t e = launch_scan_u32_dev(nch, item_off, nkeys, nullptr, n_items, partials, st, nullptr);
+  if (e != hipSuccess) return e;
+  e = launch_scan_u32_dev(nsp, split_off, nkeys, nullptr, n_split, partials, st, nullptr);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_split_expand, dim3(grid), dim3(256), 0, st, nch, item_off, nkeys, cap_items, items, overflow);
+  return hipGetLastError();
+}
+
+hipError_t launch_blend(const BlendItems& bi, const uint32_t* ranges, const uint32_t* ids, const float4* splat, int W,
+                        int H, int tile, int tiles_x, int tiles_y, float bg0, float bg1, float bg2, float* rgb,
                         float* contrib, unsigned long long* work, hipStream_t st) {
   const int n_tiles = tiles_x * tiles_y;
-  dim3 grid((unsigned)(C * n_tiles));
+  if (bi.cap_items == 0) return hipSuccess;
+  const ItemCtx ic{bi.items, bi.n_items, bi.cap_items, bi.cap_split, bi.order, bi.nch, bi.split_off, bi.prod, bi.part};
   const bool record = contrib != nullptr;
+  const bool any_split = bi.split_len > 0;
   if (tile == 8)
-    launch_blend_t<8>(record, grid, st, ranges, order, ids, splat, W, H, tiles_x, n_tiles, bg0, bg1, bg2, rgb,
+    launch_blend_t<8>(record, ic, any_split, st, ranges, ids, splat, W, H, tiles_x, n_tiles, bg0, bg1, bg2, rgb,
                       contrib, work);
   else if (tile == 16)
-    launch_blend_t<16>(record, grid, st, ranges, order, ids, splat, W, H, tiles_x, n_tiles, bg0, bg1, bg2, rgb,
+    launch_blend_t<16>(record, ic, any_split, st, ranges, ids, splat, W, H, tiles_x, n_tiles, bg0, bg1, bg2, rgb,
                        contrib, work);
   else if (tile == 32)
-    launch_blend_t<32>(record, grid, st, ranges, order, ids, splat, W, H, tiles_x, n_tiles, bg0, bg1, bg2, rgb,
+    launch_blend_t<32>(record, ic, any_split, st, ranges, ids, splat, W, H, tiles_x, n_tiles, bg0, bg1, bg2, rgb,
                        contrib, work);
   else
     return hipErrorInvalidValue;
