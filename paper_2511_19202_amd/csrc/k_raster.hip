@@ -24,8 +24,16 @@ namespace nvgs {
 // real spherical harmonics (l <= 3, order l-major, m = -l..l, no Condon-
 // Shortley phase) evaluated on a unit direction, accumulated into rgb
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void sh_color(const float* __restrict__ p, int degree, float x, float y, float z,
-                                         float rgb[3]) {
+// 16-byte load through the global address space (pointers read from a table
+// are generic, which would give flat loads)
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 ld_global(const float4* p, int64_t i) {
+  const f32x4_t v = ((const __attribute__((address_space(1))) f32x4_t*)p)[i];
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+
+template <int D>
+__device__ __forceinline__ void sh_color_t(const float4* __restrict__ row, float x, float y, float z, float rgb[3]) {
   // normalisation constants sqrt((2l+1)/(4pi) (l-m)!/(l+m)!) (x sqrt2 for m != 0)
   constexpr float c0 = 0.28209479177387814f;
   constexpr float c1 = 0.48860251190291992f;
@@ -37,22 +45,31 @@ __device__ __forceinline__ void sh_color(const float* __restrict__ p, int degree
   constexpr float c3c = 0.45704579946446572f;  // 0.25 sqrt(21/(2pi))
   constexpr float c3d = 0.37317633259011546f;  // 0.25 sqrt(7/pi)
   constexpr float c3e = 1.4453057213202769f;   // 0.25 sqrt(105/pi)
-  float Y[16];
-  Y[0] = c0;
-  int K = 1;
-  if (degree >= 1) {
-    Y[1] = c1 * y; Y[2] = c1 * z; Y[3] = c1 * x;
-    K = 4;
+  constexpr int K = (D + 1) * (D + 1);
+  constexpr int N4 = (3 * K + 3) / 4;
+  // the Gaussian's whole coefficient row in 16-byte loads
+  float c[4 * N4];
+#pragma unroll
+  for (int q = 0; q < N4; ++q) {
+    const float4 v = ld_global(row, q);
+    c[4 * q] = v.x;
+    c[4 * q + 1] = v.y;
+    c[4 * q + 2] = v.z;
+    c[4 * q + 3] = v.w;
   }
-  if (degree >= 2) {
+  float Y[K];
+  Y[0] = c0;
+  if (D >= 1) {
+    Y[1] = c1 * y; Y[2] = c1 * z; Y[3] = c1 * x;
+  }
+  if (D >= 2) {
     const float xx = x * x, yy = y * y, zz = z * z;
     Y[4] = c2a * x * y;
     Y[5] = c2a * y * z;
     Y[6] = c2b * (3.f * zz - 1.f);
     Y[7] = c2a * x * z;
     Y[8] = c2c * (xx - yy);
-    K = 9;
-    if (degree >= 3) {
+    if (D >= 3) {
       Y[9] = c3a * y * (3.f * xx - yy);
       Y[10] = c3b * x * y * z;
       Y[11] = c3c * y * (5.f * zz - 1.f);
@@ -60,18 +77,31 @@ __device__ __forceinline__ void sh_color(const float* __restrict__ p, int degree
       Y[13] = c3c * x * (5.f * zz - 1.f);
       Y[14] = c3e * z * (xx - yy);
       Y[15] = c3a * x * (xx - 3.f * yy);
-      K = 16;
     }
   }
   float r = 0.5f, gg = 0.5f, b = 0.5f;
+#pragma unroll
   for (int k = 0; k < K; ++k) {
-    r = fmaf(Y[k], p[3 * k], r);
-    gg = fmaf(Y[k], p[3 * k + 1], gg);
-    b = fmaf(Y[k], p[3 * k + 2], b);
+    r = fmaf(Y[k], c[3 * k], r);
+    gg = fmaf(Y[k], c[3 * k + 1], gg);
+    b = fmaf(Y[k], c[3 * k + 2], b);
   }
   rgb[0] = fmaxf(r, 0.f);
   rgb[1] = fmaxf(gg, 0.f);
   rgb[2] = fmaxf(b, 0.f);
+}
+
+// colour of one Gaussian: real SH up to degree 3 (l-major, m = -l..l, no
+// Condon-Shortley phase) on the unit view direction, from its packed row
+__device__ __forceinline__ void sh_color(const float* __restrict__ p, int degree, float x, float y, float z,
+                                         float rgb[3]) {
+  const float4* row = reinterpret_cast<const float4*>(p);
+  switch (degree) {
+    case 0: sh_color_t<0>(row, x, y, z, rgb); break;
+    case 1: sh_color_t<1>(row, x, y, z, rgb); break;
+    case 2: sh_color_t<2>(row, x, y, z, rgb); break;
+    default: sh_color_t<3>(row, x, y, z, rgb); break;
+  }
 }
 
 int32_t sh_stride_for(int sh_degree) {
@@ -151,7 +181,7 @@ __global__ __launch_bounds__(kChunk) void k_project(
     return;
   }
   const AssetDev& A = assets[R.asset];
-  const float4 g0 = A.geo[3 * g], g1 = A.geo[3 * g + 1], g2 = A.geo[3 * g + 2];
+  const float4 g0 = ld_global(A.geo, 3 * g), g1 = ld_global(A.geo, 3 * g + 1), g2 = ld_global(A.geo, 3 * g + 2);
   const float mu[3] = {g0.x, g0.y, g0.z};
   const float s3[3] = {g1.x, g1.y, g1.z};
   float qw = g2.x, qx = g2.y, qy = g2.z, qz = g2.w;
