@@ -591,10 +591,15 @@ nvgs_status enqueue_frame(nvgs_ctx* ctx, hipStream_t st, const Frame& f, bool ea
                           P_<SegRec>(ctx->segs_dev), P_<float>(ctx->c1_dev), 128, st));
   STAGE_END(NVGS_STAGE_SETUP);
   STAGE_BEGIN(NVGS_STAGE_CULL_MLP);
-  CK(launch_cull_mlp(P_<AssetDev>(ctx->assets_dev), P_<WorkItem>(ctx->items_dev), (int64_t)ctx->items.size(),
-                     P_<int32_t>(ctx->seglist_dev), P_<SegRec>(ctx->segs_dev), P_<float>(ctx->c1_dev), 128, ctx->width,
-                     opts->precision, shape_nb(ctx, opts->precision), 0, P_<uint32_t>(ctx->mask),
-                     P_<uint32_t>(ctx->chunk_cnt), nullptr, nullptr, counts64, st));
+  if (opts->use_mlp)
+    CK(launch_cull_mlp(P_<AssetDev>(ctx->assets_dev), P_<WorkItem>(ctx->items_dev), (int64_t)ctx->items.size(),
+                       P_<int32_t>(ctx->seglist_dev), P_<SegRec>(ctx->segs_dev), P_<float>(ctx->c1_dev), 128,
+                       ctx->width, opts->precision, shape_nb(ctx, opts->precision), 0, P_<uint32_t>(ctx->mask),
+                       P_<uint32_t>(ctx->chunk_cnt), nullptr, nullptr, counts64, st));
+  else
+    CK(launch_cull_only(P_<AssetDev>(ctx->assets_dev), P_<WorkItem>(ctx->items_dev), (int64_t)ctx->items.size(),
+                        P_<int32_t>(ctx->seglist_dev), P_<SegRec>(ctx->segs_dev), P_<uint32_t>(ctx->mask),
+                        P_<uint32_t>(ctx->chunk_cnt), counts64, st));
   STAGE_END(NVGS_STAGE_CULL_MLP);
   STAGE_BEGIN(NVGS_STAGE_COMPACT);
   CK(launch_scan_u32(P_<uint32_t>(ctx->chunk_cnt), P_<uint32_t>(ctx->chunk_off), ctx->n_chunks, counters + 0,

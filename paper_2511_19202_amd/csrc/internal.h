@@ -101,6 +101,10 @@ hipError_t launch_segment_setup(const nvgs_camera* cams_dev, const nvgs_instance
 // nb: Gaussians per wave in units of 32 (the work-group has kChunk / (32 nb)
 // waves); supported shapes: mlp_shape_supported().
 bool mlp_shape_supported(int width, int precision, int nb);
+// frustum culling only (frames rendered without the MLP)
+hipError_t launch_cull_only(const AssetDev* assets_dev, const WorkItem* items, int64_t n_items, const int32_t* seglist,
+                            const SegRec* segs, uint32_t* mask, uint32_t* chunk_count, unsigned long long* counts,
+                            hipStream_t st);
 hipError_t launch_cull_mlp(const AssetDev* assets_dev, const WorkItem* items, int64_t n_items, const int32_t* seglist,
                            const SegRec* segs, const float* c1perm, int max_width, int width, int precision, int nb,
                            int mode, uint32_t* mask, uint32_t* chunk_count, uint8_t* state, float* logits,

@@ -592,6 +592,64 @@ __global__ __launch_bounds__(64 * WAVES) void k_cull_mlp(
   }
 }
 
+// Frustum culling alone (frames without the MLP): the same work items, keep
+// bits = in-frustum bits, no weights staged and no MLP evaluated.
+__global__ __launch_bounds__(kChunk) void k_cull_only(const AssetDev* __restrict__ assets,
+                                                      const WorkItem* __restrict__ items,
+                                                      const int32_t* __restrict__ seglist,
+                                                      const SegRec* __restrict__ segs, uint32_t* __restrict__ mask,
+                                                      uint32_t* __restrict__ chunk_count,
+                                                      unsigned long long* __restrict__ frame_counts) {
+  __shared__ uint32_t s_cnt[2];
+  __shared__ uint32_t s_tot;
+  const WorkItem it = items[blockIdx.x];
+  const AssetDev* A = assets + it.asset;
+  const int lane = threadIdx.x & 63;
+  const int64_t n = A->n;
+  const int64_t g = (int64_t)it.chunk * kChunk + threadIdx.x;
+  const bool valid = g < n;
+  float mu[3];
+  for (int j = 0; j < 3; ++j) mu[j] = valid ? A->mean[j * n + g] : 0.f;
+  if (threadIdx.x < 2) s_cnt[threadIdx.x] = 0;
+  if (threadIdx.x == 0) s_tot = 0;
+  __syncthreads();
+  int parity = 0;
+  uint32_t n_in = 0;
+  for (int si = it.seg_begin; si < it.seg_end; ++si, parity ^= 1) {
+    const int seg = seglist[si];
+    const SegRec& R = segs[seg];
+    const bool in = valid && frustum(R, mu);
+    const uint64_t b = __ballot(in);
+    const uint32_t lo = (uint32_t)b, hi = (uint32_t)(b >> 32);
+    const int64_t g0 = (int64_t)it.chunk * kChunk + (threadIdx.x & ~63);
+    if (lane == 0) {
+      if (g0 < n) mask[R.word_base + (g0 >> 5)] = lo;
+      if (g0 + 32 < n) mask[R.word_base + (g0 >> 5) + 1] = hi;
+      atomicAdd(&s_cnt[parity], (uint32_t)__popcll(b));
+    }
+    n_in += lane == 0 ? (uint32_t)__popcll(b) : 0u;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      chunk_count[R.chunk_base + it.chunk] = s_cnt[parity];
+      s_cnt[parity] = 0;
+    }
+  }
+  if (frame_counts) {
+    if (lane == 0) atomicAdd(&s_tot, n_in);
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(frame_counts + 0, (unsigned long long)s_tot);
+  }
+}
+
+hipError_t launch_cull_only(const AssetDev* assets_dev, const WorkItem* items, int64_t n_items, const int32_t* seglist,
+                            const SegRec* segs, uint32_t* mask, uint32_t* chunk_count, unsigned long long* counts,
+                            hipStream_t st) {
+  if (n_items == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cull_only, dim3((unsigned)n_items), dim3(kChunk), 0, st, assets_dev, items, seglist, segs, mask,
+                     chunk_count, counts);
+  return hipGetLastError();
+}
+
 template <int P, int W, int NB, int WAVES>
 static hipError_t launch_t(const AssetDev* assets, const WorkItem* items, int64_t n_items, const int32_t* seglist,
                            const SegRec* segs, const float* c1perm, int c1_stride, int mode, uint32_t* mask,
