@@ -204,6 +204,9 @@ __global__ void k_prepare(const float* __restrict__ Pm, int W, const float* __re
         const int which = e / (2 * KQ), r = e % (2 * KQ), g = r / KQ, q = r % KQ;
         const float* vec = which == 0 ? b2 : which == 1 ? b3 : wo;
         v = vec[hid_feature(q, g)];
+        // FP8: the hidden layers' accumulators start from b / inv = b sw sa (powers of two: exact)
+        if (P == NVGS_PREC_FP8 && which == 0) v *= scales[kSw2] * scales[kSaH1];
+        if (P == NVGS_PREC_FP8 && which == 1) v *= scales[kSw3] * scales[kSaH2];
       } else if (e == 6 * KQ) {
         v = wo[W];
       } else if (e - 6 * KQ - 1 < kNumScales) {
@@ -393,38 +396,64 @@ struct Mfma<NVGS_PREC_FP8> {
   }
 };
 
-// one hidden layer: o = relu(inv * (Wp h) + b), h and o in accumulator order
-template <int P, int W, int NB>
-__device__ __forceinline__ void hidden(const uint8_t* __restrict__ Wp, const float* __restrict__ bp, float inv,
-                                       float in_scale, const float (&h)[NB][W / 2], float (&o)[NB][W / 2], int lane,
-                                       int grp) {
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+
+// Next-layer operands from KQ values per lane in accumulator order, value
+// q = relu(scale * (acc[q] + add[q])) (add may be null), rounded to the
+// operand precision: FP32 as is, BF16 round-to-nearest-even with ReLU taken
+// on the packed 16-bit patterns (a sign-bit test, exact since rounding keeps
+// the sign), FP8 E4M3 after the ReLU.
+template <int P, int W, int NB, bool ADD>
+__device__ __forceinline__ void relu_pack(const f32x16 (&acc)[NB][W / 32], float scale, const float* __restrict__ add,
+                                          float add_scale, typename Mfma<P>::Op (&out)[NB][W / Prec<P>::K]) {
   using M = Mfma<P>;
-  constexpr int EPL = Prec<P>::EPL, NT = W / 32, KSH = W / Prec<P>::K, KQ = W / 2;
-  f32x16 acc[NB][NT];
+  constexpr int EPL = Prec<P>::EPL, KSH = W / Prec<P>::K;
 #pragma unroll
   for (int b = 0; b < NB; ++b)
 #pragma unroll
-    for (int t = 0; t < NT; ++t) acc[b][t] = (f32x16){0};
+    for (int s = 0; s < KSH; ++s) {
+      float v[EPL];
+#pragma unroll
+      for (int j = 0; j < EPL; ++j) {
+        const int q = s * EPL + j;
+        const float x = ADD ? fmaf(acc[b][q / 16][q % 16], add_scale, add[q]) : acc[b][q / 16][q % 16];
+        v[j] = P == NVGS_PREC_BF16 ? x * scale : fmaxf(x * scale, 0.f);
+      }
+      if constexpr (P == NVGS_PREC_BF16) {
+        s16x8 bits = __builtin_bit_cast(s16x8, M::pack(v));
+        bits = __builtin_elementwise_max(bits, (s16x8){0, 0, 0, 0, 0, 0, 0, 0});
+        out[b][s] = __builtin_bit_cast(typename M::Op, bits);
+      } else {
+        out[b][s] = M::pack(v);
+      }
+    }
+}
+
+// One hidden layer on 32x32 MFMA tiles with the pairs as columns: the
+// accumulators start from the layer's bias (in accumulator order; for FP8
+// stored divided by the layer's dequantisation scale), so the epilogue is a
+// scale and the ReLU only.
+template <int P, int W, int NB>
+__device__ __forceinline__ void mma_layer(const uint8_t* __restrict__ Wp, const float* __restrict__ binit,
+                                          const typename Mfma<P>::Op (&in)[NB][W / Prec<P>::K],
+                                          f32x16 (&acc)[NB][W / 32], int lane) {
+  using M = Mfma<P>;
+  constexpr int NT = W / 32, KSH = W / Prec<P>::K;
+  f32x16 c0[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) c0[t][r] = binit[16 * t + r];
 #pragma unroll
   for (int s = 0; s < KSH; ++s) {
     typename M::Op a[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) a[t] = M::load(Wp, (t * KSH + s) * 64 + lane);
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      float v[EPL];
+    for (int b = 0; b < NB; ++b)
 #pragma unroll
-      for (int j = 0; j < EPL; ++j) v[j] = h[b][s * EPL + j] * in_scale;
-      const typename M::Op hb = M::pack(v);
-#pragma unroll
-      for (int t = 0; t < NT; ++t) acc[b][t] = M::mma(a[t], hb, acc[b][t]);
-    }
+      for (int t = 0; t < NT; ++t) acc[b][t] = M::mma(a[t], in[b][s], s == 0 ? c0[t] : acc[b][t]);
   }
-  const float* bg = bp + grp * KQ;
-#pragma unroll
-  for (int b = 0; b < NB; ++b)
-#pragma unroll
-    for (int q = 0; q < KQ; ++q) o[b][q] = fmaxf(fmaf(acc[b][q / 16][q % 16], inv, bg[q]), 0.f);
 }
 
 template <int P, int W, int NB, int WAVES, int MODE>
@@ -532,19 +561,21 @@ __global__ __launch_bounds__(64 * WAVES) void k_cull_mlp(
     bool keep[NB];
     if (query && wave_any) {
       const float* c1 = c1perm + (size_t)seg * c1_stride + grp * KQ;
-      float h[NB][KQ], h2[NB][KQ];
-#pragma unroll
-      for (int b = 0; b < NB; ++b)
-#pragma unroll
-        for (int q = 0; q < KQ; ++q) h[b][q] = fmaxf(fmaf(U[b][q / 16][q % 16], invU, c1[q]), 0.f);
-      hidden<P, W, NB>(W2p, b2p, inv2, saH1, h, h2, lane, grp);
-      hidden<P, W, NB>(W3p, b3p, inv3, saH2, h2, h, lane, grp);
+      constexpr int KSH = W / Prec<P>::K;
+      typename M::Op op[NB][KSH];
+      f32x16 acc[NB][NT];
+      // layer 1: h1 = relu(U + c1) (FP8: U dequantised first), as layer 2's operands
+      relu_pack<P, W, NB, true>(U, saH1, c1, invU, op);
+      mma_layer<P, W, NB>(W2p, b2p + grp * KQ, op, acc, lane);
+      relu_pack<P, W, NB, false>(acc, inv2 * saH2, nullptr, 1.f, op);
+      mma_layer<P, W, NB>(W3p, b3p + grp * KQ, op, acc, lane);
+      // output layer in FP32 on h3 = relu(inv3 acc)
       const float* wg = wop + grp * KQ;
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         float part = 0.f;
 #pragma unroll
-        for (int q = 0; q < KQ; ++q) part = fmaf(wg[q], h[b][q], part);
+        for (int q = 0; q < KQ; ++q) part = fmaf(wg[q], fmaxf(acc[b][q / 16][q % 16] * inv3, 0.f), part);
         z[b] = part + __shfl_xor(part, 32) + bo;
         keep[b] = in[b] && z[b] >= 0.f;
       }
