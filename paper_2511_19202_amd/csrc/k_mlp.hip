@@ -396,7 +396,10 @@ struct Mfma<NVGS_PREC_FP8> {
   }
 };
 
-typedef short s16x8 __attribute__((ext_vector_type(8)));
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
 
 // Next-layer operands from KQ values per lane in accumulator order, value
 // q = relu(scale * (acc[q] + add[q])) (add may be null), rounded to the
@@ -420,9 +423,16 @@ __device__ __forceinline__ void relu_pack(const f32x16 (&acc)[NB][W / 32], float
         v[j] = P == NVGS_PREC_BF16 ? x * scale : fmaxf(x * scale, 0.f);
       }
       if constexpr (P == NVGS_PREC_BF16) {
-        s16x8 bits = __builtin_bit_cast(s16x8, M::pack(v));
-        bits = __builtin_elementwise_max(bits, (s16x8){0, 0, 0, 0, 0, 0, 0, 0});
-        out[b][s] = __builtin_bit_cast(typename M::Op, bits);
+        // pairs rounded together (one v_cvt_pk_bf16_f32), ReLU as a packed
+        // signed 16-bit max with 0 (one v_pk_max_i16)
+        i32x4 w;
+#pragma unroll
+        for (int p2 = 0; p2 < 4; ++p2) {
+          const bf16x2 h = __builtin_convertvector((f32x2){v[2 * p2], v[2 * p2 + 1]}, bf16x2);
+          const s16x2 m = __builtin_elementwise_max(__builtin_bit_cast(s16x2, h), (s16x2){0, 0});
+          w[p2] = __builtin_bit_cast(int, m);
+        }
+        out[b][s] = __builtin_bit_cast(typename M::Op, w);
       } else {
         out[b][s] = M::pack(v);
       }
