@@ -238,7 +238,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="composed", choices=["composed", "batched"])
+    ap.add_argument("--workload", default="composed", choices=["composed", "batched", "sweep"],
+                    help="sweep: composed scene at several camera distances, SH 3 and SH 0, culled / unculled / "
+                         "radius-clipped")
+    ap.add_argument("--det-clip", type=float, default=0.25, help="sweep: radius-clipping threshold (px^4)")
     ap.add_argument("--tile", type=int, default=0, help="8, 16, 32, or 0 to autotune (tile and MLP block shape)")
     ap.add_argument("--precision", default=None, help="MLP precision (default fp32 composed, bf16 batched)")
     ap.add_argument("--mlp", default="trained", choices=["trained", "random"],
@@ -250,7 +253,8 @@ def parse():
     ap.add_argument("--n", type=int, default=250000)
     ap.add_argument("--frames", type=int, default=360, help="batched: ring positions (1 degree apart)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--extra-precisions", default="", help="comma list, e.g. bf16,fp8")
+    ap.add_argument("--extra-precisions", default="bf16,fp8",
+                    help="comma list of reduced-precision MLP forms timed beside the FP32 one")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many bytes (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -273,6 +277,8 @@ def main():
         sys.exit(2)
     if args.workload == "batched":
         return main_batched(args)
+    if args.workload == "sweep":
+        return main_sweep(args)
     import torch
     import paper_2511_19202_amd as nvgs
     import synth
@@ -430,6 +436,82 @@ def main_batched(args):
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_batched(sc)
     print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+def ssim(a, b):
+    """Mean SSIM over the RGB channels (Gaussian window sigma 1.5, constants
+    of the usual definition, data range 1)."""
+    from scipy.ndimage import gaussian_filter
+    c1, c2 = 0.01 ** 2, 0.03 ** 2
+    out = []
+    for ch in range(3):
+        x, y = a[..., ch].astype(np.float64), b[..., ch].astype(np.float64)
+        mx, my = gaussian_filter(x, 1.5), gaussian_filter(y, 1.5)
+        sxx = gaussian_filter(x * x, 1.5) - mx * mx
+        syy = gaussian_filter(y * y, 1.5) - my * my
+        sxy = gaussian_filter(x * y, 1.5) - mx * my
+        out.append(np.mean(((2 * mx * my + c1) * (2 * sxy + c2)) / ((mx * mx + my * my + c1) * (sxx + syy + c2))))
+    return float(np.mean(out))
+
+
+def main_sweep(args):
+    """FPS against camera distance (the camera moved along its ray to the
+    origin), for SH degree 3 and the same scene at SH degree 0, culled by the
+    trained MLP, unculled, and culled with radius clipping; PSNR / SSIM of
+    each culled image against the unculled one and the frame workspace."""
+    import copy
+    import torch
+    import paper_2511_19202_amd as nvgs
+    import synth
+
+    prec = args.precision or "fp32"
+    sc = synth.scene_composed(n_per_asset=args.n)
+    ctx = nvgs.Context(0)
+    ctx.load_assets(sc.assets)
+    ctx.set_instances(sc.instances)
+    if args.mlp == "trained":
+        train_assets(ctx, sc, views=args.views, steps=args.train_steps)
+    else:
+        calibrate_keep(ctx, sc, args.keep, prec)
+    sc0 = copy.copy(sc)
+    sc0.assets = []
+    for a in sc.assets:  # the same Gaussians with only the degree-0 coefficients
+        b = copy.copy(a)
+        b.sh = np.ascontiguousarray(a.sh[:3])
+        b.sh_degree = 0
+        sc0.assets.append(b)
+    base = sc.cameras[0]
+    rows = []
+    for label, scene in (("sh3", sc), ("sh0", sc0)):
+        ctx.load_assets(scene.assets)
+        ctx.set_instances(scene.instances)
+        for fct in (0.5, 0.75, 1.0, 1.5, 2.0, 3.0, 4.0):
+            cam = synth.camera(np.asarray(base.pos, np.float64) * fct, fovy_deg=math.degrees(base.fovy),
+                               width=base.width, height=base.height)
+            cams = [cam]
+            row = {"sh": label, "distance": float(np.linalg.norm(cam.pos))}
+            imgs = {}
+            for mode, kw in (("culled", dict(use_mlp=True)), ("unculled", dict(use_mlp=False)),
+                             ("culled_clip", dict(use_mlp=True, det_clip=args.det_clip))):
+                img, st = ctx.render(cams, tile=8, precision=prec, stats=True, **kw)
+                imgs[mode] = img.cpu().numpy()[0]
+                ctx.watermarks(reset=True)
+                ctx.render(cams, tile=8, precision=prec, **kw)
+                wm = ctx.watermarks(reset=True)
+                ctx.reserve(int(wm["max_splats"] * 1.1) + 4096, int(wm["max_duplicates"] * 1.1) + 4096)
+                t, per = time_graph(ctx, [cams], 20, 3, tile=8, precision=prec, **kw)
+                check_no_overflow(ctx)
+                row[mode] = {"fps": 1.0 / t, "kept": st["kept"], "entries": st["duplicates"],
+                             "workspace_gb": st["workspace_bytes"] / 1e9}
+            for mode in ("culled", "culled_clip"):
+                row[mode]["psnr_vs_unculled_db"] = psnr(imgs[mode], imgs["unculled"])
+                row[mode]["ssim_vs_unculled"] = ssim(imgs[mode], imgs["unculled"])
+            rows.append(row)
+            print(f"[sweep] {label} d={row['distance']:.1f}: culled {row['culled']['fps']:.1f} FPS, unculled "
+                  f"{row['unculled']['fps']:.1f}, clipped {row['culled_clip']['fps']:.1f}", file=sys.stderr, flush=True)
+    print(json.dumps({"workload": "sweep: composed-1080p at 7 camera distances, SH 3 and SH 0",
+                      "mlp_precision": prec, "det_clip": args.det_clip, "rows": rows}), flush=True)
     ctx.close()
 
 

@@ -138,6 +138,10 @@ typedef struct nvgs_render_opts {
                         sequential composite up to rounding (the association of the
                         transmittance products and colour sums); 0: default 2048;
                         < 0: never split (bit-identical across tile sizes); else >= 64 */
+  float det_clip;    /* radius clipping (Sec. 4.3 ablation): a splat whose 2D covariance
+                        (after the 0.3 px^2 dilation) has a determinant below det_clip
+                        (px^4; the 1-sigma ellipse area is pi sqrt(det)) is not binned;
+                        0: off.  Must be finite and >= 0. */
 } nvgs_render_opts;
 
 /* Stages timed with HIP events on the context stream (ms_stage index). */

@@ -228,8 +228,10 @@ def pair_to_instance(scene, pairs: np.ndarray):
     return inst.astype(np.int64), (pairs - off[inst]).astype(np.int64)
 
 
-def project(scene, cam, pairs: np.ndarray):
-    """Projection + footprint for the kept pairs of one camera, in the given order."""
+def project(scene, cam, pairs: np.ndarray, det_clip: float = 0.0):
+    """Projection + footprint for the kept pairs of one camera, in the given
+    order.  det_clip > 0: radius clipping (Sec. 4.3 ablation), a splat whose
+    2D covariance (dilated) has determinant below det_clip gets no footprint."""
     inst_of, g_of = pair_to_instance(scene, pairs)
     m = len(pairs)
     rec = np.zeros((m, REC))
@@ -248,6 +250,9 @@ def project(scene, cam, pairs: np.ndarray):
                       inst_array(inst), ca, r, pr)
         rec[sel] = r
         prect[sel] = pr
+    if det_clip > 0.0:
+        det = rec[:, 2] * rec[:, 4] - rec[:, 3] ** 2  # A C - B^2 of the dilated 2D covariance
+        prect[det < det_clip] = (1, 0, 1, 0)
     return rec, prect
 
 

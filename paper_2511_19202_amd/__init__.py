@@ -62,7 +62,7 @@ class Camera(C.Structure):
 
 class RenderOpts(C.Structure):
     _fields_ = [("tile", C.c_int32), ("use_mlp", C.c_int32), ("precision", C.c_int32), ("bg", C.c_float * 3),
-                ("flags", C.c_uint32), ("contrib", C.c_void_p), ("split_len", C.c_int32)]
+                ("flags", C.c_uint32), ("contrib", C.c_void_p), ("split_len", C.c_int32), ("det_clip", C.c_float)]
 
 
 NUM_STAGES = 8
@@ -317,7 +317,7 @@ class Context:
 
     def render(self, cams: Iterable, tile: int = 16, use_mlp: bool = True, precision="fp32", bg=(0.0, 0.0, 0.0),
                contrib=None, keep_debug: bool = False, stats: bool = False, out=None, graph: bool = False,
-               split: int = 0):
+               split: int = 0, det_clip: float = 0.0):
         """One frame for all cameras.  graph=True: persistent frame (captured
         HIP graph, no synchronisation unless stats); without `out` the image
         goes to a context-owned tensor that the next graph frame overwrites."""
@@ -337,7 +337,7 @@ class Context:
         flags = (RENDER_RECORD_CONTRIB if contrib is not None else 0) | (RENDER_KEEP_DEBUG if keep_debug else 0) | \
             (RENDER_GRAPH if graph else 0)
         opts = RenderOpts(int(tile), int(bool(use_mlp)), _PREC.get(precision, precision), (C.c_float * 3)(*bg), flags,
-                          contrib.data_ptr() if contrib is not None else None, int(split))
+                          contrib.data_ptr() if contrib is not None else None, int(split), float(det_clip))
         fs = FrameStats() if stats else None
         self._check(self.L.nvgs_render(self.h, arr, n, C.byref(opts), rgb.data_ptr(),
                                        C.byref(fs) if fs is not None else None))
@@ -374,7 +374,7 @@ class Context:
         arr, n = self._cams(cams)
         rgb = torch.empty((n, arr[0].height, arr[0].width, 3), dtype=torch.float32, device=self.device)
         opts = RenderOpts(int(tile), int(bool(use_mlp)), _PREC.get(precision, precision), (C.c_float * 3)(*bg), 0,
-                          None, 0)
+                          None, 0, 0.0)
         cap = 64
         table = (TuneEntry * cap)()
         cnt = C.c_int32()

@@ -64,7 +64,7 @@ struct nvgs_ctx {
 
   // splats and sort buffers
   int64_t cap_splats = 0, cap_dup = 0;
-  Buf splat, rec_a, rec_b, rec_c, rect, depth_key, ids, ids_tmp, keys_tmp2, pair_of, cnt, dup_off;
+  Buf splat, rec_a, rec_b, rec_c, rect, rect_sorted, depth_key, ids, ids_tmp, keys_tmp2, pair_of, cnt, dup_off;
   Buf keys, vals, keys_tmp, vals_tmp, hist, hist_part, ranges, tord;  // tord: tile order (4 arrays)
   Buf tsplit, citems, prodb, partb;  // long-list split: per-position counts and offsets, items, chunk products / records
   int64_t cap_items = 0, cap_split_px = 0;  // items; split slots x pixels per tile
@@ -323,7 +323,7 @@ void nvgs_destroy(nvgs_ctx* ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   Buf* all[] = {&ctx->assets_dev, &ctx->inst_dev, &ctx->inst_off_dev, &ctx->seg_word_dev, &ctx->seg_chunk_dev,
                 &ctx->items_dev, &ctx->seglist_dev, &ctx->segs_dev, &ctx->c1_dev, &ctx->mask, &ctx->chunk_cnt,
-                &ctx->chunk_off, &ctx->scan_part, &ctx->cam_dev, &ctx->splat, &ctx->rec_a, &ctx->rec_b, &ctx->rec_c, &ctx->rect,
+                &ctx->chunk_off, &ctx->scan_part, &ctx->cam_dev, &ctx->splat, &ctx->rect_sorted, &ctx->rec_a, &ctx->rec_b, &ctx->rec_c, &ctx->rect,
                 &ctx->depth_key, &ctx->ids, &ctx->ids_tmp, &ctx->keys_tmp2, &ctx->pair_of, &ctx->cnt, &ctx->dup_off,
                 &ctx->keys, &ctx->vals, &ctx->keys_tmp, &ctx->vals_tmp, &ctx->hist, &ctx->hist_part, &ctx->ranges, &ctx->tord,
                 &ctx->tsplit, &ctx->citems, &ctx->prodb, &ctx->partb,
@@ -508,6 +508,7 @@ nvgs_status size_splats(nvgs_ctx* ctx, int64_t need, bool slack) {
   const int64_t cap = std::max<int64_t>(slack ? need + need / 8 : need, 4096);
   ctx->cap_splats = 0;
   const bool ok = ensure(ctx, ctx->splat, 64 * cap) && ensure(ctx, ctx->rect, 16 * cap) &&
+                  ensure(ctx, ctx->rect_sorted, 16 * cap) &&
                   ensure(ctx, ctx->depth_key, 4 * cap) && ensure(ctx, ctx->ids, 4 * cap) &&
                   ensure(ctx, ctx->ids_tmp, 4 * cap) && ensure(ctx, ctx->keys_tmp2, 4 * cap) &&
                   ensure(ctx, ctx->cnt, 4 * cap) && ensure(ctx, ctx->dup_off, 4 * cap);
@@ -616,7 +617,7 @@ nvgs_status enqueue_frame(nvgs_ctx* ctx, hipStream_t st, const Frame& f, bool ea
   STAGE_BEGIN(NVGS_STAGE_PROJECT);
   CK(launch_project(P_<AssetDev>(ctx->assets_dev), P_<SegRec>(ctx->segs_dev), C * NI, P_<int64_t>(ctx->seg_chunk_dev),
                     ctx->n_chunks, P_<uint32_t>(ctx->mask), P_<uint32_t>(ctx->chunk_off), n_splats_dev,
-                    ctx->cap_splats, f.T, f.tiles_x, f.tiles_y, f.debug ? 1 : 0, P_<float4>(ctx->splat),
+                    ctx->cap_splats, f.T, f.tiles_x, f.tiles_y, f.debug ? 1 : 0, opts->det_clip, P_<float4>(ctx->splat),
                     P_<float4>(ctx->rec_a), P_<float4>(ctx->rec_b), P_<float4>(ctx->rec_c), P_<uint4>(ctx->rect),
                     P_<uint32_t>(ctx->depth_key), P_<uint32_t>(ctx->pair_of), counters + 2, st));
   STAGE_END(NVGS_STAGE_PROJECT);
@@ -629,7 +630,8 @@ nvgs_status enqueue_frame(nvgs_ctx* ctx, hipStream_t st, const Frame& f, bool ea
   const uint32_t* depth_ids = in_tmp ? P_<uint32_t>(ctx->ids_tmp) : P_<uint32_t>(ctx->ids);
   STAGE_END(NVGS_STAGE_DEPTH_SORT);
   STAGE_BEGIN(NVGS_STAGE_BIN);
-  CK(launch_gather_tiles(depth_ids, P_<uint4>(ctx->rect), n_splats_dev, ns_bound, P_<uint32_t>(ctx->cnt), st));
+  CK(launch_gather_tiles(depth_ids, P_<uint4>(ctx->rect), n_splats_dev, ns_bound, P_<uint32_t>(ctx->cnt),
+                         P_<uint4>(ctx->rect_sorted), st));
   CK(launch_scan_u32_dev(P_<uint32_t>(ctx->cnt), P_<uint32_t>(ctx->dup_off), ns_bound, n_splats_dev, counters + 1,
                          P_<uint32_t>(ctx->hist_part), st, counters + 2));
   STAGE_END(NVGS_STAGE_BIN);
@@ -646,7 +648,7 @@ nvgs_status enqueue_frame(nvgs_ctx* ctx, hipStream_t st, const Frame& f, bool ea
   }
   const uint32_t* n_dup_dev = counters + 1;
   STAGE_BEGIN(NVGS_STAGE_BIN);
-  CK(launch_emit(depth_ids, P_<uint4>(ctx->rect), P_<uint32_t>(ctx->dup_off), n_splats_dev, ns_bound, n_dup_dev,
+  CK(launch_emit(depth_ids, P_<uint4>(ctx->rect_sorted), P_<uint32_t>(ctx->dup_off), n_splats_dev, ns_bound, n_dup_dev,
                  ctx->cap_dup, f.tiles_x, f.n_tiles, P_<uint32_t>(ctx->keys), P_<uint32_t>(ctx->vals), counters + 2, st));
   STAGE_END(NVGS_STAGE_BIN);
   STAGE_BEGIN(NVGS_STAGE_TILE_SORT);
@@ -728,6 +730,8 @@ nvgs_status nvgs_render(nvgs_ctx* ctx, const nvgs_camera* cams, int32_t C, const
   if (opts->precision < NVGS_PREC_FP32 || opts->precision > NVGS_PREC_FP8)
     return fail(ctx, NVGS_E_INVALID, "bad precision");
   if (opts->split_len > 0 && opts->split_len < 64) return fail(ctx, NVGS_E_INVALID, "split_len must be 0, < 0 or >= 64");
+  if (!(opts->det_clip >= 0.f) || !finite_f(opts->det_clip))
+    return fail(ctx, NVGS_E_INVALID, "det_clip must be finite and >= 0");
   const bool record = (opts->flags & NVGS_RENDER_RECORD_CONTRIB) != 0;
   if (record && !opts->contrib) return fail(ctx, NVGS_E_INVALID, "RECORD_CONTRIB needs opts->contrib");
   const bool graph = (opts->flags & NVGS_RENDER_GRAPH) != 0;
@@ -787,6 +791,7 @@ nvgs_status nvgs_render(nvgs_ctx* ctx, const nvgs_camera* cams, int32_t C, const
       (uint64_t)reinterpret_cast<uintptr_t>(record ? opts->contrib : nullptr), (uint64_t)(stats != nullptr),
       ctx->gen, (uint64_t)shape_nb(ctx, opts->precision), (uint64_t)ctx->mlp_segs,
       (uint64_t)ctx->cap_splats, (uint64_t)ctx->cap_dup, (uint64_t)(int64_t)f.split_len,
+      (uint64_t)__builtin_bit_cast(uint32_t, opts->det_clip),
       ((uint64_t)__builtin_bit_cast(uint32_t, opts->bg[0]) << 32) | __builtin_bit_cast(uint32_t, opts->bg[1]),
       (uint64_t)__builtin_bit_cast(uint32_t, opts->bg[2])};
   if (!ctx->gexec || key != ctx->gkey) {

@@ -119,7 +119,8 @@ size_t scan_partials_needed(int64_t n);
 
 hipError_t launch_project(const AssetDev* assets, const SegRec* segs, int32_t n_segs, const int64_t* seg_chunk_base,
                           int64_t n_chunks, const uint32_t* mask, const uint32_t* chunk_off, const uint32_t* n_splats,
-                          int64_t cap_splats, int tile, int tiles_x, int tiles_y, int keep_debug, float4* splat,
+                          int64_t cap_splats, int tile, int tiles_x, int tiles_y, int keep_debug, float det_clip,
+                          float4* splat,
                           float4* rec_a, float4* rec_b, float4* rec_c, uint4* rect, uint32_t* depth_key,
                           uint32_t* pair_of, uint32_t* overflow, hipStream_t st);
 
@@ -129,8 +130,8 @@ hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp,
 size_t radix_hist_words(int64_t cap);
 
 hipError_t launch_gather_tiles(const uint32_t* sorted_ids, const uint4* rect, const uint32_t* n_dev, int64_t cap,
-                               uint32_t* out, hipStream_t st);
-hipError_t launch_emit(const uint32_t* sorted_ids, const uint4* rect, const uint32_t* dup_off, const uint32_t* n_dev,
+                               uint32_t* out, uint4* rect_sorted, hipStream_t st);
+hipError_t launch_emit(const uint32_t* sorted_ids, const uint4* rect_sorted, const uint32_t* dup_off, const uint32_t* n_dev,
                        int64_t cap, const uint32_t* n_dup_dev, int64_t cap_dup, int tiles_x, int n_tiles,
                        uint32_t* keys, uint32_t* vals, uint32_t* overflow, hipStream_t st);
 hipError_t launch_watermark(uint32_t* counters, hipStream_t st);

@@ -149,7 +149,7 @@ __global__ __launch_bounds__(kChunk) void k_project(
     const AssetDev* __restrict__ assets, const SegRec* __restrict__ segs, int32_t n_segs,
     const int64_t* __restrict__ seg_chunk_base, const uint32_t* __restrict__ mask,
     const uint32_t* __restrict__ chunk_off, int64_t cap, int tile, int tiles_x, int tiles_y, int keep_debug,
-    float4* __restrict__ splat, float4* __restrict__ rec_a, float4* __restrict__ rec_b, float4* __restrict__ rec_c,
+    float det_clip, float4* __restrict__ splat, float4* __restrict__ rec_a, float4* __restrict__ rec_b, float4* __restrict__ rec_c,
     uint4* __restrict__ rect, uint32_t* __restrict__ depth_key, uint32_t* __restrict__ pair_of,
     uint32_t* __restrict__ overflow) {
   const int64_t chunk = blockIdx.x;
@@ -257,7 +257,7 @@ __global__ __launch_bounds__(kChunk) void k_project(
   const int W = (int)(2.f * R.half_w), H = (int)(2.f * R.half_h);
   float ex = 0.f, ey = 0.f;
   uint32_t r0 = 0, r1 = 0, ntiles = 0;
-  if (k2 >= 0.f) {
+  if (k2 >= 0.f && !(det < det_clip)) {  // radius clipping: splats of small 2D area are not binned
     ex = sqrtf(k2 * a);
     ey = sqrtf(k2 * cc);
     int x0, x1, y0, y1;
@@ -291,14 +291,14 @@ __global__ __launch_bounds__(kChunk) void k_project(
 
 hipError_t launch_project(const AssetDev* assets, const SegRec* segs, int32_t n_segs, const int64_t* seg_chunk_base,
                           int64_t n_chunks, const uint32_t* mask, const uint32_t* chunk_off, const uint32_t* n_splats,
-                          int64_t cap_splats, int tile, int tiles_x, int tiles_y, int keep_debug, float4* splat,
-                          float4* rec_a, float4* rec_b, float4* rec_c, uint4* rect, uint32_t* depth_key,
+                          int64_t cap_splats, int tile, int tiles_x, int tiles_y, int keep_debug, float det_clip,
+                          float4* splat, float4* rec_a, float4* rec_b, float4* rec_c, uint4* rect, uint32_t* depth_key,
                           uint32_t* pair_of, uint32_t* overflow, hipStream_t st) {
   (void)n_splats;
   if (n_chunks == 0) return hipSuccess;
   hipLaunchKernelGGL(k_project, dim3((unsigned)n_chunks), dim3(kChunk), 0, st, assets, segs, n_segs, seg_chunk_base,
-                     mask, chunk_off, cap_splats, tile, tiles_x, tiles_y, keep_debug, splat, rec_a, rec_b, rec_c,
-                     rect, depth_key, pair_of, overflow);
+                     mask, chunk_off, cap_splats, tile, tiles_x, tiles_y, keep_debug, det_clip, splat, rec_a, rec_b,
+                     rec_c, rect, depth_key, pair_of, overflow);
   return hipGetLastError();
 }
 
@@ -309,19 +309,24 @@ __device__ __forceinline__ int64_t live(const uint32_t* n_dev, int64_t cap) {
   return n_dev ? (int64_t)min((uint64_t)*n_dev, (uint64_t)cap) : cap;
 }
 
-// tile counts of the splats in depth order
+// tile counts of the splats in depth order, and their rectangles copied into
+// depth order so that the emission reads them sequentially
 __global__ void k_gather_tiles(const uint32_t* __restrict__ ids, const uint4* __restrict__ rect,
-                               const uint32_t* __restrict__ n_dev, int64_t cap, uint32_t* __restrict__ out) {
+                               const uint32_t* __restrict__ n_dev, int64_t cap, uint32_t* __restrict__ out,
+                               uint4* __restrict__ rect_sorted) {
   const int64_t n = live(n_dev, cap);
-  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
-    out[j] = rect[ids[j]].w;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+    const uint4 r = rect[ids[j]];
+    out[j] = r.w;
+    rect_sorted[j] = r;
+  }
 }
 
 hipError_t launch_gather_tiles(const uint32_t* sorted_ids, const uint4* rect, const uint32_t* n_dev, int64_t cap,
-                               uint32_t* out, hipStream_t st) {
+                               uint32_t* out, uint4* rect_sorted, hipStream_t st) {
   if (cap == 0) return hipSuccess;
   unsigned grid = (unsigned)std::min<int64_t>((cap + 255) / 256, 65536);
-  hipLaunchKernelGGL(k_gather_tiles, dim3(grid), dim3(256), 0, st, sorted_ids, rect, n_dev, cap, out);
+  hipLaunchKernelGGL(k_gather_tiles, dim3(grid), dim3(256), 0, st, sorted_ids, rect, n_dev, cap, out, rect_sorted);
   return hipGetLastError();
 }
 
@@ -330,15 +335,15 @@ hipError_t launch_gather_tiles(const uint32_t* sorted_ids, const uint4* rect, co
 // capacity the overflow flag is raised and only the entries below it are
 // written, so every position of [0, cap_dup) still holds an entry of this
 // frame (a clipped frame, never stale keys).
-__global__ void k_emit(const uint32_t* __restrict__ ids, const uint4* __restrict__ rect,
+__global__ void k_emit(const uint32_t* __restrict__ ids, const uint4* __restrict__ rect_sorted,
                        const uint32_t* __restrict__ off, const uint32_t* __restrict__ n_dev, int64_t cap,
                        const uint32_t* __restrict__ n_dup_dev, int64_t cap_dup, int tiles_x, int n_tiles,
                        uint32_t* __restrict__ keys, uint32_t* __restrict__ vals, uint32_t* __restrict__ overflow) {
   const int64_t n = live(n_dev, cap);
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t s = ids[j];
-    const uint4 r = rect[s];
+    const uint4 r = rect_sorted[j];
     if (r.w == 0) continue;
+    const uint32_t s = ids[j];
     int64_t o = off[j];
     if (o >= cap_dup) {
       atomicOr(overflow, 2u);
@@ -359,12 +364,12 @@ __global__ void k_emit(const uint32_t* __restrict__ ids, const uint4* __restrict
   (void)n_dup_dev;
 }
 
-hipError_t launch_emit(const uint32_t* sorted_ids, const uint4* rect, const uint32_t* dup_off, const uint32_t* n_dev,
+hipError_t launch_emit(const uint32_t* sorted_ids, const uint4* rect_sorted, const uint32_t* dup_off, const uint32_t* n_dev,
                        int64_t cap, const uint32_t* n_dup_dev, int64_t cap_dup, int tiles_x, int n_tiles,
                        uint32_t* keys, uint32_t* vals, uint32_t* overflow, hipStream_t st) {
   if (cap == 0) return hipSuccess;
   unsigned grid = (unsigned)std::min<int64_t>((cap + 255) / 256, 65536);
-  hipLaunchKernelGGL(k_emit, dim3(grid), dim3(256), 0, st, sorted_ids, rect, dup_off, n_dev, cap, n_dup_dev, cap_dup,
+  hipLaunchKernelGGL(k_emit, dim3(grid), dim3(256), 0, st, sorted_ids, rect_sorted, dup_off, n_dev, cap, n_dup_dev, cap_dup,
                      tiles_x, n_tiles, keys, vals, overflow);
   return hipGetLastError();
 }

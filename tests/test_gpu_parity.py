@@ -321,3 +321,38 @@ def test_reduced_precision_mlp(nvgs, prec, width):
     assert rel.max() < (1e-2 if prec == "bf16" else 5e-2)
     assert np.array_equal(st[q] == 2, zg >= 0)
     assert flips < (0.02 if prec == "bf16" else 0.08)
+
+
+def test_radius_clipping_matches_oracle(nvgs):
+    """Radius clipping by the 2D covariance determinant (Sec. 4.3 ablation):
+    the splats the kernel leaves unbinned are those whose FP64 determinant is
+    below the threshold (up to a relative margin of 1e-5), and the pixels
+    match the oracle's clipped frame under the pixel protocol."""
+    sc = SCENES["composed_small"]()
+    ctx = make_ctx(nvgs, sc)
+    st, _ = ctx.query_visibility(sc.cameras)
+    kept = np.flatnonzero(st.cpu().numpy()[0] == 2)
+    cam = sc.cameras[0]
+    rec0, _ = oracle.project(sc, cam, kept)
+    det = rec0[:, 2] * rec0[:, 4] - rec0[:, 3] ** 2
+    tau = float(np.quantile(det, 0.4))
+    img = ctx.render(sc.cameras, tile=16, det_clip=tau, keep_debug=True)
+    dbg = ctx.debug_buffers()
+    img = img.cpu().numpy()[0].astype(np.float64)
+    gn = dbg["rect"].cpu().numpy().astype(np.int64)[:, 3] & 0xFFFFFFFF
+    ctx.close()
+    rec, prect = oracle.project(sc, cam, kept, det_clip=tau)
+    oempty = (prect[:, 0] > prect[:, 1]) | (prect[:, 2] > prect[:, 3])
+    near = np.abs(det - tau) < 1e-5 * tau
+    mism = oempty != (gn == 0)
+    log(f"[clip] tau {tau:.4g}: oracle clips {np.sum(det < tau)} of {len(det)}, mismatches {mism.sum()} "
+        f"(near threshold {np.sum(mism & near)})")
+    assert np.sum(det < tau) > 0.3 * len(det)
+    assert np.sum(mism & ~near) <= max(3, 1e-3 * len(det))
+    ref = oracle.render_camera(rec, prect, cam, 16, sc.bg)
+    d = np.abs(img - ref["image"]).max(axis=2)
+    bad = d > 1e-4
+    m = ref["margin"]
+    excused = bad & ((m[..., 0] < MARGIN_ALPHA) | (m[..., 1] < MARGIN_DEPTH))
+    log(f"[clip] max pixel err {d.max():.3e}, >1e-4 {bad.sum()} (excused {excused.sum()})")
+    assert np.sum(bad & ~excused) <= max(4, 1e-3 * d.size)

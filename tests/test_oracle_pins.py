@@ -644,3 +644,42 @@ def test_labels_with_aux_views_are_a_superset(orc):
     wide = orc.labels(a, views, aux=4, aux_angle=math.radians(10.0))
     assert np.all(wide >= base)
     assert wide.sum() > base.sum()
+
+
+def test_radius_clipping_by_covariance_determinant(orc):
+    """Radius clipping (Sec. 4.3 ablation): a splat is dropped exactly when
+    the determinant of its dilated 2D covariance, (f^2 sx^2/z^2 + 0.3)
+    (f^2 sy^2/z^2 + 0.3) on the axis, is below the threshold; the image then
+    equals the tile-free brute-force render of the scene without it."""
+    cam = axis_camera(W=64, H=48, fovy_deg=60.0)
+    f = 0.5 * 48 / math.tan(float(np.float32(math.radians(60))) / 2)
+    z = 4.0
+    small = tuple(map(float, np.float32([0.004, 0.005, 0.01])))
+    big = tuple(map(float, np.float32([0.08, 0.06, 0.1])))
+    d_small = (f * f * small[0] ** 2 / z ** 2 + 0.3) * (f * f * small[1] ** 2 / z ** 2 + 0.3)
+    zb = z - 0.5
+    d_big = (f * f * big[0] ** 2 / zb ** 2 + 0.3) * (f * f * big[1] ** 2 / zb ** 2 + 0.3)
+    assert d_small < d_big
+    tau = math.sqrt(d_small * d_big)  # between the two
+    a = one_gaussian_asset((0, 0, z), small)
+    b = one_gaussian_asset((0, 0, zb), big, rgb=(0.9, 0.1, 0.1))  # in front of a, on the axis
+    for asset, d in ((a, d_small), (b, d_big)):
+        sc = Scene(assets=[asset], instances=[synth.identity_instance(0)], cameras=[cam])
+        rec, pr = orc.project(sc, cam, np.zeros(1, np.int64), det_clip=tau)
+        assert abs(rec[0, 2] * rec[0, 4] - rec[0, 3] ** 2 - d) < 1e-9 * d
+        assert (pr[0, 0] > pr[0, 1]) == (d < tau)
+        rec0, pr0 = orc.project(sc, cam, np.zeros(1, np.int64))
+        assert pr0[0, 0] <= pr0[0, 1]  # visible without clipping
+    # two-splat scene: clipped render == brute force of the big splat alone
+    both = synth.Asset(mean=np.concatenate([a.mean, b.mean], 1), scale=np.concatenate([a.scale, b.scale], 1),
+                       quat=np.concatenate([a.quat, b.quat], 1), opacity=np.concatenate([a.opacity, b.opacity]),
+                       sh=np.concatenate([a.sh, b.sh], 1), sh_degree=0, mlp=a.mlp)
+    sc2 = Scene(assets=[both], instances=[synth.identity_instance(0)], cameras=[cam])
+    rec2, pr2 = orc.project(sc2, cam, np.arange(2), det_clip=tau)
+    img = orc.render_camera(rec2, pr2, cam, 8, want_margin=False)["image"]
+    scb = Scene(assets=[b], instances=[synth.identity_instance(0)], cameras=[cam])
+    recb, prb = orc.project(scb, cam, np.zeros(1, np.int64))
+    ref, _ = orc.render_brute(recb, cam)
+    assert np.array_equal(img, ref)
+    full = orc.render_camera(*orc.project(sc2, cam, np.arange(2)), cam, 8, want_margin=False)["image"]
+    assert not np.array_equal(full, img)
