@@ -50,25 +50,37 @@ BLEND_PEAK_GTESTS = VALU_LANE_OPS / BLEND_SLOTS_PER_TEST / 1e9
 
 
 def train_assets(ctx, sc, views=512, res=512, batch=65536, steps=5000, precision="bf16", lr=1e-3, seed=1,
-                 weighting=1, aux=6, aux_deg=5.0, offset=0.1):
+                 weighting=1, aux=6, aux_deg=5.0, offset=0.1, recipe="workload"):
     """Train each asset's visibility MLP on labels the renderer makes from
-    `views` Fibonacci-sphere views at distances U(1.5, 20), each with `aux`
-    auxiliary views on a cone of `aux_deg` degrees (one identity instance per
-    asset), with class-frequency weighted BCE when `weighting`; returns
-    per-asset training summaries."""
+    `views` Fibonacci-sphere views, each with `aux` auxiliary views on a cone
+    of `aux_deg` degrees (one identity instance per asset), with
+    class-frequency weighted BCE when `weighting`.  recipe "workload":
+    distances U(1.5, 20), constant lr; recipe "paper" (Sec. 3.1, 4.1): the
+    asset's Eq. 1 distance range (also its MLP's far clamp), batches of 2^19,
+    lr 2e-3 with warm-up and decay to 2e-4.  Returns per-asset summaries."""
     import torch
     import synth
     out = []
     for j, a in enumerate(sc.assets):
-        cams = synth.label_views(views, seed=synth.SEED_BASE + 500 + j, res=res, offset=offset)
+        d_lo, d_hi = 1.5, 20.0
+        lr_final = 0.0
+        if recipe == "paper":
+            d_lo, d_hi = synth.eq1_range(a.name)
+            a.mlp.d_max = float(np.float32(d_hi))
+            a.mlp.cam_scale = float(np.float32(1.0 / d_hi))  # keeps the encoded camera position in [-1, 1]
+            batch, lr, lr_final = 1 << 19, 2e-3, 2e-4
+        cams = synth.label_views(views, seed=synth.SEED_BASE + 500 + j, d_lo=d_lo, d_hi=d_hi, res=res,
+                                 offset=offset)
         params = torch.from_numpy(a.mlp.params.astype(np.float32).copy()).cuda()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         labels = ctx.make_labels(j, cams, aux=aux, aux_angle=math.radians(aux_deg))
         torch.cuda.synchronize()
         t1 = time.perf_counter()
+        if recipe == "paper":
+            ctx.load_assets(sc.assets)  # the new far clamp
         curve = ctx.train_visibility(j, cams, params, labels=labels, batch=batch, steps=steps, precision=precision,
-                                     lr=lr, seed=seed + j, weighting=weighting)
+                                     lr=lr, seed=seed + j, weighting=weighting, lr_final=lr_final)
         t2 = time.perf_counter()
         a.mlp.params = params.cpu().numpy()
         visible = float(np.unpackbits(labels.cpu().numpy().view(np.uint8), bitorder="little").mean())
@@ -249,6 +261,9 @@ def parse():
                          "output bias set to keep --keep of the in-frustum pairs")
     ap.add_argument("--train-steps", type=int, default=5000)
     ap.add_argument("--views", type=int, default=2000, help="label views per asset")
+    ap.add_argument("--recipe", default="workload", choices=["workload", "paper"],
+                    help="training recipe: workload (U(1.5, 20) views, batch 65,536, lr 1e-3) or paper (Eq. 1 "
+                         "range, batch 2^19, lr 2e-3 -> 2e-4 with warm-up)")
     ap.add_argument("--keep", type=float, default=0.65)
     ap.add_argument("--n", type=int, default=250000)
     ap.add_argument("--frames", type=int, default=360, help="batched: ring positions (1 degree apart)")
@@ -290,7 +305,7 @@ def main():
     ctx.set_instances(sc.instances)
     training = None
     if args.mlp == "trained":
-        training = train_assets(ctx, sc, views=args.views, steps=args.train_steps)
+        training = train_assets(ctx, sc, views=args.views, steps=args.train_steps, recipe=args.recipe)
     else:
         calibrate_keep(ctx, sc, args.keep, prec)
     tile, tune = prepare(ctx, [sc.cameras], args.tile, prec)

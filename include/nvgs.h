@@ -212,6 +212,9 @@ typedef struct nvgs_train_opts {
   int32_t tile;       /* labels made internally: tile edge of the label renders */
   int32_t weighting;  /* 0: mean BCE; 1: each sample weighted by B / (2 n_class), n_class the
                          count of its label in the batch (Sec. 4.1 frequency weighting) */
+  int32_t schedule;   /* 0: constant lr; 1 (Sec. 4.1): cosine warm-up from 0 to lr over the first
+                         20 % of the steps, then exponential decay reaching lr_final at the last step */
+  float lr_final;     /* schedule 1: final learning rate (> 0) */
 } nvgs_train_opts;
 
 /* Create a context on a device / stream.  Host call, no GPU work. */

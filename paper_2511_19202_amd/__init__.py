@@ -94,7 +94,8 @@ class TuneEntry(C.Structure):
 class TrainOpts(C.Structure):
     _fields_ = [("batch", C.c_int64), ("steps", C.c_int32), ("precision", C.c_int32), ("lr", C.c_float),
                 ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float), ("seed", C.c_uint64),
-                ("threshold", C.c_float), ("tile", C.c_int32), ("weighting", C.c_int32)]
+                ("threshold", C.c_float), ("tile", C.c_int32), ("weighting", C.c_int32), ("schedule", C.c_int32),
+                ("lr_final", C.c_float)]
 
 
 # exported symbols of the C ABI and their signatures
@@ -433,11 +434,14 @@ def _train_methods():
 
     def train_visibility(self, asset: int, views, params, labels=None, batch: int = 65536, steps: int = 5000,
                          precision="bf16", lr: float = 1e-3, betas=(0.9, 0.999), eps: float = 1e-8, seed: int = 1,
-                         threshold: float = 1.0 / 255.0, tile: int = 16, weighting: int = 0):
-        """Train in place; params is a device float32 tensor [13057]; returns the loss curve."""
+                         threshold: float = 1.0 / 255.0, tile: int = 16, weighting: int = 0,
+                         lr_final: float = 0.0):
+        """Train in place; params is a device float32 tensor [13057]; returns the loss curve.
+        lr_final > 0 selects the warm-up + exponential-decay schedule from lr to lr_final."""
         arr, V = self._cams(views)
         opts = TrainOpts(int(batch), int(steps), _PREC.get(precision, precision), float(lr), float(betas[0]),
-                         float(betas[1]), float(eps), int(seed), float(threshold), int(tile), int(weighting))
+                         float(betas[1]), float(eps), int(seed), float(threshold), int(tile), int(weighting),
+                         1 if lr_final > 0 else 0, float(lr_final))
         curve = (C.c_float * int(steps))()
         self._check(self.L.nvgs_train_visibility(self.h, asset, arr, V, _ptr(labels), C.byref(opts),
                                                  params.data_ptr(), curve))

@@ -1123,6 +1123,17 @@ nvgs_status nvgs_make_labels(nvgs_ctx* ctx, int32_t asset, const nvgs_camera* vi
   return s2;
 }
 
+// learning rate of step t (0-based) of T: constant, or (Sec. 4.1) a cosine
+// warm-up from 0 to lr over the first 20 % of the steps followed by an
+// exponential decay from lr to lr_final at the last step
+static float step_lr(const nvgs_train_opts* o, int t) {
+  if (o->schedule != 1) return o->lr;
+  const int T = o->steps, Tw = std::max(1, (int)std::lround(0.2 * T));
+  if (t < Tw) return (float)(o->lr * 0.5 * (1.0 - std::cos(M_PI * (t + 1) / Tw)));
+  const double u = T - Tw > 1 ? (double)(t - Tw) / (double)(T - Tw - 1) : 1.0;
+  return (float)(o->lr * std::pow((double)o->lr_final / o->lr, u));
+}
+
 nvgs_status nvgs_train_visibility(nvgs_ctx* ctx, int32_t asset, const nvgs_camera* views, int32_t V,
                                   const uint32_t* labels, const nvgs_train_opts* opts, float* params,
                                   float* loss_curve) {
@@ -1131,6 +1142,8 @@ nvgs_status nvgs_train_visibility(nvgs_ctx* ctx, int32_t asset, const nvgs_camer
   if (asset < 0 || asset >= (int)ctx->assets.size()) return fail(ctx, NVGS_E_INVALID, "asset index out of range");
   if (!opts || !params) return fail(ctx, NVGS_E_INVALID, "null opts or params");
   if (opts->batch < 1 || opts->steps < 1) return fail(ctx, NVGS_E_INVALID, "batch and steps must be >= 1");
+  if (opts->schedule != 0 && !(opts->schedule == 1 && opts->lr_final > 0.f && std::isfinite(opts->lr_final)))
+    return fail(ctx, NVGS_E_INVALID, "schedule must be 0, or 1 with lr_final > 0");
   if (!(opts->lr > 0.f) || !(opts->beta1 >= 0.f && opts->beta1 < 1.f) || !(opts->beta2 >= 0.f && opts->beta2 < 1.f) ||
       !(opts->eps > 0.f))
     return fail(ctx, NVGS_E_INVALID, "bad Adam hyper-parameters");
@@ -1175,8 +1188,8 @@ nvgs_status nvgs_train_visibility(nvgs_ctx* ctx, int32_t asset, const nvgs_camer
     CK(launch_mlp_train(0, bf16, nwg, kTrainChunksPerWG, ctx->stream, params, opts->batch, inv_b, A.mean, n,
                         A.mlp.mean_scale, gam, V, labels, opts->seed, step, weighted ? npos + step : nullptr, nullptr,
                         nullptr, nullptr, part, lp, nullptr));
-    CK(launch_reduce_adam(part, nwg, params, m, v, nullptr, opts->lr, opts->beta1, opts->beta2, opts->eps, step + 1,
-                          lp, inv_b, loss + step, ctx->stream));
+    CK(launch_reduce_adam(part, nwg, params, m, v, nullptr, step_lr(opts, step), opts->beta1, opts->beta2, opts->eps,
+                          step + 1, lp, inv_b, loss + step, ctx->stream));
   }
   CK(hipStreamSynchronize(ctx->stream));
   if (loss_curve) CK(hipMemcpy(loss_curve, loss, sizeof(float) * opts->steps, hipMemcpyDeviceToHost));

@@ -354,6 +354,15 @@ def ring_cameras(n_cams: int = 8, frame: float = 0.0, radius: float = 60.0, heig
     return cams
 
 
+def eq1_range(shape: str, fovy_deg: float = 50.0, near: float = 0.9, far: float = 0.05):
+    """Eq. 1 camera-distance range of an asset: the distance at which its
+    bounding-box diagonal covers `near` and `far` of the image, d = r /
+    (tan(fov/2) p), r the half-diagonal."""
+    t = math.tan(math.radians(fovy_deg) / 2)
+    r = SHAPE_HALF_DIAG[shape]
+    return r / (t * near), r / (t * far)
+
+
 def fibonacci_sphere(n: int) -> np.ndarray:
     """n unit directions on the Fibonacci (golden-angle) spiral, [n, 3]."""
     k = np.arange(n, dtype=np.float64) + 0.5
