@@ -261,7 +261,7 @@ def parse():
                          "output bias set to keep --keep of the in-frustum pairs")
     ap.add_argument("--train-steps", type=int, default=5000)
     ap.add_argument("--views", type=int, default=2000, help="label views per asset")
-    ap.add_argument("--recipe", default="workload", choices=["workload", "paper"],
+    ap.add_argument("--recipe", default="paper", choices=["workload", "paper"],
                     help="training recipe: workload (U(1.5, 20) views, batch 65,536, lr 1e-3) or paper (Eq. 1 "
                          "range, batch 2^19, lr 2e-3 -> 2e-4 with warm-up)")
     ap.add_argument("--keep", type=float, default=0.65)

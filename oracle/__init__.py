@@ -70,6 +70,16 @@ def lib():
         L.orc_mlp_forward_q.argtypes = [dp, C.c_int, dp, C.c_int64, C.c_int, dp]
         L.orc_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
         L.orc_splitmix64.restype = C.c_uint64
+        L.orc_compact_sizes.argtypes = [C.c_int]
+        L.orc_compact_sizes.restype = C.c_int
+        L.orc_cembed.argtypes = [C.c_int64, fp, fp, fp, dp, dp, vp]
+        L.orc_cinputs.argtypes = [C.c_int64, i64, C.c_int64, fp, dp, dp, dp, C.c_double, C.c_double, C.c_double,
+                                  C.c_double, dp]
+        L.orc_cmlp_forward.argtypes = [dp, dp, C.c_int64, dp, vp]
+        L.orc_cquery.argtypes = [C.c_int64, fp, dp, dp, dp, dp, C.c_double, C.c_double, C.c_double, C.c_double,
+                                 C.c_int, u8, dp, vp]
+        L.orc_cbce_backward.argtypes = [dp, dp, dp, dp, vp, C.c_int64, dp]
+        L.orc_cbce_backward.restype = C.c_double
         _lib = L
     return _lib
 
@@ -196,6 +206,7 @@ def query(scene, use_mlp: bool = True, cams=None, want_margin: bool = False):
     logit = np.full((len(cams), P), np.nan)
     margin = np.zeros((len(cams), P)) if want_margin else None
     params64 = [_f64(a.mlp.params) for a in scene.assets]
+    embeds = [cembed(a)[0] if a.mlp.kind == 1 else None for a in scene.assets]
     L = lib()
     for k, cam in enumerate(cams):
         ca = cam_array(cam)
@@ -206,14 +217,64 @@ def query(scene, use_mlp: bool = True, cams=None, want_margin: bool = False):
             st = np.zeros(n, np.uint8)
             lg = np.zeros(n)
             mg = np.zeros(n) if want_margin else None
-            L.orc_query(n, np.ascontiguousarray(a.mean), inst_array(inst), ca, params64[inst.asset],
-                        sp.width, sp.bands, sp.mean_scale, sp.cam_scale, sp.train_focal, sp.d_min,
-                        sp.d_max, int(use_mlp), st, lg, _ptr(mg))
+            if sp.kind == 1:
+                L.orc_cquery(n, np.ascontiguousarray(a.mean), embeds[inst.asset], inst_array(inst), ca,
+                             params64[inst.asset], sp.mean_scale, sp.train_focal, sp.d_min, sp.d_max,
+                             int(use_mlp), st, lg, _ptr(mg))
+            else:
+                L.orc_query(n, np.ascontiguousarray(a.mean), inst_array(inst), ca, params64[inst.asset],
+                            sp.width, sp.bands, sp.mean_scale, sp.cam_scale, sp.train_focal, sp.d_min,
+                            sp.d_max, int(use_mlp), st, lg, _ptr(mg))
             state[k, off[i]:off[i + 1]] = st
             logit[k, off[i]:off[i + 1]] = lg
             if want_margin:
                 margin[k, off[i]:off[i + 1]] = mg
     return (state, logit, margin) if want_margin else (state, logit)
+
+
+# ----------------------------------------------------------------------------
+# the compact MLP form (Sec. 3.2, 3.3, 4.1)
+# ----------------------------------------------------------------------------
+def cembed(asset):
+    """Embeddings [n, 6] of every Gaussian from the asset's embedding MLP, and
+    the embedding inputs [n, 8] (opacity, log scales, unit quaternion w >= 0)."""
+    n = asset.n
+    E = np.zeros((n, 6))
+    XE = np.zeros((n, 8))
+    lib().orc_cembed(n, np.ascontiguousarray(asset.scale), np.ascontiguousarray(asset.quat),
+                     np.ascontiguousarray(asset.opacity), _f64(asset.mlp.params), E, _ptr(XE))
+    return E, XE
+
+
+def cinputs(asset, inst, cam, gidx, E=None):
+    """The 16 visibility inputs [m, 16] of Gaussians gidx under an instance and camera."""
+    if E is None:
+        E = cembed(asset)[0]
+    gidx = np.ascontiguousarray(gidx, np.int64)
+    X = np.zeros((len(gidx), 16))
+    sp = asset.mlp
+    lib().orc_cinputs(len(gidx), gidx, asset.n, np.ascontiguousarray(asset.mean), np.ascontiguousarray(E),
+                      inst_array(inst), cam_array(cam), sp.train_focal, sp.d_min, sp.d_max, sp.mean_scale, X)
+    return X
+
+
+def cmlp_forward(params, X):
+    """Logits and the sum |wo h2| + |bo| of the compact visibility MLP."""
+    X = _f64(X)
+    z = np.zeros(X.shape[0])
+    sc = np.zeros(X.shape[0])
+    lib().orc_cmlp_forward(_f64(params), X, X.shape[0], z, _ptr(sc))
+    return z, sc
+
+
+def cbce_backward(params, XV, XE, y, w=None):
+    """Mean (weighted) BCE of the joint compact model and its gradient over all
+    parameters (visibility, then embedding)."""
+    B = len(y)
+    dP = np.zeros(lib().orc_compact_sizes(0) + lib().orc_compact_sizes(1))
+    loss = lib().orc_cbce_backward(_f64(params), _f64(XV), _f64(XE), _f64(y), _ptr(_f64(w) if w is not None else None),
+                                   B, dP)
+    return loss, dP
 
 
 def compact(state: np.ndarray) -> List[np.ndarray]:

@@ -735,3 +735,268 @@ uint64_t orc_splitmix64(uint64_t seed, uint64_t i) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// The paper's compact MLP form (Sec. 3.2, 3.3, 4.1).  A secondary MLP maps a
+// Gaussian's opacity, scales and rotation to a 6-D embedding, computed once
+// per asset; the visibility MLP takes 16 inputs: the normalised mean, the
+// unit direction from the camera to the Gaussian, the camera distance mapped
+// to [-1, 1] by min-max over the asset's distance range, the camera forward
+// vector (all in the asset frame) and the embedding.  Both have two hidden
+// layers of 32 ReLU units; outputs 1 (logit) and 6 (linear).
+// Parameters (one packed vector): visibility W1[32][16] b1[32] W2[32][32]
+// b2[32] wo[32] bo, then embedding E1[32][8] e1[32] E2[32][32] e2[32]
+// E3[6][32] e3[6].
+// ---------------------------------------------------------------------------
+constexpr int kCH = 32, kCIn = 16, kCEIn = 8, kCEOut = 6;
+constexpr int kCVis = kCH * kCIn + kCH + kCH * kCH + kCH + kCH + 1;                // 1633
+constexpr int kCEmb = kCH * kCEIn + kCH + kCH * kCH + kCH + kCEOut * kCH + kCEOut;  // 1542
+
+// y = W x + b for a row-major W [rows][cols]
+static void dense(const double* W, const double* b, int rows, int cols, const double* x, double* y) {
+  for (int r = 0; r < rows; ++r) {
+    double s = b[r];
+    for (int k = 0; k < cols; ++k) s += W[(size_t)r * cols + k] * x[k];
+    y[r] = s;
+  }
+}
+
+// embedding inputs: opacity, log scales, unit quaternion with w >= 0 (q and -q
+// are the same rotation)
+static void cembed_input(double o, const double* s, const double* q, double* xe) {
+  xe[0] = o;
+  for (int k = 0; k < 3; ++k) xe[1 + k] = std::log(s[k]);
+  double n = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  double sg = q[0] < 0 ? -1.0 : 1.0;
+  for (int k = 0; k < 4; ++k) xe[4 + k] = sg * q[k] / n;
+}
+
+// embedding MLP; pre1/pre2 (nullable) receive the hidden pre-activations
+static void cembed(const double* PE, const double* xe, double* e, double* pre1, double* pre2) {
+  const double* E1 = PE;
+  const double* e1 = E1 + kCH * kCEIn;
+  const double* E2 = e1 + kCH;
+  const double* e2 = E2 + kCH * kCH;
+  const double* E3 = e2 + kCH;
+  const double* e3 = E3 + kCEOut * kCH;
+  double a[kCH], h[kCH], a2[kCH], h2[kCH];
+  dense(E1, e1, kCH, kCEIn, xe, a);
+  for (int r = 0; r < kCH; ++r) h[r] = a[r] > 0 ? a[r] : 0.0;
+  dense(E2, e2, kCH, kCH, h, a2);
+  for (int r = 0; r < kCH; ++r) h2[r] = a2[r] > 0 ? a2[r] : 0.0;
+  dense(E3, e3, kCEOut, kCH, h2, e);
+  if (pre1) std::copy(a, a + kCH, pre1);
+  if (pre2) std::copy(a2, a2 + kCH, pre2);
+}
+
+// visibility MLP: logit; scale (nullable) = sum |wo h2| + |bo| (the size of
+// the terms the logit is a sum of)
+static double cvis(const double* PV, const double* x, double* pre1, double* pre2, double* scale) {
+  const double* W1 = PV;
+  const double* b1 = W1 + kCH * kCIn;
+  const double* W2 = b1 + kCH;
+  const double* b2 = W2 + kCH * kCH;
+  const double* wo = b2 + kCH;
+  double a[kCH], h[kCH], a2[kCH];
+  dense(W1, b1, kCH, kCIn, x, a);
+  for (int r = 0; r < kCH; ++r) h[r] = a[r] > 0 ? a[r] : 0.0;
+  dense(W2, b2, kCH, kCH, h, a2);
+  double z = wo[kCH], sc = std::fabs(wo[kCH]);
+  for (int r = 0; r < kCH; ++r) {
+    double h2 = a2[r] > 0 ? a2[r] : 0.0;
+    z += wo[r] * h2;
+    sc += std::fabs(wo[r] * h2);
+  }
+  if (pre1) std::copy(a, a + kCH, pre1);
+  if (pre2) std::copy(a2, a2 + kCH, pre2);
+  if (scale) *scale = sc;
+  return z;
+}
+
+// The first ten visibility inputs of Gaussian mean mu (asset frame) under an
+// instance and camera: sigma_mu mu, the unit direction from the camera to the
+// Gaussian, the distance corrected by f_t / f_r (Eq. 2, pixel focal lengths;
+// the instance scale is undone by working in the asset frame) and mapped to
+// [-1, 1] over [d_min, d_max] (clamped), and the camera forward vector.
+static void cinputs10(const Inst& in, const Cam& c, double train_focal, double d_min, double d_max,
+                      double mean_scale, const double* mu, double* x) {
+  double d[3] = {c.pos[0] - in.t[0], c.pos[1] - in.t[1], c.pos[2] - in.t[2]};
+  double r[3], cl[3];
+  mat3t_vec(in.R, d, r);
+  for (int k = 0; k < 3; ++k) cl[k] = r[k] / in.s;
+  double v[3] = {mu[0] - cl[0], mu[1] - cl[1], mu[2] - cl[2]};
+  double len = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+  double dt = len * train_focal / c.focal();
+  double dn = 2.0 * (dt - d_min) / (d_max - d_min) - 1.0;
+  dn = std::min(1.0, std::max(-1.0, dn));
+  double fw[3];
+  mat3t_vec(in.R, c.R + 6, fw);  // forward row of R_c, into the asset frame
+  for (int k = 0; k < 3; ++k) {
+    x[k] = mean_scale * mu[k];
+    x[3 + k] = v[k] / len;
+    x[7 + k] = fw[k];
+  }
+  x[6] = dn;
+}
+
+extern "C" {
+
+int orc_compact_sizes(int which) { return which == 0 ? kCVis : kCEmb; }
+
+// embeddings E [n][6] of every Gaussian of an asset (P: full parameter vector)
+void orc_cembed(int64_t n, const float* scale, const float* quat, const float* opacity, const double* P,
+                double* E, double* XE) {
+#pragma omp parallel for schedule(static)
+  for (int64_t g = 0; g < n; ++g) {
+    double s[3] = {scale[g], scale[n + g], scale[2 * n + g]};
+    double q[4] = {quat[g], quat[n + g], quat[2 * n + g], quat[3 * n + g]};
+    double xe[kCEIn];
+    cembed_input(opacity[g], s, q, xe);
+    cembed(P + kCVis, xe, E + g * kCEOut, nullptr, nullptr);
+    if (XE) std::copy(xe, xe + kCEIn, XE + g * kCEIn);
+  }
+}
+
+// visibility inputs X [m][16] of Gaussians gidx under an instance and camera
+void orc_cinputs(int64_t m, const int64_t* gidx, int64_t n, const float* mean, const double* E,
+                 const double* inst_p, const double* cam_p, double train_focal, double d_min, double d_max,
+                 double mean_scale, double* X) {
+  Inst in = load_inst(inst_p);
+  Cam c = load_cam(cam_p);
+  for (int64_t j = 0; j < m; ++j) {
+    const int64_t g = gidx[j];
+    double mu[3] = {mean[g], mean[n + g], mean[2 * n + g]};
+    double* x = X + j * kCIn;
+    cinputs10(in, c, train_focal, d_min, d_max, mean_scale, mu, x);
+    for (int k = 0; k < kCEOut; ++k) x[10 + k] = E[g * kCEOut + k];
+  }
+}
+
+void orc_cmlp_forward(const double* P, const double* X, int64_t B, double* z, double* scale) {
+  for (int64_t b = 0; b < B; ++b) z[b] = cvis(P, X + b * kCIn, nullptr, nullptr, scale ? scale + b : nullptr);
+}
+
+// Cull + compact-MLP query for every Gaussian of one (instance, camera): as
+// orc_query; the gate compares the corrected distance of the camera from the
+// asset centre with d_min.
+void orc_cquery(int64_t n, const float* mean, const double* E, const double* inst_p, const double* cam_p,
+                const double* P, double mean_scale, double train_focal, double d_min, double d_max, int use_mlp,
+                uint8_t* state, double* logit, double* margin) {
+  Inst in = load_inst(inst_p);
+  Cam c = load_cam(cam_p);
+  double cl[3];
+  local_camera(in, c, train_focal, 0.0, cl);
+  double cl_len = std::sqrt(cl[0] * cl[0] + cl[1] * cl[1] + cl[2] * cl[2]);
+  bool gate_open = cl_len >= d_min;
+#pragma omp parallel for schedule(static)
+  for (int64_t g = 0; g < n; ++g) {
+    double mu[3] = {mean[g], mean[n + g], mean[2 * n + g]};
+    double w[3], p[3], fm;
+    world_mean(in, mu, w);
+    cam_space(c, w, p);
+    bool inside = in_frustum(c, p, &fm);
+    logit[g] = std::numeric_limits<double>::quiet_NaN();
+    if (margin) margin[g] = fm;
+    if (!inside) { state[g] = 0; continue; }
+    if (!use_mlp || !gate_open) { state[g] = 2; continue; }
+    double x[kCIn];
+    cinputs10(in, c, train_focal, d_min, d_max, mean_scale, mu, x);
+    for (int k = 0; k < kCEOut; ++k) x[10 + k] = E[g * kCEOut + k];
+    double sc;
+    double z = cvis(P, x, nullptr, nullptr, &sc);
+    logit[g] = z;
+    state[g] = z >= 0.0 ? 2 : 1;
+    if (margin) margin[g] = std::min(fm, std::fabs(z) / std::max(sc, 1e-300));
+  }
+}
+
+// Weighted BCE-with-logits over a batch of the joint model (the embedding of
+// each sample computed from its inputs XE [B][8], the other ten visibility
+// inputs XV [B][10]), and the gradient dP [kCVis + kCEmb] of the mean loss.
+double orc_cbce_backward(const double* P, const double* XV, const double* XE, const double* y, const double* wts,
+                         int64_t B, double* dP) {
+  std::fill(dP, dP + kCVis + kCEmb, 0.0);
+  const double* W1 = P;
+  const double* W2 = W1 + kCH * kCIn + kCH;
+  const double* wo = W2 + kCH * kCH + kCH;
+  const double* PE = P + kCVis;
+  const double* E2 = PE + kCH * kCEIn + kCH;
+  const double* E3 = E2 + kCH * kCH + kCH;
+  double* dW1 = dP;
+  double* db1 = dW1 + kCH * kCIn;
+  double* dW2 = db1 + kCH;
+  double* db2 = dW2 + kCH * kCH;
+  double* dwo = db2 + kCH;
+  double* dE1 = dP + kCVis;
+  double* de1 = dE1 + kCH * kCEIn;
+  double* dE2 = de1 + kCH;
+  double* de2 = dE2 + kCH * kCH;
+  double* dE3 = de2 + kCH;
+  double* de3 = dE3 + kCEOut * kCH;
+  double loss = 0.0;
+  // serial over the batch: the gradient is a sum in a fixed order
+  for (int64_t b = 0; b < B; ++b) {
+    double x[kCIn], pe1[kCH], pe2[kCH], p1[kCH], p2[kCH];
+    const double* xe = XE + b * kCEIn;
+    for (int k = 0; k < 10; ++k) x[k] = XV[b * 10 + k];
+    cembed(PE, xe, x + 10, pe1, pe2);
+    double z = cvis(P, x, p1, p2, nullptr);
+    double wb = wts ? wts[b] : 1.0, yb = y[b];
+    loss += wb * (std::max(z, 0.0) - z * yb + std::log1p(std::exp(-std::fabs(z))));
+    double dz = wb * (1.0 / (1.0 + std::exp(-z)) - yb) / (double)B;
+    // visibility output and hidden layers
+    double d2[kCH], d1[kCH], dx[kCIn];
+    for (int r = 0; r < kCH; ++r) {
+      double h2 = p2[r] > 0 ? p2[r] : 0.0;
+      dwo[r] += dz * h2;
+      d2[r] = dz * wo[r] * (p2[r] > 0 ? 1.0 : 0.0);
+    }
+    dwo[kCH] += dz;
+    for (int r = 0; r < kCH; ++r) {
+      db2[r] += d2[r];
+      for (int k = 0; k < kCH; ++k) dW2[r * kCH + k] += d2[r] * (p1[k] > 0 ? p1[k] : 0.0);
+    }
+    for (int k = 0; k < kCH; ++k) {
+      double s = 0;
+      for (int r = 0; r < kCH; ++r) s += d2[r] * W2[r * kCH + k];
+      d1[k] = s * (p1[k] > 0 ? 1.0 : 0.0);
+    }
+    for (int r = 0; r < kCH; ++r) {
+      db1[r] += d1[r];
+      for (int k = 0; k < kCIn; ++k) dW1[r * kCIn + k] += d1[r] * x[k];
+    }
+    for (int k = 0; k < kCIn; ++k) {
+      double s = 0;
+      for (int r = 0; r < kCH; ++r) s += d1[r] * W1[r * kCIn + k];
+      dx[k] = s;
+    }
+    // embedding: output (linear), then its two hidden layers
+    double g2[kCH], g1[kCH];
+    for (int r = 0; r < kCEOut; ++r) {
+      const double de = dx[10 + r];
+      de3[r] += de;
+      for (int k = 0; k < kCH; ++k) dE3[r * kCH + k] += de * (pe2[k] > 0 ? pe2[k] : 0.0);
+    }
+    for (int k = 0; k < kCH; ++k) {
+      double s = 0;
+      for (int r = 0; r < kCEOut; ++r) s += dx[10 + r] * E3[r * kCH + k];
+      g2[k] = s * (pe2[k] > 0 ? 1.0 : 0.0);
+    }
+    for (int r = 0; r < kCH; ++r) {
+      de2[r] += g2[r];
+      for (int k = 0; k < kCH; ++k) dE2[r * kCH + k] += g2[r] * (pe1[k] > 0 ? pe1[k] : 0.0);
+    }
+    for (int k = 0; k < kCH; ++k) {
+      double s = 0;
+      for (int r = 0; r < kCH; ++r) s += g2[r] * E2[r * kCH + k];
+      g1[k] = s * (pe1[k] > 0 ? 1.0 : 0.0);
+    }
+    for (int r = 0; r < kCH; ++r) {
+      de1[r] += g1[r];
+      for (int k = 0; k < kCEIn; ++k) dE1[r * kCEIn + k] += g1[r] * xe[k];
+    }
+  }
+  return loss / (double)B;
+}
+
+}  // extern "C"

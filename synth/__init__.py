@@ -55,6 +55,7 @@ class MLPSpec:
     train_focal: float = 548.9  # focal length (pixels) of the training views: (H/2) / tan(fovy/2)
     d_min: float = 0.0          # minimum-distance gate (0 = off)
     d_max: float = 0.0          # far clamp of the local camera distance (0 = off)
+    kind: int = 0               # 0: frequency-encoded 72-input MLP; 1: the compact 16-input form
 
 
 @dataclass
@@ -127,6 +128,31 @@ def mlp_params(width: int, g: np.random.Generator, in_dim: int = 72, hidden: int
     parts.append(g.uniform(-b, b, size=width))
     parts.append(g.uniform(-b, b, size=1))
     return np.concatenate(parts).astype(np.float32)
+
+
+COMPACT_VIS_PARAMS = 32 * 16 + 32 + 32 * 32 + 32 + 32 + 1
+COMPACT_EMB_PARAMS = 32 * 8 + 32 + 32 * 32 + 32 + 6 * 32 + 6
+
+
+def compact_params(g: np.random.Generator) -> np.ndarray:
+    """The compact form's packed parameters (visibility 16-32-32-1, then the
+    embedding 8-32-32-6), each layer U(-1/sqrt(fan_in), 1/sqrt(fan_in))."""
+    parts = []
+    for rows, fan in ((32, 16), (32, 32), (1, 32), (32, 8), (32, 32), (6, 32)):
+        b = 1.0 / math.sqrt(fan)
+        parts.append(g.uniform(-b, b, size=(rows, fan)).ravel())
+        parts.append(g.uniform(-b, b, size=rows))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def make_compact(asset, seed: int, d_min: float, d_max: float):
+    """The asset with the compact MLP form (seeded weights), normalising the
+    camera distance over [d_min, d_max]."""
+    import copy
+    a = copy.copy(asset)
+    a.mlp = MLPSpec(params=compact_params(rng(seed)), width=32, bands=0, mean_scale=asset.mlp.mean_scale,
+                    cam_scale=0.0, train_focal=asset.mlp.train_focal, d_min=d_min, d_max=d_max, kind=1)
+    return a
 
 
 def mlp_param_count(width: int, in_dim: int = 72, hidden: int = 3) -> int:

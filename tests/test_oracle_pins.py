@@ -683,3 +683,159 @@ def test_radius_clipping_by_covariance_determinant(orc):
     assert np.array_equal(img, ref)
     full = orc.render_camera(*orc.project(sc2, cam, np.arange(2)), cam, 8, want_margin=False)["image"]
     assert not np.array_equal(full, img)
+
+
+# ---------------------------------------------------------------------------
+# the compact MLP form (Sec. 3.2, 3.3, 4.1)
+# ---------------------------------------------------------------------------
+def _np_compact(P, X, XE=None):
+    """The two compact MLPs written out with NumPy matmuls."""
+    P = np.asarray(P, np.float64)
+    o = 0
+    def take(r, c):
+        nonlocal o
+        W = P[o:o + r * c].reshape(r, c); o += r * c
+        b = P[o:o + r]; o += r
+        return W, b
+    W1, b1 = take(32, 16); W2, b2 = take(32, 32); wo, bo = take(1, 32)
+    E1, e1 = take(32, 8); E2, e2 = take(32, 32); E3, e3 = take(6, 32)
+    relu = lambda a: np.maximum(a, 0)
+    if XE is not None:
+        emb = relu(relu(XE @ E1.T + e1) @ E2.T + e2) @ E3.T + e3
+        X = np.concatenate([X[:, :10], emb], 1)
+    return (relu(relu(X @ W1.T + b1) @ W2.T + b2) @ wo.T + bo)[:, 0]
+
+
+def test_compact_mlps_equal_numpy_chain(orc):
+    g = np.random.default_rng(3)
+    P = synth.compact_params(g).astype(np.float64)
+    assert P.size == synth.COMPACT_VIS_PARAMS + synth.COMPACT_EMB_PARAMS == 3175
+    X = g.uniform(-1, 1, (64, 16))
+    z, _ = orc.cmlp_forward(P, X)
+    np.testing.assert_allclose(z, _np_compact(P, X), rtol=1e-12, atol=1e-12)
+    a = one_gaussian_asset((0.1, 0.2, 0.3), (0.02, 0.03, 0.05), quat=(0.3, -0.5, 0.2, 0.7), opacity=0.6)
+    a.mlp = synth.MLPSpec(params=P.astype(np.float32), width=32, bands=0, kind=1)
+    E, XE = orc.cembed(a)
+    Pf = a.mlp.params.astype(np.float64)
+    emb_ref = _np_compact(Pf, np.zeros((1, 16)), XE)  # visibility of [0, E]: checks E through a second path
+    x = np.concatenate([np.zeros(10), E[0]])[None]
+    np.testing.assert_allclose(orc.cmlp_forward(Pf, x)[0], emb_ref, rtol=1e-12, atol=1e-12)
+
+
+def test_compact_embedding_inputs_and_quaternion_sign(orc):
+    q = (0.3, -0.5, 0.2, 0.7)
+    a = one_gaussian_asset((0, 0, 0), (0.02, 0.03, 0.05), quat=q, opacity=0.6)
+    b = one_gaussian_asset((0, 0, 0), (0.02, 0.03, 0.05), quat=tuple(-np.float32(v) for v in q), opacity=0.6)
+    P = synth.compact_params(np.random.default_rng(1))
+    for x in (a, b):
+        x.mlp = synth.MLPSpec(params=P, width=32, bands=0, kind=1)
+    Ea, XEa = orc.cembed(a)
+    Eb, XEb = orc.cembed(b)
+    qn = np.float32(q).astype(np.float64) / np.linalg.norm(np.float32(q).astype(np.float64))
+    assert abs(XEa[0, 0] - np.float32(0.6)) < 1e-12
+    np.testing.assert_allclose(XEa[0, 1:4], np.log(np.float32([0.02, 0.03, 0.05]).astype(np.float64)), atol=1e-12)
+    np.testing.assert_allclose(XEa[0, 4:], qn, atol=1e-12)
+    np.testing.assert_array_equal(XEa, XEb)  # q and -q: the same rotation, the same embedding
+    np.testing.assert_array_equal(Ea, Eb)
+
+
+def test_compact_inputs_closed_form_and_invariance(orc):
+    """Identity instance, camera on the x axis at distance D looking at the
+    origin: a Gaussian at the origin sees direction (-1, 0, 0), forward
+    (-1, 0, 0) and distance D f_t / f_r mapped to [-1, 1]; an instance scaled
+    by s at the same camera distance halves / scales that distance, and a
+    rigid motion of camera and instance together changes no input."""
+    D, res, fov = 6.0, 96, 50.0
+    cam = synth.camera((D, 0.0, 0.0), width=res, height=res, fovy_deg=fov)
+    a = one_gaussian_asset((0, 0, 0), (0.02, 0.03, 0.05))
+    ft = float(np.float32(0.5 * 512 / math.tan(math.radians(fov) / 2)))
+    a.mlp = synth.MLPSpec(params=synth.compact_params(np.random.default_rng(2)), width=32, bands=0,
+                          mean_scale=0.5, train_focal=ft, d_min=2.0, d_max=50.0, kind=1)
+    fr = 0.5 * res / math.tan(float(np.float32(math.radians(fov))) / 2)
+    x = orc.cinputs(a, synth.identity_instance(0), cam, [0])[0]
+    np.testing.assert_allclose(x[:3], 0.0, atol=1e-15)
+    np.testing.assert_allclose(x[3:6], [-1, 0, 0], atol=1e-12)
+    np.testing.assert_allclose(x[7:10], [-1, 0, 0], atol=1e-6)
+    dt = D * ft / fr
+    assert abs(x[6] - (2 * (dt - 2.0) / 48.0 - 1)) < 1e-9
+    # an instance scaled by 2 at the origin: the local distance halves
+    inst2 = Instance(asset=0, R=np.eye(3, dtype=np.float32), s=2.0, t=np.zeros(3, np.float32))
+    x2 = orc.cinputs(a, inst2, cam, [0])[0]
+    assert abs(x2[6] - (2 * (dt / 2 - 2.0) / 48.0 - 1)) < 1e-9
+    # rigid motion of the world (exactly representable: a 90 degree yaw and an integer shift)
+    Rz = np.array([[0, -1, 0], [1, 0, 0], [0, 0, 1]], np.float32)
+    inst3 = Instance(asset=0, R=Rz, s=1.0, t=np.array([3, -2, 1], np.float32))
+    cam3 = Camera(pos=(Rz.astype(np.float64) @ cam.pos.astype(np.float64) + [3, -2, 1]).astype(np.float32),
+                  R=(cam.R.astype(np.float64) @ Rz.T.astype(np.float64)).astype(np.float32), fovy=cam.fovy,
+                  width=res, height=res)
+    x3 = orc.cinputs(a, inst3, cam3, [0])[0]
+    np.testing.assert_allclose(x3, x, atol=1e-6)
+    # far beyond the range the distance input saturates at 1
+    far = synth.camera((500.0, 0.0, 0.0), width=res, height=res, fovy_deg=fov)
+    assert orc.cinputs(a, synth.identity_instance(0), far, [0])[0][6] == 1.0
+
+
+def test_compact_backward_central_differences(orc):
+    g = np.random.default_rng(11)
+    P = synth.compact_params(g).astype(np.float64)
+    B = 24
+    XV = np.concatenate([g.uniform(-1, 1, (B, 3)), g.standard_normal((B, 3)), g.uniform(-1, 1, (B, 1)),
+                         g.standard_normal((B, 3))], 1)
+    XE = np.concatenate([g.uniform(0.1, 1, (B, 1)), g.normal(-4.5, 0.3, (B, 3)), g.standard_normal((B, 4))], 1)
+    y = (g.uniform(0, 1, B) > 0.5).astype(np.float64)
+    w = g.uniform(0.5, 2.0, B)
+    loss, dP = orc.cbce_backward(P, XV, XE, y, w)
+
+    def pre_acts(Pp):
+        # every hidden pre-activation of the batch (to skip parameters whose step crosses a ReLU kink)
+        o = 0
+        def take(r, c):
+            nonlocal o
+            W = Pp[o:o + r * c].reshape(r, c); o += r * c
+            b = Pp[o:o + r]; o += r
+            return W, b
+        W1, b1 = take(32, 16); W2, b2 = take(32, 32); take(1, 32)
+        E1, e1 = take(32, 8); E2, e2 = take(32, 32); E3, e3 = take(6, 32)
+        a1 = XE @ E1.T + e1; a2 = np.maximum(a1, 0) @ E2.T + e2
+        emb = np.maximum(a2, 0) @ E3.T + e3
+        X = np.concatenate([XV, emb], 1)
+        v1 = X @ W1.T + b1; v2 = np.maximum(v1, 0) @ W2.T + b2
+        return np.concatenate([a1.ravel(), a2.ravel(), v1.ravel(), v2.ravel()])
+
+    eps = 1e-3
+    base = np.sign(pre_acts(P))
+    checked = 0
+    for k in range(P.size):
+        Pp, Pm = P.copy(), P.copy()
+        Pp[k] += eps; Pm[k] -= eps
+        if not (np.array_equal(np.sign(pre_acts(Pp)), base) and np.array_equal(np.sign(pre_acts(Pm)), base)):
+            continue
+        lp, _ = orc.cbce_backward(Pp, XV, XE, y, w)
+        lm, _ = orc.cbce_backward(Pm, XV, XE, y, w)
+        fd = (lp - lm) / (2 * eps)
+        assert abs(fd - dP[k]) <= 1e-3 * max(abs(dP[k]), 1e-6 * np.abs(dP).max()) + 1e-9, k
+        checked += 1
+    assert checked > 0.9 * P.size
+    # the loss itself
+    z = _np_compact(P, XV, XE)
+    assert abs(loss - np.mean(w * (np.logaddexp(0, z) - z * y))) < 1e-12
+
+
+def test_compact_query_gate(orc):
+    """Below the minimum distance every in-frustum Gaussian is kept without a
+    query; beyond it the keep decision is the sign of the compact MLP's logit."""
+    a = synth.make_asset("sphere", 400, 0, 77, width=16)
+    # 48 px views with the 512 px training focal: distances are corrected by about 11.4
+    a = synth.make_compact(a, seed=5, d_min=40.0, d_max=200.0)
+    near = synth.camera((0.0, -2.5, 0.5), width=48, height=48)   # corrected ~29 < d_min
+    far = synth.camera((0.0, -6.0, 1.0), width=48, height=48)    # corrected ~69 > d_min
+    sc = Scene(assets=[a], instances=[synth.identity_instance(0)], cameras=[near, far])
+    st, lg = orc.query(sc)
+    inside = st > 0
+    assert inside[0].any() and inside[1].any()
+    assert np.all(st[0][inside[0]] == 2) and np.all(np.isnan(lg[0]))
+    q = inside[1]
+    X = orc.cinputs(a, synth.identity_instance(0), far, np.flatnonzero(q))
+    z, _ = orc.cmlp_forward(a.mlp.params, X)
+    np.testing.assert_array_equal(lg[1][q], z)
+    np.testing.assert_array_equal(st[1][q] == 2, z >= 0)
