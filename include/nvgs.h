@@ -87,10 +87,22 @@ typedef struct nvgs_create_info {
  * in order.  A pair is kept iff the logit is >= 0.  If |c_local| < d_min
  * the MLP is not queried and every in-frustum Gaussian is kept (Sec. 3.3). */
 typedef struct nvgs_mlp {
-  int32_t width; /* 64 or 128 */
-  int32_t bands; /* 6 */
+  int32_t width; /* 64 or 128 (kind 0); 32 (kind 1) */
+  int32_t bands; /* 6 (kind 0); ignored (kind 1) */
   const float* params;
   float mean_scale, cam_scale, train_focal, d_min, d_max;
+  int32_t kind;  /* 0: the frequency-encoded MLP above.  1: the paper's compact form
+                    (Sec. 3.2, 3.3, 4.1): params = visibility W1[32][16], b1[32],
+                    W2[32][32], b2[32], wo[32], bo, then embedding E1[32][8], e1[32],
+                    E2[32][32], e2[32], E3[6][32], e3[6] (3175 floats); the embedding
+                    MLP maps (opacity, ln scale x3, unit quaternion with w >= 0) of each
+                    Gaussian to 6 values once at load time; the visibility inputs are
+                    (mean_scale * mu, unit direction camera -> Gaussian, distance
+                    |mu - c_local| * train_focal / f_render mapped linearly from
+                    [d_min, d_max] to [-1, 1] and clamped, camera forward in the asset
+                    frame, embedding), ReLU hidden layers; requires d_max > d_min >= 0;
+                    cam_scale is unused; FP32 and BF16 only.  All assets of a context
+                    share the kind. */
 } nvgs_mlp;
 
 /* One asset, float32 structure-of-arrays in device memory (borrowed). */

@@ -76,6 +76,7 @@ def lib():
         L.orc_cinputs.argtypes = [C.c_int64, i64, C.c_int64, fp, dp, dp, dp, C.c_double, C.c_double, C.c_double,
                                   C.c_double, dp]
         L.orc_cmlp_forward.argtypes = [dp, dp, C.c_int64, dp, vp]
+        L.orc_cmlp_forward_bf16.argtypes = [dp, dp, C.c_int64, dp]
         L.orc_cquery.argtypes = [C.c_int64, fp, dp, dp, dp, dp, C.c_double, C.c_double, C.c_double, C.c_double,
                                  C.c_int, u8, dp, vp]
         L.orc_cbce_backward.argtypes = [dp, dp, dp, dp, vp, C.c_int64, dp]
@@ -265,6 +266,15 @@ def cmlp_forward(params, X):
     sc = np.zeros(X.shape[0])
     lib().orc_cmlp_forward(_f64(params), X, X.shape[0], z, _ptr(sc))
     return z, sc
+
+
+def cmlp_forward_bf16(params, X):
+    """Logits of the compact visibility MLP with its second-layer operands
+    rounded to BF16 (the reduced-precision form of the query)."""
+    X = _f64(X)
+    z = np.zeros(X.shape[0])
+    lib().orc_cmlp_forward_bf16(_f64(params), X, X.shape[0], z)
+    return z
 
 
 def cbce_backward(params, XV, XE, y, w=None):

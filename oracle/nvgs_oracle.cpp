@@ -876,6 +876,29 @@ void orc_cmlp_forward(const double* P, const double* X, int64_t B, double* z, do
   for (int64_t b = 0; b < B; ++b) z[b] = cvis(P, X + b * kCIn, nullptr, nullptr, scale ? scale + b : nullptr);
 }
 
+// Logits of the compact visibility MLP with its second-layer operands (the
+// weights and the first hidden layer's activations) rounded to BF16; the
+// first layer and the output in FP64 otherwise.  X [B][16].
+void orc_cmlp_forward_bf16(const double* P, const double* X, int64_t B, double* z) {
+  const double* W1 = P;
+  const double* b1 = W1 + kCH * kCIn;
+  const double* W2 = b1 + kCH;
+  const double* b2 = W2 + kCH * kCH;
+  const double* wo = b2 + kCH;
+  for (int64_t b = 0; b < B; ++b) {
+    double a[kCH], h[kCH];
+    dense(W1, b1, kCH, kCIn, X + b * kCIn, a);
+    for (int r = 0; r < kCH; ++r) h[r] = to_bf16(to_f32(a[r] > 0 ? a[r] : 0.0));
+    double zz = wo[kCH];
+    for (int r = 0; r < kCH; ++r) {
+      double s = b2[r];
+      for (int k = 0; k < kCH; ++k) s += to_bf16(W2[r * kCH + k]) * h[k];
+      zz += wo[r] * (s > 0 ? s : 0.0);
+    }
+    z[b] = zz;
+  }
+}
+
 // Cull + compact-MLP query for every Gaussian of one (instance, camera): as
 // orc_query; the gate compares the corrected distance of the camera from the
 // asset centre with d_min.

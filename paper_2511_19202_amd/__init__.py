@@ -43,7 +43,7 @@ class CreateInfo(C.Structure):
 class MLP(C.Structure):
     _fields_ = [("width", C.c_int32), ("bands", C.c_int32), ("params", C.c_void_p),
                 ("mean_scale", C.c_float), ("cam_scale", C.c_float), ("train_focal", C.c_float),
-                ("d_min", C.c_float), ("d_max", C.c_float)]
+                ("d_min", C.c_float), ("d_max", C.c_float), ("kind", C.c_int32)]
 
 
 class Asset(C.Structure):
@@ -211,7 +211,7 @@ class DeviceAsset:
         a.opacity, a.sh = self.opacity.data_ptr(), self.sh.data_ptr()
         sp = self.spec
         a.mlp = MLP(int(sp.width), int(sp.bands), self.params.data_ptr(), float(sp.mean_scale), float(sp.cam_scale),
-                    float(sp.train_focal), float(sp.d_min), float(sp.d_max))
+                    float(sp.train_focal), float(sp.d_min), float(sp.d_max), int(sp.kind))
         return a
 
 

@@ -36,6 +36,7 @@ struct nvgs_ctx {
   std::vector<Buf> op_bufs;
   Buf assets_dev;
   int width = 0;
+  int kind = 0;  // MLP kind shared by the assets
 
   // instances
   std::vector<nvgs_instance> inst;
@@ -278,6 +279,21 @@ int shape_nb(const nvgs_ctx* ctx, int precision) {
   return mlp_shape_supported(ctx->width, precision, ctx->mlp_nb) ? ctx->mlp_nb : 2;
 }
 
+// cull + visibility query of every (camera, instance, Gaussian) pair with the
+// context's MLP kind (mode 1 also writes per-pair state and logits)
+hipError_t launch_query(nvgs_ctx* ctx, int precision, int mode, uint8_t* state, float* logits,
+                        unsigned long long* counts, hipStream_t st) {
+  if (ctx->kind == 1)
+    return launch_cull_cmlp(P_<AssetDev>(ctx->assets_dev), P_<WorkItem>(ctx->items_dev), (int64_t)ctx->items.size(),
+                            P_<int32_t>(ctx->seglist_dev), P_<SegRec>(ctx->segs_dev), P_<float>(ctx->c1_dev), 128,
+                            precision, mode, P_<uint32_t>(ctx->mask), P_<uint32_t>(ctx->chunk_cnt), state, logits,
+                            counts, st);
+  return launch_cull_mlp(P_<AssetDev>(ctx->assets_dev), P_<WorkItem>(ctx->items_dev), (int64_t)ctx->items.size(),
+                         P_<int32_t>(ctx->seglist_dev), P_<SegRec>(ctx->segs_dev), P_<float>(ctx->c1_dev), 128,
+                         ctx->width, precision, shape_nb(ctx, precision), mode, P_<uint32_t>(ctx->mask),
+                         P_<uint32_t>(ctx->chunk_cnt), state, logits, counts, st);
+}
+
 int bits_for(int64_t v) {
   int b = 0;
   while (((int64_t)1 << b) < v) ++b;
@@ -350,15 +366,22 @@ nvgs_status nvgs_load_assets(nvgs_ctx* ctx, const nvgs_asset* a, int32_t n) {
   if (!ctx) return NVGS_E_INVALID;
   if (!a || n <= 0) return fail(ctx, NVGS_E_INVALID, "assets: null pointer or n <= 0");
   int width = a[0].mlp.width;
+  const int kind = a[0].mlp.kind;
+  if (kind != 0 && kind != 1) return fail(ctx, NVGS_E_INVALID, "asset: MLP kind must be 0 or 1");
   for (int j = 0; j < n; ++j) {
     const nvgs_asset& x = a[j];
+    if (x.mlp.kind != kind) return fail(ctx, NVGS_E_INVALID, "assets of one context must share the MLP kind");
     if (x.n <= 0 || x.n >= ((int64_t)1 << 31)) return fail(ctx, NVGS_E_INVALID, "asset: n out of range");
     if (x.sh_degree < 0 || x.sh_degree > 3) return fail(ctx, NVGS_E_INVALID, "asset: sh_degree must be 0..3");
     if (!x.mean || !x.scale || !x.quat || !x.opacity || !x.sh || !x.mlp.params)
       return fail(ctx, NVGS_E_INVALID, "asset: null array");
-    if (x.mlp.width != 64 && x.mlp.width != 128) return fail(ctx, NVGS_E_INVALID, "asset: MLP width must be 64 or 128");
+    if (kind == 0 && x.mlp.width != 64 && x.mlp.width != 128)
+      return fail(ctx, NVGS_E_INVALID, "asset: MLP width must be 64 or 128");
+    if (kind == 1 && x.mlp.width != 32) return fail(ctx, NVGS_E_INVALID, "asset: compact MLP width must be 32");
     if (x.mlp.width != width) return fail(ctx, NVGS_E_INVALID, "assets of one context must share the MLP width");
-    if (x.mlp.bands != 6) return fail(ctx, NVGS_E_INVALID, "asset: MLP bands must be 6");
+    if (kind == 0 && x.mlp.bands != 6) return fail(ctx, NVGS_E_INVALID, "asset: MLP bands must be 6");
+    if (kind == 1 && !(x.mlp.d_max > x.mlp.d_min && x.mlp.d_min >= 0.f))
+      return fail(ctx, NVGS_E_INVALID, "asset: compact MLP needs d_max > d_min >= 0");
     if (!finite_f(x.mlp.mean_scale) || !finite_f(x.mlp.cam_scale) || !finite_f(x.mlp.train_focal) ||
         !finite_f(x.mlp.d_min) || !finite_f(x.mlp.d_max) || x.mlp.train_focal <= 0.f)
       return fail(ctx, NVGS_E_INVALID, "asset: non-finite MLP metadata");
@@ -366,8 +389,9 @@ nvgs_status nvgs_load_assets(nvgs_ctx* ctx, const nvgs_asset* a, int32_t n) {
   CK(hipSetDevice(ctx->device));
   CK(hipStreamSynchronize(ctx->stream));
   for (Buf& b : ctx->op_bufs) release(ctx, b);
-  // per asset: FP32, BF16, FP8 operand images, FP8 scales, projection geometry and SH records
-  ctx->op_bufs.assign(6 * (size_t)n, Buf{});
+  // per asset: FP32, BF16, FP8 operand images, FP8 scales, projection geometry and SH records,
+  // compact-form embeddings
+  ctx->op_bufs.assign(7 * (size_t)n, Buf{});
   ctx->assets.assign(a, a + n);
   ctx->adev.assign(n, AssetDev{});
   for (int j = 0; j < n; ++j) {
@@ -378,7 +402,29 @@ nvgs_status nvgs_load_assets(nvgs_ctx* ctx, const nvgs_asset* a, int32_t n) {
     d.mean_scale = x.mlp.mean_scale; d.cam_scale = x.mlp.cam_scale; d.train_focal = x.mlp.train_focal;
     d.d_min = x.mlp.d_min; d.d_max = x.mlp.d_max;
     d.params = x.mlp.params;
-    Buf* ob = &ctx->op_bufs[6 * (size_t)j];
+    Buf* ob = &ctx->op_bufs[7 * (size_t)j];
+    d.kind = kind;
+    if (kind == 1) {
+      if (!ensure(ctx, ob[0], cmlp_image_floats() * sizeof(float)) || !ensure(ctx, ob[1], 2048 * sizeof(uint16_t)) ||
+          !ensure(ctx, ob[6], 8 * sizeof(float) * (size_t)x.n) ||
+          !ensure(ctx, ob[4], 3 * sizeof(float4) * (size_t)x.n) ||
+          !ensure(ctx, ob[5], sizeof(float) * (size_t)sh_stride_for(x.sh_degree) * (size_t)x.n))
+        return fail(ctx, NVGS_E_NOMEM, "operand images");
+      d.op_f32 = P_<float>(ob[0]);
+      d.op_bf16 = P_<uint16_t>(ob[1]);
+      d.op_fp8 = nullptr;
+      d.fp8_scale = nullptr;
+      d.emb = P_<float>(ob[6]);
+      d.geo = P_<float4>(ob[4]);
+      d.shp = P_<float>(ob[5]);
+      d.sh_stride = sh_stride_for(x.sh_degree);
+      CK(launch_pack_asset(x.mean, x.scale, x.quat, x.opacity, x.sh, x.n, x.sh_degree, P_<float4>(ob[4]),
+                           P_<float>(ob[5]), ctx->stream));
+      CK(launch_prepare_cmlp(x.mlp.params, P_<float>(ob[0]), P_<uint16_t>(ob[1]), ctx->stream));
+      CK(launch_cembed(x.mlp.params, x.scale, x.quat, x.opacity, x.n, P_<float>(ob[6]), ctx->stream));
+      continue;
+    }
+    d.emb = nullptr;
     if (!ensure(ctx, ob[0], mlp_op_f32_floats(width) * sizeof(float)) ||
         !ensure(ctx, ob[1], mlp_op_bf16_elems(width) * sizeof(uint16_t)) ||
         !ensure(ctx, ob[2], mlp_op_fp8_bytes(width)) || !ensure(ctx, ob[3], 16 * sizeof(float)) ||
@@ -401,6 +447,7 @@ nvgs_status nvgs_load_assets(nvgs_ctx* ctx, const nvgs_asset* a, int32_t n) {
   CK(hipMemcpyAsync(ctx->assets_dev.p, ctx->adev.data(), sizeof(AssetDev) * n, hipMemcpyHostToDevice, ctx->stream));
   CK(hipStreamSynchronize(ctx->stream));
   ctx->width = width;
+  ctx->kind = kind;
   ctx->inst.clear();
   ctx->planC = -1;
   ++ctx->gen;
@@ -446,6 +493,8 @@ nvgs_status nvgs_query_visibility(nvgs_ctx* ctx, const nvgs_camera* cams, int32_
   if ((s = check_cams(ctx, cams, C))) return s;
   if (!state) return fail(ctx, NVGS_E_INVALID, "state: null pointer");
   if (precision < NVGS_PREC_FP32 || precision > NVGS_PREC_FP8) return fail(ctx, NVGS_E_INVALID, "bad precision");
+  if (ctx->kind == 1 && precision == NVGS_PREC_FP8)
+    return fail(ctx, NVGS_E_INVALID, "the compact MLP runs in FP32 or BF16");
   CK(hipSetDevice(ctx->device));
   if ((s = plan(ctx, C))) return s;
   if ((s = upload_cams(ctx, cams, C))) return s;
@@ -461,10 +510,7 @@ nvgs_status nvgs_query_visibility(nvgs_ctx* ctx, const nvgs_camera* cams, int32_
     if (!ensure(ctx, scratch, sizeof(float) * (size_t)C * ctx->P)) return fail(ctx, NVGS_E_NOMEM, "logit scratch");
     lg = P_<float>(scratch);
   }
-  CK(launch_cull_mlp(P_<AssetDev>(ctx->assets_dev), P_<WorkItem>(ctx->items_dev), (int64_t)ctx->items.size(),
-                     P_<int32_t>(ctx->seglist_dev), P_<SegRec>(ctx->segs_dev), P_<float>(ctx->c1_dev), 128, ctx->width,
-                     precision, shape_nb(ctx, precision), 1, P_<uint32_t>(ctx->mask), P_<uint32_t>(ctx->chunk_cnt),
-                     state, lg, nullptr, ctx->stream));
+  CK(launch_query(ctx, precision, 1, state, lg, nullptr, ctx->stream));
   if (scratch.p) {
     CK(hipStreamSynchronize(ctx->stream));
     release(ctx, scratch);
@@ -593,10 +639,7 @@ nvgs_status enqueue_frame(nvgs_ctx* ctx, hipStream_t st, const Frame& f, bool ea
   STAGE_END(NVGS_STAGE_SETUP);
   STAGE_BEGIN(NVGS_STAGE_CULL_MLP);
   if (opts->use_mlp)
-    CK(launch_cull_mlp(P_<AssetDev>(ctx->assets_dev), P_<WorkItem>(ctx->items_dev), (int64_t)ctx->items.size(),
-                       P_<int32_t>(ctx->seglist_dev), P_<SegRec>(ctx->segs_dev), P_<float>(ctx->c1_dev), 128,
-                       ctx->width, opts->precision, shape_nb(ctx, opts->precision), 0, P_<uint32_t>(ctx->mask),
-                       P_<uint32_t>(ctx->chunk_cnt), nullptr, nullptr, counts64, st));
+    CK(launch_query(ctx, opts->precision, 0, nullptr, nullptr, counts64, st));
   else
     CK(launch_cull_only(P_<AssetDev>(ctx->assets_dev), P_<WorkItem>(ctx->items_dev), (int64_t)ctx->items.size(),
                         P_<int32_t>(ctx->seglist_dev), P_<SegRec>(ctx->segs_dev), P_<uint32_t>(ctx->mask),
@@ -729,6 +772,8 @@ nvgs_status nvgs_render(nvgs_ctx* ctx, const nvgs_camera* cams, int32_t C, const
   if (T != 8 && T != 16 && T != 32) return fail(ctx, NVGS_E_INVALID, "tile must be 8, 16 or 32");
   if (opts->precision < NVGS_PREC_FP32 || opts->precision > NVGS_PREC_FP8)
     return fail(ctx, NVGS_E_INVALID, "bad precision");
+  if (ctx->kind == 1 && opts->use_mlp && opts->precision == NVGS_PREC_FP8)
+    return fail(ctx, NVGS_E_INVALID, "the compact MLP runs in FP32 or BF16");
   if (opts->split_len > 0 && opts->split_len < 64) return fail(ctx, NVGS_E_INVALID, "split_len must be 0, < 0 or >= 64");
   if (!(opts->det_clip >= 0.f) || !finite_f(opts->det_clip))
     return fail(ctx, NVGS_E_INVALID, "det_clip must be finite and >= 0");
@@ -918,7 +963,8 @@ nvgs_status nvgs_autotune(nvgs_ctx* ctx, const nvgs_camera* cams, int32_t C, nvg
   int best_nb = saved_nb, best_segs = saved_segs;
   float best_cull = INFINITY;
   for (int nb : {1, 2, 4}) {
-    if (!mlp_shape_supported(ctx->width, o.precision, nb)) continue;
+    // the compact MLP has one block shape: only the segment grouping varies
+    if (ctx->kind == 1 ? nb != saved_nb : !mlp_shape_supported(ctx->width, o.precision, nb)) continue;
     for (int segs : {4, 8, 16, 32, 64}) {
       ctx->mlp_nb = nb;
       ctx->mlp_segs = segs;

@@ -44,7 +44,17 @@ struct AssetDev {
   const float4* geo;
   const float* shp;
   int32_t sh_stride;     // 3 (d+1)^2 rounded up to a multiple of 4
+  int32_t kind;          // 0: frequency-encoded MLP; 1: the compact form
+  const float* emb;      // compact form: per-Gaussian embedding [n][8] (6 used), library-owned
 };
+
+// compact MLP form (16 inputs, 2 x 32 hidden, per-Gaussian 6-D embedding)
+constexpr int kCompactVis = 32 * 16 + 32 + 32 * 32 + 32 + 32 + 1;
+constexpr int kCompactEmb = 32 * 8 + 32 + 32 * 32 + 32 + 6 * 32 + 6;
+size_t cmlp_image_floats();  // FP32 operand image (the BF16 one fits in it)
+hipError_t launch_prepare_cmlp(const float* params, float* img_f32, uint16_t* img_bf16, hipStream_t st);
+hipError_t launch_cembed(const float* params, const float* scale, const float* quat, const float* opacity, int64_t n,
+                         float* emb, hipStream_t st);
 
 int32_t sh_stride_for(int sh_degree);
 hipError_t launch_pack_asset(const float* mean, const float* scale, const float* quat, const float* opacity,
@@ -60,7 +70,7 @@ struct SegRec {
   float half_w, half_h;
   int32_t asset, inst, cam, n;
   int32_t query;     // 1 = the MLP decides, 0 = every in-frustum Gaussian is kept
-  int32_t pad0;
+  float dn_a, dn_b;  // compact MLP form: distance input = clamp(dn_a |mu - cl| + dn_b, -1, 1)
   int64_t pair_base;   // cam * P + instance offset  (index into [C][P] outputs)
   int64_t word_base;   // first 32-pair mask word of the segment
   int64_t chunk_base;  // first compaction chunk of the segment
@@ -109,6 +119,10 @@ hipError_t launch_cull_mlp(const AssetDev* assets_dev, const WorkItem* items, in
                            const SegRec* segs, const float* c1perm, int max_width, int width, int precision, int nb,
                            int mode, uint32_t* mask, uint32_t* chunk_count, uint8_t* state, float* logits,
                            unsigned long long* counts, hipStream_t st);
+hipError_t launch_cull_cmlp(const AssetDev* assets, const WorkItem* items, int64_t n_items, const int32_t* seglist,
+                            const SegRec* segs, const float* c1perm, int c1_stride, int precision, int mode,
+                            uint32_t* mask, uint32_t* chunk_count, uint8_t* state, float* logits,
+                            unsigned long long* counts, hipStream_t st);
 
 hipError_t launch_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, uint32_t* partials,
                            hipStream_t st);

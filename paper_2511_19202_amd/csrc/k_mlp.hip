@@ -268,13 +268,27 @@ __global__ void k_segment_setup(const nvgs_camera* __restrict__ cams, const nvgs
     len = (double)A.d_max;
   }
   if (threadIdx.x == 0) s_query = (use_mlp && len >= (double)A.d_min) ? 1 : 0;
-  if (threadIdx.x < 36) {
+  if (A.kind == 1) {
+    // compact form: per-segment vector = b1 + W1[:, forward] (R_i^T forward), in the
+    // lane order kappa(j, g) = 16 (j / 8) + 8 g + j % 8 of the compact kernel
+    double fw[3];
+    for (int r = 0; r < 3; ++r)
+      fw[r] = (double)in.R[r] * cam.R[6] + (double)in.R[3 + r] * cam.R[7] + (double)in.R[6 + r] * cam.R[8];
+    const float* W1 = A.params;
+    const float* b1 = W1 + 32 * 16;
+    for (int e = threadIdx.x; e < 32; e += blockDim.x) {
+      const int gq = e / 16, j = e % 16, kk = 16 * (j / 8) + 8 * gq + (j % 8);
+      double s = b1[kk];
+      for (int q = 0; q < 3; ++q) s += (double)W1[kk * 16 + 7 + q] * fw[q];
+      c1perm[(size_t)seg * c1_stride + e] = (float)s;
+    }
+  } else if (threadIdx.x < 36) {
     int j = threadIdx.x / 12, band = (threadIdx.x % 12) / 2, cs = threadIdx.x % 2;
     double a = ldexp(M_PI * ((double)A.cam_scale * cm[j]), band);
     s_gam[threadIdx.x] = cs ? cos(a) : sin(a);
   }
   __syncthreads();
-  const int W = A.width;
+  const int W = A.kind == 1 ? 0 : A.width;
   const float* W1 = A.params;
   const float* b1 = W1 + (size_t)W * 72;
   for (int r = threadIdx.x; r < W; r += blockDim.x) {
@@ -316,7 +330,10 @@ __global__ void k_segment_setup(const nvgs_camera* __restrict__ cams, const nvgs
     R.cam = k;
     R.n = (int32_t)A.n;
     R.query = s_query;
-    R.pad0 = 0;
+    // compact form: distance input = 2 (|mu - cl| f_t / f_r - d_min) / (d_max - d_min) - 1
+    const double span = (double)A.d_max - (double)A.d_min;
+    R.dn_a = A.kind == 1 ? (float)(2.0 * fac / span) : 0.f;
+    R.dn_b = A.kind == 1 ? (float)(-2.0 * (double)A.d_min / span - 1.0) : 0.f;
     R.pair_base = (int64_t)k * P + inst_offset[i];
     R.word_base = word_base[seg];
     R.chunk_base = chunk_base[seg];

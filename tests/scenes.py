@@ -24,7 +24,8 @@ def calibrate_keep(sc, frac=0.65):
         k = int(np.clip(round((1 - frac) * len(z)), 1, len(z) - 1))
         thr = 0.5 * (z[k - 1] + z[k])
         p = a.mlp.params.copy()
-        p[-1] = np.float32(p[-1] - thr)
+        bo = synth.COMPACT_VIS_PARAMS - 1 if a.mlp.kind == 1 else -1  # the output bias
+        p[bo] = np.float32(p[bo] - thr)
         a.mlp.params = p
     return sc
 
@@ -53,3 +54,27 @@ def small_batched(frame=0, n_cams=3, res=(160, 96), width=64):
 
 def batched_small(**kw):
     return calibrate_keep(small_batched(**kw))
+
+
+def compact(sc, lo=0.5, hi=1.3, seed=50):
+    """The scene with every asset switched to the compact MLP form (Sec. 3.2).
+    Each asset's distance range is set from the FoV-corrected camera distances
+    of its instances (lo and hi times their median), so that some pairs clamp
+    at either end of the range and the nearest segments fall below d_min."""
+    d = {}
+    for cam in sc.cameras:
+        for inst in sc.instances:
+            a = sc.assets[inst.asset]
+            d.setdefault(inst.asset, []).append(np.linalg.norm(oracle.local_camera(inst, cam, a.mlp.train_focal)))
+    for j in range(len(sc.assets)):
+        med = float(np.median(d.get(j, [1.0])))
+        sc.assets[j] = synth.make_compact(sc.assets[j], seed + j, d_min=lo * med, d_max=hi * med)
+    return calibrate_keep(sc)
+
+
+def tiny_compact(n=20000, res=256):
+    return compact(synth.scene_tiny(n=n, res=res, width=64))
+
+
+def batched_compact(**kw):
+    return compact(small_batched(**kw), lo=0.8, hi=2.0)

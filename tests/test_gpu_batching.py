@@ -31,6 +31,16 @@ def env():
     return nvgs, torch, sc
 
 
+_SCENES = {}
+
+
+def scene_of(kind):
+    """The batching scene with the frequency-encoded MLP, or with the compact form."""
+    if kind not in _SCENES:
+        _SCENES[kind] = scenes.batched_small() if kind == "frequency" else scenes.batched_compact()
+    return _SCENES[kind]
+
+
 def make_ctx(nvgs, sc):
     ctx = nvgs.Context(0)
     ctx.load_assets(sc.assets)
@@ -44,8 +54,11 @@ def ring(sc, frame):
     return synth.ring_cameras(len(sc.cameras), frame, 8.0, 2.5, (c.width, c.height))
 
 
-def test_multi_camera_frame_matches_oracle(env):
-    nvgs, torch, sc = env
+@pytest.mark.parametrize("kind", ["frequency", "compact"])
+def test_multi_camera_frame_matches_oracle(env, kind):
+    nvgs, torch, _ = env
+    sc = scene_of(kind)
+    log(f"[multi] MLP {kind}")
     ctx = make_ctx(nvgs, sc)
     C = len(sc.cameras)
     img, stats = ctx.render(sc.cameras, tile=16, keep_debug=True, stats=True)
@@ -80,11 +93,14 @@ def test_multi_camera_frame_matches_oracle(env):
         assert np.sum(bad & ~excused) == 0
 
 
-def test_graph_frames_equal_eager_frames(env):
+@pytest.mark.parametrize("kind", ["frequency", "compact"])
+def test_graph_frames_equal_eager_frames(env, kind):
     """The captured frame, replayed for a turning ring of cameras with eager
     frames and other device work in between, gives the eager images bit for
     bit on every replay."""
-    nvgs, torch, sc = env
+    nvgs, torch, _ = env
+    sc = scene_of(kind)
+    log(f"[graph] MLP {kind}")
     ctx = make_ctx(nvgs, sc)
     frames = [0, 7, 14]
     for f in frames:  # size the capacities from eager frames

@@ -61,7 +61,17 @@ SCENES = {
     "tiny_w128": lambda: scenes.tiny(n=5000, res=128, width=128),
     "composed_small": lambda: scenes.composed_small(),
     "batched_small": lambda: scenes.batched_small(),
+    "tiny_compact": lambda: scenes.tiny_compact(),
+    "batched_compact": lambda: scenes.batched_compact(),
 }
+
+
+def _logit_scale(a, inst, cam, gidx):
+    """FP64 size |wo h| + |bo| of the terms of each queried logit."""
+    if a.mlp.kind == 1:
+        return oracle.cmlp_forward(a.mlp.params, oracle.cinputs(a, inst, cam, gidx))[1]
+    cl = oracle.local_camera(inst, cam, a.mlp.train_focal, a.mlp.d_max)
+    return oracle.mlp_forward(a.mlp.params, a.mlp.width, oracle.mlp_inputs(a, gidx, cl))[1]
 
 
 @pytest.mark.parametrize("name", list(SCENES))
@@ -84,14 +94,11 @@ def test_query_state_and_logits(nvgs, name):
     k_of = idx // st.shape[1]
     p_of = idx % st.shape[1]
     inst_of = np.searchsorted(off, p_of, side="right") - 1
-    for i in np.unique(inst_of):
-        sel = inst_of == i
-        inst = sc.instances[int(i)]
-        a = sc.assets[inst.asset]
-        cl = oracle.local_camera(inst, sc.cameras[int(k_of[sel][0])], a.mlp.train_focal, a.mlp.d_max)
-        X = oracle.mlp_inputs(a, p_of[sel] - off[i], cl)
-        _, sc_i = oracle.mlp_forward(a.mlp.params, a.mlp.width, X)
-        scale[sel] = sc_i
+    for k in np.unique(k_of):
+        for i in np.unique(inst_of[k_of == k]):
+            sel = (inst_of == i) & (k_of == k)
+            inst = sc.instances[int(i)]
+            scale[sel] = _logit_scale(sc.assets[inst.asset], inst, sc.cameras[int(k)], p_of[sel] - off[i])
     err = np.abs(lg[both] - z64)
     tol = logit_tol(z64, scale)
     log(f"[query] {name}: queried {both.sum()}, max |dz| {err.max():.3e}, max err/tol {np.max(err / tol):.3f}")
@@ -136,7 +143,8 @@ def _same_input_rect(u, v, ex, ey, W, H, T):
     return x0.astype(np.int64) // T, x1.astype(np.int64) // T, y0.astype(np.int64) // T, y1.astype(np.int64) // T, empty
 
 
-@pytest.mark.parametrize("name,tile", [("tiny", 16), ("tiny", 8), ("composed_small", 16), ("composed_small", 32)])
+@pytest.mark.parametrize("name,tile", [("tiny", 16), ("tiny", 8), ("composed_small", 16), ("composed_small", 32),
+                                       ("tiny_compact", 16)])
 def test_frame_stages_against_oracle(nvgs, name, tile):
     sc = SCENES[name]()
     log(f"[frame] scene={name} tile={tile}")
@@ -321,6 +329,50 @@ def test_reduced_precision_mlp(nvgs, prec, width):
     assert rel.max() < (1e-2 if prec == "bf16" else 5e-2)
     assert np.array_equal(st[q] == 2, zg >= 0)
     assert flips < (0.02 if prec == "bf16" else 0.08)
+
+
+def test_compact_mlp_bf16(nvgs):
+    """The compact form with BF16 second-layer operands: logits equal the
+    oracle's emulation of that rounding up to FP32 accumulation order; FP8
+    is refused for this form."""
+    sc = scenes.batched_compact()
+    log("[prec] compact bf16")
+    ctx = make_ctx(nvgs, sc)
+    st, lg = ctx.query_visibility(sc.cameras, precision="bf16")
+    st, lg = st.cpu().numpy(), lg.cpu().numpy().astype(np.float64)
+    with pytest.raises(nvgs.NvgsError):
+        ctx.query_visibility(sc.cameras, precision="fp8")
+    with pytest.raises(nvgs.NvgsError):
+        ctx.render(sc.cameras, precision="fp8")
+    ctx.close()
+    ost, olg = oracle.query(sc)
+    off = sc.pair_offsets()
+    zq, z64, zg, scale = [], [], [], []
+    for k, cam in enumerate(sc.cameras):
+        for i, inst in enumerate(sc.instances):
+            q = np.flatnonzero(~np.isnan(olg[k, off[i]:off[i + 1]]))
+            if len(q) == 0:
+                continue
+            a = sc.assets[inst.asset]
+            X = oracle.cinputs(a, inst, cam, q)
+            zq.append(oracle.cmlp_forward_bf16(a.mlp.params, X))
+            z, s = oracle.cmlp_forward(a.mlp.params, X)
+            z64.append(z)
+            scale.append(s)
+            zg.append(lg[k, off[i] + q])
+    zq, z64, zg, scale = map(np.concatenate, (zq, z64, zg, scale))
+    rel = np.abs(zg - zq) / np.maximum(np.abs(zq), scale)
+    flips = np.mean((zg >= 0) != (z64 >= 0))
+    log(f"[prec] compact bf16: {len(zg)} queried, median rel {np.median(rel):.3e}, "
+        f"p99.9 rel {np.quantile(rel, 0.999):.3e}, max rel {rel.max():.3e}, flip rate vs FP64 {flips:.4f}")
+    # a first-layer activation whose FP32 (kernel) and FP64 (emulation) values
+    # straddle a BF16 rounding boundary rounds one unit (2^-8 relative) apart
+    assert np.median(rel) < 1e-5
+    assert np.quantile(rel, 0.999) < 1e-3
+    assert rel.max() < 1e-2
+    gq = ~np.isnan(lg)
+    assert np.array_equal(st[gq] == 2, lg[gq] >= 0)
+    assert flips < 0.02
 
 
 def test_radius_clipping_matches_oracle(nvgs):

@@ -722,6 +722,39 @@ def test_compact_mlps_equal_numpy_chain(orc):
     np.testing.assert_allclose(orc.cmlp_forward(Pf, x)[0], emb_ref, rtol=1e-12, atol=1e-12)
 
 
+def _bf16_rne(x):
+    """Round to BF16 (nearest, ties to even) through the FP32 bit pattern."""
+    b = np.asarray(x, np.float32).view(np.uint32).astype(np.uint64)
+    b = (b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000
+    return b.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def test_compact_bf16_emulation(orc):
+    """BF16 second layer of the compact MLP: equals a NumPy chain with
+    bit-level rounding of the FP32 first-layer activations and of W2; with
+    W2 already on the BF16 grid and activations made exact the two forms
+    agree with the FP64 logits."""
+    g = np.random.default_rng(21)
+    P = synth.compact_params(g).astype(np.float64)
+    X = g.uniform(-1, 1, (256, 16))
+    o = 32 * 16 + 32
+    W1, b1 = P[:512].reshape(32, 16), P[512:o]
+    W2, b2 = P[o:o + 1024].reshape(32, 32), P[o + 1024:o + 1056]
+    wo, bo = P[o + 1056:o + 1088], P[o + 1088]
+    h = _bf16_rne(np.maximum(X @ W1.T + b1, 0).astype(np.float32))
+    ref = np.maximum(h @ _bf16_rne(W2).T + b2, 0) @ wo + bo
+    z = orc.cmlp_forward_bf16(P, X)
+    np.testing.assert_allclose(z, ref, rtol=1e-12, atol=1e-12)
+    z64, _ = orc.cmlp_forward(P, X)
+    assert np.max(np.abs(z - z64)) > 1e-6  # the rounding is there
+    # layer-1 weights zero but the bias, on the BF16 grid: no rounding left
+    Q = P.copy()
+    Q[:512] = 0.0
+    Q[512:o] = _bf16_rne(np.abs(Q[512:o]))
+    Q[o:o + 1024] = _bf16_rne(Q[o:o + 1024])
+    np.testing.assert_allclose(orc.cmlp_forward_bf16(Q, X), orc.cmlp_forward(Q, X)[0], rtol=1e-12, atol=1e-12)
+
+
 def test_compact_embedding_inputs_and_quaternion_sign(orc):
     q = (0.3, -0.5, 0.2, 0.7)
     a = one_gaussian_asset((0, 0, 0), (0.02, 0.03, 0.05), quat=q, opacity=0.6)
