@@ -8,7 +8,7 @@
 // inputs), a per-(camera, instance) part (forward vector, folded with the
 // bias into one vector by the segment setup) and a per-pair part (direction
 // and distance: 4 inputs).  A work-group covers 256 Gaussians of one asset
-// (8 waves x 32); the two halves of a wave hold the two halves of the hidden
+// (8 waves of 64 lanes, 32 Gaussians each); the two halves of a wave hold the two halves of the hidden
 // layer of the same 32 Gaussians, so layer 1 is 4 FMAs per hidden unit per
 // pair on top of the per-chunk part, and layer 2 runs on MFMA with the pairs
 // as columns (FP32 32x32x2 or BF16 32x32x16), its operands built straight
@@ -136,10 +136,13 @@ __device__ __forceinline__ bool cfrustum(const SegRec& R, const float mu[3]) {
   return pz > R.near_plane && fabsf(px) <= R.tanx_g * pz && fabsf(py) <= R.tany_g * pz;
 }
 
+constexpr int kCThreads = 2 * kChunk;  // 8 waves, 32 Gaussians each
+static_assert(kChunk == 256, "one compact work-group covers a 256-Gaussian chunk in 8 waves");
+
 // Cull + compact MLP.  P: FP32 or BF16 layer-2 operands; MODE 0: keep bits
 // and chunk counts, 1: state and logits as well.
 template <int P, int MODE>
-__global__ __launch_bounds__(256) void k_cull_cmlp(
+__global__ __launch_bounds__(kCThreads) void k_cull_cmlp(
     const AssetDev* __restrict__ assets, const WorkItem* __restrict__ items, const int32_t* __restrict__ seglist,
     const SegRec* __restrict__ segs, const float* __restrict__ c1perm, int c1_stride, uint32_t* __restrict__ mask,
     uint32_t* __restrict__ chunk_count, uint8_t* __restrict__ state, float* __restrict__ logits,
@@ -150,9 +153,9 @@ __global__ __launch_bounds__(256) void k_cull_cmlp(
   __shared__ uint32_t s_tot[2];
   const WorkItem it = items[blockIdx.x];
   const AssetDev* A = assets + it.asset;
-  for (int e = threadIdx.x; e < kImFloats; e += 256) s_img[e] = A->op_f32[e];
+  for (int e = threadIdx.x; e < kImFloats; e += kCThreads) s_img[e] = A->op_f32[e];
   if (P == NVGS_PREC_BF16)
-    for (int e = threadIdx.x; e < 2 * 64 * 8; e += 256) s_w16[e] = reinterpret_cast<const __bf16*>(A->op_bf16)[e];
+    for (int e = threadIdx.x; e < 2 * 64 * 8; e += kCThreads) s_w16[e] = reinterpret_cast<const __bf16*>(A->op_bf16)[e];
   if (threadIdx.x < 2) s_cnt[threadIdx.x] = s_tot[threadIdx.x] = 0;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 31, grp = lane >> 5;
@@ -280,7 +283,7 @@ hipError_t launch_cull_cmlp(const AssetDev* assets, const WorkItem* items, int64
                             uint32_t* mask, uint32_t* chunk_count, uint8_t* state, float* logits,
                             unsigned long long* counts, hipStream_t st) {
   if (n_items == 0) return hipSuccess;
-  const dim3 grid((unsigned)n_items), block(256);
+  const dim3 grid((unsigned)n_items), block(kCThreads);
 #define NVGS_C(P, M)                                                                                          \
   hipLaunchKernelGGL((k_cull_cmlp<P, M>), grid, block, 0, st, assets, items, seglist, segs, c1perm, c1_stride, \
                      mask, chunk_count, state, logits, counts)
