@@ -320,14 +320,19 @@ nvgs_status nvgs_debug_buffers(nvgs_ctx* ctx, nvgs_debug_view* out);
 nvgs_status nvgs_make_labels(nvgs_ctx* ctx, int32_t asset, const nvgs_camera* views, int32_t V, float threshold,
                              int32_t tile, int32_t aux, float aux_angle, uint32_t* labels);
 
-/* Train the width-64 visibility MLP of one asset (Sec. 3.2) on (Gaussian,
+/* Train the visibility MLP of one asset (Sec. 3.2) on (Gaussian,
  * view) pairs drawn uniformly with replacement: pair i of step s comes from
  * r = SplitMix64(opts->seed, s * batch + i), Gaussian ((r mod 2^32) n) >> 32,
  * view ((r >> 32) V) >> 32.  Loss: mean BCE with logits against the labels
  * (labels == NULL: made here with opts->threshold and opts->tile).  Adam
- * (beta1, beta2, eps, bias-corrected, constant lr) on FP32 master weights.
+ * (beta1, beta2, eps, bias-corrected, lr per opts->schedule) on FP32 master weights.
  * precision NVGS_PREC_BF16 rounds every GEMM operand of the forward and
  * backward pass to BF16 (FP32 accumulation); NVGS_PREC_FP32 keeps FP32.
+ * Frequency-encoded assets (nvgs_mlp.kind 0) need width 64.  Compact assets
+ * (kind 1, Sec. 3.2, 3.3, 4.1) train the embedding MLP and the visibility MLP
+ * jointly (all 3175 parameters): each pair's inputs are those of the query
+ * with the view as camera of an identity instance, the embedding computed
+ * from the Gaussian's (opacity, log scales, unit quaternion) in the same pass.
  * params: device FP32 packed parameters (layout of nvgs_mlp.params), read as
  * the initial weights and updated in place (reload the asset to render with
  * them).  loss_curve: host [steps] (mean batch loss before each update) or
@@ -346,6 +351,22 @@ nvgs_status nvgs_mlp_forward(nvgs_ctx* ctx, const float* params, int32_t width, 
  * dz_b/dX[b][k] (device [B][72]).  The sum over b runs in a fixed order. */
 nvgs_status nvgs_mlp_backward(nvgs_ctx* ctx, const float* params, int32_t width, const float* X, int64_t B,
                               const float* dlogits, int32_t precision, float* dparams, float* dX);
+
+/* The compact model (Sec. 3.2, 3.3, 4.1) as one function of its raw inputs,
+ * for automatic differentiation frameworks.  X: device [B][18]: the ten
+ * per-pair visibility inputs (mean_scale * mu, unit direction camera ->
+ * Gaussian, normalised distance, camera forward), then the eight embedding
+ * inputs (opacity, log scales, unit quaternion with w >= 0); the embedding
+ * MLP's six outputs complete the sixteen visibility inputs.  params: device
+ * [3175] (layout of nvgs_mlp.params for kind 1).  logits: device [B].
+ * precision: NVGS_PREC_FP32 or NVGS_PREC_BF16 (GEMM operands rounded). */
+nvgs_status nvgs_cmlp_forward(nvgs_ctx* ctx, const float* params, const float* X, int64_t B, int32_t precision,
+                              float* logits);
+/* Vector-Jacobian product over the parameters: dparams[p] = sum_b dlogits[b]
+ * dz_b/dparams[p] (device [3175], overwritten); the sum over b runs in a
+ * fixed order. */
+nvgs_status nvgs_cmlp_backward(nvgs_ctx* ctx, const float* params, const float* X, int64_t B, const float* dlogits,
+                               int32_t precision, float* dparams);
 
 #ifdef __cplusplus
 }

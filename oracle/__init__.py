@@ -77,6 +77,7 @@ def lib():
                                   C.c_double, dp]
         L.orc_cmlp_forward.argtypes = [dp, dp, C.c_int64, dp, vp]
         L.orc_cmlp_forward_bf16.argtypes = [dp, dp, C.c_int64, dp]
+        L.orc_cjoint_forward.argtypes = [dp, dp, dp, C.c_int64, dp, vp]
         L.orc_cquery.argtypes = [C.c_int64, fp, dp, dp, dp, dp, C.c_double, C.c_double, C.c_double, C.c_double,
                                  C.c_int, u8, dp, vp]
         L.orc_cbce_backward.argtypes = [dp, dp, dp, dp, vp, C.c_int64, dp]
@@ -265,6 +266,16 @@ def cmlp_forward(params, X):
     z = np.zeros(X.shape[0])
     sc = np.zeros(X.shape[0])
     lib().orc_cmlp_forward(_f64(params), X, X.shape[0], z, _ptr(sc))
+    return z, sc
+
+
+def cjoint_forward(params, XV, XE):
+    """Logits and term sizes of the joint compact model (embedding MLP, then
+    the visibility MLP) on raw inputs XV [B, 10] and XE [B, 8]."""
+    XV, XE = _f64(XV), _f64(XE)
+    z = np.zeros(XV.shape[0])
+    sc = np.zeros(XV.shape[0])
+    lib().orc_cjoint_forward(_f64(params), XV, XE, XV.shape[0], z, _ptr(sc))
     return z, sc
 
 

@@ -876,6 +876,19 @@ void orc_cmlp_forward(const double* P, const double* X, int64_t B, double* z, do
   for (int64_t b = 0; b < B; ++b) z[b] = cvis(P, X + b * kCIn, nullptr, nullptr, scale ? scale + b : nullptr);
 }
 
+// The joint compact model on raw inputs: the embedding of each sample from
+// its eight embedding inputs XE [B][8], then the visibility MLP on the ten
+// other inputs XV [B][10] and that embedding.  z [B]; scale [B] (nullable)
+// as in cvis.
+void orc_cjoint_forward(const double* P, const double* XV, const double* XE, int64_t B, double* z, double* scale) {
+  for (int64_t b = 0; b < B; ++b) {
+    double x[kCIn];
+    std::copy(XV + b * 10, XV + b * 10 + 10, x);
+    cembed(P + kCVis, XE + b * kCEIn, x + 10, nullptr, nullptr);
+    z[b] = cvis(P, x, nullptr, nullptr, scale ? scale + b : nullptr);
+  }
+}
+
 // Logits of the compact visibility MLP with its second-layer operands (the
 // weights and the first hidden layer's activations) rounded to BF16; the
 // first layer and the output in FP64 otherwise.  X [B][16].

@@ -125,9 +125,13 @@ _SIGS = {
                          C.c_int32),
     "nvgs_mlp_backward": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p, C.c_int32,
                            C.c_void_p, C.c_void_p], C.c_int32),
+    "nvgs_cmlp_forward": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p], C.c_int32),
+    "nvgs_cmlp_backward": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int32, C.c_void_p],
+                           C.c_int32),
 }
 
 NUM_PARAMS_W64 = 72 * 64 + 64 + 2 * (64 * 64 + 64) + 64 + 1
+NUM_PARAMS_COMPACT = (32 * 16 + 32 + 32 * 32 + 32 + 32 + 1) + (32 * 8 + 32 + 32 * 32 + 32 + 6 * 32 + 6)
 
 _lib = None
 
@@ -461,10 +465,25 @@ def _train_methods():
                                              _ptr(dx)))
         return dp, dx
 
+    def cmlp_forward(self, params, X, precision="fp32"):
+        """Logits of the compact model on raw inputs X [B, 18]."""
+        z = torch.empty(X.shape[0], dtype=torch.float32, device=self.device)
+        self._check(self.L.nvgs_cmlp_forward(self.h, params.data_ptr(), X.data_ptr(), X.shape[0],
+                                             _PREC.get(precision, precision), z.data_ptr()))
+        return z
+
+    def cmlp_backward(self, params, X, dlogits, precision="fp32"):
+        dp = torch.empty(NUM_PARAMS_COMPACT, dtype=torch.float32, device=self.device)
+        self._check(self.L.nvgs_cmlp_backward(self.h, params.data_ptr(), X.data_ptr(), X.shape[0],
+                                              dlogits.data_ptr(), _PREC.get(precision, precision), dp.data_ptr()))
+        return dp
+
     Context.make_labels = make_labels
     Context.train_visibility = train_visibility
     Context.mlp_forward = mlp_forward
     Context.mlp_backward = mlp_backward
+    Context.cmlp_forward = cmlp_forward
+    Context.cmlp_backward = cmlp_backward
 
 
 _train_methods_installed = False
@@ -493,6 +512,32 @@ def visibility_mlp_function():
             return dx, dp, None, None
 
     return VisibilityMLPFunction
+
+
+def compact_mlp_function():
+    """torch.autograd.Function over the compact model's forward and
+    hand-written backward: apply(X [B, 18], params [3175], ctx, precision)
+    -> logits [B]; gradients flow to the parameters only."""
+    torch = _torch()
+
+    class CompactMLPFunction(torch.autograd.Function):
+        @staticmethod
+        def forward(fctx, X, params, nctx, precision="fp32"):
+            X = X.contiguous()
+            params = params.contiguous()
+            fctx.save_for_backward(X, params)
+            fctx.nctx = nctx
+            fctx.precision = precision
+            return nctx.cmlp_forward(params, X, precision)
+
+        @staticmethod
+        def backward(fctx, grad):
+            X, params = fctx.saved_tensors
+            if fctx.needs_input_grad[0]:
+                raise NotImplementedError("the compact model's backward gives parameter gradients only")
+            return None, fctx.nctx.cmlp_backward(params, X, grad.contiguous().float(), fctx.precision), None, None
+
+    return CompactMLPFunction
 
 
 def exported_symbols() -> list:

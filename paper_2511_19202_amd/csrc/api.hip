@@ -1046,11 +1046,18 @@ struct Tmp {
   }
 };
 
-nvgs_status check_train_prec(nvgs_ctx* ctx, int32_t precision, int32_t width) {
+nvgs_status check_train_prec(nvgs_ctx* ctx, int32_t precision, int32_t width, int32_t kind = 0) {
   if (precision != NVGS_PREC_FP32 && precision != NVGS_PREC_BF16)
     return fail(ctx, NVGS_E_INVALID, "training precision must be FP32 or BF16");
-  if (width != 64) return fail(ctx, NVGS_E_INVALID, "training supports width 64");
+  if (kind == 0 && width != 64) return fail(ctx, NVGS_E_INVALID, "training supports width 64");
+  if (kind == 1 && width != 32) return fail(ctx, NVGS_E_INVALID, "the compact MLP has width 32");
   return NVGS_OK;
+}
+
+// chunks of 128 samples per compact-training work-group: about 512 groups for large batches
+int ctrain_chunks(int64_t batch) {
+  const int64_t per = ctrain_samples_per_chunk();
+  return (int)std::min<int64_t>(16, std::max<int64_t>(1, (batch + per * 512 - 1) / (per * 512)));
 }
 
 constexpr int kTrainChunksPerWG = 4;  // 4 x 64 pairs per work-group
@@ -1193,7 +1200,7 @@ nvgs_status nvgs_train_visibility(nvgs_ctx* ctx, int32_t asset, const nvgs_camer
   if (!(opts->lr > 0.f) || !(opts->beta1 >= 0.f && opts->beta1 < 1.f) || !(opts->beta2 >= 0.f && opts->beta2 < 1.f) ||
       !(opts->eps > 0.f))
     return fail(ctx, NVGS_E_INVALID, "bad Adam hyper-parameters");
-  nvgs_status s = check_train_prec(ctx, opts->precision, ctx->assets[asset].mlp.width);
+  nvgs_status s = check_train_prec(ctx, opts->precision, ctx->assets[asset].mlp.width, ctx->kind);
   if (s) return s;
   if ((s = check_cams(ctx, views, V))) return s;
   CK(hipSetDevice(ctx->device));
@@ -1206,12 +1213,15 @@ nvgs_status nvgs_train_visibility(nvgs_ctx* ctx, int32_t asset, const nvgs_camer
     if ((s = nvgs_make_labels(ctx, asset, views, V, opts->threshold, opts->tile, 0, 0.f, lb))) return s;
     labels = lb;
   }
-  const int np = train_num_params();
-  const int nwg = (int)((opts->batch + kPairsPerWG - 1) / kPairsPerWG);
+  const bool compact = ctx->kind == 1;
+  const int np = compact ? ctrain_num_params() : train_num_params();
+  const int cpw = compact ? ctrain_chunks(opts->batch) : kTrainChunksPerWG;
+  const int64_t per_wg = compact ? (int64_t)ctrain_samples_per_chunk() * cpw : (int64_t)kPairsPerWG;
+  const int nwg = (int)((opts->batch + per_wg - 1) / per_wg);
   if (opts->weighting != 0 && opts->weighting != 1) return fail(ctx, NVGS_E_INVALID, "weighting must be 0 or 1");
   Tmp cams_t(ctx), gam_t(ctx), part_t(ctx), lp_t(ctx), m_t(ctx), v_t(ctx), loss_t(ctx), cnt_t(ctx);
   nvgs_camera* cams_d = cams_t.get<nvgs_camera>(V);
-  float* gam = gam_t.get<float>((size_t)V * 36);
+  float* gam = gam_t.get<float>((size_t)V * (compact ? 8 : 36));
   float* part = part_t.get<float>((size_t)nwg * np);
   float* lp = lp_t.get<float>(nwg);
   float* m = m_t.get<float>(np);
@@ -1223,7 +1233,10 @@ nvgs_status nvgs_train_visibility(nvgs_ctx* ctx, int32_t asset, const nvgs_camer
   CK(hipMemcpy(cams_d, views, sizeof(nvgs_camera) * V, hipMemcpyHostToDevice));
   CK(launch_fill_u32(reinterpret_cast<uint32_t*>(m), 0u, np, ctx->stream));
   CK(launch_fill_u32(reinterpret_cast<uint32_t*>(v), 0u, np, ctx->stream));
-  CK(launch_view_gam(cams_d, V, A.mlp.cam_scale, A.mlp.train_focal, A.mlp.d_max, gam, ctx->stream));
+  if (compact)
+    CK(launch_cview(cams_d, V, A.mlp.train_focal, A.mlp.d_min, A.mlp.d_max, gam, ctx->stream));
+  else
+    CK(launch_view_gam(cams_d, V, A.mlp.cam_scale, A.mlp.train_focal, A.mlp.d_max, gam, ctx->stream));
   const bool bf16 = opts->precision == NVGS_PREC_BF16;
   const float inv_b = 1.f / (float)opts->batch;
   const bool weighted = opts->weighting == 1;
@@ -1231,11 +1244,18 @@ nvgs_status nvgs_train_visibility(nvgs_ctx* ctx, int32_t asset, const nvgs_camer
   for (int step = 0; step < opts->steps; ++step) {
     if (weighted)
       CK(launch_count_pos(opts->batch, n, V, labels, opts->seed, step, npos + step, ctx->stream));
-    CK(launch_mlp_train(0, bf16, nwg, kTrainChunksPerWG, ctx->stream, params, opts->batch, inv_b, A.mean, n,
-                        A.mlp.mean_scale, gam, V, labels, opts->seed, step, weighted ? npos + step : nullptr, nullptr,
-                        nullptr, nullptr, part, lp, nullptr));
-    CK(launch_reduce_adam(part, nwg, params, m, v, nullptr, step_lr(opts, step), opts->beta1, opts->beta2, opts->eps,
-                          step + 1, lp, inv_b, loss + step, ctx->stream));
+    if (compact) {
+      const CTrainArgs ca{A.mean, A.scale, A.quat, A.opacity, n, A.mlp.mean_scale, gam, V, labels, opts->seed,
+                          step, weighted ? npos + step : nullptr};
+      CK(launch_cmlp_train(0, bf16, nwg, cpw, ctx->stream, params, opts->batch, inv_b, ca, nullptr, nullptr, nullptr,
+                           part, lp));
+    } else {
+      CK(launch_mlp_train(0, bf16, nwg, kTrainChunksPerWG, ctx->stream, params, opts->batch, inv_b, A.mean, n,
+                          A.mlp.mean_scale, gam, V, labels, opts->seed, step, weighted ? npos + step : nullptr,
+                          nullptr, nullptr, nullptr, part, lp, nullptr));
+    }
+    CK(launch_reduce_adam_n(part, nwg, np, params, m, v, nullptr, step_lr(opts, step), opts->beta1, opts->beta2,
+                            opts->eps, step + 1, lp, inv_b, loss + step, ctx->stream));
   }
   CK(hipStreamSynchronize(ctx->stream));
   if (loss_curve) CK(hipMemcpy(loss_curve, loss, sizeof(float) * opts->steps, hipMemcpyDeviceToHost));
@@ -1271,6 +1291,45 @@ nvgs_status nvgs_mlp_backward(nvgs_ctx* ctx, const float* params, int32_t width,
                       1, 0.f, nullptr, 1, nullptr, 0, 0, nullptr, X, dlogits, nullptr, part, nullptr, dX));
   CK(launch_reduce_adam(part, nwg, nullptr, nullptr, nullptr, dparams, 0.f, 0.f, 0.f, 1.f, 1, nullptr, 0.f, nullptr,
                         ctx->stream));
+  return NVGS_OK;
+}
+
+nvgs_status nvgs_cmlp_forward(nvgs_ctx* ctx, const float* params, const float* X, int64_t B, int32_t precision,
+                              float* logits) {
+  if (!ctx) return NVGS_E_INVALID;
+  if (!params || !X || !logits || B < 1) return fail(ctx, NVGS_E_INVALID, "cmlp_forward: null pointer or B < 1");
+  nvgs_status s = check_train_prec(ctx, precision, 32, 1);
+  if (s) return s;
+  CK(hipSetDevice(ctx->device));
+  const int cpw = ctrain_chunks(B);
+  const int64_t per_wg = (int64_t)ctrain_samples_per_chunk() * cpw;
+  const int nwg = (int)((B + per_wg - 1) / per_wg);
+  const CTrainArgs none{};
+  CK(launch_cmlp_train(1, precision == NVGS_PREC_BF16, nwg, cpw, ctx->stream, params, B, 1.f, none, X, nullptr,
+                       logits, nullptr, nullptr));
+  return NVGS_OK;
+}
+
+nvgs_status nvgs_cmlp_backward(nvgs_ctx* ctx, const float* params, const float* X, int64_t B, const float* dlogits,
+                               int32_t precision, float* dparams) {
+  if (!ctx) return NVGS_E_INVALID;
+  if (!params || !X || !dlogits || !dparams || B < 1)
+    return fail(ctx, NVGS_E_INVALID, "cmlp_backward: null pointer or B < 1");
+  nvgs_status s = check_train_prec(ctx, precision, 32, 1);
+  if (s) return s;
+  CK(hipSetDevice(ctx->device));
+  const int cpw = ctrain_chunks(B);
+  const int64_t per_wg = (int64_t)ctrain_samples_per_chunk() * cpw;
+  const int nwg = (int)((B + per_wg - 1) / per_wg);
+  const int np = ctrain_num_params();
+  Tmp part_t(ctx);
+  float* part = part_t.get<float>((size_t)nwg * np);
+  if (!part) return fail(ctx, NVGS_E_NOMEM, "gradient partials");
+  const CTrainArgs none{};
+  CK(launch_cmlp_train(2, precision == NVGS_PREC_BF16, nwg, cpw, ctx->stream, params, B, 1.f, none, X, dlogits,
+                       nullptr, part, nullptr));
+  CK(launch_reduce_adam_n(part, nwg, np, nullptr, nullptr, nullptr, dparams, 0.f, 0.f, 0.f, 1.f, 1, nullptr, 0.f,
+                          nullptr, ctx->stream));
   return NVGS_OK;
 }
 

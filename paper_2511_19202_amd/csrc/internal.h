@@ -198,4 +198,30 @@ hipError_t launch_count_pos(int64_t batch, int64_t n, int V, const uint32_t* lab
 hipError_t launch_reduce_adam(const float* partial, int nwg, float* params, float* m, float* v, float* grad_out,
                               float lr, float b1, float b2, float eps, int64_t t, const float* loss_part,
                               float inv_batch, float* loss_out, hipStream_t st);
+hipError_t launch_reduce_adam_n(const float* partial, int nwg, int np, float* params, float* m, float* v,
+                                float* grad_out, float lr, float b1, float b2, float eps, int64_t t,
+                                const float* loss_part, float inv_batch, float* loss_out, hipStream_t st);
+
+// training of the compact form (k_ctrain.hip)
+struct CTrainArgs {
+  const float *mean, *scale, *quat, *opacity;  // asset SoA
+  int64_t n;
+  float mean_scale;
+  const float* vrec;  // [V][8] from launch_cview
+  int V;
+  const uint32_t* labels;  // [V][ceil(n / 32)] bits
+  uint64_t seed;
+  int64_t step;
+  const uint32_t* n_pos;  // positives of the step's batch (class weighting) or null
+};
+size_t ctrain_smem_bytes();
+int ctrain_num_params();
+int ctrain_samples_per_chunk();
+hipError_t launch_cview(const nvgs_camera* views, int V, float train_focal, float d_min, float d_max, float* out,
+                        hipStream_t st);
+// mode 0: train step gradients from sampled (Gaussian, view) pairs; 1: logits of X [B][18];
+// 2: parameter-gradient partials of X under dlogits.  Partials: one [3175] row per work-group.
+hipError_t launch_cmlp_train(int mode, bool bf16, int nwg, int chunks_per_wg, hipStream_t st, const float* params,
+                             int64_t batch, float inv_batch, const CTrainArgs& a, const float* X,
+                             const float* dlogits, float* logits, float* partial, float* loss_part);
 }  // namespace nvgs

@@ -338,14 +338,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 }
 
 // sum of the per-group partials (fixed order), then Adam or a plain store
-__global__ void k_reduce_adam(const float* __restrict__ partial, int nwg, float* __restrict__ params,
+__global__ void k_reduce_adam(const float* __restrict__ partial, int nwg, int np, float* __restrict__ params,
                               float* __restrict__ m, float* __restrict__ v, float* __restrict__ grad_out, float lr,
                               float b1, float b2, float eps, float c1, float c2, const float* __restrict__ loss_part,
                               float inv_batch, float* __restrict__ loss_out) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p < kNumParams) {
+  if (p < np) {
     float g = 0.f;
-    for (int w = 0; w < nwg; ++w) g += partial[(int64_t)w * kNumParams + p];
+    for (int w = 0; w < nwg; ++w) g += partial[(int64_t)w * np + p];
     if (grad_out) {
       grad_out[p] = g;
     } else {
@@ -492,13 +492,20 @@ hipError_t launch_mlp_train(int mode, bool bf16, int nwg, int chunks_per_wg, hip
 #undef NVGS_MLPT
 }
 
+hipError_t launch_reduce_adam_n(const float* partial, int nwg, int np, float* params, float* m, float* v,
+                                float* grad_out, float lr, float b1, float b2, float eps, int64_t t,
+                                const float* loss_part, float inv_batch, float* loss_out, hipStream_t st) {
+  const float c1 = 1.f - powf(b1, (float)t), c2 = 1.f - powf(b2, (float)t);
+  hipLaunchKernelGGL(k_reduce_adam, dim3((np + 255) / 256), dim3(256), 0, st, partial, nwg, np, params, m, v,
+                     grad_out, lr, b1, b2, eps, c1, c2, loss_part, inv_batch, loss_out);
+  return hipGetLastError();
+}
+
 hipError_t launch_reduce_adam(const float* partial, int nwg, float* params, float* m, float* v, float* grad_out,
                               float lr, float b1, float b2, float eps, int64_t t, const float* loss_part,
                               float inv_batch, float* loss_out, hipStream_t st) {
-  const float c1 = 1.f - powf(b1, (float)t), c2 = 1.f - powf(b2, (float)t);
-  hipLaunchKernelGGL(k_reduce_adam, dim3((kNumParams + 255) / 256), dim3(256), 0, st, partial, nwg, params, m, v,
-                     grad_out, lr, b1, b2, eps, c1, c2, loss_part, inv_batch, loss_out);
-  return hipGetLastError();
+  return launch_reduce_adam_n(partial, nwg, kNumParams, params, m, v, grad_out, lr, b1, b2, eps, t, loss_part,
+                              inv_batch, loss_out, st);
 }
 
 }  // namespace nvgs

@@ -171,3 +171,132 @@ def test_training_reduces_loss(env):
     log(f"[train] loss {curve[0]:.4f} -> {curve[-20:].mean():.4f}")
     assert np.all(np.isfinite(curve))
     assert curve[-20:].mean() < 0.8 * curve[:5].mean()
+
+
+# ---------------------------------------------------------------------------
+# the compact form (Sec. 3.2, 3.3, 4.1): embedding and visibility MLPs jointly
+# ---------------------------------------------------------------------------
+def _compact_batch(B, seed):
+    """Raw inputs of the joint model: ten visibility inputs (normalised mean,
+    unit direction, distance in [-1, 1], unit forward vector) and eight
+    embedding inputs (opacity, log scales, unit quaternion with w >= 0)."""
+    g = np.random.default_rng(seed)
+    p = synth.compact_params(g)
+    unit = lambda m: m / np.linalg.norm(m, axis=1, keepdims=True)
+    XV = np.concatenate([g.uniform(-1, 1, (B, 3)), unit(g.standard_normal((B, 3))), g.uniform(-1, 1, (B, 1)),
+                         unit(g.standard_normal((B, 3)))], 1)
+    q = unit(g.standard_normal((B, 4)))
+    q *= np.where(q[:, :1] < 0, -1.0, 1.0)
+    XE = np.concatenate([g.uniform(0.3, 1, (B, 1)), g.normal(-4.5, 0.3, (B, 3)), q], 1)
+    X = np.concatenate([XV, XE], 1).astype(np.float32)
+    y = (g.uniform(0, 1, B) > 0.5).astype(np.float64)
+    return p, X, y
+
+
+@pytest.mark.parametrize("B", [300, 1024, 70000])
+def test_compact_forward_backward_fp32_vs_oracle(env, B):
+    nvgs, ctx, torch = env
+    p, X, y = _compact_batch(B, 30 + B)
+    XV, XE = X[:, :10].astype(np.float64), X[:, 10:].astype(np.float64)
+    z64, scale = oracle.cjoint_forward(p, XV, XE)
+    pt, Xt = torch.from_numpy(p).cuda(), torch.from_numpy(X).cuda()
+    zg = ctx.cmlp_forward(pt, Xt).cpu().numpy().astype(np.float64)
+    err = np.abs(zg - z64) / np.maximum(np.abs(z64), scale)
+    log(f"[cgrad] B={B}: forward max err / max(|z|, scale) {err.max():.2e}")
+    assert err.max() < 1e-5
+    dlog = ((1 / (1 + np.exp(-z64)) - y) / B).astype(np.float32)
+    _, dP = oracle.cbce_backward(p, XV, XE, y)
+    dg = ctx.cmlp_backward(pt, Xt, torch.from_numpy(dlog).cuda()).cpu().numpy().astype(np.float64)
+    nrm, rel = _grad_close(dg, dP)
+    nv = synth.COMPACT_VIS_PARAMS
+    log(f"[cgrad] B={B}: param grad rel norm err {nrm:.2e} (visibility "
+        f"{np.linalg.norm(dg[:nv] - dP[:nv]) / np.linalg.norm(dP[:nv]):.2e}, embedding "
+        f"{np.linalg.norm(dg[nv:] - dP[nv:]) / np.linalg.norm(dP[nv:]):.2e}), max rel {rel.max():.2e}")
+    assert nrm < 1e-4 and np.mean(rel < 1e-3) > 0.999
+
+
+def test_compact_backward_bf16_and_autograd(env):
+    nvgs, ctx, torch = env
+    B = 4096
+    p, X, y = _compact_batch(B, 77)
+    XV, XE = X[:, :10].astype(np.float64), X[:, 10:].astype(np.float64)
+    l64, dP = oracle.cbce_backward(p, XV, XE, y)
+    # autograd over the BF16 form: loss and gradient direction
+    pt = torch.from_numpy(p).cuda().requires_grad_(True)
+    f = nvgs.compact_mlp_function()
+    z = f.apply(torch.from_numpy(X).cuda(), pt, ctx, "bf16")
+    loss = torch.nn.functional.binary_cross_entropy_with_logits(z, torch.from_numpy(y).float().cuda())
+    loss.backward()
+    g = pt.grad.cpu().numpy().astype(np.float64)
+    cos = float(np.dot(g, dP) / (np.linalg.norm(g) * np.linalg.norm(dP)))
+    log(f"[cgrad] bf16: loss {loss.item():.6f} vs FP64 {l64:.6f}, gradient cosine {cos:.6f}")
+    assert abs(loss.item() - l64) < 2e-3 * max(1.0, l64)
+    assert cos >= 0.999
+    # FP32 through autograd: the loss to FP32 accuracy
+    pt32 = torch.from_numpy(p).cuda().requires_grad_(True)
+    z32 = f.apply(torch.from_numpy(X).cuda(), pt32, ctx, "fp32")
+    l32 = torch.nn.functional.binary_cross_entropy_with_logits(z32, torch.from_numpy(y).float().cuda())
+    l32.backward()
+    assert abs(l32.item() - l64) < 1e-5 * max(1.0, l64)
+    assert _grad_close(pt32.grad.cpu().numpy().astype(np.float64), dP)[0] < 1e-4
+
+
+def _compact_asset(n=2000, seed=6, d_min=1.0, d_max=8.0):
+    return synth.make_compact(_small_asset(n=n, seed=seed), seed + 100, d_min=d_min, d_max=d_max)
+
+
+@pytest.mark.parametrize("weighting", [0, 1])
+def test_compact_training_step_matches_oracle(env, weighting):
+    """One FP32 Adam step of the compact model on oracle labels: the GPU's
+    batch loss equals the oracle's on the same SplitMix64-drawn pairs, and the
+    first update agrees with the oracle's Adam step."""
+    nvgs, ctx, torch = env
+    a = _compact_asset()
+    views = synth.label_views(4, seed=5, d_lo=2.0, d_hi=4.0, res=64)
+    lab = oracle.labels(a, views)
+    words = (a.n + 31) // 32
+    packed = np.zeros((len(views), words * 32), np.uint8)
+    packed[:, :a.n] = lab
+    lab_words = np.packbits(packed, axis=1, bitorder="little").view(np.uint32).reshape(len(views), words)
+    ctx.load_assets([a])
+    p0 = a.mlp.params.astype(np.float32)
+    pt = torch.from_numpy(p0.copy()).cuda()
+    B, seed, lr = 1000, 91, 1e-3
+    curve = ctx.train_visibility(0, views, pt, labels=torch.from_numpy(lab_words.view(np.int32)).cuda(), batch=B,
+                                 steps=1, precision="fp32", lr=lr, seed=seed, weighting=weighting)
+    g_idx, v_idx = oracle.sample_pairs(seed, 0, B, a.n, len(views))
+    E, XE_all = oracle.cembed(a)
+    XV = np.zeros((B, 10))
+    for v in np.unique(v_idx):
+        sel = np.flatnonzero(v_idx == v)
+        XV[sel] = oracle.cinputs(a, synth.identity_instance(), views[v], g_idx[sel], E)[:, :10]
+    XE = XE_all[g_idx]
+    y = lab[v_idx, g_idx].astype(np.float64)
+    w = None
+    if weighting:  # each sample weighted by B / (2 n_class)
+        npos = y.sum()
+        w = np.where(y > 0.5, B / (2 * npos), B / (2 * (B - npos)))
+    loss, dP = oracle.cbce_backward(p0, XV, XE, y, w=w)
+    log(f"[ctrain] loss gpu {curve[0]:.6f} oracle {loss:.6f}")
+    assert abs(curve[0] - loss) < 1e-5 * max(1.0, loss)
+    p64 = p0.astype(np.float64)
+    m = np.zeros_like(p64); v = np.zeros_like(p64)
+    oracle.adam_step(p64, dP, m, v, 1, lr=lr)
+    dg = pt.cpu().numpy().astype(np.float64) - p0
+    do = p64 - p0
+    big = np.abs(dP) > 1e-5 * np.abs(dP).max()
+    agree = np.abs(dg - do) < 1e-6
+    log(f"[ctrain] first update agrees on {agree[big].mean():.5f} of {big.sum()} parameters")
+    assert agree[big].mean() > 0.995
+
+
+def test_compact_training_reduces_loss(env):
+    nvgs, ctx, torch = env
+    a = _compact_asset(n=4000, seed=8, d_min=1.5, d_max=7.0)
+    views = synth.label_views(24, seed=9, d_lo=2.0, d_hi=6.0, res=96)
+    ctx.load_assets([a])
+    pt = torch.from_numpy(a.mlp.params.astype(np.float32).copy()).cuda()
+    curve = ctx.train_visibility(0, views, pt, batch=4096, steps=300, precision="bf16", lr=3e-3, seed=1)
+    log(f"[ctrain] loss {curve[0]:.4f} -> {curve[-20:].mean():.4f}")
+    assert np.all(np.isfinite(curve))
+    assert curve[-20:].mean() < 0.8 * curve[:5].mean()

@@ -720,6 +720,12 @@ def test_compact_mlps_equal_numpy_chain(orc):
     emb_ref = _np_compact(Pf, np.zeros((1, 16)), XE)  # visibility of [0, E]: checks E through a second path
     x = np.concatenate([np.zeros(10), E[0]])[None]
     np.testing.assert_allclose(orc.cmlp_forward(Pf, x)[0], emb_ref, rtol=1e-12, atol=1e-12)
+    # the joint model on raw inputs against the NumPy chain through both networks
+    XV = g.uniform(-1, 1, (40, 10))
+    XE = np.concatenate([g.uniform(0.1, 1, (40, 1)), g.normal(-4.5, 0.3, (40, 3)), g.standard_normal((40, 4))], 1)
+    zj, _ = orc.cjoint_forward(P, XV, XE)
+    np.testing.assert_allclose(zj, _np_compact(P, np.concatenate([XV, np.zeros((40, 6))], 1), XE),
+                               rtol=1e-12, atol=1e-12)
 
 
 def _bf16_rne(x):
