@@ -42,6 +42,9 @@ sys.path.insert(0, ROOT)
 # per queried pair: the two hidden layers and the output layer (layer 1 is
 # computed once per Gaussian chunk and once per (camera, instance) segment)
 FLOP_PER_QUERY = {64: 2 * (2 * 64 * 64 + 64), 128: 2 * (2 * 128 * 128 + 128)}
+# compact form per queried pair: the per-pair part of layer 1 (4 inputs), layer 2 and the output
+FLOP_PER_QUERY[32] = 2 * (4 * 32 + 32 * 32 + 32)
+COMPACT_BO = 32 * 16 + 32 + 32 * 32 + 32 + 32  # index of the compact form's output bias
 MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0}
 HBM_PEAK_GBS = 8000.0
 VALU_LANE_OPS = 256 * 64 * 2.4e9          # non-packed FP32 lane-ops per second
@@ -50,14 +53,17 @@ BLEND_PEAK_GTESTS = VALU_LANE_OPS / BLEND_SLOTS_PER_TEST / 1e9
 
 
 def train_assets(ctx, sc, views=512, res=512, batch=65536, steps=5000, precision="bf16", lr=1e-3, seed=1,
-                 weighting=1, aux=6, aux_deg=5.0, offset=0.1, recipe="workload"):
+                 weighting=1, aux=6, aux_deg=5.0, offset=0.1, recipe="workload", sampling="fibonacci",
+                 fovy_deg=50.0):
     """Train each asset's visibility MLP on labels the renderer makes from
-    `views` Fibonacci-sphere views, each with `aux` auxiliary views on a cone
-    of `aux_deg` degrees (one identity instance per asset), with
-    class-frequency weighted BCE when `weighting`.  recipe "workload":
-    distances U(1.5, 20), constant lr; recipe "paper" (Sec. 3.1, 4.1): the
-    asset's Eq. 1 distance range (also its MLP's far clamp), batches of 2^19,
-    lr 2e-3 with warm-up and decay to 2e-4.  Returns per-asset summaries."""
+    `views` Fibonacci-sphere (or longitude-latitude) views of `fovy_deg`,
+    each with `aux` auxiliary views on a cone of `aux_deg` degrees (one
+    identity instance per asset), with class-frequency weighted BCE when
+    `weighting`.  recipe "workload": distances U(1.5, 20), constant lr;
+    recipe "paper" (Sec. 3.1, 4.1): the asset's Eq. 1 distance range (for
+    the frequency form also its MLP's far clamp; the compact form normalises
+    its distance input over it), batches of 2^19, lr 2e-3 with warm-up and
+    decay to 2e-4.  Returns per-asset summaries."""
     import torch
     import synth
     out = []
@@ -65,12 +71,13 @@ def train_assets(ctx, sc, views=512, res=512, batch=65536, steps=5000, precision
         d_lo, d_hi = 1.5, 20.0
         lr_final = 0.0
         if recipe == "paper":
-            d_lo, d_hi = synth.eq1_range(a.name)
-            a.mlp.d_max = float(np.float32(d_hi))
-            a.mlp.cam_scale = float(np.float32(1.0 / d_hi))  # keeps the encoded camera position in [-1, 1]
+            d_lo, d_hi = synth.eq1_range(a.name, fovy_deg=fovy_deg)
+            if a.mlp.kind == 0:
+                a.mlp.d_max = float(np.float32(d_hi))
+                a.mlp.cam_scale = float(np.float32(1.0 / d_hi))  # keeps the encoded camera position in [-1, 1]
             batch, lr, lr_final = 1 << 19, 2e-3, 2e-4
         cams = synth.label_views(views, seed=synth.SEED_BASE + 500 + j, d_lo=d_lo, d_hi=d_hi, res=res,
-                                 offset=offset)
+                                 offset=offset, fovy_deg=fovy_deg, sampling=sampling)
         params = torch.from_numpy(a.mlp.params.astype(np.float32).copy()).cuda()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -86,6 +93,9 @@ def train_assets(ctx, sc, views=512, res=512, batch=65536, steps=5000, precision
         visible = float(np.unpackbits(labels.cpu().numpy().view(np.uint8), bitorder="little").mean())
         out.append({"asset": a.name, "label_s": t1 - t0, "train_s": t2 - t1, "loss_first": float(curve[0]),
                     "loss_last100": float(curve[-100:].mean()), "label_visible_frac": visible})
+        print(f"[train] {a.name} ({'compact' if a.mlp.kind == 1 else 'frequency'} form): labels {t1 - t0:.1f} s, "
+              f"training {t2 - t1:.1f} s, loss {curve[0]:.4f} -> {curve[-100:].mean():.4f}", file=sys.stderr,
+              flush=True)
     ctx.load_assets(sc.assets)
     ctx.set_instances(sc.instances)
     return out
@@ -105,7 +115,8 @@ def calibrate_keep(ctx, sc, frac, precision):
             continue
         k = int(np.clip(round((1 - frac) * len(z)), 1, len(z) - 1))
         p = a.mlp.params.copy()
-        p[-1] = np.float32(p[-1] - 0.5 * (z[k - 1] + z[k]))
+        bo = COMPACT_BO if a.mlp.kind == 1 else -1  # the output bias
+        p[bo] = np.float32(p[bo] - 0.5 * (z[k - 1] + z[k]))
         a.mlp.params = p
     ctx.load_assets(sc.assets)
     ctx.set_instances(sc.instances)
@@ -250,7 +261,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="composed", choices=["composed", "batched", "sweep"],
+    ap.add_argument("--workload", default="composed", choices=["composed", "batched", "sweep", "ablation"],
                     help="sweep: composed scene at several camera distances, SH 3 and SH 0, culled / unculled / "
                          "radius-clipped")
     ap.add_argument("--det-clip", type=float, default=0.25, help="sweep: radius-clipping threshold (px^4)")
@@ -268,6 +279,7 @@ def parse():
     ap.add_argument("--n", type=int, default=250000)
     ap.add_argument("--frames", type=int, default=360, help="batched: ring positions (1 degree apart)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compact", action="store_true", help="composed: skip the compact-form comparison")
     ap.add_argument("--extra-precisions", default="bf16,fp8",
                     help="comma list of reduced-precision MLP forms timed beside the FP32 one")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -294,6 +306,8 @@ def main():
         return main_batched(args)
     if args.workload == "sweep":
         return main_sweep(args)
+    if args.workload == "ablation":
+        return main_ablation(args)
     import torch
     import paper_2511_19202_amd as nvgs
     import synth
@@ -374,9 +388,154 @@ def main():
         "keep_frac_of_in_frustum": st_c["kept"] / max(1, st_c["in_frustum"]),
         "training": training,
     }
+    if not args.no_compact:
+        out["compact_form"] = compact_report(ctx, sc, args, img_u)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, img_c)
     print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+def compact_assets(sc, fovy_deg=50.0):
+    """The scene's assets with the paper's compact MLP form (Sec. 3.2):
+    seeded weights, distance input normalised over the asset's Eq. 1 range."""
+    import synth
+    return [synth.make_compact(a, synth.SEED_BASE + 700 + j, *synth.eq1_range(a.name, fovy_deg=fovy_deg))
+            for j, a in enumerate(sc.assets)]
+
+
+def compact_report(ctx, sc, args, img_u):
+    """The same frame with each asset's MLP in the paper's compact form,
+    trained with the same recipe (or calibrated like the headline form): FPS,
+    MLP stage time and queries/s, PSNR against the unculled frame, in FP32 and
+    with a BF16 second layer."""
+    import copy
+    sc2 = copy.copy(sc)
+    sc2.assets = compact_assets(sc)
+    ctx.load_assets(sc2.assets)
+    ctx.set_instances(sc2.instances)
+    training = None
+    if args.mlp == "trained":
+        training = train_assets(ctx, sc2, views=args.views, steps=args.train_steps, recipe=args.recipe)
+    else:
+        calibrate_keep(ctx, sc2, args.keep, "fp32")
+    tile, tune = prepare(ctx, [sc2.cameras], args.tile, "fp32")
+    rep = {"tile": tile, "mlp_shape": list(ctx.mlp_shape), "autotune": tune, "training": training,
+           "params_per_asset": int(sc2.assets[0].mlp.params.size)}
+    for p in ("fp32", "bf16"):
+        t, per = time_graph(ctx, [sc2.cameras], args.steps, args.warmup, use_mlp=True, tile=tile, precision=p)
+        check_no_overflow(ctx)
+        _, stage, st, img = time_frames(ctx, sc2, max(5, args.steps // 5), 2, use_mlp=True, tile=tile, precision=p)
+        rep[p] = {"fps": 1.0 / t, "frame_ms_p50": float(np.percentile(per, 50)),
+                  "frame_ms_p99": float(np.percentile(per, 99)), "ms_stage": stage,
+                  "mlp_queries_per_s": st["queried"] / (stage["cull_mlp"] * 1e-3),
+                  "psnr_culled_vs_unculled_db": psnr(img.cpu().numpy(), img_u), "queried": st["queried"],
+                  "kept": st["kept"], "keep_frac_of_in_frustum": st["kept"] / max(1, st["in_frustum"]),
+                  "workspace_bytes": st["workspace_bytes"]}
+    # restore the headline form
+    ctx.load_assets(sc.assets)
+    ctx.set_instances(sc.instances)
+    return rep
+
+
+def main_ablation(args):
+    """A synthetic analogue of the paper's ablation (Sec. 4.3): compact MLPs
+    trained on views of 60 degree FoV, rendered by a 20 degree camera at six
+    distances along one ray; variants add, in order, Fibonacci instead of
+    longitude-latitude view sampling, the random view offset, auxiliary
+    views, the FoV correction of Eq. 2 (without it the renderer feeds the
+    uncorrected distance) and radius clipping.  Per variant: FPS at the
+    largest distance, PSNR and 1 - SSIM against the unculled frame averaged
+    over the distances, and the peak frame workspace."""
+    import copy
+    import torch
+    import paper_2511_19202_amd as nvgs
+    import synth
+
+    prec = args.precision or "fp32"
+    f_train, fov_r = 60.0, 20.0
+    sc = synth.scene_composed(n_per_asset=args.n)
+    sc.assets = compact_assets(sc, fovy_deg=f_train)
+    ft = float(np.float32(0.5 * 512 / math.tan(math.radians(f_train) / 2)))
+    for a in sc.assets:
+        a.mlp.train_focal = ft
+    base = sc.cameras[0]
+    # the narrow camera backed off so that it frames the composed plane as the 50 degree one does
+    back = math.tan(math.radians(25.0)) / math.tan(math.radians(fov_r / 2))
+    factors = (1.0, 1.5, 2.0, 3.0, 4.0, 6.0)
+    cams = [synth.camera(np.asarray(base.pos, np.float64) * back * f, fovy_deg=fov_r, width=base.width,
+                         height=base.height) for f in factors]
+    f_r = 0.5 * base.height / math.tan(float(np.float32(math.radians(fov_r))) / 2)
+    ctx = nvgs.Context(0)
+    ctx.load_assets(sc.assets)
+    ctx.set_instances(sc.instances)
+
+    def size_for(cam, **kw):
+        ctx.watermarks(reset=True)
+        ctx.render([cam], tile=8, precision=prec, **kw)
+        wm = ctx.watermarks(reset=True)
+        ctx.reserve(int(wm["max_splats"] * 1.1) + 4096, int(wm["max_duplicates"] * 1.1) + 4096)
+
+    # unculled references and their FPS (the same for every variant)
+    ref, fps_u = [], []
+    for cam in cams:
+        ref.append(ctx.render([cam], tile=8, precision=prec, use_mlp=False).cpu().numpy()[0])
+        size_for(cam, use_mlp=False)
+        t, _ = time_graph(ctx, [[cam]], 20, 3, tile=8, precision=prec, use_mlp=False)
+        fps_u.append(1.0 / t)
+    trainings = {"longlat": dict(sampling="longlat", offset=0.0, aux=0),
+                 "fibonacci": dict(offset=0.0, aux=0),
+                 "offset": dict(offset=0.1, aux=0),
+                 "aux": dict(offset=0.1, aux=6)}
+    variants = [("LongLat sampling", "longlat", False, 0.0), ("Fibonacci sampling", "fibonacci", False, 0.0),
+                ("+ random offset", "offset", False, 0.0), ("+ auxiliary views", "aux", False, 0.0),
+                ("full (+ FoV correction)", "aux", True, 0.0), ("+ radius clipping", "aux", True, args.det_clip)]
+    trained = {}
+    rows = []
+    init = [a.mlp.params for a in sc.assets]  # every variant trains from the same seeded weights
+    for name, tkey, fov_corr, clip in variants:
+        if tkey not in trained:
+            scv = copy.copy(sc)
+            scv.assets = [copy.copy(a) for a in sc.assets]
+            for a, p in zip(scv.assets, init):
+                a.mlp = copy.copy(a.mlp)
+                a.mlp.params = p
+                a.mlp.train_focal = ft
+            ctx.load_assets(scv.assets)
+            ctx.set_instances(scv.instances)
+            t0 = time.perf_counter()
+            train_assets(ctx, scv, views=args.views, steps=args.train_steps, recipe="paper", fovy_deg=f_train,
+                         **trainings[tkey])
+            trained[tkey] = ([a.mlp.params for a in scv.assets], time.perf_counter() - t0)
+            print(f"[ablation] trained '{tkey}' in {trained[tkey][1]:.1f} s", file=sys.stderr, flush=True)
+        for a, p in zip(sc.assets, trained[tkey][0]):
+            a.mlp.params = p
+            # without the correction the renderer's own focal length stands in for the training one
+            a.mlp.train_focal = ft if fov_corr else float(np.float32(f_r))
+        ctx.load_assets(sc.assets)
+        ctx.set_instances(sc.instances)
+        per_d = []
+        for cam, r in zip(cams, ref):
+            img, st = ctx.render([cam], tile=8, precision=prec, det_clip=clip, stats=True)
+            img = img.cpu().numpy()[0]
+            size_for(cam, det_clip=clip)
+            t, _ = time_graph(ctx, [[cam]], 20, 3, tile=8, precision=prec, det_clip=clip)
+            check_no_overflow(ctx)
+            per_d.append({"distance": float(np.linalg.norm(cam.pos)), "fps": 1.0 / t, "psnr_db": psnr(img, r),
+                          "ssim": ssim(img, r), "kept": st["kept"], "in_frustum": st["in_frustum"],
+                          "workspace_gb": st["workspace_bytes"] / 1e9})
+        row = {"variant": name, "fps_at_max_distance": per_d[-1]["fps"],
+               "psnr_mean_db": float(np.mean([x["psnr_db"] for x in per_d])),
+               "one_minus_ssim_mean": float(np.mean([1 - x["ssim"] for x in per_d])),
+               "workspace_gb_peak": max(x["workspace_gb"] for x in per_d), "per_distance": per_d}
+        rows.append(row)
+        print(f"[ablation] {name}: {row['fps_at_max_distance']:.1f} FPS at the largest distance, "
+              f"PSNR {row['psnr_mean_db']:.2f} dB, 1-SSIM {row['one_minus_ssim_mean']:.4f}, "
+              f"{row['workspace_gb_peak']:.2f} GB", file=sys.stderr, flush=True)
+    print(json.dumps({"workload": "ablation: composed scene, compact MLPs trained at 60 deg FoV, 20 deg camera "
+                                  "at 6 distances", "mlp_precision": prec, "det_clip": args.det_clip,
+                      "unculled_fps": fps_u, "distances": [float(np.linalg.norm(c.pos)) for c in cams],
+                      "training_s": {k: v[1] for k, v in trained.items()}, "rows": rows}), flush=True)
     ctx.close()
 
 
@@ -486,7 +645,7 @@ def main_sweep(args):
     ctx.load_assets(sc.assets)
     ctx.set_instances(sc.instances)
     if args.mlp == "trained":
-        train_assets(ctx, sc, views=args.views, steps=args.train_steps)
+        train_assets(ctx, sc, views=args.views, steps=args.train_steps, recipe=args.recipe)
     else:
         calibrate_keep(ctx, sc, args.keep, prec)
     sc0 = copy.copy(sc)

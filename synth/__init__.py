@@ -398,14 +398,28 @@ def fibonacci_sphere(n: int) -> np.ndarray:
     return np.stack([rho * np.cos(phi), rho * np.sin(phi), z], axis=1)
 
 
+def longlat_sphere(n: int) -> np.ndarray:
+    """About n unit directions on a longitude-latitude grid (equal angular
+    steps, so denser towards the poles), [n, 3]: ceil(sqrt(n / 2)) latitude
+    rings at cell centres, 2x as many longitudes, truncated to n."""
+    n_lat = max(1, math.ceil(math.sqrt(n / 2)))
+    n_lon = max(1, math.ceil(n / n_lat))
+    lat = -math.pi / 2 + math.pi * (np.arange(n_lat) + 0.5) / n_lat
+    lon = 2 * math.pi * np.arange(n_lon) / n_lon
+    la, lo = np.meshgrid(lat, lon, indexing="ij")
+    d = np.stack([np.cos(la) * np.cos(lo), np.cos(la) * np.sin(lo), np.sin(la)], axis=-1).reshape(-1, 3)
+    return d[:n]
+
+
 def label_views(n_views: int, seed: int, d_lo: float = 1.5, d_hi: float = 20.0,
-                res: int = 512, fovy_deg: float = 50.0, offset: float = 0.0) -> List[Camera]:
-    """Training views (Sec. 3.1 recipe): Fibonacci-sphere directions, distance
-    U(d_lo, d_hi) per view, looking at the asset centre displaced by a random
-    offset of at most `offset` * distance * tan(fovy / 2) per axis (so the
-    asset stays in the frustum while leaving the image centre)."""
+                res: int = 512, fovy_deg: float = 50.0, offset: float = 0.0, sampling: str = "fibonacci") -> List[Camera]:
+    """Training views (Sec. 3.1 recipe): Fibonacci-sphere directions (or a
+    longitude-latitude grid, the ablation's baseline), distance U(d_lo, d_hi)
+    per view, looking at the asset centre displaced by a random offset of at
+    most `offset` * distance * tan(fovy / 2) per axis (so the asset stays in
+    the frustum while leaving the image centre)."""
     g = rng(seed)
-    d = fibonacci_sphere(n_views)
+    d = fibonacci_sphere(n_views) if sampling == "fibonacci" else longlat_sphere(n_views)
     r = g.uniform(d_lo, d_hi, n_views)
     off = g.uniform(-1.0, 1.0, (n_views, 3))
     t = math.tan(math.radians(fovy_deg) / 2)
