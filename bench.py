@@ -264,7 +264,7 @@ def parse():
     ap.add_argument("--workload", default="composed", choices=["composed", "batched", "sweep", "ablation"],
                     help="sweep: composed scene at several camera distances, SH 3 and SH 0, culled / unculled / "
                          "radius-clipped")
-    ap.add_argument("--det-clip", type=float, default=0.25, help="sweep: radius-clipping threshold (px^4)")
+    ap.add_argument("--det-clip", type=float, default=0.1, help="sweep, ablation: radius-clipping threshold (px^4)")
     ap.add_argument("--tile", type=int, default=0, help="8, 16, 32, or 0 to autotune (tile and MLP block shape)")
     ap.add_argument("--precision", default=None, help="MLP precision (default fp32 composed, bf16 batched)")
     ap.add_argument("--mlp", default="trained", choices=["trained", "random"],
