@@ -280,6 +280,10 @@ def parse():
     ap.add_argument("--frames", type=int, default=360, help="batched: ring positions (1 degree apart)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compact", action="store_true", help="composed: skip the compact-form comparison")
+    ap.add_argument("--aligned", action="store_true",
+                    help="composed, sweep, ablation: flat surface-aligned Gaussians instead of random orientations")
+    ap.add_argument("--compact-steps", type=int, default=0,
+                    help="training steps of the compact form (0: --train-steps)")
     ap.add_argument("--extra-precisions", default="bf16,fp8",
                     help="comma list of reduced-precision MLP forms timed beside the FP32 one")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -313,7 +317,7 @@ def main():
     import synth
 
     prec = args.precision or "fp32"
-    sc = synth.scene_composed(n_per_asset=args.n)
+    sc = synth.scene_composed(n_per_asset=args.n, aligned=args.aligned)
     ctx = nvgs.Context(0)
     ctx.load_assets(sc.assets)
     ctx.set_instances(sc.instances)
@@ -366,6 +370,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "composed-1080p: 4 assets x 250k SH3 Gaussians, 64 instances, 1 camera, "
                                "width-64 MLP per asset",
+                   "gaussian_orientation": "surface-aligned discs" if args.aligned else "random",
                    "gaussians_stored": sum(a.n for a in sc.assets), "instances": len(sc.instances),
                    "pairs": st_c["pairs"], "resolution": "1920x1080", "mlp_precision": prec,
                    "tile": tile, "mlp_shape": list(ctx.mlp_shape), "autotune": tune, "mlp": args.mlp,
@@ -416,7 +421,8 @@ def compact_report(ctx, sc, args, img_u):
     ctx.set_instances(sc2.instances)
     training = None
     if args.mlp == "trained":
-        training = train_assets(ctx, sc2, views=args.views, steps=args.train_steps, recipe=args.recipe)
+        training = train_assets(ctx, sc2, views=args.views, steps=args.compact_steps or args.train_steps,
+                                recipe=args.recipe)
     else:
         calibrate_keep(ctx, sc2, args.keep, "fp32")
     tile, tune = prepare(ctx, [sc2.cameras], args.tile, "fp32")
@@ -454,7 +460,7 @@ def main_ablation(args):
 
     prec = args.precision or "fp32"
     f_train, fov_r = 60.0, 20.0
-    sc = synth.scene_composed(n_per_asset=args.n)
+    sc = synth.scene_composed(n_per_asset=args.n, aligned=args.aligned)
     sc.assets = compact_assets(sc, fovy_deg=f_train)
     ft = float(np.float32(0.5 * 512 / math.tan(math.radians(f_train) / 2)))
     for a in sc.assets:
@@ -504,8 +510,8 @@ def main_ablation(args):
             ctx.load_assets(scv.assets)
             ctx.set_instances(scv.instances)
             t0 = time.perf_counter()
-            train_assets(ctx, scv, views=args.views, steps=args.train_steps, recipe="paper", fovy_deg=f_train,
-                         **trainings[tkey])
+            train_assets(ctx, scv, views=args.views, steps=args.compact_steps or args.train_steps, recipe="paper",
+                         fovy_deg=f_train, **trainings[tkey])
             trained[tkey] = ([a.mlp.params for a in scv.assets], time.perf_counter() - t0)
             print(f"[ablation] trained '{tkey}' in {trained[tkey][1]:.1f} s", file=sys.stderr, flush=True)
         for a, p in zip(sc.assets, trained[tkey][0]):
@@ -640,7 +646,7 @@ def main_sweep(args):
     import synth
 
     prec = args.precision or "fp32"
-    sc = synth.scene_composed(n_per_asset=args.n)
+    sc = synth.scene_composed(n_per_asset=args.n, aligned=args.aligned)
     ctx = nvgs.Context(0)
     ctx.load_assets(sc.assets)
     ctx.set_instances(sc.instances)

@@ -186,8 +186,9 @@ def gaussian_params(means: np.ndarray, g: np.random.Generator, sh_degree: int,
 # ----------------------------------------------------------------------------
 # shapes (means only)
 # ----------------------------------------------------------------------------
-def torus_means(n, g, R=1.0, r=0.35, jitter=0.01):
-    """Area-uniform torus surface (axis +z) plus N(0, jitter^2) jitter."""
+def torus_means(n, g, R=1.0, r=0.35, jitter=0.01, normals=False):
+    """Area-uniform torus surface (axis +z) plus N(0, jitter^2) jitter (and the
+    unit surface normals [3, n] of the points before jitter if `normals`)."""
     out_u = np.empty(0)
     out_v = np.empty(0)
     while out_u.size < n:
@@ -203,16 +204,19 @@ def torus_means(n, g, R=1.0, r=0.35, jitter=0.01):
     y = (R + r * np.cos(v)) * np.sin(u)
     z = r * np.sin(v)
     p = np.stack([x, y, z]) + g.normal(0, jitter, size=(3, n))
+    if normals:
+        return p.astype(np.float32), np.stack([np.cos(v) * np.cos(u), np.cos(v) * np.sin(u), np.sin(v)])
     return p.astype(np.float32)
 
 
-def sphere_means(n, g, radius=1.0, jitter=0.01):
+def sphere_means(n, g, radius=1.0, jitter=0.01, normals=False):
     d = g.standard_normal((3, n))
     d /= np.linalg.norm(d, axis=0, keepdims=True)
-    return (radius * d + g.normal(0, jitter, size=(3, n))).astype(np.float32)
+    p = (radius * d + g.normal(0, jitter, size=(3, n))).astype(np.float32)
+    return (p, d) if normals else p
 
 
-def box_means(n, g, half=1.0, jitter=0.01):
+def box_means(n, g, half=1.0, jitter=0.01, normals=False):
     face = g.integers(0, 6, n)
     a = g.uniform(-half, half, n)
     b = g.uniform(-half, half, n)
@@ -225,10 +229,15 @@ def box_means(n, g, half=1.0, jitter=0.01):
         p[ax, sel] = sign[sel] * half
         p[o1, sel] = a[sel]
         p[o2, sel] = b[sel]
-    return (p + g.normal(0, jitter, size=(3, n))).astype(np.float32)
+    q = (p + g.normal(0, jitter, size=(3, n))).astype(np.float32)
+    if normals:
+        nrm = np.zeros((3, n))
+        nrm[axis, np.arange(n)] = sign
+        return q, nrm
+    return q
 
 
-def helix_means(n, g, radius=0.8, pitch=0.15, turns=3.0, tube=0.15, jitter=0.01):
+def helix_means(n, g, radius=0.8, pitch=0.15, turns=3.0, tube=0.15, jitter=0.01, normals=False):
     th = g.uniform(0, 2 * np.pi * turns, n)
     ph = g.uniform(0, 2 * np.pi, n)
     c = np.stack([radius * np.cos(th), radius * np.sin(th), pitch * th - pitch * np.pi * turns])
@@ -236,8 +245,10 @@ def helix_means(n, g, radius=0.8, pitch=0.15, turns=3.0, tube=0.15, jitter=0.01)
     t /= np.linalg.norm(t, axis=0, keepdims=True)
     nrm = np.stack([-np.cos(th), -np.sin(th), np.zeros(n)])
     bin_ = np.cross(t.T, nrm.T).T
-    p = c + tube * (np.cos(ph) * nrm + np.sin(ph) * bin_)
-    return (p + g.normal(0, jitter, size=(3, n))).astype(np.float32)
+    out = np.cos(ph) * nrm + np.sin(ph) * bin_
+    p = c + tube * out
+    q = (p + g.normal(0, jitter, size=(3, n))).astype(np.float32)
+    return (q, out / np.linalg.norm(out, axis=0, keepdims=True)) if normals else q
 
 
 SHAPES = {"torus": torus_means, "sphere": sphere_means, "box": box_means, "helix": helix_means}
@@ -255,12 +266,40 @@ def pow2_scale(r: float) -> float:
     return 2.0 ** (-math.ceil(math.log2(r)))
 
 
+def surface_frames(normals: np.ndarray, g: np.random.Generator) -> np.ndarray:
+    """Unit quaternions (w, x, y, z), [4, n], of rotations whose third axis is
+    the given normal, with a uniform random twist about it: the shortest-arc
+    rotation from +z to the normal composed with a rotation about +z."""
+    nz = normals / np.linalg.norm(normals, axis=0, keepdims=True)
+    n = nz.shape[1]
+    # shortest arc z -> n: (1 + z.n, z x n) normalised; the antipode takes a half turn about x
+    q1 = np.stack([1.0 + nz[2], -nz[1], nz[0], np.zeros(n)])
+    flip = nz[2] < -1.0 + 1e-9
+    q1[:, flip] = np.array([[0.0], [1.0], [0.0], [0.0]])
+    q1 /= np.linalg.norm(q1, axis=0, keepdims=True)
+    psi = g.uniform(0, 2 * np.pi, n)
+    c, s_ = np.cos(psi / 2), np.sin(psi / 2)
+    w1, x1, y1, z1 = q1
+    # q1 * (c, 0, 0, s)
+    q = np.stack([w1 * c - z1 * s_, x1 * c + y1 * s_, y1 * c - x1 * s_, z1 * c + w1 * s_])
+    return q.astype(np.float32)
+
+
 def make_asset(shape: str, n: int, sh_degree: int, seed: int, width: int = 64,
                cam_scale: float = 0.05, fov_train: float = math.radians(50.0), res_train: int = 512,
-               d_max: float = 20.0) -> Asset:
+               d_max: float = 20.0, aligned: bool = False) -> Asset:
+    """One synthetic asset.  aligned: the Gaussians are flat discs lying in
+    the surface (as in optimised 3DGS assets): the scale along the surface
+    normal shrunk 10x and the rotation's third axis on the normal (random
+    twist); otherwise random orientations with independent per-axis scales."""
     g = rng(seed)
-    means = SHAPES[shape](n, g)
+    means, normals = SHAPES[shape](n, g, normals=True)
     scale, quat, opacity, sh = gaussian_params(means, g, sh_degree)
+    if aligned:
+        g2 = rng(seed + 7919)
+        scale = scale.copy()
+        scale[2] *= np.float32(0.1)
+        quat = surface_frames(normals, g2)
     params = mlp_params(width, g)
     spec = MLPSpec(params=params, width=width, bands=6,
                    mean_scale=pow2_scale(SHAPE_HALF_DIAG[shape]), cam_scale=cam_scale,
@@ -315,12 +354,13 @@ def scene_tiny(n: int = 20000, seed: int = SEED_BASE + 1, width: int = 64,
 
 def scene_composed(n_per_asset: int = 250000, n_inst: int = 64, seed: int = SEED_BASE + 2,
                    width: int = 64, res=(1920, 1080), tile: int = 16, sh_degree: int = 3,
-                   half_extent: float = 20.0) -> Scene:
+                   half_extent: float = 20.0, aligned: bool = False) -> Scene:
     """4 assets (torus, sphere shell, box shell, helix tube), SH3; n_inst
     instances with random yaw, scale U(0.5, 2), positions U(-20, 20)^2 at z=0;
-    one camera at (0, -30, 12) looking at the origin."""
+    one camera at (0, -30, 12) looking at the origin.  aligned: surface-aligned
+    flat Gaussians (see make_asset)."""
     names = ["torus", "sphere", "box", "helix"]
-    assets = [make_asset(nm, n_per_asset, sh_degree, seed * 100 + j, width=width)
+    assets = [make_asset(nm, n_per_asset, sh_degree, seed * 100 + j, width=width, aligned=aligned)
               for j, nm in enumerate(names)]
     g = rng(seed)
     insts = []
