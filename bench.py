@@ -53,7 +53,7 @@ BLEND_PEAK_GTESTS = VALU_LANE_OPS / BLEND_SLOTS_PER_TEST / 1e9
 
 
 def train_assets(ctx, sc, views=512, res=512, batch=65536, steps=5000, precision="bf16", lr=1e-3, seed=1,
-                 weighting=1, aux=6, aux_deg=5.0, offset=0.1, recipe="workload", sampling="fibonacci",
+                 weighting=1, aux=6, aux_deg=5.0, offset=1.0, recipe="workload", sampling="fibonacci",
                  fovy_deg=50.0):
     """Train each asset's visibility MLP on labels the renderer makes from
     `views` Fibonacci-sphere (or longitude-latitude) views of `fovy_deg`,
@@ -77,7 +77,8 @@ def train_assets(ctx, sc, views=512, res=512, batch=65536, steps=5000, precision
                 a.mlp.cam_scale = float(np.float32(1.0 / d_hi))  # keeps the encoded camera position in [-1, 1]
             batch, lr, lr_final = 1 << 19, 2e-3, 2e-4
         cams = synth.label_views(views, seed=synth.SEED_BASE + 500 + j, d_lo=d_lo, d_hi=d_hi, res=res,
-                                 offset=offset, fovy_deg=fovy_deg, sampling=sampling)
+                                 offset=offset, fovy_deg=fovy_deg, sampling=sampling,
+                                 radius=synth.SHAPE_HALF_DIAG[a.name])
         params = torch.from_numpy(a.mlp.params.astype(np.float32).copy()).cuda()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -491,8 +492,8 @@ def main_ablation(args):
         fps_u.append(1.0 / t)
     trainings = {"longlat": dict(sampling="longlat", offset=0.0, aux=0),
                  "fibonacci": dict(offset=0.0, aux=0),
-                 "offset": dict(offset=0.1, aux=0),
-                 "aux": dict(offset=0.1, aux=6)}
+                 "offset": dict(offset=1.0, aux=0),
+                 "aux": dict(offset=1.0, aux=6)}
     variants = [("LongLat sampling", "longlat", False, 0.0), ("Fibonacci sampling", "fibonacci", False, 0.0),
                 ("+ random offset", "offset", False, 0.0), ("+ auxiliary views", "aux", False, 0.0),
                 ("full (+ FoV correction)", "aux", True, 0.0), ("+ radius clipping", "aux", True, args.det_clip)]

@@ -452,18 +452,24 @@ def longlat_sphere(n: int) -> np.ndarray:
 
 
 def label_views(n_views: int, seed: int, d_lo: float = 1.5, d_hi: float = 20.0,
-                res: int = 512, fovy_deg: float = 50.0, offset: float = 0.0, sampling: str = "fibonacci") -> List[Camera]:
-    """Training views (Sec. 3.1 recipe): Fibonacci-sphere directions (or a
-    longitude-latitude grid, the ablation's baseline), distance U(d_lo, d_hi)
-    per view, looking at the asset centre displaced by a random offset of at
-    most `offset` * distance * tan(fovy / 2) per axis (so the asset stays in
-    the frustum while leaving the image centre)."""
+                res: int = 512, fovy_deg: float = 50.0, offset: float = 0.0, sampling: str = "fibonacci",
+                radius: float = 1.0) -> List[Camera]:
+    """Training views (Sec. 3.1, 4.1 recipe): Fibonacci-sphere directions (or
+    a longitude-latitude grid, the ablation's baseline), distance U(d_lo,
+    d_hi) per view, looking at the asset centre displaced by a random offset:
+    none at d_lo, growing linearly with the distance to at most
+    `offset` * radius * d_hi / d_lo at d_hi, uniform in that ball.  With
+    offset 1 and the asset's half-diagonal as radius, an asset at d_hi (where
+    it covers p_far of the image) moves by up to (p_near / p_far) radii, so it
+    stays in the frame at every distance."""
     g = rng(seed)
     d = fibonacci_sphere(n_views) if sampling == "fibonacci" else longlat_sphere(n_views)
     r = g.uniform(d_lo, d_hi, n_views)
-    off = g.uniform(-1.0, 1.0, (n_views, 3))
-    t = math.tan(math.radians(fovy_deg) / 2)
-    return [camera(d[k] * r[k], target=tuple(off[k] * offset * r[k] * t), fovy_deg=fovy_deg, width=res, height=res)
+    u = g.standard_normal((n_views, 3))
+    u *= (g.uniform(0.0, 1.0, n_views) ** (1.0 / 3.0) / np.linalg.norm(u, axis=1))[:, None]
+    lam = (r - d_lo) / max(d_hi - d_lo, 1e-12)
+    off = u * (offset * radius * (d_hi / d_lo) * lam)[:, None]
+    return [camera(d[k] * r[k], target=tuple(off[k]), fovy_deg=fovy_deg, width=res, height=res)
             for k in range(n_views)]
 
 
