@@ -148,7 +148,7 @@ typedef struct nvgs_render_opts {
   int32_t split_len; /* tile lists longer than this are composited in chunks of at most
                         this many entries by separate work-groups, which equals the
                         sequential composite up to rounding (the association of the
-                        transmittance products and colour sums); 0: default 2048;
+                        transmittance products and colour sums); 0: default 1024;
                         < 0: never split (bit-identical across tile sizes); else >= 64 */
   float det_clip;    /* radius clipping (Sec. 4.3 ablation): a splat whose 2D covariance
                         (after the 0.3 px^2 dilation) has a determinant below det_clip

@@ -19,7 +19,7 @@ struct Buf {
 };
 
 constexpr int kCounters = 24;       // u32 words of the frame counters
-constexpr int kSplitDefault = 2048; // tile-list entries per compositing chunk
+constexpr int kSplitDefault = 1024; // tile-list entries per compositing chunk
 
 }  // namespace
 

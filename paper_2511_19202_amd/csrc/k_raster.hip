@@ -500,8 +500,15 @@ struct ItemCtx {
   float4* part;             // [split chunk][T*T]: r, g, b, flag
 };
 
-// MODE 0: composite; 1: composite and record contributions; 2: product pass
-template <int T, int MODE>
+// A pixel that has stopped (or lies outside the image, or stopped in an
+// earlier chunk) is moved to x = kFar: every later quadratic form is -inf, so
+// it fails the level-set test with no per-pixel flag to keep.
+constexpr float kFar = 1e30f;
+constexpr float kFarTest = 1e29f;
+
+// MODE 0: composite; 1: composite and record contributions; 2: product pass.
+// STATS: also count the list entries each pixel examined (statistics frames).
+template <int T, int MODE, bool STATS>
 __global__ __launch_bounds__(T == 8 ? 64 : 256) void k_blend(
     ItemCtx ic, const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ ids,
     const float4* __restrict__ splat, int W, int H, int tiles_x, int n_tiles, float bg0, float bg1, float bg2,
@@ -534,19 +541,20 @@ __global__ __launch_bounds__(T == 8 ? 64 : 256) void k_blend(
   }
   const int64_t sbase = split ? ((int64_t)ic.split_off[it.x] + it.y) * (T * T) : 0;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  auto pix_x = [&](int j) { return tx * T + ((wave * BPW + j) % (T / 8)) * 8 + (lane & 7); };
+  auto pix_y = [&](int j) { return ty * T + ((wave * BPW + j) / (T / 8)) * 8 + (lane >> 3); };
   float px[BPW], py[BPW], Tr[BPW], cr[BPW], cg[BPW], cb[BPW];
-  bool done[BPW], before[BPW];
-  uint32_t stop[BPW];  // list position at which the pixel stopped (end if it never did)
+  bool before[BPW];
+  uint32_t stop[BPW];  // statistics: list position at which the pixel stopped (end if it never did)
 #pragma unroll
   for (int j = 0; j < BPW; ++j) {
     stop[j] = end;
     const int blk = wave * BPW + j;
-    const int x = tx * T + (blk % (T / 8)) * 8 + (lane & 7), y = ty * T + (blk / (T / 8)) * 8 + (lane >> 3);
-    px[j] = (float)x + 0.5f;
+    const int x = pix_x(j), y = pix_y(j);
+    px[j] = (x < W && y < H) ? (float)x + 0.5f : kFar;
     py[j] = (float)y + 0.5f;
     Tr[j] = 1.f;
     cr[j] = cg[j] = cb[j] = 0.f;
-    done[j] = !(x < W && y < H);
     before[j] = false;
     if (split && !PROD && it.y > 0) {
       // transmittance entering this chunk: product of the earlier chunks' products
@@ -556,7 +564,7 @@ __global__ __launch_bounds__(T == 8 ? 64 : 256) void k_blend(
       for (uint32_t q = 0; q < it.y; ++q) tin *= ic.prod[b0 + (int64_t)q * (T * T)];
       Tr[j] = tin;
       before[j] = tin < kTMin;
-      done[j] = done[j] || before[j];
+      px[j] = before[j] ? kFar : px[j];
     }
   }
   // the next batch's record of this thread, fetched while the current one is composited
@@ -581,29 +589,30 @@ __global__ __launch_bounds__(T == 8 ? 64 : 256) void k_blend(
     const float dx = px[j] - g.x, dy = py[j] - g.y;
     const float pw = dx * fmaf(g.z, dx, g.w * dy) + h.x * dy * dy;
     const float al = fminf(kAlphaMax, h.y * __builtin_amdgcn_exp2f(pw));
-    const bool ok = !done[j] && pw >= h.z && pw <= 0.f && al >= kAlphaMin;
+    const bool ok = pw >= h.z && pw <= 0.f && al >= kAlphaMin;
     const float Tn = Tr[j] * (1.f - al);
     if (PROD) {
       Tr[j] = ok ? Tn : Tr[j];
-      done[j] = done[j] || Tr[j] < kTMin;
+      px[j] = Tr[j] < kTMin ? kFar : px[j];
       return;
     }
     const float2 c = s_c[k];
-    const bool halt = ok && Tn < kTMin;
-    const bool take = ok && !halt;
+    const bool low = Tn < kTMin;
+    const bool take = ok && !low;
     const float w = take ? al * Tr[j] : 0.f;
     cr[j] = fmaf(w, h.w, cr[j]);
     cg[j] = fmaf(w, c.x, cg[j]);
     cb[j] = fmaf(w, c.y, cb[j]);
     Tr[j] = take ? Tn : Tr[j];
-    stop[j] = halt ? b0k + (uint32_t)k : stop[j];
-    done[j] = done[j] || halt;
+    if (STATS) stop[j] = (ok && low) ? b0k + (uint32_t)k : stop[j];
+    px[j] = (ok && low) ? kFar : px[j];
     if (RECORD && take) atomicMax(contrib + s_p[k], __float_as_uint(w));
   };
+  auto live = [&](int j) { return px[j] < kFarTest; };
   for (uint32_t b0 = start; b0 < end; b0 += BATCH) {
     bool any = false;
 #pragma unroll
-    for (int j = 0; j < BPW; ++j) any |= !done[j];
+    for (int j = 0; j < BPW; ++j) any |= live(j);
     if (__syncthreads_count(any) == 0) break;  // also: the previous batch is consumed
     const int cnt = (int)min((uint32_t)BATCH, end - b0);
     b0k = b0;
@@ -637,14 +646,14 @@ __global__ __launch_bounds__(T == 8 ? 64 : 256) void k_blend(
     }
 #pragma unroll
     for (int j = 0; j < BPW; ++j) {
-      if (__ballot(!done[j]) == 0) continue;
+      if (__ballot(live(j)) == 0) continue;
       if (T == 8) {
         // every listed splat touches the tile
         for (int k = 0; k < cnt; k += 8) {
 #pragma unroll
           for (int u = 0; u < 8; ++u)
             if (k + u < cnt) step(j, k + u);
-          if (__ballot(!done[j]) == 0) break;
+          if (__ballot(live(j)) == 0) break;
         }
       } else {
         // splats whose box touches this wave's block, as 64-bit ballot sets
@@ -663,7 +672,7 @@ __global__ __launch_bounds__(T == 8 ? 64 : 256) void k_blend(
             m &= m - 1;
             step(j, k);
           }
-          if (__ballot(!done[j]) == 0) break;
+          if (__ballot(live(j)) == 0) break;
         }
       }
     }
@@ -673,12 +682,12 @@ __global__ __launch_bounds__(T == 8 ? 64 : 256) void k_blend(
     for (int j = 0; j < BPW; ++j) ic.prod[sbase + (wave * BPW + j) * 64 + lane] = Tr[j];
     return;
   }
-  if (work) {
+  if (STATS && work) {
     // entries of the tile list each pixel examined: up to and including its stop
     uint32_t wk = 0;
 #pragma unroll
     for (int j = 0; j < BPW; ++j) {
-      const int x = (int)px[j], y = (int)py[j];
+      const int x = pix_x(j), y = pix_y(j);
       if (x < W && y < H && !before[j]) wk += (stop[j] < end ? stop[j] + 1 : end) - start;
     }
     for (int o = 32; o > 0; o >>= 1) wk += __shfl_xor(wk, o);
@@ -686,14 +695,16 @@ __global__ __launch_bounds__(T == 8 ? 64 : 256) void k_blend(
   }
 #pragma unroll
   for (int j = 0; j < BPW; ++j) {
+    const int x = pix_x(j), y = pix_y(j);
     if (split) {
       // chunk record: colour and a flag: 0 if the pixel stopped in an earlier
       // chunk, -T if it stopped in this one, else the transmittance leaving it
-      const float flag = before[j] ? 0.f : (stop[j] < end ? -Tr[j] : Tr[j]);
+      // (pixels outside the image are never read back)
+      const bool stopped_here = !before[j] && !live(j);
+      const float flag = before[j] ? 0.f : (stopped_here ? -Tr[j] : Tr[j]);
       ic.part[sbase + (wave * BPW + j) * 64 + lane] = make_float4(cr[j], cg[j], cb[j], flag);
       continue;
     }
-    const int x = (int)px[j], y = (int)py[j];
     if (x < W && y < H) {
       float* o = rgb + (((int64_t)cam * H + y) * W + x) * 3;
       o[0] = fmaf(Tr[j], bg0, cr[j]);
@@ -750,14 +761,17 @@ static void launch_blend_t(bool record, const ItemCtx& ic, bool any_split, hipSt
   const dim3 grid((unsigned)ic.cap_items);
   uint32_t* cu = reinterpret_cast<uint32_t*>(contrib);
   if (any_split)
-    hipLaunchKernelGGL((k_blend<T, 2>), grid, dim3(NT), 0, st, ic, ranges, ids, splat, W, H, tiles_x, n_tiles, b0,
-                       b1, b2, rgb, cu, nullptr);
-  if (record)
-    hipLaunchKernelGGL((k_blend<T, 1>), grid, dim3(NT), 0, st, ic, ranges, ids, splat, W, H, tiles_x, n_tiles, b0,
-                       b1, b2, rgb, cu, work);
-  else
-    hipLaunchKernelGGL((k_blend<T, 0>), grid, dim3(NT), 0, st, ic, ranges, ids, splat, W, H, tiles_x, n_tiles, b0,
-                       b1, b2, rgb, cu, work);
+    hipLaunchKernelGGL((k_blend<T, 2, false>), grid, dim3(NT), 0, st, ic, ranges, ids, splat, W, H, tiles_x, n_tiles,
+                       b0, b1, b2, rgb, cu, nullptr);
+#define NVGS_BL(M, S)                                                                                            \
+  hipLaunchKernelGGL((k_blend<T, M, S>), grid, dim3(NT), 0, st, ic, ranges, ids, splat, W, H, tiles_x, n_tiles, b0, \
+                     b1, b2, rgb, cu, work)
+  if (record) {
+    if (work) NVGS_BL(1, true); else NVGS_BL(1, false);
+  } else {
+    if (work) NVGS_BL(0, true); else NVGS_BL(0, false);
+  }
+#undef NVGS_BL
   if (any_split)
     hipLaunchKernelGGL((k_blend_combine<T>), grid, dim3(256), 0, st, ic, W, H, tiles_x, n_tiles, b0, b1, b2, rgb);
 }

@@ -3,8 +3,10 @@
 // binning).  Stability is what makes the id the final tie-break: values
 // enter in id order and equal keys never swap.
 //
-// Per pass: a histogram kernel (per-block digit counts, digit-major), one
-// exclusive scan over all (digit, block) counts, and a scatter kernel.  The
+// Per pass: a histogram kernel (per-block digit counts, digit-major), a row
+// scan (one work-group per digit: exclusive scan of that digit's block counts
+// and the digit's total), and a scatter kernel, which turns the 256 digit
+// totals into digit bases with an in-block scan.  The
 // scatter ranks keys inside a block with 64-lane ballots (eight ballots give
 // the set of lanes sharing a digit), so the rank is exact and in input order
 // without atomics deciding the order; the block's keys are then reordered by
@@ -48,14 +50,60 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t* __r
   }
 }
 
+// one work-group per digit: exclusive scan of hist[d][0..nblocks) in place,
+// the row total to tot[d]
+constexpr int kRowItems = 16;
+__global__ __launch_bounds__(kSortThreads) void k_radix_rowscan(uint32_t* __restrict__ hist, int64_t nblocks,
+                                                                uint32_t* __restrict__ tot) {
+  __shared__ uint32_t s_w[kSortWaves];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t* row = hist + (int64_t)blockIdx.x * nblocks;
+  uint32_t carry = 0;
+  for (int64_t off = 0; off < nblocks; off += kSortThreads * kRowItems) {
+    const int64_t base = off + (int64_t)threadIdx.x * kRowItems;
+    uint32_t v[kRowItems];
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kRowItems; ++k) {
+      v[k] = base + k < nblocks ? row[base + k] : 0u;
+      s += v[k];
+    }
+    uint32_t x = s;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) s_w[wave] = x;
+    __syncthreads();
+    uint32_t pre = carry, all = 0;
+#pragma unroll
+    for (int w = 0; w < kSortWaves; ++w) {
+      pre += (w < wave) ? s_w[w] : 0u;
+      all += s_w[w];
+    }
+    __syncthreads();
+    pre += x - s;
+#pragma unroll
+    for (int k = 0; k < kRowItems; ++k) {
+      if (base + k < nblocks) row[base + k] = pre;
+      pre += v[k];
+    }
+    carry += all;
+  }
+  if (threadIdx.x == 0) tot[blockIdx.x] = carry;
+}
+
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, uint32_t* __restrict__ keys_out,
     uint32_t* __restrict__ vals_out, const uint32_t* __restrict__ n_dev, int64_t cap, int shift, uint32_t dmask,
-    int nbits, const uint32_t* __restrict__ offs, int64_t nblocks, int iota_vals) {
+    int nbits, const uint32_t* __restrict__ offs, int64_t nblocks, const uint32_t* __restrict__ digit_tot,
+    int iota_vals) {
   __shared__ uint32_t s_cnt[kSortWaves][256];  // per-wave digit counts, then per-wave digit bases in the block
   __shared__ uint32_t s_start[256];            // first block-local position of each digit
   __shared__ uint32_t s_glob[256];             // global position of each digit's first key of this block
   __shared__ uint32_t s_wsum[kSortWaves];
+  __shared__ uint32_t s_gsum[kSortWaves];
   __shared__ uint32_t s_k[kSortBlock];
   __shared__ uint32_t s_v[kSortBlock];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -95,19 +143,31 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     s_cnt[w][d] = tot;
     tot += c;
   }
-  s_glob[d] = offs[(int64_t)d * nblocks + blockIdx.x];
-  uint32_t x = tot;
+  // digit d's global base: the exclusive scan of the digit totals plus this
+  // block's row-exclusive count
+  const uint32_t gt = digit_tot[d];
+  uint32_t x = tot, xg = gt;
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t y = __shfl_up(x, o);
-    if (lane >= o) x += y;
+    const uint32_t y = __shfl_up(x, o), yg = __shfl_up(xg, o);
+    if (lane >= o) {
+      x += y;
+      xg += yg;
+    }
   }
-  if (lane == 63) s_wsum[wave] = x;
+  if (lane == 63) {
+    s_wsum[wave] = x;
+    s_gsum[wave] = xg;
+  }
   __syncthreads();
-  uint32_t wbase = 0;
+  uint32_t wbase = 0, gbase = 0;
 #pragma unroll
-  for (int w = 0; w < kSortWaves; ++w) wbase += (w < wave) ? s_wsum[w] : 0u;
+  for (int w = 0; w < kSortWaves; ++w) {
+    wbase += (w < wave) ? s_wsum[w] : 0u;
+    gbase += (w < wave) ? s_gsum[w] : 0u;
+  }
   s_start[d] = wbase + x - tot;
+  s_glob[d] = gbase + xg - gt + offs[(int64_t)d * nblocks + blockIdx.x];
   __syncthreads();
   // phase 3: keys and values into LDS in (digit, input) order
 #pragma unroll
@@ -132,9 +192,10 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
   }
 }
 
+// digit-major block counts, then the 256 digit totals
 size_t radix_hist_words(int64_t cap) {
   int64_t nb = (cap + kSortBlock - 1) / kSortBlock;
-  return (size_t)(256 * (nb > 0 ? nb : 1));
+  return (size_t)(256 * ((nb > 0 ? nb : 1) + 1));
 }
 
 // Sorts keys[0..n) (n = *n_dev, at most cap) by bits [begin_bit, end_bit).
@@ -157,11 +218,12 @@ hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp,
   for (int shift = begin_bit; shift < end_bit; shift += 8) {
     const int nbits = min(8, end_bit - shift);
     const uint32_t dmask = (1u << nbits) - 1u;
+    uint32_t* tot = hist + 256 * nb;
     hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kSortThreads), 0, st, kin, n_dev, cap, shift, dmask,
                        hist, nb);
-    (void)launch_scan_u32_dev(hist, hist, 256 * nb, nullptr, nullptr, partials, st, nullptr);
+    hipLaunchKernelGGL(k_radix_rowscan, dim3(256), dim3(kSortThreads), 0, st, hist, nb, tot);
     hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(kSortThreads), 0, st, kin, vin, kout, vout, n_dev,
-                       cap, shift, dmask, nbits, hist, nb, (first && iota_vals) ? 1 : 0);
+                       cap, shift, dmask, nbits, hist, nb, tot, (first && iota_vals) ? 1 : 0);
     first = false;
     std::swap(kin, kout);
     std::swap(vin, vout);
