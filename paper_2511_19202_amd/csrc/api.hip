@@ -283,6 +283,9 @@ int shape_nb(const nvgs_ctx* ctx, int precision) {
 // context's MLP kind (mode 1 also writes per-pair state and logits)
 hipError_t launch_query(nvgs_ctx* ctx, int precision, int mode, uint8_t* state, float* logits,
                         unsigned long long* counts, hipStream_t st) {
+  // the query kernels add their per-wave kept counts into the chunk counts
+  hipError_t e = launch_fill_u32(P_<uint32_t>(ctx->chunk_cnt), 0u, ctx->n_chunks, st);
+  if (e != hipSuccess) return e;
   if (ctx->kind == 1)
     return launch_cull_cmlp(P_<AssetDev>(ctx->assets_dev), P_<WorkItem>(ctx->items_dev), (int64_t)ctx->items.size(),
                             P_<int32_t>(ctx->seglist_dev), P_<SegRec>(ctx->segs_dev), P_<float>(ctx->c1_dev), 128,

@@ -149,14 +149,13 @@ __global__ __launch_bounds__(kCThreads) void k_cull_cmlp(
     unsigned long long* __restrict__ frame_counts) {
   __shared__ __attribute__((aligned(16))) float s_img[kImFloats];
   __shared__ __attribute__((aligned(16))) __bf16 s_w16[P == NVGS_PREC_BF16 ? 2 * 64 * 8 : 8];
-  __shared__ uint32_t s_cnt[2];
   __shared__ uint32_t s_tot[2];
   const WorkItem it = items[blockIdx.x];
   const AssetDev* A = assets + it.asset;
   for (int e = threadIdx.x; e < kImFloats; e += kCThreads) s_img[e] = A->op_f32[e];
   if (P == NVGS_PREC_BF16)
     for (int e = threadIdx.x; e < 2 * 64 * 8; e += kCThreads) s_w16[e] = reinterpret_cast<const __bf16*>(A->op_bf16)[e];
-  if (threadIdx.x < 2) s_cnt[threadIdx.x] = s_tot[threadIdx.x] = 0;
+  if (threadIdx.x < 2) s_tot[threadIdx.x] = 0;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 31, grp = lane >> 5;
   const int64_t n = A->n;
@@ -191,9 +190,10 @@ __global__ __launch_bounds__(kCThreads) void k_cull_cmlp(
   const float* b2p = s_img + kImB2 + grp * 16;
   const float* wop = s_img + kImWo + grp * 16;
   const float bo = s_img[kImBo];
-  int parity = 0;
   uint32_t n_in = 0, n_q = 0;
-  for (int si = it.seg_begin; si < it.seg_end; ++si, parity ^= 1) {
+  // waves proceed through the segments independently: each adds its kept
+  // count to the (zero-filled) chunk count
+  for (int si = it.seg_begin; si < it.seg_end; ++si) {
     const int seg = seglist[si];
     const SegRec& R = segs[seg];
     const bool in = valid && cfrustum(R, mu);
@@ -252,17 +252,12 @@ __global__ __launch_bounds__(kCThreads) void k_cull_cmlp(
     if (lane == 0) {
       const int64_t g0 = (int64_t)it.chunk * kChunk + wave * 32;
       if (g0 < n) mask[R.word_base + (g0 >> 5)] = word;
-      atomicAdd(&s_cnt[parity], (uint32_t)__popc(word));
+      if (word) atomicAdd(chunk_count + R.chunk_base + it.chunk, (uint32_t)__popc(word));
     }
     if (MODE == 1 && grp == 0 && valid) {
       const int64_t idx = R.pair_base + g;
       state[idx] = keep ? 2 : (in ? 1 : 0);
       logits[idx] = (in && query) ? z : __builtin_nanf("");
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      chunk_count[R.chunk_base + it.chunk] = s_cnt[parity];
-      s_cnt[parity] = 0;
     }
   }
   if (frame_counts) {

@@ -494,7 +494,6 @@ __global__ __launch_bounds__(64 * WAVES) void k_cull_mlp(
   using I = Img<P, W>;
   constexpr int EPL = Prec<P>::EPL, NT = W / 32, KQ = W / 2, KS1 = I::KS1;
   __shared__ __attribute__((aligned(16))) uint8_t lds[I::BYTES];
-  __shared__ uint32_t s_cnt[2];
   __shared__ uint32_t s_tot[2];
   const WorkItem it = items[blockIdx.x];
   const AssetDev* A = assets + it.asset;
@@ -505,7 +504,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_cull_mlp(
     const uint4* src = reinterpret_cast<const uint4*>(img);
     for (int k = threadIdx.x; k < I::BYTES / 16; k += 64 * WAVES) reinterpret_cast<uint4*>(lds)[k] = src[k];
   }
-  if (threadIdx.x < 2) s_cnt[threadIdx.x] = s_tot[threadIdx.x] = 0;
+  if (threadIdx.x < 2) s_tot[threadIdx.x] = 0;
   const uint8_t* W1u = lds + I::W1;
   const uint8_t* W2p = lds + I::W2;
   const uint8_t* W3p = lds + I::W3;
@@ -563,9 +562,10 @@ __global__ __launch_bounds__(64 * WAVES) void k_cull_mlp(
       for (int t = 0; t < NT; ++t) U[b][t] = M::mma(a[t], eb, U[b][t]);
     }
   }
-  int parity = 0;
   uint32_t n_in = 0, n_q = 0;  // in-frustum and queried pairs of this wave
-  for (int si = it.seg_begin; si < it.seg_end; ++si, parity ^= 1) {
+  // waves proceed through the segments independently: each adds its kept
+  // count to the (zero-filled) chunk count
+  for (int si = it.seg_begin; si < it.seg_end; ++si) {
     const int seg = seglist[si];
     const SegRec& R = segs[seg];
     bool in[NB];
@@ -620,7 +620,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_cull_mlp(
       cnt += __popc(word);
       if (lane == 0 && g0 + 32 * b < n) mask[R.word_base + (g0 >> 5) + b] = word;
     }
-    if (lane == 0) atomicAdd(&s_cnt[parity], cnt);
+    if (lane == 0 && cnt) atomicAdd(chunk_count + R.chunk_base + it.chunk, cnt);
     if (MODE == 1 && grp == 0) {
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
@@ -630,11 +630,6 @@ __global__ __launch_bounds__(64 * WAVES) void k_cull_mlp(
           logits[idx] = (in[b] && query) ? z[b] : __builtin_nanf("");
         }
       }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      chunk_count[R.chunk_base + it.chunk] = s_cnt[parity];
-      s_cnt[parity] = 0;
     }
   }
   if (frame_counts) {
