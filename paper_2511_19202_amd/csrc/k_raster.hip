@@ -518,9 +518,10 @@ __global__ __launch_bounds__(T == 8 ? 64 : 256) void k_blend(
   constexpr int NB = T * T / 64;         // 8x8 pixel blocks per tile
   constexpr int BPW = NB / (NT / 64);    // blocks per wave (1, 1, 4)
   constexpr int BATCH = NT;              // one staged splat per thread per batch
-  __shared__ float4 s_g[BATCH];  // u, v, A, B   (A, B, C: conic scaled by -log2(e)/2, -log2(e), -log2(e)/2)
-  __shared__ float4 s_h[BATCH];  // C, opacity, log2 bound, r
-  __shared__ float2 s_c[BATCH];  // g, b
+  // staged records, one array so that a fragment's three reads share one
+  // address: [k][0] = u, v, A, B (A, B, C: conic scaled by -log2(e)/2,
+  // -log2(e), -log2(e)/2); [k][1] = C, opacity, log2 bound, r; [k][2] = g, b
+  __shared__ float4 s_rec[BATCH][3];
   __shared__ uint32_t s_ov[T == 8 ? 1 : BATCH];  // bit b: the footprint box touches 8x8 block b
   __shared__ uint32_t s_p[RECORD ? BATCH : 1];
   const int64_t item = blockIdx.x;
@@ -584,8 +585,8 @@ __global__ __launch_bounds__(T == 8 ? 64 : 256) void k_blend(
   // pixel instead (Sec. 4.1).  The product pass multiplies (1 - alpha) of the
   // passing fragments, stopping once below 1e-4 (later chunks only test that).
   auto step = [&](int j, int k) {
-    const float4 g = s_g[k];
-    const float4 h = s_h[k];
+    const float4 g = s_rec[k][0];
+    const float4 h = s_rec[k][1];
     const float dx = px[j] - g.x, dy = py[j] - g.y;
     const float pw = dx * fmaf(g.z, dx, g.w * dy) + h.x * dy * dy;
     const float al = fminf(kAlphaMax, h.y * __builtin_amdgcn_exp2f(pw));
@@ -596,16 +597,18 @@ __global__ __launch_bounds__(T == 8 ? 64 : 256) void k_blend(
       px[j] = Tr[j] < kTMin ? kFar : px[j];
       return;
     }
-    const float2 c = s_c[k];
-    const bool low = Tn < kTMin;
-    const bool take = ok && !low;
+    const float4 c = s_rec[k][2];
+    // Tn >= 0, so the FP32 order is the order of the bit patterns
+    const bool low = __float_as_uint(Tn) < __float_as_uint(kTMin);
+    const bool halt = ok && low;
+    const bool take = ok != halt;  // ok and not low
     const float w = take ? al * Tr[j] : 0.f;
     cr[j] = fmaf(w, h.w, cr[j]);
     cg[j] = fmaf(w, c.x, cg[j]);
     cb[j] = fmaf(w, c.y, cb[j]);
     Tr[j] = take ? Tn : Tr[j];
-    if (STATS) stop[j] = (ok && low) ? b0k + (uint32_t)k : stop[j];
-    px[j] = (ok && low) ? kFar : px[j];
+    if (STATS) stop[j] = halt ? b0k + (uint32_t)k : stop[j];
+    px[j] = halt ? kFar : px[j];
     if (RECORD && take) atomicMax(contrib + s_p[k], __float_as_uint(w));
   };
   auto live = [&](int j) { return px[j] < kFarTest; };
@@ -617,9 +620,9 @@ __global__ __launch_bounds__(T == 8 ? 64 : 256) void k_blend(
     const int cnt = (int)min((uint32_t)BATCH, end - b0);
     b0k = b0;
     if (t < cnt) {
-      s_g[t] = qa;
-      s_h[t] = qb;
-      s_c[t] = make_float2(qc.x, qc.y);
+      s_rec[t][0] = qa;
+      s_rec[t][1] = qb;
+      s_rec[t][2] = qc;
       if (T != 8) {
         // blocks touched by the footprint box (same widening as the tile rectangle); qc = g, b, ex, ey
         const float wx = 1e-4f * qc.z + 1e-3f, wy = 1e-4f * qc.w + 1e-3f;
