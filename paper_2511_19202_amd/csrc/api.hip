@@ -1225,7 +1225,7 @@ nvgs_status nvgs_train_visibility(nvgs_ctx* ctx, int32_t asset, const nvgs_camer
   Tmp cams_t(ctx), gam_t(ctx), part_t(ctx), lp_t(ctx), m_t(ctx), v_t(ctx), loss_t(ctx), cnt_t(ctx);
   nvgs_camera* cams_d = cams_t.get<nvgs_camera>(V);
   float* gam = gam_t.get<float>((size_t)V * (compact ? 8 : 36));
-  float* part = part_t.get<float>((size_t)nwg * np);
+  float* part = part_t.get<float>((size_t)nwg * np + reduce_scratch_floats(nwg, np));
   float* lp = lp_t.get<float>(nwg);
   float* m = m_t.get<float>(np);
   float* v = v_t.get<float>(np);
@@ -1258,7 +1258,7 @@ nvgs_status nvgs_train_visibility(nvgs_ctx* ctx, int32_t asset, const nvgs_camer
                           nullptr, nullptr, nullptr, part, lp, nullptr));
     }
     CK(launch_reduce_adam_n(part, nwg, np, params, m, v, nullptr, step_lr(opts, step), opts->beta1, opts->beta2,
-                            opts->eps, step + 1, lp, inv_b, loss + step, ctx->stream));
+                            opts->eps, step + 1, lp, inv_b, loss + step, ctx->stream, part + (size_t)nwg * np));
   }
   CK(hipStreamSynchronize(ctx->stream));
   if (loss_curve) CK(hipMemcpy(loss_curve, loss, sizeof(float) * opts->steps, hipMemcpyDeviceToHost));
@@ -1288,12 +1288,13 @@ nvgs_status nvgs_mlp_backward(nvgs_ctx* ctx, const float* params, int32_t width,
   CK(hipSetDevice(ctx->device));
   const int nwg = (int)((B + kPairsPerWG - 1) / kPairsPerWG);
   Tmp part_t(ctx);
-  float* part = part_t.get<float>((size_t)nwg * train_num_params());
+  const int np = train_num_params();
+  float* part = part_t.get<float>((size_t)nwg * np + reduce_scratch_floats(nwg, np));
   if (!part) return fail(ctx, NVGS_E_NOMEM, "gradient partials");
   CK(launch_mlp_train(2, precision == NVGS_PREC_BF16, nwg, kTrainChunksPerWG, ctx->stream, params, B, 1.f, nullptr,
                       1, 0.f, nullptr, 1, nullptr, 0, 0, nullptr, X, dlogits, nullptr, part, nullptr, dX));
-  CK(launch_reduce_adam(part, nwg, nullptr, nullptr, nullptr, dparams, 0.f, 0.f, 0.f, 1.f, 1, nullptr, 0.f, nullptr,
-                        ctx->stream));
+  CK(launch_reduce_adam_n(part, nwg, np, nullptr, nullptr, nullptr, dparams, 0.f, 0.f, 0.f, 1.f, 1, nullptr, 0.f,
+                          nullptr, ctx->stream, part + (size_t)nwg * np));
   return NVGS_OK;
 }
 
@@ -1326,13 +1327,13 @@ nvgs_status nvgs_cmlp_backward(nvgs_ctx* ctx, const float* params, const float* 
   const int nwg = (int)((B + per_wg - 1) / per_wg);
   const int np = ctrain_num_params();
   Tmp part_t(ctx);
-  float* part = part_t.get<float>((size_t)nwg * np);
+  float* part = part_t.get<float>((size_t)nwg * np + reduce_scratch_floats(nwg, np));
   if (!part) return fail(ctx, NVGS_E_NOMEM, "gradient partials");
   const CTrainArgs none{};
   CK(launch_cmlp_train(2, precision == NVGS_PREC_BF16, nwg, cpw, ctx->stream, params, B, 1.f, none, X, dlogits,
                        nullptr, part, nullptr));
   CK(launch_reduce_adam_n(part, nwg, np, nullptr, nullptr, nullptr, dparams, 0.f, 0.f, 0.f, 1.f, 1, nullptr, 0.f,
-                          nullptr, ctx->stream));
+                          nullptr, ctx->stream, part + (size_t)nwg * np));
   return NVGS_OK;
 }
 

@@ -198,9 +198,12 @@ hipError_t launch_count_pos(int64_t batch, int64_t n, int V, const uint32_t* lab
 hipError_t launch_reduce_adam(const float* partial, int nwg, float* params, float* m, float* v, float* grad_out,
                               float lr, float b1, float b2, float eps, int64_t t, const float* loss_part,
                               float inv_batch, float* loss_out, hipStream_t st);
+// scratch (nullable, reduce_scratch_floats(nwg, np) floats) enables a two-level sum
+size_t reduce_scratch_floats(int nwg, int np);
 hipError_t launch_reduce_adam_n(const float* partial, int nwg, int np, float* params, float* m, float* v,
                                 float* grad_out, float lr, float b1, float b2, float eps, int64_t t,
-                                const float* loss_part, float inv_batch, float* loss_out, hipStream_t st);
+                                const float* loss_part, float inv_batch, float* loss_out, hipStream_t st,
+                                float* scratch);
 
 // training of the compact form (k_ctrain.hip)
 struct CTrainArgs {

@@ -337,6 +337,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   }
 }
 
+// first level of the gradient sum: slice s of the work-group partials
+// (a fixed contiguous range) summed in order, for every parameter and the loss
+__global__ void k_reduce_slices(const float* __restrict__ partial, int nwg, int np, int S,
+                                const float* __restrict__ loss_part, float* __restrict__ tmp,
+                                float* __restrict__ tmp_loss) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x, s = blockIdx.y;
+  const int w0 = (int)((int64_t)nwg * s / S), w1 = (int)((int64_t)nwg * (s + 1) / S);
+  if (p < np) {
+    float g = 0.f;
+    for (int w = w0; w < w1; ++w) g += partial[(int64_t)w * np + p];
+    tmp[(int64_t)s * np + p] = g;
+  }
+  if (loss_part && blockIdx.x == 0 && threadIdx.x == 0) {
+    float l = 0.f;
+    for (int w = w0; w < w1; ++w) l += loss_part[w];
+    tmp_loss[s] = l;
+  }
+}
+
 // sum of the per-group partials (fixed order), then Adam or a plain store
 __global__ void k_reduce_adam(const float* __restrict__ partial, int nwg, int np, float* __restrict__ params,
                               float* __restrict__ m, float* __restrict__ v, float* __restrict__ grad_out, float lr,
@@ -492,10 +511,25 @@ hipError_t launch_mlp_train(int mode, bool bf16, int nwg, int chunks_per_wg, hip
 #undef NVGS_MLPT
 }
 
+constexpr int kSlices = 32;  // first-level slices of a two-level gradient sum
+
+size_t reduce_scratch_floats(int nwg, int np) { return nwg > 2 * kSlices ? (size_t)kSlices * (np + 1) : 0; }
+
 hipError_t launch_reduce_adam_n(const float* partial, int nwg, int np, float* params, float* m, float* v,
                                 float* grad_out, float lr, float b1, float b2, float eps, int64_t t,
-                                const float* loss_part, float inv_batch, float* loss_out, hipStream_t st) {
+                                const float* loss_part, float inv_batch, float* loss_out, hipStream_t st,
+                                float* scratch) {
   const float c1 = 1.f - powf(b1, (float)t), c2 = 1.f - powf(b2, (float)t);
+  if (scratch && reduce_scratch_floats(nwg, np) > 0) {
+    // two levels: kSlices contiguous slices of the partials, then the slices in order
+    float* tmp = scratch;
+    float* tmp_loss = scratch + (size_t)kSlices * np;
+    hipLaunchKernelGGL(k_reduce_slices, dim3((np + 255) / 256, kSlices), dim3(256), 0, st, partial, nwg, np, kSlices,
+                       loss_part, tmp, tmp_loss);
+    partial = tmp;
+    nwg = kSlices;
+    loss_part = loss_part ? tmp_loss : nullptr;
+  }
   hipLaunchKernelGGL(k_reduce_adam, dim3((np + 255) / 256), dim3(256), 0, st, partial, nwg, np, params, m, v,
                      grad_out, lr, b1, b2, eps, c1, c2, loss_part, inv_batch, loss_out);
   return hipGetLastError();
@@ -505,7 +539,7 @@ hipError_t launch_reduce_adam(const float* partial, int nwg, float* params, floa
                               float lr, float b1, float b2, float eps, int64_t t, const float* loss_part,
                               float inv_batch, float* loss_out, hipStream_t st) {
   return launch_reduce_adam_n(partial, nwg, kNumParams, params, m, v, grad_out, lr, b1, b2, eps, t, loss_part,
-                              inv_batch, loss_out, st);
+                              inv_batch, loss_out, st, nullptr);
 }
 
 }  // namespace nvgs
