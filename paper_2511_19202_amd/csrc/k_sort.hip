@@ -24,9 +24,16 @@ constexpr int kSortWaves = kSortThreads / 64;
 constexpr int kPerWave = kSortBlock / kSortWaves;  // 1024 keys per wave
 constexpr int kRounds = kPerWave / 64;             // 16 rounds of 64
 static_assert(kSortThreads == 256, "the scatter gives one thread to each of the 256 digits");
+constexpr int64_t kSortGrid = 1024;  // work-groups per pass: 4 per CU (the scatter's LDS allows 4)
 
 __device__ __forceinline__ int64_t live_n(const uint32_t* n_dev, int64_t cap) {
   return n_dev ? (int64_t)min((uint64_t)*n_dev, (uint64_t)cap) : cap;
+}
+
+// blocks of kSortBlock keys holding live keys (the launches are sized by the
+// capacity; work-groups loop over the live blocks only)
+__device__ __forceinline__ int64_t live_blocks(const uint32_t* n_dev, int64_t cap) {
+  return (live_n(n_dev, cap) + kSortBlock - 1) / kSortBlock;
 }
 
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t* __restrict__ keys,
@@ -34,19 +41,23 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t* __r
                                                              uint32_t dmask, uint32_t* __restrict__ hist, int64_t nblocks) {
   __shared__ uint32_t s_h[kSortWaves][256];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int d = threadIdx.x; d < kSortWaves * 256; d += kSortThreads) (&s_h[0][0])[d] = 0;
-  __syncthreads();
   const int64_t n = live_n(n_dev, cap);
-  const int64_t base = (int64_t)blockIdx.x * kSortBlock + wave * kPerWave;
-  for (int r = 0; r < kRounds; ++r) {
-    int64_t idx = base + r * 64 + lane;
-    if (idx < n) atomicAdd(&s_h[wave][(keys[idx] >> shift) & dmask], 1u);
-  }
-  __syncthreads();
-  for (int d = threadIdx.x; d < 256; d += kSortThreads) {
-    uint32_t s = 0;
-    for (int w = 0; w < kSortWaves; ++w) s += s_h[w][d];
-    hist[(int64_t)d * nblocks + blockIdx.x] = s;
+  const int64_t nbl = live_blocks(n_dev, cap);
+  for (int64_t blk = blockIdx.x; blk < nbl; blk += gridDim.x) {
+    for (int d = threadIdx.x; d < kSortWaves * 256; d += kSortThreads) (&s_h[0][0])[d] = 0;
+    __syncthreads();
+    const int64_t base = blk * kSortBlock + wave * kPerWave;
+    for (int r = 0; r < kRounds; ++r) {
+      int64_t idx = base + r * 64 + lane;
+      if (idx < n) atomicAdd(&s_h[wave][(keys[idx] >> shift) & dmask], 1u);
+    }
+    __syncthreads();
+    for (int d = threadIdx.x; d < 256; d += kSortThreads) {
+      uint32_t s = 0;
+      for (int w = 0; w < kSortWaves; ++w) s += s_h[w][d];
+      hist[(int64_t)d * nblocks + blk] = s;
+    }
+    __syncthreads();
   }
 }
 
@@ -54,18 +65,20 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t* __r
 // the row total to tot[d]
 constexpr int kRowItems = 16;
 __global__ __launch_bounds__(kSortThreads) void k_radix_rowscan(uint32_t* __restrict__ hist, int64_t nblocks,
+                                                                const uint32_t* __restrict__ n_dev, int64_t cap,
                                                                 uint32_t* __restrict__ tot) {
   __shared__ uint32_t s_w[kSortWaves];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t* row = hist + (int64_t)blockIdx.x * nblocks;
+  const int64_t nbl = live_blocks(n_dev, cap);  // the row's live entries
   uint32_t carry = 0;
-  for (int64_t off = 0; off < nblocks; off += kSortThreads * kRowItems) {
+  for (int64_t off = 0; off < nbl; off += kSortThreads * kRowItems) {
     const int64_t base = off + (int64_t)threadIdx.x * kRowItems;
     uint32_t v[kRowItems];
     uint32_t s = 0;
 #pragma unroll
     for (int k = 0; k < kRowItems; ++k) {
-      v[k] = base + k < nblocks ? row[base + k] : 0u;
+      v[k] = base + k < nbl ? row[base + k] : 0u;
       s += v[k];
     }
     uint32_t x = s;
@@ -86,7 +99,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_rowscan(uint32_t* __rest
     pre += x - s;
 #pragma unroll
     for (int k = 0; k < kRowItems; ++k) {
-      if (base + k < nblocks) row[base + k] = pre;
+      if (base + k < nbl) row[base + k] = pre;
       pre += v[k];
     }
     carry += all;
@@ -107,88 +120,92 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
   __shared__ uint32_t s_k[kSortBlock];
   __shared__ uint32_t s_v[kSortBlock];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int d = threadIdx.x; d < kSortWaves * 256; d += kSortThreads) (&s_cnt[0][0])[d] = 0;
-  __syncthreads();
   const int64_t n = live_n(n_dev, cap);
-  const int64_t block0 = (int64_t)blockIdx.x * kSortBlock;
-  const int64_t base = block0 + wave * kPerWave;
-  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  uint32_t key[kRounds], local[kRounds];
-  // phase 1: rank every key among the equal digits of this wave, in order
+  const int64_t nbl = live_blocks(n_dev, cap);
+  for (int64_t blk = blockIdx.x; blk < nbl; blk += gridDim.x) {
+    for (int d = threadIdx.x; d < kSortWaves * 256; d += kSortThreads) (&s_cnt[0][0])[d] = 0;
+    __syncthreads();
+    const int64_t block0 = blk * kSortBlock;
+    const int64_t base = block0 + wave * kPerWave;
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    uint32_t key[kRounds], local[kRounds];
+    // phase 1: rank every key among the equal digits of this wave, in order
 #pragma unroll
-  for (int r = 0; r < kRounds; ++r) {
-    const int64_t idx = base + r * 64 + lane;
-    const bool ok = idx < n;
-    key[r] = ok ? keys_in[idx] : 0u;
-    const uint32_t d = (key[r] >> shift) & dmask;
-    uint64_t peers = __ballot(ok);
-    for (int b = 0; b < nbits; ++b) {
-      const bool bit = (d >> b) & 1u;
-      const uint64_t m = __ballot(bit);
-      peers &= bit ? m : ~m;
+    for (int r = 0; r < kRounds; ++r) {
+      const int64_t idx = base + r * 64 + lane;
+      const bool ok = idx < n;
+      key[r] = ok ? keys_in[idx] : 0u;
+      const uint32_t d = (key[r] >> shift) & dmask;
+      uint64_t peers = __ballot(ok);
+      for (int b = 0; b < nbits; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t m = __ballot(bit);
+        peers &= bit ? m : ~m;
+      }
+      const uint32_t before = s_cnt[wave][d];
+      local[r] = before + (uint32_t)__popcll(peers & lt);
+      // the highest peer publishes the new running count (one writer per digit)
+      if (ok && (peers >> lane) == 1ull) s_cnt[wave][d] = before + (uint32_t)__popcll(peers);
     }
-    const uint32_t before = s_cnt[wave][d];
-    local[r] = before + (uint32_t)__popcll(peers & lt);
-    // the highest peer publishes the new running count (one writer per digit)
-    if (ok && (peers >> lane) == 1ull) s_cnt[wave][d] = before + (uint32_t)__popcll(peers);
-  }
-  __syncthreads();
-  // phase 2: one thread per digit: block total, per-wave bases, global base;
-  // then an exclusive scan of the digit totals gives each digit's block start
-  const int d = threadIdx.x;  // kSortThreads == 256 digits
-  uint32_t tot = 0;
+    __syncthreads();
+    // phase 2: one thread per digit: block total, per-wave bases, global base;
+    // then an exclusive scan of the digit totals gives each digit's block start
+    const int d = threadIdx.x;  // kSortThreads == 256 digits
+    uint32_t tot = 0;
 #pragma unroll
-  for (int w = 0; w < kSortWaves; ++w) {
-    const uint32_t c = s_cnt[w][d];
-    s_cnt[w][d] = tot;
-    tot += c;
-  }
-  // digit d's global base: the exclusive scan of the digit totals plus this
-  // block's row-exclusive count
-  const uint32_t gt = digit_tot[d];
-  uint32_t x = tot, xg = gt;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t y = __shfl_up(x, o), yg = __shfl_up(xg, o);
-    if (lane >= o) {
-      x += y;
-      xg += yg;
+    for (int w = 0; w < kSortWaves; ++w) {
+      const uint32_t c = s_cnt[w][d];
+      s_cnt[w][d] = tot;
+      tot += c;
     }
-  }
-  if (lane == 63) {
-    s_wsum[wave] = x;
-    s_gsum[wave] = xg;
-  }
-  __syncthreads();
-  uint32_t wbase = 0, gbase = 0;
+    // digit d's global base: the exclusive scan of the digit totals plus this
+    // block's row-exclusive count
+    const uint32_t gt = digit_tot[d];
+    uint32_t x = tot, xg = gt;
 #pragma unroll
-  for (int w = 0; w < kSortWaves; ++w) {
-    wbase += (w < wave) ? s_wsum[w] : 0u;
-    gbase += (w < wave) ? s_gsum[w] : 0u;
-  }
-  s_start[d] = wbase + x - tot;
-  s_glob[d] = gbase + xg - gt + offs[(int64_t)d * nblocks + blockIdx.x];
-  __syncthreads();
-  // phase 3: keys and values into LDS in (digit, input) order
-#pragma unroll
-  for (int r = 0; r < kRounds; ++r) {
-    const int64_t idx = base + r * 64 + lane;
-    if (idx < n) {
-      const uint32_t dg = (key[r] >> shift) & dmask;
-      const uint32_t p = s_start[dg] + s_cnt[wave][dg] + local[r];
-      s_k[p] = key[r];
-      s_v[p] = iota_vals ? (uint32_t)idx : vals_in[idx];
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o), yg = __shfl_up(xg, o);
+      if (lane >= o) {
+        x += y;
+        xg += yg;
+      }
     }
-  }
-  __syncthreads();
-  // phase 4: consecutive threads write consecutive positions of each digit run
-  const int cnt = (int)min<int64_t>(kSortBlock, n - block0);
-  for (int p = threadIdx.x; p < cnt; p += kSortThreads) {
-    const uint32_t k = s_k[p];
-    const uint32_t dg = (k >> shift) & dmask;
-    const uint32_t pos = s_glob[dg] + (uint32_t)p - s_start[dg];
-    keys_out[pos] = k;
-    vals_out[pos] = s_v[p];
+    if (lane == 63) {
+      s_wsum[wave] = x;
+      s_gsum[wave] = xg;
+    }
+    __syncthreads();
+    uint32_t wbase = 0, gbase = 0;
+#pragma unroll
+    for (int w = 0; w < kSortWaves; ++w) {
+      wbase += (w < wave) ? s_wsum[w] : 0u;
+      gbase += (w < wave) ? s_gsum[w] : 0u;
+    }
+    s_start[d] = wbase + x - tot;
+    s_glob[d] = gbase + xg - gt + offs[(int64_t)d * nblocks + blk];
+    __syncthreads();
+    // phase 3: keys and values into LDS in (digit, input) order
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+      const int64_t idx = base + r * 64 + lane;
+      if (idx < n) {
+        const uint32_t dg = (key[r] >> shift) & dmask;
+        const uint32_t p = s_start[dg] + s_cnt[wave][dg] + local[r];
+        s_k[p] = key[r];
+        s_v[p] = iota_vals ? (uint32_t)idx : vals_in[idx];
+      }
+    }
+    __syncthreads();
+    // phase 4: consecutive threads write consecutive positions of each digit run
+    const int cnt = (int)min<int64_t>(kSortBlock, n - block0);
+    for (int p = threadIdx.x; p < cnt; p += kSortThreads) {
+      const uint32_t k = s_k[p];
+      const uint32_t dg = (k >> shift) & dmask;
+      const uint32_t pos = s_glob[dg] + (uint32_t)p - s_start[dg];
+      keys_out[pos] = k;
+      vals_out[pos] = s_v[p];
+    }
+    __syncthreads();  // LDS is reused by the next block
   }
 }
 
@@ -210,6 +227,8 @@ hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp,
     *result_in_tmp = false;
     return hipSuccess;
   }
+  // at most kSortGrid work-groups, each looping over the live blocks
+  const unsigned grid = (unsigned)std::min<int64_t>(nb, kSortGrid);
   uint32_t* kin = keys;
   uint32_t* vin = vals;
   uint32_t* kout = keys_tmp;
@@ -219,11 +238,10 @@ hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp,
     const int nbits = min(8, end_bit - shift);
     const uint32_t dmask = (1u << nbits) - 1u;
     uint32_t* tot = hist + 256 * nb;
-    hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kSortThreads), 0, st, kin, n_dev, cap, shift, dmask,
-                       hist, nb);
-    hipLaunchKernelGGL(k_radix_rowscan, dim3(256), dim3(kSortThreads), 0, st, hist, nb, tot);
-    hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(kSortThreads), 0, st, kin, vin, kout, vout, n_dev,
-                       cap, shift, dmask, nbits, hist, nb, tot, (first && iota_vals) ? 1 : 0);
+    hipLaunchKernelGGL(k_radix_hist, dim3(grid), dim3(kSortThreads), 0, st, kin, n_dev, cap, shift, dmask, hist, nb);
+    hipLaunchKernelGGL(k_radix_rowscan, dim3(256), dim3(kSortThreads), 0, st, hist, nb, n_dev, cap, tot);
+    hipLaunchKernelGGL(k_radix_scatter, dim3(grid), dim3(kSortThreads), 0, st, kin, vin, kout, vout, n_dev, cap, shift,
+                       dmask, nbits, hist, nb, tot, (first && iota_vals) ? 1 : 0);
     first = false;
     std::swap(kin, kout);
     std::swap(vin, vout);
