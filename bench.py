@@ -53,19 +53,25 @@ BLEND_PEAK_GTESTS = VALU_LANE_OPS / BLEND_SLOTS_PER_TEST / 1e9
 
 
 def train_assets(ctx, sc, views=512, res=512, batch=65536, steps=5000, precision="bf16", lr=1e-3, seed=1,
-                 weighting=1, aux=6, aux_deg=5.0, offset=1.0, recipe="workload", sampling="fibonacci",
+                 weighting=1, aux=None, aux_deg=5.0, offset=None, recipe="workload", sampling="fibonacci",
                  fovy_deg=50.0):
     """Train each asset's visibility MLP on labels the renderer makes from
     `views` Fibonacci-sphere (or longitude-latitude) views of `fovy_deg`,
     each with `aux` auxiliary views on a cone of `aux_deg` degrees (one
     identity instance per asset), with class-frequency weighted BCE when
-    `weighting`.  recipe "workload": distances U(1.5, 20), constant lr;
-    recipe "paper" (Sec. 3.1, 4.1): the asset's Eq. 1 distance range (for
-    the frequency form also its MLP's far clamp; the compact form normalises
-    its distance input over it), batches of 2^19, lr 2e-3 with warm-up and
-    decay to 2e-4.  Returns per-asset summaries."""
+    `weighting`.  recipe "workload" (the differentiation workload's): distances
+    U(1.5, 20), constant lr, no view offset and no auxiliary views unless
+    given; recipe "paper" (Sec. 3.1, 4.1): the asset's Eq. 1 distance range
+    (for the frequency form also its MLP's far clamp; the compact form
+    normalises its distance input over it), the distance-scaled view offset,
+    6 auxiliary views, batches of 2^19, lr 2e-3 with warm-up and decay to
+    2e-4.  Returns per-asset summaries."""
     import torch
     import synth
+    if aux is None:
+        aux = 6 if recipe == "paper" else 0
+    if offset is None:
+        offset = 1.0 if recipe == "paper" else 0.0
     out = []
     for j, a in enumerate(sc.assets):
         d_lo, d_hi = 1.5, 20.0
@@ -562,7 +568,7 @@ def main_batched(args):
           f"{len(sc.instances)} instances, {sc.pairs_per_camera} pairs per camera", file=sys.stderr, flush=True)
     training = None
     if args.mlp == "trained":
-        training = train_assets(ctx, sc, views=args.views, steps=args.train_steps)
+        training = train_assets(ctx, sc, views=args.views, steps=args.train_steps, recipe=args.recipe)
         print("[batched] trained", file=sys.stderr, flush=True)
     else:
         calibrate_keep(ctx, sc, args.keep, prec)
