@@ -24,7 +24,8 @@ constexpr int kSortWaves = kSortThreads / 64;
 constexpr int kPerWave = kSortBlock / kSortWaves;  // 1024 keys per wave
 constexpr int kRounds = kPerWave / 64;             // 16 rounds of 64
 static_assert(kSortThreads == 256, "the scatter gives one thread to each of the 256 digits");
-constexpr int64_t kSortGrid = 1024;  // work-groups per pass: 4 per CU (the scatter's LDS allows 4)
+constexpr int64_t kSortGrid = 1024;  // scatter work-groups per pass: 4 per CU (its LDS allows 4)
+constexpr int64_t kHistGrid = 2048;  // histogram work-groups per pass: 8 per CU
 
 __device__ __forceinline__ int64_t live_n(const uint32_t* n_dev, int64_t cap) {
   return n_dev ? (int64_t)min((uint64_t)*n_dev, (uint64_t)cap) : cap;
@@ -47,10 +48,16 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t* __r
     for (int d = threadIdx.x; d < kSortWaves * 256; d += kSortThreads) (&s_h[0][0])[d] = 0;
     __syncthreads();
     const int64_t base = blk * kSortBlock + wave * kPerWave;
+    // all of the wave's loads first, then the LDS counts
+    uint32_t kv[kRounds];
+#pragma unroll
     for (int r = 0; r < kRounds; ++r) {
-      int64_t idx = base + r * 64 + lane;
-      if (idx < n) atomicAdd(&s_h[wave][(keys[idx] >> shift) & dmask], 1u);
+      const int64_t idx = base + r * 64 + lane;
+      kv[r] = idx < n ? keys[idx] : 0xffffffffu;
     }
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r)
+      if (base + r * 64 + lane < n) atomicAdd(&s_h[wave][(kv[r] >> shift) & dmask], 1u);
     __syncthreads();
     for (int d = threadIdx.x; d < 256; d += kSortThreads) {
       uint32_t s = 0;
@@ -229,6 +236,7 @@ hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp,
   }
   // at most kSortGrid work-groups, each looping over the live blocks
   const unsigned grid = (unsigned)std::min<int64_t>(nb, kSortGrid);
+  const unsigned hgrid = (unsigned)std::min<int64_t>(nb, kHistGrid);
   uint32_t* kin = keys;
   uint32_t* vin = vals;
   uint32_t* kout = keys_tmp;
@@ -238,7 +246,7 @@ hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp,
     const int nbits = min(8, end_bit - shift);
     const uint32_t dmask = (1u << nbits) - 1u;
     uint32_t* tot = hist + 256 * nb;
-    hipLaunchKernelGGL(k_radix_hist, dim3(grid), dim3(kSortThreads), 0, st, kin, n_dev, cap, shift, dmask, hist, nb);
+    hipLaunchKernelGGL(k_radix_hist, dim3(hgrid), dim3(kSortThreads), 0, st, kin, n_dev, cap, shift, dmask, hist, nb);
     hipLaunchKernelGGL(k_radix_rowscan, dim3(256), dim3(kSortThreads), 0, st, hist, nb, n_dev, cap, tot);
     hipLaunchKernelGGL(k_radix_scatter, dim3(grid), dim3(kSortThreads), 0, st, kin, vin, kout, vout, n_dev, cap, shift,
                        dmask, nbits, hist, nb, tot, (first && iota_vals) ? 1 : 0);
