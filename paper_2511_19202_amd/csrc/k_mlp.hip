@@ -494,6 +494,10 @@ __global__ __launch_bounds__(64 * WAVES) void k_cull_mlp(
   using I = Img<P, W>;
   constexpr int EPL = Prec<P>::EPL, NT = W / 32, KQ = W / 2, KS1 = I::KS1;
   __shared__ __attribute__((aligned(16))) uint8_t lds[I::BYTES];
+  // per wave: the current segment's layer-1 camera half, published from
+  // registers that were loaded one segment earlier (so the MFMA chain never
+  // waits on its global load)
+  __shared__ __attribute__((aligned(16))) float s_c1[WAVES][W];
   __shared__ uint32_t s_tot[2];
   const WorkItem it = items[blockIdx.x];
   const AssetDev* A = assets + it.asset;
@@ -563,11 +567,24 @@ __global__ __launch_bounds__(64 * WAVES) void k_cull_mlp(
     }
   }
   uint32_t n_in = 0, n_q = 0;  // in-frustum and queried pairs of this wave
+  constexpr int CPL = W / 64;  // camera-half values per lane
+  float pref[CPL];
+  auto fetch_c1 = [&](int s_idx) {
+    if (s_idx < it.seg_end) {
+      const float* row = c1perm + (size_t)seglist[s_idx] * c1_stride;
+#pragma unroll
+      for (int q = 0; q < CPL; ++q) pref[q] = row[q * 64 + lane];
+    }
+  };
+  fetch_c1(it.seg_begin);
   // waves proceed through the segments independently: each adds its kept
   // count to the (zero-filled) chunk count
   for (int si = it.seg_begin; si < it.seg_end; ++si) {
     const int seg = seglist[si];
     const SegRec& R = segs[seg];
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) s_c1[wave][q * 64 + lane] = pref[q];
+    fetch_c1(si + 1);
     bool in[NB];
     bool any = false;
 #pragma unroll
@@ -587,7 +604,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_cull_mlp(
     float z[NB];
     bool keep[NB];
     if (query && wave_any) {
-      const float* c1 = c1perm + (size_t)seg * c1_stride + grp * KQ;
+      const float* c1 = &s_c1[wave][grp * KQ];
       constexpr int KSH = W / Prec<P>::K;
       typename M::Op op[NB][KSH];
       f32x16 acc[NB][NT];
