@@ -18,7 +18,7 @@ constexpr float kGuard = 1.3f;   // frustum / Jacobian side guard band
 constexpr float kDilate = 0.3f;  // screen-space low-pass added to the 2D covariance
 
 constexpr int kChunk = 256;           // pairs per compaction chunk (one cull/MLP work-group)
-constexpr int kSortBlock = 4096;      // keys per radix-sort block
+constexpr int kSortBlock = 2048;      // keys per radix-sort block
 constexpr int kScanBlock = 4096;      // items per scan block
 
 // Per-asset device record (library-owned copy of the borrowed pointers and

@@ -21,11 +21,14 @@ namespace nvgs {
 
 constexpr int kSortThreads = 256;
 constexpr int kSortWaves = kSortThreads / 64;
-constexpr int kPerWave = kSortBlock / kSortWaves;  // 1024 keys per wave
-constexpr int kRounds = kPerWave / 64;             // 16 rounds of 64
+constexpr int kPerWave = kSortBlock / kSortWaves;  // 512 keys per wave
+constexpr int kRounds = kPerWave / 64;             // 8 rounds of 64
 static_assert(kSortThreads == 256, "the scatter gives one thread to each of the 256 digits");
-constexpr int64_t kSortGrid = 1024;  // scatter work-groups per pass: 4 per CU (its LDS allows 4)
-constexpr int64_t kHistGrid = 2048;  // histogram work-groups per pass: 8 per CU
+// work-groups per pass (they loop over the live blocks); 2048-key blocks and
+// these grids were the fastest of 1024-8192 keys and 1024-4096 groups for
+// 6-100M keys
+constexpr int64_t kSortGrid = 2048;  // scatter: 8 per CU
+constexpr int64_t kHistGrid = 4096;  // histogram: 16 per CU
 
 __device__ __forceinline__ int64_t live_n(const uint32_t* n_dev, int64_t cap) {
   return n_dev ? (int64_t)min((uint64_t)*n_dev, (uint64_t)cap) : cap;
