@@ -506,13 +506,17 @@ struct ItemCtx {
 constexpr float kFar = 1e30f;
 constexpr float kFarTest = 1e29f;
 
-// MODE 0: composite; 1: composite and record contributions; 2: product pass.
-// STATS: also count the list entries each pixel examined (statistics frames).
-template <int T, int MODE, bool STATS>
-__global__ __launch_bounds__(T == 8 ? 64 : 256) void k_blend(
-    ItemCtx ic, const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ ids,
-    const float4* __restrict__ splat, int W, int H, int tiles_x, int n_tiles, float bg0, float bg1, float bg2,
-    float* __restrict__ rgb, uint32_t* __restrict__ contrib, unsigned long long* __restrict__ work) {
+// One compositing item.  MODE 0: composite; 1: composite and record
+// contributions; 2: product pass.  STATS: also count the list entries each
+// pixel examined (statistics frames).  FIRST_PROD: composite of a split
+// list's first chunk that also stores the chunk's transmittance product
+// (0 if the pixel stopped in it), so the product pass can skip that chunk.
+template <int T, int MODE, bool STATS, bool FIRST_PROD>
+__device__ __forceinline__ void blend_item(
+    const ItemCtx& ic, const uint2 it, const uint32_t nch, const uint32_t* __restrict__ ranges,
+    const uint32_t* __restrict__ ids, const float4* __restrict__ splat, int W, int H, int tiles_x, int n_tiles,
+    float bg0, float bg1, float bg2, float* __restrict__ rgb, uint32_t* __restrict__ contrib,
+    unsigned long long* __restrict__ work) {
   constexpr bool RECORD = MODE == 1, PROD = MODE == 2;
   constexpr int NT = T == 8 ? 64 : 256;  // threads
   constexpr int NB = T * T / 64;         // 8x8 pixel blocks per tile
@@ -524,12 +528,7 @@ __global__ __launch_bounds__(T == 8 ? 64 : 256) void k_blend(
   __shared__ float4 s_rec[BATCH][3];
   __shared__ uint32_t s_ov[T == 8 ? 1 : BATCH];  // bit b: the footprint box touches 8x8 block b
   __shared__ uint32_t s_p[RECORD ? BATCH : 1];
-  const int64_t item = blockIdx.x;
-  if (item >= min((int64_t)*ic.n_items, ic.cap_items)) return;
-  const uint2 it = ic.items[item];
-  const uint32_t nch = ic.nch[it.x];
   const bool split = nch > 1;
-  if (PROD && (!split || it.y + 1 == nch)) return;  // products are needed for all but the last chunk
   if (split && (int64_t)ic.split_off[it.x] + nch > ic.cap_split) return;  // cannot happen within the sizing bound
   const int key = (int)ic.order[it.x];
   const int cam = key / n_tiles, tile = key % n_tiles;
@@ -706,6 +705,7 @@ __global__ __launch_bounds__(T == 8 ? 64 : 256) void k_blend(
       const bool stopped_here = !before[j] && !live(j);
       const float flag = before[j] ? 0.f : (stopped_here ? -Tr[j] : Tr[j]);
       ic.part[sbase + (wave * BPW + j) * 64 + lane] = make_float4(cr[j], cg[j], cb[j], flag);
+      if (FIRST_PROD) ic.prod[sbase + (wave * BPW + j) * 64 + lane] = stopped_here ? 0.f : Tr[j];
       continue;
     }
     if (x < W && y < H) {
@@ -715,6 +715,34 @@ __global__ __launch_bounds__(T == 8 ? 64 : 256) void k_blend(
       o[2] = fmaf(Tr[j], bg2, cb[j]);
     }
   }
+}
+
+// merge0 (frames without contribution recording or statistics): the product
+// pass (MODE 2) composites every split list's first chunk and stores its
+// product instead of walking it twice; the composite pass then skips it.
+template <int T, int MODE, bool STATS>
+__global__ __launch_bounds__(T == 8 ? 64 : 256) void k_blend(
+    ItemCtx ic, const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ ids,
+    const float4* __restrict__ splat, int W, int H, int tiles_x, int n_tiles, float bg0, float bg1, float bg2,
+    float* __restrict__ rgb, uint32_t* __restrict__ contrib, unsigned long long* __restrict__ work, int merge0) {
+  const int64_t item = blockIdx.x;
+  if (item >= min((int64_t)*ic.n_items, ic.cap_items)) return;
+  const uint2 it = ic.items[item];
+  const uint32_t nch = ic.nch[it.x];
+  const bool split = nch > 1;
+  if (MODE == 2) {
+    if (!split || it.y + 1 == nch) return;  // products are needed for all but the last chunk
+    if (merge0 && it.y == 0)
+      blend_item<T, 0, false, true>(ic, it, nch, ranges, ids, splat, W, H, tiles_x, n_tiles, bg0, bg1, bg2, rgb,
+                                    contrib, nullptr);
+    else
+      blend_item<T, 2, false, false>(ic, it, nch, ranges, ids, splat, W, H, tiles_x, n_tiles, bg0, bg1, bg2, rgb,
+                                     contrib, nullptr);
+    return;
+  }
+  if (merge0 && split && it.y == 0) return;  // composited by the product pass
+  blend_item<T, MODE, STATS, false>(ic, it, nch, ranges, ids, splat, W, H, tiles_x, n_tiles, bg0, bg1, bg2, rgb,
+                                    contrib, work);
 }
 
 // pixels of split tiles: chunk colours summed in list order, the final
@@ -763,12 +791,15 @@ static void launch_blend_t(bool record, const ItemCtx& ic, bool any_split, hipSt
   constexpr int NT = T == 8 ? 64 : 256;
   const dim3 grid((unsigned)ic.cap_items);
   uint32_t* cu = reinterpret_cast<uint32_t*>(contrib);
+  // the first chunk of a split list is composited in the product pass unless
+  // contributions or statistics are recorded
+  const int merge0 = (any_split && !record && !work) ? 1 : 0;
   if (any_split)
     hipLaunchKernelGGL((k_blend<T, 2, false>), grid, dim3(NT), 0, st, ic, ranges, ids, splat, W, H, tiles_x, n_tiles,
-                       b0, b1, b2, rgb, cu, nullptr);
+                       b0, b1, b2, rgb, cu, nullptr, merge0);
 #define NVGS_BL(M, S)                                                                                            \
   hipLaunchKernelGGL((k_blend<T, M, S>), grid, dim3(NT), 0, st, ic, ranges, ids, splat, W, H, tiles_x, n_tiles, b0, \
-                     b1, b2, rgb, cu, work)
+                     b1, b2, rgb, cu, work, merge0)
   if (record) {
     if (work) NVGS_BL(1, true); else NVGS_BL(1, false);
   } else {
