@@ -148,34 +148,58 @@ def time_frames(ctx, sc, steps, warmup, **kw):
     return (t1 - t0) / steps, dict(zip(names, (stage / steps).tolist())), last, img
 
 
-def roofline(stage_ms, st, width, precision, sh_degree):
-    """Roofline of the dominant kernel stage from algorithmic work per launch."""
-    dom = max(stage_ms, key=stage_ms.get)
-    sec = stage_ms[dom] * 1e-3
-    if dom == "cull_mlp":
-        flop = st["queried"] * FLOP_PER_QUERY[width]
-        a = flop / sec / 1e12
+def stage_roof(stage, ms, st, width, precision, sh_degree, n_keys_tiles):
+    """Roofline of one frame stage from its algorithmic work per launch:
+    MLP FLOP per queried pair; bytes for the memory-bound stages (projection:
+    48 B geometry + the SH row (rounded to 16 B) read and 84 B written per
+    kept splat; a radix pass: 4 B histogram read + 8 B read + 8 B written per
+    key; binning: 72 B per splat (gather, count scan, rectangle re-read) + 8 B
+    per tile entry; the tile stage: its radix passes + 4 B per entry for the
+    ranges); fragment tests for the blend (about 20 VALU lane-slots each)."""
+    sec = ms * 1e-3
+    if sec <= 0:
+        return None
+    if stage == "cull_mlp":
+        a = st["queried"] * FLOP_PER_QUERY[width] / sec / 1e12
         p = MFMA_PEAK_TFLOPS[precision]
-        return dom, {"bound": "mfma", "achieved": a, "peak": p, "unit": "TFLOP/s", "frac": a / p,
-                     "traffic": measured_traffic(dom)}
-    if dom == "project":
-        per = (12 + 12 + 16 + 4 + 12 * (sh_degree + 1) ** 2) + 68
-        a = st["kept"] * per / sec / 1e9
-        return dom, {"bound": "hbm", "achieved": a, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": a / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(dom)}
-    if dom in ("depth_sort", "tile_sort", "bin"):
-        n = st["kept"] if dom == "depth_sort" else st["duplicates"]
-        passes = 4 if dom == "depth_sort" else 2
-        per = 20 * passes if dom != "bin" else 8 + 24
-        a = n * per / sec / 1e9
-        return dom, {"bound": "hbm", "achieved": a, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": a / HBM_PEAK_GBS,
-                     "traffic": None}
-    # blend: one (pixel, tile-list entry) test costs ~20 VALU lane-slots (exp at 4),
-    # so the chip's 256 CU x 64 lanes x 2.4 GHz non-packed issue rate bounds it
-    a = st["blend_tests"] / sec / 1e9
-    p = BLEND_PEAK_GTESTS
-    return dom, {"bound": "alu", "achieved": a, "peak": p, "unit": "Gtests/s", "frac": a / p,
-                 "traffic": measured_traffic(dom)}
+        return {"bound": "mfma", "achieved": a, "peak": p, "unit": "TFLOP/s", "frac": a / p}
+    if stage == "blend":
+        a = st["blend_tests"] / sec / 1e9
+        return {"bound": "alu", "achieved": a, "peak": BLEND_PEAK_GTESTS, "unit": "Gtests/s",
+                "frac": a / BLEND_PEAK_GTESTS}
+    if stage == "project":
+        nb = st["kept"] * (48 + 4 * (-(-3 * (sh_degree + 1) ** 2 // 4) * 4) + 84)
+    elif stage == "depth_sort":
+        nb = st["kept"] * 4 * 20
+    elif stage == "bin":
+        nb = st["kept"] * 72 + st["duplicates"] * 8
+    elif stage == "tile_sort":
+        passes = max(1, -(-max(1, int(n_keys_tiles - 1).bit_length()) // 8))
+        nb = st["duplicates"] * (20 * passes + 4)
+    else:
+        return None
+    a = nb / sec / 1e9
+    return {"bound": "hbm", "achieved": a, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": a / HBM_PEAK_GBS}
+
+
+def roofline(stage_ms, st, width, precision, sh_degree, n_keys_tiles):
+    """Roofline of the dominant kernel stage (see stage_roof), with the HBM
+    traffic measured for its kernel when the committed counters match the
+    source."""
+    dom = max(stage_ms, key=stage_ms.get)
+    r = dict(stage_roof(dom, stage_ms[dom], st, width, precision, sh_degree, n_keys_tiles))
+    r["traffic"] = measured_traffic(dom) if dom in ("cull_mlp", "project", "blend") else None
+    return dom, r
+
+
+def stage_rooflines(stage_ms, st, width, precision, sh_degree, n_keys_tiles):
+    out = {}
+    for k, v in stage_ms.items():
+        r = stage_roof(k, v, st, width, precision, sh_degree, n_keys_tiles)
+        if r:
+            out[k] = {"bound": r["bound"], "frac": round(r["frac"], 4), "achieved": round(r["achieved"], 2),
+                      "unit": r["unit"]}
+    return out
 
 
 def measured_traffic(kernel):
@@ -348,7 +372,10 @@ def main():
     graph_equals_eager = bool(np.array_equal(g_c, img_c))
 
     width = sc.assets[0].mlp.width
-    dom, roof = roofline(stage_c, st_c, width, prec, sc.assets[0].sh_degree)
+    cam0 = sc.cameras[0]
+    nkt = len(sc.cameras) * (-(-cam0.width // tile)) * (-(-cam0.height // tile))
+    dom, roof = roofline(stage_c, st_c, width, prec, sc.assets[0].sh_degree, nkt)
+    stage_roofs = stage_rooflines(stage_c, st_c, width, prec, sc.assets[0].sh_degree, nkt)
     extra = {}
     for p2 in [p for p in args.extra_precisions.split(",") if p]:
         try:
@@ -395,6 +422,7 @@ def main():
         "ms_stage": stage_c, "ms_stage_unculled": stage_u,
         "dominant_kernel": dom,
         "roofline": roof,
+        "stage_rooflines": stage_roofs,
         "precisions": extra,
         "workspace_bytes": st_c["workspace_bytes"],
         "keep_frac_of_in_frustum": st_c["kept"] / max(1, st_c["in_frustum"]),
@@ -589,7 +617,10 @@ def main_batched(args):
     iu = ctx.render(sc.cameras[:2], tile=tile, precision=prec, use_mlp=False).cpu().numpy()
     psnrs = [psnr(ic[k], iu[k]) for k in range(2)]
     width = sc.assets[0].mlp.width
-    dom, roof = roofline(stage, st, width, prec, sc.assets[0].sh_degree)
+    cam0 = sc.cameras[0]
+    nkt = len(sc.cameras) * (-(-cam0.width // tile)) * (-(-cam0.height // tile))
+    dom, roof = roofline(stage, st, width, prec, sc.assets[0].sh_degree, nkt)
+    stage_roofs = stage_rooflines(stage, st, width, prec, sc.assets[0].sh_degree, nkt)
     C = len(sc.cameras)
     out = {
         "metric": "1080p FPS + visibility-MLP queries/s, culled vs unculled, PSNR vs FP64 oracle",
@@ -617,7 +648,8 @@ def main_batched(args):
         "psnr_culled_vs_unculled_db_cameras_0_1": psnrs,
         "in_frustum": st["in_frustum"], "queried": st["queried"], "kept": st["kept"],
         "duplicates": st["duplicates"], "blend_tests": st["blend_tests"], "ms_stage": stage,
-        "dominant_kernel": dom, "roofline": roof, "workspace_bytes": st["workspace_bytes"],
+        "dominant_kernel": dom, "roofline": roof,
+        "stage_rooflines": stage_roofs, "workspace_bytes": st["workspace_bytes"],
         "training": training,
     }
     if not args.no_cpu_baseline:
