@@ -263,7 +263,7 @@ def time_graph(ctx, cam_sets, steps, warmup, **kw):
     return (t1 - t0) / steps, per
 
 
-def prepare(ctx, cam_sets, tile_arg, precision, reps=3, use_mlp_modes=(True, False)):
+def prepare(ctx, cam_sets, tile_arg, precision, reps=7, use_mlp_modes=(True, False)):
     """Autotune (unless a tile is given), then size the persistent frame's
     capacities from eager frames over the camera sets (10% headroom)."""
     tune = None
