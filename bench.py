@@ -292,7 +292,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="composed", choices=["composed", "batched", "sweep", "ablation"],
+    ap.add_argument("--workload", default="composed", choices=["composed", "batched", "sweep", "ablation", "precision"],
                     help="sweep: composed scene at several camera distances, SH 3 and SH 0, culled / unculled / "
                          "radius-clipped")
     ap.add_argument("--det-clip", type=float, default=0.1, help="sweep, ablation: radius-clipping threshold (px^4)")
@@ -343,6 +343,8 @@ def main():
         return main_sweep(args)
     if args.workload == "ablation":
         return main_ablation(args)
+    if args.workload == "precision":
+        return main_precision(args)
     import torch
     import paper_2511_19202_amd as nvgs
     import synth
@@ -732,6 +734,91 @@ def main_sweep(args):
     print(json.dumps({"workload": "sweep: composed-1080p at 7 camera distances, SH 3 and SH 0",
                       "mlp_precision": prec, "det_clip": args.det_clip, "rows": rows}), flush=True)
     ctx.close()
+
+
+def main_precision(args):
+    """The precision form on the tiny scene (20k-Gaussian torus, 256^2, one
+    camera): MLP widths 64 and 128 in FP32, BF16 and FP8 -- FPS, the keep
+    flip rate against the FP64 MLP and the PSNR against the unculled FP64
+    render (both from the oracle, in the cpu_baseline leg) -- and the MLP
+    kernel alone on the composed scene's 16M pairs, where it fills the GPU:
+    queries/s and the fraction of the MFMA peak of each precision.  The
+    width-64 MLP is trained (the differentiation workload's recipe at 20k
+    Gaussians); training supports width 64 only, so width 128 uses seeded
+    weights with the output bias set to keep 65 % of the in-frustum pairs."""
+    import torch
+    import paper_2511_19202_amd as nvgs
+    import synth
+
+    precs = ("fp32", "bf16", "fp8")
+    tiny_rows, keep = [], {}
+    for W in (64, 128):
+        sc = synth.scene_tiny(n=20000, res=256, width=W)
+        ctx = nvgs.Context(0)
+        ctx.load_assets(sc.assets)
+        ctx.set_instances(sc.instances)
+        if W == 64 and args.mlp == "trained":
+            train_assets(ctx, sc, views=512, res=512, batch=65536, steps=args.train_steps, recipe="workload")
+            how = "trained"
+        else:
+            calibrate_keep(ctx, sc, args.keep, "fp32")
+            how = "seeded, 65 % kept"
+        row = {"width": W, "mlp": how}
+        for prec in precs + ("unculled",):
+            kw = dict(tile=16, precision="fp32" if prec == "unculled" else prec, use_mlp=prec != "unculled")
+            ctx.watermarks(reset=True)
+            img = ctx.render(sc.cameras, **kw).cpu().numpy()[0]
+            wm = ctx.watermarks(reset=True)
+            ctx.reserve(int(wm["max_splats"] * 1.1) + 4096, int(wm["max_duplicates"] * 1.1) + 4096)
+            t, per = time_graph(ctx, [sc.cameras], args.steps, args.warmup, **kw)
+            r = {"fps": 1.0 / t, "frame_ms_p50": float(np.percentile(per, 50))}
+            if prec != "unculled":
+                _, lg = ctx.query_visibility(sc.cameras, precision=prec)
+                keep[(W, prec)] = (lg.cpu().numpy()[0].astype(np.float64), img)
+            row[prec] = r
+        tiny_rows.append((sc, row))
+        ctx.close()
+        print(f"[precision] tiny W={W}: " + ", ".join(f"{p} {row[p]['fps']:.0f} FPS" for p in precs + ("unculled",)),
+              file=sys.stderr, flush=True)
+    # the MLP kernel alone at the composed scene's 16M pairs
+    big = []
+    for W in (64, 128):
+        sc = synth.scene_composed(n_per_asset=args.n, width=W)
+        ctx = nvgs.Context(0)
+        ctx.load_assets(sc.assets)
+        ctx.set_instances(sc.instances)
+        calibrate_keep(ctx, sc, args.keep, "fp32")
+        for prec in precs:
+            _, stage, st, _ = time_frames(ctx, sc, 5, 2, tile=8, precision=prec)
+            sec = stage["cull_mlp"] * 1e-3
+            tf = st["queried"] * FLOP_PER_QUERY[W] / sec / 1e12
+            big.append({"width": W, "precision": prec, "ms": stage["cull_mlp"], "queried": st["queried"],
+                        "queries_per_s": st["queried"] / sec, "tflops": tf, "peak_tflops": MFMA_PEAK_TFLOPS[prec],
+                        "frac": tf / MFMA_PEAK_TFLOPS[prec]})
+        ctx.close()
+    out = {"workload": "precision: tiny scene (20k torus, 256^2) at MLP widths 64/128 in FP32/BF16/FP8; the MLP "
+                       "kernel on the composed scene's 16M pairs",
+           "tiny": [row for _, row in tiny_rows], "mlp_kernel_composed": big}
+    if not args.no_cpu_baseline:
+        import oracle
+        cb = []
+        for sc, row in tiny_rows:
+            t0 = time.perf_counter()
+            _, olg = oracle.query(sc)
+            ref = oracle.frame(sc, use_mlp=False, want_margin=False)["images"][0]
+            dt = time.perf_counter() - t0
+            olg = olg[0]
+            for prec in precs:
+                lg, img = keep[(row["width"], prec)]
+                q = ~np.isnan(olg) & ~np.isnan(lg)
+                row[prec]["flip_rate_vs_fp64_mlp"] = float(np.mean((lg[q] >= 0) != (olg[q] >= 0)))
+                row[prec]["psnr_vs_fp64_unculled_db"] = psnr(img, ref)
+            cb.append({"width": row["width"], "seconds": dt})
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        out["cpu_baseline"] = {"value": 2.0 / sum(c["seconds"] for c in cb), "unit": "frames/s", "cores": threads,
+                               "kind": "oracle",
+                               "sample": "FP64 MLP query and unculled render of the tiny scene at widths 64 and 128"}
+    print(json.dumps(out), flush=True)
 
 
 def cpu_baseline_batched(sc, every=16):
