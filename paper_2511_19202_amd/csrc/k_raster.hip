@@ -271,11 +271,11 @@ __global__ __launch_bounds__(kChunk) void k_project(
     }
   }
   // the compositing record: one 64-byte line per splat, the conic scaled so
-  // that the exponent is base 2, and the log2 pre-test bound precomputed
+  // that the exponent is base 2, and log2 of the opacity that joins it there
   constexpr float kLog2e = 1.4426950408889634f;
   float4* sp = splat + 4 * (int64_t)slot;
   sp[0] = make_float4(u, v, -0.5f * kLog2e * ca, -kLog2e * cb);
-  sp[1] = make_float4(-0.5f * kLog2e * cc2, o, -__log2f(255.f * o) - 0.01f, rgb[0]);
+  sp[1] = make_float4(-0.5f * kLog2e * cc2, o, __log2f(o), rgb[0]);
   sp[2] = make_float4(rgb[1], rgb[2], ex, ey);
   sp[3] = make_float4(__uint_as_float((uint32_t)(R.pair_base + g)), pz, 0.f, 0.f);
   rect[slot] = make_uint4(r0, r1, (uint32_t)R.cam, ntiles);
@@ -447,18 +447,17 @@ hipError_t launch_tile_keys(const uint32_t* ranges, int64_t n, uint32_t* keys, u
 // Each wave owns an 8x8 block of pixels (one lane per pixel; the 32-pixel
 // tile gives every lane four blocks).  Splats are staged in LDS 256 at a
 // time; the next batch is fetched into registers while the current one is
-// composited.  Per (pixel, splat) the quadratic form is compared against a
-// conservative per-splat bound log2(1/(255 o)) - 0.01 before the exponential:
-// below it alpha is certainly under 1/255, so the skip decision is the same
-// as evaluating alpha.  A wave skips splats whose alpha footprint box misses
-// its pixel block.
+// composited.  Per (pixel, splat) alpha is one base-2 exponential whose
+// argument carries log2 of the opacity.  A wave skips splats whose alpha
+// footprint box misses its pixel block.
 // ---------------------------------------------------------------------------
 // ---------------------------------------------------------------------------
 // compositing work items.  A tile list longer than split_len entries is cut
-// into nch equal chunks composited by nch work-groups: a product pass gives
-// each chunk's per-pixel product of (1 - alpha) over its passing fragments
-// (no stop rule); chunk j then starts from the product of the chunks before
-// it.  Transmittance only falls, so a pixel stopped before chunk j exactly
+// into nch equal chunks composited by nch work-groups: the first chunk is
+// composited from T = 1 and stores its per-pixel product, while a product pass
+// gives each middle chunk's per-pixel product of (1 - alpha) over its passing
+// fragments (no stop rule); chunk j then starts from the product of the chunks
+// before it.  Transmittance only falls, so a pixel stopped before chunk j exactly
 // when that product is below 1e-4, and chunk j applies the stop rule from
 // there.  A combine pass sums the chunks' colours in list order.  The result
 // equals the sequential composite up to the association of the products and
@@ -524,7 +523,7 @@ __device__ __forceinline__ void blend_item(
   constexpr int BATCH = NT;              // one staged splat per thread per batch
   // staged records, one array so that a fragment's three reads share one
   // address: [k][0] = u, v, A, B (A, B, C: conic scaled by -log2(e)/2,
-  // -log2(e), -log2(e)/2); [k][1] = C, opacity, log2 bound, r; [k][2] = g, b
+  // -log2(e), -log2(e)/2); [k][1] = C, opacity, log2(opacity), r; [k][2] = g, b
   __shared__ float4 s_rec[BATCH][3];
   __shared__ uint32_t s_ov[T == 8 ? 1 : BATCH];  // bit b: the footprint box touches 8x8 block b
   __shared__ uint32_t s_p[RECORD ? BATCH : 1];
@@ -587,10 +586,13 @@ __device__ __forceinline__ void blend_item(
     const float4 g = s_rec[k][0];
     const float4 h = s_rec[k][1];
     const float dx = px[j] - g.x, dy = py[j] - g.y;
-    const float pw = dx * fmaf(g.z, dx, g.w * dy) + h.x * dy * dy;
-    const float al = fminf(kAlphaMax, h.y * __builtin_amdgcn_exp2f(pw));
-    const bool ok = pw >= h.z && pw <= 0.f && al >= kAlphaMin;
-    const float Tn = Tr[j] * (1.f - al);
+    // alpha = min(0.99, o 2^pw) with pw = -log2(e) d^T conic d / 2 <= 0, as
+    // 2^(pw + log2 o); a positive pw (rounding) is skipped as pw > 0 is
+    const float q = fmaf(dx, fmaf(g.z, dx, g.w * dy), fmaf(h.x * dy, dy, h.z));
+    const float al = fminf(kAlphaMax, __builtin_amdgcn_exp2f(q));
+    const bool ok = q <= h.z && al >= kAlphaMin;
+    const float w0 = al * Tr[j];
+    const float Tn = Tr[j] - w0;  // T (1 - alpha)
     if (PROD) {
       Tr[j] = ok ? Tn : Tr[j];
       px[j] = Tr[j] < kTMin ? kFar : px[j];
@@ -601,7 +603,7 @@ __device__ __forceinline__ void blend_item(
     const bool low = __float_as_uint(Tn) < __float_as_uint(kTMin);
     const bool halt = ok && low;
     const bool take = ok != halt;  // ok and not low
-    const float w = take ? al * Tr[j] : 0.f;
+    const float w = take ? w0 : 0.f;
     cr[j] = fmaf(w, h.w, cr[j]);
     cg[j] = fmaf(w, c.x, cg[j]);
     cb[j] = fmaf(w, c.y, cb[j]);
@@ -717,30 +719,32 @@ __device__ __forceinline__ void blend_item(
   }
 }
 
-// merge0 (frames without contribution recording or statistics): the product
-// pass (MODE 2) composites every split list's first chunk and stores its
-// product instead of walking it twice; the composite pass then skips it.
-template <int T, int MODE, bool STATS>
+// Compositing in two launches.  PHASE 0: the first chunk of every split list,
+// composited from T = 1 (storing its product, 0 where the pixel stopped), and
+// the product pass over the middle chunks; PHASE 1: lists that are not split,
+// and the later chunks of split ones, each starting from the product of the
+// chunks before it.
+template <int T, int MODE, bool STATS, int PHASE>
 __global__ __launch_bounds__(T == 8 ? 64 : 256) void k_blend(
     ItemCtx ic, const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ ids,
     const float4* __restrict__ splat, int W, int H, int tiles_x, int n_tiles, float bg0, float bg1, float bg2,
-    float* __restrict__ rgb, uint32_t* __restrict__ contrib, unsigned long long* __restrict__ work, int merge0) {
+    float* __restrict__ rgb, uint32_t* __restrict__ contrib, unsigned long long* __restrict__ work) {
   const int64_t item = blockIdx.x;
   if (item >= min((int64_t)*ic.n_items, ic.cap_items)) return;
   const uint2 it = ic.items[item];
   const uint32_t nch = ic.nch[it.x];
   const bool split = nch > 1;
-  if (MODE == 2) {
-    if (!split || it.y + 1 == nch) return;  // products are needed for all but the last chunk
-    if (merge0 && it.y == 0)
-      blend_item<T, 0, false, true>(ic, it, nch, ranges, ids, splat, W, H, tiles_x, n_tiles, bg0, bg1, bg2, rgb,
-                                    contrib, nullptr);
+  if (PHASE == 0) {
+    if (!split || it.y + 1 == nch) return;  // the last chunk's product is never needed
+    if (it.y == 0)
+      blend_item<T, MODE, STATS, true>(ic, it, nch, ranges, ids, splat, W, H, tiles_x, n_tiles, bg0, bg1, bg2, rgb,
+                                       contrib, work);
     else
       blend_item<T, 2, false, false>(ic, it, nch, ranges, ids, splat, W, H, tiles_x, n_tiles, bg0, bg1, bg2, rgb,
                                      contrib, nullptr);
     return;
   }
-  if (merge0 && split && it.y == 0) return;  // composited by the product pass
+  if (split && it.y == 0) return;  // composited in phase 0
   blend_item<T, MODE, STATS, false>(ic, it, nch, ranges, ids, splat, W, H, tiles_x, n_tiles, bg0, bg1, bg2, rgb,
                                     contrib, work);
 }
@@ -791,20 +795,20 @@ static void launch_blend_t(bool record, const ItemCtx& ic, bool any_split, hipSt
   constexpr int NT = T == 8 ? 64 : 256;
   const dim3 grid((unsigned)ic.cap_items);
   uint32_t* cu = reinterpret_cast<uint32_t*>(contrib);
-  // the first chunk of a split list is composited in the product pass unless
-  // contributions or statistics are recorded
-  const int merge0 = (any_split && !record && !work) ? 1 : 0;
-  if (any_split)
-    hipLaunchKernelGGL((k_blend<T, 2, false>), grid, dim3(NT), 0, st, ic, ranges, ids, splat, W, H, tiles_x, n_tiles,
-                       b0, b1, b2, rgb, cu, nullptr, merge0);
-#define NVGS_BL(M, S)                                                                                            \
-  hipLaunchKernelGGL((k_blend<T, M, S>), grid, dim3(NT), 0, st, ic, ranges, ids, splat, W, H, tiles_x, n_tiles, b0, \
-                     b1, b2, rgb, cu, work, merge0)
-  if (record) {
-    if (work) NVGS_BL(1, true); else NVGS_BL(1, false);
-  } else {
-    if (work) NVGS_BL(0, true); else NVGS_BL(0, false);
-  }
+#define NVGS_BL(M, S, P)                                                                                         \
+  hipLaunchKernelGGL((k_blend<T, M, S, P>), grid, dim3(NT), 0, st, ic, ranges, ids, splat, W, H, tiles_x, n_tiles, \
+                     b0, b1, b2, rgb, cu, work)
+#define NVGS_BL_MS(P)                                          \
+  do {                                                         \
+    if (record) {                                              \
+      if (work) NVGS_BL(1, true, P); else NVGS_BL(1, false, P); \
+    } else {                                                   \
+      if (work) NVGS_BL(0, true, P); else NVGS_BL(0, false, P); \
+    }                                                          \
+  } while (0)
+  if (any_split) NVGS_BL_MS(0);
+  NVGS_BL_MS(1);
+#undef NVGS_BL_MS
 #undef NVGS_BL
   if (any_split)
     hipLaunchKernelGGL((k_blend_combine<T>), grid, dim3(256), 0, st, ic, W, H, tiles_x, n_tiles, b0, b1, b2, rgb);
