@@ -401,22 +401,45 @@ hipError_t launch_watermark(uint32_t* counters, hipStream_t st) {
   return hipGetLastError();
 }
 
-// [start, end) of every tile key in the sorted list (ranges pre-filled with 0)
+// [start, end) of every tile key in the sorted list (ranges pre-filled with
+// 0).  Each thread takes four consecutive positions with one 16-byte load and
+// handles the boundaries after each of them (and before position 0).
 __global__ void k_ranges(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_dev, int64_t cap,
                          int64_t nkeys, uint32_t* __restrict__ ranges) {
   const int64_t n = live(n_dev, cap);
-  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t k = keys[j];
-    if (k >= nkeys) continue;
-    if (j == 0 || keys[j - 1] != k) ranges[2 * (int64_t)k] = (uint32_t)j;
-    if (j == n - 1 || keys[j + 1] != k) ranges[2 * (int64_t)k + 1] = (uint32_t)(j + 1);
+  const uint32_t kNone = 0xffffffffu;
+  for (int64_t j0 = 4 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x); j0 < n;
+       j0 += 4 * (int64_t)gridDim.x * blockDim.x) {
+    uint32_t k[5];
+    if (j0 + 4 <= n) {
+      const uint4 q = *reinterpret_cast<const uint4*>(keys + j0);
+      k[0] = q.x;
+      k[1] = q.y;
+      k[2] = q.z;
+      k[3] = q.w;
+    } else {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) k[u] = j0 + u < n ? keys[j0 + u] : kNone;
+    }
+    k[4] = j0 + 4 < n ? keys[j0 + 4] : kNone;
+    if (j0 == 0 && k[0] < nkeys) ranges[2 * (int64_t)k[0]] = 0u;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      // boundary between positions j0 + u and j0 + u + 1
+      if (j0 + u < n && k[u] != k[u + 1]) {
+        const uint32_t pos = (uint32_t)(j0 + u + 1);
+        if (k[u] < nkeys) ranges[2 * (int64_t)k[u] + 1] = pos;
+        if (k[u + 1] < nkeys) ranges[2 * (int64_t)k[u + 1]] = pos;
+      }
+    }
   }
 }
 
 hipError_t launch_ranges(const uint32_t* keys, const uint32_t* n_dev, int64_t cap, int64_t nkeys, uint32_t* ranges,
                          hipStream_t st) {
   if (cap == 0) return hipSuccess;
-  unsigned grid = (unsigned)std::min<int64_t>((cap + 255) / 256, 65536);
+  if (reinterpret_cast<uintptr_t>(keys) % 16 != 0) return hipErrorInvalidValue;  // the 16-byte loads
+  unsigned grid = (unsigned)std::min<int64_t>((cap + 1023) / 1024, 65536);
   hipLaunchKernelGGL(k_ranges, dim3(grid), dim3(256), 0, st, keys, n_dev, cap, nkeys, ranges);
   return hipGetLastError();
 }

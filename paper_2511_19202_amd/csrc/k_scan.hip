@@ -44,11 +44,13 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* __
   __shared__ uint32_t s_wave[kScanThreads / 64];
   __shared__ unsigned long long s_wide[kScanThreads / 64];
   const int64_t n = scan_n(n_cap, n_dev);
-  const int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * kScanItems;
+  const int64_t blk0 = (int64_t)blockIdx.x * kScanBlock;
   unsigned long long s = 0;
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k)
-    if (base + k < n) s += in[base + k];
+  for (int k = 0; k < kScanItems; ++k) {  // coalesced: consecutive threads read consecutive items
+    const int64_t i = blk0 + k * kScanThreads + threadIdx.x;
+    if (i < n) s += in[i];
+  }
   uint32_t tot;
   block_exclusive_scan((uint32_t)s, s_wave, &tot);
   if (wrap) {
@@ -95,24 +97,44 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_partials(uint32_t* __rest
   if (threadIdx.x == 0 && wrap && (wide >> 32)) atomicOr(wrap, 4u);
 }
 
+// The block's items are read and written coalesced (consecutive threads,
+// consecutive items) and transposed through LDS so that each thread scans 16
+// consecutive items; one padding word per 16 keeps both access patterns free
+// of bank conflicts.
+__device__ __forceinline__ int scan_pad(int i) { return i + (i >> 4); }
+
 __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* in, uint32_t* out,  // may alias
                                                             int64_t n_cap, const uint32_t* __restrict__ n_dev,
                                                             const uint32_t* __restrict__ partials) {
   __shared__ uint32_t s_wave[kScanThreads / 64];
+  __shared__ uint32_t s_x[kScanBlock + kScanBlock / 16];
   const int64_t n = scan_n(n_cap, n_dev);
-  const int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * kScanItems;
+  const int64_t blk0 = (int64_t)blockIdx.x * kScanBlock;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int i = k * kScanThreads + threadIdx.x;
+    s_x[scan_pad(i)] = blk0 + i < n ? in[blk0 + i] : 0u;
+  }
+  __syncthreads();
   uint32_t v[kScanItems];
   uint32_t s = 0;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
-    v[k] = base + k < n ? in[base + k] : 0u;
+    v[k] = s_x[scan_pad(threadIdx.x * kScanItems + k)];
     s += v[k];
   }
+  // (the scan's barriers also order the reads above before the writes below)
   uint32_t pre = block_exclusive_scan(s, s_wave, nullptr) + partials[blockIdx.x];
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
-    if (base + k < n) out[base + k] = pre;
+    s_x[scan_pad(threadIdx.x * kScanItems + k)] = pre;
     pre += v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int i = k * kScanThreads + threadIdx.x;
+    if (blk0 + i < n) out[blk0 + i] = s_x[scan_pad(i)];
   }
 }
 
