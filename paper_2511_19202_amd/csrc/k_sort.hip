@@ -72,23 +72,34 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t* __r
 }
 
 // one work-group per digit: exclusive scan of hist[d][0..nblocks) in place,
-// the row total to tot[d]
+// the row total to tot[d].  The row is read and written coalesced and
+// transposed through LDS (one padding word per 16) so that each thread scans
+// 16 consecutive entries.
 constexpr int kRowItems = 16;
+constexpr int kRowTile = kSortThreads * kRowItems;
+__device__ __forceinline__ int row_pad(int i) { return i + (i >> 4); }
+
 __global__ __launch_bounds__(kSortThreads) void k_radix_rowscan(uint32_t* __restrict__ hist, int64_t nblocks,
                                                                 const uint32_t* __restrict__ n_dev, int64_t cap,
                                                                 uint32_t* __restrict__ tot) {
   __shared__ uint32_t s_w[kSortWaves];
+  __shared__ uint32_t s_x[kRowTile + kRowTile / 16];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t* row = hist + (int64_t)blockIdx.x * nblocks;
   const int64_t nbl = live_blocks(n_dev, cap);  // the row's live entries
   uint32_t carry = 0;
-  for (int64_t off = 0; off < nbl; off += kSortThreads * kRowItems) {
-    const int64_t base = off + (int64_t)threadIdx.x * kRowItems;
+  for (int64_t off = 0; off < nbl; off += kRowTile) {
+#pragma unroll
+    for (int k = 0; k < kRowItems; ++k) {
+      const int i = k * kSortThreads + threadIdx.x;
+      s_x[row_pad(i)] = off + i < nbl ? row[off + i] : 0u;
+    }
+    __syncthreads();
     uint32_t v[kRowItems];
     uint32_t s = 0;
 #pragma unroll
     for (int k = 0; k < kRowItems; ++k) {
-      v[k] = base + k < nbl ? row[base + k] : 0u;
+      v[k] = s_x[row_pad(threadIdx.x * kRowItems + k)];
       s += v[k];
     }
     uint32_t x = s;
@@ -98,21 +109,27 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_rowscan(uint32_t* __rest
       if (lane >= o) x += y;
     }
     if (lane == 63) s_w[wave] = x;
-    __syncthreads();
+    __syncthreads();  // also orders every thread's reads of s_x before the writes below
     uint32_t pre = carry, all = 0;
 #pragma unroll
     for (int w = 0; w < kSortWaves; ++w) {
       pre += (w < wave) ? s_w[w] : 0u;
       all += s_w[w];
     }
-    __syncthreads();
     pre += x - s;
 #pragma unroll
     for (int k = 0; k < kRowItems; ++k) {
-      if (base + k < nbl) row[base + k] = pre;
+      s_x[row_pad(threadIdx.x * kRowItems + k)] = pre;
       pre += v[k];
     }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kRowItems; ++k) {
+      const int i = k * kSortThreads + threadIdx.x;
+      if (off + i < nbl) row[off + i] = s_x[row_pad(i)];
+    }
     carry += all;
+    __syncthreads();  // s_w and s_x are reused by the next tile
   }
   if (threadIdx.x == 0) tot[blockIdx.x] = carry;
 }
