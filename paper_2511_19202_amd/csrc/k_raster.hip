@@ -330,36 +330,57 @@ hipError_t launch_gather_tiles(const uint32_t* sorted_ids, const uint4* rect, co
   return hipGetLastError();
 }
 
-// one thread per splat in depth order: one (tile key, splat id) entry per
-// overlapped tile, written at the splat's exclusive offset.  Past the entry
-// capacity the overflow flag is raised and only the entries below it are
-// written, so every position of [0, cap_dup) still holds an entry of this
-// frame (a clipped frame, never stale keys).
-__global__ void k_emit(const uint32_t* __restrict__ ids, const uint4* __restrict__ rect_sorted,
-                       const uint32_t* __restrict__ off, const uint32_t* __restrict__ n_dev, int64_t cap,
-                       const uint32_t* __restrict__ n_dup_dev, int64_t cap_dup, int tiles_x, int n_tiles,
-                       uint32_t* __restrict__ keys, uint32_t* __restrict__ vals, uint32_t* __restrict__ overflow) {
+// One (tile key, splat id) entry per overlapped tile of each splat, in depth
+// order: splat j's entries occupy [off[j], off[j] + ntiles_j), its tiles in
+// row-major order.  A wave takes 64 consecutive splats and its lanes write
+// the group's entries consecutively (coalesced, and a splat over many tiles
+// does not hold one lane for all of them): entry e of the group belongs to the
+// last lane whose group-relative offset is <= e (binary search over the
+// lanes).  Past the entry capacity the overflow flag is raised and only the
+// entries below it are written, so every position of [0, cap_dup) still holds
+// an entry of this frame (a clipped frame, never stale keys).
+__global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ ids, const uint4* __restrict__ rect_sorted,
+                                              const uint32_t* __restrict__ off, const uint32_t* __restrict__ n_dev,
+                                              int64_t cap, const uint32_t* __restrict__ n_dup_dev, int64_t cap_dup,
+                                              int tiles_x, int n_tiles, uint32_t* __restrict__ keys,
+                                              uint32_t* __restrict__ vals, uint32_t* __restrict__ overflow) {
+  const int lane = threadIdx.x & 63;
   const int64_t n = live(n_dev, cap);
-  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
-    const uint4 r = rect_sorted[j];
-    if (r.w == 0) continue;
-    const uint32_t s = ids[j];
-    int64_t o = off[j];
-    if (o >= cap_dup) {
-      atomicOr(overflow, 2u);
-      continue;
+  const int64_t ngroups = (n + 63) / 64;
+  const int64_t wstride = (int64_t)gridDim.x * (blockDim.x / 64);
+  for (int64_t grp = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); grp < ngroups; grp += wstride) {
+    const int64_t j = grp * 64 + lane;
+    uint4 r = make_uint4(0u, 0u, 0u, 0u);
+    uint32_t o = 0u, id = 0u;
+    if (j < n) {
+      r = rect_sorted[j];
+      o = off[j];
+      id = ids[j];
     }
-    if (o + r.w > cap_dup) atomicOr(overflow, 2u);
-    const int tx0 = r.x & 0xffff, ty0 = r.x >> 16, tx1 = r.y & 0xffff, ty1 = r.y >> 16;
-    const uint32_t kb = r.z * (uint32_t)n_tiles;
-    for (int ty = ty0; ty <= ty1; ++ty)
-      for (int tx = tx0; tx <= tx1; ++tx) {
-        if (o < cap_dup) {
-          keys[o] = kb + (uint32_t)(ty * tiles_x + tx);
-          vals[o] = s;
-        }
-        ++o;
+    const uint32_t start = __shfl(o, 0);  // lane 0's splat is live
+    const uint32_t rel = j < n ? o - start : 0xffffffffu;
+    uint32_t total = j < n ? rel + r.w : 0u;
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) total = max(total, __shfl_xor(total, m));
+    if (lane == 0 && (int64_t)start + total > cap_dup) atomicOr(overflow, 2u);
+    // every lane stays in the loop (the shuffles read all 64 lanes); only the
+    // stores are limited to the group's entries
+    for (uint32_t e0 = 0; e0 < total; e0 += 64) {
+      const uint32_t e = e0 + (uint32_t)lane;
+      int src = 0;  // rel of lane 0 is 0 <= e
+#pragma unroll
+      for (int step = 32; step > 0; step >>= 1)
+        if (__shfl(rel, src + step) <= e) src += step;
+      const uint32_t q = e - __shfl(rel, src);
+      const uint32_t rx = __shfl(r.x, src), ry = __shfl(r.y, src), rz = __shfl(r.z, src), sid = __shfl(id, src);
+      const uint32_t tx0 = rx & 0xffffu, ty0 = rx >> 16, w = (ry & 0xffffu) - tx0 + 1u;
+      const uint32_t dy = q / w, dx = q - dy * w;
+      const int64_t pos = (int64_t)start + e;
+      if (e < total && pos < cap_dup) {
+        keys[pos] = rz * (uint32_t)n_tiles + (ty0 + dy) * (uint32_t)tiles_x + tx0 + dx;
+        vals[pos] = sid;
       }
+    }
   }
   (void)n_dup_dev;
 }
