@@ -726,6 +726,8 @@ nvgs_status enqueue_frame(nvgs_ctx* ctx, hipStream_t st, const Frame& f, bool ea
   bi.order = tile_order;
   bi.nch = ts;
   bi.split_off = ts + 3 * nk;
+  bi.item_off = ts + 2 * nk;
+  bi.nkeys = nk;
   bi.items = P_<uint2>(ctx->citems);
   bi.n_items = counters + 16;
   bi.cap_items = ctx->cap_items;

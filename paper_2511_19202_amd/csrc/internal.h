@@ -166,6 +166,8 @@ struct BlendItems {
   int64_t cap_split;        // split-chunk slots (at most 2 cap_dup / split_len + 2 are used)
   float* prod;              // [split slots][T*T]
   float4* part;             // [split slots][T*T]
+  const uint32_t* item_off; // [nkeys] first item per position
+  int64_t nkeys;            // positions (cameras x tiles)
 };
 // Builds nch / item_off / split_off and the item list; n_items and n_split
 // receive the totals; overflow bit value 8 when cap_items is exceeded.

@@ -541,6 +541,8 @@ struct ItemCtx {
   const uint32_t* split_off;
   float* prod;              // [split chunk][T*T]
   float4* part;             // [split chunk][T*T]: r, g, b, flag
+  const uint32_t* item_off; // [nkeys] first item per position
+  int64_t nkeys;            // positions
 };
 
 // A pixel that has stopped (or lies outside the image, or stopped in an
@@ -798,37 +800,40 @@ __global__ __launch_bounds__(T == 8 ? 64 : 256) void k_blend(
 template <int T>
 __global__ __launch_bounds__(256) void k_blend_combine(ItemCtx ic, int W, int H, int tiles_x, int n_tiles, float bg0,
                                                        float bg1, float bg2, float* __restrict__ rgb) {
-  const int64_t item = blockIdx.x;
-  if (item >= min((int64_t)*ic.n_items, ic.cap_items)) return;
-  const uint2 it = ic.items[item];
-  const uint32_t nch = ic.nch[it.x];
-  if (nch <= 1 || it.y != 0) return;
-  if ((int64_t)ic.split_off[it.x] + nch > ic.cap_split) return;
-  const int key = (int)ic.order[it.x];
-  const int cam = key / n_tiles, tile = key % n_tiles;
-  const int tx = tile % tiles_x, ty = tile / tiles_x;
-  const int64_t base = (int64_t)ic.split_off[it.x] * (T * T);
-  for (int pix = threadIdx.x; pix < T * T; pix += 256) {
-    const int blk = pix / 64, lane = pix % 64;
-    const int x = tx * T + (blk % (T / 8)) * 8 + (lane & 7), y = ty * T + (blk / (T / 8)) * 8 + (lane >> 3);
-    if (!(x < W && y < H)) continue;
-    float r = 0.f, g = 0.f, b = 0.f, tf = 1.f;
-    for (uint32_t q = 0; q < nch; ++q) {
-      const float4 v = ic.part[base + (int64_t)q * (T * T) + pix];
-      if (v.w == 0.f) break;  // stopped before this chunk: tf is the last chunk's exit value
-      r += v.x;
-      g += v.y;
-      b += v.z;
-      if (v.w < 0.f) {
-        tf = -v.w;
-        break;
+  // work-groups loop over the launch positions; a split one is combined when
+  // all of its chunks were composited (items within the capacity)
+  const int64_t live_items = min((int64_t)*ic.n_items, ic.cap_items);
+  for (int64_t p = blockIdx.x; p < ic.nkeys; p += gridDim.x) {
+    const uint32_t nch = ic.nch[p];
+    if (nch <= 1) continue;
+    if ((int64_t)ic.item_off[p] + nch > live_items) continue;
+    if ((int64_t)ic.split_off[p] + nch > ic.cap_split) continue;
+    const int key = (int)ic.order[p];
+    const int cam = key / n_tiles, tile = key % n_tiles;
+    const int tx = tile % tiles_x, ty = tile / tiles_x;
+    const int64_t base = (int64_t)ic.split_off[p] * (T * T);
+    for (int pix = threadIdx.x; pix < T * T; pix += 256) {
+      const int blk = pix / 64, lane = pix % 64;
+      const int x = tx * T + (blk % (T / 8)) * 8 + (lane & 7), y = ty * T + (blk / (T / 8)) * 8 + (lane >> 3);
+      if (!(x < W && y < H)) continue;
+      float r = 0.f, g = 0.f, b = 0.f, tf = 1.f;
+      for (uint32_t q = 0; q < nch; ++q) {
+        const float4 v = ic.part[base + (int64_t)q * (T * T) + pix];
+        if (v.w == 0.f) break;  // stopped before this chunk: tf is the last chunk's exit value
+        r += v.x;
+        g += v.y;
+        b += v.z;
+        if (v.w < 0.f) {
+          tf = -v.w;
+          break;
+        }
+        tf = v.w;
       }
-      tf = v.w;
+      float* o = rgb + (((int64_t)cam * H + y) * W + x) * 3;
+      o[0] = fmaf(tf, bg0, r);
+      o[1] = fmaf(tf, bg1, g);
+      o[2] = fmaf(tf, bg2, b);
     }
-    float* o = rgb + (((int64_t)cam * H + y) * W + x) * 3;
-    o[0] = fmaf(tf, bg0, r);
-    o[1] = fmaf(tf, bg1, g);
-    o[2] = fmaf(tf, bg2, b);
   }
 }
 
@@ -855,7 +860,8 @@ static void launch_blend_t(bool record, const ItemCtx& ic, bool any_split, hipSt
 #undef NVGS_BL_MS
 #undef NVGS_BL
   if (any_split)
-    hipLaunchKernelGGL((k_blend_combine<T>), grid, dim3(256), 0, st, ic, W, H, tiles_x, n_tiles, b0, b1, b2, rgb);
+    hipLaunchKernelGGL((k_blend_combine<T>), dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(ic.nkeys, 2048))), dim3(256), 0, st, ic, W,
+                       H, tiles_x, n_tiles, b0, b1, b2, rgb);
 }
 
 hipError_t launch_split_items(const uint32_t* ranges, const uint32_t* order, int64_t nkeys, int split_len,
@@ -878,7 +884,8 @@ hipError_t launch_blend(const BlendItems& bi, const uint32_t* ranges, const uint
                         float* contrib, unsigned long long* work, hipStream_t st) {
   const int n_tiles = tiles_x * tiles_y;
   if (bi.cap_items == 0) return hipSuccess;
-  const ItemCtx ic{bi.items, bi.n_items, bi.cap_items, bi.cap_split, bi.order, bi.nch, bi.split_off, bi.prod, bi.part};
+  const ItemCtx ic{bi.items, bi.n_items, bi.cap_items, bi.cap_split, bi.order,   bi.nch,
+                   bi.split_off, bi.prod,   bi.part,      bi.item_off,  bi.nkeys};
   const bool record = contrib != nullptr;
   const bool any_split = bi.split_len > 0;
   if (tile == 8)
