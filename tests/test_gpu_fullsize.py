@@ -186,3 +186,66 @@ def test_full_size_graph_frame_matches_oracle(nvgs, full):
     _check_pixels(img[0], oracle.render_camera(rec_g, prect, cam, TILE, sc.bg), "compositing (same input)", 1e-4)
     rec, _ = oracle.project(sc, cam, kept)
     _check_pixels(img[0], oracle.render_camera(rec, prect, cam, TILE, sc.bg), "from scratch", 1e-3)
+
+
+def test_full_size_batched_frame(nvgs):
+    """The batching workload at its full size (16 uneven SH3 assets, 1,024
+    instances, 8 ring cameras at 1920x1080; BF16 MLP, 8x8 tiles, reserved
+    capacities, graph frame).  Its 3.45e9 pairs are beyond the oracle as a
+    whole, so it is checked on sampled (camera, instance) segments and by
+    properties that hold at any size: the keep states of sampled segments
+    (FP32 MLP) against the oracle run on that one instance and camera; the
+    graph frame equals the eager frame; a camera's image in the 8-camera
+    frame equals that camera rendered alone (the depth sort is stable and
+    splat ids follow (camera, instance, Gaussian) order, so its tile lists
+    are the same entries in the same order)."""
+    import torch
+    log("[full] batched scene: 16 assets, 1024 instances, 8 cameras")
+    sc = synth.scene_batched()
+    ctx = _ctx(nvgs, sc)
+    # output biases set so that 29 % of each asset's in-frustum pairs of camera
+    # 0 keep (the trained networks' rate on this workload); the threshold is
+    # taken from the kernel's FP32 logits, as an input setting only: the
+    # oracle below runs the resulting weights through its own MLP
+    _, lg = ctx.query_visibility(sc.cameras[:1])
+    lg = lg[0].cpu().numpy()
+    off = sc.pair_offsets()
+    for a_idx, a in enumerate(sc.assets):
+        z = np.concatenate([lg[off[i]:off[i + 1]] for i, inst in enumerate(sc.instances) if inst.asset == a_idx])
+        z = np.sort(z[~np.isnan(z)])
+        if len(z) < 2:
+            continue
+        j = int(np.clip(round(0.71 * len(z)), 1, len(z) - 1))
+        p = a.mlp.params.copy()
+        p[-1] = np.float32(p[-1] - 0.5 * (z[j - 1] + z[j]))  # the output bias
+        a.mlp.params = p
+    del lg
+    ctx.load_assets(sc.assets)
+    ctx.set_instances(sc.instances)
+    st, _ = ctx.query_visibility(sc.cameras, want_logits=False)
+    pick = np.random.default_rng(11)
+    for k, i in zip(pick.integers(0, len(sc.cameras), 6), pick.integers(0, len(sc.instances), 6)):
+        k, i = int(k), int(i)
+        sub = synth.Scene(assets=sc.assets, instances=[sc.instances[i]], cameras=[sc.cameras[k]], tile=sc.tile)
+        ost, _, omg = oracle.query(sub, want_margin=True)
+        g = st[k, off[i]:off[i + 1]].cpu().numpy()
+        diff = g != ost[0]
+        log(f"[full] camera {k}, instance {i}: {g.size} pairs, {int((g == 2).sum())} kept, "
+            f"mismatches {int(diff.sum())} (excused {int(np.sum(diff & (omg[0] < MARGIN)))})")
+        assert np.sum(diff & ~(omg[0] < MARGIN)) == 0
+    del st
+    kw = dict(tile=TILE, precision="bf16")
+    eager = ctx.render(sc.cameras, **kw).cpu().numpy()
+    wm = ctx.watermarks(reset=True)
+    ctx.reserve(int(wm["max_splats"] * 1.1) + 4096, int(wm["max_duplicates"] * 1.1) + 4096)
+    for _ in range(3):  # capture, then replays
+        g = ctx.render(sc.cameras, graph=True, **kw)
+    torch.cuda.synchronize()
+    img = g.cpu().numpy()
+    assert not ctx.watermarks()["overflowed"]
+    assert np.array_equal(img, eager)
+    for k in (0, 5):
+        alone = ctx.render([sc.cameras[k]], **kw).cpu().numpy()
+        log(f"[full] camera {k} alone vs in the 8-camera frame: max diff {np.abs(alone[0] - img[k]).max():.2e}")
+        assert np.array_equal(alone[0], img[k])
+    ctx.close()
