@@ -47,17 +47,24 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t* __r
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t n = live_n(n_dev, cap);
   const int64_t nbl = live_blocks(n_dev, cap);
-  for (int64_t blk = blockIdx.x; blk < nbl; blk += gridDim.x) {
-    for (int d = threadIdx.x; d < kSortWaves * 256; d += kSortThreads) (&s_h[0][0])[d] = 0;
-    __syncthreads();
+  // the wave's keys of a block (beyond the live keys: none); the next block's
+  // are loaded while this one is counted
+  auto load = [&](int64_t blk, uint32_t* kv) {
     const int64_t base = blk * kSortBlock + wave * kPerWave;
-    // all of the wave's loads first, then the LDS counts
-    uint32_t kv[kRounds];
 #pragma unroll
     for (int r = 0; r < kRounds; ++r) {
       const int64_t idx = base + r * 64 + lane;
       kv[r] = idx < n ? keys[idx] : 0xffffffffu;
     }
+  };
+  uint32_t kv[kRounds];
+  load(blockIdx.x, kv);
+  for (int64_t blk = blockIdx.x; blk < nbl; blk += gridDim.x) {
+    uint32_t kn[kRounds];
+    load(blk + gridDim.x, kn);
+    for (int d = threadIdx.x; d < kSortWaves * 256; d += kSortThreads) (&s_h[0][0])[d] = 0;
+    __syncthreads();
+    const int64_t base = blk * kSortBlock + wave * kPerWave;
 #pragma unroll
     for (int r = 0; r < kRounds; ++r)
       if (base + r * 64 + lane < n) atomicAdd(&s_h[wave][(kv[r] >> shift) & dmask], 1u);
@@ -68,6 +75,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t* __r
       hist[(int64_t)d * nblocks + blk] = s;
     }
     __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) kv[r] = kn[r];
   }
 }
 
@@ -149,19 +158,34 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t n = live_n(n_dev, cap);
   const int64_t nbl = live_blocks(n_dev, cap);
+  // the wave's keys and values of a block; the next block's are loaded while
+  // this one is ranked and written
+  auto load = [&](int64_t blk, uint32_t* k, uint32_t* v) {
+    const int64_t base = blk * kSortBlock + wave * kPerWave;
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+      const int64_t idx = base + r * 64 + lane;
+      const bool ok = idx < n;
+      k[r] = ok ? keys_in[idx] : 0u;
+      v[r] = ok ? (iota_vals ? (uint32_t)idx : vals_in[idx]) : 0u;
+    }
+  };
+  uint32_t key[kRounds], val[kRounds];
+  load(blockIdx.x, key, val);
   for (int64_t blk = blockIdx.x; blk < nbl; blk += gridDim.x) {
+    uint32_t nkey[kRounds], nval[kRounds];
+    load(blk + gridDim.x, nkey, nval);
     for (int d = threadIdx.x; d < kSortWaves * 256; d += kSortThreads) (&s_cnt[0][0])[d] = 0;
     __syncthreads();
     const int64_t block0 = blk * kSortBlock;
     const int64_t base = block0 + wave * kPerWave;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    uint32_t key[kRounds], local[kRounds];
+    uint32_t local[kRounds];
     // phase 1: rank every key among the equal digits of this wave, in order
 #pragma unroll
     for (int r = 0; r < kRounds; ++r) {
       const int64_t idx = base + r * 64 + lane;
       const bool ok = idx < n;
-      key[r] = ok ? keys_in[idx] : 0u;
       const uint32_t d = (key[r] >> shift) & dmask;
       uint64_t peers = __ballot(ok);
       for (int b = 0; b < nbits; ++b) {
@@ -219,7 +243,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
         const uint32_t dg = (key[r] >> shift) & dmask;
         const uint32_t p = s_start[dg] + s_cnt[wave][dg] + local[r];
         s_k[p] = key[r];
-        s_v[p] = iota_vals ? (uint32_t)idx : vals_in[idx];
+        s_v[p] = val[r];
       }
     }
     __syncthreads();
@@ -233,6 +257,11 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
       vals_out[pos] = s_v[p];
     }
     __syncthreads();  // LDS is reused by the next block
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+      key[r] = nkey[r];
+      val[r] = nval[r];
+    }
   }
 }
 
