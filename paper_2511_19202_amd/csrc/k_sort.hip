@@ -97,12 +97,21 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_rowscan(uint32_t* __rest
   uint32_t* row = hist + (int64_t)blockIdx.x * nblocks;
   const int64_t nbl = live_blocks(n_dev, cap);  // the row's live entries
   uint32_t carry = 0;
-  for (int64_t off = 0; off < nbl; off += kRowTile) {
+  // a tile's entries, coalesced; the next tile's are loaded while this one is scanned
+  auto load = [&](int64_t off, uint32_t* v) {
 #pragma unroll
     for (int k = 0; k < kRowItems; ++k) {
-      const int i = k * kSortThreads + threadIdx.x;
-      s_x[row_pad(i)] = off + i < nbl ? row[off + i] : 0u;
+      const int64_t i = off + k * kSortThreads + threadIdx.x;
+      v[k] = i < nbl ? row[i] : 0u;
     }
+  };
+  uint32_t cur[kRowItems];
+  load(0, cur);
+  for (int64_t off = 0; off < nbl; off += kRowTile) {
+    uint32_t nxt[kRowItems];
+    load(off + kRowTile, nxt);  // the entries past this tile, which its stores below do not touch
+#pragma unroll
+    for (int k = 0; k < kRowItems; ++k) s_x[row_pad(k * kSortThreads + threadIdx.x)] = cur[k];
     __syncthreads();
     uint32_t v[kRowItems];
     uint32_t s = 0;
@@ -139,6 +148,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_rowscan(uint32_t* __rest
     }
     carry += all;
     __syncthreads();  // s_w and s_x are reused by the next tile
+#pragma unroll
+    for (int k = 0; k < kRowItems; ++k) cur[k] = nxt[k];
   }
   if (threadIdx.x == 0) tot[blockIdx.x] = carry;
 }
