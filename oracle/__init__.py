@@ -68,6 +68,12 @@ def lib():
                                     C.c_double, C.c_double]
         L.orc_fp8_scales.argtypes = [dp, C.c_int, dp]
         L.orc_mlp_forward_q.argtypes = [dp, C.c_int, dp, C.c_int64, C.c_int, dp]
+        L.orc_to_bf16.argtypes = [C.c_double]
+        L.orc_to_bf16.restype = C.c_double
+        L.orc_to_e4m3.argtypes = [C.c_double]
+        L.orc_to_e4m3.restype = C.c_double
+        L.orc_lr_schedule.argtypes = [C.c_double, C.c_double, C.c_int64, C.c_int64]
+        L.orc_lr_schedule.restype = C.c_double
         L.orc_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
         L.orc_splitmix64.restype = C.c_uint64
         L.orc_compact_sizes.argtypes = [C.c_int]
@@ -147,6 +153,23 @@ def fp8_scales(params, width: int) -> np.ndarray:
     out = np.zeros(9)
     lib().orc_fp8_scales(_f64(params), width, out)
     return out
+
+
+def to_bf16(x) -> np.ndarray:
+    """BF16 round-to-nearest-even of float32(x), elementwise."""
+    f = np.vectorize(lambda v: lib().orc_to_bf16(float(v)), otypes=[np.float64])
+    return f(np.asarray(x, np.float64))
+
+
+def to_e4m3(x) -> np.ndarray:
+    """OCP E4M3 round-to-nearest-even with saturation at 448, elementwise."""
+    f = np.vectorize(lambda v: lib().orc_to_e4m3(float(v)), otypes=[np.float64])
+    return f(np.asarray(x, np.float64))
+
+
+def lr_schedule(lr: float, lr_final: float, T: int, t: int) -> float:
+    """Learning rate of step t of T under the warm-up + exponential decay schedule (Sec. 4.1)."""
+    return float(lib().orc_lr_schedule(lr, lr_final, T, t))
 
 
 def sh_basis(d, degree: int = 3) -> np.ndarray:

@@ -725,6 +725,27 @@ void orc_mlp_forward_q(const double* P, int W, const double* X, int64_t B, int p
   }
 }
 
+// The two roundings on their own (for the pins of the reduced-precision checker).
+double orc_to_bf16(double x) { return to_bf16(x); }
+double orc_to_e4m3(double x) { return to_e4m3(x); }
+
+// Learning rate of step t (0-based) of a T-step run under the schedule of
+// Sec. 4.1: the rate rises along a cosine from 0 to lr over the first 20 % of
+// the iterations (Tw = max(1, round(0.2 T)) steps; step t < Tw uses the
+// warm-up curve evaluated at the end of the step, (t + 1) / Tw, so the last
+// warm-up step runs at lr), then decays exponentially from lr at step Tw to
+// lr_final at the last step T - 1 (a fixed ratio per step).
+double orc_lr_schedule(double lr, double lr_final, int64_t T, int64_t t) {
+  const int64_t Tw = std::max<int64_t>(1, (int64_t)std::llround(0.2 * (double)T));
+  if (t < Tw) {
+    const double phase = (double)(t + 1) / (double)Tw;  // in (0, 1]
+    return lr * 0.5 * (1.0 - std::cos(kPi * phase));
+  }
+  if (T - Tw <= 1) return lr_final;  // a single decay step ends at lr_final
+  const double frac = (double)(t - Tw) / (double)(T - 1 - Tw);  // 0 at Tw, 1 at T - 1
+  return lr * std::pow(lr_final / lr, frac);
+}
+
 // SplitMix64 (Steele, Lea and Flood, OOPSLA 2014) evaluated at counter i:
 // the i-th output of the generator seeded with `seed`.
 uint64_t orc_splitmix64(uint64_t seed, uint64_t i) {
