@@ -148,14 +148,50 @@ def time_frames(ctx, sc, steps, warmup, **kw):
     return (t1 - t0) / steps, dict(zip(names, (stage / steps).tolist())), last, img
 
 
+def algorithmic_bytes(stage, st, sh_degree):
+    """HBM bytes a memory-bound stage must move, per the method's data (the
+    per-unit figures of the design notes): projection 56 B (SH 0) or 236 B
+    (SH 3) of Gaussian read + a 48 B splat record written per kept splat; the
+    depth sort of the splats 4 passes x 16 B (4 B key + 4 B id, read and
+    written) per splat; binning 8 B per (tile, splat) entry written; the
+    stable tile sort 2 passes x 16 B per entry."""
+    if stage == "project":
+        return st["kept"] * (44 + 12 * (sh_degree + 1) ** 2 + 48)
+    if stage == "depth_sort":
+        return st["kept"] * 64
+    if stage == "bin":
+        return st["duplicates"] * 8
+    if stage == "tile_sort":
+        return st["duplicates"] * 32
+    return None
+
+
+def implementation_bytes(stage, st, sh_degree, n_keys_tiles):
+    """Bytes the kernels as built move: the projection's 48 B geometry record
+    + SH row (rounded to 16 B) read and its 64 B compositing record, 16 B
+    rectangle and 4 B depth key written; a radix pass 4 B histogram + 8 B read
+    + 8 B written per key; binning 72 B per splat (gather, count scan,
+    rectangle re-read) + 8 B per entry; the tile stage its radix passes + 4 B
+    per entry for the ranges."""
+    if stage == "project":
+        return st["kept"] * (48 + 4 * (-(-3 * (sh_degree + 1) ** 2 // 4) * 4) + 84)
+    if stage == "depth_sort":
+        return st["kept"] * 4 * 20
+    if stage == "bin":
+        return st["kept"] * 72 + st["duplicates"] * 8
+    if stage == "tile_sort":
+        passes = max(1, -(-max(1, int(n_keys_tiles - 1).bit_length()) // 8))
+        return st["duplicates"] * (20 * passes + 4)
+    return None
+
+
 def stage_roof(stage, ms, st, width, precision, sh_degree, n_keys_tiles):
-    """Roofline of one frame stage from its algorithmic work per launch:
-    MLP FLOP per queried pair; bytes for the memory-bound stages (projection:
-    48 B geometry + the SH row (rounded to 16 B) read and 84 B written per
-    kept splat; a radix pass: 4 B histogram read + 8 B read + 8 B written per
-    key; binning: 72 B per splat (gather, count scan, rectangle re-read) + 8 B
-    per tile entry; the tile stage: its radix passes + 4 B per entry for the
-    ranges); fragment tests for the blend (about 20 VALU lane-slots each)."""
+    """Roofline of one frame stage from its algorithmic work per launch: MLP
+    FLOP per queried pair (layers 2, 3 and the output; layer 1's camera half
+    is per (camera, instance) and its Gaussian half per 256-Gaussian chunk,
+    both shared by many queries and not counted); fragment tests for the blend
+    (about 20 VALU lane-slots each); algorithmic_bytes() for the memory-bound
+    stages, with the implementation's own bytes beside them."""
     sec = ms * 1e-3
     if sec <= 0:
         return None
@@ -167,28 +203,23 @@ def stage_roof(stage, ms, st, width, precision, sh_degree, n_keys_tiles):
         a = st["blend_tests"] / sec / 1e9
         return {"bound": "alu", "achieved": a, "peak": BLEND_PEAK_GTESTS, "unit": "Gtests/s",
                 "frac": a / BLEND_PEAK_GTESTS}
-    if stage == "project":
-        nb = st["kept"] * (48 + 4 * (-(-3 * (sh_degree + 1) ** 2 // 4) * 4) + 84)
-    elif stage == "depth_sort":
-        nb = st["kept"] * 4 * 20
-    elif stage == "bin":
-        nb = st["kept"] * 72 + st["duplicates"] * 8
-    elif stage == "tile_sort":
-        passes = max(1, -(-max(1, int(n_keys_tiles - 1).bit_length()) // 8))
-        nb = st["duplicates"] * (20 * passes + 4)
-    else:
+    nb = algorithmic_bytes(stage, st, sh_degree)
+    if nb is None:
         return None
     a = nb / sec / 1e9
-    return {"bound": "hbm", "achieved": a, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": a / HBM_PEAK_GBS}
+    ib = implementation_bytes(stage, st, sh_degree, n_keys_tiles) / sec / 1e9
+    return {"bound": "hbm", "achieved": a, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": a / HBM_PEAK_GBS,
+            "impl_achieved": ib, "impl_frac": ib / HBM_PEAK_GBS}
 
 
-def roofline(stage_ms, st, width, precision, sh_degree, n_keys_tiles):
+def roofline(stage_ms, st, width, precision, sh_degree, n_keys_tiles, workload="composed1080p"):
     """Roofline of the dominant kernel stage (see stage_roof), with the HBM
-    traffic measured for its kernel when the committed counters match the
-    source."""
+    traffic measured for its kernel on this workload when the committed
+    counters match the source."""
     dom = max(stage_ms, key=stage_ms.get)
-    r = dict(stage_roof(dom, stage_ms[dom], st, width, precision, sh_degree, n_keys_tiles))
-    r["traffic"] = measured_traffic(dom) if dom in ("cull_mlp", "project", "blend") else None
+    r = {k: v for k, v in stage_roof(dom, stage_ms[dom], st, width, precision, sh_degree, n_keys_tiles).items()
+         if not k.startswith("impl_")}
+    r["traffic"] = measured_traffic(dom, workload)
     return dom, r
 
 
@@ -199,38 +230,65 @@ def stage_rooflines(stage_ms, st, width, precision, sh_degree, n_keys_tiles):
         if r:
             out[k] = {"bound": r["bound"], "frac": round(r["frac"], 4), "achieved": round(r["achieved"], 2),
                       "unit": r["unit"]}
+            if "impl_frac" in r:
+                out[k]["impl_frac"] = round(r["impl_frac"], 4)
     return out
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, or None when the kernel source changed since it was measured."""
+def measured_traffic(stage, workload):
+    """HBM bytes per launch of the stage's kernel(s) on `workload` from the
+    committed rocprofv3 counter summary, or None when none was measured for
+    that workload or the kernel source changed since."""
     import hashlib
     try:
-        t = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))[kernel]
+        t = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))[workload][stage]
         cur = hashlib.sha256(open(os.path.join(ROOT, t["source"]), "rb").read()).hexdigest()
         return t["fetch_bytes"] + t["write_bytes"] if cur == t["source_sha256"] else None
     except (OSError, KeyError, ValueError):
         return None
 
 
-def cpu_baseline(sc, img_culled, every=1):
-    """The FP64 oracle on one full culled frame of the scene (every `every`-th
-    instance if `every` > 1, the time then scaled by the pair-count ratio);
-    its unculled frame gives the PSNR of the GPU's culled image against the
-    FP64 reference."""
+def host_cpu():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
+
+
+def cpu_baseline(sc, img_culled, every=1, every_1core=8):
+    """The FP64 oracle timed on the host: on all cores, one full culled frame
+    of the scene (every `every`-th instance if `every` > 1, the time then
+    scaled by the pair-count ratio); on one core, every `every_1core`-th
+    instance of that sample, scaled likewise.  The all-core run's unculled
+    frame gives the PSNR of the GPU's culled image against the FP64
+    reference."""
     import oracle
     import synth
-    sub = synth.Scene(assets=sc.assets, instances=sc.instances[::every], cameras=sc.cameras, tile=sc.tile)
-    t0 = time.perf_counter()
-    oracle.frame(sub, use_mlp=True, want_margin=False)
-    dt = time.perf_counter() - t0
-    scale = sc.pairs_per_camera / sub.pairs_per_camera
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    out = {"value": 1.0 / (dt * scale), "unit": "frames/s", "cores": threads, "kind": "oracle",
-           "sample": f"{len(sub.instances)} of {len(sc.instances)} instances, one full culled "
-                     f"{sc.cameras[0].width}x{sc.cameras[0].height} frame in {dt:.1f} s"
-                     + (f", scaled x{scale:.1f} by pair count" if every > 1 else "")}
+
+    def timed(step, threads):
+        used = oracle.set_threads(threads)
+        sub = synth.Scene(assets=sc.assets, instances=sc.instances[::step], cameras=sc.cameras, tile=sc.tile)
+        t0 = time.perf_counter()
+        oracle.frame(sub, use_mlp=True, want_margin=False)
+        dt = time.perf_counter() - t0
+        return used, dt, sc.pairs_per_camera / sub.pairs_per_camera, len(sub.instances)
+
+    res = f"{sc.cameras[0].width}x{sc.cameras[0].height}"
+    used, dt, scale, ni = timed(every, 0)
+    out = {"value": 1.0 / (dt * scale), "unit": "frames/s", "cores": used, "kind": "oracle",
+           "sample": f"{ni} of {len(sc.instances)} instances, one full culled {res} frame in {dt:.1f} s on "
+                     f"{used} threads" + (f", scaled x{scale:.1f} by pair count" if every > 1 else "")}
+    used1, dt1, scale1, ni1 = timed(every * every_1core, 1)
+    out["single_core"] = {"value": 1.0 / (dt1 * scale1), "unit": "frames/s", "cores": used1,
+                          "sample": f"{ni1} of {len(sc.instances)} instances of the culled {res} frame in "
+                                    f"{dt1:.1f} s on one thread, scaled x{scale1:.1f} by pair count"}
+    out["host"] = host_cpu()
+    oracle.set_threads(0)
     if every == 1:
         ref = oracle.frame(sc, use_mlp=False, want_margin=False)["images"][0]
         out["psnr_gpu_culled_vs_fp64_unculled_db"] = psnr(img_culled[0], ref)
@@ -623,7 +681,7 @@ def main_batched(args):
     width = sc.assets[0].mlp.width
     cam0 = sc.cameras[0]
     nkt = len(sc.cameras) * (-(-cam0.width // tile)) * (-(-cam0.height // tile))
-    dom, roof = roofline(stage, st, width, prec, sc.assets[0].sh_degree, nkt)
+    dom, roof = roofline(stage, st, width, prec, sc.assets[0].sh_degree, nkt, workload="batched8x1080p")
     stage_roofs = stage_rooflines(stage, st, width, prec, sc.assets[0].sh_degree, nkt)
     C = len(sc.cameras)
     out = {
@@ -744,10 +802,10 @@ def main_precision(args):
     flip rate against the FP64 MLP and the PSNR against the unculled FP64
     render (both from the oracle, in the cpu_baseline leg) -- and the MLP
     kernel alone on the composed scene's 16M pairs, where it fills the GPU:
-    queries/s and the fraction of the MFMA peak of each precision.  The
-    width-64 MLP is trained (the differentiation workload's recipe at 20k
-    Gaussians); training supports width 64 only, so width 128 uses seeded
-    weights with the output bias set to keep 65 % of the in-frustum pairs."""
+    queries/s and the fraction of the MFMA peak of each precision.  Both
+    widths are trained with the differentiation workload's recipe at 20k
+    Gaussians (unless --mlp random: seeded weights with the output bias set
+    to keep 65 % of the in-frustum pairs)."""
     import torch
     import paper_2511_19202_amd as nvgs
     import synth
@@ -759,7 +817,7 @@ def main_precision(args):
         ctx = nvgs.Context(0)
         ctx.load_assets(sc.assets)
         ctx.set_instances(sc.instances)
-        if W == 64 and args.mlp == "trained":
+        if args.mlp == "trained":
             train_assets(ctx, sc, views=512, res=512, batch=65536, steps=args.train_steps, recipe="workload")
             how = "trained"
         else:

@@ -74,6 +74,10 @@ def lib():
         L.orc_to_e4m3.restype = C.c_double
         L.orc_lr_schedule.argtypes = [C.c_double, C.c_double, C.c_int64, C.c_int64]
         L.orc_lr_schedule.restype = C.c_double
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_set_threads.restype = None
+        L.orc_max_threads.argtypes = []
+        L.orc_max_threads.restype = C.c_int
         L.orc_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
         L.orc_splitmix64.restype = C.c_uint64
         L.orc_compact_sizes.argtypes = [C.c_int]
@@ -165,6 +169,12 @@ def to_e4m3(x) -> np.ndarray:
     """OCP E4M3 round-to-nearest-even with saturation at 448, elementwise."""
     f = np.vectorize(lambda v: lib().orc_to_e4m3(float(v)), otypes=[np.float64])
     return f(np.asarray(x, np.float64))
+
+
+def set_threads(n: int) -> int:
+    """Threads of the oracle's parallel loops (n <= 0: all processors); returns the count now in use."""
+    lib().orc_set_threads(int(n))
+    return int(lib().orc_max_threads())
 
 
 def lr_schedule(lr: float, lr_final: float, T: int, t: int) -> float:

@@ -725,6 +725,23 @@ void orc_mlp_forward_q(const double* P, int W, const double* X, int64_t B, int p
   }
 }
 
+// OpenMP threads of the parallel loops (for timing the oracle on 1 core and on
+// all cores); results do not depend on it.
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  omp_set_num_threads(n > 0 ? n : omp_get_num_procs());
+#else
+  (void)n;
+#endif
+}
+int orc_max_threads() {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
 // The two roundings on their own (for the pins of the reduced-precision checker).
 double orc_to_bf16(double x) { return to_bf16(x); }
 double orc_to_e4m3(double x) { return to_e4m3(x); }
