@@ -352,6 +352,20 @@ nvgs_status nvgs_mlp_forward(nvgs_ctx* ctx, const float* params, int32_t width, 
 nvgs_status nvgs_mlp_backward(nvgs_ctx* ctx, const float* params, int32_t width, const float* X, int64_t B,
                               const float* dlogits, int32_t precision, float* dparams, float* dX);
 
+/* nvgs_mlp_backward without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, kernels and results (bit-identical) as
+ * nvgs_mlp_backward; the per-work-group gradient partials live in a fixed
+ * 16 MiB device workspace that each GPU holds from library load until the
+ * process ends.  B must be <= NVGS_NOALLOC_MAX_BATCH (E_INVALID otherwise).
+ * Every call on a device shares that device's workspace: calls that overlap
+ * in time on one device (other streams or contexts) race and give undefined
+ * results; calls on one stream are ordered and safe.  The workspace keeps the
+ * last call's contents; nothing in it needs clearing between calls. */
+#define NVGS_NOALLOC_MAX_BATCH 65536
+nvgs_status nvgs_mlp_backward_noalloc(nvgs_ctx* ctx, const float* params, int32_t width, const float* X, int64_t B,
+                                      const float* dlogits, int32_t precision, float* dparams, float* dX);
+
 /* The compact model (Sec. 3.2, 3.3, 4.1) as one function of its raw inputs,
  * for automatic differentiation frameworks.  X: device [B][18]: the ten
  * per-pair visibility inputs (mean_scale * mu, unit direction camera ->

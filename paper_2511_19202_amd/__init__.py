@@ -125,6 +125,8 @@ _SIGS = {
                          C.c_int32),
     "nvgs_mlp_backward": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p, C.c_int32,
                            C.c_void_p, C.c_void_p], C.c_int32),
+    "nvgs_mlp_backward_noalloc": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p, C.c_int32,
+                                   C.c_void_p, C.c_void_p], C.c_int32),
     "nvgs_cmlp_forward": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p], C.c_int32),
     "nvgs_cmlp_backward": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int32, C.c_void_p],
                            C.c_int32),
@@ -465,6 +467,13 @@ def _train_methods():
                                              _ptr(dx)))
         return dp, dx
 
+    def mlp_backward_noalloc(self, params, X, dlogits, dparams, dx=None, precision="fp32"):
+        """nvgs_mlp_backward into caller-provided outputs, with no device allocation."""
+        self._check(self.L.nvgs_mlp_backward_noalloc(self.h, params.data_ptr(), 64, X.data_ptr(), X.shape[0],
+                                                     dlogits.data_ptr(), _PREC.get(precision, precision),
+                                                     dparams.data_ptr(), _ptr(dx)))
+        return dparams, dx
+
     def cmlp_forward(self, params, X, precision="fp32"):
         """Logits of the compact model on raw inputs X [B, 18]."""
         z = torch.empty(X.shape[0], dtype=torch.float32, device=self.device)
@@ -482,6 +491,7 @@ def _train_methods():
     Context.train_visibility = train_visibility
     Context.mlp_forward = mlp_forward
     Context.mlp_backward = mlp_backward
+    Context.mlp_backward_noalloc = mlp_backward_noalloc
     Context.cmlp_forward = cmlp_forward
     Context.cmlp_backward = cmlp_backward
 

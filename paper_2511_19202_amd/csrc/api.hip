@@ -315,6 +315,8 @@ nvgs_status nvgs_create(const nvgs_create_info* info, nvgs_ctx** out) {
   if (info->device < 0 || info->device >= ndev) return NVGS_E_INVALID;
   if ((info->allocator.alloc == nullptr) != (info->allocator.free == nullptr)) return NVGS_E_INVALID;
   if (hipSetDevice(info->device) != hipSuccess) return NVGS_E_DEVICE;
+  // address of this device's fixed workspace (allocation-free backward)
+  if (static_scratch_init(info->device) != hipSuccess) return NVGS_E_DEVICE;
   nvgs_ctx* ctx = new nvgs_ctx();
   ctx->device = info->device;
   ctx->stream = reinterpret_cast<hipStream_t>(info->stream);
@@ -1293,6 +1295,31 @@ nvgs_status nvgs_mlp_backward(nvgs_ctx* ctx, const float* params, int32_t width,
   const int np = train_num_params();
   float* part = part_t.get<float>((size_t)nwg * np + reduce_scratch_floats(nwg, np));
   if (!part) return fail(ctx, NVGS_E_NOMEM, "gradient partials");
+  CK(launch_mlp_train(2, precision == NVGS_PREC_BF16, nwg, kTrainChunksPerWG, ctx->stream, params, B, 1.f, nullptr,
+                      1, 0.f, nullptr, 1, nullptr, 0, 0, nullptr, X, dlogits, nullptr, part, nullptr, dX));
+  CK(launch_reduce_adam_n(part, nwg, np, nullptr, nullptr, nullptr, dparams, 0.f, 0.f, 0.f, 1.f, 1, nullptr, 0.f,
+                          nullptr, ctx->stream, part + (size_t)nwg * np));
+  return NVGS_OK;
+}
+
+nvgs_status nvgs_mlp_backward_noalloc(nvgs_ctx* ctx, const float* params, int32_t width, const float* X, int64_t B,
+                                      const float* dlogits, int32_t precision, float* dparams, float* dX) {
+  if (!ctx) return NVGS_E_INVALID;
+  if (!params || !X || !dlogits || !dparams || B < 1)
+    return fail(ctx, NVGS_E_INVALID, "mlp_backward_noalloc: null pointer or B < 1");
+  if (B > NVGS_NOALLOC_MAX_BATCH)
+    return fail(ctx, NVGS_E_INVALID, "mlp_backward_noalloc: B exceeds NVGS_NOALLOC_MAX_BATCH (65536)");
+  nvgs_status s = check_train_prec(ctx, precision, width);
+  if (s) return s;
+  CK(hipSetDevice(ctx->device));
+  size_t cap = 0;
+  float* part = static_scratch(ctx->device, &cap);
+  if (!part) return fail(ctx, NVGS_E_STATE, "mlp_backward_noalloc: workspace address of this device not looked up");
+  // the same partition and kernels as nvgs_mlp_backward, so the results are identical
+  const int nwg = (int)((B + kPairsPerWG - 1) / kPairsPerWG);
+  const int np = train_num_params();
+  const size_t need = (size_t)nwg * np + reduce_scratch_floats(nwg, np);
+  if (need > cap) return fail(ctx, NVGS_E_INVALID, "mlp_backward_noalloc: batch needs more than the fixed workspace");
   CK(launch_mlp_train(2, precision == NVGS_PREC_BF16, nwg, kTrainChunksPerWG, ctx->stream, params, B, 1.f, nullptr,
                       1, 0.f, nullptr, 1, nullptr, 0, 0, nullptr, X, dlogits, nullptr, part, nullptr, dX));
   CK(launch_reduce_adam_n(part, nwg, np, nullptr, nullptr, nullptr, dparams, 0.f, 0.f, 0.f, 1.f, 1, nullptr, 0.f,

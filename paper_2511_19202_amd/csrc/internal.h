@@ -200,12 +200,18 @@ hipError_t launch_count_pos(int64_t batch, int64_t n, int V, const uint32_t* lab
 hipError_t launch_reduce_adam(const float* partial, int nwg, float* params, float* m, float* v, float* grad_out,
                               float lr, float b1, float b2, float eps, int64_t t, const float* loss_part,
                               float inv_batch, float* loss_out, hipStream_t st);
-// scratch (nullable, reduce_scratch_floats(nwg, np) floats) enables a two-level sum
+// slices (nullable, reduce_scratch_floats(nwg, np) floats) enables a two-level sum
 size_t reduce_scratch_floats(int nwg, int np);
 hipError_t launch_reduce_adam_n(const float* partial, int nwg, int np, float* params, float* m, float* v,
                                 float* grad_out, float lr, float b1, float b2, float eps, int64_t t,
                                 const float* loss_part, float inv_batch, float* loss_out, hipStream_t st,
-                                float* scratch);
+                                float* slices);
+// Fixed per-device workspace (16 MiB) of the allocation-free backward: the
+// address is looked up once per device (static_scratch_init, with that device
+// made current for the lookup); static_scratch returns it (NULL before the
+// lookup) and its size in floats.
+hipError_t static_scratch_init(int device);
+float* static_scratch(int device, size_t* floats);
 
 // training of the compact form (k_ctrain.hip)
 struct CTrainArgs {

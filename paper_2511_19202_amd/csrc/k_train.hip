@@ -15,8 +15,17 @@
 // it is staged, so the FP32 MFMA forms the same exact products as a BF16
 // MFMA with FP32 accumulation.
 #include <algorithm>
+#include <mutex>
 
 #include "internal.h"
+
+// Fixed device workspace of the allocation-free backward entry point: the
+// per-work-group gradient partials and the slices of their two-level sum.
+// Each device the library runs on holds its own copy until the process ends.
+// Host code never passes this name to a kernel (on the host it is only a
+// stand-in for the symbol): it uses the address looked up per device below.
+static constexpr size_t kStaticScratchFloats = size_t(1) << 22;  // 16 MiB
+static __device__ __align__(256) float scratch[kStaticScratchFloats];
 
 namespace nvgs {
 
@@ -518,12 +527,12 @@ size_t reduce_scratch_floats(int nwg, int np) { return nwg > 2 * kSlices ? (size
 hipError_t launch_reduce_adam_n(const float* partial, int nwg, int np, float* params, float* m, float* v,
                                 float* grad_out, float lr, float b1, float b2, float eps, int64_t t,
                                 const float* loss_part, float inv_batch, float* loss_out, hipStream_t st,
-                                float* scratch) {
+                                float* slices) {
   const float c1 = 1.f - powf(b1, (float)t), c2 = 1.f - powf(b2, (float)t);
-  if (scratch && reduce_scratch_floats(nwg, np) > 0) {
+  if (slices && reduce_scratch_floats(nwg, np) > 0) {
     // two levels: kSlices contiguous slices of the partials, then the slices in order
-    float* tmp = scratch;
-    float* tmp_loss = scratch + (size_t)kSlices * np;
+    float* tmp = slices;
+    float* tmp_loss = slices + (size_t)kSlices * np;
     hipLaunchKernelGGL(k_reduce_slices, dim3((np + 255) / 256, kSlices), dim3(256), 0, st, partial, nwg, np, kSlices,
                        loss_part, tmp, tmp_loss);
     partial = tmp;
@@ -533,6 +542,36 @@ hipError_t launch_reduce_adam_n(const float* partial, int nwg, int np, float* pa
   hipLaunchKernelGGL(k_reduce_adam, dim3((np + 255) / 256), dim3(256), 0, st, partial, nwg, np, params, m, v,
                      grad_out, lr, b1, b2, eps, c1, c2, loss_part, inv_batch, loss_out);
   return hipGetLastError();
+}
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t static_scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  int cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return e;
+  if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+  void* p = nullptr;
+  e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (cur != device) (void)hipSetDevice(cur);
+  if (e != hipSuccess) return e;
+  if (!p) return hipErrorInvalidSymbol;
+  g_scratch_ptr[device] = static_cast<float*>(p);
+  return hipSuccess;
+}
+
+float* static_scratch(int device, size_t* floats) {
+  if (floats) *floats = kStaticScratchFloats;
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[device];
 }
 
 hipError_t launch_reduce_adam(const float* partial, int nwg, float* params, float* m, float* v, float* grad_out,
