@@ -9,7 +9,10 @@ cameras uploaded before each replay).
 --workload composed (default): the composed 1080p scene, 4 assets (torus,
 sphere shell, box shell, helix tube) of 250,000 SH-degree-3 Gaussians each,
 64 instances with random yaw, scale U(0.5, 2) and positions on a 40 x 40
-ground plane, one camera, one width-64 FP32 visibility MLP per asset.
+ground plane, one camera, one width-64 FP32 visibility MLP per asset (run as
+the split FP32 form: three BF16 matrix-core products per FP32 product, held
+to the FP32 logit tolerance; the FP32-matrix-core form, BF16 and FP8 are
+timed beside it).
 
 --workload batched: 16 assets of log-uniform sizes in [50k, 1M] (SH 3),
 1,024 instances with Zipf counts per asset on a 160 x 160 plane, 8 cameras at
@@ -45,7 +48,13 @@ FLOP_PER_QUERY = {64: 2 * (2 * 64 * 64 + 64), 128: 2 * (2 * 128 * 128 + 128)}
 # compact form per queried pair: the per-pair part of layer 1 (4 inputs), layer 2 and the output
 FLOP_PER_QUERY[32] = 2 * (4 * 32 + 32 * 32 + 32)
 COMPACT_BO = 32 * 16 + 32 + 32 * 32 + 32 + 32  # index of the compact form's output bias
-MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0}
+# dense MFMA peaks; the split FP32 form issues three BF16 products per FP32
+# product, so its FP32-equivalent peak is a third of the BF16 one
+MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0, "fp32s": 2500.0 / 3}
+MLP_ARITH = {"fp32": "FP32 operands on FP32 matrix cores",
+             "fp32s": "FP32 MLP on BF16 matrix cores: each FP32 operand split into two BF16 parts, three products "
+                      "per FP32 product, FP32 accumulation (logits within 1e-5 of the FP64 oracle's logit scale)",
+             "bf16": "BF16 operands, FP32 accumulation", "fp8": "FP8 E4M3 operands, per-layer scales, FP32 accumulation"}
 HBM_PEAK_GBS = 8000.0
 VALU_LANE_OPS = 256 * 64 * 2.4e9          # non-packed FP32 lane-ops per second
 BLEND_SLOTS_PER_TEST = 20
@@ -355,7 +364,9 @@ def parse():
                          "radius-clipped")
     ap.add_argument("--det-clip", type=float, default=0.1, help="sweep, ablation: radius-clipping threshold (px^4)")
     ap.add_argument("--tile", type=int, default=0, help="8, 16, 32, or 0 to autotune (tile and MLP block shape)")
-    ap.add_argument("--precision", default=None, help="MLP precision (default fp32 composed, bf16 batched)")
+    ap.add_argument("--precision", default=None,
+                    help="MLP precision: fp32s (FP32 via split BF16 products), fp32, bf16, fp8 (default fp32s "
+                         "composed, bf16 batched)")
     ap.add_argument("--mlp", default="trained", choices=["trained", "random"],
                     help="trained: per-asset MLPs trained on renderer labels; random: seeded weights with the "
                          "output bias set to keep --keep of the in-frustum pairs")
@@ -373,8 +384,8 @@ def parse():
                     help="composed, sweep, ablation: flat surface-aligned Gaussians instead of random orientations")
     ap.add_argument("--compact-steps", type=int, default=0,
                     help="training steps of the compact form (0: --train-steps)")
-    ap.add_argument("--extra-precisions", default="bf16,fp8",
-                    help="comma list of reduced-precision MLP forms timed beside the FP32 one")
+    ap.add_argument("--extra-precisions", default="fp32,bf16,fp8",
+                    help="comma list of MLP forms timed beside the headline one")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many bytes (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -409,7 +420,7 @@ def main():
     import paper_2511_19202_amd as nvgs
     import synth
 
-    prec = args.precision or "fp32"
+    prec = args.precision or "fp32s"
     sc = synth.scene_composed(n_per_asset=args.n, aligned=args.aligned)
     ctx = nvgs.Context(0)
     ctx.load_assets(sc.assets)
@@ -444,8 +455,8 @@ def main():
             t_p, _ = time_graph(ctx, [sc.cameras], args.steps, args.warmup, use_mlp=True, tile=tile, precision=p2)
             check_no_overflow(ctx)
             _, stage_p, st_p, img_p = time_frames(ctx, sc, 5, 1, use_mlp=True, tile=tile, precision=p2)
-            extra[p2] = {"fps": 1.0 / t_p, "ms_cull_mlp": stage_p["cull_mlp"],
-                         "psnr_vs_fp32_culled_db": psnr(img_p.cpu().numpy(), img_c),
+            extra[p2] = {"fps": 1.0 / t_p, "ms_cull_mlp": stage_p["cull_mlp"], "mlp_arith": MLP_ARITH.get(p2),
+                         "psnr_vs_headline_culled_db": psnr(img_p.cpu().numpy(), img_c),
                          "psnr_vs_unculled_db": psnr(img_p.cpu().numpy(), img_u),
                          "kept": st_p["kept"]}
         except Exception as e:  # report, do not hide
@@ -469,6 +480,7 @@ def main():
                    "gaussian_orientation": "surface-aligned discs" if args.aligned else "random",
                    "gaussians_stored": sum(a.n for a in sc.assets), "instances": len(sc.instances),
                    "pairs": st_c["pairs"], "resolution": "1920x1080", "mlp_precision": prec,
+                   "mlp_arith": MLP_ARITH.get(prec),
                    "tile": tile, "mlp_shape": list(ctx.mlp_shape), "autotune": tune, "mlp": args.mlp,
                    "keep_target": args.keep if args.mlp == "random" else None, "frame": "persistent (HIP graph)"},
         "fps_unculled": 1.0 / t_u,
@@ -810,7 +822,7 @@ def main_precision(args):
     import paper_2511_19202_amd as nvgs
     import synth
 
-    precs = ("fp32", "bf16", "fp8")
+    precs = ("fp32", "fp32s", "bf16", "fp8")
     tiny_rows, keep = [], {}
     for W in (64, 128):
         sc = synth.scene_tiny(n=20000, res=256, width=W)

@@ -54,6 +54,13 @@ typedef int32_t nvgs_status;
 #define NVGS_PREC_FP32 0 /* MLP operands in FP32, FP32 accumulation */
 #define NVGS_PREC_BF16 1 /* MLP operands in BF16 (round to nearest even), FP32 accumulation */
 #define NVGS_PREC_FP8 2  /* MLP operands in OCP FP8 E4M3 with per-layer scales, FP32 accumulation */
+/* FP32 MLP on BF16 matrix cores: every FP32 operand x of the hidden layers is
+ * split into x_hi = bf16(x) and x_lo = bf16(x - x_hi), and each product is
+ * formed as a_hi b_hi + a_hi b_lo + a_lo b_hi with FP32 accumulation (the
+ * dropped a_lo b_lo and the split's residuals are below 2^-16 relative); layer
+ * 1 and the output layer stay in FP32.  Logits meet the FP32 contract (1e-5
+ * relative to the logit scale).  Frequency form only. */
+#define NVGS_PREC_FP32_SPLIT 3
 
 #define NVGS_RENDER_RECORD_CONTRIB 1u /* write per-pair max alpha*T into opts->contrib */
 #define NVGS_RENDER_KEEP_DEBUG 2u     /* keep per-splat debug arrays (nvgs_debug_buffers) */
@@ -144,7 +151,11 @@ typedef struct nvgs_render_opts {
   uint32_t flags;    /* NVGS_RENDER_* */
   float* contrib;    /* device [C][P] (P = pairs per camera, instance-major) or NULL;
                         with RECORD_CONTRIB the max alpha*T of every blended fragment
-                        of each pair is max-accumulated into it (caller zero-fills) */
+                        of each pair is max-accumulated into it (caller zero-fills);
+                        a fragment tested with alpha >= 1/255 whose blend would take T
+                        below 1e-4 (the stop, Sec. 4.1) is reached but not blended and
+                        records the smallest positive float (bit pattern 1), so
+                        contrib > 0 marks exactly the pairs reached before the stop */
   int32_t split_len; /* tile lists longer than this are composited in chunks of at most
                         this many entries by separate work-groups, which equals the
                         sequential composite up to rounding (the association of the
@@ -193,6 +204,7 @@ typedef struct nvgs_debug_view {
   const uint32_t* sorted_id;  /* [n_dup] splat id, (depth, id) order within a tile */
   const uint32_t* ranges;  /* [C * n_tiles][2] start, end into the sorted arrays */
   int32_t tiles_x, tiles_y;
+  const float* rec_d;      /* [n_splats][2]: low-order parts of u and v (the centre is u + u_lo; KEEP_DEBUG only) */
 } nvgs_debug_view;
 
 /* Block shape of the cull + visibility-MLP kernel.  A work-group covers 256
@@ -306,7 +318,9 @@ nvgs_status nvgs_debug_buffers(nvgs_ctx* ctx, nvgs_debug_view* out);
  * view renders a single identity instance of the asset with frustum culling
  * only and records, per Gaussian, the largest contribution alpha*T of its
  * blended fragments; the label is contribution > threshold (1/255 for a
- * non-zero 8-bit contribution).  views: host [V], equal sizes.
+ * non-zero 8-bit contribution; threshold must exceed the smallest normal
+ * float, below which the "reached but not blended" marker of RECORD_CONTRIB
+ * lies).  views: host [V], equal sizes.
  * labels: device [V][ceil(n/32)] bit words (bit g%32 of word g/32), written.
  * With aux > 0 (at most 64) each view also renders `aux` auxiliary views:
  * the view rotated rigidly about the asset centre by aux_angle (radians)
@@ -326,9 +340,10 @@ nvgs_status nvgs_make_labels(nvgs_ctx* ctx, int32_t asset, const nvgs_camera* vi
  * view ((r >> 32) V) >> 32.  Loss: mean BCE with logits against the labels
  * (labels == NULL: made here with opts->threshold and opts->tile).  Adam
  * (beta1, beta2, eps, bias-corrected, lr per opts->schedule) on FP32 master weights.
- * precision NVGS_PREC_BF16 rounds every GEMM operand of the forward and
- * backward pass to BF16 (FP32 accumulation); NVGS_PREC_FP32 keeps FP32.
- * Frequency-encoded assets (nvgs_mlp.kind 0) need width 64.  Compact assets
+ * precision NVGS_PREC_BF16 runs every GEMM of the forward and backward pass
+ * on BF16 operands with FP32 accumulation (BF16 matrix cores for the
+ * frequency form); NVGS_PREC_FP32 keeps FP32.
+ * Frequency-encoded assets (nvgs_mlp.kind 0) have width 64 or 128.  Compact assets
  * (kind 1, Sec. 3.2, 3.3, 4.1) train the embedding MLP and the visibility MLP
  * jointly (all 3175 parameters): each pair's inputs are those of the query
  * with the view as camera of an identity instance, the embedding computed
@@ -341,13 +356,14 @@ nvgs_status nvgs_train_visibility(nvgs_ctx* ctx, int32_t asset, const nvgs_camer
                                   const uint32_t* labels, const nvgs_train_opts* opts, float* params,
                                   float* loss_curve);
 
-/* MLP on encoded inputs, for automatic differentiation frameworks (width 64).
- * X: device [B][72] encoded inputs; logits: device [B].  precision as in
- * nvgs_train_visibility. */
+/* MLP on encoded inputs, for automatic differentiation frameworks (width 64
+ * or 128).  X: device [B][72] encoded inputs; logits: device [B].  precision
+ * as in nvgs_train_visibility. */
 nvgs_status nvgs_mlp_forward(nvgs_ctx* ctx, const float* params, int32_t width, const float* X, int64_t B,
                              int32_t precision, float* logits);
 /* Vector-Jacobian product: dparams[p] = sum_b dlogits[b] dz_b/dparams[p]
- * (device [13057], overwritten) and, if dX != NULL, dX[b][k] = dlogits[b]
+ * (device [13057] at width 64, [42497] at width 128, overwritten) and, if
+ * dX != NULL, dX[b][k] = dlogits[b]
  * dz_b/dX[b][k] (device [B][72]).  The sum over b runs in a fixed order. */
 nvgs_status nvgs_mlp_backward(nvgs_ctx* ctx, const float* params, int32_t width, const float* X, int64_t B,
                               const float* dlogits, int32_t precision, float* dparams, float* dX);
@@ -357,12 +373,14 @@ nvgs_status nvgs_mlp_backward(nvgs_ctx* ctx, const float* params, int32_t width,
  * forbid hipMalloc).  Same arguments, kernels and results (bit-identical) as
  * nvgs_mlp_backward; the per-work-group gradient partials live in a fixed
  * 16 MiB device workspace that each GPU holds from library load until the
- * process ends.  B must be <= NVGS_NOALLOC_MAX_BATCH (E_INVALID otherwise).
+ * process ends.  B must be <= NVGS_NOALLOC_MAX_BATCH at width 64 and
+ * <= NVGS_NOALLOC_MAX_BATCH_W128 at width 128 (E_INVALID otherwise).
  * Every call on a device shares that device's workspace: calls that overlap
  * in time on one device (other streams or contexts) race and give undefined
  * results; calls on one stream are ordered and safe.  The workspace keeps the
  * last call's contents; nothing in it needs clearing between calls. */
 #define NVGS_NOALLOC_MAX_BATCH 65536
+#define NVGS_NOALLOC_MAX_BATCH_W128 16896
 nvgs_status nvgs_mlp_backward_noalloc(nvgs_ctx* ctx, const float* params, int32_t width, const float* X, int64_t B,
                                       const float* dlogits, int32_t precision, float* dparams, float* dX);
 

@@ -59,7 +59,7 @@ def lib():
         L.orc_query.argtypes = [C.c_int64, fp, dp, dp, dp, C.c_int, C.c_int, C.c_double, C.c_double,
                                 C.c_double, C.c_double, C.c_double, C.c_int, u8, dp, vp]
         L.orc_project.argtypes = [C.c_int64, i64, C.c_int64, fp, fp, fp, fp, fp, C.c_int, dp, dp, dp, i32]
-        L.orc_render.argtypes = [C.c_int64, dp, i32, dp, C.c_int, dp, dp, vp, vp, vp, vp, vp, C.c_int64]
+        L.orc_render.argtypes = [C.c_int64, dp, i32, dp, C.c_int, dp, dp, vp, vp, vp, vp, vp, C.c_int64, vp]
         L.orc_render.restype = C.c_int64
         L.orc_render_brute.argtypes = [C.c_int64, dp, dp, dp, dp, vp]
         L.orc_bce_backward.argtypes = [dp, C.c_int, C.c_int, dp, dp, vp, C.c_int64, dp, vp]
@@ -372,9 +372,10 @@ def project(scene, cam, pairs: np.ndarray, det_clip: float = 0.0):
 
 
 def render_camera(rec, prect, cam, tile: int, bg=(0.0, 0.0, 0.0), contrib=None, reached=None,
-                  want_margin: bool = True, want_order: bool = False):
-    """Binning + compositing for one camera.  contrib/reached arrays (length m) are updated
-    in place when given."""
+                  want_margin: bool = True, want_order: bool = False, smargin=None):
+    """Binning + compositing for one camera.  contrib/reached arrays (length m) and
+    smargin [m, 2] (per-splat decision margins, min-accumulated; start at inf) are
+    updated in place when given."""
     m = rec.shape[0]
     H, W = cam.height, cam.width
     img = np.zeros((H, W, 3))
@@ -386,7 +387,8 @@ def render_camera(rec, prect, cam, tile: int, bg=(0.0, 0.0, 0.0), contrib=None, 
         cap = int(np.sum(_tiles_per_rect(prect, tile))) if m else 0
         order = np.zeros((max(cap, 1), 2), np.int64)
     n = lib().orc_render(m, _f64(rec), np.ascontiguousarray(prect, np.int32), cam_array(cam), tile,
-                         _f64(bg), img, _ptr(tf), _ptr(contrib), _ptr(reached), _ptr(mg), _ptr(order), cap)
+                         _f64(bg), img, _ptr(tf), _ptr(contrib), _ptr(reached), _ptr(mg), _ptr(order), cap,
+                         _ptr(smargin))
     out = {"image": img, "T": tf, "entries": int(n)}
     if want_margin:
         out["margin"] = mg
@@ -435,21 +437,30 @@ def frame(scene, use_mlp: bool = True, tile: Optional[int] = None, record: bool 
     return out
 
 
-def contributions(asset, views, tile: int = 16) -> np.ndarray:
+def contributions(asset, views, tile: int = 16, want_detail: bool = False):
     """Largest contribution alpha*T of each Gaussian's blended fragments in
     each view (Sec. 3.1), single identity instance, frustum culling only:
-    [V, n] (0 where outside the frustum or never blended)."""
+    [V, n] (0 where outside the frustum or never blended).  want_detail: also
+    the "reached" flags [V, n] and the per-Gaussian decision margins
+    [V, n, 2] (inf where never tested)."""
     from synth import Scene, identity_instance  # inputs only
     sc = Scene(assets=[asset], instances=[identity_instance(0)], cameras=list(views), tile=tile)
     state, _ = query(sc, use_mlp=False)
     kept = compact(state)
     out = np.zeros((len(views), asset.n))
+    rch = np.zeros((len(views), asset.n), np.uint8)
+    smg = np.full((len(views), asset.n, 2), np.inf)
     for k, cam in enumerate(views):
         rec, prect = project(sc, cam, kept[k])
         cb = np.zeros(len(kept[k]))
-        render_camera(rec, prect, cam, tile, (0.0, 0.0, 0.0), cb, None, want_margin=False)
+        rc = np.zeros(len(kept[k]), np.uint8)
+        sm = np.full((len(kept[k]), 2), np.inf)
+        render_camera(rec, prect, cam, tile, (0.0, 0.0, 0.0), cb, rc if want_detail else None,
+                      want_margin=False, smargin=sm if want_detail else None)
         out[k, kept[k]] = cb
-    return out
+        rch[k, kept[k]] = rc
+        smg[k, kept[k]] = sm
+    return (out, rch, smg) if want_detail else out
 
 
 def aux_views(view, aux: int, angle: float):

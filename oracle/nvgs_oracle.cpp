@@ -407,9 +407,15 @@ void orc_project(int64_t m, const int64_t* gidx, int64_t n, const float* mean, c
 //   consecutive fragments with alpha >= 1/255 (how close the pixel's blend
 //   order is to a tie).
 //   order_out nullable: the sorted (tile, id) list, ntile_entries returned.
+//   smargin [m][2] nullable: per splat, the smallest pixel margins ([0] alpha /
+//   stop, [1] depth order, as in `margin`) of every decision taken at a pixel
+//   up to and including that splat's own test there, and, at a pixel that
+//   stopped, of all decisions up to the stop for every splat listed after it
+//   (min-accumulated like contrib): how close the splat's contribution and
+//   "reached" state are to changing with a decision elsewhere.
 int64_t orc_render(int64_t m, const double* rec, const int32_t* prect, const double* cam_p, int T,
                    const double* bg, double* image, double* tfinal, double* contrib, uint8_t* reached,
-                   double* margin, int64_t* order_out, int64_t order_cap) {
+                   double* margin, int64_t* order_out, int64_t order_cap, double* smargin) {
   Cam c = load_cam(cam_p);
   int W = (int)c.W, H = (int)c.H;
   int tw = (W + T - 1) / T, th = (H + T - 1) / T;
@@ -442,6 +448,7 @@ int64_t orc_render(int64_t m, const double* rec, const int32_t* prect, const dou
 #endif
   std::vector<std::vector<double>> cmax(nthreads);
   std::vector<std::vector<uint8_t>> rch(nthreads);
+  std::vector<std::vector<double>> smg(nthreads);
 #pragma omp parallel
   {
     int tid = 0;
@@ -450,6 +457,12 @@ int64_t orc_render(int64_t m, const double* rec, const int32_t* prect, const dou
 #endif
     cmax[tid].assign(contrib ? m : 0, 0.0);
     rch[tid].assign(reached ? m : 0, 0);
+    smg[tid].assign(smargin ? 2 * m : 0, std::numeric_limits<double>::infinity());
+    auto note = [&](int64_t j, double a_m, double d_m) {
+      if (!smargin) return;
+      smg[tid][2 * j] = std::min(smg[tid][2 * j], a_m);
+      smg[tid][2 * j + 1] = std::min(smg[tid][2 * j + 1], d_m);
+    };
 #pragma omp for schedule(dynamic, 16)
     for (int64_t pix = 0; pix < (int64_t)W * H; ++pix) {
       int px = (int)(pix % W), py = (int)(pix / W);
@@ -468,13 +481,20 @@ int64_t orc_render(int64_t m, const double* rec, const int32_t* prect, const dou
         if (power > 0) continue;
         double a = std::min(kAlphaMax, r[9] * std::exp(power));
         mg = std::min(mg, std::fabs(a - kAlphaMin) / kAlphaMin);
-        if (a < kAlphaMin) continue;
+        if (a < kAlphaMin) {
+          note(j, mg, mgd);
+          continue;
+        }
         if (prev_depth >= 0) mgd = std::min(mgd, (r[8] - prev_depth) / r[8]);
         prev_depth = r[8];
         double Tn = Tr * (1.0 - a);
         mg = std::min(mg, std::fabs(Tn - kTMin) / kTMin);
+        note(j, mg, mgd);
         if (reached) rch[tid][j] = 1;
-        if (Tn < kTMin) break;
+        if (Tn < kTMin) {
+          for (int64_t k2 = k + 1; smargin && k2 < start[tile + 1]; ++k2) note(ent[k2].id, mg, mgd);
+          break;
+        }
         for (int ch = 0; ch < 3; ++ch) col[ch] += a * Tr * r[10 + ch];
         if (contrib) cmax[tid][j] = std::max(cmax[tid][j], a * Tr);
         Tr = Tn;
@@ -489,6 +509,8 @@ int64_t orc_render(int64_t m, const double* rec, const int32_t* prect, const dou
       for (int64_t j = 0; j < m; ++j) contrib[j] = std::max(contrib[j], cmax[t][j]);
     if (reached && !rch[t].empty())
       for (int64_t j = 0; j < m; ++j) reached[j] |= rch[t][j];
+    if (smargin && !smg[t].empty())
+      for (int64_t j = 0; j < 2 * m; ++j) smargin[j] = std::min(smargin[j], smg[t][j]);
   }
   return (int64_t)ent.size();
 }

@@ -17,9 +17,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libnvgs.so")
 
 OK, E_INVALID, E_STATE, E_NOMEM, E_CAPACITY, E_DEVICE = range(6)
-PREC_FP32, PREC_BF16, PREC_FP8 = 0, 1, 2
+PREC_FP32, PREC_BF16, PREC_FP8, PREC_FP32_SPLIT = 0, 1, 2, 3
 RENDER_RECORD_CONTRIB, RENDER_KEEP_DEBUG, RENDER_GRAPH = 1, 2, 4
-_PREC = {"fp32": PREC_FP32, "bf16": PREC_BF16, "fp8": PREC_FP8}
+_PREC = {"fp32": PREC_FP32, "bf16": PREC_BF16, "fp8": PREC_FP8, "fp32s": PREC_FP32_SPLIT}
 
 
 class NvgsError(RuntimeError):
@@ -79,7 +79,8 @@ class FrameStats(C.Structure):
 class DebugView(C.Structure):
     _fields_ = [("n_splats", C.c_int64), ("n_dup", C.c_int64), ("pair", C.c_void_p), ("rec_a", C.c_void_p),
                 ("rec_b", C.c_void_p), ("rec_c", C.c_void_p), ("rect", C.c_void_p), ("sorted_key", C.c_void_p),
-                ("sorted_id", C.c_void_p), ("ranges", C.c_void_p), ("tiles_x", C.c_int32), ("tiles_y", C.c_int32)]
+                ("sorted_id", C.c_void_p), ("ranges", C.c_void_p), ("tiles_x", C.c_int32), ("tiles_y", C.c_int32),
+                ("rec_d", C.c_void_p)]
 
 
 class MlpShape(C.Structure):
@@ -133,6 +134,17 @@ _SIGS = {
 }
 
 NUM_PARAMS_W64 = 72 * 64 + 64 + 2 * (64 * 64 + 64) + 64 + 1
+NUM_PARAMS_W128 = 72 * 128 + 128 + 2 * (128 * 128 + 128) + 128 + 1
+
+
+def _mlp_width(params):
+    """Hidden width of a packed frequency-form MLP from its parameter count."""
+    n = int(params.numel())
+    if n == NUM_PARAMS_W64:
+        return 64
+    if n == NUM_PARAMS_W128:
+        return 128
+    raise ValueError(f"{n} parameters: not a width-64 ({NUM_PARAMS_W64}) or width-128 ({NUM_PARAMS_W128}) MLP")
 NUM_PARAMS_COMPACT = (32 * 16 + 32 + 32 * 32 + 32 + 32 + 1) + (32 * 8 + 32 + 32 * 32 + 32 + 6 * 32 + 6)
 
 _lib = None
@@ -411,6 +423,7 @@ class Context:
             "rec_a": grab(v.rec_a, (ns, 4), torch.float32),
             "rec_b": grab(v.rec_b, (ns, 4), torch.float32),
             "rec_c": grab(v.rec_c, (ns, 4), torch.float32),
+            "rec_d": grab(v.rec_d, (ns, 2), torch.float32),
             "rect": grab(v.rect, (ns, 4), torch.int32),
             "sorted_key": grab(v.sorted_key, (nd,), torch.int32),
             "sorted_id": grab(v.sorted_id, (nd,), torch.int32),
@@ -442,7 +455,8 @@ def _train_methods():
                          precision="bf16", lr: float = 1e-3, betas=(0.9, 0.999), eps: float = 1e-8, seed: int = 1,
                          threshold: float = 1.0 / 255.0, tile: int = 16, weighting: int = 0,
                          lr_final: float = 0.0):
-        """Train in place; params is a device float32 tensor [13057]; returns the loss curve.
+        """Train in place; params is a device float32 tensor [13057] (width 64) or
+        [42497] (width 128), the asset's own width; returns the loss curve.
         lr_final > 0 selects the warm-up + exponential-decay schedule from lr to lr_final."""
         arr, V = self._cams(views)
         opts = TrainOpts(int(batch), int(steps), _PREC.get(precision, precision), float(lr), float(betas[0]),
@@ -455,21 +469,22 @@ def _train_methods():
 
     def mlp_forward(self, params, X, precision="fp32"):
         z = torch.empty(X.shape[0], dtype=torch.float32, device=self.device)
-        self._check(self.L.nvgs_mlp_forward(self.h, params.data_ptr(), 64, X.data_ptr(), X.shape[0],
+        self._check(self.L.nvgs_mlp_forward(self.h, params.data_ptr(), _mlp_width(params), X.data_ptr(), X.shape[0],
                                             _PREC.get(precision, precision), z.data_ptr()))
         return z
 
     def mlp_backward(self, params, X, dlogits, precision="fp32", want_dx=True):
-        dp = torch.empty(NUM_PARAMS_W64, dtype=torch.float32, device=self.device)
+        dp = torch.empty(params.numel(), dtype=torch.float32, device=self.device)
         dx = torch.empty_like(X) if want_dx else None
-        self._check(self.L.nvgs_mlp_backward(self.h, params.data_ptr(), 64, X.data_ptr(), X.shape[0],
+        self._check(self.L.nvgs_mlp_backward(self.h, params.data_ptr(), _mlp_width(params), X.data_ptr(), X.shape[0],
                                              dlogits.data_ptr(), _PREC.get(precision, precision), dp.data_ptr(),
                                              _ptr(dx)))
         return dp, dx
 
     def mlp_backward_noalloc(self, params, X, dlogits, dparams, dx=None, precision="fp32"):
         """nvgs_mlp_backward into caller-provided outputs, with no device allocation."""
-        self._check(self.L.nvgs_mlp_backward_noalloc(self.h, params.data_ptr(), 64, X.data_ptr(), X.shape[0],
+        self._check(self.L.nvgs_mlp_backward_noalloc(self.h, params.data_ptr(), _mlp_width(params), X.data_ptr(),
+                                                     X.shape[0],
                                                      dlogits.data_ptr(), _PREC.get(precision, precision),
                                                      dparams.data_ptr(), _ptr(dx)))
         return dparams, dx
@@ -501,7 +516,7 @@ _train_methods_installed = False
 
 def visibility_mlp_function():
     """torch.autograd.Function over the library's MLP forward and hand-written
-    backward: apply(X [B, 72], params [13057], ctx, precision) -> logits [B]."""
+    backward: apply(X [B, 72], params [13057 or 42497], ctx, precision) -> logits [B]."""
     torch = _torch()
 
     class VisibilityMLPFunction(torch.autograd.Function):

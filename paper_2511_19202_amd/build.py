@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libnvgs.so")
-SOURCES = ["api.hip", "k_mlp.hip", "k_scan.hip", "k_sort.hip", "k_raster.hip", "k_train.hip", "k_cmlp.hip", "k_ctrain.hip"]
+SOURCES = ["api.hip", "k_mlp.hip", "k_scan.hip", "k_sort.hip", "k_raster.hip", "k_train.hip", "k_train_mfma.hip", "k_cmlp.hip", "k_ctrain.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
          # packed FP32 instructions stay off (compiler-generated v_pk_*_f32)

@@ -1,6 +1,7 @@
 // C ABI of the NVGS renderer: context, asset store, instance list, and the
 // per-frame launch sequence (declared in include/nvgs.h).
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -65,7 +66,7 @@ struct nvgs_ctx {
 
   // splats and sort buffers
   int64_t cap_splats = 0, cap_dup = 0;
-  Buf splat, rec_a, rec_b, rec_c, rect, rect_sorted, depth_key, ids, ids_tmp, keys_tmp2, pair_of, cnt, dup_off;
+  Buf splat, rec_a, rec_b, rec_c, rec_d, rect, rect_sorted, depth_key, ids, ids_tmp, keys_tmp2, pair_of, cnt, dup_off;
   Buf keys, vals, keys_tmp, vals_tmp, hist, hist_part, ranges, tord;  // tord: tile order (4 arrays)
   Buf tsplit, citems, prodb, partb;  // long-list split: per-position counts and offsets, items, chunk products / records
   int64_t cap_items = 0, cap_split_px = 0;  // items; split slots x pixels per tile
@@ -344,7 +345,7 @@ void nvgs_destroy(nvgs_ctx* ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   Buf* all[] = {&ctx->assets_dev, &ctx->inst_dev, &ctx->inst_off_dev, &ctx->seg_word_dev, &ctx->seg_chunk_dev,
                 &ctx->items_dev, &ctx->seglist_dev, &ctx->segs_dev, &ctx->c1_dev, &ctx->mask, &ctx->chunk_cnt,
-                &ctx->chunk_off, &ctx->scan_part, &ctx->cam_dev, &ctx->splat, &ctx->rect_sorted, &ctx->rec_a, &ctx->rec_b, &ctx->rec_c, &ctx->rect,
+                &ctx->chunk_off, &ctx->scan_part, &ctx->cam_dev, &ctx->splat, &ctx->rect_sorted, &ctx->rec_a, &ctx->rec_b, &ctx->rec_c, &ctx->rec_d, &ctx->rect,
                 &ctx->depth_key, &ctx->ids, &ctx->ids_tmp, &ctx->keys_tmp2, &ctx->pair_of, &ctx->cnt, &ctx->dup_off,
                 &ctx->keys, &ctx->vals, &ctx->keys_tmp, &ctx->vals_tmp, &ctx->hist, &ctx->hist_part, &ctx->ranges, &ctx->tord,
                 &ctx->tsplit, &ctx->citems, &ctx->prodb, &ctx->partb,
@@ -418,6 +419,7 @@ nvgs_status nvgs_load_assets(nvgs_ctx* ctx, const nvgs_asset* a, int32_t n) {
       d.op_f32 = P_<float>(ob[0]);
       d.op_bf16 = P_<uint16_t>(ob[1]);
       d.op_fp8 = nullptr;
+      d.op_split = nullptr;
       d.fp8_scale = nullptr;
       d.emb = P_<float>(ob[6]);
       d.geo = P_<float4>(ob[4]);
@@ -433,6 +435,7 @@ nvgs_status nvgs_load_assets(nvgs_ctx* ctx, const nvgs_asset* a, int32_t n) {
     if (!ensure(ctx, ob[0], mlp_op_f32_floats(width) * sizeof(float)) ||
         !ensure(ctx, ob[1], mlp_op_bf16_elems(width) * sizeof(uint16_t)) ||
         !ensure(ctx, ob[2], mlp_op_fp8_bytes(width)) || !ensure(ctx, ob[3], 16 * sizeof(float)) ||
+        !ensure(ctx, ob[6], mlp_op_split_bytes(width)) ||
         !ensure(ctx, ob[4], 3 * sizeof(float4) * (size_t)x.n) ||
         !ensure(ctx, ob[5], sizeof(float) * (size_t)sh_stride_for(x.sh_degree) * (size_t)x.n))
       return fail(ctx, NVGS_E_NOMEM, "operand images");
@@ -444,9 +447,11 @@ nvgs_status nvgs_load_assets(nvgs_ctx* ctx, const nvgs_asset* a, int32_t n) {
     d.op_f32 = P_<float>(ob[0]);
     d.op_bf16 = P_<uint16_t>(ob[1]);
     d.op_fp8 = P_<uint8_t>(ob[2]);
+    d.op_split = P_<uint8_t>(ob[6]);
     d.fp8_scale = P_<float>(ob[3]);
     CK(launch_prepare_mlp(x.mlp.params, width, P_<float>(ob[0]), P_<uint16_t>(ob[1]), P_<uint8_t>(ob[2]),
                           P_<float>(ob[3]), ctx->stream));
+    CK(launch_prepare_split(x.mlp.params, width, P_<uint8_t>(ob[6]), ctx->stream));
   }
   if (!ensure(ctx, ctx->assets_dev, sizeof(AssetDev) * n)) return fail(ctx, NVGS_E_NOMEM, "asset table");
   CK(hipMemcpyAsync(ctx->assets_dev.p, ctx->adev.data(), sizeof(AssetDev) * n, hipMemcpyHostToDevice, ctx->stream));
@@ -497,8 +502,8 @@ nvgs_status nvgs_query_visibility(nvgs_ctx* ctx, const nvgs_camera* cams, int32_
   if (s) return s;
   if ((s = check_cams(ctx, cams, C))) return s;
   if (!state) return fail(ctx, NVGS_E_INVALID, "state: null pointer");
-  if (precision < NVGS_PREC_FP32 || precision > NVGS_PREC_FP8) return fail(ctx, NVGS_E_INVALID, "bad precision");
-  if (ctx->kind == 1 && precision == NVGS_PREC_FP8)
+  if (precision < NVGS_PREC_FP32 || precision > NVGS_PREC_FP32_SPLIT) return fail(ctx, NVGS_E_INVALID, "bad precision");
+  if (ctx->kind == 1 && precision >= NVGS_PREC_FP8)
     return fail(ctx, NVGS_E_INVALID, "the compact MLP runs in FP32 or BF16");
   CK(hipSetDevice(ctx->device));
   if ((s = plan(ctx, C))) return s;
@@ -545,7 +550,7 @@ nvgs_status size_debug(nvgs_ctx* ctx) {
   if (ctx->cap_debug >= ctx->cap_splats && ctx->cap_debug > 0) return NVGS_OK;
   const int64_t cap = ctx->cap_splats;
   if (!ensure(ctx, ctx->rec_a, 16 * cap) || !ensure(ctx, ctx->rec_b, 16 * cap) ||
-      !ensure(ctx, ctx->rec_c, 16 * cap) || !ensure(ctx, ctx->pair_of, 4 * cap)) {
+      !ensure(ctx, ctx->rec_c, 16 * cap) || !ensure(ctx, ctx->rec_d, 8 * cap) || !ensure(ctx, ctx->pair_of, 4 * cap)) {
     ctx->cap_debug = 0;
     return fail(ctx, NVGS_E_NOMEM, "debug buffers");
   }
@@ -666,7 +671,7 @@ nvgs_status enqueue_frame(nvgs_ctx* ctx, hipStream_t st, const Frame& f, bool ea
   CK(launch_project(P_<AssetDev>(ctx->assets_dev), P_<SegRec>(ctx->segs_dev), C * NI, P_<int64_t>(ctx->seg_chunk_dev),
                     ctx->n_chunks, P_<uint32_t>(ctx->mask), P_<uint32_t>(ctx->chunk_off), n_splats_dev,
                     ctx->cap_splats, f.T, f.tiles_x, f.tiles_y, f.debug ? 1 : 0, opts->det_clip, P_<float4>(ctx->splat),
-                    P_<float4>(ctx->rec_a), P_<float4>(ctx->rec_b), P_<float4>(ctx->rec_c), P_<uint4>(ctx->rect),
+                    P_<float4>(ctx->rec_a), P_<float4>(ctx->rec_b), P_<float4>(ctx->rec_c), P_<float2>(ctx->rec_d), P_<uint4>(ctx->rect),
                     P_<uint32_t>(ctx->depth_key), P_<uint32_t>(ctx->pair_of), counters + 2, st));
   STAGE_END(NVGS_STAGE_PROJECT);
   // depth order of the splats (stable: equal depths keep id order)
@@ -777,9 +782,9 @@ nvgs_status nvgs_render(nvgs_ctx* ctx, const nvgs_camera* cams, int32_t C, const
   if (!opts || !rgb) return fail(ctx, NVGS_E_INVALID, "render: null opts or rgb");
   const int T = opts->tile;
   if (T != 8 && T != 16 && T != 32) return fail(ctx, NVGS_E_INVALID, "tile must be 8, 16 or 32");
-  if (opts->precision < NVGS_PREC_FP32 || opts->precision > NVGS_PREC_FP8)
+  if (opts->precision < NVGS_PREC_FP32 || opts->precision > NVGS_PREC_FP32_SPLIT)
     return fail(ctx, NVGS_E_INVALID, "bad precision");
-  if (ctx->kind == 1 && opts->use_mlp && opts->precision == NVGS_PREC_FP8)
+  if (ctx->kind == 1 && opts->use_mlp && opts->precision >= NVGS_PREC_FP8)
     return fail(ctx, NVGS_E_INVALID, "the compact MLP runs in FP32 or BF16");
   if (opts->split_len > 0 && opts->split_len < 64) return fail(ctx, NVGS_E_INVALID, "split_len must be 0, < 0 or >= 64");
   if (!(opts->det_clip >= 0.f) || !finite_f(opts->det_clip))
@@ -1020,6 +1025,7 @@ nvgs_status nvgs_debug_buffers(nvgs_ctx* ctx, nvgs_debug_view* out) {
   out->rec_a = ctx->last_debug ? P_<float>(ctx->rec_a) : nullptr;
   out->rec_b = ctx->last_debug ? P_<float>(ctx->rec_b) : nullptr;
   out->rec_c = ctx->last_debug ? P_<float>(ctx->rec_c) : nullptr;
+  out->rec_d = ctx->last_debug ? P_<float>(ctx->rec_d) : nullptr;
   out->rect = P_<uint32_t>(ctx->rect);
   out->sorted_key = ctx->last_sorted_key;
   out->sorted_id = ctx->last_sorted_id;
@@ -1056,7 +1062,7 @@ struct Tmp {
 nvgs_status check_train_prec(nvgs_ctx* ctx, int32_t precision, int32_t width, int32_t kind = 0) {
   if (precision != NVGS_PREC_FP32 && precision != NVGS_PREC_BF16)
     return fail(ctx, NVGS_E_INVALID, "training precision must be FP32 or BF16");
-  if (kind == 0 && width != 64) return fail(ctx, NVGS_E_INVALID, "training supports width 64");
+  if (kind == 0 && width != 64 && width != 128) return fail(ctx, NVGS_E_INVALID, "training supports widths 64 and 128");
   if (kind == 1 && width != 32) return fail(ctx, NVGS_E_INVALID, "the compact MLP has width 32");
   return NVGS_OK;
 }
@@ -1133,7 +1139,8 @@ nvgs_status nvgs_make_labels(nvgs_ctx* ctx, int32_t asset, const nvgs_camera* vi
   if (ctx->assets.empty()) return fail(ctx, NVGS_E_STATE, "no assets loaded");
   if (asset < 0 || asset >= (int)ctx->assets.size()) return fail(ctx, NVGS_E_INVALID, "asset index out of range");
   if (!labels) return fail(ctx, NVGS_E_INVALID, "labels: null pointer");
-  if (!std::isfinite(threshold)) return fail(ctx, NVGS_E_INVALID, "non-finite threshold");
+  if (!std::isfinite(threshold) || !(threshold >= FLT_MIN))
+    return fail(ctx, NVGS_E_INVALID, "threshold must be finite and at least the smallest normal float");
   nvgs_status s = check_cams(ctx, views, V);
   if (s) return s;
   CK(hipSetDevice(ctx->device));
@@ -1221,7 +1228,7 @@ nvgs_status nvgs_train_visibility(nvgs_ctx* ctx, int32_t asset, const nvgs_camer
     labels = lb;
   }
   const bool compact = ctx->kind == 1;
-  const int np = compact ? ctrain_num_params() : train_num_params();
+  const int np = compact ? ctrain_num_params() : train_num_params(A.mlp.width);
   const int cpw = compact ? ctrain_chunks(opts->batch) : kTrainChunksPerWG;
   const int64_t per_wg = compact ? (int64_t)ctrain_samples_per_chunk() * cpw : (int64_t)kPairsPerWG;
   const int nwg = (int)((opts->batch + per_wg - 1) / per_wg);
@@ -1257,7 +1264,7 @@ nvgs_status nvgs_train_visibility(nvgs_ctx* ctx, int32_t asset, const nvgs_camer
       CK(launch_cmlp_train(0, bf16, nwg, cpw, ctx->stream, params, opts->batch, inv_b, ca, nullptr, nullptr, nullptr,
                            part, lp));
     } else {
-      CK(launch_mlp_train(0, bf16, nwg, kTrainChunksPerWG, ctx->stream, params, opts->batch, inv_b, A.mean, n,
+      CK(launch_mlp_train(0, bf16, A.mlp.width, nwg, ctx->stream, params, opts->batch, inv_b, A.mean, n,
                           A.mlp.mean_scale, gam, V, labels, opts->seed, step, weighted ? npos + step : nullptr,
                           nullptr, nullptr, nullptr, part, lp, nullptr));
     }
@@ -1277,7 +1284,7 @@ nvgs_status nvgs_mlp_forward(nvgs_ctx* ctx, const float* params, int32_t width, 
   if (s) return s;
   CK(hipSetDevice(ctx->device));
   const int nwg = (int)((B + kPairsPerWG - 1) / kPairsPerWG);
-  CK(launch_mlp_train(1, precision == NVGS_PREC_BF16, nwg, kTrainChunksPerWG, ctx->stream, params, B, 1.f, nullptr,
+  CK(launch_mlp_train(1, precision == NVGS_PREC_BF16, width, nwg, ctx->stream, params, B, 1.f, nullptr,
                       1, 0.f, nullptr, 1, nullptr, 0, 0, nullptr, X, nullptr, logits, nullptr, nullptr, nullptr));
   return NVGS_OK;
 }
@@ -1292,10 +1299,10 @@ nvgs_status nvgs_mlp_backward(nvgs_ctx* ctx, const float* params, int32_t width,
   CK(hipSetDevice(ctx->device));
   const int nwg = (int)((B + kPairsPerWG - 1) / kPairsPerWG);
   Tmp part_t(ctx);
-  const int np = train_num_params();
+  const int np = train_num_params(width);
   float* part = part_t.get<float>((size_t)nwg * np + reduce_scratch_floats(nwg, np));
   if (!part) return fail(ctx, NVGS_E_NOMEM, "gradient partials");
-  CK(launch_mlp_train(2, precision == NVGS_PREC_BF16, nwg, kTrainChunksPerWG, ctx->stream, params, B, 1.f, nullptr,
+  CK(launch_mlp_train(2, precision == NVGS_PREC_BF16, width, nwg, ctx->stream, params, B, 1.f, nullptr,
                       1, 0.f, nullptr, 1, nullptr, 0, 0, nullptr, X, dlogits, nullptr, part, nullptr, dX));
   CK(launch_reduce_adam_n(part, nwg, np, nullptr, nullptr, nullptr, dparams, 0.f, 0.f, 0.f, 1.f, 1, nullptr, 0.f,
                           nullptr, ctx->stream, part + (size_t)nwg * np));
@@ -1307,8 +1314,10 @@ nvgs_status nvgs_mlp_backward_noalloc(nvgs_ctx* ctx, const float* params, int32_
   if (!ctx) return NVGS_E_INVALID;
   if (!params || !X || !dlogits || !dparams || B < 1)
     return fail(ctx, NVGS_E_INVALID, "mlp_backward_noalloc: null pointer or B < 1");
-  if (B > NVGS_NOALLOC_MAX_BATCH)
-    return fail(ctx, NVGS_E_INVALID, "mlp_backward_noalloc: B exceeds NVGS_NOALLOC_MAX_BATCH (65536)");
+  if (B > (width == 128 ? NVGS_NOALLOC_MAX_BATCH_W128 : NVGS_NOALLOC_MAX_BATCH))
+    return fail(ctx, NVGS_E_INVALID,
+                "mlp_backward_noalloc: B exceeds NVGS_NOALLOC_MAX_BATCH (65536; NVGS_NOALLOC_MAX_BATCH_W128 = 16896 "
+                "at width 128)");
   nvgs_status s = check_train_prec(ctx, precision, width);
   if (s) return s;
   CK(hipSetDevice(ctx->device));
@@ -1317,10 +1326,10 @@ nvgs_status nvgs_mlp_backward_noalloc(nvgs_ctx* ctx, const float* params, int32_
   if (!part) return fail(ctx, NVGS_E_STATE, "mlp_backward_noalloc: workspace address of this device not looked up");
   // the same partition and kernels as nvgs_mlp_backward, so the results are identical
   const int nwg = (int)((B + kPairsPerWG - 1) / kPairsPerWG);
-  const int np = train_num_params();
+  const int np = train_num_params(width);
   const size_t need = (size_t)nwg * np + reduce_scratch_floats(nwg, np);
   if (need > cap) return fail(ctx, NVGS_E_INVALID, "mlp_backward_noalloc: batch needs more than the fixed workspace");
-  CK(launch_mlp_train(2, precision == NVGS_PREC_BF16, nwg, kTrainChunksPerWG, ctx->stream, params, B, 1.f, nullptr,
+  CK(launch_mlp_train(2, precision == NVGS_PREC_BF16, width, nwg, ctx->stream, params, B, 1.f, nullptr,
                       1, 0.f, nullptr, 1, nullptr, 0, 0, nullptr, X, dlogits, nullptr, part, nullptr, dX));
   CK(launch_reduce_adam_n(part, nwg, np, nullptr, nullptr, nullptr, dparams, 0.f, 0.f, 0.f, 1.f, 1, nullptr, 0.f,
                           nullptr, ctx->stream, part + (size_t)nwg * np));

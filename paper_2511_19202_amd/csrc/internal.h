@@ -37,6 +37,7 @@ struct AssetDev {
   const float* op_f32;   // FP32 operand image (library-owned)
   const uint16_t* op_bf16;
   const uint8_t* op_fp8;
+  const uint8_t* op_split;  // split-FP32 operand image (frequency form)
   const float* fp8_scale; // per-layer dequantisation scales
   // projection image (library-owned, one record per Gaussian so that the
   // gathers of sparse survivors read whole lines): geo[3g..3g+2] =
@@ -63,10 +64,12 @@ hipError_t launch_pack_asset(const float* mean, const float* scale, const float*
 // Per (camera, instance) segment, built on the device every frame.
 struct SegRec {
   float M[12];       // camera-space p = M[:, 0:3] mu + M[:, 3]  (row-major 3x4)
+  float Mlo[12];     // M - (double)M: low-order parts, so that M + Mlo carries ~48 bits
   float cl[3];       // camera position in the asset frame (undoes R, t, s)
   float near_plane;
   float tanx_g, tany_g;  // 1.3 * tan(fov/2) in x and y
   float focal;           // pixels
+  float focal_lo;        // focal - (double)focal
   float half_w, half_h;
   int32_t asset, inst, cam, n;
   int32_t query;     // 1 = the MLP decides, 0 = every in-frustum Gaussian is kept
@@ -101,6 +104,8 @@ hipError_t launch_prepare_mlp(const float* params, int width, float* op_f32, uin
 size_t mlp_op_f32_floats(int width);
 size_t mlp_op_bf16_elems(int width);
 size_t mlp_op_fp8_bytes(int width);
+size_t mlp_op_split_bytes(int width);
+hipError_t launch_prepare_split(const float* params, int width, uint8_t* op_split, hipStream_t st);
 
 hipError_t launch_segment_setup(const nvgs_camera* cams_dev, const nvgs_instance* inst_dev, const AssetDev* assets,
                                 const int64_t* inst_offset, int32_t n_inst, int32_t C, int64_t P, int use_mlp,
@@ -135,7 +140,7 @@ hipError_t launch_project(const AssetDev* assets, const SegRec* segs, int32_t n_
                           int64_t n_chunks, const uint32_t* mask, const uint32_t* chunk_off, const uint32_t* n_splats,
                           int64_t cap_splats, int tile, int tiles_x, int tiles_y, int keep_debug, float det_clip,
                           float4* splat,
-                          float4* rec_a, float4* rec_b, float4* rec_c, uint4* rect, uint32_t* depth_key,
+                          float4* rec_a, float4* rec_b, float4* rec_c, float2* rec_d, uint4* rect, uint32_t* depth_key,
                           uint32_t* pair_of, uint32_t* overflow, hipStream_t st);
 
 hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint32_t* vals_tmp,
@@ -185,15 +190,24 @@ hipError_t launch_blend(const BlendItems& bi, const uint32_t* ranges, const uint
 namespace nvgs {
 // training (k_train.hip)
 size_t train_smem_bytes();
-int train_num_params();
+int train_num_params(int width = 64);
+// modes of the training kernels: sampled pairs with BCE, logits only, vector-Jacobian product
+enum { kModeTrainW = 0, kModeForwardW = 1, kModeBackwardW = 2 };
 hipError_t launch_view_gam(const nvgs_camera* views, int V, float cam_scale, float train_focal, float d_max,
                            float* gam, hipStream_t st);
 hipError_t launch_label_bits(const float* contrib, int64_t n, int V, float thr, uint32_t* bits, hipStream_t st);
-hipError_t launch_mlp_train(int mode, bool bf16, int nwg, int chunks_per_wg, hipStream_t st, const float* params,
+// work-groups of 256 pairs (nwg = ceil(batch / 256)); FP32 width 64 on the
+// FP32 MFMA kernel, BF16 (widths 64, 128) and FP32 width 128 on k_mlp_train_w
+hipError_t launch_mlp_train(int mode, bool bf16, int width, int nwg, hipStream_t st, const float* params,
                             int64_t batch, float inv_batch, const float* mean, int64_t n, float mean_scale,
                             const float* view_gam, int V, const uint32_t* labels, uint64_t seed, int64_t step,
                             const uint32_t* n_pos, const float* X, const float* dlogits, float* logits,
                             float* partial, float* loss_part, float* dX);
+hipError_t launch_mlp_train_w(int mode, bool bf16, int width, int nwg, int pairs_per_wg, hipStream_t st,
+                              const float* params, int64_t batch, float inv_batch, const float* mean, int64_t n,
+                              float mean_scale, const float* view_gam, int V, const uint32_t* labels, uint64_t seed,
+                              int64_t step, const uint32_t* n_pos, const float* X, const float* dlogits,
+                              float* logits, float* partial, float* loss_part, float* dX);
 hipError_t launch_or_groups(const uint32_t* rows, int V, int group, int64_t words, uint32_t* out, hipStream_t st);
 hipError_t launch_count_pos(int64_t batch, int64_t n, int V, const uint32_t* labels, uint64_t seed, int64_t step,
                             uint32_t* count, hipStream_t st);

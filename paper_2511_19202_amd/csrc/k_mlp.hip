@@ -53,6 +53,11 @@ template <>
 struct Prec<NVGS_PREC_FP8> {
   static constexpr int EPL = 32, ESZ = 1, K = 64;
 };
+// split FP32: the hidden layers' operands are BF16 pairs (hi, lo)
+template <>
+struct Prec<NVGS_PREC_FP32_SPLIT> {
+  static constexpr int EPL = 8, ESZ = 2, K = 16;
+};
 
 // scale slots of the vec section (FP8 only)
 enum { kInvU = 0, kInv2 = 1, kInv3 = 2, kSaH1 = 3, kSaH2 = 4, kSaG = 5, kSw1 = 6, kSw2 = 7, kSw3 = 8, kNumScales = 9 };
@@ -77,7 +82,26 @@ struct Img {
   static constexpr int BYTES = img_bytes(W, T::K, T::EPL, T::ESZ);
 };
 
+// split FP32: layer 1's Gaussian half in the FP32 layout, then the hidden
+// layers' hi and lo BF16 images (W2 hi, W2 lo, W3 hi, W3 lo), then the vectors
+template <int W>
+struct Img<NVGS_PREC_FP32_SPLIT, W> {
+  static constexpr int NT = W / 32, KS1 = img_ks1(2), KSH = W / 16;
+  static constexpr int W1 = 0;
+  static constexpr int HB = img_wh_bytes(W, 16, 8, 2);
+  static constexpr int W2 = img_w1_bytes(W, 2, 1, 4);
+  static constexpr int W2L = W2 + HB;
+  static constexpr int W3 = W2L + HB;
+  static constexpr int W3L = W3 + HB;
+  static constexpr int VEC = W3L + HB;
+  static constexpr int BYTES = VEC + 4 * img_vec_floats(W);
+};
+static size_t img_size_split(int W) {
+  return img_w1_bytes(W, 2, 1, 4) + 4 * img_wh_bytes(W, 16, 8, 2) + 4 * img_vec_floats(W);
+}
+
 static size_t img_size(int P, int W) {
+  if (P == NVGS_PREC_FP32_SPLIT) return img_size_split(W);
   if (P == NVGS_PREC_FP32) return img_bytes(W, 2, 1, 4);
   if (P == NVGS_PREC_BF16) return img_bytes(W, 16, 8, 2);
   return img_bytes(W, 64, 32, 1);
@@ -85,6 +109,7 @@ static size_t img_size(int P, int W) {
 size_t mlp_op_f32_floats(int width) { return img_size(NVGS_PREC_FP32, width) / 4; }
 size_t mlp_op_bf16_elems(int width) { return img_size(NVGS_PREC_BF16, width) / 2; }
 size_t mlp_op_fp8_bytes(int width) { return img_size(NVGS_PREC_FP8, width); }
+size_t mlp_op_split_bytes(int width) { return img_size(NVGS_PREC_FP32_SPLIT, width); }
 
 __host__ __device__ inline float pow2_floor(float x) {  // largest power of two <= x (x > 0)
   int e;
@@ -217,6 +242,54 @@ __global__ void k_prepare(const float* __restrict__ Pm, int W, const float* __re
   }
 }
 
+// operand image of the split-FP32 form (layout of Img<NVGS_PREC_FP32_SPLIT, W>)
+__global__ void k_prepare_split(const float* __restrict__ Pm, int W, uint8_t* __restrict__ img) {
+  const int NT = W / 32, KS1 = img_ks1(2), KSH = W / 16;
+  const float* W1 = Pm;
+  const float* b1 = W1 + W * 72;
+  const float* W2 = b1 + W;
+  const float* b2 = W2 + W * W;
+  const float* W3 = b2 + W;
+  const float* b3 = W3 + W * W;
+  const float* wo = b3 + W;
+  const int n1 = NT * KS1 * 64, nh = NT * KSH * 64 * 8, nvec = img_vec_floats(W);
+  const int total = n1 + 4 * nh + nvec;
+  float* f1 = reinterpret_cast<float*>(img);
+  __bf16* hb = reinterpret_cast<__bf16*>(img + 4 * (size_t)n1);
+  float* vecp = reinterpret_cast<float*>(img + 4 * (size_t)n1 + 2 * (size_t)(4 * nh));
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += gridDim.x * blockDim.x) {
+    if (idx < n1) {
+      const int lane = idx % 64, s = (idx / 64) % KS1, t = idx / (64 * KS1);
+      const int k = s * 2 + lane / 32;  // Gaussian feature (natural order)
+      f1[idx] = k < 36 ? W1[(32 * t + lane % 32) * 72 + k] : 0.f;
+    } else if (idx < n1 + 4 * nh) {
+      const int o = idx - n1, which = o / nh, r = o % nh;  // W2 hi, W2 lo, W3 hi, W3 lo
+      const int j = r % 8, lane = (r / 8) % 64, s = (r / 512) % KSH, t = r / (512 * KSH);
+      const float v = (which < 2 ? W2 : W3)[(32 * t + lane % 32) * W + hid_feature(s * 8 + j, lane / 32)];
+      const __bf16 hi = (__bf16)v;
+      hb[o] = (which & 1) ? (__bf16)(v - (float)hi) : hi;
+    } else {
+      const int e = idx - n1 - 4 * nh, KQ = W / 2;
+      float v = 0.f;
+      if (e < 6 * KQ) {
+        const int which = e / (2 * KQ), r = e % (2 * KQ), g = r / KQ, q = r % KQ;
+        v = (which == 0 ? b2 : which == 1 ? b3 : wo)[hid_feature(q, g)];
+      } else if (e == 6 * KQ) {
+        v = wo[W];
+      } else if (e - 6 * KQ - 1 < kNumScales) {
+        v = 1.f;
+      }
+      vecp[e] = v;
+    }
+  }
+}
+
+hipError_t launch_prepare_split(const float* params, int width, uint8_t* op_split, hipStream_t st) {
+  const size_t n = img_size_split(width) / 2;  // more than enough threads (one per element at most)
+  hipLaunchKernelGGL(k_prepare_split, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, params, width, op_split);
+  return hipGetLastError();
+}
+
 hipError_t launch_prepare_mlp(const float* params, int width, float* op_f32, uint16_t* op_bf16, uint8_t* op_fp8,
                               float* fp8_scale, hipStream_t st) {
   const int W = width;
@@ -311,9 +384,13 @@ __global__ void k_segment_setup(const nvgs_camera* __restrict__ cams, const nvgs
       for (int c = 0; c < 3; ++c) {
         double s = 0;
         for (int q = 0; q < 3; ++q) s += Rc[3 * r + q] * Ri[3 * q + c];
-        R.M[4 * r + c] = (float)(s * (double)in.s);
+        const double m = s * (double)in.s;
+        R.M[4 * r + c] = (float)m;
+        R.Mlo[4 * r + c] = (float)(m - (double)R.M[4 * r + c]);
       }
-      R.M[4 * r + 3] = (float)(Rc[3 * r] * -d[0] + Rc[3 * r + 1] * -d[1] + Rc[3 * r + 2] * -d[2]);
+      const double m = Rc[3 * r] * -d[0] + Rc[3 * r + 1] * -d[1] + Rc[3 * r + 2] * -d[2];
+      R.M[4 * r + 3] = (float)m;
+      R.Mlo[4 * r + 3] = (float)(m - (double)R.M[4 * r + 3]);
     }
     for (int r = 0; r < 3; ++r) R.cl[r] = (float)cl[r];
     double tany = tan(0.5 * (double)cam.fovy);
@@ -323,6 +400,7 @@ __global__ void k_segment_setup(const nvgs_camera* __restrict__ cams, const nvgs
     R.tanx_g = (float)(1.3 * tanx);
     R.tany_g = (float)(1.3 * tany);
     R.focal = (float)focal;
+    R.focal_lo = (float)(focal - (double)R.focal);
     R.half_w = 0.5f * (float)cam.width;
     R.half_h = 0.5f * (float)cam.height;
     R.asset = in.asset;
@@ -456,6 +534,73 @@ __device__ __forceinline__ void relu_pack(const f32x16 (&acc)[NB][W / 32], float
     }
 }
 
+// Split-FP32 operands of the next layer: v = relu(acc[q] (+ add[q])) in FP32,
+// hi = bf16(v) and lo = bf16(v - hi) (v - hi is exact in FP32), packed as
+// BF16 operands in accumulator order.
+template <int W, int NB, bool ADD>
+__device__ __forceinline__ void relu_split(const f32x16 (&acc)[NB][W / 32], const float* __restrict__ add,
+                                           bf16x8 (&hi)[NB][W / 16], bf16x8 (&lo)[NB][W / 16]) {
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int s = 0; s < W / 16; ++s) {
+      i32x4 wh, wl;
+#pragma unroll
+      for (int p2 = 0; p2 < 4; ++p2) {
+        const int q = s * 8 + 2 * p2;
+        const float x0 = ADD ? acc[b][q / 16][q % 16] + add[q] : acc[b][q / 16][q % 16];
+        const float x1 = ADD ? acc[b][(q + 1) / 16][(q + 1) % 16] + add[q + 1] : acc[b][(q + 1) / 16][(q + 1) % 16];
+        const float v0 = fmaxf(x0, 0.f), v1 = fmaxf(x1, 0.f);
+        const bf16x2 h = __builtin_convertvector((f32x2){v0, v1}, bf16x2);
+        const uint32_t hbits = __builtin_bit_cast(uint32_t, h);
+        const float h0 = __uint_as_float(hbits << 16), h1 = __uint_as_float(hbits & 0xffff0000u);
+        const bf16x2 l = __builtin_convertvector((f32x2){v0 - h0, v1 - h1}, bf16x2);
+        wh[p2] = (int)hbits;
+        wl[p2] = __builtin_bit_cast(int, l);
+      }
+      hi[b][s] = __builtin_bit_cast(bf16x8, wh);
+      lo[b][s] = __builtin_bit_cast(bf16x8, wl);
+    }
+}
+
+// One hidden layer of the split-FP32 form: acc = bias + sum over the depth of
+// W_lo x_hi + W_hi x_lo + W_hi x_hi (three BF16 MFMAs per 32x32x16 block,
+// FP32 accumulation; the independent tiles of a round are issued between the
+// dependent accumulations)
+template <int W, int NB>
+__device__ __forceinline__ void mma_layer_split(const uint8_t* __restrict__ Wh, const uint8_t* __restrict__ Wl,
+                                                const float* __restrict__ binit, const bf16x8 (&xh)[NB][W / 16],
+                                                const bf16x8 (&xl)[NB][W / 16], f32x16 (&acc)[NB][W / 32], int lane) {
+  constexpr int NT = W / 32, KSH = W / 16;
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[b][t][r] = binit[16 * t + r];
+#pragma unroll
+  for (int s = 0; s < KSH; ++s) {
+    bf16x8 ah[NT], al[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      ah[t] = reinterpret_cast<const bf16x8*>(Wh)[(t * KSH + s) * 64 + lane];
+      al[t] = reinterpret_cast<const bf16x8*>(Wl)[(t * KSH + s) * 64 + lane];
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[b][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[t], xh[b][s], acc[b][t], 0, 0, 0);
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[b][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[t], xl[b][s], acc[b][t], 0, 0, 0);
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[b][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[t], xh[b][s], acc[b][t], 0, 0, 0);
+  }
+}
+
 // One hidden layer on 32x32 MFMA tiles with the pairs as columns: the
 // accumulators start from the layer's bias (in accumulator order; for FP8
 // stored divided by the layer's dequantisation scale), so the epilogue is a
@@ -490,9 +635,12 @@ __global__ __launch_bounds__(64 * WAVES) void k_cull_mlp(
     uint32_t* __restrict__ chunk_count, uint8_t* __restrict__ state, float* __restrict__ logits,
     unsigned long long* __restrict__ frame_counts) {
   static_assert(WAVES * NB * 32 == kChunk, "a work-group covers one compaction chunk");
-  using M = Mfma<P>;
+  // split FP32: layer 1's Gaussian half on FP32 MFMA, hidden layers on BF16 (hi, lo) pairs
+  constexpr bool SPLIT = P == NVGS_PREC_FP32_SPLIT;
+  constexpr int P1 = SPLIT ? NVGS_PREC_FP32 : P;
+  using M = Mfma<P1>;
   using I = Img<P, W>;
-  constexpr int EPL = Prec<P>::EPL, NT = W / 32, KQ = W / 2, KS1 = I::KS1;
+  constexpr int EPL = Prec<P1>::EPL, NT = W / 32, KQ = W / 2, KS1 = I::KS1;
   __shared__ __attribute__((aligned(16))) uint8_t lds[I::BYTES];
   // per wave: the current segment's layer-1 camera half, published from
   // registers that were loaded one segment earlier (so the MFMA chain never
@@ -504,7 +652,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_cull_mlp(
   {
     const uint8_t* img = P == NVGS_PREC_FP32 ? reinterpret_cast<const uint8_t*>(A->op_f32)
                          : P == NVGS_PREC_BF16 ? reinterpret_cast<const uint8_t*>(A->op_bf16)
-                                               : A->op_fp8;
+                         : P == NVGS_PREC_FP8  ? A->op_fp8
+                                               : A->op_split;
     const uint4* src = reinterpret_cast<const uint4*>(img);
     for (int k = threadIdx.x; k < I::BYTES / 16; k += 64 * WAVES) reinterpret_cast<uint4*>(lds)[k] = src[k];
   }
@@ -605,14 +754,22 @@ __global__ __launch_bounds__(64 * WAVES) void k_cull_mlp(
     bool keep[NB];
     if (query && wave_any) {
       const float* c1 = &s_c1[wave][grp * KQ];
-      constexpr int KSH = W / Prec<P>::K;
-      typename M::Op op[NB][KSH];
       f32x16 acc[NB][NT];
-      // layer 1: h1 = relu(U + c1) (FP8: U dequantised first), as layer 2's operands
-      relu_pack<P, W, NB, true>(U, saH1, c1, invU, op);
-      mma_layer<P, W, NB>(W2p, b2p + grp * KQ, op, acc, lane);
-      relu_pack<P, W, NB, false>(acc, inv2 * saH2, nullptr, 1.f, op);
-      mma_layer<P, W, NB>(W3p, b3p + grp * KQ, op, acc, lane);
+      if constexpr (SPLIT) {
+        bf16x8 oph[NB][W / 16], opl[NB][W / 16];
+        relu_split<W, NB, true>(U, c1, oph, opl);
+        mma_layer_split<W, NB>(W2p, lds + I::W2L, b2p + grp * KQ, oph, opl, acc, lane);
+        relu_split<W, NB, false>(acc, nullptr, oph, opl);
+        mma_layer_split<W, NB>(W3p, lds + I::W3L, b3p + grp * KQ, oph, opl, acc, lane);
+      } else {
+        constexpr int KSH = W / Prec<P>::K;
+        typename Mfma<P>::Op op[NB][KSH];
+        // layer 1: h1 = relu(U + c1) (FP8: U dequantised first), as layer 2's operands
+        relu_pack<P, W, NB, true>(U, saH1, c1, invU, op);
+        mma_layer<P, W, NB>(W2p, b2p + grp * KQ, op, acc, lane);
+        relu_pack<P, W, NB, false>(acc, inv2 * saH2, nullptr, 1.f, op);
+        mma_layer<P, W, NB>(W3p, b3p + grp * KQ, op, acc, lane);
+      }
       // output layer in FP32 on h3 = relu(inv3 acc)
       const float* wg = wop + grp * KQ;
 #pragma unroll
@@ -764,6 +921,9 @@ hipError_t launch_cull_mlp(const AssetDev* assets_dev, const WorkItem* items, in
     if (width == 64 && nb == 4) NVGS_LAUNCH(NVGS_PREC_BF16, 64, 4);
   } else if (precision == NVGS_PREC_FP8) {
     NVGS_SHAPES(NVGS_PREC_FP8)
+  } else if (precision == NVGS_PREC_FP32_SPLIT) {
+    NVGS_SHAPES(NVGS_PREC_FP32_SPLIT)
+    if (width == 64 && nb == 4) NVGS_LAUNCH(NVGS_PREC_FP32_SPLIT, 64, 4);
   }
 #undef NVGS_SHAPES
 #undef NVGS_LAUNCH

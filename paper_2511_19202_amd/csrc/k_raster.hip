@@ -16,6 +16,8 @@
 #include <algorithm>
 #include <utility>
 
+#include <hip/hip_fp16.h>
+
 #include "internal.h"
 
 namespace nvgs {
@@ -132,6 +134,61 @@ hipError_t launch_pack_asset(const float* mean, const float* scale, const float*
   return hipGetLastError();
 }
 
+// Error-free transformations of FP32 values (Knuth's TwoSum; TwoProduct with
+// one FMA): a + b = s + e and a * b = p + e exactly, so that a quantity can be
+// carried as an unevaluated sum hi + lo of two floats (about 48 bits).
+__device__ __forceinline__ float two_sum(float a, float b, float* e) {
+#pragma clang fp contract(off)
+  const float s = a + b;
+  const float bb = s - a;
+  *e = (a - (s - bb)) + (b - bb);
+  return s;
+}
+__device__ __forceinline__ float two_prod(float a, float b, float* e) {
+  const float p = a * b;
+  *e = fmaf(a, b, -p);
+  return p;
+}
+
+// one camera-space coordinate (M + Mlo)[0:3] . mu + (M + Mlo)[3] as hi + lo:
+// the 3x4 row is the composite s_i Rc Ri | Rc (t_i - c) of the segment, held
+// to ~48 bits, so a centre 30 m away keeps its sub-micrometre position
+__device__ __forceinline__ float cam_coord(const float* M, const float* Mlo, float m0, float m1, float m2,
+                                           float* lo) {
+#pragma clang fp contract(off)
+  float e0, e1, e2, e3, e4, e5;
+  float s = two_prod(M[0], m0, &e0);
+  float t = two_prod(M[1], m1, &e1);
+  s = two_sum(s, t, &e2);
+  t = two_prod(M[2], m2, &e3);
+  s = two_sum(s, t, &e4);
+  s = two_sum(M[3], s, &e5);
+  const float small = fmaf(Mlo[0], m0, fmaf(Mlo[1], m1, fmaf(Mlo[2], m2, Mlo[3])));
+  const float l = ((e0 + e1) + (e2 + e3)) + ((e4 + e5) + small);
+  const float h = s + l;
+  *lo = l - (h - s);
+  return h;
+}
+
+// pixel coordinate f p / p_z + c of a camera-space position given as hi + lo
+// parts, returned as hi + lo: the quotient's remainder is exact with an FMA,
+// and the product with the focal length and the offset are error-free
+__device__ __forceinline__ float screen_coord(float ph, float pl, float zh, float zl, float fh, float fl, float c,
+                                              float* lo) {
+#pragma clang fp contract(off)
+  const float qh = ph / zh;
+  const float r = fmaf(-qh, zh, ph);  // ph - qh zh, exact
+  const float ql = fmaf(-qh, zl, r + pl) / zh;
+  float me, ue;
+  const float mh = two_prod(fh, qh, &me);
+  const float ml = me + fmaf(fh, ql, fl * qh);
+  const float uh = two_sum(mh, c, &ue);
+  const float ul = ue + ml;
+  const float h = uh + ul;
+  *lo = ul - (h - uh);
+  return h;
+}
+
 // pixel-rectangle bound of the alpha >= 1/255 set: centres x + 0.5 within
 // u -/+ e, widened by 1e-4 e + 1e-3 px (evaluated without FMA contraction)
 __device__ __forceinline__ void pixel_range(float u, float e, int size, int* lo, int* hi) {
@@ -150,6 +207,7 @@ __global__ __launch_bounds__(kChunk) void k_project(
     const int64_t* __restrict__ seg_chunk_base, const uint32_t* __restrict__ mask,
     const uint32_t* __restrict__ chunk_off, int64_t cap, int tile, int tiles_x, int tiles_y, int keep_debug,
     float det_clip, float4* __restrict__ splat, float4* __restrict__ rec_a, float4* __restrict__ rec_b, float4* __restrict__ rec_c,
+    float2* __restrict__ rec_d,
     uint4* __restrict__ rect, uint32_t* __restrict__ depth_key, uint32_t* __restrict__ pair_of,
     uint32_t* __restrict__ overflow) {
   const int64_t chunk = blockIdx.x;
@@ -186,11 +244,13 @@ __global__ __launch_bounds__(kChunk) void k_project(
   const float s3[3] = {g1.x, g1.y, g1.z};
   float qw = g2.x, qx = g2.y, qy = g2.z, qz = g2.w;
   const float o = g0.w;
-  // camera space
+  // camera space, each coordinate as hi + lo (the hi parts drive the
+  // Jacobian and the depth key; the centre below uses both)
   const float* M = R.M;
-  const float px = fmaf(M[0], mu[0], fmaf(M[1], mu[1], fmaf(M[2], mu[2], M[3])));
-  const float py = fmaf(M[4], mu[0], fmaf(M[5], mu[1], fmaf(M[6], mu[2], M[7])));
-  const float pz = fmaf(M[8], mu[0], fmaf(M[9], mu[1], fmaf(M[10], mu[2], M[11])));
+  float px_lo, py_lo, pz_lo;
+  const float px = cam_coord(M, R.Mlo, mu[0], mu[1], mu[2], &px_lo);
+  const float py = cam_coord(M + 4, R.Mlo + 4, mu[0], mu[1], mu[2], &py_lo);
+  const float pz = cam_coord(M + 8, R.Mlo + 8, mu[0], mu[1], mu[2], &pz_lo);
   const float f = R.focal;
   const float iz = 1.f / pz;
   // perspective Jacobian at the guard-clamped tangent position
@@ -226,27 +286,40 @@ __global__ __launch_bounds__(kChunk) void k_project(
   const float x1 = V0[2] * V1[0] - V0[0] * V1[2];
   const float x2 = V0[0] * V1[1] - V0[1] * V1[0];
   const float det = (x0 * x0 + x1 * x1 + x2 * x2) + kDilate * (a0 + c0) + kDilate * kDilate;
-  float ca, cb, cc2;
-  if (a * cc > 1024.f * det) {
-    // near-degenerate (condition number above 1024): invert in FP64 from the
-    // exact products of the FP32 rows
-    double v0[3], v1[3];
-    for (int k = 0; k < 3; ++k) { v0[k] = V0[k]; v1[k] = V1[k]; }
-    const double da = v0[0] * v0[0] + v0[1] * v0[1] + v0[2] * v0[2] + 0.3;
-    const double dc = v1[0] * v1[0] + v1[1] * v1[1] + v1[2] * v1[2] + 0.3;
-    const double db = v0[0] * v1[0] + v0[1] * v1[1] + v0[2] * v1[2];
-    const double dd = da * dc - db * db;
-    ca = (float)(dc / dd);
-    cb = (float)(-db / dd);
-    cc2 = (float)(da / dd);
-  } else {
-    const float id = 1.f / det;
-    ca = cc * id;
-    cb = -b * id;
-    cc2 = a * id;
+  // inverse 2D covariance (conic) for the debug record
+  const float id = 1.f / det;
+  const float ca = cc * id, cb = -b * id, cc2 = a * id;
+  // The compositing evaluates the exponent as -|F d|^2 with F's rows along
+  // the ellipse axes, F^T F = (log2(e) / 2) conic: a sum of two squares.  The
+  // expanded form A dx^2 + 2B dx dy + C dy^2 cancels along the long axis of
+  // a thin splat and loses ~kappa * 2^-24 of the exponent to the rounding of
+  // A, B, C (kappa = condition number of Sigma2D); the axis form loses
+  // ~sqrt(kappa) * 2^-24.  Eigenvalues l1 >= l2 of Sigma2D: l1 = m + r
+  // (sums of non-negative terms), l2 = det / l1 with the cancellation-free
+  // determinant; l1's eigenvector from the row whose entries do not cancel.
+  float f1x, f1y, f2x, f2y;
+  {
+    constexpr float kS = 0.72134752044448170f;  // log2(e) / 2
+    const float hd = 0.5f * (a - cc);
+    const float r = sqrtf(hd * hd + b * b);
+    const float l1 = 0.5f * (a + cc) + r;
+    const float l2 = det / l1;
+    float e0 = hd >= 0.f ? hd + r : b, e1 = hd >= 0.f ? b : r - hd;
+    float nn = e0 * e0 + e1 * e1;
+    if (!(nn > 0.f)) e0 = 1.f, e1 = 0.f, nn = 1.f;  // isotropic: any axes
+    const float in = rsqrtf(nn);
+    const float s1 = sqrtf(kS / l1) * in, s2 = sqrtf(kS / l2) * in;
+    f1x = s1 * e0; f1y = s1 * e1;
+    f2x = -s2 * e1; f2y = s2 * e0;
   }
-  const float u = fmaf(f * px, iz, R.half_w);
-  const float v = fmaf(f * py, iz, R.half_h);
+  // the centre to ~48 bits: a 1080p centre rounded to FP32 is off by up to
+  // 3e-5 px, and the narrowest splats (dilated variance 0.3 px^2) change alpha
+  // by about one part in 1e4 for that, above the pixel tolerance once
+  // dozens of fragments are blended; the compositing takes u - tile origin
+  // from the two parts
+  float u_lo, v_lo;
+  const float u = screen_coord(px, px_lo, pz, pz_lo, f, R.focal_lo, R.half_w, &u_lo);
+  const float v = screen_coord(py, py_lo, pz, pz_lo, f, R.focal_lo, R.half_h, &v_lo);
   // colour: SH along the camera -> Gaussian direction in the asset frame
   float dx = mu[0] - R.cl[0], dy = mu[1] - R.cl[1], dz = mu[2] - R.cl[2];
   const float dn = rsqrtf(dx * dx + dy * dy + dz * dz);
@@ -270,20 +343,24 @@ __global__ __launch_bounds__(kChunk) void k_project(
       ntiles = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
     }
   }
-  // the compositing record: one 64-byte line per splat, the conic scaled so
-  // that the exponent is base 2, and log2 of the opacity that joins it there
-  constexpr float kLog2e = 1.4426950408889634f;
+  // the compositing record: one 64-byte line per splat: the centre (hi
+  // parts), the axis rows F (exponent base 2), log2 of the opacity that
+  // joins the exponent, the colour, the centre's low parts; then the pair id
+  // and the footprint extents (they only pick 8x8 blocks of a larger tile:
+  // rounded up to FP16)
+  const __half2 exy = __halves2half2(__float2half_ru(ex), __float2half_ru(ey));
   float4* sp = splat + 4 * (int64_t)slot;
-  sp[0] = make_float4(u, v, -0.5f * kLog2e * ca, -kLog2e * cb);
-  sp[1] = make_float4(-0.5f * kLog2e * cc2, o, __log2f(o), rgb[0]);
-  sp[2] = make_float4(rgb[1], rgb[2], ex, ey);
-  sp[3] = make_float4(__uint_as_float((uint32_t)(R.pair_base + g)), pz, 0.f, 0.f);
+  sp[0] = make_float4(u, v, f1x, f1y);
+  sp[1] = make_float4(f2x, f2y, __log2f(o), rgb[0]);
+  sp[2] = make_float4(rgb[1], rgb[2], u_lo, v_lo);
+  sp[3] = make_float4(__uint_as_float((uint32_t)(R.pair_base + g)), __builtin_bit_cast(float, exy), pz, 0.f);
   rect[slot] = make_uint4(r0, r1, (uint32_t)R.cam, ntiles);
   depth_key[slot] = fbits(pz);
   if (keep_debug) {
     rec_a[slot] = make_float4(u, v, ca, cb);
     rec_b[slot] = make_float4(cc2, o, rgb[0], rgb[1]);
     rec_c[slot] = make_float4(rgb[2], pz, ex, ey);
+    rec_d[slot] = make_float2(u_lo, v_lo);
     pair_of[slot] = (uint32_t)(R.pair_base + g);
   }
   (void)tiles_x; (void)tiles_y;
@@ -292,13 +369,13 @@ __global__ __launch_bounds__(kChunk) void k_project(
 hipError_t launch_project(const AssetDev* assets, const SegRec* segs, int32_t n_segs, const int64_t* seg_chunk_base,
                           int64_t n_chunks, const uint32_t* mask, const uint32_t* chunk_off, const uint32_t* n_splats,
                           int64_t cap_splats, int tile, int tiles_x, int tiles_y, int keep_debug, float det_clip,
-                          float4* splat, float4* rec_a, float4* rec_b, float4* rec_c, uint4* rect, uint32_t* depth_key,
+                          float4* splat, float4* rec_a, float4* rec_b, float4* rec_c, float2* rec_d, uint4* rect, uint32_t* depth_key,
                           uint32_t* pair_of, uint32_t* overflow, hipStream_t st) {
   (void)n_splats;
   if (n_chunks == 0) return hipSuccess;
   hipLaunchKernelGGL(k_project, dim3((unsigned)n_chunks), dim3(kChunk), 0, st, assets, segs, n_segs, seg_chunk_base,
                      mask, chunk_off, cap_splats, tile, tiles_x, tiles_y, keep_debug, det_clip, splat, rec_a, rec_b,
-                     rec_c, rect, depth_key, pair_of, overflow);
+                     rec_c, rec_d, rect, depth_key, pair_of, overflow);
   return hipGetLastError();
 }
 
@@ -568,8 +645,8 @@ __device__ __forceinline__ void blend_item(
   constexpr int BPW = NB / (NT / 64);    // blocks per wave (1, 1, 4)
   constexpr int BATCH = NT;              // one staged splat per thread per batch
   // staged records, one array so that a fragment's three reads share one
-  // address: [k][0] = u, v, A, B (A, B, C: conic scaled by -log2(e)/2,
-  // -log2(e), -log2(e)/2); [k][1] = C, opacity, log2(opacity), r; [k][2] = g, b
+  // address: [k][0] = u, v relative to the first pixel centre of the tile's
+  // 32-pixel block, F row 1; [k][1] = F row 2, log2(opacity), r; [k][2] = g, b
   __shared__ float4 s_rec[BATCH][3];
   __shared__ uint32_t s_ov[T == 8 ? 1 : BATCH];  // bit b: the footprint box touches 8x8 block b
   __shared__ uint32_t s_p[RECORD ? BATCH : 1];
@@ -596,8 +673,10 @@ __device__ __forceinline__ void blend_item(
     stop[j] = end;
     const int blk = wave * BPW + j;
     const int x = pix_x(j), y = pix_y(j);
-    px[j] = (x < W && y < H) ? (float)x + 0.5f : kFar;
-    py[j] = (float)y + 0.5f;
+    // pixel offsets within the 32-pixel block holding the tile (the staged
+    // centres are relative to it, the same for every tile size)
+    px[j] = (x < W && y < H) ? (float)(x & 31) : kFar;
+    py[j] = (float)(y & 31);
     Tr[j] = 1.f;
     cr[j] = cg[j] = cb[j] = 0.f;
     before[j] = false;
@@ -614,13 +693,13 @@ __device__ __forceinline__ void blend_item(
   }
   // the next batch's record of this thread, fetched while the current one is composited
   float4 qa = make_float4(0.f, 0.f, 0.f, 0.f), qb = qa, qc = qa;
-  uint32_t qp = 0;
+  float2 qd = make_float2(0.f, 0.f);  // pair id, extents
   if (start + t < end) {
     const float4* r = splat + 4 * (int64_t)ids[start + t];
     qa = r[0];
     qb = r[1];
     qc = r[2];
-    if (RECORD) qp = __float_as_uint(r[3].x);
+    if (RECORD || T != 8) qd = *reinterpret_cast<const float2*>(r + 3);
   }
   uint32_t b0k = start;
   // composite staged splat k into pixel block j.  Branch-free: a fragment that
@@ -632,11 +711,13 @@ __device__ __forceinline__ void blend_item(
     const float4 g = s_rec[k][0];
     const float4 h = s_rec[k][1];
     const float dx = px[j] - g.x, dy = py[j] - g.y;
-    // alpha = min(0.99, o 2^pw) with pw = -log2(e) d^T conic d / 2 <= 0, as
-    // 2^(pw + log2 o); a positive pw (rounding) is skipped as pw > 0 is
-    const float q = fmaf(dx, fmaf(g.z, dx, g.w * dy), fmaf(h.x * dy, dy, h.z));
+    // alpha = min(0.99, o 2^pw) with pw = -log2(e) d^T conic d / 2 = -|F d|^2,
+    // as 2^(pw + log2 o)
+    const float t1 = fmaf(g.z, dx, g.w * dy);
+    const float t2 = fmaf(h.x, dx, h.y * dy);
+    const float q = fmaf(-t1, t1, fmaf(-t2, t2, h.z));
     const float al = fminf(kAlphaMax, __builtin_amdgcn_exp2f(q));
-    const bool ok = q <= h.z && al >= kAlphaMin;
+    const bool ok = al >= kAlphaMin;
     const float w0 = al * Tr[j];
     const float Tn = Tr[j] - w0;  // T (1 - alpha)
     if (PROD) {
@@ -656,7 +737,9 @@ __device__ __forceinline__ void blend_item(
     Tr[j] = take ? Tn : Tr[j];
     if (STATS) stop[j] = halt ? b0k + (uint32_t)k : stop[j];
     px[j] = halt ? kFar : px[j];
-    if (RECORD && take) atomicMax(contrib + s_p[k], __float_as_uint(w));
+    // contribution: alpha T of a blended fragment; the stopping fragment was
+    // reached but not blended and records the smallest positive float
+    if (RECORD && ok) atomicMax(contrib + s_p[k], take ? __float_as_uint(w) : 1u);
   };
   auto live = [&](int j) { return px[j] < kFarTest; };
   for (uint32_t b0 = start; b0 < end; b0 += BATCH) {
@@ -667,24 +750,35 @@ __device__ __forceinline__ void blend_item(
     const int cnt = (int)min((uint32_t)BATCH, end - b0);
     b0k = b0;
     if (t < cnt) {
-      s_rec[t][0] = qa;
+      // the centre relative to the first pixel centre of the tile's 32-pixel
+      // block, from its hi + lo parts (qc.z, qc.w): for a splat over the
+      // tile, u - origin is (nearly) exact in FP32, so d = offset - centre
+      // keeps the centre's precision, and the same for every tile size
+      const int bx = (tx * T) & ~31, by = (ty * T) & ~31;
+      const float ur = (qa.x - ((float)bx + 0.5f)) + qc.z;
+      const float vr = (qa.y - ((float)by + 0.5f)) + qc.w;
+      s_rec[t][0] = make_float4(ur, vr, qa.z, qa.w);
       s_rec[t][1] = qb;
       s_rec[t][2] = qc;
       if (T != 8) {
-        // blocks touched by the footprint box (same widening as the tile rectangle); qc = g, b, ex, ey
-        const float wx = 1e-4f * qc.z + 1e-3f, wy = 1e-4f * qc.w + 1e-3f;
-        const float x0 = qa.x - qc.z - wx - (float)(tx * T) - 0.5f;
-        const float x1 = qa.x + qc.z + wx - (float)(tx * T) - 0.5f;
-        const float y0 = qa.y - qc.w - wy - (float)(ty * T) - 0.5f;
-        const float y1 = qa.y + qc.w + wy - (float)(ty * T) - 0.5f;
-        const int bx0 = max(0, (int)floorf(x0 * 0.125f)), bx1 = min(T / 8 - 1, (int)floorf(x1 * 0.125f));
-        const int by0 = max(0, (int)floorf(y0 * 0.125f)), by1 = min(T / 8 - 1, (int)floorf(y1 * 0.125f));
+        // 8x8 blocks of the tile touched by the footprint box (same widening
+        // as the tile rectangle); qd.y = the half extents, rounded up to FP16
+        const __half2 exy = __builtin_bit_cast(__half2, qd.y);
+        const float ex = __low2float(exy), ey = __high2float(exy);
+        const float wx = 1e-4f * ex + 1e-3f, wy = 1e-4f * ey + 1e-3f;
+        const float ox = (float)(tx * T - bx), oy = (float)(ty * T - by);
+        const float x0 = fmaxf(-1.f, (ur - ox - ex - wx) * 0.125f);
+        const float x1 = fminf((float)T, (ur - ox + ex + wx) * 0.125f);
+        const float y0 = fmaxf(-1.f, (vr - oy - ey - wy) * 0.125f);
+        const float y1 = fminf((float)T, (vr - oy + ey + wy) * 0.125f);
+        const int bx0 = max(0, (int)floorf(x0)), bx1 = min(T / 8 - 1, (int)floorf(x1));
+        const int by0 = max(0, (int)floorf(y0)), by1 = min(T / 8 - 1, (int)floorf(y1));
         uint32_t m = 0;
         for (int by = by0; by <= by1; ++by)
           for (int bx = bx0; bx <= bx1; ++bx) m |= 1u << (by * (T / 8) + bx);
         s_ov[t] = m;
       }
-      if (RECORD) s_p[t] = qp;
+      if (RECORD) s_p[t] = __float_as_uint(qd.x);
     }
     __syncthreads();
     if (b0 + BATCH + t < end) {  // overlaps the compositing below
@@ -692,7 +786,7 @@ __device__ __forceinline__ void blend_item(
       qa = r[0];
       qb = r[1];
       qc = r[2];
-      if (RECORD) qp = __float_as_uint(r[3].x);
+      if (RECORD || T != 8) qd = *reinterpret_cast<const float2*>(r + 3);
     }
 #pragma unroll
     for (int j = 0; j < BPW; ++j) {

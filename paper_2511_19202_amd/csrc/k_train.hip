@@ -467,7 +467,7 @@ hipError_t launch_or_groups(const uint32_t* rows, int V, int group, int64_t word
 }
 
 size_t train_smem_bytes() { return sizeof(TrainSmem); }
-int train_num_params() { return kNumParams; }
+int train_num_params(int width) { return kIn * width + width + 2 * (width * width + width) + width + 1; }
 
 hipError_t launch_view_gam(const nvgs_camera* views, int V, float cam_scale, float train_focal, float d_max,
                            float* gam, hipStream_t st) {
@@ -501,19 +501,20 @@ static hipError_t launch_mlp_t(int nwg, int cpw, hipStream_t st, const float* pa
 }
 
 // mode: 0 train (sampled pairs, BCE), 1 forward (logits), 2 backward (given dlogits)
-hipError_t launch_mlp_train(int mode, bool bf16, int nwg, int chunks_per_wg, hipStream_t st, const float* params,
+hipError_t launch_mlp_train(int mode, bool bf16, int width, int nwg, hipStream_t st, const float* params,
                             int64_t batch, float inv_batch, const float* mean, int64_t n, float mean_scale,
                             const float* view_gam, int V, const uint32_t* labels, uint64_t seed, int64_t step,
                             const uint32_t* n_pos, const float* X, const float* dlogits, float* logits,
                             float* partial, float* loss_part, float* dX) {
+  constexpr int kPairsPerWG = 256;
+  if (bf16 || width != 64)
+    return launch_mlp_train_w(mode, bf16, width, nwg, kPairsPerWG, st, params, batch, inv_batch, mean, n,
+                              mean_scale, view_gam, V, labels, seed, step, n_pos, X, dlogits, logits, partial,
+                              loss_part, dX);
+  const int chunks_per_wg = kPairsPerWG / kTP;
 #define NVGS_MLPT(B, M)                                                                                             \
   return launch_mlp_t<B, M>(nwg, chunks_per_wg, st, params, batch, inv_batch, mean, n, mean_scale, view_gam, V,   \
                             labels, seed, step, n_pos, X, dlogits, logits, partial, loss_part, dX)
-  if (bf16) {
-    if (mode == 0) NVGS_MLPT(true, 0);
-    if (mode == 1) NVGS_MLPT(true, 1);
-    NVGS_MLPT(true, 2);
-  }
   if (mode == 0) NVGS_MLPT(false, 0);
   if (mode == 1) NVGS_MLPT(false, 1);
   NVGS_MLPT(false, 2);

@@ -21,7 +21,8 @@ import pytest
 import oracle
 import synth
 from tests import scenes
-from tests.test_gpu_parity import MARGIN, MARGIN_ALPHA, MARGIN_DEPTH, _logit_scale, _same_input_rect, logit_tol
+from tests.protocol import MARGIN, check_pixels
+from tests.test_gpu_parity import _logit_scale, _same_input_rect, logit_tol
 
 pytestmark = pytest.mark.gpu
 
@@ -59,10 +60,14 @@ def _ctx(nvgs, sc):
     return ctx
 
 
-def test_full_size_query(nvgs, full):
+@pytest.mark.parametrize("prec", ["fp32", "fp32s"])
+def test_full_size_query(nvgs, full, prec):
+    """Keep states over all 16M pairs and logits of a 20,000-pair sample, for
+    the FP32 matrix-core MLP and the split form (three BF16 products per FP32
+    product), against the FP64 oracle."""
     sc, ost, olg, omg = full
     ctx = _ctx(nvgs, sc)
-    st, lg = ctx.query_visibility(sc.cameras)
+    st, lg = ctx.query_visibility(sc.cameras, precision=prec)
     st = st.cpu().numpy()
     lg = lg.cpu().numpy().astype(np.float64)
     ctx.close()
@@ -85,7 +90,7 @@ def test_full_size_query(nvgs, full):
         inst = sc.instances[int(i)]
         scale[sel] = _logit_scale(sc.assets[inst.asset], inst, sc.cameras[0], p_of[sel] - off[i])
     err = np.abs(lg.ravel()[sample] - z64)
-    log(f"[full] logits: sample {len(sample)}, max err/tol {np.max(err / logit_tol(z64, scale)):.3f}")
+    log(f"[full] {prec} logits: sample {len(sample)}, max err/tol {np.max(err / logit_tol(z64, scale)):.3f}")
     assert np.all(err <= logit_tol(z64, scale))
 
 
@@ -131,31 +136,15 @@ def test_full_size_binning_and_sort(nvgs, full):
     assert np.array_equal(sid, owner[order])
 
 
-def _check_pixels(img, ref, label, tol):
-    dimg = np.abs(img.astype(np.float64) - ref["image"]).max(axis=2)
-    bad = dimg > 1e-4
-    tie_a = ref["margin"][..., 0] < MARGIN_ALPHA
-    tie_d = ref["margin"][..., 1] < MARGIN_DEPTH
-    excused = bad & (tie_a | tie_d)
-    other = float(np.max(np.where(excused, 0.0, dimg)))
-    log(f"[full] {label}: max pixel err {dimg.max():.3e}, >1e-4: {int(bad.sum())} (excused {int(excused.sum())}: "
-        f"alpha/stop {int(np.sum(bad & tie_a))}, depth order {int(np.sum(bad & tie_d))}); others at most {other:.2e}")
-    assert other <= tol
-    assert bad.sum() <= 1e-2 * dimg.size
-
-
 def test_full_size_graph_frame_matches_oracle(nvgs, full):
     """The graph frame against the oracle's compositing of the same splats,
     binned with the GPU's tile rectangles (footprints are checked on their own
     above).  Same input: the oracle composites the GPU's projected records in
     FP64, and every pixel is within 1e-4 unless an alpha, stop or depth-order
     decision there lies within FP32 resolution (at ~300 fragments per pixel
-    many pixels hold two fragments that close in depth, so the excused share
-    is larger than in the small scenes; it stays below 1 %).  From scratch:
-    the oracle's own FP64 projection; the FP32 centre of a 1080p splat is off
-    by up to ~1e-4 px and the sharpest splats (dilated variance >= 0.3 px^2)
-    change alpha by up to ~3x per pixel of offset, so these pixels are held to
-    1e-3."""
+    many pixels hold two fragments that close in depth; each excusal is
+    counted and logged).  From scratch: the oracle's own FP64 projection,
+    under the same 1e-4 protocol."""
     import torch
     sc = full[0]
     cam = sc.cameras[0]
@@ -183,9 +172,12 @@ def test_full_size_graph_frame_matches_oracle(nvgs, full):
     rec_g[:, 0], rec_g[:, 1], rec_g[:, 5], rec_g[:, 6], rec_g[:, 7] = ra[:, 0], ra[:, 1], ra[:, 2], ra[:, 3], rb[:, 0]
     rec_g[:, 8], rec_g[:, 9] = rc[:, 1], rb[:, 1]
     rec_g[:, 10], rec_g[:, 11], rec_g[:, 12] = rb[:, 2], rb[:, 3], rc[:, 0]
-    _check_pixels(img[0], oracle.render_camera(rec_g, prect, cam, TILE, sc.bg), "compositing (same input)", 1e-4)
+    rd = d["rec_d"].astype(np.float64)  # the centre's low-order parts
+    rec_g[:, 0] += rd[:, 0]
+    rec_g[:, 1] += rd[:, 1]
+    check_pixels(img[0], oracle.render_camera(rec_g, prect, cam, TILE, sc.bg), "full size, same input")
     rec, _ = oracle.project(sc, cam, kept)
-    _check_pixels(img[0], oracle.render_camera(rec, prect, cam, TILE, sc.bg), "from scratch", 1e-3)
+    check_pixels(img[0], oracle.render_camera(rec, prect, cam, TILE, sc.bg), "full size, from scratch")
 
 
 def test_full_size_batched_frame(nvgs):
@@ -203,35 +195,44 @@ def test_full_size_batched_frame(nvgs):
     log("[full] batched scene: 16 assets, 1024 instances, 8 cameras")
     sc = synth.scene_batched()
     ctx = _ctx(nvgs, sc)
-    # output biases set so that 29 % of each asset's in-frustum pairs of camera
-    # 0 keep (the trained networks' rate on this workload); the threshold is
-    # taken from the kernel's FP32 logits, as an input setting only: the
-    # oracle below runs the resulting weights through its own MLP
-    _, lg = ctx.query_visibility(sc.cameras[:1])
-    lg = lg[0].cpu().numpy()
-    off = sc.pair_offsets()
+    # output biases set so that about 29 % of each asset's pairs keep (the
+    # trained networks' rate on this workload): the threshold is the oracle's
+    # FP64 logit quantile over a seeded sample of (instance, Gaussian) pairs
+    # of camera 0 (an input setting; the checks below use the oracle's own MLP)
+    rng = np.random.default_rng(7)
+    cam0 = sc.cameras[0]
     for a_idx, a in enumerate(sc.assets):
-        z = np.concatenate([lg[off[i]:off[i + 1]] for i, inst in enumerate(sc.instances) if inst.asset == a_idx])
-        z = np.sort(z[~np.isnan(z)])
-        if len(z) < 2:
-            continue
-        j = int(np.clip(round(0.71 * len(z)), 1, len(z) - 1))
+        insts = [inst for inst in sc.instances if inst.asset == a_idx][:8]
+        z = []
+        for inst in insts:
+            gidx = rng.integers(0, a.n, 2048)
+            cl = oracle.local_camera(inst, cam0, a.mlp.train_focal, a.mlp.d_max)
+            z.append(oracle.mlp_forward(a.mlp.params, a.mlp.width, oracle.mlp_inputs(a, gidx, cl))[0])
+        z = np.sort(np.concatenate(z))
         p = a.mlp.params.copy()
-        p[-1] = np.float32(p[-1] - 0.5 * (z[j - 1] + z[j]))  # the output bias
+        p[-1] = np.float32(p[-1] - z[int(0.71 * len(z))])  # the output bias
         a.mlp.params = p
-    del lg
     ctx.load_assets(sc.assets)
     ctx.set_instances(sc.instances)
     st, _ = ctx.query_visibility(sc.cameras, want_logits=False)
+    off = sc.pair_offsets()
+    # sampled (camera, instance) segments, drawn until six hold in-frustum pairs
     pick = np.random.default_rng(11)
-    for k, i in zip(pick.integers(0, len(sc.cameras), 6), pick.integers(0, len(sc.instances), 6)):
-        k, i = int(k), int(i)
+    checked = tried = 0
+    while checked < 6:
+        tried += 1
+        assert tried <= 200, "too few (camera, instance) segments with in-frustum pairs"
+        k, i = int(pick.integers(0, len(sc.cameras))), int(pick.integers(0, len(sc.instances)))
         sub = synth.Scene(assets=sc.assets, instances=[sc.instances[i]], cameras=[sc.cameras[k]], tile=sc.tile)
         ost, _, omg = oracle.query(sub, want_margin=True)
+        if not np.any(ost[0] > 0):
+            continue
+        checked += 1
         g = st[k, off[i]:off[i + 1]].cpu().numpy()
         diff = g != ost[0]
-        log(f"[full] camera {k}, instance {i}: {g.size} pairs, {int((g == 2).sum())} kept, "
-            f"mismatches {int(diff.sum())} (excused {int(np.sum(diff & (omg[0] < MARGIN)))})")
+        log(f"[full] camera {k}, instance {i}: {g.size} pairs, {int((ost[0] > 0).sum())} in frustum, "
+            f"{int((ost[0] == 2).sum())} kept by the oracle, mismatches {int(diff.sum())} "
+            f"(excused {int(np.sum(diff & (omg[0] < MARGIN)))})")
         assert np.sum(diff & ~(omg[0] < MARGIN)) == 0
     del st
     kw = dict(tile=TILE, precision="bf16")

@@ -19,15 +19,7 @@ from tests import scenes
 
 pytestmark = pytest.mark.gpu
 
-MARGIN = 1e-5  # relative FP64 margin of frustum / keep decisions below which FP32 may differ
-# Alpha and transmittance decisions at a pixel: the FP32 quadratic form
-# q = d^T conic d of an elongated splat carries a relative error of about
-# kappa * 2^-24 (kappa = condition number of Sigma2D, up to ~1e3 here) and
-# alpha = o e^(-q/2) near 1/255 has q ~ 11, so alpha's relative error reaches
-# ~1e-3 / 2; decisions closer than this to the 1/255 or 1e-4 thresholds may
-# flip.  Depth-order ties: FP32 depth keys resolve ~1e-7 relative.
-MARGIN_ALPHA = 1e-3
-MARGIN_DEPTH = 1e-6
+from tests.protocol import MARGIN, MARGIN_ALPHA, MARGIN_DEPTH, check_pixels, rect_bound_margin  # noqa: F401
 
 
 def log(*a):
@@ -74,12 +66,20 @@ def _logit_scale(a, inst, cam, gidx):
     return oracle.mlp_forward(a.mlp.params, a.mlp.width, oracle.mlp_inputs(a, gidx, cl))[1]
 
 
-@pytest.mark.parametrize("name", list(SCENES))
-def test_query_state_and_logits(nvgs, name):
+QUERY_CASES = [(name, "fp32") for name in SCENES] + \
+    [(name, "fp32s") for name in ("tiny", "tiny_w128", "composed_small", "batched_small")]
+
+
+@pytest.mark.parametrize("name,prec", QUERY_CASES)
+def test_query_state_and_logits(nvgs, name, prec):
+    """FP32 logits (FP32 matrix cores, and the split form: three BF16
+    products per FP32 product) within 1e-5 of the logit scale of the FP64
+    oracle's; keep states exact on the kernel's own logits and from scratch
+    up to the decision margin."""
     sc = SCENES[name]()
-    log(f"[query] scene={name}")
+    log(f"[query] scene={name} precision={prec}")
     ctx = make_ctx(nvgs, sc)
-    st, lg = ctx.query_visibility(sc.cameras)
+    st, lg = ctx.query_visibility(sc.cameras, precision=prec)
     st = st.cpu().numpy()
     lg = lg.cpu().numpy().astype(np.float64)
     ost, olg, omg = oracle.query(sc, want_margin=True)
@@ -101,7 +101,7 @@ def test_query_state_and_logits(nvgs, name):
             scale[sel] = _logit_scale(sc.assets[inst.asset], inst, sc.cameras[int(k)], p_of[sel] - off[i])
     err = np.abs(lg[both] - z64)
     tol = logit_tol(z64, scale)
-    log(f"[query] {name}: queried {both.sum()}, max |dz| {err.max():.3e}, max err/tol {np.max(err / tol):.3f}")
+    log(f"[query] {name} {prec}: queried {both.sum()}, max |dz| {err.max():.3e}, max err/tol {np.max(err / tol):.3f}")
     assert np.all(err <= tol)
     # same input: the keep rule applied to the GPU's logits reproduces its state
     gq = ~np.isnan(lg)
@@ -160,8 +160,14 @@ def test_frame_stages_against_oracle(nvgs, name, tile):
     # --- projection vs FP64 oracle on the same kept list
     rec, prect = oracle.project(sc, cam, kept_ref)
     ra, rb, rc = r["rec_a"].astype(np.float64), r["rec_b"].astype(np.float64), r["rec_c"].astype(np.float64)
-    np.testing.assert_allclose(ra[:, 0], rec[:, 0], rtol=0, atol=2e-3)       # u (pixels)
-    np.testing.assert_allclose(ra[:, 1], rec[:, 1], rtol=0, atol=2e-3)       # v
+    rd = r["rec_d"].astype(np.float64)
+    # the centre as hi + lo parts, against FP64 (hi alone is the nearest float)
+    du = np.abs(ra[:, 0] + rd[:, 0] - rec[:, 0]).max(initial=0.0)
+    dv = np.abs(ra[:, 1] + rd[:, 1] - rec[:, 1]).max(initial=0.0)
+    log(f"[frame] {name}: centre max err u {du:.2e} px, v {dv:.2e} px")
+    assert du < 2e-6 and dv < 2e-6
+    np.testing.assert_allclose(ra[:, 0], rec[:, 0], rtol=0, atol=np.spacing(np.float32(W)))  # u (pixels)
+    np.testing.assert_allclose(ra[:, 1], rec[:, 1], rtol=0, atol=np.spacing(np.float32(H)))  # v
     np.testing.assert_allclose(rc[:, 1], rec[:, 8], rtol=2e-6)               # depth
     np.testing.assert_allclose(rb[:, 1], rec[:, 9], rtol=0, atol=0)          # opacity
     for gi, oi in [(ra[:, 2], 5), (ra[:, 3], 6), (rb[:, 0], 7)]:             # conic
@@ -185,8 +191,11 @@ def test_frame_stages_against_oracle(nvgs, name, tile):
     both = ~oempty & (gn > 0)
     mism[both] |= (prect[both, 0] // tile != gx0[both]) | (prect[both, 1] // tile != gx1[both]) | \
                    (prect[both, 2] // tile != gy0[both]) | (prect[both, 3] // tile != gy1[both])
-    log(f"[frame] {name}: rect mismatches vs FP64 {mism.sum()} of {ns}")
-    assert mism.sum() <= max(3, 1e-3 * ns)
+    dist, close = rect_bound_margin(rec, W, H)
+    log(f"[frame] {name}: rect mismatches vs FP64 {mism.sum()} of {ns}, all with a bound within "
+        f"{dist[mism].max(initial=0.0):.1e} px of a pixel line" if mism.any() else
+        f"[frame] {name}: rect mismatches vs FP64 0 of {ns}")
+    assert not np.any(mism & ~close)
     # --- sort order: the (tile, depth, id) order of the kernel's own keys
     sk = r["sorted_key"].astype(np.int64) & 0xFFFFFFFF
     sid = r["sorted_id"].astype(np.int64) & 0xFFFFFFFF
@@ -205,12 +214,7 @@ def test_frame_stages_against_oracle(nvgs, name, tile):
     assert np.array_equal(sk, ent_t[order]) and np.array_equal(sid, ent_i[order])
     # --- pixels vs the FP64 oracle from scratch
     ref = oracle.render_camera(rec, prect, cam, tile, sc.bg)
-    dimg = np.abs(r["img"][0] - ref["image"]).max(axis=2)
-    bad = dimg > 1e-4
-    excused = bad & ((ref["margin"][..., 0] < MARGIN_ALPHA) | (ref["margin"][..., 1] < MARGIN_DEPTH))
-    log(f"[frame] {name}: max pixel err {dimg.max():.3e}, >1e-4: {bad.sum()} (excused {excused.sum()})")
-    assert np.sum(bad & ~excused) == 0
-    assert bad.sum() <= max(4, 1e-3 * dimg.size)
+    check_pixels(r["img"][0], ref, f"frame {name} T={tile}")
 
 
 def test_image_independent_of_tile_size_and_deterministic(nvgs):
@@ -252,15 +256,11 @@ def test_split_lists_match_sequential_and_oracle(nvgs, name, tile):
     kept = np.flatnonzero(st[0] == 2)
     rec, prect = oracle.project(sc, cam, kept)
     ref = oracle.render_camera(rec, prect, cam, tile, sc.bg)
-    d = np.abs(img[0] - ref["image"]).max(axis=2)
-    bad = d > 1e-4
-    m = ref["margin"]
-    excused = bad & ((m[..., 0] < MARGIN_ALPHA) | (m[..., 1] < MARGIN_DEPTH))
     dc = np.abs(cb_split - cb_seq)
     log(f"[split] {name} T={tile}: {stats['duplicates']} entries; max |split - sequential| {d_seq:.2e}; "
-        f"vs FP64 max {d.max():.2e}, >1e-4 {bad.sum()} (excused {excused.sum()}); contrib max diff {dc.max():.2e}")
+        f"contrib max diff {dc.max():.2e}")
+    check_pixels(img[0], ref, f"split {name} T={tile}")
     assert d_seq < 1e-5 or np.sum(np.abs(img - seq) > 1e-5) <= max(4, 1e-3 * img[..., 0].size)
-    assert np.sum(bad & ~excused) == 0
     assert np.mean(dc <= 1e-5 * np.maximum(cb_seq, 1e-3)) > 0.999
 
 
@@ -270,12 +270,7 @@ def test_unculled_render_matches_oracle(nvgs):
     img = ctx.render(sc.cameras, tile=16, use_mlp=False).cpu().numpy()[0].astype(np.float64)
     ctx.close()
     ref = oracle.frame(sc, use_mlp=False)
-    d = np.abs(img - ref["images"][0]).max(axis=2)
-    m = ref["margin"][0]
-    bad = d > 1e-4
-    excused = bad & ((m[..., 0] < MARGIN_ALPHA) | (m[..., 1] < MARGIN_DEPTH))
-    log(f"[unculled] max err {d.max():.3e}, bad {bad.sum()} excused {excused.sum()}")
-    assert np.sum(bad & ~excused) == 0
+    check_pixels(img, {"image": ref["images"][0], "margin": ref["margin"][0]}, "unculled tiny")
 
 
 def test_empty_frame_and_invalid_arguments(nvgs):
@@ -395,16 +390,15 @@ def test_radius_clipping_matches_oracle(nvgs):
     ctx.close()
     rec, prect = oracle.project(sc, cam, kept, det_clip=tau)
     oempty = (prect[:, 0] > prect[:, 1]) | (prect[:, 2] > prect[:, 3])
+    # the FP32 determinant (a sum of non-negative terms) is within a few 1e-7
+    # relative of FP64; a clip decision closer than 1e-5 may go either way,
+    # as may an empty rectangle whose bound sits on a pixel line
     near = np.abs(det - tau) < 1e-5 * tau
+    _, close = rect_bound_margin(rec0, cam.width, cam.height)
     mism = oempty != (gn == 0)
     log(f"[clip] tau {tau:.4g}: oracle clips {np.sum(det < tau)} of {len(det)}, mismatches {mism.sum()} "
-        f"(near threshold {np.sum(mism & near)})")
+        f"(determinant near the threshold {np.sum(mism & near)}, a bound on a pixel line {np.sum(mism & close)})")
     assert np.sum(det < tau) > 0.3 * len(det)
-    assert np.sum(mism & ~near) <= max(3, 1e-3 * len(det))
+    assert not np.any(mism & ~near & ~close)
     ref = oracle.render_camera(rec, prect, cam, 16, sc.bg)
-    d = np.abs(img - ref["image"]).max(axis=2)
-    bad = d > 1e-4
-    m = ref["margin"]
-    excused = bad & ((m[..., 0] < MARGIN_ALPHA) | (m[..., 1] < MARGIN_DEPTH))
-    log(f"[clip] max pixel err {d.max():.3e}, >1e-4 {bad.sum()} (excused {excused.sum()})")
-    assert np.sum(bad & ~excused) <= max(4, 1e-3 * d.size)
+    check_pixels(img, ref, "radius clipping")

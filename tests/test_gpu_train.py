@@ -8,6 +8,7 @@ import pytest
 
 import oracle
 import synth
+from tests.protocol import MARGIN_ALPHA, MARGIN_DEPTH
 
 pytestmark = pytest.mark.gpu
 
@@ -28,9 +29,9 @@ def env():
     ctx.close()
 
 
-def _batch(B, seed):
+def _batch(B, seed, width=64):
     g = np.random.default_rng(seed)
-    p = synth.mlp_params(64, synth.rng(seed)).astype(np.float32)
+    p = synth.mlp_params(width, synth.rng(seed)).astype(np.float32)
     X = g.uniform(-1, 1, (B, 72)).astype(np.float32)
     y = (g.uniform(0, 1, B) > 0.5).astype(np.float64)
     return p, X, y
@@ -42,36 +43,54 @@ def _grad_close(dg, do, tol=1e-3):
     return np.linalg.norm(dg - do) / np.linalg.norm(do), rel
 
 
-@pytest.mark.parametrize("B", [300, 1024, 65536])  # 65,536: the differentiation workload's batch
-def test_mlp_forward_backward_fp32_vs_oracle(env, B):
+@pytest.mark.parametrize("width,B", [(64, 300), (64, 1024), (64, 65536), (128, 300), (128, 1024), (128, 4133)])
+def test_mlp_forward_backward_fp32_vs_oracle(env, width, B):
+    """FP32 forward and hand-written backward against the FP64 oracle at both
+    widths (65,536: the differentiation workload's batch; 4,133: several
+    work-groups and a ragged last chunk at width 128)."""
     nvgs, ctx, torch = env
-    p, X, y = _batch(B, 5 + B)
-    z64, scale = oracle.mlp_forward(p, 64, X)
+    p, X, y = _batch(B, 5 + B, width)
+    z64, scale = oracle.mlp_forward(p, width, X)
     zg = ctx.mlp_forward(torch.from_numpy(p).cuda(), torch.from_numpy(X).cuda()).cpu().numpy()
-    assert np.all(np.abs(zg - z64) <= 1e-5 * np.maximum(np.abs(z64), scale))
+    err = np.abs(zg - z64) / (1e-5 * np.maximum(np.abs(z64), scale))
+    log(f"[grad] W={width} B={B}: logits max err/tol {err.max():.3f}")
+    assert np.all(err <= 1.0)
     dlog = ((1 / (1 + np.exp(-z64)) - y) / B).astype(np.float32)
-    loss, dP, dX = oracle.bce_backward(p, 64, X, y, want_dx=True)
+    loss, dP, dX = oracle.bce_backward(p, width, X, y, want_dx=True)
     dp_g, dx_g = ctx.mlp_backward(torch.from_numpy(p).cuda(), torch.from_numpy(X).cuda(), torch.from_numpy(dlog).cuda())
     nrm, rel = _grad_close(dp_g.cpu().numpy().astype(np.float64), dP)
-    log(f"[grad] B={B}: param grad rel norm err {nrm:.2e}, max rel {rel.max():.2e}")
+    log(f"[grad] W={width} B={B}: param grad rel norm err {nrm:.2e}, max rel {rel.max():.2e}")
     assert nrm < 1e-3 and np.mean(rel < 1e-3) > 0.999
     nrm_x, rel_x = _grad_close(dx_g.cpu().numpy().astype(np.float64), dX)
+    log(f"[grad] W={width} B={B}: input grad rel norm err {nrm_x:.2e}")
     assert nrm_x < 1e-3
 
 
-def test_mlp_backward_bf16_cosine(env):
+@pytest.mark.parametrize("width", [64, 128])
+def test_mlp_backward_bf16_cosine(env, width):
+    """The BF16 form (BF16 matrix-core GEMMs, FP32 accumulation): logits near
+    FP64's, and the parameter gradient points the FP64 way (cosine >= 0.999).
+    The input gradient's last product has BF16 operands on both sides and no
+    sum over the batch to average their rounding, so it is held to 0.99."""
     nvgs, ctx, torch = env
     B = 2048
-    p, X, y = _batch(B, 9)
-    z64, _ = oracle.mlp_forward(p, 64, X)
+    p, X, y = _batch(B, 9, width)
+    z64, scale = oracle.mlp_forward(p, width, X)
+    zb = ctx.mlp_forward(torch.from_numpy(p).cuda(), torch.from_numpy(X).cuda(), precision="bf16").cpu().numpy()
+    zerr = np.abs(zb - z64) / scale  # BF16 operands: about 2^-9 relative each
+    log(f"[grad] W={width} bf16 logits vs FP64: error / logit scale median {np.median(zerr):.2e}, "
+        f"max {zerr.max():.2e}")
+    assert np.median(zerr) < 5e-3 and zerr.max() < 5e-2
     dlog = ((1 / (1 + np.exp(-z64)) - y) / B).astype(np.float32)
-    _, dP = oracle.bce_backward(p, 64, X, y)
-    dp_g, _ = ctx.mlp_backward(torch.from_numpy(p).cuda(), torch.from_numpy(X).cuda(), torch.from_numpy(dlog).cuda(),
-                               precision="bf16", want_dx=False)
+    _, dP, dX = oracle.bce_backward(p, width, X, y, want_dx=True)
+    dp_g, dx_g = ctx.mlp_backward(torch.from_numpy(p).cuda(), torch.from_numpy(X).cuda(),
+                                  torch.from_numpy(dlog).cuda(), precision="bf16")
     g = dp_g.cpu().numpy().astype(np.float64)
     cos = float(np.dot(g, dP) / (np.linalg.norm(g) * np.linalg.norm(dP)))
-    log(f"[grad] bf16 cosine similarity to FP64 gradient {cos:.6f}")
-    assert cos >= 0.999
+    gx = dx_g.cpu().numpy().astype(np.float64).ravel()
+    cos_x = float(np.dot(gx, dX.ravel()) / (np.linalg.norm(gx) * np.linalg.norm(dX)))
+    log(f"[grad] W={width} bf16 cosine similarity to the FP64 gradient: params {cos:.6f}, inputs {cos_x:.6f}")
+    assert cos >= 0.999 and cos_x >= 0.99
 
 
 def test_autograd_function(env):
@@ -90,37 +109,63 @@ def test_autograd_function(env):
     assert _grad_close(Xt.grad.cpu().numpy().astype(np.float64), dX)[0] < 1e-3
 
 
-def _small_asset(n=3000, seed=4):
-    a = synth.make_asset("torus", n, 0, seed, width=64, cam_scale=1.0 / 20.0, d_max=20.0)
+def _small_asset(n=3000, seed=4, width=64):
+    a = synth.make_asset("torus", n, 0, seed, width=width, cam_scale=1.0 / 20.0, d_max=20.0)
     a.opacity[:] = np.clip(a.opacity * 1.2, 0, 1)
     a.scale[:] *= 2.0
     return a
 
 
+def _label_bits(lab, V, n):
+    return np.unpackbits(lab.view(np.uint8).reshape(V, -1), axis=1, bitorder="little")[:, :n].astype(bool)
+
+
+def _label_excusal(cb, smg):
+    """Label decisions the FP32 renderer may take differently from FP64: the
+    contribution itself within MARGIN_ALPHA (relative) of 1/255, or a decision
+    that shapes it (an alpha or stop test, the depth order of two fragments)
+    within margin at a pixel where the Gaussian was tested or listed after a
+    stop.  cb [V, n], smg [V, n, 2] from the oracle."""
+    near = np.abs(cb - 1 / 255) < MARGIN_ALPHA / 255
+    return near | (smg[..., 0] < MARGIN_ALPHA) | (smg[..., 1] < MARGIN_DEPTH)
+
+
+def _check_labels(bits, cb, smg, label):
+    ref = cb > 1 / 255
+    diff = bits != ref
+    exc = _label_excusal(cb, smg)
+    log(f"[labels {label}] {ref.mean():.3f} visible; mismatches {diff.sum()} of {diff.size} "
+        f"(excused: contribution near 1/255 {np.sum(diff & (np.abs(cb - 1 / 255) < MARGIN_ALPHA / 255))}, "
+        f"a decision in margin {np.sum(diff & exc)})")
+    assert not np.any(diff & ~exc)
+    return ref
+
+
 @pytest.mark.parametrize("aux", [0, 6])
 def test_labels_match_oracle(env, aux):
     """Labels rendered by the library equal the oracle's (largest alpha*T over
-    the view and its auxiliary views above 1/255) away from the threshold."""
+    the view and its auxiliary views above 1/255) except where a decision that
+    shapes the contribution is within the FP32 margin."""
     nvgs, ctx, torch = env
     a = _small_asset()
     views = synth.label_views(6, seed=3, d_lo=2.0, d_hi=4.0, res=96, offset=0.2)
     ang = math.radians(5.0)
     ctx.load_assets([a])
     lab = ctx.make_labels(0, views, aux=aux, aux_angle=ang).cpu().numpy().view(np.uint32)
-    bits = np.unpackbits(lab.view(np.uint8).reshape(len(views), -1), axis=1, bitorder="little")[:, :a.n]
-    cb = np.stack([oracle.contributions(a, [v] + oracle.aux_views(v, aux, ang)).max(axis=0) for v in views])
-    ref = cb > 1 / 255
-    diff = bits.astype(bool) != ref
-    near = np.abs(cb - 1 / 255) < 2e-3 / 255
-    log(f"[labels aux={aux}] {ref.mean():.3f} visible; mismatches {diff.sum()} (near threshold {np.sum(diff & near)})")
+    bits = _label_bits(lab, len(views), a.n)
+    cb, smg = [], []
+    for v in views:
+        c, _, m = oracle.contributions(a, [v] + oracle.aux_views(v, aux, ang), want_detail=True)
+        cb.append(c.max(axis=0))
+        smg.append(m.min(axis=0))
+    ref = _check_labels(bits, np.stack(cb), np.stack(smg), f"aux={aux}")
     assert 0.1 < ref.mean() < 0.95
-    assert np.sum(diff & ~near) <= max(2, 1e-4 * diff.size)
 
 
 def test_labels_full_size(env):
     """Labels of the differentiation workload's own asset (500k SH3
     Gaussians) on three of its 512 label views at 512x512, against the
-    oracle's largest alpha*T per Gaussian, away from the threshold."""
+    oracle's largest alpha*T per Gaussian, under the same margin rule."""
     nvgs, ctx, torch = env
     sc = synth.scene_train()
     a = sc.assets[0]
@@ -128,24 +173,100 @@ def test_labels_full_size(env):
     views = [views[j] for j in (0, 171, 342)]
     ctx.load_assets([a])
     lab = ctx.make_labels(0, views).cpu().numpy().view(np.uint32)
-    bits = np.unpackbits(lab.view(np.uint8).reshape(len(views), -1), axis=1, bitorder="little")[:, :a.n]
-    cb = oracle.contributions(a, views)
-    ref = cb > 1 / 255
-    diff = bits.astype(bool) != ref
-    near = np.abs(cb - 1 / 255) < 2e-3 / 255
-    log(f"[labels full size] {a.n} Gaussians x {len(views)} views: {ref.mean():.3f} visible; mismatches "
-        f"{diff.sum()} (near threshold {np.sum(diff & near)})")
+    bits = _label_bits(lab, len(views), a.n)
+    cb, _, smg = oracle.contributions(a, views, want_detail=True)
+    ref = _check_labels(bits, cb, smg, f"full size {a.n} x {len(views)}")
     assert 0.01 < ref.mean() < 0.95
-    assert np.sum(diff & ~near) <= max(2, 1e-4 * diff.size)
 
 
-@pytest.mark.parametrize("weighting", [0, 1])
-def test_training_step_matches_oracle(env, weighting):
+def test_labels_same_input(env):
+    """Same input: label bits recomputed on the host from the renderer's own
+    recorded contributions (frames of the same views, tile and chunking)
+    equal the library's label bits exactly."""
+    nvgs, ctx, torch = env
+    a = _small_asset(n=20000, seed=8)
+    views = synth.label_views(12, seed=9, d_lo=1.5, d_hi=6.0, res=128, offset=0.2)
+    ctx.load_assets([a])
+    lab = ctx.make_labels(0, views, tile=16).cpu().numpy().view(np.uint32)
+    bits = _label_bits(lab, len(views), a.n)
+    ctx.set_instances([synth.identity_instance(0)])
+    cb = torch.zeros((len(views), a.n), device="cuda")
+    ctx.render(views, tile=16, use_mlp=False, contrib=cb)
+    cb = cb.cpu().numpy()
+    host = cb > np.float32(1 / 255)
+    log(f"[labels same input] {host.mean():.3f} visible, {np.sum(bits != host)} differences")
+    assert np.array_equal(bits, host)
+
+
+def test_reached_and_ground_truth_visibility(env):
+    """Contributions and "reached" flags (contrib > 0) of a frame against the
+    oracle's, under the margin rule; then the ground-truth-visibility
+    invariant on the GPU: removing every pair the renderer never reached
+    (contrib == 0: skipped wherever tested, or listed after the stop) leaves
+    every pixel bit-identical, and removing every pair it never blended (also
+    the fragments that stopped a pixel) changes no pixel by more than that
+    pixel's transmittance at the stop (T_final, read as the difference of a
+    white- and a black-background frame) times the largest colour."""
+    nvgs, ctx, torch = env
+    a = _small_asset(n=20000, seed=10)
+    cam = synth.label_views(1, seed=12, d_lo=2.5, d_hi=2.5, res=128)[0]
+    ctx.load_assets([a])
+    ctx.set_instances([synth.identity_instance(0)])
+    cb = torch.zeros(a.n, device="cuda")
+    img = ctx.render([cam], tile=16, use_mlp=False, contrib=cb, split=-1).cpu().numpy()[0]
+    white = ctx.render([cam], tile=16, use_mlp=False, bg=(1.0, 1.0, 1.0), split=-1).cpu().numpy()[0]
+    cb = cb.cpu().numpy()
+    reached_g = cb > 0
+    c64, r64, smg = oracle.contributions(a, [cam], want_detail=True)
+    exc = (smg[0, :, 0] < MARGIN_ALPHA) | (smg[0, :, 1] < MARGIN_DEPTH)
+    dr = reached_g != r64[0].astype(bool)
+    log(f"[reached] GPU {reached_g.sum()}, oracle {int(r64.sum())} of {a.n}; mismatches {dr.sum()} "
+        f"(excused {np.sum(dr & exc)})")
+    assert not np.any(dr & ~exc)
+    blended = cb >= np.finfo(np.float32).tiny
+    both = blended & (c64[0] > 0) & ~exc
+    rel = np.abs(cb[both] - c64[0][both]) / c64[0][both]
+    log(f"[reached] contributions of {both.sum()} blended pairs: max rel err {rel.max():.2e}")
+    assert rel.max() < MARGIN_ALPHA
+    assert reached_g.sum() > blended.sum() > 0.2 * a.n  # some pairs stop a pixel without blending
+
+    def without(keep):
+        b = synth.Asset(mean=a.mean, scale=a.scale, quat=a.quat, opacity=np.where(keep, a.opacity, 0).astype(np.float32),
+                        sh=a.sh, sh_degree=a.sh_degree, mlp=a.mlp)
+        ctx.load_assets([b])
+        ctx.set_instances([synth.identity_instance(0)])
+        return ctx.render([cam], tile=16, use_mlp=False, split=-1).cpu().numpy()[0]
+
+    img_r = without(reached_g)
+    log(f"[ground truth] removing {np.sum(~reached_g)} never-reached pairs: max change {np.abs(img_r - img).max():.2e}")
+    assert np.array_equal(img_r, img)
+    img_b = without(blended)
+    t_final = (white - img)[..., 0]
+    bound = t_final * _max_colour(a, cam)
+    dch = np.abs(img_b - img).max(axis=2)
+    log(f"[ground truth] removing {np.sum(~blended)} never-blended pairs: max change {dch.max():.2e}, "
+        f"{np.sum(dch > 1e-4)} pixels above 1e-4 (each within its T at the stop: worst ratio "
+        f"{np.max(dch / np.maximum(bound, 1e-30)):.3f})")
+    assert np.all(dch <= bound + 1e-6)
+    ctx.load_assets([a])
+
+
+def _max_colour(a, cam):
+    """Largest colour channel of the asset's in-frustum Gaussians seen from
+    cam (the oracle's SH colour, an upper bound per fragment)."""
+    sc = synth.Scene(assets=[a], instances=[synth.identity_instance(0)], cameras=[cam], tile=16)
+    st, _ = oracle.query(sc, use_mlp=False)
+    rec, _ = oracle.project(sc, cam, np.flatnonzero(st[0] == 2))
+    return float(rec[:, 10:13].max())
+
+
+@pytest.mark.parametrize("weighting,width", [(0, 64), (1, 64), (1, 128)])
+def test_training_step_matches_oracle(env, weighting, width):
     """One FP32 Adam step on oracle labels: the GPU's batch loss equals the
     oracle's on the same SplitMix64-drawn pairs, and the first Adam update
     (lr * sign(g) where |g| >> eps) agrees."""
     nvgs, ctx, torch = env
-    a = _small_asset(n=2000, seed=6)
+    a = _small_asset(n=2000, seed=6, width=width)
     views = synth.label_views(4, seed=5, d_lo=2.0, d_hi=4.0, res=64)
     lab = oracle.labels(a, views)
     words = (a.n + 31) // 32
@@ -169,8 +290,8 @@ def test_training_step_matches_oracle(env, weighting):
     if weighting:  # each sample weighted by B / (2 n_class)
         npos = y.sum()
         w = np.where(y > 0.5, B / (2 * npos), B / (2 * (B - npos)))
-    loss, dP = oracle.bce_backward(p0, 64, X, y, w=w)
-    log(f"[train] loss gpu {curve[0]:.6f} oracle {loss:.6f}")
+    loss, dP = oracle.bce_backward(p0, width, X, y, w=w)
+    log(f"[train] W={width}: loss gpu {curve[0]:.6f} oracle {loss:.6f}")
     assert abs(curve[0] - loss) < 1e-5 * max(1.0, loss)
     p64 = p0.astype(np.float64)
     m = np.zeros_like(p64); v = np.zeros_like(p64)
@@ -183,14 +304,61 @@ def test_training_step_matches_oracle(env, weighting):
     assert agree[big].mean() > 0.995
 
 
-def test_training_reduces_loss(env):
+def _oracle_inputs(a, views, g_idx, v_idx):
+    X = np.zeros((len(g_idx), 72))
+    for v in np.unique(v_idx):
+        sel = np.flatnonzero(v_idx == v)
+        cl = oracle.local_camera(synth.identity_instance(), views[v], a.mlp.train_focal, a.mlp.d_max)
+        X[sel] = oracle.mlp_inputs(a, g_idx[sel], cl)
+    return X
+
+
+def test_training_schedule_matches_oracle(env):
+    """The warm-up + exponential-decay schedule (Sec. 4.1) in training: four
+    FP32 steps with lr_final > 0 against the oracle's Adam run with the
+    oracle's schedule on the same SplitMix64 pairs (the learning rate of each
+    step scales its update, so a rate off by a step or a factor shows)."""
     nvgs, ctx, torch = env
-    a = _small_asset(n=4000, seed=8)
+    a = _small_asset(n=2000, seed=6)
+    views = synth.label_views(4, seed=5, d_lo=2.0, d_hi=4.0, res=64)
+    lab = oracle.labels(a, views)
+    words = (a.n + 31) // 32
+    packed = np.zeros((len(views), words * 32), np.uint8)
+    packed[:, :a.n] = lab
+    lab_words = np.packbits(packed, axis=1, bitorder="little").view(np.uint32).reshape(len(views), words)
+    ctx.load_assets([a])
+    p0 = a.mlp.params.astype(np.float32)
+    steps, B, seed, lr, lr_final = 10, 1000, 91, 2e-3, 2e-4
+    p64 = p0.astype(np.float64)
+    m = np.zeros_like(p64); v = np.zeros_like(p64)
+    rates = [oracle.lr_schedule(lr, lr_final, steps, t) for t in range(steps)]
+    for t in range(steps):
+        g_idx, v_idx = oracle.sample_pairs(seed, t, B, a.n, len(views))
+        X = _oracle_inputs(a, views, g_idx, v_idx)
+        _, dP = oracle.bce_backward(p64, 64, X, lab[v_idx, g_idx].astype(np.float64))
+        oracle.adam_step(p64, dP, m, v, t + 1, lr=rates[t])
+    pt = torch.from_numpy(p0.copy()).cuda()
+    ctx.train_visibility(0, views, pt, labels=torch.from_numpy(lab_words.view(np.int32)).cuda(), batch=B,
+                         steps=steps, precision="fp32", lr=lr, seed=seed, lr_final=lr_final)
+    dg = pt.cpu().numpy().astype(np.float64) - p0
+    do = p64 - p0
+    big = np.abs(do) > 0.5 * sum(rates)  # parameters whose updates kept one sign
+    rel = np.abs(dg - do) / np.abs(do)
+    log(f"[schedule] rates {['%.3g' % r for r in rates]}; {big.sum()} steadily moving parameters, "
+        f"update rel err median {np.median(rel[big]):.2e}, within 1e-3: {np.mean(rel[big] < 1e-3):.4f}")
+    assert rates[0] < rates[1] and rates[-1] == pytest.approx(lr_final, rel=1e-6)
+    assert big.sum() > 100 and np.mean(rel[big] < 1e-3) > 0.99
+
+
+@pytest.mark.parametrize("width", [64, 128])
+def test_training_reduces_loss(env, width):
+    nvgs, ctx, torch = env
+    a = _small_asset(n=4000, seed=8, width=width)
     views = synth.label_views(24, seed=9, d_lo=2.0, d_hi=6.0, res=96)
     ctx.load_assets([a])
     pt = torch.from_numpy(a.mlp.params.astype(np.float32).copy()).cuda()
     curve = ctx.train_visibility(0, views, pt, batch=4096, steps=300, precision="bf16", lr=3e-3, seed=1)
-    log(f"[train] loss {curve[0]:.4f} -> {curve[-20:].mean():.4f}")
+    log(f"[train] W={width}: loss {curve[0]:.4f} -> {curve[-20:].mean():.4f}")
     assert np.all(np.isfinite(curve))
     assert curve[-20:].mean() < 0.8 * curve[:5].mean()
 

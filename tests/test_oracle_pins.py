@@ -878,3 +878,33 @@ def test_compact_query_gate(orc):
     z, _ = orc.cmlp_forward(a.mlp.params, X)
     np.testing.assert_array_equal(lg[1][q], z)
     np.testing.assert_array_equal(st[1][q] == 2, z >= 0)
+
+
+def test_per_splat_decision_margins(orc):
+    """Per-splat margins of the decisions that decide a splat's contribution:
+    the three-opaque-splats case, where the second blend lands T exactly on
+    1e-4 (a knife edge), so every splat tested at or listed after that
+    decision carries its near-zero margin; the first splat's only decisions
+    are far from their thresholds (alpha 0.99, then T = 0.01: relative
+    margin 99 to 1e-4).  The splats are wide, so every pixel holds the stack."""
+    cam = axis_camera(4, 4)
+    rec = np.stack([_rec(1.5, 1.5, 1e6, 0, 1e6, 1.0 + k, 1.0, (1.0, 1.0, 1.0)) for k in range(4)])
+    sm = np.full((4, 2), np.inf)
+    orc.render_camera(rec, _full_rect(4, 4, 4), cam, 4, smargin=sm)
+    assert abs(sm[0, 0] - 99.0) < 1e-9 and sm[0, 1] == np.inf
+    assert np.all(sm[1:, 0] < 1e-10)
+    # depth gaps: (2 - 1) / 2 at the second splat, then (3 - 2) / 3
+    assert abs(sm[1, 1] - 0.5) < 1e-15 and abs(sm[2, 1] - 1.0 / 3.0) < 1e-15 and abs(sm[3, 1] - 1.0 / 3.0) < 1e-15
+    # the same stack without the knife edge (first alpha 0.9): wide margins,
+    # and the never-reached fourth splat inherits the stop decision's margin
+    rec[0, 9] = 0.9
+    sm = np.full((4, 2), np.inf)
+    rc = np.zeros(4, np.uint8)
+    orc.render_camera(rec, _full_rect(4, 4, 4), cam, 4, reached=rc, smargin=sm)
+    # T: 1 -> 0.1 -> 0.001 -> 1e-5 < 1e-4 (third splat stops the pixel)
+    assert rc.tolist() == [1, 1, 1, 0]
+    # (the off-centre pixels see alpha lower by ~1e-6 relative: the splat is
+    # wide, not infinite)
+    stop_margin = abs(0.1 * 0.01 * 0.01 - 1e-4) / 1e-4
+    assert abs(sm[3, 0] - min(stop_margin, abs(0.001 - 1e-4) / 1e-4, abs(0.1 - 1e-4) / 1e-4)) < 1e-4
+    assert abs(sm[0, 0] - (0.9 - 1 / 255) * 255) < 1e-2
