@@ -404,8 +404,9 @@ void orc_project(int64_t m, const int64_t* gidx, int64_t n, const float* mean, c
 //   reached [m] (set to 1 if tested with alpha >= 1/255 before the stop),
 //   margin [H][W][2] nullable: [0] smallest relative margin of any alpha /
 //   stop decision taken at the pixel, [1] smallest relative depth gap between
-//   consecutive fragments with alpha >= 1/255 (how close the pixel's blend
-//   order is to a tie).
+//   consecutive fragments with alpha >= 1/255, up to and including the first
+//   such fragment after the stop (how close the pixel's blend order is to a
+//   tie).
 //   order_out nullable: the sorted (tile, id) list, ntile_entries returned.
 //   smargin [m][2] nullable: per splat, the smallest pixel margins ([0] alpha /
 //   stop, [1] depth order, as in `margin`) of every decision taken at a pixel
@@ -492,6 +493,18 @@ int64_t orc_render(int64_t m, const double* rec, const int32_t* prect, const dou
         note(j, mg, mgd);
         if (reached) rch[tid][j] = 1;
         if (Tn < kTMin) {
+          // the next fragment with alpha >= 1/255 comes after the stop only
+          // by its depth: a renderer whose depths tie them may blend it
+          // before this one, so its depth gap is a decision margin too
+          for (int64_t k2 = k + 1; k2 < start[tile + 1]; ++k2) {
+            const double* r2 = rec + ent[k2].id * kRec;
+            const double ex = cx - r2[0], ey = cy - r2[1];
+            const double q2 = r2[5] * ex * ex + 2.0 * r2[6] * ex * ey + r2[7] * ey * ey;
+            if (std::min(kAlphaMax, r2[9] * std::exp(-0.5 * q2)) < kAlphaMin) continue;
+            mgd = std::min(mgd, (r2[8] - r[8]) / r2[8]);
+            break;
+          }
+          note(j, mg, mgd);
           for (int64_t k2 = k + 1; smargin && k2 < start[tile + 1]; ++k2) note(ent[k2].id, mg, mgd);
           break;
         }

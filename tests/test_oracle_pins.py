@@ -893,8 +893,9 @@ def test_per_splat_decision_margins(orc):
     orc.render_camera(rec, _full_rect(4, 4, 4), cam, 4, smargin=sm)
     assert abs(sm[0, 0] - 99.0) < 1e-9 and sm[0, 1] == np.inf
     assert np.all(sm[1:, 0] < 1e-10)
-    # depth gaps: (2 - 1) / 2 at the second splat, then (3 - 2) / 3
-    assert abs(sm[1, 1] - 0.5) < 1e-15 and abs(sm[2, 1] - 1.0 / 3.0) < 1e-15 and abs(sm[3, 1] - 1.0 / 3.0) < 1e-15
+    # depth gaps: (2 - 1) / 2 at the second splat, then (3 - 2) / 3, and at
+    # the stop the gap to the next fragment, (4 - 3) / 4
+    assert abs(sm[1, 1] - 0.5) < 1e-15 and abs(sm[2, 1] - 0.25) < 1e-15 and abs(sm[3, 1] - 0.25) < 1e-15
     # the same stack without the knife edge (first alpha 0.9): wide margins,
     # and the never-reached fourth splat inherits the stop decision's margin
     rec[0, 9] = 0.9
@@ -908,3 +909,21 @@ def test_per_splat_decision_margins(orc):
     stop_margin = abs(0.1 * 0.01 * 0.01 - 1e-4) / 1e-4
     assert abs(sm[3, 0] - min(stop_margin, abs(0.001 - 1e-4) / 1e-4, abs(0.1 - 1e-4) / 1e-4)) < 1e-4
     assert abs(sm[0, 0] - (0.9 - 1 / 255) * 255) < 1e-2
+
+
+def test_depth_margin_covers_the_fragment_after_the_stop(orc):
+    """The pixel stops at the third splat; a fourth lies 1e-7 (relative)
+    behind it.  A renderer whose depth keys tie the two may blend the fourth
+    before the stop, so the pixel's depth margin (and the fourth splat's) is
+    that gap, not the 1/3 between the blended ones."""
+    cam = axis_camera(4, 4)
+    specs = [(1.0, 1.0), (2.0, 0.9), (3.0, 0.95), (3.0 * (1 + 1e-7), 0.5)]  # depth, opacity
+    rec = np.stack([_rec(1.5, 1.5, 1e6, 0, 1e6, dep, o, (1.0, 1.0, 1.0)) for dep, o in specs])
+    sm = np.full((4, 2), np.inf)
+    rc = np.zeros(4, np.uint8)
+    out = orc.render_camera(rec, _full_rect(4, 4, 4), cam, 4, reached=rc, smargin=sm)
+    # T: 1 -> 0.01 -> 0.001 -> 5e-5 < 1e-4: the third splat stops the pixel
+    assert rc.tolist() == [1, 1, 1, 0]
+    gap = 3.0 * 1e-7 / (3.0 * (1 + 1e-7))
+    assert abs(out["margin"][1, 1, 1] - gap) < 1e-15
+    assert abs(sm[3, 1] - gap) < 1e-15 and abs(sm[2, 1] - gap) < 1e-15 and abs(sm[1, 1] - 0.5) < 1e-15
