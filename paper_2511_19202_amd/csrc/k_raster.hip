@@ -864,13 +864,25 @@ __device__ __forceinline__ void blend_item(
 // the product pass over the middle chunks; PHASE 1: lists that are not split,
 // and the later chunks of split ones, each starting from the product of the
 // chunks before it.
+// Work-groups are dispatched to the 8 XCDs round-robin by id, and each XCD
+// has its own L2.  Item order follows the tile launch order (row-major within
+// a list-length class), so neighbouring tiles, which share most of their
+// splats, should run on the same XCD: id b runs item x * (n / 8) + b / 8 of XCD
+// x = b % 8's contiguous share of the n live items (a bijection on [0, n)).
+__device__ __forceinline__ int64_t xcd_item(int64_t b, int64_t n) {
+  constexpr int64_t kXcd = 8;
+  const int64_t x = b % kXcd, q = b / kXcd, per = n / kXcd, rem = n % kXcd;
+  return x < rem ? x * (per + 1) + q : rem * (per + 1) + (x - rem) * per + q;
+}
+
 template <int T, int MODE, bool STATS, int PHASE>
 __global__ __launch_bounds__(T == 8 ? 64 : 256) void k_blend(
     ItemCtx ic, const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ ids,
     const float4* __restrict__ splat, int W, int H, int tiles_x, int n_tiles, float bg0, float bg1, float bg2,
     float* __restrict__ rgb, uint32_t* __restrict__ contrib, unsigned long long* __restrict__ work) {
-  const int64_t item = blockIdx.x;
-  if (item >= min((int64_t)*ic.n_items, ic.cap_items)) return;
+  const int64_t n_live = min((int64_t)*ic.n_items, ic.cap_items);
+  if ((int64_t)blockIdx.x >= n_live) return;
+  const int64_t item = xcd_item(blockIdx.x, n_live);
   const uint2 it = ic.items[item];
   const uint32_t nch = ic.nch[it.x];
   const bool split = nch > 1;
