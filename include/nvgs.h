@@ -297,7 +297,8 @@ nvgs_status nvgs_frame_watermarks(nvgs_ctx* ctx, int64_t* max_splats, int64_t* m
                                   int32_t reset);
 
 /* Set / read the cull + MLP block shape used by later frames and queries
- * (default 64 Gaussians per wave, 16 segments per work-group). */
+ * (default 32 Gaussians per wave, 64 segments per work-group, the autotuner's
+ * choice on the composed 1080p scene for the FP32 and split-FP32 forms). */
 nvgs_status nvgs_set_mlp_shape(nvgs_ctx* ctx, const nvgs_mlp_shape* shape);
 nvgs_status nvgs_get_mlp_shape(nvgs_ctx* ctx, nvgs_mlp_shape* shape);
 

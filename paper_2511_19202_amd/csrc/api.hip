@@ -47,7 +47,7 @@ struct nvgs_ctx {
 
   // plan (depends on the camera count and the MLP block shape)
   int planC = -1, plan_segs = -1;
-  int mlp_nb = 2, mlp_segs = 16;  // Gaussians per wave / 32, (camera, instance) segments per work-group
+  int mlp_nb = 1, mlp_segs = 64;  // Gaussians per wave / 32, (camera, instance) segments per work-group
   uint64_t gen = 1;               // changes whenever a device buffer moves or the plan is rebuilt
   int64_t n_words = 0, n_chunks = 0;
   std::vector<int64_t> seg_word_base, seg_chunk_base;

@@ -645,8 +645,8 @@ __device__ __forceinline__ void blend_item(
   constexpr int BPW = NB / (NT / 64);    // blocks per wave (1, 1, 4)
   constexpr int BATCH = NT;              // one staged splat per thread per batch
   // staged records, one array so that a fragment's three reads share one
-  // address: [k][0] = u_hi, v_hi, F row 1; [k][1] = F row 2, log2(opacity),
-  // r; [k][2] = g, b, u_lo, v_lo
+  // address: [k][0] = u, v relative to the first pixel centre of the tile's
+  // 32-pixel block, F row 1; [k][1] = F row 2, log2(opacity), r; [k][2] = g, b
   __shared__ float4 s_rec[BATCH][3];
   __shared__ uint32_t s_ov[T == 8 ? 1 : BATCH];  // bit b: the footprint box touches 8x8 block b
   __shared__ uint32_t s_p[RECORD ? BATCH : 1];
@@ -673,10 +673,10 @@ __device__ __forceinline__ void blend_item(
     stop[j] = end;
     const int blk = wave * BPW + j;
     const int x = pix_x(j), y = pix_y(j);
-    // pixel centres; the offset to a splat is (centre - u_hi) - u_lo, the
-    // same arithmetic for every tile size
-    px[j] = (x < W && y < H) ? (float)x + 0.5f : kFar;
-    py[j] = (float)y + 0.5f;
+    // pixel offsets within the 32-pixel block holding the tile (the staged
+    // centres are relative to it, the same for every tile size)
+    px[j] = (x < W && y < H) ? (float)(x & 31) : kFar;
+    py[j] = (float)(y & 31);
     Tr[j] = 1.f;
     cr[j] = cg[j] = cb[j] = 0.f;
     before[j] = false;
@@ -710,10 +710,7 @@ __device__ __forceinline__ void blend_item(
   auto step = [&](int j, int k) {
     const float4 g = s_rec[k][0];
     const float4 h = s_rec[k][1];
-    const float4 c = s_rec[k][2];
-    // the first difference is exact or nearly so for a splat over the tile,
-    // so d keeps the centre's ~48-bit precision
-    const float dx = (px[j] - g.x) - c.z, dy = (py[j] - g.y) - c.w;
+    const float dx = px[j] - g.x, dy = py[j] - g.y;
     // alpha = min(0.99, o 2^pw) with pw = -log2(e) d^T conic d / 2 = -|F d|^2,
     // as 2^(pw + log2 o)
     const float t1 = fmaf(g.z, dx, g.w * dy);
@@ -728,6 +725,7 @@ __device__ __forceinline__ void blend_item(
       px[j] = Tr[j] < kTMin ? kFar : px[j];
       return;
     }
+    const float4 c = s_rec[k][2];
     // Tn >= 0, so the FP32 order is the order of the bit patterns
     const bool low = __float_as_uint(Tn) < __float_as_uint(kTMin);
     const bool halt = ok && low;
@@ -752,7 +750,14 @@ __device__ __forceinline__ void blend_item(
     const int cnt = (int)min((uint32_t)BATCH, end - b0);
     b0k = b0;
     if (t < cnt) {
-      s_rec[t][0] = qa;
+      // the centre relative to the first pixel centre of the tile's 32-pixel
+      // block, from its hi + lo parts (qc.z, qc.w): for a splat over the
+      // tile, u - origin is (nearly) exact in FP32, so d = offset - centre
+      // keeps the centre's precision, and the same for every tile size
+      const int bx = (tx * T) & ~31, by = (ty * T) & ~31;
+      const float ur = (qa.x - ((float)bx + 0.5f)) + qc.z;
+      const float vr = (qa.y - ((float)by + 0.5f)) + qc.w;
+      s_rec[t][0] = make_float4(ur, vr, qa.z, qa.w);
       s_rec[t][1] = qb;
       s_rec[t][2] = qc;
       if (T != 8) {
@@ -761,12 +766,11 @@ __device__ __forceinline__ void blend_item(
         const __half2 exy = __builtin_bit_cast(__half2, qd.y);
         const float ex = __low2float(exy), ey = __high2float(exy);
         const float wx = 1e-4f * ex + 1e-3f, wy = 1e-4f * ey + 1e-3f;
-        // centre relative to the tile's first pixel centre
-        const float ur = (qa.x - ((float)(tx * T) + 0.5f)) + qc.z, vr = (qa.y - ((float)(ty * T) + 0.5f)) + qc.w;
-        const float x0 = fmaxf(-1.f, (ur - ex - wx) * 0.125f);
-        const float x1 = fminf((float)T, (ur + ex + wx) * 0.125f);
-        const float y0 = fmaxf(-1.f, (vr - ey - wy) * 0.125f);
-        const float y1 = fminf((float)T, (vr + ey + wy) * 0.125f);
+        const float ox = (float)(tx * T - bx), oy = (float)(ty * T - by);
+        const float x0 = fmaxf(-1.f, (ur - ox - ex - wx) * 0.125f);
+        const float x1 = fminf((float)T, (ur - ox + ex + wx) * 0.125f);
+        const float y0 = fmaxf(-1.f, (vr - oy - ey - wy) * 0.125f);
+        const float y1 = fminf((float)T, (vr - oy + ey + wy) * 0.125f);
         const int bx0 = max(0, (int)floorf(x0)), bx1 = min(T / 8 - 1, (int)floorf(x1));
         const int by0 = max(0, (int)floorf(y0)), by1 = min(T / 8 - 1, (int)floorf(y1));
         uint32_t m = 0;
@@ -855,182 +859,33 @@ __device__ __forceinline__ void blend_item(
   }
 }
 
-// The 8x8-tile item: one wave, one lane per pixel.  Every lane composites
-// the same list entry at each step, so the entry's splat id and compositing
-// record are wave-uniform: they are read with scalar loads (constant
-// address space) straight into SGPRs, which the VALU reads as operands, with
-// no LDS staging, no broadcast reads and no barriers.  The pixel offset to
-// the centre is (pixel centre - u_hi) - u_lo: the first difference is exact
-// or nearly so for any splat over the tile, so d keeps the centre's ~48-bit
-// precision, and no tile origin enters (the image does not depend on the
-// tile size).  Semantics are those of blend_item (modes, statistics, split
-// chunks, contribution recording).
-typedef const __attribute__((address_space(4))) f32x4_t* const_f4p;
-typedef const __attribute__((address_space(4))) uint32_t* const_u32p;
-__device__ __forceinline__ float4 ld_const(const_f4p p, int i) {
-  const f32x4_t v = p[i];
-  return make_float4(v.x, v.y, v.z, v.w);
-}
-
-template <int MODE, bool STATS, bool FIRST_PROD>
-__device__ __forceinline__ void blend_item8(
-    const ItemCtx& ic, const uint2 it, const uint32_t nch, const uint32_t* __restrict__ ranges,
-    const uint32_t* __restrict__ ids, const float4* __restrict__ splat, int W, int H, int tiles_x, int n_tiles,
-    float bg0, float bg1, float bg2, float* __restrict__ rgb, uint32_t* __restrict__ contrib,
-    unsigned long long* __restrict__ work) {
-  constexpr bool RECORD = MODE == 1, PROD = MODE == 2;
-  constexpr int UNR = 8;  // entries per unrolled group (and per all-stopped check)
-  const bool split = nch > 1;
-  if (split && (int64_t)ic.split_off[it.x] + nch > ic.cap_split) return;  // cannot happen within the sizing bound
-  const int key = (int)ic.order[it.x];
-  const int cam = key / n_tiles, tile = key % n_tiles;
-  const int tx = tile % tiles_x, ty = tile / tiles_x;
-  uint32_t start = ranges[2 * (int64_t)key], end = ranges[2 * (int64_t)key + 1];
-  if (split) {
-    const uint32_t clen = (end - start + nch - 1) / nch;
-    start = min(end, start + it.y * clen);
-    end = min(end, start + clen);
-  }
-  const int64_t sbase = split ? ((int64_t)ic.split_off[it.x] + it.y) * 64 : 0;
-  const int lane = threadIdx.x & 63;
-  const int x = tx * 8 + (lane & 7), y = ty * 8 + (lane >> 3);
-  float px = (x < W && y < H) ? (float)x + 0.5f : kFar;
-  const float py = (float)y + 0.5f;
-  float Tr = 1.f, cr = 0.f, cg = 0.f, cb = 0.f;
-  bool before = false;
-  uint32_t stop = end;
-  if (split && !PROD && it.y > 0) {
-    const int64_t b0 = (int64_t)ic.split_off[it.x] * 64 + lane;
-    float tin = 1.f;
-    for (uint32_t q = 0; q < it.y; ++q) tin *= ic.prod[b0 + (int64_t)q * 64];
-    Tr = tin;
-    before = tin < kTMin;
-    px = before ? kFar : px;
-  }
-  const const_u32p idp = (const_u32p)(ids);
-  const const_f4p rp = (const_f4p)(splat);
-  auto step = [&](const float4 g, const float4 h, const float4 c, uint32_t k, uint32_t pair) {
-    const float dx = (px - g.x) - c.z, dy = (py - g.y) - c.w;
-    // alpha = min(0.99, o 2^pw), pw = -|F d|^2, as 2^(pw + log2 o)
-    const float t1 = fmaf(g.z, dx, g.w * dy);
-    const float t2 = fmaf(h.x, dx, h.y * dy);
-    const float q = fmaf(-t1, t1, fmaf(-t2, t2, h.z));
-    const float al = fminf(kAlphaMax, __builtin_amdgcn_exp2f(q));
-    const bool ok = al >= kAlphaMin;
-    const float w0 = al * Tr;
-    const float Tn = Tr - w0;  // T (1 - alpha)
-    if (PROD) {
-      Tr = ok ? Tn : Tr;
-      px = Tr < kTMin ? kFar : px;
-      return;
-    }
-    const bool low = __float_as_uint(Tn) < __float_as_uint(kTMin);
-    const bool halt = ok && low;
-    const bool take = ok != halt;
-    const float w = take ? w0 : 0.f;
-    cr = fmaf(w, h.w, cr);
-    cg = fmaf(w, c.x, cg);
-    cb = fmaf(w, c.y, cb);
-    Tr = take ? Tn : Tr;
-    if (STATS) stop = halt ? k : stop;
-    px = halt ? kFar : px;
-    if (RECORD && ok) atomicMax(contrib + pair, take ? __float_as_uint(w) : 1u);
-  };
-  for (uint32_t k0 = start; k0 < end; k0 += UNR) {
-    if (__ballot(px < kFarTest) == 0) break;  // every pixel stopped
-    if (k0 + UNR <= end) {
-#pragma unroll
-      for (int u = 0; u < UNR; ++u) {
-        const uint32_t id = idp[k0 + u];
-        const const_f4p r = rp + 4 * (int64_t)id;
-        step(ld_const(r, 0), ld_const(r, 1), ld_const(r, 2), k0 + u, RECORD ? __float_as_uint(r[3].x) : 0u);
-      }
-    } else {
-      for (uint32_t k = k0; k < end; ++k) {
-        const uint32_t id = idp[k];
-        const const_f4p r = rp + 4 * (int64_t)id;
-        step(ld_const(r, 0), ld_const(r, 1), ld_const(r, 2), k, RECORD ? __float_as_uint(r[3].x) : 0u);
-      }
-    }
-  }
-  if (PROD) {
-    ic.prod[sbase + lane] = Tr;
-    return;
-  }
-  if (STATS && work) {
-    uint32_t wk = (x < W && y < H && !before) ? (stop < end ? stop + 1 : end) - start : 0u;
-    for (int o = 32; o > 0; o >>= 1) wk += __shfl_xor(wk, o);
-    if (lane == 0) atomicAdd(work, (unsigned long long)wk);
-  }
-  if (split) {
-    const bool stopped_here = !before && !(px < kFarTest);
-    const float flag = before ? 0.f : (stopped_here ? -Tr : Tr);
-    ic.part[sbase + lane] = make_float4(cr, cg, cb, flag);
-    if (FIRST_PROD) ic.prod[sbase + lane] = stopped_here ? 0.f : Tr;
-    return;
-  }
-  if (x < W && y < H) {
-    float* o = rgb + (((int64_t)cam * H + y) * W + x) * 3;
-    o[0] = fmaf(Tr, bg0, cr);
-    o[1] = fmaf(Tr, bg1, cg);
-    o[2] = fmaf(Tr, bg2, cb);
-  }
-}
-
-// the 8x8 tile's scalar-fed item, or the LDS-staged item of larger tiles
-template <int T, int MODE, bool STATS, bool FIRST_PROD>
-__device__ __forceinline__ void blend_any(
-    const ItemCtx& ic, const uint2 it, const uint32_t nch, const uint32_t* __restrict__ ranges,
-    const uint32_t* __restrict__ ids, const float4* __restrict__ splat, int W, int H, int tiles_x, int n_tiles,
-    float bg0, float bg1, float bg2, float* __restrict__ rgb, uint32_t* __restrict__ contrib,
-    unsigned long long* __restrict__ work) {
-  if constexpr (T == 8)
-    blend_item8<MODE, STATS, FIRST_PROD>(ic, it, nch, ranges, ids, splat, W, H, tiles_x, n_tiles, bg0, bg1, bg2, rgb,
-                                         contrib, work);
-  else
-    blend_item<T, MODE, STATS, FIRST_PROD>(ic, it, nch, ranges, ids, splat, W, H, tiles_x, n_tiles, bg0, bg1, bg2,
-                                           rgb, contrib, work);
-}
-
 // Compositing in two launches.  PHASE 0: the first chunk of every split list,
 // composited from T = 1 (storing its product, 0 where the pixel stopped), and
 // the product pass over the middle chunks; PHASE 1: lists that are not split,
 // and the later chunks of split ones, each starting from the product of the
 // chunks before it.
-// Work-groups are dispatched to the 8 XCDs round-robin by id, and each XCD
-// has its own L2.  Item order follows the tile launch order (row-major within
-// a list-length class), so neighbouring tiles, which share most of their
-// splats, should run on the same XCD: id b runs item x * (n / 8) + b / 8 of XCD
-// x = b % 8's contiguous share of the n live items (a bijection on [0, n)).
-__device__ __forceinline__ int64_t xcd_item(int64_t b, int64_t n) {
-  constexpr int64_t kXcd = 8;
-  const int64_t x = b % kXcd, q = b / kXcd, per = n / kXcd, rem = n % kXcd;
-  return x < rem ? x * (per + 1) + q : rem * (per + 1) + (x - rem) * per + q;
-}
-
 template <int T, int MODE, bool STATS, int PHASE>
 __global__ __launch_bounds__(T == 8 ? 64 : 256) void k_blend(
     ItemCtx ic, const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ ids,
     const float4* __restrict__ splat, int W, int H, int tiles_x, int n_tiles, float bg0, float bg1, float bg2,
     float* __restrict__ rgb, uint32_t* __restrict__ contrib, unsigned long long* __restrict__ work) {
-  const int64_t n_live = min((int64_t)*ic.n_items, ic.cap_items);
-  if ((int64_t)blockIdx.x >= n_live) return;
-  const int64_t item = xcd_item(blockIdx.x, n_live);
+  const int64_t item = blockIdx.x;
+  if (item >= min((int64_t)*ic.n_items, ic.cap_items)) return;
   const uint2 it = ic.items[item];
   const uint32_t nch = ic.nch[it.x];
   const bool split = nch > 1;
   if (PHASE == 0) {
     if (!split || it.y + 1 == nch) return;  // the last chunk's product is never needed
     if (it.y == 0)
-      blend_any<T, MODE, STATS, true>(ic, it, nch, ranges, ids, splat, W, H, tiles_x, n_tiles, bg0, bg1, bg2, rgb,
+      blend_item<T, MODE, STATS, true>(ic, it, nch, ranges, ids, splat, W, H, tiles_x, n_tiles, bg0, bg1, bg2, rgb,
                                        contrib, work);
     else
-      blend_any<T, 2, false, false>(ic, it, nch, ranges, ids, splat, W, H, tiles_x, n_tiles, bg0, bg1, bg2, rgb,
+      blend_item<T, 2, false, false>(ic, it, nch, ranges, ids, splat, W, H, tiles_x, n_tiles, bg0, bg1, bg2, rgb,
                                      contrib, nullptr);
     return;
   }
   if (split && it.y == 0) return;  // composited in phase 0
-  blend_any<T, MODE, STATS, false>(ic, it, nch, ranges, ids, splat, W, H, tiles_x, n_tiles, bg0, bg1, bg2, rgb,
+  blend_item<T, MODE, STATS, false>(ic, it, nch, ranges, ids, splat, W, H, tiles_x, n_tiles, bg0, bg1, bg2, rgb,
                                     contrib, work);
 }
 
