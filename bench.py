@@ -758,7 +758,7 @@ def main_sweep(args):
     import paper_2511_19202_amd as nvgs
     import synth
 
-    prec = args.precision or "fp32"
+    prec = args.precision or "fp32s"
     sc = synth.scene_composed(n_per_asset=args.n, aligned=args.aligned)
     ctx = nvgs.Context(0)
     ctx.load_assets(sc.assets)
