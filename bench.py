@@ -147,13 +147,18 @@ def time_frames(ctx, sc, steps, warmup, **kw):
     last = None
     t0 = time.perf_counter()
     for _ in range(steps):
-        img, st = ctx.render(sc.cameras, stats=True, **kw)
+        # stage times of the kernels a frame without statistics runs (the
+        # compositing test count changes the compositing kernels)
+        img, st = ctx.render(sc.cameras, stats=True, count_tests=False, **kw)
         ms = np.array(list(st["ms_stage"].values()))
         stage = ms if stage is None else stage + ms
         last = st
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     names = list(last["ms_stage"].keys())
+    # one more frame for the compositing test count
+    _, st_count = ctx.render(sc.cameras, stats=True, **kw)
+    last = dict(last, blend_tests=st_count["blend_tests"])
     return (t1 - t0) / steps, dict(zip(names, (stage / steps).tolist())), last, img
 
 

@@ -65,6 +65,8 @@ typedef int32_t nvgs_status;
 #define NVGS_RENDER_RECORD_CONTRIB 1u /* write per-pair max alpha*T into opts->contrib */
 #define NVGS_RENDER_KEEP_DEBUG 2u     /* keep per-splat debug arrays (nvgs_debug_buffers) */
 #define NVGS_RENDER_GRAPH 4u          /* persistent frame: see nvgs_render */
+#define NVGS_RENDER_NO_TEST_COUNT 8u  /* with stats: leave blend_tests uncounted (-1), so that the compositing
+                                         kernels are the ones a frame without stats runs (stage timing) */
 
 typedef struct nvgs_ctx nvgs_ctx;
 
@@ -184,7 +186,8 @@ typedef struct nvgs_frame_stats {
   int64_t queried;    /* pairs the MLP was evaluated for */
   int64_t kept;       /* instantiated splats (survived frustum + MLP) */
   int64_t duplicates; /* (splat, tile) entries sorted */
-  int64_t blend_tests; /* (pixel, tile-list entry) pairs examined before each pixel stopped */
+  int64_t blend_tests; /* (pixel, tile-list entry) pairs examined before each pixel stopped
+                          (-1 with NVGS_RENDER_NO_TEST_COUNT) */
   int64_t workspace_bytes;
   float ms_total;     /* frame wall time on the stream (first to last event) */
   float ms_stage[NVGS_NUM_STAGES]; /* per-stage kernel time (HIP events) */
@@ -299,6 +302,18 @@ nvgs_status nvgs_frame_watermarks(nvgs_ctx* ctx, int64_t* max_splats, int64_t* m
 /* Set / read the cull + MLP block shape used by later frames and queries
  * (default 32 Gaussians per wave, 64 segments per work-group, the autotuner's
  * choice on the composed 1080p scene for the FP32 and split-FP32 forms). */
+/* Stable LSD radix sort, in place, of n (key, value) pairs held in device
+ * arrays keys[n] and vals[n] (caller-owned), by key bits [begin_bit, end_bit)
+ * (0 <= begin_bit <= end_bit <= 32; 8-bit digits, one pass each): pairs with
+ * equal key bits keep their input order.  It is the sort behind the frame's
+ * depth order and (tile, depth, id) order of the tile lists (Sec. 3.3, the
+ * binning of original 3DGS), exposed for checking and reuse.  Runs on the
+ * context stream and synchronises it; the context keeps a grow-only
+ * workspace of about 8.5 n bytes.  E_INVALID for n outside [0, 2^32),
+ * a bad bit range or null arrays with n > 0. */
+nvgs_status nvgs_sort_pairs(nvgs_ctx* ctx, uint32_t* keys, uint32_t* vals, int64_t n, int32_t begin_bit,
+                            int32_t end_bit);
+
 nvgs_status nvgs_set_mlp_shape(nvgs_ctx* ctx, const nvgs_mlp_shape* shape);
 nvgs_status nvgs_get_mlp_shape(nvgs_ctx* ctx, nvgs_mlp_shape* shape);
 

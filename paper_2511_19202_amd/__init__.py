@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libnvgs.so")
 
 OK, E_INVALID, E_STATE, E_NOMEM, E_CAPACITY, E_DEVICE = range(6)
 PREC_FP32, PREC_BF16, PREC_FP8, PREC_FP32_SPLIT = 0, 1, 2, 3
-RENDER_RECORD_CONTRIB, RENDER_KEEP_DEBUG, RENDER_GRAPH = 1, 2, 4
+RENDER_RECORD_CONTRIB, RENDER_KEEP_DEBUG, RENDER_GRAPH, RENDER_NO_TEST_COUNT = 1, 2, 4, 8
 _PREC = {"fp32": PREC_FP32, "bf16": PREC_BF16, "fp8": PREC_FP8, "fp32s": PREC_FP32_SPLIT}
 
 
@@ -128,6 +128,7 @@ _SIGS = {
                            C.c_void_p, C.c_void_p], C.c_int32),
     "nvgs_mlp_backward_noalloc": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p, C.c_int32,
                                    C.c_void_p, C.c_void_p], C.c_int32),
+    "nvgs_sort_pairs": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_int32], C.c_int32),
     "nvgs_cmlp_forward": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p], C.c_int32),
     "nvgs_cmlp_backward": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int32, C.c_void_p],
                            C.c_int32),
@@ -336,10 +337,12 @@ class Context:
 
     def render(self, cams: Iterable, tile: int = 16, use_mlp: bool = True, precision="fp32", bg=(0.0, 0.0, 0.0),
                contrib=None, keep_debug: bool = False, stats: bool = False, out=None, graph: bool = False,
-               split: int = 0, det_clip: float = 0.0):
+               split: int = 0, det_clip: float = 0.0, count_tests: bool = True):
         """One frame for all cameras.  graph=True: persistent frame (captured
         HIP graph, no synchronisation unless stats); without `out` the image
-        goes to a context-owned tensor that the next graph frame overwrites."""
+        goes to a context-owned tensor that the next graph frame overwrites.
+        count_tests=False (with stats): blend_tests is -1 and the compositing
+        kernels are those of a frame without stats."""
         torch = _torch()
         arr, n = self._cams(cams)
         W, H = arr[0].width, arr[0].height
@@ -354,7 +357,7 @@ class Context:
         else:
             rgb = torch.empty((n, H, W, 3), dtype=torch.float32, device=self.device)
         flags = (RENDER_RECORD_CONTRIB if contrib is not None else 0) | (RENDER_KEEP_DEBUG if keep_debug else 0) | \
-            (RENDER_GRAPH if graph else 0)
+            (RENDER_GRAPH if graph else 0) | (0 if count_tests else RENDER_NO_TEST_COUNT)
         opts = RenderOpts(int(tile), int(bool(use_mlp)), _PREC.get(precision, precision), (C.c_float * 3)(*bg), flags,
                           contrib.data_ptr() if contrib is not None else None, int(split), float(det_clip))
         fs = FrameStats() if stats else None
@@ -369,6 +372,20 @@ class Context:
 
     def reserve(self, max_splats: int, max_duplicates: int):
         self._check(self.L.nvgs_reserve(self.h, int(max_splats), int(max_duplicates)))
+
+    def sort_pairs(self, keys, vals, begin_bit: int = 0, end_bit: int = 32):
+        """Stable radix sort, in place, of two contiguous 32-bit device tensors
+        (int32 or uint32) of equal length by key bits [begin_bit, end_bit)."""
+        torch = _torch()
+        ok = (torch.int32, getattr(torch, "uint32", torch.int32))
+        if keys.dtype not in ok or vals.dtype not in ok or keys.numel() != vals.numel():
+            raise ValueError("sort_pairs: keys and vals must be 32-bit tensors of equal length")
+        if not (keys.is_contiguous() and vals.is_contiguous()):
+            raise ValueError("sort_pairs: keys and vals must be contiguous")
+        if keys.device != self.device or vals.device != self.device:
+            raise ValueError("sort_pairs: keys and vals must be on the context's device")
+        self._check(self.L.nvgs_sort_pairs(self.h, keys.data_ptr(), vals.data_ptr(), int(keys.numel()),
+                                           int(begin_bit), int(end_bit)))
 
     def watermarks(self, reset: bool = False) -> dict:
         a, b, o = C.c_int64(), C.c_int64(), C.c_int32()

@@ -69,6 +69,7 @@ struct nvgs_ctx {
   Buf splat, rec_a, rec_b, rec_c, rec_d, rect, rect_sorted, depth_key, ids, ids_tmp, keys_tmp2, pair_of, cnt, dup_off;
   Buf keys, vals, keys_tmp, vals_tmp, hist, hist_part, ranges, tord;  // tord: tile order (4 arrays)
   Buf tsplit, citems, prodb, partb;  // long-list split: per-position counts and offsets, items, chunk products / records
+  Buf sort_tmp, sort_ws;             // nvgs_sort_pairs: ping-pong pairs and workspace
   int64_t cap_items = 0, cap_split_px = 0;  // items; split slots x pixels per tile
   int64_t cap_keys = 0;  // tile keys (cameras x tiles) the range buffers hold
   int64_t cap_hist = 0;  // longest list the sort histograms and scan partials cover
@@ -348,7 +349,7 @@ void nvgs_destroy(nvgs_ctx* ctx) {
                 &ctx->chunk_off, &ctx->scan_part, &ctx->cam_dev, &ctx->splat, &ctx->rect_sorted, &ctx->rec_a, &ctx->rec_b, &ctx->rec_c, &ctx->rec_d, &ctx->rect,
                 &ctx->depth_key, &ctx->ids, &ctx->ids_tmp, &ctx->keys_tmp2, &ctx->pair_of, &ctx->cnt, &ctx->dup_off,
                 &ctx->keys, &ctx->vals, &ctx->keys_tmp, &ctx->vals_tmp, &ctx->hist, &ctx->hist_part, &ctx->ranges, &ctx->tord,
-                &ctx->tsplit, &ctx->citems, &ctx->prodb, &ctx->partb,
+                &ctx->tsplit, &ctx->citems, &ctx->prodb, &ctx->partb, &ctx->sort_tmp, &ctx->sort_ws,
                 &ctx->counters};
   for (Buf* b : all) release(ctx, *b);
   for (Buf& b : ctx->op_bufs) release(ctx, b);
@@ -537,7 +538,7 @@ nvgs_status size_hist(nvgs_ctx* ctx) {
   const int64_t m = std::max({ctx->cap_dup, ctx->cap_splats, ctx->cap_keys, (int64_t)4096});
   if (m <= ctx->cap_hist) return NVGS_OK;
   if (!ensure(ctx, ctx->hist, 4 * radix_hist_words(m)) ||
-      !ensure(ctx, ctx->hist_part, 4 * scan_partials_needed(radix_hist_words(m)) + 4 * scan_partials_needed(m))) {
+      !ensure(ctx, ctx->hist_part, 8 * scan_partials_needed(m))) {
     ctx->cap_hist = 0;
     return fail(ctx, NVGS_E_NOMEM, "sort histograms");
   }
@@ -763,7 +764,7 @@ void fill_stats(nvgs_ctx* ctx, const Frame& f, nvgs_frame_stats* stats) {
   stats->pairs = (int64_t)f.C * ctx->P;
   stats->in_frustum = (int64_t)c64[0];
   stats->queried = (int64_t)c64[1];
-  stats->blend_tests = (int64_t)c64[2];
+  stats->blend_tests = f.count_tests ? (int64_t)c64[2] : -1;
   stats->kept = ctx->counters_host[0];
   stats->duplicates = ctx->counters_host[1];
   stats->workspace_bytes = (int64_t)ctx->workspace;
@@ -809,7 +810,7 @@ nvgs_status nvgs_render(nvgs_ctx* ctx, const nvgs_camera* cams, int32_t C, const
   f.record = record;
   f.split_len = opts->split_len == 0 ? kSplitDefault : (opts->split_len < 0 ? 0 : opts->split_len);
   f.debug = record || (opts->flags & NVGS_RENDER_KEEP_DEBUG);
-  f.count_tests = stats != nullptr;
+  f.count_tests = stats != nullptr && !(opts->flags & NVGS_RENDER_NO_TEST_COUNT);
   f.opts = opts;
   f.rgb = rgb;
   hipStream_t st = ctx->stream;
@@ -916,6 +917,30 @@ nvgs_status nvgs_frame_watermarks(nvgs_ctx* ctx, int64_t* max_splats, int64_t* m
   return NVGS_OK;
 }
 
+nvgs_status nvgs_sort_pairs(nvgs_ctx* ctx, uint32_t* keys, uint32_t* vals, int64_t n, int32_t begin_bit,
+                            int32_t end_bit) {
+  if (!ctx) return NVGS_E_INVALID;
+  if (n < 0 || n >= ((int64_t)1 << 32)) return fail(ctx, NVGS_E_INVALID, "sort_pairs: n must be in [0, 2^32)");
+  if (begin_bit < 0 || end_bit > 32 || begin_bit > end_bit)
+    return fail(ctx, NVGS_E_INVALID, "sort_pairs: need 0 <= begin_bit <= end_bit <= 32");
+  if (n > 0 && (!keys || !vals)) return fail(ctx, NVGS_E_INVALID, "sort_pairs: null keys or vals");
+  if (n == 0 || begin_bit == end_bit) return NVGS_OK;
+  CK(hipSetDevice(ctx->device));
+  if (!ensure(ctx, ctx->sort_tmp, 8 * (size_t)n) || !ensure(ctx, ctx->sort_ws, 4 * radix_hist_words(n)))
+    return fail(ctx, NVGS_E_NOMEM, "sort_pairs: workspace");
+  hipStream_t st = ctx->stream;
+  uint32_t* kt = P_<uint32_t>(ctx->sort_tmp);
+  bool in_tmp = false;
+  CK(launch_radix_sort(keys, vals, kt, kt + n, nullptr, n, begin_bit, end_bit, 0, P_<uint32_t>(ctx->sort_ws), nullptr,
+                       &in_tmp, st));
+  if (in_tmp) {
+    CK(hipMemcpyAsync(keys, kt, 4 * (size_t)n, hipMemcpyDeviceToDevice, st));
+    CK(hipMemcpyAsync(vals, kt + n, 4 * (size_t)n, hipMemcpyDeviceToDevice, st));
+  }
+  CK(hipStreamSynchronize(st));
+  return NVGS_OK;
+}
+
 nvgs_status nvgs_set_mlp_shape(nvgs_ctx* ctx, const nvgs_mlp_shape* shape) {
   if (!ctx) return NVGS_E_INVALID;
   if (!shape) return fail(ctx, NVGS_E_INVALID, "null shape");
@@ -946,6 +971,7 @@ nvgs_status nvgs_autotune(nvgs_ctx* ctx, const nvgs_camera* cams, int32_t C, nvg
   if (s) return s;
   nvgs_render_opts o = *opts;
   o.flags &= ~(int32_t)NVGS_RENDER_GRAPH;
+  o.flags |= NVGS_RENDER_NO_TEST_COUNT;  // time the kernels of frames without statistics
   if (o.tile != 8 && o.tile != 16 && o.tile != 32) o.tile = 16;
   const int saved_nb = ctx->mlp_nb, saved_segs = ctx->mlp_segs;
   int n = 0;

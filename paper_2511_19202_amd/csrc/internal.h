@@ -146,7 +146,7 @@ hipError_t launch_project(const AssetDev* assets, const SegRec* segs, int32_t n_
 hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint32_t* vals_tmp,
                              const uint32_t* n_dev, int64_t cap, int begin_bit, int end_bit, int iota_vals,
                              uint32_t* hist, uint32_t* partials, bool* result_in_tmp, hipStream_t st);
-size_t radix_hist_words(int64_t cap);
+size_t radix_hist_words(int64_t cap);  // sort workspace (32-bit words) for up to cap keys
 
 hipError_t launch_gather_tiles(const uint32_t* sorted_ids, const uint4* rect, const uint32_t* n_dev, int64_t cap,
                                uint32_t* out, uint4* rect_sorted, hipStream_t st);

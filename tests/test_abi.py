@@ -73,6 +73,10 @@ def test_null_and_invalid_arguments_are_rejected(so):
     so.nvgs_load_assets.restype = ctypes.c_int32
     so.nvgs_load_assets.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]
     assert so.nvgs_load_assets(None, None, 0) == 1
+    so.nvgs_sort_pairs.restype = ctypes.c_int32
+    so.nvgs_sort_pairs.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                   ctypes.c_int32, ctypes.c_int32]
+    assert so.nvgs_sort_pairs(None, None, None, 0, 0, 32) == 1
     so.nvgs_last_error.restype = ctypes.c_char_p
     so.nvgs_last_error.argtypes = [ctypes.c_void_p]
     assert so.nvgs_last_error(None) == b"null context"
