@@ -17,6 +17,11 @@ constexpr float kTMin = 1e-4f;
 constexpr float kGuard = 1.3f;   // frustum / Jacobian side guard band
 constexpr float kDilate = 0.3f;  // screen-space low-pass added to the 2D covariance
 
+// ReLU as a signed integer max on the bit pattern (negative values and -0
+// have the sign bit set): one instruction, where fmaxf on an MFMA result also
+// costs a canonicalising max
+__device__ __forceinline__ float relu(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
+
 constexpr int kChunk = 256;           // pairs per compaction chunk (one cull/MLP work-group)
 constexpr int kSortBlock = 2048;      // keys per radix-sort block
 constexpr int kScanBlock = 4096;      // items per scan block

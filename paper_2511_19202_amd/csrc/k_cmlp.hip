@@ -244,7 +244,7 @@ __global__ __launch_bounds__(kCThreads) void k_cull_cmlp(
       }
       float part = 0.f;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) part = fmaf(wop[r], fmaxf(acc[r], 0.f), part);
+      for (int r = 0; r < 16; ++r) part = fmaf(wop[r], relu(acc[r]), part);
       z = part + __shfl_xor(part, 32) + bo;
       keep = in && z >= 0.f;
     }

@@ -515,7 +515,7 @@ __device__ __forceinline__ void relu_pack(const f32x16 (&acc)[NB][W / 32], float
       for (int j = 0; j < EPL; ++j) {
         const int q = s * EPL + j;
         const float x = ADD ? fmaf(acc[b][q / 16][q % 16], add_scale, add[q]) : acc[b][q / 16][q % 16];
-        v[j] = P == NVGS_PREC_BF16 ? x * scale : fmaxf(x * scale, 0.f);
+        v[j] = P == NVGS_PREC_BF16 ? x * scale : relu(x * scale);
       }
       if constexpr (P == NVGS_PREC_BF16) {
         // pairs rounded together (one v_cvt_pk_bf16_f32), ReLU as a packed
@@ -550,7 +550,7 @@ __device__ __forceinline__ void relu_split(const f32x16 (&acc)[NB][W / 32], cons
         const int q = s * 8 + 2 * p2;
         const float x0 = ADD ? acc[b][q / 16][q % 16] + add[q] : acc[b][q / 16][q % 16];
         const float x1 = ADD ? acc[b][(q + 1) / 16][(q + 1) % 16] + add[q + 1] : acc[b][(q + 1) / 16][(q + 1) % 16];
-        const float v0 = fmaxf(x0, 0.f), v1 = fmaxf(x1, 0.f);
+        const float v0 = relu(x0), v1 = relu(x1);
         const bf16x2 h = __builtin_convertvector((f32x2){v0, v1}, bf16x2);
         const uint32_t hbits = __builtin_bit_cast(uint32_t, h);
         const float h0 = __uint_as_float(hbits << 16), h1 = __uint_as_float(hbits & 0xffff0000u);
@@ -776,7 +776,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_cull_mlp(
       for (int b = 0; b < NB; ++b) {
         float part = 0.f;
 #pragma unroll
-        for (int q = 0; q < KQ; ++q) part = fmaf(wg[q], fmaxf(acc[b][q / 16][q % 16] * inv3, 0.f), part);
+        for (int q = 0; q < KQ; ++q) part = fmaf(wg[q], relu(acc[b][q / 16][q % 16] * inv3), part);
         z[b] = part + __shfl_xor(part, 32) + bo;
         keep[b] = in[b] && z[b] >= 0.f;
       }
