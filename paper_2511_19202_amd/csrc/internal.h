@@ -143,10 +143,9 @@ size_t scan_partials_needed(int64_t n);
 
 hipError_t launch_project(const AssetDev* assets, const SegRec* segs, int32_t n_segs, const int64_t* seg_chunk_base,
                           int64_t n_chunks, const uint32_t* mask, const uint32_t* chunk_off, const uint32_t* n_splats,
-                          int64_t cap_splats, int tile, int tiles_x, int tiles_y, int keep_debug, float det_clip,
-                          float4* splat,
-                          float4* rec_a, float4* rec_b, float4* rec_c, float2* rec_d, uint4* rect, uint32_t* depth_key,
-                          uint32_t* pair_of, uint32_t* overflow, hipStream_t st);
+                          int64_t cap_splats, int64_t grid_slots, int tile, int keep_debug, float det_clip,
+                          float4* splat, float4* rec_a, float4* rec_b, float4* rec_c, float2* rec_d, uint4* rect,
+                          uint32_t* depth_key, uint32_t* pair_of, uint32_t* overflow, hipStream_t st);
 
 hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint32_t* vals_tmp,
                              const uint32_t* n_dev, int64_t cap, int begin_bit, int end_bit, int iota_vals,

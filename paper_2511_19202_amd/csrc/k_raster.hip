@@ -202,42 +202,14 @@ __device__ __forceinline__ void pixel_range(float u, float e, int size, int* lo,
   *hi = (int)b;
 }
 
-__global__ __launch_bounds__(kChunk) void k_project(
-    const AssetDev* __restrict__ assets, const SegRec* __restrict__ segs, int32_t n_segs,
-    const int64_t* __restrict__ seg_chunk_base, const uint32_t* __restrict__ mask,
-    const uint32_t* __restrict__ chunk_off, int64_t cap, int tile, int tiles_x, int tiles_y, int keep_debug,
-    float det_clip, float4* __restrict__ splat, float4* __restrict__ rec_a, float4* __restrict__ rec_b, float4* __restrict__ rec_c,
-    float2* __restrict__ rec_d,
-    uint4* __restrict__ rect, uint32_t* __restrict__ depth_key, uint32_t* __restrict__ pair_of,
-    uint32_t* __restrict__ overflow) {
-  const int64_t chunk = blockIdx.x;
-  // segment of this chunk: last s with seg_chunk_base[s] <= chunk
-  int lo = 0, hi = n_segs - 1;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (seg_chunk_base[mid] <= chunk) lo = mid; else hi = mid - 1;
-  }
-  const SegRec& R = segs[lo];
-  const int64_t c = chunk - seg_chunk_base[lo];
-  const int t = threadIdx.x;
-  const int64_t g = c * kChunk + t;
-  const int64_t n = R.n;
-  const int64_t words = (n + 31) >> 5;
-  __shared__ uint32_t s_w[kChunk / 32];
-  if (t < kChunk / 32) {
-    const int64_t wi = c * (kChunk / 32) + t;
-    s_w[t] = wi < words ? mask[R.word_base + wi] : 0u;
-  }
-  __syncthreads();
-  const uint32_t word = s_w[t >> 5];
-  if (!((word >> (t & 31)) & 1u)) return;
-  uint32_t before = __popc(word & ((1u << (t & 31)) - 1u));
-  for (int w = 0; w < (t >> 5); ++w) before += __popc(s_w[w]);
-  const uint32_t slot = chunk_off[chunk] + before;
-  if (slot >= cap) {
-    atomicOr(overflow, 1u);
-    return;
-  }
+// Projection of one kept pair (Gaussian g of segment R) into output slot
+// `slot`: the compositing record, tile rectangle, depth key and, on debug
+// frames, the per-splat debug arrays.
+__device__ __forceinline__ void project_pair(
+    const AssetDev* __restrict__ assets, const SegRec& R, int64_t g, uint32_t slot, int tile, int keep_debug,
+    float det_clip, float4* __restrict__ splat, float4* __restrict__ rec_a, float4* __restrict__ rec_b,
+    float4* __restrict__ rec_c, float2* __restrict__ rec_d, uint4* __restrict__ rect, uint32_t* __restrict__ depth_key,
+    uint32_t* __restrict__ pair_of) {
   const AssetDev& A = assets[R.asset];
   const float4 g0 = ld_global(A.geo, 3 * g), g1 = ld_global(A.geo, 3 * g + 1), g2 = ld_global(A.geo, 3 * g + 2);
   const float mu[3] = {g0.x, g0.y, g0.z};
@@ -363,19 +335,105 @@ __global__ __launch_bounds__(kChunk) void k_project(
     rec_d[slot] = make_float2(u_lo, v_lo);
     pair_of[slot] = (uint32_t)(R.pair_base + g);
   }
-  (void)tiles_x; (void)tiles_y;
+
+}
+
+// One thread per output slot, i.e. per kept pair in (camera, instance,
+// Gaussian) order, so that every lane of a wave projects a splat whatever
+// the keep rate.  The slots of a chunk are [chunk_off[c], chunk_off[c + 1])
+// (exclusive scan of the chunks' keep counts); a slot's chunk is the last c
+// with chunk_off[c] <= slot, found by binary search (the wave's first and
+// last slots bound each lane's search), and its Gaussian is the set bit of
+// the chunk's 256-bit keep mask with that rank.  A wave's slots usually lie
+// in one segment; it loops over the segments they span so that the segment
+// record is read with wave-uniform loads.
+__global__ __launch_bounds__(256) void k_project(
+    const AssetDev* __restrict__ assets, const SegRec* __restrict__ segs, int32_t n_segs,
+    const int64_t* __restrict__ seg_chunk_base, int64_t n_chunks, const uint32_t* __restrict__ mask,
+    const uint32_t* __restrict__ chunk_off, const uint32_t* __restrict__ n_splats, int64_t cap, int tile,
+    int keep_debug, float det_clip, float4* __restrict__ splat, float4* __restrict__ rec_a,
+    float4* __restrict__ rec_b, float4* __restrict__ rec_c, float2* __restrict__ rec_d, uint4* __restrict__ rect,
+    uint32_t* __restrict__ depth_key, uint32_t* __restrict__ pair_of, uint32_t* __restrict__ overflow) {
+  const uint32_t n_all = *n_splats;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && (int64_t)n_all > cap) atomicOr(overflow, 1u);
+  const int64_t ns = min((int64_t)n_all, cap);
+  const int lane = threadIdx.x & 63;
+  const int64_t w0 = __builtin_amdgcn_readfirstlane((int)blockIdx.x) * (int64_t)256 +
+                     __builtin_amdgcn_readfirstlane((int)(threadIdx.x & ~63u));
+  if (w0 >= ns) return;  // the whole wave
+  const int64_t slot = w0 + lane;
+  const bool live = slot < ns;
+  const int64_t w1 = min(w0 + 63, ns - 1);
+  // last index in [lo, hi] whose key is <= x, over a non-decreasing array
+  auto last_le = [](auto key, int64_t x, int64_t lo, int64_t hi) {
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if ((int64_t)key(mid) <= x) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+  };
+  auto coff = [&](int64_t c) { return chunk_off[c]; };
+  auto sbase = [&](int64_t q) { return seg_chunk_base[q]; };
+  // wave-uniform bounds (read-first-lane keeps them in scalar registers)
+  auto uni = [](int64_t v) {
+    return (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(v >> 32)) << 32) |
+                     (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v));
+  };
+  const int64_t c_lo = uni(last_le(coff, w0, 0, n_chunks - 1));
+  const int64_t c_hi = uni(last_le(coff, w1, c_lo, n_chunks - 1));
+  const int64_t c = live ? last_le(coff, slot, c_lo, c_hi) : c_lo;
+  const int32_t s_lo = (int32_t)uni(last_le(sbase, c_lo, 0, n_segs - 1));
+  const int32_t s_hi = (int32_t)uni(last_le(sbase, c_hi, s_lo, n_segs - 1));
+  const int32_t sg = s_lo == s_hi ? s_lo : (int32_t)last_le(sbase, c, s_lo, s_hi);
+  for (int32_t si = s_lo; si <= s_hi; ++si) {
+    if (!live || sg != si) continue;
+    const SegRec& R = segs[__builtin_amdgcn_readfirstlane(si)];
+    const int64_t cl = c - seg_chunk_base[si];  // chunk within the segment
+    const int64_t words = ((int64_t)R.n + 31) >> 5;
+    // rank of the slot among the chunk's kept pairs -> mask word and bit
+    const uint32_t r = (uint32_t)(slot - (int64_t)chunk_off[c]);
+    uint32_t cum = 0, below = 0, x = 0;
+    int wsel = -1;
+#pragma unroll
+    for (int w = 0; w < kChunk / 32; ++w) {
+      const int64_t wi = cl * (kChunk / 32) + w;
+      const uint32_t m = wi < words ? mask[R.word_base + wi] : 0u;
+      const uint32_t pc = (uint32_t)__popc(m);
+      if (wsel < 0 && r < cum + pc) {
+        wsel = w;
+        below = cum;
+        x = m;
+      }
+      cum += pc;
+    }
+    uint32_t rr = r - below;
+    int pos = 0;
+#pragma unroll
+    for (int half = 16; half > 0; half >>= 1) {
+      const uint32_t low = (uint32_t)__popc(x & ((1u << half) - 1u));
+      if (rr >= low) {
+        rr -= low;
+        x >>= half;
+        pos += half;
+      }
+    }
+    const int64_t g = cl * kChunk + wsel * 32 + pos;
+    project_pair(assets, R, g, (uint32_t)slot, tile, keep_debug, det_clip, splat, rec_a, rec_b, rec_c, rec_d, rect,
+                 depth_key, pair_of);
+  }
 }
 
 hipError_t launch_project(const AssetDev* assets, const SegRec* segs, int32_t n_segs, const int64_t* seg_chunk_base,
                           int64_t n_chunks, const uint32_t* mask, const uint32_t* chunk_off, const uint32_t* n_splats,
-                          int64_t cap_splats, int tile, int tiles_x, int tiles_y, int keep_debug, float det_clip,
-                          float4* splat, float4* rec_a, float4* rec_b, float4* rec_c, float2* rec_d, uint4* rect, uint32_t* depth_key,
-                          uint32_t* pair_of, uint32_t* overflow, hipStream_t st) {
-  (void)n_splats;
-  if (n_chunks == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_project, dim3((unsigned)n_chunks), dim3(kChunk), 0, st, assets, segs, n_segs, seg_chunk_base,
-                     mask, chunk_off, cap_splats, tile, tiles_x, tiles_y, keep_debug, det_clip, splat, rec_a, rec_b,
-                     rec_c, rec_d, rect, depth_key, pair_of, overflow);
+                          int64_t cap_splats, int64_t grid_slots, int tile, int keep_debug, float det_clip,
+                          float4* splat, float4* rec_a, float4* rec_b, float4* rec_c, float2* rec_d, uint4* rect,
+                          uint32_t* depth_key, uint32_t* pair_of, uint32_t* overflow, hipStream_t st) {
+  if (n_chunks == 0 || n_segs == 0) return hipSuccess;
+  // slots beyond the capacity are never written (the kernel raises the overflow flag)
+  const int64_t slots = std::max<int64_t>(std::min(grid_slots, cap_splats), 1);
+  hipLaunchKernelGGL(k_project, dim3((unsigned)((slots + 255) / 256)), dim3(256), 0, st, assets, segs, n_segs,
+                     seg_chunk_base, n_chunks, mask, chunk_off, n_splats, cap_splats, tile, keep_debug, det_clip,
+                     splat, rec_a, rec_b, rec_c, rec_d, rect, depth_key, pair_of, overflow);
   return hipGetLastError();
 }
 
