@@ -229,9 +229,9 @@ __global__ void k_prepare(const float* __restrict__ Pm, int W, const float* __re
         const int which = e / (2 * KQ), r = e % (2 * KQ), g = r / KQ, q = r % KQ;
         const float* vec = which == 0 ? b2 : which == 1 ? b3 : wo;
         v = vec[hid_feature(q, g)];
-        // FP8: the hidden layers' accumulators start from b / inv = b sw sa (powers of two: exact)
-        if (P == NVGS_PREC_FP8 && which == 0) v *= scales[kSw2] * scales[kSaH1];
-        if (P == NVGS_PREC_FP8 && which == 1) v *= scales[kSw3] * scales[kSaH2];
+        // FP8: layer 2's accumulators hold sa2 (W2 h1 + b2) and start from sa2 b2
+        // (a power of two: exact); layer 3's hold W3 h2 + b3
+        if (P == NVGS_PREC_FP8 && which == 0) v *= scales[kSaH2];
       } else if (e == 6 * KQ) {
         v = wo[W];
       } else if (e - 6 * KQ - 1 < kNumScales) {
@@ -450,7 +450,7 @@ struct Mfma<NVGS_PREC_FP32> {
     return reinterpret_cast<const float*>(p)[idx];
   }
   static __device__ __forceinline__ Op pack(const float* v) { return v[0]; }
-  static __device__ __forceinline__ f32x16 mma(Op a, Op b, f32x16 c) {
+  static __device__ __forceinline__ f32x16 mma(Op a, Op b, f32x16 c, int = 127, int = 127) {
     return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
   }
 };
@@ -466,7 +466,7 @@ struct Mfma<NVGS_PREC_BF16> {
     for (int j = 0; j < 8; ++j) r[j] = (__bf16)v[j];
     return r;
   }
-  static __device__ __forceinline__ f32x16 mma(Op a, Op b, f32x16 c) {
+  static __device__ __forceinline__ f32x16 mma(Op a, Op b, f32x16 c, int = 127, int = 127) {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
   }
 };
@@ -485,11 +485,17 @@ struct Mfma<NVGS_PREC_FP8> {
     }
     return r;
   }
-  static __device__ __forceinline__ f32x16 mma(Op a, Op b, f32x16 c) {
-    // E4M3 x E4M3, block scales 2^0 (the per-layer scales are applied in the epilogue)
-    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, 127, 0, 127);
+  // E4M3 x E4M3; ea, eb: E8M0 block scales (2^(e - 127)) of the weights and
+  // the activations, the same in every lane: the per-layer dequantisation
+  // and the next layer's quantisation scale (powers of two) are applied to
+  // every product by the matrix core, not by the epilogue
+  static __device__ __forceinline__ f32x16 mma(Op a, Op b, f32x16 c, int ea = 127, int eb = 127) {
+    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, ea, 0, eb);
   }
 };
+
+// E8M0 code of a normal power-of-two float: its biased exponent
+__device__ __forceinline__ int e8m0(float s) { return (int)((__float_as_uint(s) >> 23) & 0xffu); }
 
 typedef short s16x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
@@ -608,7 +614,7 @@ __device__ __forceinline__ void mma_layer_split(const uint8_t* __restrict__ Wh, 
 template <int P, int W, int NB>
 __device__ __forceinline__ void mma_layer(const uint8_t* __restrict__ Wp, const float* __restrict__ binit,
                                           const typename Mfma<P>::Op (&in)[NB][W / Prec<P>::K],
-                                          f32x16 (&acc)[NB][W / 32], int lane) {
+                                          f32x16 (&acc)[NB][W / 32], int lane, int ea = 127, int eb = 127) {
   using M = Mfma<P>;
   constexpr int NT = W / 32, KSH = W / Prec<P>::K;
   f32x16 c0[NT];
@@ -624,7 +630,7 @@ __device__ __forceinline__ void mma_layer(const uint8_t* __restrict__ Wp, const 
 #pragma unroll
     for (int b = 0; b < NB; ++b)
 #pragma unroll
-      for (int t = 0; t < NT; ++t) acc[b][t] = M::mma(a[t], in[b][s], s == 0 ? c0[t] : acc[b][t]);
+      for (int t = 0; t < NT; ++t) acc[b][t] = M::mma(a[t], in[b][s], s == 0 ? c0[t] : acc[b][t], ea, eb);
   }
 }
 
@@ -687,6 +693,12 @@ __global__ __launch_bounds__(64 * WAVES) void k_cull_mlp(
   const float saG = P == NVGS_PREC_FP8 ? scl[kSaG] : 1.f;
   const float saH1 = P == NVGS_PREC_FP8 ? scl[kSaH1] : 1.f;
   const float saH2 = P == NVGS_PREC_FP8 ? scl[kSaH2] : 1.f;
+  // FP8: E8M0 scales of the three MFMA stages (weights, activations): U comes
+  // out as sa1 (W1u gamma), layer 2 as sa2 (W2 h1 + b2), layer 3 as W3 h2 + b3
+  // (the accumulators start from the biases in those units), so the epilogues
+  // are an add (layer 1, with the camera half staged as sa1 c1), the ReLU and
+  // the conversion
+  const int eU_a = e8m0(invU), eU_b = e8m0(saH1), e2_a = e8m0(inv2), e2_b = e8m0(saH2), e3_a = e8m0(inv3);
   // layer 1, Gaussian half: U = W1u gamma(mean_scale * mu), features in the
   // natural order k = s*2*EPL + grp*EPL + j (zero beyond 36)
   f32x16 U[NB][NT];
@@ -712,7 +724,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_cull_mlp(
       }
       const typename M::Op eb = M::pack(e);
 #pragma unroll
-      for (int t = 0; t < NT; ++t) U[b][t] = M::mma(a[t], eb, U[b][t]);
+      for (int t = 0; t < NT; ++t) U[b][t] = M::mma(a[t], eb, U[b][t], eU_a, eU_b);
     }
   }
   uint32_t n_in = 0, n_q = 0;  // in-frustum and queried pairs of this wave
@@ -732,7 +744,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_cull_mlp(
     const int seg = seglist[si];
     const SegRec& R = segs[seg];
 #pragma unroll
-    for (int q = 0; q < CPL; ++q) s_c1[wave][q * 64 + lane] = pref[q];
+    for (int q = 0; q < CPL; ++q) s_c1[wave][q * 64 + lane] = P == NVGS_PREC_FP8 ? pref[q] * saH1 : pref[q];
     fetch_c1(si + 1);
     bool in[NB];
     bool any = false;
@@ -764,19 +776,19 @@ __global__ __launch_bounds__(64 * WAVES) void k_cull_mlp(
       } else {
         constexpr int KSH = W / Prec<P>::K;
         typename Mfma<P>::Op op[NB][KSH];
-        // layer 1: h1 = relu(U + c1) (FP8: U dequantised first), as layer 2's operands
-        relu_pack<P, W, NB, true>(U, saH1, c1, invU, op);
-        mma_layer<P, W, NB>(W2p, b2p + grp * KQ, op, acc, lane);
-        relu_pack<P, W, NB, false>(acc, inv2 * saH2, nullptr, 1.f, op);
-        mma_layer<P, W, NB>(W3p, b3p + grp * KQ, op, acc, lane);
+        // layer 1: h1 = relu(U + c1) as layer 2's operands (FP8: both already in units of sa1)
+        relu_pack<P, W, NB, true>(U, 1.f, c1, 1.f, op);
+        mma_layer<P, W, NB>(W2p, b2p + grp * KQ, op, acc, lane, e2_a, e2_b);
+        relu_pack<P, W, NB, false>(acc, 1.f, nullptr, 1.f, op);
+        mma_layer<P, W, NB>(W3p, b3p + grp * KQ, op, acc, lane, e3_a, 127);
       }
-      // output layer in FP32 on h3 = relu(inv3 acc)
+      // output layer in FP32 on h3 = relu(acc)
       const float* wg = wop + grp * KQ;
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         float part = 0.f;
 #pragma unroll
-        for (int q = 0; q < KQ; ++q) part = fmaf(wg[q], relu(acc[b][q / 16][q % 16] * inv3), part);
+        for (int q = 0; q < KQ; ++q) part = fmaf(wg[q], relu(acc[b][q / 16][q % 16]), part);
         z[b] = part + __shfl_xor(part, 32) + bo;
         keep[b] = in[b] && z[b] >= 0.f;
       }
