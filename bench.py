@@ -262,6 +262,17 @@ def measured_traffic(stage, workload):
         return None
 
 
+def workspace_report(ctx):
+    """The context's device memory by class (GB) with the frame buffers'
+    capacities and bytes per splat and per entry (peak VRAM of the frame
+    beside the paper's VRAM figures, which are context, not a target)."""
+    w = ctx.workspace_info()
+    gb = {k: w[k] / 1e9 for k in ("total", "assets", "pairs", "splats", "entries", "tiles", "debug", "other")}
+    return {"gb": gb, "splat_capacity": w["splat_capacity"], "entry_capacity": w["entry_capacity"],
+            "bytes_per_splat": w["splats"] / max(1, w["splat_capacity"]),
+            "bytes_per_entry": w["entries"] / max(1, w["entry_capacity"])}
+
+
 def host_cpu():
     model = "unknown"
     try:
@@ -504,6 +515,7 @@ def main():
         "stage_rooflines": stage_roofs,
         "precisions": extra,
         "workspace_bytes": st_c["workspace_bytes"],
+        "workspace": workspace_report(ctx),
         "keep_frac_of_in_frustum": st_c["kept"] / max(1, st_c["in_frustum"]),
         "training": training,
     }
@@ -729,6 +741,7 @@ def main_batched(args):
         "duplicates": st["duplicates"], "blend_tests": st["blend_tests"], "ms_stage": stage,
         "dominant_kernel": dom, "roofline": roof,
         "stage_rooflines": stage_roofs, "workspace_bytes": st["workspace_bytes"],
+        "workspace": workspace_report(ctx),
         "training": training,
     }
     if not args.no_cpu_baseline:

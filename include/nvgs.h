@@ -302,6 +302,24 @@ nvgs_status nvgs_frame_watermarks(nvgs_ctx* ctx, int64_t* max_splats, int64_t* m
 /* Set / read the cull + MLP block shape used by later frames and queries
  * (default 32 Gaussians per wave, 64 segments per work-group, the autotuner's
  * choice on the composed 1080p scene for the FP32 and split-FP32 forms). */
+/* Device memory the context holds, by what it is sized by (bytes).  Frame
+ * buffers grow to the largest frame seen (or nvgs_reserve) and are kept. */
+typedef struct nvgs_workspace {
+  int64_t total;    /* every buffer: nvgs_frame_stats.workspace_bytes */
+  int64_t assets;   /* per asset and instance: projection and MLP operand images, embeddings, tables */
+  int64_t pairs;    /* per (camera, instance) segment and 256-pair chunk: keep masks, chunk counts and
+                       offsets, segment records, layer-1 camera halves, cameras */
+  int64_t splats;   /* per kept splat: compositing record (64 B), 8-byte tile rectangle in projection
+                       and depth order, depth key, id, tile count / entry offset (92 B) */
+  int64_t entries;  /* per (splat, tile) entry: tile key and id, the radix sort's ping-pong pair (which
+                       the depth sort of the splats uses first) and its histograms */
+  int64_t tiles;    /* per tile and compositing item: ranges, launch order, split-list records */
+  int64_t debug;    /* per splat, KEEP_DEBUG / RECORD_CONTRIB frames only: debug records (60 B) */
+  int64_t other;    /* frame counters, nvgs_sort_pairs' buffers, buffers of a call in progress */
+  int64_t splat_capacity, entry_capacity;  /* splats and entries the frame buffers hold */
+} nvgs_workspace;
+nvgs_status nvgs_workspace_info(nvgs_ctx* ctx, nvgs_workspace* out);
+
 /* Stable LSD radix sort, in place, of n (key, value) pairs held in device
  * arrays keys[n] and vals[n] (caller-owned), by key bits [begin_bit, end_bit)
  * (0 <= begin_bit <= end_bit <= 32; 8-bit digits, one pass each): pairs with

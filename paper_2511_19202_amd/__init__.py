@@ -92,6 +92,11 @@ class TuneEntry(C.Structure):
                 ("ms", C.c_float)]
 
 
+class Workspace(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in ("total", "assets", "pairs", "splats", "entries", "tiles", "debug", "other",
+                                         "splat_capacity", "entry_capacity")]
+
+
 class TrainOpts(C.Structure):
     _fields_ = [("batch", C.c_int64), ("steps", C.c_int32), ("precision", C.c_int32), ("lr", C.c_float),
                 ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float), ("seed", C.c_uint64),
@@ -128,6 +133,7 @@ _SIGS = {
                            C.c_void_p, C.c_void_p], C.c_int32),
     "nvgs_mlp_backward_noalloc": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p, C.c_int32,
                                    C.c_void_p, C.c_void_p], C.c_int32),
+    "nvgs_workspace_info": ([C.c_void_p, C.c_void_p], C.c_int32),
     "nvgs_sort_pairs": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_int32], C.c_int32),
     "nvgs_cmlp_forward": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p], C.c_int32),
     "nvgs_cmlp_backward": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int32, C.c_void_p],
@@ -372,6 +378,12 @@ class Context:
 
     def reserve(self, max_splats: int, max_duplicates: int):
         self._check(self.L.nvgs_reserve(self.h, int(max_splats), int(max_duplicates)))
+
+    def workspace_info(self) -> dict:
+        """Device memory the context holds, by class (nvgs_workspace)."""
+        w = Workspace()
+        self._check(self.L.nvgs_workspace_info(self.h, C.byref(w)))
+        return {name: int(getattr(w, name)) for name, _ in Workspace._fields_}
 
     def sort_pairs(self, keys, vals, begin_bit: int = 0, end_bit: int = 32):
         """Stable radix sort, in place, of two contiguous 32-bit device tensors

@@ -1,6 +1,7 @@
 // C ABI of the NVGS renderer: context, asset store, instance list, and the
 // per-frame launch sequence (declared in include/nvgs.h).
 #include <algorithm>
+#include <initializer_list>
 #include <cfloat>
 #include <cmath>
 #include <cstdio>
@@ -66,11 +67,19 @@ struct nvgs_ctx {
 
   // splats and sort buffers
   int64_t cap_splats = 0, cap_dup = 0;
-  Buf splat, rec_a, rec_b, rec_c, rec_d, rect, rect_sorted, depth_key, ids, ids_tmp, keys_tmp2, pair_of, cnt, dup_off;
+  // per splat: compositing record, 8-byte tile rectangle (projection order and
+  // depth order), depth key, ids, tile count (scanned in place into entry
+  // offsets); debug frames add rec_* , rect_dbg and pair_of
+  Buf splat, rec_a, rec_b, rec_c, rec_d, rect_dbg, rect, rect_sorted, depth_key, ids, pair_of, cnt;
+  // per entry: tile key and splat id, and the radix sort's ping-pong pair,
+  // which the depth sort of the splats uses first (sized for both)
   Buf keys, vals, keys_tmp, vals_tmp, hist, hist_part, ranges, tord;  // tord: tile order (4 arrays)
   Buf tsplit, citems, prodb, partb;  // long-list split: per-position counts and offsets, items, chunk products / records
   Buf sort_tmp, sort_ws;             // nvgs_sort_pairs: ping-pong pairs and workspace
   int64_t cap_items = 0, cap_split_px = 0;  // items; split slots x pixels per tile
+  // largest compositing-item and split-slot counts of the eager frames seen,
+  // per tile size (8, 16, 32): the sizes of the persistent frame's buffers
+  int64_t wm_items[3] = {}, wm_split[3] = {};
   int64_t cap_keys = 0;  // tile keys (cameras x tiles) the range buffers hold
   int64_t cap_hist = 0;  // longest list the sort histograms and scan partials cover
   int64_t cap_debug = 0; // splats the debug arrays hold
@@ -347,7 +356,7 @@ void nvgs_destroy(nvgs_ctx* ctx) {
   Buf* all[] = {&ctx->assets_dev, &ctx->inst_dev, &ctx->inst_off_dev, &ctx->seg_word_dev, &ctx->seg_chunk_dev,
                 &ctx->items_dev, &ctx->seglist_dev, &ctx->segs_dev, &ctx->c1_dev, &ctx->mask, &ctx->chunk_cnt,
                 &ctx->chunk_off, &ctx->scan_part, &ctx->cam_dev, &ctx->splat, &ctx->rect_sorted, &ctx->rec_a, &ctx->rec_b, &ctx->rec_c, &ctx->rec_d, &ctx->rect,
-                &ctx->depth_key, &ctx->ids, &ctx->ids_tmp, &ctx->keys_tmp2, &ctx->pair_of, &ctx->cnt, &ctx->dup_off,
+                &ctx->rect_dbg, &ctx->depth_key, &ctx->ids, &ctx->pair_of, &ctx->cnt,
                 &ctx->keys, &ctx->vals, &ctx->keys_tmp, &ctx->vals_tmp, &ctx->hist, &ctx->hist_part, &ctx->ranges, &ctx->tord,
                 &ctx->tsplit, &ctx->citems, &ctx->prodb, &ctx->partb, &ctx->sort_tmp, &ctx->sort_ws,
                 &ctx->counters};
@@ -551,7 +560,8 @@ nvgs_status size_debug(nvgs_ctx* ctx) {
   if (ctx->cap_debug >= ctx->cap_splats && ctx->cap_debug > 0) return NVGS_OK;
   const int64_t cap = ctx->cap_splats;
   if (!ensure(ctx, ctx->rec_a, 16 * cap) || !ensure(ctx, ctx->rec_b, 16 * cap) ||
-      !ensure(ctx, ctx->rec_c, 16 * cap) || !ensure(ctx, ctx->rec_d, 8 * cap) || !ensure(ctx, ctx->pair_of, 4 * cap)) {
+      !ensure(ctx, ctx->rec_c, 16 * cap) || !ensure(ctx, ctx->rec_d, 8 * cap) || !ensure(ctx, ctx->rect_dbg, 16 * cap) ||
+      !ensure(ctx, ctx->pair_of, 4 * cap)) {
     ctx->cap_debug = 0;
     return fail(ctx, NVGS_E_NOMEM, "debug buffers");
   }
@@ -559,17 +569,28 @@ nvgs_status size_debug(nvgs_ctx* ctx) {
   return NVGS_OK;
 }
 
+// The radix sort's ping-pong pair serves the splats' depth sort and the
+// entries' tile sort: after a failed allocation, the capacity it no longer
+// covers is dropped as well.
+void drop_shared_temps(nvgs_ctx* ctx) {
+  const size_t have = std::min(ctx->keys_tmp.bytes, ctx->vals_tmp.bytes);
+  if (have < 4 * (size_t)ctx->cap_splats) ctx->cap_splats = 0;
+  if (have < 4 * (size_t)ctx->cap_dup) ctx->cap_dup = 0;
+}
+
 // Grow-only splat buffers for `need` splats (1/8 headroom when `slack`).
 nvgs_status size_splats(nvgs_ctx* ctx, int64_t need, bool slack) {
   if (need <= ctx->cap_splats && ctx->cap_splats > 0) return NVGS_OK;
   const int64_t cap = std::max<int64_t>(slack ? need + need / 8 : need, 4096);
   ctx->cap_splats = 0;
-  const bool ok = ensure(ctx, ctx->splat, 64 * cap) && ensure(ctx, ctx->rect, 16 * cap) &&
-                  ensure(ctx, ctx->rect_sorted, 16 * cap) &&
-                  ensure(ctx, ctx->depth_key, 4 * cap) && ensure(ctx, ctx->ids, 4 * cap) &&
-                  ensure(ctx, ctx->ids_tmp, 4 * cap) && ensure(ctx, ctx->keys_tmp2, 4 * cap) &&
-                  ensure(ctx, ctx->cnt, 4 * cap) && ensure(ctx, ctx->dup_off, 4 * cap);
-  if (!ok) return fail(ctx, NVGS_E_NOMEM, "splat buffers");
+  const bool ok = ensure(ctx, ctx->splat, 64 * cap) && ensure(ctx, ctx->rect, 8 * cap) &&
+                  ensure(ctx, ctx->rect_sorted, 8 * cap) && ensure(ctx, ctx->depth_key, 4 * cap) &&
+                  ensure(ctx, ctx->ids, 4 * cap) && ensure(ctx, ctx->cnt, 4 * cap) &&
+                  ensure(ctx, ctx->keys_tmp, 4 * cap) && ensure(ctx, ctx->vals_tmp, 4 * cap);
+  if (!ok) {
+    drop_shared_temps(ctx);
+    return fail(ctx, NVGS_E_NOMEM, "splat buffers");
+  }
   ctx->cap_splats = cap;
   return size_hist(ctx);
 }
@@ -581,7 +602,10 @@ nvgs_status size_dups(nvgs_ctx* ctx, int64_t need, bool slack) {
   ctx->cap_dup = 0;
   const bool ok = ensure(ctx, ctx->keys, 4 * cap) && ensure(ctx, ctx->vals, 4 * cap) &&
                   ensure(ctx, ctx->keys_tmp, 4 * cap) && ensure(ctx, ctx->vals_tmp, 4 * cap);
-  if (!ok) return fail(ctx, NVGS_E_NOMEM, "tile entry buffers");
+  if (!ok) {
+    drop_shared_temps(ctx);
+    return fail(ctx, NVGS_E_NOMEM, "tile entry buffers");
+  }
   ctx->cap_dup = cap;
   return size_hist(ctx);
 }
@@ -591,28 +615,48 @@ nvgs_status size_tiles(nvgs_ctx* ctx, int64_t nkeys) {
   if (nkeys <= ctx->cap_keys) return NVGS_OK;
   ctx->cap_keys = 0;
   if (!ensure(ctx, ctx->ranges, sizeof(uint32_t) * 2 * (size_t)nkeys) ||
-      !ensure(ctx, ctx->tord, sizeof(uint32_t) * 4 * (size_t)nkeys))
+      !ensure(ctx, ctx->tord, sizeof(uint32_t) * 4 * (size_t)nkeys) ||
+      !ensure(ctx, ctx->tsplit, sizeof(uint32_t) * 4 * (size_t)nkeys))
     return fail(ctx, NVGS_E_NOMEM, "tile ranges");
   ctx->cap_keys = nkeys;
   return size_hist(ctx);
 }
 
-// Compositing items and split-chunk buffers for nkeys tiles of T x T pixels
-// and the current entry capacity.
-nvgs_status size_items(nvgs_ctx* ctx, int64_t nkeys, int T, int split_len) {
-  const int64_t per = split_len > 0 ? ctx->cap_dup / split_len : 0;
-  const int64_t cap_items = nkeys + per + 1;
-  const int64_t cap_split_px = split_len > 0 ? (2 * per + 2) * (int64_t)T * T : 0;
-  if (cap_items <= ctx->cap_items && cap_split_px <= ctx->cap_split_px && ctx->tsplit.bytes >= 16 * (size_t)nkeys)
-    return NVGS_OK;
+int tile_index(int T) { return T == 8 ? 0 : T == 16 ? 1 : 2; }
+
+// Compositing items and split-chunk buffers (grow-only) for a frame of nkeys
+// tiles of T x T pixels.  An eager frame passes its own counts (need_items,
+// need_split >= 0) and gets them with 1/8 headroom.  A persistent frame
+// passes -1: the largest counts of the eager frames seen at this tile size
+// plus 1/4, or, before any, the bound for the entry capacity (every list
+// longer than split_len splits into at most 2 len / split_len chunks).  A
+// frame beyond the capacity raises the overflow flag.
+nvgs_status size_items(nvgs_ctx* ctx, int64_t nkeys, int T, int split_len, int64_t need_items, int64_t need_split) {
+  int64_t items, slots;
+  const int ti = tile_index(T);
+  if (need_items >= 0) {
+    items = need_items + need_items / 8;
+    slots = need_split + need_split / 8;
+  } else if (ctx->wm_items[ti] > 0) {
+    items = ctx->wm_items[ti] + ctx->wm_items[ti] / 4 + 256;
+    slots = ctx->wm_split[ti] + ctx->wm_split[ti] / 4 + 16;
+  } else {
+    const int64_t per = split_len > 0 ? ctx->cap_dup / split_len : 0;
+    items = nkeys + per + 1;
+    slots = 2 * per + 2;
+  }
+  items = std::max(items, nkeys + 1);
+  const int64_t cap_split_px = split_len > 0 ? std::max<int64_t>(slots, 1) * T * T : 0;
+  if (items <= ctx->cap_items && cap_split_px <= ctx->cap_split_px) return NVGS_OK;
+  items = std::max(items, ctx->cap_items);
+  const int64_t px = std::max(cap_split_px, ctx->cap_split_px);
   ctx->cap_items = 0;
   ctx->cap_split_px = 0;
-  if (!ensure(ctx, ctx->tsplit, 16 * (size_t)nkeys) || !ensure(ctx, ctx->citems, 8 * (size_t)cap_items) ||
-      !ensure(ctx, ctx->prodb, 4 * (size_t)std::max<int64_t>(cap_split_px, 1)) ||
-      !ensure(ctx, ctx->partb, 16 * (size_t)std::max<int64_t>(cap_split_px, 1)))
+  if (!ensure(ctx, ctx->citems, 8 * (size_t)items) || !ensure(ctx, ctx->prodb, 4 * (size_t)std::max<int64_t>(px, 1)) ||
+      !ensure(ctx, ctx->partb, 16 * (size_t)std::max<int64_t>(px, 1)))
     return fail(ctx, NVGS_E_NOMEM, "compositing items");
-  ctx->cap_items = cap_items;
-  ctx->cap_split_px = cap_split_px;
+  ctx->cap_items = items;
+  ctx->cap_split_px = px;
   return NVGS_OK;
 }
 
@@ -630,7 +674,8 @@ struct Frame {
 // recorded.  Otherwise the reserved capacities bound every launch, nothing
 // is read back and no buffer is allocated, so the sequence can be captured;
 // kernels clamp to the capacities and raise overflow flags.
-nvgs_status enqueue_frame(nvgs_ctx* ctx, hipStream_t st, const Frame& f, bool eager, float* ms_bin_count) {
+nvgs_status enqueue_frame(nvgs_ctx* ctx, hipStream_t st, const Frame& f, bool eager, float* ms_bin_count,
+                          float* ms_tile_count) {
   hipEvent_t* ev = ctx->ev;
 #define STAGE_BEGIN(k) \
   if (eager) CK(hipEventRecord(ev[2 * (k)], st))
@@ -671,22 +716,27 @@ nvgs_status enqueue_frame(nvgs_ctx* ctx, hipStream_t st, const Frame& f, bool ea
   STAGE_BEGIN(NVGS_STAGE_PROJECT);
   CK(launch_project(P_<AssetDev>(ctx->assets_dev), P_<SegRec>(ctx->segs_dev), C * NI, P_<int64_t>(ctx->seg_chunk_dev),
                     ctx->n_chunks, P_<uint32_t>(ctx->mask), P_<uint32_t>(ctx->chunk_off), n_splats_dev,
-                    ctx->cap_splats, ns_bound, f.T, f.debug ? 1 : 0, opts->det_clip, P_<float4>(ctx->splat),
-                    P_<float4>(ctx->rec_a), P_<float4>(ctx->rec_b), P_<float4>(ctx->rec_c), P_<float2>(ctx->rec_d), P_<uint4>(ctx->rect),
+                    ctx->cap_splats, ns_bound, f.T, f.tiles_x, f.n_tiles, f.debug ? 1 : 0, opts->det_clip,
+                    P_<float4>(ctx->splat), P_<float4>(ctx->rec_a), P_<float4>(ctx->rec_b), P_<float4>(ctx->rec_c),
+                    P_<float2>(ctx->rec_d), P_<uint4>(ctx->rect_dbg), P_<uint2>(ctx->rect),
                     P_<uint32_t>(ctx->depth_key), P_<uint32_t>(ctx->pair_of), counters + 2, st));
   STAGE_END(NVGS_STAGE_PROJECT);
   // depth order of the splats (stable: equal depths keep id order)
   STAGE_BEGIN(NVGS_STAGE_DEPTH_SORT);
   bool in_tmp = false;
-  CK(launch_radix_sort(P_<uint32_t>(ctx->depth_key), P_<uint32_t>(ctx->ids), P_<uint32_t>(ctx->keys_tmp2),
-                       P_<uint32_t>(ctx->ids_tmp), n_splats_dev, ns_bound, 0, 32, 1, P_<uint32_t>(ctx->hist),
+  CK(launch_radix_sort(P_<uint32_t>(ctx->depth_key), P_<uint32_t>(ctx->ids), P_<uint32_t>(ctx->keys_tmp),
+                       P_<uint32_t>(ctx->vals_tmp), n_splats_dev, ns_bound, 0, 32, 1, P_<uint32_t>(ctx->hist),
                        P_<uint32_t>(ctx->hist_part), &in_tmp, st));
-  const uint32_t* depth_ids = in_tmp ? P_<uint32_t>(ctx->ids_tmp) : P_<uint32_t>(ctx->ids);
+  // four passes: the order ends in ids, and the ping-pong pair, which the
+  // entry sizing below may reallocate, is free again for the tile sort
+  if (in_tmp) return fail(ctx, NVGS_E_DEVICE, "depth sort: the order must end in the id buffer");
+  const uint32_t* depth_ids = P_<uint32_t>(ctx->ids);
   STAGE_END(NVGS_STAGE_DEPTH_SORT);
   STAGE_BEGIN(NVGS_STAGE_BIN);
-  CK(launch_gather_tiles(depth_ids, P_<uint4>(ctx->rect), n_splats_dev, ns_bound, P_<uint32_t>(ctx->cnt),
-                         P_<uint4>(ctx->rect_sorted), st));
-  CK(launch_scan_u32_dev(P_<uint32_t>(ctx->cnt), P_<uint32_t>(ctx->dup_off), ns_bound, n_splats_dev, counters + 1,
+  CK(launch_gather_tiles(depth_ids, P_<uint2>(ctx->rect), n_splats_dev, ns_bound, P_<uint32_t>(ctx->cnt),
+                         P_<uint2>(ctx->rect_sorted), st));
+  // tile counts -> entry offsets, in place
+  CK(launch_scan_u32_dev(P_<uint32_t>(ctx->cnt), P_<uint32_t>(ctx->cnt), ns_bound, n_splats_dev, counters + 1,
                          P_<uint32_t>(ctx->hist_part), st, counters + 2));
   STAGE_END(NVGS_STAGE_BIN);
   int64_t nd_bound = ctx->cap_dup;
@@ -698,11 +748,10 @@ nvgs_status enqueue_frame(nvgs_ctx* ctx, hipStream_t st, const Frame& f, bool ea
     if (ms_bin_count) CK(hipEventElapsedTime(ms_bin_count, ev[2 * NVGS_STAGE_BIN], ev[2 * NVGS_STAGE_BIN + 1]));
     if ((s = size_dups(ctx, nd_bound, true))) return s;
     if ((s = size_tiles(ctx, f.nkeys))) return s;
-    if ((s = size_items(ctx, f.nkeys, f.T, f.split_len))) return s;
   }
   const uint32_t* n_dup_dev = counters + 1;
   STAGE_BEGIN(NVGS_STAGE_BIN);
-  CK(launch_emit(depth_ids, P_<uint4>(ctx->rect_sorted), P_<uint32_t>(ctx->dup_off), n_splats_dev, ns_bound, n_dup_dev,
+  CK(launch_emit(depth_ids, P_<uint2>(ctx->rect_sorted), P_<uint32_t>(ctx->cnt), n_splats_dev, ns_bound, n_dup_dev,
                  ctx->cap_dup, f.tiles_x, f.n_tiles, P_<uint32_t>(ctx->keys), P_<uint32_t>(ctx->vals), counters + 2, st));
   STAGE_END(NVGS_STAGE_BIN);
   STAGE_BEGIN(NVGS_STAGE_TILE_SORT);
@@ -724,9 +773,24 @@ nvgs_status enqueue_frame(nvgs_ctx* ctx, hipStream_t st, const Frame& f, bool ea
   const uint32_t* tile_order = in_tmp3 ? tk + 3 * nk : tk + nk;
   // compositing items: long lists split into chunks
   uint32_t* ts = P_<uint32_t>(ctx->tsplit);
-  CK(launch_split_items(P_<uint32_t>(ctx->ranges), tile_order, nk, f.split_len, ts, ts + nk, ts + 2 * nk, ts + 3 * nk,
-                        counters + 16, counters + 17, P_<uint2>(ctx->citems), ctx->cap_items,
-                        P_<uint32_t>(ctx->hist_part), counters + 2, st));
+  CK(launch_split_count(P_<uint32_t>(ctx->ranges), tile_order, nk, f.split_len, ts, ts + nk, ts + 2 * nk, ts + 3 * nk,
+                        counters + 16, counters + 17, P_<uint32_t>(ctx->hist_part), st));
+  if (eager) {
+    // item and split-slot counts of this frame: the buffers are sized from them
+    STAGE_END(NVGS_STAGE_TILE_SORT);
+    if ((s = read_counters(ctx))) return s;
+    if (ms_tile_count)
+      CK(hipEventElapsedTime(ms_tile_count, ev[2 * NVGS_STAGE_TILE_SORT], ev[2 * NVGS_STAGE_TILE_SORT + 1]));
+    const int64_t n_items = ctx->counters_host[16], n_split = ctx->counters_host[17];
+    const int ti = tile_index(f.T);
+    ctx->wm_items[ti] = std::max(ctx->wm_items[ti], n_items);
+    ctx->wm_split[ti] = std::max(ctx->wm_split[ti], n_split);
+    if ((s = size_items(ctx, nk, f.T, f.split_len, n_items, n_split))) return s;
+    STAGE_BEGIN(NVGS_STAGE_TILE_SORT);
+  }
+  const int64_t cap_split = f.split_len > 0 ? ctx->cap_split_px / ((int64_t)f.T * f.T) : 0;
+  CK(launch_split_expand(ts, ts + 2 * nk, nk, P_<uint2>(ctx->citems), ctx->cap_items, counters + 17, cap_split,
+                         counters + 2, st));
   STAGE_END(NVGS_STAGE_TILE_SORT);
   STAGE_BEGIN(NVGS_STAGE_BLEND);
   BlendItems bi{};
@@ -739,7 +803,7 @@ nvgs_status enqueue_frame(nvgs_ctx* ctx, hipStream_t st, const Frame& f, bool ea
   bi.items = P_<uint2>(ctx->citems);
   bi.n_items = counters + 16;
   bi.cap_items = ctx->cap_items;
-  bi.cap_split = f.split_len > 0 ? ctx->cap_split_px / ((int64_t)f.T * f.T) : 0;
+  bi.cap_split = cap_split;
   bi.prod = P_<float>(ctx->prodb);
   bi.part = P_<float4>(ctx->partb);
   CK(launch_blend(bi, P_<uint32_t>(ctx->ranges), sids, P_<float4>(ctx->splat), f.W, f.H, f.T, f.tiles_x,
@@ -816,8 +880,8 @@ nvgs_status nvgs_render(nvgs_ctx* ctx, const nvgs_camera* cams, int32_t C, const
   hipStream_t st = ctx->stream;
   if (!graph) {
     if ((s = upload_cams(ctx, cams, C))) return s;
-    float ms_bin_count = 0.f;
-    if ((s = enqueue_frame(ctx, st, f, true, &ms_bin_count))) return s;
+    float ms_bin_count = 0.f, ms_tile_count = 0.f;
+    if ((s = enqueue_frame(ctx, st, f, true, &ms_bin_count, &ms_tile_count))) return s;
     if (stats) {
       if ((s = read_counters(ctx))) return s;
       float ms = 0.f;
@@ -828,6 +892,7 @@ nvgs_status nvgs_render(nvgs_ctx* ctx, const nvgs_camera* cams, int32_t C, const
         stats->ms_stage[k] = m;
       }
       stats->ms_stage[NVGS_STAGE_BIN] += ms_bin_count;
+      stats->ms_stage[NVGS_STAGE_TILE_SORT] += ms_tile_count;
       stats->ms_total = ms;
       fill_stats(ctx, f, stats);
       if (ctx->counters_host[2]) return fail(ctx, NVGS_E_CAPACITY, "capacity exceeded");
@@ -837,7 +902,7 @@ nvgs_status nvgs_render(nvgs_ctx* ctx, const nvgs_camera* cams, int32_t C, const
   // persistent frame
   if (ctx->cap_splats <= 0 || ctx->cap_dup <= 0)
     return fail(ctx, NVGS_E_STATE, "GRAPH frames need capacities: nvgs_reserve, or one frame without NVGS_RENDER_GRAPH");
-  if ((s = size_tiles(ctx, f.nkeys)) || (s = size_hist(ctx)) || (s = size_items(ctx, f.nkeys, f.T, f.split_len)))
+  if ((s = size_tiles(ctx, f.nkeys)) || (s = size_hist(ctx)) || (s = size_items(ctx, f.nkeys, f.T, f.split_len, -1, -1)))
     return s;
   if (f.debug && (s = size_debug(ctx))) return s;
   if (ctx->cap_keys < f.nkeys || ctx->cap_hist < std::max({ctx->cap_dup, ctx->cap_splats, ctx->cap_keys}) ||
@@ -859,7 +924,7 @@ nvgs_status nvgs_render(nvgs_ctx* ctx, const nvgs_camera* cams, int32_t C, const
       ctx->gexec = nullptr;
     }
     CK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
-    s = enqueue_frame(ctx, ctx->cap_stream, f, false, nullptr);
+    s = enqueue_frame(ctx, ctx->cap_stream, f, false, nullptr, nullptr);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(ctx->cap_stream, &g);
     if (s || e != hipSuccess) {
@@ -914,6 +979,31 @@ nvgs_status nvgs_frame_watermarks(nvgs_ctx* ctx, int64_t* max_splats, int64_t* m
     CK(launch_fill_u32(P_<uint32_t>(ctx->counters) + 12, 0u, 3, ctx->stream));
     CK(hipStreamSynchronize(ctx->stream));
   }
+  return NVGS_OK;
+}
+
+nvgs_status nvgs_workspace_info(nvgs_ctx* ctx, nvgs_workspace* out) {
+  if (!ctx) return NVGS_E_INVALID;
+  if (!out) return fail(ctx, NVGS_E_INVALID, "workspace_info: null out");
+  auto sum = [](std::initializer_list<const Buf*> l) {
+    int64_t t = 0;
+    for (const Buf* b : l) t += (int64_t)b->bytes;
+    return t;
+  };
+  nvgs_workspace w{};
+  w.total = (int64_t)ctx->workspace;
+  w.assets = sum({&ctx->assets_dev, &ctx->inst_dev, &ctx->inst_off_dev});
+  for (const Buf& b : ctx->op_bufs) w.assets += (int64_t)b.bytes;
+  w.pairs = sum({&ctx->seg_word_dev, &ctx->seg_chunk_dev, &ctx->items_dev, &ctx->seglist_dev, &ctx->segs_dev,
+                 &ctx->c1_dev, &ctx->mask, &ctx->chunk_cnt, &ctx->chunk_off, &ctx->scan_part, &ctx->cam_dev});
+  w.splats = sum({&ctx->splat, &ctx->rect, &ctx->rect_sorted, &ctx->depth_key, &ctx->ids, &ctx->cnt});
+  w.entries = sum({&ctx->keys, &ctx->vals, &ctx->keys_tmp, &ctx->vals_tmp, &ctx->hist, &ctx->hist_part});
+  w.tiles = sum({&ctx->ranges, &ctx->tord, &ctx->tsplit, &ctx->citems, &ctx->prodb, &ctx->partb});
+  w.debug = sum({&ctx->rec_a, &ctx->rec_b, &ctx->rec_c, &ctx->rec_d, &ctx->rect_dbg, &ctx->pair_of});
+  w.other = w.total - (w.assets + w.pairs + w.splats + w.entries + w.tiles + w.debug);
+  w.splat_capacity = ctx->cap_splats;
+  w.entry_capacity = ctx->cap_dup;
+  *out = w;
   return NVGS_OK;
 }
 
@@ -1052,7 +1142,7 @@ nvgs_status nvgs_debug_buffers(nvgs_ctx* ctx, nvgs_debug_view* out) {
   out->rec_b = ctx->last_debug ? P_<float>(ctx->rec_b) : nullptr;
   out->rec_c = ctx->last_debug ? P_<float>(ctx->rec_c) : nullptr;
   out->rec_d = ctx->last_debug ? P_<float>(ctx->rec_d) : nullptr;
-  out->rect = P_<uint32_t>(ctx->rect);
+  out->rect = P_<uint32_t>(ctx->rect_dbg);
   out->sorted_key = ctx->last_sorted_key;
   out->sorted_id = ctx->last_sorted_id;
   out->ranges = P_<uint32_t>(ctx->ranges);

@@ -143,18 +143,19 @@ size_t scan_partials_needed(int64_t n);
 
 hipError_t launch_project(const AssetDev* assets, const SegRec* segs, int32_t n_segs, const int64_t* seg_chunk_base,
                           int64_t n_chunks, const uint32_t* mask, const uint32_t* chunk_off, const uint32_t* n_splats,
-                          int64_t cap_splats, int64_t grid_slots, int tile, int keep_debug, float det_clip,
-                          float4* splat, float4* rec_a, float4* rec_b, float4* rec_c, float2* rec_d, uint4* rect,
-                          uint32_t* depth_key, uint32_t* pair_of, uint32_t* overflow, hipStream_t st);
+                          int64_t cap_splats, int64_t grid_slots, int tile, int tiles_x, int n_tiles, int keep_debug,
+                          float det_clip, float4* splat, float4* rec_a, float4* rec_b, float4* rec_c, float2* rec_d,
+                          uint4* rect_dbg, uint2* rect, uint32_t* depth_key, uint32_t* pair_of, uint32_t* overflow,
+                          hipStream_t st);
 
 hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint32_t* vals_tmp,
                              const uint32_t* n_dev, int64_t cap, int begin_bit, int end_bit, int iota_vals,
                              uint32_t* hist, uint32_t* partials, bool* result_in_tmp, hipStream_t st);
 size_t radix_hist_words(int64_t cap);  // sort workspace (32-bit words) for up to cap keys
 
-hipError_t launch_gather_tiles(const uint32_t* sorted_ids, const uint4* rect, const uint32_t* n_dev, int64_t cap,
-                               uint32_t* out, uint4* rect_sorted, hipStream_t st);
-hipError_t launch_emit(const uint32_t* sorted_ids, const uint4* rect_sorted, const uint32_t* dup_off, const uint32_t* n_dev,
+hipError_t launch_gather_tiles(const uint32_t* sorted_ids, const uint2* rect, const uint32_t* n_dev, int64_t cap,
+                               uint32_t* out, uint2* rect_sorted, hipStream_t st);
+hipError_t launch_emit(const uint32_t* sorted_ids, const uint2* rect_sorted, const uint32_t* dup_off, const uint32_t* n_dev,
                        int64_t cap, const uint32_t* n_dup_dev, int64_t cap_dup, int tiles_x, int n_tiles,
                        uint32_t* keys, uint32_t* vals, uint32_t* overflow, hipStream_t st);
 hipError_t launch_watermark(uint32_t* counters, hipStream_t st);
@@ -180,10 +181,12 @@ struct BlendItems {
 };
 // Builds nch / item_off / split_off and the item list; n_items and n_split
 // receive the totals; overflow bit value 8 when cap_items is exceeded.
-hipError_t launch_split_items(const uint32_t* ranges, const uint32_t* order, int64_t nkeys, int split_len,
+hipError_t launch_split_count(const uint32_t* ranges, const uint32_t* order, int64_t nkeys, int split_len,
                               uint32_t* nch, uint32_t* nsp, uint32_t* item_off, uint32_t* split_off, uint32_t* n_items,
-                              uint32_t* n_split, uint2* items, int64_t cap_items, uint32_t* partials,
-                              uint32_t* overflow, hipStream_t st);
+                              uint32_t* n_split, uint32_t* partials, hipStream_t st);
+hipError_t launch_split_expand(const uint32_t* nch, const uint32_t* item_off, int64_t nkeys, uint2* items,
+                               int64_t cap_items, const uint32_t* n_split, int64_t cap_split, uint32_t* overflow,
+                               hipStream_t st);
 // splat: [n][4] float4 compositing records written by launch_project
 hipError_t launch_blend(const BlendItems& bi, const uint32_t* ranges, const uint32_t* ids, const float4* splat, int W,
                         int H, int tile, int tiles_x, int tiles_y, float bg0, float bg1, float bg2, float* rgb,

@@ -206,10 +206,10 @@ __device__ __forceinline__ void pixel_range(float u, float e, int size, int* lo,
 // `slot`: the compositing record, tile rectangle, depth key and, on debug
 // frames, the per-splat debug arrays.
 __device__ __forceinline__ void project_pair(
-    const AssetDev* __restrict__ assets, const SegRec& R, int64_t g, uint32_t slot, int tile, int keep_debug,
-    float det_clip, float4* __restrict__ splat, float4* __restrict__ rec_a, float4* __restrict__ rec_b,
-    float4* __restrict__ rec_c, float2* __restrict__ rec_d, uint4* __restrict__ rect, uint32_t* __restrict__ depth_key,
-    uint32_t* __restrict__ pair_of) {
+    const AssetDev* __restrict__ assets, const SegRec& R, int64_t g, uint32_t slot, int tile, int tiles_x,
+    int n_tiles, int keep_debug, float det_clip, float4* __restrict__ splat, float4* __restrict__ rec_a,
+    float4* __restrict__ rec_b, float4* __restrict__ rec_c, float2* __restrict__ rec_d, uint4* __restrict__ rect_dbg,
+    uint2* __restrict__ rect, uint32_t* __restrict__ depth_key, uint32_t* __restrict__ pair_of) {
   const AssetDev& A = assets[R.asset];
   const float4 g0 = ld_global(A.geo, 3 * g), g1 = ld_global(A.geo, 3 * g + 1), g2 = ld_global(A.geo, 3 * g + 2);
   const float mu[3] = {g0.x, g0.y, g0.z};
@@ -301,7 +301,7 @@ __device__ __forceinline__ void project_pair(
   const float k2 = 2.f * logf(255.f * o);
   const int W = (int)(2.f * R.half_w), H = (int)(2.f * R.half_h);
   float ex = 0.f, ey = 0.f;
-  uint32_t r0 = 0, r1 = 0, ntiles = 0;
+  uint32_t r0 = 0, r1 = 0, ntiles = 0, key0 = 0, wh = 0;
   if (k2 >= 0.f && !(det < det_clip)) {  // radius clipping: splats of small 2D area are not binned
     ex = sqrtf(k2 * a);
     ey = sqrtf(k2 * cc);
@@ -313,6 +313,10 @@ __device__ __forceinline__ void project_pair(
       r0 = (uint32_t)tx0 | ((uint32_t)ty0 << 16);
       r1 = (uint32_t)tx1 | ((uint32_t)ty1 << 16);
       ntiles = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+      // the binning's 8-byte form: the tile key of the top-left tile, and
+      // the rectangle's width and height in tiles
+      key0 = (uint32_t)R.cam * (uint32_t)n_tiles + (uint32_t)ty0 * (uint32_t)tiles_x + (uint32_t)tx0;
+      wh = (uint32_t)(tx1 - tx0 + 1) | ((uint32_t)(ty1 - ty0 + 1) << 16);
     }
   }
   // the compositing record: one 64-byte line per splat: the centre (hi
@@ -326,13 +330,14 @@ __device__ __forceinline__ void project_pair(
   sp[1] = make_float4(f2x, f2y, __log2f(o), rgb[0]);
   sp[2] = make_float4(rgb[1], rgb[2], u_lo, v_lo);
   sp[3] = make_float4(__uint_as_float((uint32_t)(R.pair_base + g)), __builtin_bit_cast(float, exy), pz, 0.f);
-  rect[slot] = make_uint4(r0, r1, (uint32_t)R.cam, ntiles);
+  rect[slot] = make_uint2(key0, wh);
   depth_key[slot] = fbits(pz);
   if (keep_debug) {
     rec_a[slot] = make_float4(u, v, ca, cb);
     rec_b[slot] = make_float4(cc2, o, rgb[0], rgb[1]);
     rec_c[slot] = make_float4(rgb[2], pz, ex, ey);
     rec_d[slot] = make_float2(u_lo, v_lo);
+    rect_dbg[slot] = make_uint4(r0, r1, (uint32_t)R.cam, ntiles);
     pair_of[slot] = (uint32_t)(R.pair_base + g);
   }
 
@@ -351,9 +356,10 @@ __global__ __launch_bounds__(256) void k_project(
     const AssetDev* __restrict__ assets, const SegRec* __restrict__ segs, int32_t n_segs,
     const int64_t* __restrict__ seg_chunk_base, int64_t n_chunks, const uint32_t* __restrict__ mask,
     const uint32_t* __restrict__ chunk_off, const uint32_t* __restrict__ n_splats, int64_t cap, int tile,
-    int keep_debug, float det_clip, float4* __restrict__ splat, float4* __restrict__ rec_a,
-    float4* __restrict__ rec_b, float4* __restrict__ rec_c, float2* __restrict__ rec_d, uint4* __restrict__ rect,
-    uint32_t* __restrict__ depth_key, uint32_t* __restrict__ pair_of, uint32_t* __restrict__ overflow) {
+    int tiles_x, int n_tiles, int keep_debug, float det_clip, float4* __restrict__ splat,
+    float4* __restrict__ rec_a, float4* __restrict__ rec_b, float4* __restrict__ rec_c, float2* __restrict__ rec_d,
+    uint4* __restrict__ rect_dbg, uint2* __restrict__ rect, uint32_t* __restrict__ depth_key,
+    uint32_t* __restrict__ pair_of, uint32_t* __restrict__ overflow) {
   const uint32_t n_all = *n_splats;
   if (blockIdx.x == 0 && threadIdx.x == 0 && (int64_t)n_all > cap) atomicOr(overflow, 1u);
   const int64_t ns = min((int64_t)n_all, cap);
@@ -418,22 +424,24 @@ __global__ __launch_bounds__(256) void k_project(
       }
     }
     const int64_t g = cl * kChunk + wsel * 32 + pos;
-    project_pair(assets, R, g, (uint32_t)slot, tile, keep_debug, det_clip, splat, rec_a, rec_b, rec_c, rec_d, rect,
-                 depth_key, pair_of);
+    project_pair(assets, R, g, (uint32_t)slot, tile, tiles_x, n_tiles, keep_debug, det_clip, splat, rec_a, rec_b,
+                 rec_c, rec_d, rect_dbg, rect, depth_key, pair_of);
   }
 }
 
 hipError_t launch_project(const AssetDev* assets, const SegRec* segs, int32_t n_segs, const int64_t* seg_chunk_base,
                           int64_t n_chunks, const uint32_t* mask, const uint32_t* chunk_off, const uint32_t* n_splats,
-                          int64_t cap_splats, int64_t grid_slots, int tile, int keep_debug, float det_clip,
-                          float4* splat, float4* rec_a, float4* rec_b, float4* rec_c, float2* rec_d, uint4* rect,
-                          uint32_t* depth_key, uint32_t* pair_of, uint32_t* overflow, hipStream_t st) {
+                          int64_t cap_splats, int64_t grid_slots, int tile, int tiles_x, int n_tiles, int keep_debug,
+                          float det_clip, float4* splat, float4* rec_a, float4* rec_b, float4* rec_c, float2* rec_d,
+                          uint4* rect_dbg, uint2* rect, uint32_t* depth_key, uint32_t* pair_of, uint32_t* overflow,
+                          hipStream_t st) {
   if (n_chunks == 0 || n_segs == 0) return hipSuccess;
   // slots beyond the capacity are never written (the kernel raises the overflow flag)
   const int64_t slots = std::max<int64_t>(std::min(grid_slots, cap_splats), 1);
   hipLaunchKernelGGL(k_project, dim3((unsigned)((slots + 255) / 256)), dim3(256), 0, st, assets, segs, n_segs,
-                     seg_chunk_base, n_chunks, mask, chunk_off, n_splats, cap_splats, tile, keep_debug, det_clip,
-                     splat, rec_a, rec_b, rec_c, rec_d, rect, depth_key, pair_of, overflow);
+                     seg_chunk_base, n_chunks, mask, chunk_off, n_splats, cap_splats, tile, tiles_x, n_tiles,
+                     keep_debug, det_clip, splat, rec_a, rec_b, rec_c, rec_d, rect_dbg, rect, depth_key, pair_of,
+                     overflow);
   return hipGetLastError();
 }
 
@@ -446,19 +454,19 @@ __device__ __forceinline__ int64_t live(const uint32_t* n_dev, int64_t cap) {
 
 // tile counts of the splats in depth order, and their rectangles copied into
 // depth order so that the emission reads them sequentially
-__global__ void k_gather_tiles(const uint32_t* __restrict__ ids, const uint4* __restrict__ rect,
+__global__ void k_gather_tiles(const uint32_t* __restrict__ ids, const uint2* __restrict__ rect,
                                const uint32_t* __restrict__ n_dev, int64_t cap, uint32_t* __restrict__ out,
-                               uint4* __restrict__ rect_sorted) {
+                               uint2* __restrict__ rect_sorted) {
   const int64_t n = live(n_dev, cap);
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
-    const uint4 r = rect[ids[j]];
-    out[j] = r.w;
+    const uint2 r = rect[ids[j]];
+    out[j] = (r.y & 0xffffu) * (r.y >> 16);  // tiles: width x height
     rect_sorted[j] = r;
   }
 }
 
-hipError_t launch_gather_tiles(const uint32_t* sorted_ids, const uint4* rect, const uint32_t* n_dev, int64_t cap,
-                               uint32_t* out, uint4* rect_sorted, hipStream_t st) {
+hipError_t launch_gather_tiles(const uint32_t* sorted_ids, const uint2* rect, const uint32_t* n_dev, int64_t cap,
+                               uint32_t* out, uint2* rect_sorted, hipStream_t st) {
   if (cap == 0) return hipSuccess;
   unsigned grid = (unsigned)std::min<int64_t>((cap + 255) / 256, 65536);
   hipLaunchKernelGGL(k_gather_tiles, dim3(grid), dim3(256), 0, st, sorted_ids, rect, n_dev, cap, out, rect_sorted);
@@ -474,7 +482,7 @@ hipError_t launch_gather_tiles(const uint32_t* sorted_ids, const uint4* rect, co
 // lanes).  Past the entry capacity the overflow flag is raised and only the
 // entries below it are written, so every position of [0, cap_dup) still holds
 // an entry of this frame (a clipped frame, never stale keys).
-__global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ ids, const uint4* __restrict__ rect_sorted,
+__global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ ids, const uint2* __restrict__ rect_sorted,
                                               const uint32_t* __restrict__ off, const uint32_t* __restrict__ n_dev,
                                               int64_t cap, const uint32_t* __restrict__ n_dup_dev, int64_t cap_dup,
                                               int tiles_x, int n_tiles, uint32_t* __restrict__ keys,
@@ -485,7 +493,7 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ ids, 
   const int64_t wstride = (int64_t)gridDim.x * (blockDim.x / 64);
   for (int64_t grp = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); grp < ngroups; grp += wstride) {
     const int64_t j = grp * 64 + lane;
-    uint4 r = make_uint4(0u, 0u, 0u, 0u);
+    uint2 r = make_uint2(0u, 0u);  // (tile key of the top-left tile, width | height << 16)
     uint32_t o = 0u, id = 0u;
     if (j < n) {
       r = rect_sorted[j];
@@ -494,7 +502,7 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ ids, 
     }
     const uint32_t start = __shfl(o, 0);  // lane 0's splat is live
     const uint32_t rel = j < n ? o - start : 0xffffffffu;
-    uint32_t total = j < n ? rel + r.w : 0u;
+    uint32_t total = j < n ? rel + (r.y & 0xffffu) * (r.y >> 16) : 0u;
 #pragma unroll
     for (int m = 32; m > 0; m >>= 1) total = max(total, __shfl_xor(total, m));
     if (lane == 0 && (int64_t)start + total > cap_dup) atomicOr(overflow, 2u);
@@ -507,20 +515,20 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ ids, 
       for (int step = 32; step > 0; step >>= 1)
         if (__shfl(rel, src + step) <= e) src += step;
       const uint32_t q = e - __shfl(rel, src);
-      const uint32_t rx = __shfl(r.x, src), ry = __shfl(r.y, src), rz = __shfl(r.z, src), sid = __shfl(id, src);
-      const uint32_t tx0 = rx & 0xffffu, ty0 = rx >> 16, w = (ry & 0xffffu) - tx0 + 1u;
-      const uint32_t dy = q / w, dx = q - dy * w;
+      const uint32_t key0 = __shfl(r.x, src), w = __shfl(r.y, src) & 0xffffu, sid = __shfl(id, src);
+      const uint32_t dy = q / max(w, 1u), dx = q - dy * w;
       const int64_t pos = (int64_t)start + e;
       if (e < total && pos < cap_dup) {
-        keys[pos] = rz * (uint32_t)n_tiles + (ty0 + dy) * (uint32_t)tiles_x + tx0 + dx;
+        keys[pos] = key0 + dy * (uint32_t)tiles_x + dx;
         vals[pos] = sid;
       }
     }
   }
   (void)n_dup_dev;
+  (void)n_tiles;
 }
 
-hipError_t launch_emit(const uint32_t* sorted_ids, const uint4* rect_sorted, const uint32_t* dup_off, const uint32_t* n_dev,
+hipError_t launch_emit(const uint32_t* sorted_ids, const uint2* rect_sorted, const uint32_t* dup_off, const uint32_t* n_dev,
                        int64_t cap, const uint32_t* n_dup_dev, int64_t cap_dup, int tiles_x, int n_tiles,
                        uint32_t* keys, uint32_t* vals, uint32_t* overflow, hipStream_t st) {
   if (cap == 0) return hipSuccess;
@@ -653,8 +661,12 @@ __global__ void k_split_count(const uint32_t* __restrict__ ranges, const uint32_
   }
 }
 
+// Items of every launch position; past the item or split-slot capacity the
+// overflow flag (8) is raised (such a frame is reported, never used).
 __global__ void k_split_expand(const uint32_t* __restrict__ nch, const uint32_t* __restrict__ item_off, int64_t nkeys,
-                               int64_t cap_items, uint2* __restrict__ items, uint32_t* __restrict__ overflow) {
+                               int64_t cap_items, uint2* __restrict__ items, const uint32_t* __restrict__ n_split,
+                               int64_t cap_split, uint32_t* __restrict__ overflow) {
+  if (blockIdx.x == 0 && threadIdx.x == 0 && (int64_t)*n_split > cap_split) atomicOr(overflow, 8u);
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < nkeys; p += (int64_t)gridDim.x * blockDim.x) {
     const uint32_t c = nch[p], o = item_off[p];
     for (uint32_t j = 0; j < c; ++j) {
@@ -709,7 +721,7 @@ __device__ __forceinline__ void blend_item(
   __shared__ uint32_t s_ov[T == 8 ? 1 : BATCH];  // bit b: the footprint box touches 8x8 block b
   __shared__ uint32_t s_p[RECORD ? BATCH : 1];
   const bool split = nch > 1;
-  if (split && (int64_t)ic.split_off[it.x] + nch > ic.cap_split) return;  // cannot happen within the sizing bound
+  if (split && (int64_t)ic.split_off[it.x] + nch > ic.cap_split) return;  // over capacity: the frame is flagged
   const int key = (int)ic.order[it.x];
   const int cam = key / n_tiles, tile = key % n_tiles;
   const int tx = tile % tiles_x, ty = tile / tiles_x;
@@ -1016,18 +1028,25 @@ static void launch_blend_t(bool record, const ItemCtx& ic, bool any_split, hipSt
                        H, tiles_x, n_tiles, b0, b1, b2, rgb);
 }
 
-hipError_t launch_split_items(const uint32_t* ranges, const uint32_t* order, int64_t nkeys, int split_len,
+// chunks per launch position, their offsets and the totals (items, split slots)
+hipError_t launch_split_count(const uint32_t* ranges, const uint32_t* order, int64_t nkeys, int split_len,
                               uint32_t* nch, uint32_t* nsp, uint32_t* item_off, uint32_t* split_off, uint32_t* n_items,
-                              uint32_t* n_split, uint2* items, int64_t cap_items, uint32_t* partials,
-                              uint32_t* overflow, hipStream_t st) {
+                              uint32_t* n_split, uint32_t* partials, hipStream_t st) {
   if (nkeys == 0) return hipSuccess;
   const unsigned grid = (unsigned)std::min<int64_t>((nkeys + 255) / 256, 65536);
   hipLaunchKernelGGL(k_split_count, dim3(grid), dim3(256), 0, st, ranges, order, nkeys, split_len, nch, nsp);
   hipError_t e = launch_scan_u32_dev(nch, item_off, nkeys, nullptr, n_items, partials, st, nullptr);
   if (e != hipSuccess) return e;
-  e = launch_scan_u32_dev(nsp, split_off, nkeys, nullptr, n_split, partials, st, nullptr);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_split_expand, dim3(grid), dim3(256), 0, st, nch, item_off, nkeys, cap_items, items, overflow);
+  return launch_scan_u32_dev(nsp, split_off, nkeys, nullptr, n_split, partials, st, nullptr);
+}
+
+hipError_t launch_split_expand(const uint32_t* nch, const uint32_t* item_off, int64_t nkeys, uint2* items,
+                               int64_t cap_items, const uint32_t* n_split, int64_t cap_split, uint32_t* overflow,
+                               hipStream_t st) {
+  if (nkeys == 0) return hipSuccess;
+  const unsigned grid = (unsigned)std::min<int64_t>((nkeys + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_split_expand, dim3(grid), dim3(256), 0, st, nch, item_off, nkeys, cap_items, items, n_split,
+                     cap_split, overflow);
   return hipGetLastError();
 }
 

@@ -53,7 +53,7 @@ def test_struct_layouts_match_the_header():
                "nvgs_instance": nvgs.Instance, "nvgs_camera": nvgs.Camera, "nvgs_render_opts": nvgs.RenderOpts,
                "nvgs_frame_stats": nvgs.FrameStats, "nvgs_debug_view": nvgs.DebugView,
                "nvgs_train_opts": nvgs.TrainOpts, "nvgs_mlp_shape": nvgs.MlpShape,
-               "nvgs_tune_entry": nvgs.TuneEntry}
+               "nvgs_tune_entry": nvgs.TuneEntry, "nvgs_workspace": nvgs.Workspace}
     body = "\n".join(f'printf("%zu\\n", sizeof({k}));' for k in structs)
     with tempfile.TemporaryDirectory() as d:
         c = os.path.join(d, "s.c")

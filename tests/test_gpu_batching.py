@@ -157,6 +157,15 @@ def test_graph_frame_overflow_is_reported(env):
     eager = ctx.render(sc.cameras, tile=16)
     same = np.array_equal(g.cpu().numpy(), eager.cpu().numpy())
     assert same, "graph frame differs from the eager frame"
+    # the workspace by class: the classes add up, a splat costs 92 bytes and
+    # an entry at least 16 (key and id, plus the shared ping-pong pair)
+    _, st = ctx.render(sc.cameras, tile=16, stats=True)
+    w = ctx.workspace_info()
+    log(f"[workspace] {w}")
+    assert w["total"] == st["workspace_bytes"]
+    assert w["other"] >= 0 and w["debug"] == 0
+    assert w["splats"] == 92 * w["splat_capacity"] and w["splat_capacity"] >= st["kept"]
+    assert w["entries"] >= 16 * w["entry_capacity"] and w["entry_capacity"] >= st["duplicates"]
     ctx.close()
 
 
