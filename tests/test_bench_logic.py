@@ -21,12 +21,12 @@ def test_projection_bytes_per_splat():
     # algorithmic: SH3 236 B Gaussian (56 B + 180 B of higher SH) read + 48 B splat written
     r = bench.stage_roof("project", 1.0, _st(kept=10 ** 6), 64, "fp32", 3, 32400)
     assert abs(r["achieved"] - 284e6 / 1e-3 / 1e9) < 1e-6
-    # implementation: 48 B geometry + 48 floats of SH (192 B) read + 84 B written
-    assert abs(r["impl_achieved"] - 324e6 / 1e-3 / 1e9) < 1e-6
+    # implementation: 48 B geometry + 48 floats of SH (192 B) read + 76 B written
+    assert abs(r["impl_achieved"] - 316e6 / 1e-3 / 1e9) < 1e-6
     # SH0: 56 + 48 B; the implementation reads 3 floats rounded up to 4 (16 B)
     r0 = bench.stage_roof("project", 1.0, _st(kept=10 ** 6), 64, "fp32", 0, 32400)
     assert abs(r0["achieved"] - 104e6 / 1e-3 / 1e9) < 1e-6
-    assert abs(r0["impl_achieved"] - 148e6 / 1e-3 / 1e9) < 1e-6
+    assert abs(r0["impl_achieved"] - 140e6 / 1e-3 / 1e9) < 1e-6
 
 
 def test_sort_and_binning_bytes():
