@@ -714,12 +714,13 @@ nvgs_status enqueue_frame(nvgs_ctx* ctx, hipStream_t st, const Frame& f, bool ea
   }
   const uint32_t* n_splats_dev = counters + 0;
   STAGE_BEGIN(NVGS_STAGE_PROJECT);
-  CK(launch_project(P_<AssetDev>(ctx->assets_dev), P_<SegRec>(ctx->segs_dev), C * NI, P_<int64_t>(ctx->seg_chunk_dev),
-                    ctx->n_chunks, P_<uint32_t>(ctx->mask), P_<uint32_t>(ctx->chunk_off), n_splats_dev,
-                    ctx->cap_splats, ns_bound, f.T, f.tiles_x, f.n_tiles, f.debug ? 1 : 0, opts->det_clip,
-                    P_<float4>(ctx->splat), P_<float4>(ctx->rec_a), P_<float4>(ctx->rec_b), P_<float4>(ctx->rec_c),
-                    P_<float2>(ctx->rec_d), P_<uint4>(ctx->rect_dbg), P_<uint2>(ctx->rect),
-                    P_<uint32_t>(ctx->depth_key), P_<uint32_t>(ctx->pair_of), counters + 2, st));
+  CK(launch_project(P_<AssetDev>(ctx->assets_dev), P_<WorkItem>(ctx->items_dev), (int64_t)ctx->items.size(),
+                    P_<int32_t>(ctx->seglist_dev), P_<SegRec>(ctx->segs_dev), P_<uint32_t>(ctx->mask),
+                    P_<uint32_t>(ctx->chunk_off), n_splats_dev, ctx->cap_splats, f.T, f.tiles_x, f.n_tiles,
+                    f.debug ? 1 : 0, opts->det_clip, P_<float4>(ctx->splat), P_<float4>(ctx->rec_a),
+                    P_<float4>(ctx->rec_b), P_<float4>(ctx->rec_c), P_<float2>(ctx->rec_d), P_<uint4>(ctx->rect_dbg),
+                    P_<uint2>(ctx->rect), P_<uint32_t>(ctx->depth_key), P_<uint32_t>(ctx->pair_of), counters + 2,
+                    st));
   STAGE_END(NVGS_STAGE_PROJECT);
   // depth order of the splats (stable: equal depths keep id order)
   STAGE_BEGIN(NVGS_STAGE_DEPTH_SORT);

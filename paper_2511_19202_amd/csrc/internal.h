@@ -141,12 +141,11 @@ hipError_t launch_scan_u32_dev(const uint32_t* in, uint32_t* out, int64_t n, con
                                uint32_t* partials, hipStream_t st, uint32_t* wrap);
 size_t scan_partials_needed(int64_t n);
 
-hipError_t launch_project(const AssetDev* assets, const SegRec* segs, int32_t n_segs, const int64_t* seg_chunk_base,
-                          int64_t n_chunks, const uint32_t* mask, const uint32_t* chunk_off, const uint32_t* n_splats,
-                          int64_t cap_splats, int64_t grid_slots, int tile, int tiles_x, int n_tiles, int keep_debug,
-                          float det_clip, float4* splat, float4* rec_a, float4* rec_b, float4* rec_c, float2* rec_d,
-                          uint4* rect_dbg, uint2* rect, uint32_t* depth_key, uint32_t* pair_of, uint32_t* overflow,
-                          hipStream_t st);
+hipError_t launch_project(const AssetDev* assets, const WorkItem* items, int64_t n_items, const int32_t* seglist,
+                          const SegRec* segs, const uint32_t* mask, const uint32_t* chunk_off, const uint32_t* n_splats,
+                          int64_t cap_splats, int tile, int tiles_x, int n_tiles, int keep_debug, float det_clip,
+                          float4* splat, float4* rec_a, float4* rec_b, float4* rec_c, float2* rec_d, uint4* rect_dbg,
+                          uint2* rect, uint32_t* depth_key, uint32_t* pair_of, uint32_t* overflow, hipStream_t st);
 
 hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint32_t* vals_tmp,
                              const uint32_t* n_dev, int64_t cap, int begin_bit, int end_bit, int iota_vals,

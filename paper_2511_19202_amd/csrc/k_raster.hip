@@ -34,7 +34,7 @@ __device__ __forceinline__ float4 ld_global(const float4* p, int64_t i) {
   return make_float4(v.x, v.y, v.z, v.w);
 }
 
-template <int D>
+template <int D, bool SHARED>
 __device__ __forceinline__ void sh_color_t(const float4* __restrict__ row, float x, float y, float z, float rgb[3]) {
   // normalisation constants sqrt((2l+1)/(4pi) (l-m)!/(l+m)!) (x sqrt2 for m != 0)
   constexpr float c0 = 0.28209479177387814f;
@@ -53,7 +53,7 @@ __device__ __forceinline__ void sh_color_t(const float4* __restrict__ row, float
   float c[4 * N4];
 #pragma unroll
   for (int q = 0; q < N4; ++q) {
-    const float4 v = ld_global(row, q);
+    const float4 v = SHARED ? row[q] : ld_global(row, q);
     c[4 * q] = v.x;
     c[4 * q + 1] = v.y;
     c[4 * q + 2] = v.z;
@@ -94,15 +94,16 @@ __device__ __forceinline__ void sh_color_t(const float4* __restrict__ row, float
 }
 
 // colour of one Gaussian: real SH up to degree 3 (l-major, m = -l..l, no
-// Condon-Shortley phase) on the unit view direction, from its packed row
-__device__ __forceinline__ void sh_color(const float* __restrict__ p, int degree, float x, float y, float z,
+// Condon-Shortley phase) on the unit view direction, from its packed row (in
+// global memory, or in LDS when SHARED)
+template <bool SHARED = false>
+__device__ __forceinline__ void sh_color(const float4* __restrict__ row, int degree, float x, float y, float z,
                                          float rgb[3]) {
-  const float4* row = reinterpret_cast<const float4*>(p);
   switch (degree) {
-    case 0: sh_color_t<0>(row, x, y, z, rgb); break;
-    case 1: sh_color_t<1>(row, x, y, z, rgb); break;
-    case 2: sh_color_t<2>(row, x, y, z, rgb); break;
-    default: sh_color_t<3>(row, x, y, z, rgb); break;
+    case 0: sh_color_t<0, SHARED>(row, x, y, z, rgb); break;
+    case 1: sh_color_t<1, SHARED>(row, x, y, z, rgb); break;
+    case 2: sh_color_t<2, SHARED>(row, x, y, z, rgb); break;
+    default: sh_color_t<3, SHARED>(row, x, y, z, rgb); break;
   }
 }
 
@@ -205,13 +206,14 @@ __device__ __forceinline__ void pixel_range(float u, float e, int size, int* lo,
 // Projection of one kept pair (Gaussian g of segment R) into output slot
 // `slot`: the compositing record, tile rectangle, depth key and, on debug
 // frames, the per-splat debug arrays.
+// The Gaussian: its geometry record (g0, g1, g2) and SH row (sh_row, in LDS),
+// pair id pid.
 __device__ __forceinline__ void project_pair(
-    const AssetDev* __restrict__ assets, const SegRec& R, int64_t g, uint32_t slot, int tile, int tiles_x,
-    int n_tiles, int keep_debug, float det_clip, float4* __restrict__ splat, float4* __restrict__ rec_a,
-    float4* __restrict__ rec_b, float4* __restrict__ rec_c, float2* __restrict__ rec_d, uint4* __restrict__ rect_dbg,
-    uint2* __restrict__ rect, uint32_t* __restrict__ depth_key, uint32_t* __restrict__ pair_of) {
-  const AssetDev& A = assets[R.asset];
-  const float4 g0 = ld_global(A.geo, 3 * g), g1 = ld_global(A.geo, 3 * g + 1), g2 = ld_global(A.geo, 3 * g + 2);
+    const SegRec& R, float4 g0, float4 g1, float4 g2, const float4* sh_row, int sh_degree, uint32_t pid,
+    uint32_t slot, int tile, int tiles_x, int n_tiles, int keep_debug, float det_clip, float4* __restrict__ splat,
+    float4* __restrict__ rec_a, float4* __restrict__ rec_b, float4* __restrict__ rec_c, float2* __restrict__ rec_d,
+    uint4* __restrict__ rect_dbg, uint2* __restrict__ rect, uint32_t* __restrict__ depth_key,
+    uint32_t* __restrict__ pair_of) {
   const float mu[3] = {g0.x, g0.y, g0.z};
   const float s3[3] = {g1.x, g1.y, g1.z};
   float qw = g2.x, qx = g2.y, qy = g2.z, qz = g2.w;
@@ -296,7 +298,7 @@ __device__ __forceinline__ void project_pair(
   float dx = mu[0] - R.cl[0], dy = mu[1] - R.cl[1], dz = mu[2] - R.cl[2];
   const float dn = rsqrtf(dx * dx + dy * dy + dz * dz);
   float rgb[3];
-  sh_color(A.shp + g * A.sh_stride, A.sh_degree, dx * dn, dy * dn, dz * dn, rgb);
+  sh_color<true>(sh_row, sh_degree, dx * dn, dy * dn, dz * dn, rgb);
   // footprint
   const float k2 = 2.f * logf(255.f * o);
   const int W = (int)(2.f * R.half_w), H = (int)(2.f * R.half_h);
@@ -329,7 +331,7 @@ __device__ __forceinline__ void project_pair(
   sp[0] = make_float4(u, v, f1x, f1y);
   sp[1] = make_float4(f2x, f2y, __log2f(o), rgb[0]);
   sp[2] = make_float4(rgb[1], rgb[2], u_lo, v_lo);
-  sp[3] = make_float4(__uint_as_float((uint32_t)(R.pair_base + g)), __builtin_bit_cast(float, exy), pz, 0.f);
+  sp[3] = make_float4(__uint_as_float(pid), __builtin_bit_cast(float, exy), pz, 0.f);
   rect[slot] = make_uint2(key0, wh);
   depth_key[slot] = fbits(pz);
   if (keep_debug) {
@@ -338,110 +340,140 @@ __device__ __forceinline__ void project_pair(
     rec_c[slot] = make_float4(rgb[2], pz, ex, ey);
     rec_d[slot] = make_float2(u_lo, v_lo);
     rect_dbg[slot] = make_uint4(r0, r1, (uint32_t)R.cam, ntiles);
-    pair_of[slot] = (uint32_t)(R.pair_base + g);
+    pair_of[slot] = pid;
   }
 
 }
 
-// One thread per output slot, i.e. per kept pair in (camera, instance,
-// Gaussian) order, so that every lane of a wave projects a splat whatever
-// the keep rate.  The slots of a chunk are [chunk_off[c], chunk_off[c + 1])
-// (exclusive scan of the chunks' keep counts); a slot's chunk is the last c
-// with chunk_off[c] <= slot, found by binary search (the wave's first and
-// last slots bound each lane's search), and its Gaussian is the set bit of
-// the chunk's 256-bit keep mask with that rank.  A wave's slots usually lie
-// in one segment; it loops over the segments they span so that the segment
-// record is read with wave-uniform loads.
+// Projection over the cull/MLP work items: a work-group takes one 256-
+// Gaussian chunk of an asset and a run of its segments (camera x instance),
+// stages the chunk's geometry records and SH rows in LDS once, and then
+// projects the kept pairs of all those segments with one thread per pair, so
+// that a Gaussian kept by several instances is read from memory once and
+// every lane has a pair whatever the keep rate.  A pair's output slot is its
+// segment-chunk's offset (exclusive scan of the chunks' keep counts) plus its
+// rank among the chunk's kept pairs, as in the ordered compaction.
+constexpr int kPjSegs = 32;       // segments staged at a time
+constexpr int kPjRow = 13;        // float4 per staged SH row (48 floats + padding)
 __global__ __launch_bounds__(256) void k_project(
-    const AssetDev* __restrict__ assets, const SegRec* __restrict__ segs, int32_t n_segs,
-    const int64_t* __restrict__ seg_chunk_base, int64_t n_chunks, const uint32_t* __restrict__ mask,
-    const uint32_t* __restrict__ chunk_off, const uint32_t* __restrict__ n_splats, int64_t cap, int tile,
-    int tiles_x, int n_tiles, int keep_debug, float det_clip, float4* __restrict__ splat,
-    float4* __restrict__ rec_a, float4* __restrict__ rec_b, float4* __restrict__ rec_c, float2* __restrict__ rec_d,
-    uint4* __restrict__ rect_dbg, uint2* __restrict__ rect, uint32_t* __restrict__ depth_key,
-    uint32_t* __restrict__ pair_of, uint32_t* __restrict__ overflow) {
-  const uint32_t n_all = *n_splats;
-  if (blockIdx.x == 0 && threadIdx.x == 0 && (int64_t)n_all > cap) atomicOr(overflow, 1u);
-  const int64_t ns = min((int64_t)n_all, cap);
-  const int lane = threadIdx.x & 63;
-  const int64_t w0 = __builtin_amdgcn_readfirstlane((int)blockIdx.x) * (int64_t)256 +
-                     __builtin_amdgcn_readfirstlane((int)(threadIdx.x & ~63u));
-  if (w0 >= ns) return;  // the whole wave
-  const int64_t slot = w0 + lane;
-  const bool live = slot < ns;
-  const int64_t w1 = min(w0 + 63, ns - 1);
-  // last index in [lo, hi] whose key is <= x, over a non-decreasing array
-  auto last_le = [](auto key, int64_t x, int64_t lo, int64_t hi) {
-    while (lo < hi) {
-      const int64_t mid = (lo + hi + 1) >> 1;
-      if ((int64_t)key(mid) <= x) lo = mid; else hi = mid - 1;
+    const AssetDev* __restrict__ assets, const WorkItem* __restrict__ items, const int32_t* __restrict__ seglist,
+    const SegRec* __restrict__ segs, const uint32_t* __restrict__ mask, const uint32_t* __restrict__ chunk_off,
+    const uint32_t* __restrict__ n_splats, int64_t cap, int tile, int tiles_x, int n_tiles, int keep_debug,
+    float det_clip, float4* __restrict__ splat, float4* __restrict__ rec_a, float4* __restrict__ rec_b,
+    float4* __restrict__ rec_c, float2* __restrict__ rec_d, uint4* __restrict__ rect_dbg, uint2* __restrict__ rect,
+    uint32_t* __restrict__ depth_key, uint32_t* __restrict__ pair_of, uint32_t* __restrict__ overflow) {
+  __shared__ float4 s_geo[3 * kChunk];
+  __shared__ float4 s_sh[kChunk * kPjRow];
+  __shared__ SegRec s_seg[kPjSegs];
+  __shared__ uint32_t s_mask[kPjSegs][kChunk / 32];
+  __shared__ uint32_t s_base[kPjSegs + 1];  // exclusive scan of the segments' kept counts in this chunk
+  __shared__ uint32_t s_slot[kPjSegs];      // output slot of each segment's first kept pair
+  const int t = threadIdx.x;
+  if (blockIdx.x == 0 && t == 0 && (int64_t)*n_splats > cap) atomicOr(overflow, 1u);
+  const WorkItem it = items[blockIdx.x];
+  const AssetDev& A = assets[it.asset];
+  const int64_t n = A.n;
+  const int64_t g0 = (int64_t)it.chunk * kChunk;
+  const int64_t words = (n + 31) >> 5;
+  constexpr int RW = sizeof(SegRec) / 4;
+  static_assert(sizeof(SegRec) % 4 == 0, "segment records are copied word by word");
+  bool staged = false;
+  for (int sb = it.seg_begin; sb < it.seg_end; sb += kPjSegs) {
+    const int ns = min(kPjSegs, it.seg_end - sb);
+    __syncthreads();  // the previous batch's reads of the segment records and masks are done
+    for (int i = t; i < ns * RW; i += 256)
+      reinterpret_cast<uint32_t*>(s_seg)[i] = reinterpret_cast<const uint32_t*>(segs + seglist[sb + i / RW])[i % RW];
+    for (int i = t; i < ns * (kChunk / 32); i += 256) {
+      const int j = i / (kChunk / 32), w = i % (kChunk / 32);
+      const int64_t wi = (int64_t)it.chunk * (kChunk / 32) + w;
+      s_mask[j][w] = wi < words ? mask[segs[seglist[sb + j]].word_base + wi] : 0u;
     }
-    return lo;
-  };
-  auto coff = [&](int64_t c) { return chunk_off[c]; };
-  auto sbase = [&](int64_t q) { return seg_chunk_base[q]; };
-  // wave-uniform bounds (read-first-lane keeps them in scalar registers)
-  auto uni = [](int64_t v) {
-    return (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(v >> 32)) << 32) |
-                     (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v));
-  };
-  const int64_t c_lo = uni(last_le(coff, w0, 0, n_chunks - 1));
-  const int64_t c_hi = uni(last_le(coff, w1, c_lo, n_chunks - 1));
-  const int64_t c = live ? last_le(coff, slot, c_lo, c_hi) : c_lo;
-  const int32_t s_lo = (int32_t)uni(last_le(sbase, c_lo, 0, n_segs - 1));
-  const int32_t s_hi = (int32_t)uni(last_le(sbase, c_hi, s_lo, n_segs - 1));
-  const int32_t sg = s_lo == s_hi ? s_lo : (int32_t)last_le(sbase, c, s_lo, s_hi);
-  for (int32_t si = s_lo; si <= s_hi; ++si) {
-    if (!live || sg != si) continue;
-    const SegRec& R = segs[__builtin_amdgcn_readfirstlane(si)];
-    const int64_t cl = c - seg_chunk_base[si];  // chunk within the segment
-    const int64_t words = ((int64_t)R.n + 31) >> 5;
-    // rank of the slot among the chunk's kept pairs -> mask word and bit
-    const uint32_t r = (uint32_t)(slot - (int64_t)chunk_off[c]);
-    uint32_t cum = 0, below = 0, x = 0;
-    int wsel = -1;
+    __syncthreads();
+    if (t < 64) {  // one wave: kept counts, their scan, the slot bases
+      uint32_t c = 0;
+      if (t < ns)
+        for (int w = 0; w < kChunk / 32; ++w) c += (uint32_t)__popc(s_mask[t][w]);
+      uint32_t x = c;
 #pragma unroll
-    for (int w = 0; w < kChunk / 32; ++w) {
-      const int64_t wi = cl * (kChunk / 32) + w;
-      const uint32_t m = wi < words ? mask[R.word_base + wi] : 0u;
-      const uint32_t pc = (uint32_t)__popc(m);
-      if (wsel < 0 && r < cum + pc) {
-        wsel = w;
-        below = cum;
-        x = m;
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o);
+        if (t >= o) x += y;
       }
-      cum += pc;
-    }
-    uint32_t rr = r - below;
-    int pos = 0;
-#pragma unroll
-    for (int half = 16; half > 0; half >>= 1) {
-      const uint32_t low = (uint32_t)__popc(x & ((1u << half) - 1u));
-      if (rr >= low) {
-        rr -= low;
-        x >>= half;
-        pos += half;
+      if (t == 0) s_base[0] = 0;
+      if (t < ns) {
+        s_base[t + 1] = x;
+        s_slot[t] = chunk_off[s_seg[t].chunk_base + it.chunk];
       }
     }
-    const int64_t g = cl * kChunk + wsel * 32 + pos;
-    project_pair(assets, R, g, (uint32_t)slot, tile, tiles_x, n_tiles, keep_debug, det_clip, splat, rec_a, rec_b,
-                 rec_c, rec_d, rect_dbg, rect, depth_key, pair_of);
+    __syncthreads();
+    const uint32_t K = s_base[ns];
+    if (K == 0) continue;
+    if (!staged) {
+      const int q4 = A.sh_stride / 4;
+      for (int i = t; i < 3 * kChunk; i += 256)
+        s_geo[i] = g0 + i / 3 < n ? ld_global(A.geo, 3 * g0 + i) : make_float4(0.f, 0.f, 0.f, 0.f);
+      const float4* shp = reinterpret_cast<const float4*>(A.shp);
+      for (int i = t; i < kChunk * q4; i += 256) {
+        const int gi = i / q4, q = i % q4;
+        s_sh[gi * kPjRow + q] = g0 + gi < n ? ld_global(shp, (g0 + gi) * q4 + q) : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+      staged = true;
+      __syncthreads();
+    }
+    for (uint32_t p = (uint32_t)t; p < K; p += 256) {
+      // segment: the last j with s_base[j] <= p
+      int j = 0;
+#pragma unroll
+      for (int step = kPjSegs / 2; step > 0; step >>= 1)
+        if (j + step < ns && s_base[j + step] <= p) j += step;
+      // rank among the segment's kept pairs of this chunk -> mask word and bit
+      const uint32_t r = p - s_base[j];
+      uint32_t cum = 0, below = 0, x = 0;
+      int wsel = 0;
+      bool found = false;
+#pragma unroll
+      for (int w = 0; w < kChunk / 32; ++w) {
+        const uint32_t m = s_mask[j][w];
+        const uint32_t pc = (uint32_t)__popc(m);
+        if (!found && r < cum + pc) {
+          found = true;
+          wsel = w;
+          below = cum;
+          x = m;
+        }
+        cum += pc;
+      }
+      uint32_t rr = r - below;
+      int pos = 0;
+#pragma unroll
+      for (int half = 16; half > 0; half >>= 1) {
+        const uint32_t low = (uint32_t)__popc(x & ((1u << half) - 1u));
+        if (rr >= low) {
+          rr -= low;
+          x >>= half;
+          pos += half;
+        }
+      }
+      const int gl = wsel * 32 + pos;
+      const uint32_t slot = s_slot[j] + r;
+      if ((int64_t)slot >= cap) continue;  // flagged above
+      const SegRec& R = s_seg[j];
+      project_pair(R, s_geo[3 * gl], s_geo[3 * gl + 1], s_geo[3 * gl + 2], s_sh + gl * kPjRow, A.sh_degree,
+                   (uint32_t)(R.pair_base + g0 + gl), slot, tile, tiles_x, n_tiles, keep_debug, det_clip, splat,
+                   rec_a, rec_b, rec_c, rec_d, rect_dbg, rect, depth_key, pair_of);
+    }
   }
 }
 
-hipError_t launch_project(const AssetDev* assets, const SegRec* segs, int32_t n_segs, const int64_t* seg_chunk_base,
-                          int64_t n_chunks, const uint32_t* mask, const uint32_t* chunk_off, const uint32_t* n_splats,
-                          int64_t cap_splats, int64_t grid_slots, int tile, int tiles_x, int n_tiles, int keep_debug,
-                          float det_clip, float4* splat, float4* rec_a, float4* rec_b, float4* rec_c, float2* rec_d,
-                          uint4* rect_dbg, uint2* rect, uint32_t* depth_key, uint32_t* pair_of, uint32_t* overflow,
-                          hipStream_t st) {
-  if (n_chunks == 0 || n_segs == 0) return hipSuccess;
-  // slots beyond the capacity are never written (the kernel raises the overflow flag)
-  const int64_t slots = std::max<int64_t>(std::min(grid_slots, cap_splats), 1);
-  hipLaunchKernelGGL(k_project, dim3((unsigned)((slots + 255) / 256)), dim3(256), 0, st, assets, segs, n_segs,
-                     seg_chunk_base, n_chunks, mask, chunk_off, n_splats, cap_splats, tile, tiles_x, n_tiles,
-                     keep_debug, det_clip, splat, rec_a, rec_b, rec_c, rec_d, rect_dbg, rect, depth_key, pair_of,
-                     overflow);
+hipError_t launch_project(const AssetDev* assets, const WorkItem* items, int64_t n_items, const int32_t* seglist,
+                          const SegRec* segs, const uint32_t* mask, const uint32_t* chunk_off, const uint32_t* n_splats,
+                          int64_t cap_splats, int tile, int tiles_x, int n_tiles, int keep_debug, float det_clip,
+                          float4* splat, float4* rec_a, float4* rec_b, float4* rec_c, float2* rec_d, uint4* rect_dbg,
+                          uint2* rect, uint32_t* depth_key, uint32_t* pair_of, uint32_t* overflow, hipStream_t st) {
+  if (n_items == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_project, dim3((unsigned)n_items), dim3(256), 0, st, assets, items, seglist, segs, mask,
+                     chunk_off, n_splats, cap_splats, tile, tiles_x, n_tiles, keep_debug, det_clip, splat, rec_a,
+                     rec_b, rec_c, rec_d, rect_dbg, rect, depth_key, pair_of, overflow);
   return hipGetLastError();
 }
 
