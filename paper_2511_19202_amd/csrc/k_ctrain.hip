@@ -5,16 +5,16 @@
 //
 // One 256-thread work-group processes chunks of 128 samples; wave w owns
 // samples 32w .. 32w + 31 of a chunk and every GEMM of its samples runs on
-// v_mfma_f32_32x32x2_f32 with one 32 x 32 output tile (outputs x samples in
+// one 32 x 32 MFMA output tile (FP32 or BF16 operands; outputs x samples in
 // the forward pass and for the input deltas, outputs x inputs for the weight
 // gradients, which stay in the accumulators across the chunks).  The bias
 // gradients of the layers with fewer than 32 inputs ride in the spare
 // columns of the weight-gradient tiles (a column of ones); the others are
 // lane sums.  At the end the four waves' gradients are summed in LDS into
 // one partial per work-group; the reduce kernel adds the partials in a
-// fixed order, so runs are deterministic.  With BF16 rounding on, every
-// GEMM operand is rounded to BF16 when it is staged (the FP32 MFMA then
-// forms the exact products of a BF16 MFMA with FP32 accumulation).
+// fixed order, so runs are deterministic.  With BF16 on, every GEMM operand
+// is rounded to BF16 when it is staged and the GEMMs run on
+// v_mfma_f32_32x32x16_bf16 (FP32 accumulation).
 #include <algorithm>
 
 #include "internal.h"
@@ -68,15 +68,33 @@ __device__ __forceinline__ uint64_t smix(uint64_t seed, uint64_t i) {
   return z ^ (z >> 31);
 }
 
-// acc[r][c] += sum_k A(r, k) B(k, c) over K (even), r = lane % 32 for A,
-// c = lane % 32 for B, k = 2 s + lane / 32
-template <class FA, class FB>
+typedef __bf16 bf16x8c __attribute__((ext_vector_type(8)));
+
+// acc[r][c] += sum_k A(r, k) B(k, c) over K, r = lane % 32 for A, c = lane %
+// 32 for B.  FP32: v_mfma_f32_32x32x2f32, k = 2 s + lane / 32 (K even).
+// BF16: v_mfma_f32_32x32x16_bf16 on operands the caller has rounded to BF16
+// (the conversion is exact), lane group g holding k = 16 s + 8 g .. + 7, K
+// padded to a multiple of 16 with zeros.
+template <bool BF16, class FA, class FB>
 __device__ __forceinline__ f32x16t mma(f32x16t acc, int K, FA a_at, FB b_at) {
   const int l = threadIdx.x & 63, r = l & 31, g = l >> 5;
+  if constexpr (BF16) {
+    for (int k0 = 0; k0 < K; k0 += 16) {
+      bf16x8c av, bv;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int k = k0 + 8 * g + j;
+        av[j] = (__bf16)(k < K ? a_at(r, k) : 0.f);
+        bv[j] = (__bf16)(k < K ? b_at(k, r) : 0.f);
+      }
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+    }
+  } else {
 #pragma unroll 4
-  for (int s = 0; s < K / 2; ++s) {
-    const int k = 2 * s + g;
-    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a_at(r, k), b_at(k, r), acc, 0, 0, 0);
+    for (int s = 0; s < K / 2; ++s) {
+      const int k = 2 * s + g;
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a_at(r, k), b_at(k, r), acc, 0, 0, 0);
+    }
   }
   return acc;
 }
@@ -187,19 +205,19 @@ __global__ __launch_bounds__(256) void k_cmlp_train(
     __syncthreads();
     // ---- forward, per wave on its 32 samples: outputs (rows) x samples (columns)
     {
-      f32x16t a = mma(zero, 8, [&](int r, int k) { return S.E1[r * kLdE + k]; },
+      f32x16t a = mma<BF16R>(zero, 8, [&](int r, int k) { return S.E1[r * kLdE + k]; },
                       [&](int k, int c) { return S.XE[(p0 + c) * kLdE + k]; });
       for (int i = 0; i < 16; ++i) G1[(p0 + col) * kLd + arow(i)] = rnd(fmaxf(a[i] + S.e1[arow(i)], 0.f));
     }
     __syncthreads();
     {
-      f32x16t a = mma(zero, kH, [&](int r, int k) { return S.E2[r * kLd + k]; },
+      f32x16t a = mma<BF16R>(zero, kH, [&](int r, int k) { return S.E2[r * kLd + k]; },
                       [&](int k, int c) { return G1[(p0 + c) * kLd + k]; });
       for (int i = 0; i < 16; ++i) G2[(p0 + col) * kLd + arow(i)] = rnd(fmaxf(a[i] + S.e2[arow(i)], 0.f));
     }
     __syncthreads();
     {
-      f32x16t a = mma(zero, kH, [&](int r, int k) { return r < 6 ? S.E3[r * kLd + k] : 0.f; },
+      f32x16t a = mma<BF16R>(zero, kH, [&](int r, int k) { return r < 6 ? S.E3[r * kLd + k] : 0.f; },
                       [&](int k, int c) { return G2[(p0 + c) * kLd + k]; });
       for (int i = 0; i < 16; ++i) {
         const int r = arow(i);
@@ -208,13 +226,13 @@ __global__ __launch_bounds__(256) void k_cmlp_train(
     }
     __syncthreads();
     {
-      f32x16t a = mma(zero, 16, [&](int r, int k) { return S.W1[r * kLdX + k]; },
+      f32x16t a = mma<BF16R>(zero, 16, [&](int r, int k) { return S.W1[r * kLdX + k]; },
                       [&](int k, int c) { return S.X[(p0 + c) * kLdX + k]; });
       for (int i = 0; i < 16; ++i) H1[(p0 + col) * kLd + arow(i)] = rnd(fmaxf(a[i] + S.b1[arow(i)], 0.f));
     }
     __syncthreads();
     {
-      f32x16t a = mma(zero, kH, [&](int r, int k) { return S.W2[r * kLd + k]; },
+      f32x16t a = mma<BF16R>(zero, kH, [&](int r, int k) { return S.W2[r * kLd + k]; },
                       [&](int k, int c) { return H1[(p0 + c) * kLd + k]; });
       // FP32: the output layer is a VALU dot
       for (int i = 0; i < 16; ++i) H2[(p0 + col) * kLd + arow(i)] = fmaxf(a[i] + S.b2[arow(i)], 0.f);
@@ -262,11 +280,11 @@ __global__ __launch_bounds__(256) void k_cmlp_train(
         for (int p = p0; p < p0 + 32; ++p) r_dbo += S.dz[p];
     }
     // dW2 += D2' H1 (outputs x inputs, over this wave's samples)
-    gW2 = mma(gW2, 32, [&](int r, int k) { return DA[(p0 + k) * kLd + r]; },
+    gW2 = mma<BF16R>(gW2, 32, [&](int r, int k) { return DA[(p0 + k) * kLd + r]; },
               [&](int k, int c) { return H1[(p0 + k) * kLd + c]; });
     // D1 = (W2' D2) * 1[H1 > 0]
     {
-      f32x16t a = mma(zero, kH, [&](int r, int k) { return S.W2[k * kLd + r]; },
+      f32x16t a = mma<BF16R>(zero, kH, [&](int r, int k) { return S.W2[k * kLd + r]; },
                       [&](int k, int c) { return DA[(p0 + c) * kLd + k]; });
       for (int i = 0; i < 16; ++i) {
         const int r = arow(i);
@@ -275,10 +293,10 @@ __global__ __launch_bounds__(256) void k_cmlp_train(
     }
     __syncthreads();
     // dW1 += D1' [X | 1] (the column of ones gives db1); embedding deltas = (W1' D1) rows 10..15
-    gW1 = mma(gW1, 32, [&](int r, int k) { return DB[(p0 + k) * kLd + r]; },
+    gW1 = mma<BF16R>(gW1, 32, [&](int r, int k) { return DB[(p0 + k) * kLd + r]; },
               [&](int k, int c) { return c < 16 ? S.X[(p0 + k) * kLdX + c] : (c == 16 ? 1.f : 0.f); });
     {
-      f32x16t a = mma(zero, kH, [&](int r, int k) { return r < 16 ? S.W1[k * kLdX + r] : 0.f; },
+      f32x16t a = mma<BF16R>(zero, kH, [&](int r, int k) { return r < 16 ? S.W1[k * kLdX + r] : 0.f; },
                       [&](int k, int c) { return DB[(p0 + c) * kLd + k]; });
       for (int i = 0; i < 16; ++i) {
         const int r = arow(i);
@@ -287,7 +305,7 @@ __global__ __launch_bounds__(256) void k_cmlp_train(
     }
     __syncthreads();
     // dE3 += DE' G2 ; de3 ; DG2 = (E3' DE) * 1[G2 > 0]
-    gE3 = mma(gE3, 32, [&](int r, int k) { return r < 6 ? S.DE[(p0 + k) * kLdE + r] : 0.f; },
+    gE3 = mma<BF16R>(gE3, 32, [&](int r, int k) { return r < 6 ? S.DE[(p0 + k) * kLdE + r] : 0.f; },
               [&](int k, int c) { return G2[(p0 + k) * kLd + c]; });
     if (lane >= 32 && lane < 38) {
       float s = 0.f;
@@ -295,7 +313,7 @@ __global__ __launch_bounds__(256) void k_cmlp_train(
       r_de3 += s;
     }
     {
-      f32x16t a = mma(zero, 8, [&](int r, int k) { return k < 6 ? S.E3[k * kLd + r] : 0.f; },
+      f32x16t a = mma<BF16R>(zero, 8, [&](int r, int k) { return k < 6 ? S.E3[k * kLd + r] : 0.f; },
                       [&](int k, int c) { return k < 6 ? S.DE[(p0 + c) * kLdE + k] : 0.f; });
       for (int i = 0; i < 16; ++i) {
         const int r = arow(i);
@@ -304,7 +322,7 @@ __global__ __launch_bounds__(256) void k_cmlp_train(
     }
     __syncthreads();
     // dE2 += DG2' G1 ; de2 ; DG1 = (E2' DG2) * 1[G1 > 0]
-    gE2 = mma(gE2, 32, [&](int r, int k) { return DA[(p0 + k) * kLd + r]; },
+    gE2 = mma<BF16R>(gE2, 32, [&](int r, int k) { return DA[(p0 + k) * kLd + r]; },
               [&](int k, int c) { return G1[(p0 + k) * kLd + c]; });
     if (lane < 32) {
       float s = 0.f;
@@ -312,7 +330,7 @@ __global__ __launch_bounds__(256) void k_cmlp_train(
       r_de2 += s;
     }
     {
-      f32x16t a = mma(zero, kH, [&](int r, int k) { return S.E2[k * kLd + r]; },
+      f32x16t a = mma<BF16R>(zero, kH, [&](int r, int k) { return S.E2[k * kLd + r]; },
                       [&](int k, int c) { return DA[(p0 + c) * kLd + k]; });
       for (int i = 0; i < 16; ++i) {
         const int r = arow(i);
@@ -321,7 +339,7 @@ __global__ __launch_bounds__(256) void k_cmlp_train(
     }
     __syncthreads();
     // dE1 += DG1' [XE | 1] (the column of ones gives de1)
-    gE1 = mma(gE1, 32, [&](int r, int k) { return DB[(p0 + k) * kLd + r]; },
+    gE1 = mma<BF16R>(gE1, 32, [&](int r, int k) { return DB[(p0 + k) * kLd + r]; },
               [&](int k, int c) { return c < 8 ? S.XE[(p0 + k) * kLdE + c] : (c == 8 ? 1.f : 0.f); });
     __syncthreads();
   }
