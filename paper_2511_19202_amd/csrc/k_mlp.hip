@@ -569,6 +569,82 @@ __device__ __forceinline__ void relu_split(const f32x16 (&acc)[NB][W / 32], cons
     }
 }
 
+// Split-FP32 operands from one 32-unit accumulator tile tt (the K-steps 2 tt
+// and 2 tt + 1 of the next layer), as relu_split.
+template <int W, int NB, bool ADD>
+__device__ __forceinline__ void relu_split_tile(const f32x16 (&acc)[NB][W / 32], int tt, const float* __restrict__ add,
+                                                bf16x8 (&hi)[NB][W / 16], bf16x8 (&lo)[NB][W / 16]) {
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int s = 2 * tt; s < 2 * tt + 2; ++s) {
+      i32x4 wh, wl;
+#pragma unroll
+      for (int p2 = 0; p2 < 4; ++p2) {
+        const int q = s * 8 + 2 * p2;
+        const float x0 = ADD ? acc[b][tt][q % 16] + add[q] : acc[b][tt][q % 16];
+        const float x1 = ADD ? acc[b][tt][(q + 1) % 16] + add[q + 1] : acc[b][tt][(q + 1) % 16];
+        const float v0 = relu(x0), v1 = relu(x1);
+        const bf16x2 h = __builtin_convertvector((f32x2){v0, v1}, bf16x2);
+        const uint32_t hbits = __builtin_bit_cast(uint32_t, h);
+        const float h0 = __uint_as_float(hbits << 16), h1 = __uint_as_float(hbits & 0xffff0000u);
+        const bf16x2 l = __builtin_convertvector((f32x2){v0 - h0, v1 - h1}, bf16x2);
+        wh[p2] = (int)hbits;
+        wl[p2] = __builtin_bit_cast(int, l);
+      }
+      hi[b][s] = __builtin_bit_cast(bf16x8, wh);
+      lo[b][s] = __builtin_bit_cast(bf16x8, wl);
+    }
+}
+
+// One split-FP32 layer, pipelined with the previous layer's epilogue: for each
+// 32-unit tile tt of the previous activations (prev, + add for layer 1), its
+// ReLU and split, then the K-steps 2 tt, 2 tt + 1 of every output tile, so
+// that a tile's epilogue can issue while the previous tile's MFMAs run.  Each
+// accumulator sees the same sequence of products as in mma_layer_split.
+template <int W, int NB, bool ADD>
+__device__ __forceinline__ void split_layer_pipelined(const f32x16 (&prev)[NB][W / 32], const float* __restrict__ add,
+                                                      const uint8_t* __restrict__ Wh, const uint8_t* __restrict__ Wl,
+                                                      const float* __restrict__ binit, f32x16 (&acc)[NB][W / 32],
+                                                      int lane) {
+  constexpr int NT = W / 32, KSH = W / 16;
+  bf16x8 xh[NB][KSH], xl[NB][KSH];
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[b][t][r] = binit[16 * t + r];
+#pragma unroll
+  for (int tt = 0; tt < NT; ++tt) {
+    relu_split_tile<W, NB, ADD>(prev, tt, add, xh, xl);
+#pragma unroll
+    for (int s = 2 * tt; s < 2 * tt + 2; ++s) {
+      bf16x8 ah[NT], al[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        ah[t] = reinterpret_cast<const bf16x8*>(Wh)[(t * KSH + s) * 64 + lane];
+        al[t] = reinterpret_cast<const bf16x8*>(Wl)[(t * KSH + s) * 64 + lane];
+      }
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+          acc[b][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[t], xh[b][s], acc[b][t], 0, 0, 0);
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+          acc[b][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[t], xl[b][s], acc[b][t], 0, 0, 0);
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+          acc[b][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[t], xh[b][s], acc[b][t], 0, 0, 0);
+    }
+  }
+}
+
 // One hidden layer of the split-FP32 form: acc = bias + sum over the depth of
 // W_lo x_hi + W_hi x_lo + W_hi x_hi (three BF16 MFMAs per 32x32x16 block,
 // FP32 accumulation; the independent tiles of a round are issued between the
@@ -768,11 +844,9 @@ __global__ __launch_bounds__(64 * WAVES) void k_cull_mlp(
       const float* c1 = &s_c1[wave][grp * KQ];
       f32x16 acc[NB][NT];
       if constexpr (SPLIT) {
-        bf16x8 oph[NB][W / 16], opl[NB][W / 16];
-        relu_split<W, NB, true>(U, c1, oph, opl);
-        mma_layer_split<W, NB>(W2p, lds + I::W2L, b2p + grp * KQ, oph, opl, acc, lane);
-        relu_split<W, NB, false>(acc, nullptr, oph, opl);
-        mma_layer_split<W, NB>(W3p, lds + I::W3L, b3p + grp * KQ, oph, opl, acc, lane);
+        f32x16 acc2[NB][NT];
+        split_layer_pipelined<W, NB, true>(U, c1, W2p, lds + I::W2L, b2p + grp * KQ, acc2, lane);
+        split_layer_pipelined<W, NB, false>(acc2, nullptr, W3p, lds + I::W3L, b3p + grp * KQ, acc, lane);
       } else {
         constexpr int KSH = W / Prec<P>::K;
         typename Mfma<P>::Op op[NB][KSH];
