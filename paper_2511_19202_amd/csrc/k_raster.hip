@@ -12,7 +12,8 @@
 //    depend on the tile size.
 //  * k_blend stages batches of splats (one per thread) in LDS, fetching the
 //    next batch while compositing the current one, and stops a tile as soon
-//    as every pixel of it has stopped.
+//    as every pixel of it has stopped; an 8x8 tile passes over the splats
+//    whose footprint box holds none of its live pixels.
 #include <algorithm>
 #include <utility>
 
@@ -801,7 +802,7 @@ __device__ __forceinline__ void blend_item(
     qa = r[0];
     qb = r[1];
     qc = r[2];
-    if (RECORD || T != 8) qd = *reinterpret_cast<const float2*>(r + 3);
+    qd = *reinterpret_cast<const float2*>(r + 3);
   }
   uint32_t b0k = start;
   // composite staged splat k into pixel block j.  Branch-free: a fragment that
@@ -851,6 +852,7 @@ __device__ __forceinline__ void blend_item(
     if (__syncthreads_count(any) == 0) break;  // also: the previous batch is consumed
     const int cnt = (int)min((uint32_t)BATCH, end - b0);
     b0k = b0;
+    uint64_t pm = 0;  // 8x8 tiles: bit p = pixel p of the tile lies in this thread's footprint box
     if (t < cnt) {
       // the centre relative to the first pixel centre of the tile's 32-pixel
       // block, from its hi + lo parts (qc.z, qc.w): for a splat over the
@@ -862,7 +864,22 @@ __device__ __forceinline__ void blend_item(
       s_rec[t][0] = make_float4(ur, vr, qa.z, qa.w);
       s_rec[t][1] = qb;
       s_rec[t][2] = qc;
-      if (T != 8) {
+      if (T == 8) {
+        // pixels of the tile whose centre lies in the footprint box (the
+        // alpha >= 1/255 bound of the tile rectangle, with the same widening);
+        // qd.y = the half extents, rounded up to FP16.  Pixel p = 8 row + column.
+        const __half2 exy = __builtin_bit_cast(__half2, qd.y);
+        const float ex = __low2float(exy), ey = __high2float(exy);
+        const float wx = 1e-4f * ex + 1e-3f, wy = 1e-4f * ey + 1e-3f;
+        const float ox = (float)(tx * T - bx), oy = (float)(ty * T - by);
+        const float c0 = fmaxf(0.f, ceilf(ur - ox - ex - wx)), c1 = fminf(7.f, floorf(ur - ox + ex + wx));
+        const float r0 = fmaxf(0.f, ceilf(vr - oy - ey - wy)), r1 = fminf(7.f, floorf(vr - oy + ey + wy));
+        if (c0 <= c1 && r0 <= r1) {
+          const uint32_t cols = (2u << (int)c1) - (1u << (int)c0);
+          const uint64_t rows = (~0ull >> (56 - 8 * (int)r1)) & (~0ull << (8 * (int)r0));
+          pm = ((uint64_t)cols * 0x0101010101010101ull) & rows;
+        }
+      } else {
         // 8x8 blocks of the tile touched by the footprint box (same widening
         // as the tile rectangle); qd.y = the half extents, rounded up to FP16
         const __half2 exy = __builtin_bit_cast(__half2, qd.y);
@@ -888,18 +905,28 @@ __device__ __forceinline__ void blend_item(
       qa = r[0];
       qb = r[1];
       qc = r[2];
-      if (RECORD || T != 8) qd = *reinterpret_cast<const float2*>(r + 3);
+      qd = *reinterpret_cast<const float2*>(r + 3);
     }
 #pragma unroll
     for (int j = 0; j < BPW; ++j) {
       if (__ballot(live(j)) == 0) continue;
       if (T == 8) {
-        // every listed splat touches the tile
-        for (int k = 0; k < cnt; k += 8) {
-#pragma unroll
-          for (int u = 0; u < 8; ++u)
-            if (k + u < cnt) step(j, k + u);
-          if (__ballot(live(j)) == 0) break;
+        // the batch's splats in list order, skipping those whose footprint
+        // box holds no live pixel of the tile: their alpha is below 1/255 at
+        // every live pixel, so compositing them would change nothing (lane k
+        // staged splat k; the set is refreshed every 8 splats)
+        uint64_t lm = __ballot(live(j));
+        uint64_t set = __ballot((pm & lm) != 0);
+        int n = 0;
+        while (set) {
+          const int k = __builtin_ctzll(set);
+          set &= set - 1;
+          step(j, k);
+          if (++n == 8) {
+            n = 0;
+            lm = __ballot(live(j));
+            set &= __ballot((pm & lm) != 0);
+          }
         }
       } else {
         // splats whose box touches this wave's block, as 64-bit ballot sets

@@ -219,7 +219,9 @@ def test_frame_stages_against_oracle(nvgs, name, tile):
 
 def test_image_independent_of_tile_size_and_deterministic(nvgs):
     """Sequential compositing (no list split): the image is bit-identical for
-    tile edges 8, 16 and 32 and across repeated frames."""
+    tile edges 8, 16 and 32 and across repeated frames.  (8x8 tiles skip the
+    splats whose footprint box holds no live pixel; the larger tiles only skip
+    8x8 blocks their box misses, so this also checks that the skip is exact.)"""
     sc = SCENES["composed_small"]()
     ctx = make_ctx(nvgs, sc)
     imgs = [ctx.render(sc.cameras, tile=t, split=-1).cpu().numpy() for t in (8, 16, 32)]
