@@ -161,8 +161,12 @@ typedef struct nvgs_render_opts {
   int32_t split_len; /* tile lists longer than this are composited in chunks of at most
                         this many entries by separate work-groups, which equals the
                         sequential composite up to rounding (the association of the
-                        transmittance products and colour sums); 0: default 1024;
-                        < 0: never split (bit-identical across tile sizes); else >= 64 */
+                        transmittance products and colour sums); 0: default, a length
+                        set by the frame on the device: max(256, ceil(entries / D)), D =
+                        2 x compute units x 2048 / threads per compositing work-group
+                        (64 for 8x8 tiles, else 256), i.e. about two chunks per
+                        work-group the launch keeps resident; < 0: never split
+                        (bit-identical across tile sizes); else >= 64, fixed */
   float det_clip;    /* radius clipping (Sec. 4.3 ablation): a splat whose 2D covariance
                         (after the 0.3 px^2 dilation) has a determinant below det_clip
                         (px^4; the 1-sigma ellipse area is pi sqrt(det)) is not binned;
@@ -191,6 +195,10 @@ typedef struct nvgs_frame_stats {
   int64_t workspace_bytes;
   float ms_total;     /* frame wall time on the stream (first to last event) */
   float ms_stage[NVGS_NUM_STAGES]; /* per-stage kernel time (HIP events) */
+  int64_t blend_items; /* compositing work items: one per tile list, plus one per extra chunk
+                          of a split list */
+  int32_t chunk_len;   /* entries per chunk of a split list in this frame (0: not split) */
+  int32_t reserved;
 } nvgs_frame_stats;
 
 /* Borrowed views of the last frame's device buffers (valid until the next

@@ -73,7 +73,8 @@ class FrameStats(C.Structure):
     _fields_ = [("pairs", C.c_int64), ("in_frustum", C.c_int64), ("queried", C.c_int64), ("kept", C.c_int64),
                 ("duplicates", C.c_int64), ("blend_tests", C.c_int64), ("workspace_bytes", C.c_int64),
                 ("ms_total", C.c_float),
-                ("ms_stage", C.c_float * NUM_STAGES)]
+                ("ms_stage", C.c_float * NUM_STAGES), ("blend_items", C.c_int64), ("chunk_len", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class DebugView(C.Structure):
@@ -373,7 +374,8 @@ class Context:
             return rgb, {"pairs": fs.pairs, "in_frustum": fs.in_frustum, "queried": fs.queried, "kept": fs.kept,
                          "duplicates": fs.duplicates, "blend_tests": fs.blend_tests,
                          "workspace_bytes": fs.workspace_bytes, "ms": fs.ms_total,
-                         "ms_stage": dict(zip(STAGES, list(fs.ms_stage)))}
+                         "ms_stage": dict(zip(STAGES, list(fs.ms_stage))), "blend_items": fs.blend_items,
+                         "chunk_len": fs.chunk_len}
         return rgb
 
     def reserve(self, max_splats: int, max_duplicates: int):

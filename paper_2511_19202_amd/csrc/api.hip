@@ -21,12 +21,12 @@ struct Buf {
 };
 
 constexpr int kCounters = 24;       // u32 words of the frame counters
-constexpr int kSplitDefault = 1024; // tile-list entries per compositing chunk
 
 }  // namespace
 
 struct nvgs_ctx {
   int device = 0;
+  int n_cu = 256;  // compute units of the device
   hipStream_t stream = nullptr;
   nvgs_allocator alloc{};
   std::string err;
@@ -330,6 +330,9 @@ nvgs_status nvgs_create(const nvgs_create_info* info, nvgs_ctx** out) {
   if (static_scratch_init(info->device) != hipSuccess) return NVGS_E_DEVICE;
   nvgs_ctx* ctx = new nvgs_ctx();
   ctx->device = info->device;
+  if (hipDeviceGetAttribute(&ctx->n_cu, hipDeviceAttributeMultiprocessorCount, info->device) != hipSuccess ||
+      ctx->n_cu < 1)
+    ctx->n_cu = 256;
   ctx->stream = reinterpret_cast<hipStream_t>(info->stream);
   ctx->alloc = info->allocator;
   bool ok = hipHostMalloc(reinterpret_cast<void**>(&ctx->counters_host), kCounters * sizeof(uint32_t),
@@ -629,9 +632,11 @@ int tile_index(int T) { return T == 8 ? 0 : T == 16 ? 1 : 2; }
 // need_split >= 0) and gets them with 1/8 headroom.  A persistent frame
 // passes -1: the largest counts of the eager frames seen at this tile size
 // plus 1/4, or, before any, the bound for the entry capacity (every list
-// longer than split_len splits into at most 2 len / split_len chunks).  A
+// longer than the chunk length S splits into at most 2 len / S chunks; with
+// the frame-adaptive length S >= n / split_div, so n / S <= split_div).  A
 // frame beyond the capacity raises the overflow flag.
-nvgs_status size_items(nvgs_ctx* ctx, int64_t nkeys, int T, int split_len, int64_t need_items, int64_t need_split) {
+nvgs_status size_items(nvgs_ctx* ctx, int64_t nkeys, int T, int split_len, int64_t split_div, int64_t need_items,
+                       int64_t need_split) {
   int64_t items, slots;
   const int ti = tile_index(T);
   if (need_items >= 0) {
@@ -641,12 +646,13 @@ nvgs_status size_items(nvgs_ctx* ctx, int64_t nkeys, int T, int split_len, int64
     items = ctx->wm_items[ti] + ctx->wm_items[ti] / 4 + 256;
     slots = ctx->wm_split[ti] + ctx->wm_split[ti] / 4 + 16;
   } else {
-    const int64_t per = split_len > 0 ? ctx->cap_dup / split_len : 0;
+    const int64_t per = split_len > 0 ? ctx->cap_dup / split_len
+                        : split_len == kSplitAuto ? std::min<int64_t>(ctx->cap_dup / kSplitMin, split_div) : 0;
     items = nkeys + per + 1;
     slots = 2 * per + 2;
   }
   items = std::max(items, nkeys + 1);
-  const int64_t cap_split_px = split_len > 0 ? std::max<int64_t>(slots, 1) * T * T : 0;
+  const int64_t cap_split_px = split_len != 0 ? std::max<int64_t>(slots, 1) * T * T : 0;
   if (items <= ctx->cap_items && cap_split_px <= ctx->cap_split_px) return NVGS_OK;
   items = std::max(items, ctx->cap_items);
   const int64_t px = std::max(cap_split_px, ctx->cap_split_px);
@@ -662,7 +668,8 @@ nvgs_status size_items(nvgs_ctx* ctx, int64_t nkeys, int T, int split_len, int64
 
 struct Frame {
   int C, W, H, T, tiles_x, tiles_y, n_tiles;
-  int split_len;  // <= 0: no split
+  int split_len;     // 0: no split; kSplitAuto: frame-adaptive
+  int64_t split_div; // kSplitAuto: the frame's entries are cut into about this many chunks
   int64_t nkeys;
   bool record, debug, count_tests;
   const nvgs_render_opts* opts;
@@ -774,8 +781,9 @@ nvgs_status enqueue_frame(nvgs_ctx* ctx, hipStream_t st, const Frame& f, bool ea
   const uint32_t* tile_order = in_tmp3 ? tk + 3 * nk : tk + nk;
   // compositing items: long lists split into chunks
   uint32_t* ts = P_<uint32_t>(ctx->tsplit);
-  CK(launch_split_count(P_<uint32_t>(ctx->ranges), tile_order, nk, f.split_len, ts, ts + nk, ts + 2 * nk, ts + 3 * nk,
-                        counters + 16, counters + 17, P_<uint32_t>(ctx->hist_part), st));
+  CK(launch_split_count(P_<uint32_t>(ctx->ranges), tile_order, nk, f.split_len, n_dup_dev, nd_bound, f.split_div, ts,
+                        ts + nk, ts + 2 * nk, ts + 3 * nk, counters + 16, counters + 17, counters + 18,
+                        P_<uint32_t>(ctx->hist_part), st));
   if (eager) {
     // item and split-slot counts of this frame: the buffers are sized from them
     STAGE_END(NVGS_STAGE_TILE_SORT);
@@ -786,10 +794,10 @@ nvgs_status enqueue_frame(nvgs_ctx* ctx, hipStream_t st, const Frame& f, bool ea
     const int ti = tile_index(f.T);
     ctx->wm_items[ti] = std::max(ctx->wm_items[ti], n_items);
     ctx->wm_split[ti] = std::max(ctx->wm_split[ti], n_split);
-    if ((s = size_items(ctx, nk, f.T, f.split_len, n_items, n_split))) return s;
+    if ((s = size_items(ctx, nk, f.T, f.split_len, f.split_div, n_items, n_split))) return s;
     STAGE_BEGIN(NVGS_STAGE_TILE_SORT);
   }
-  const int64_t cap_split = f.split_len > 0 ? ctx->cap_split_px / ((int64_t)f.T * f.T) : 0;
+  const int64_t cap_split = f.split_len != 0 ? ctx->cap_split_px / ((int64_t)f.T * f.T) : 0;
   CK(launch_split_expand(ts, ts + 2 * nk, nk, P_<uint2>(ctx->citems), ctx->cap_items, counters + 17, cap_split,
                          counters + 2, st));
   STAGE_END(NVGS_STAGE_TILE_SORT);
@@ -833,6 +841,9 @@ void fill_stats(nvgs_ctx* ctx, const Frame& f, nvgs_frame_stats* stats) {
   stats->kept = ctx->counters_host[0];
   stats->duplicates = ctx->counters_host[1];
   stats->workspace_bytes = (int64_t)ctx->workspace;
+  stats->blend_items = ctx->counters_host[16];
+  stats->chunk_len = f.split_len != 0 ? (int32_t)ctx->counters_host[18] : 0;
+  stats->reserved = 0;
 }
 
 }  // namespace
@@ -873,7 +884,10 @@ nvgs_status nvgs_render(nvgs_ctx* ctx, const nvgs_camera* cams, int32_t C, const
   f.nkeys = (int64_t)C * f.n_tiles;
   if (f.nkeys >= ((int64_t)1 << 31)) return fail(ctx, NVGS_E_INVALID, "too many tiles");
   f.record = record;
-  f.split_len = opts->split_len == 0 ? kSplitDefault : (opts->split_len < 0 ? 0 : opts->split_len);
+  f.split_len = opts->split_len == 0 ? kSplitAuto : (opts->split_len < 0 ? 0 : opts->split_len);
+  // about two chunks per work-group the compositing launch keeps resident
+  // (2048 threads per compute unit; 64 threads per 8x8 tile, 256 otherwise)
+  f.split_div = 2 * (int64_t)ctx->n_cu * 2048 / (T == 8 ? 64 : 256);
   f.debug = record || (opts->flags & NVGS_RENDER_KEEP_DEBUG);
   f.count_tests = stats != nullptr && !(opts->flags & NVGS_RENDER_NO_TEST_COUNT);
   f.opts = opts;
@@ -903,7 +917,8 @@ nvgs_status nvgs_render(nvgs_ctx* ctx, const nvgs_camera* cams, int32_t C, const
   // persistent frame
   if (ctx->cap_splats <= 0 || ctx->cap_dup <= 0)
     return fail(ctx, NVGS_E_STATE, "GRAPH frames need capacities: nvgs_reserve, or one frame without NVGS_RENDER_GRAPH");
-  if ((s = size_tiles(ctx, f.nkeys)) || (s = size_hist(ctx)) || (s = size_items(ctx, f.nkeys, f.T, f.split_len, -1, -1)))
+  if ((s = size_tiles(ctx, f.nkeys)) || (s = size_hist(ctx)) ||
+      (s = size_items(ctx, f.nkeys, f.T, f.split_len, f.split_div, -1, -1)))
     return s;
   if (f.debug && (s = size_debug(ctx))) return s;
   if (ctx->cap_keys < f.nkeys || ctx->cap_hist < std::max({ctx->cap_dup, ctx->cap_splats, ctx->cap_keys}) ||

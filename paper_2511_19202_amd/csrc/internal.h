@@ -163,7 +163,10 @@ hipError_t launch_ranges(const uint32_t* keys, const uint32_t* n_dev, int64_t ca
                          hipStream_t st);
 hipError_t launch_tile_keys(const uint32_t* ranges, int64_t n, uint32_t* keys, uint32_t* vals, hipStream_t st);
 // Compositing work items (tile lists longer than split_len entries are cut
-// into chunks composited by separate work-groups; split_len <= 0: never).
+// into chunks composited by separate work-groups; split_len == 0: never;
+// kSplitAuto: the length follows the frame's entry count, see k_split_count).
+constexpr int kSplitAuto = -1;
+constexpr int kSplitMin = 256;  // shortest chunk of the frame-adaptive length
 struct BlendItems {
   int split_len;
   const uint32_t* order;    // tile launch order (positions -> tile keys)
@@ -180,9 +183,12 @@ struct BlendItems {
 };
 // Builds nch / item_off / split_off and the item list; n_items and n_split
 // receive the totals; overflow bit value 8 when cap_items is exceeded.
+// split_len == kSplitAuto: chunks of max(kSplitMin, ceil(n_entries / split_div))
+// entries, n_entries = min(*n_dev, cap) (the frame's tile-list entries).
 hipError_t launch_split_count(const uint32_t* ranges, const uint32_t* order, int64_t nkeys, int split_len,
-                              uint32_t* nch, uint32_t* nsp, uint32_t* item_off, uint32_t* split_off, uint32_t* n_items,
-                              uint32_t* n_split, uint32_t* partials, hipStream_t st);
+                              const uint32_t* n_dev, int64_t cap, int64_t split_div, uint32_t* nch, uint32_t* nsp,
+                              uint32_t* item_off, uint32_t* split_off, uint32_t* n_items, uint32_t* n_split,
+                              uint32_t* chunk_len, uint32_t* partials, hipStream_t st);
 hipError_t launch_split_expand(const uint32_t* nch, const uint32_t* item_off, int64_t nkeys, uint2* items,
                                int64_t cap_items, const uint32_t* n_split, int64_t cap_split, uint32_t* overflow,
                                hipStream_t st);

@@ -684,7 +684,16 @@ hipError_t launch_tile_keys(const uint32_t* ranges, int64_t n, uint32_t* keys, u
 // sums (rounding).  Items are (position in the tile launch order, chunk).
 // ---------------------------------------------------------------------------
 __global__ void k_split_count(const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ order, int64_t nkeys,
-                              int split_len, uint32_t* __restrict__ nch, uint32_t* __restrict__ nsp) {
+                              int split_len, const uint32_t* __restrict__ n_dev, int64_t cap, int64_t split_div,
+                              uint32_t* __restrict__ nch, uint32_t* __restrict__ nsp, uint32_t* __restrict__ chunk_len) {
+  if (split_len == kSplitAuto) {
+    // the frame's entries over split_div chunks (about two per work-group
+    // the compositing launch keeps resident): long lists are cut into pieces
+    // that balance the launch, short frames keep kSplitMin
+    const int64_t n = min((int64_t)*n_dev, cap);
+    split_len = (int)max((int64_t)kSplitMin, (n + split_div - 1) / split_div);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *chunk_len = (uint32_t)max(split_len, 0);
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < nkeys; p += (int64_t)gridDim.x * blockDim.x) {
     const uint32_t key = order[p];
     const uint32_t len = ranges[2 * (int64_t)key + 1] - ranges[2 * (int64_t)key];
@@ -1089,11 +1098,14 @@ static void launch_blend_t(bool record, const ItemCtx& ic, bool any_split, hipSt
 
 // chunks per launch position, their offsets and the totals (items, split slots)
 hipError_t launch_split_count(const uint32_t* ranges, const uint32_t* order, int64_t nkeys, int split_len,
-                              uint32_t* nch, uint32_t* nsp, uint32_t* item_off, uint32_t* split_off, uint32_t* n_items,
-                              uint32_t* n_split, uint32_t* partials, hipStream_t st) {
+                              const uint32_t* n_dev, int64_t cap, int64_t split_div, uint32_t* nch, uint32_t* nsp,
+                              uint32_t* item_off, uint32_t* split_off, uint32_t* n_items, uint32_t* n_split,
+                              uint32_t* chunk_len, uint32_t* partials, hipStream_t st) {
   if (nkeys == 0) return hipSuccess;
+  if (split_len == kSplitAuto && split_div < 1) return hipErrorInvalidValue;
   const unsigned grid = (unsigned)std::min<int64_t>((nkeys + 255) / 256, 65536);
-  hipLaunchKernelGGL(k_split_count, dim3(grid), dim3(256), 0, st, ranges, order, nkeys, split_len, nch, nsp);
+  hipLaunchKernelGGL(k_split_count, dim3(grid), dim3(256), 0, st, ranges, order, nkeys, split_len, n_dev, cap,
+                     split_div, nch, nsp, chunk_len);
   hipError_t e = launch_scan_u32_dev(nch, item_off, nkeys, nullptr, n_items, partials, st, nullptr);
   if (e != hipSuccess) return e;
   return launch_scan_u32_dev(nsp, split_off, nkeys, nullptr, n_split, partials, st, nullptr);
@@ -1117,7 +1129,7 @@ hipError_t launch_blend(const BlendItems& bi, const uint32_t* ranges, const uint
   const ItemCtx ic{bi.items, bi.n_items, bi.cap_items, bi.cap_split, bi.order,   bi.nch,
                    bi.split_off, bi.prod,   bi.part,      bi.item_off,  bi.nkeys};
   const bool record = contrib != nullptr;
-  const bool any_split = bi.split_len > 0;
+  const bool any_split = bi.split_len != 0;
   if (tile == 8)
     launch_blend_t<8>(record, ic, any_split, st, ranges, ids, splat, W, H, tiles_x, n_tiles, bg0, bg1, bg2, rgb,
                       contrib, work);

@@ -245,8 +245,17 @@ def test_full_size_batched_frame(nvgs):
     img = g.cpu().numpy()
     assert not ctx.watermarks()["overflowed"]
     assert np.array_equal(img, eager)
+    # a camera alone and in the 8-camera frame: bit-identical with a fixed
+    # chunk length; the default length follows the frame's entry count, so
+    # the two frames cut long lists differently (equal up to rounding)
+    fixed = ctx.render(sc.cameras, split=1024, **kw).cpu().numpy()
     for k in (0, 5):
+        alone = ctx.render([sc.cameras[k]], split=1024, **kw).cpu().numpy()
+        log(f"[full] camera {k} alone vs in the 8-camera frame, fixed chunks: "
+            f"max diff {np.abs(alone[0] - fixed[k]).max():.2e}")
+        assert np.array_equal(alone[0], fixed[k])
         alone = ctx.render([sc.cameras[k]], **kw).cpu().numpy()
-        log(f"[full] camera {k} alone vs in the 8-camera frame: max diff {np.abs(alone[0] - img[k]).max():.2e}")
-        assert np.array_equal(alone[0], img[k])
+        e = np.abs(alone[0] - img[k])
+        log(f"[full] camera {k} alone vs in the 8-camera frame, frame-set chunks: max diff {e.max():.2e}")
+        assert e.max() < 1e-5 or np.sum(e > 1e-5) <= max(4, 1e-3 * e[..., 0].size)
     ctx.close()

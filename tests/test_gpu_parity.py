@@ -266,6 +266,39 @@ def test_split_lists_match_sequential_and_oracle(nvgs, name, tile):
     assert np.mean(dc <= 1e-5 * np.maximum(cb_seq, 1e-3)) > 0.999
 
 
+@pytest.mark.parametrize("tile", [8, 16])
+def test_default_chunk_length_follows_the_frame(nvgs, tile):
+    """The default compositing chunk length is set by the frame on the device:
+    max(256, ceil(entries / D)) with D = 2 x compute units x 2048 / threads
+    per compositing work-group; the work items are one per tile list plus
+    one per extra chunk, and the image is the sequential one up to rounding
+    and, where FP64 decides, the oracle's."""
+    import torch
+    sc = SCENES["composed_small"]()
+    ctx = make_ctx(nvgs, sc)
+    img, st = ctx.render(sc.cameras, tile=tile, keep_debug=True, stats=True)
+    dbg = ctx.debug_buffers()
+    sk = dbg["sorted_key"].cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+    lens = np.bincount(sk, minlength=len(sc.cameras) * dbg["tiles_x"] * dbg["tiles_y"])
+    seq = ctx.render(sc.cameras, tile=tile, split=-1).cpu().numpy().astype(np.float64)
+    img = img.cpu().numpy().astype(np.float64)
+    q, _ = ctx.query_visibility(sc.cameras)
+    q = q.cpu().numpy()
+    ctx.close()
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    D = 2 * n_cu * 2048 // (64 if tile == 8 else 256)
+    S = max(256, -(-st["duplicates"] // D))
+    items = int(np.sum(np.where(lens > S, -(-lens // S), 1)))
+    log(f"[chunks] T={tile}: {st['duplicates']} entries, longest list {lens.max()}, chunk {st['chunk_len']} "
+        f"(rule {S}), items {st['blend_items']} (rule {items})")
+    assert st["chunk_len"] == S and st["blend_items"] == items
+    assert lens.max() > S, "the scene has no list long enough to split"
+    assert np.abs(img - seq).max() < 1e-5 or np.sum(np.abs(img - seq) > 1e-5) <= max(4, 1e-3 * img[..., 0].size)
+    cam = sc.cameras[0]
+    rec, prect = oracle.project(sc, cam, np.flatnonzero(q[0] == 2))
+    check_pixels(img[0], oracle.render_camera(rec, prect, cam, tile, sc.bg), f"default chunks T={tile}")
+
+
 def test_unculled_render_matches_oracle(nvgs):
     sc = SCENES["tiny"]()
     ctx = make_ctx(nvgs, sc)
