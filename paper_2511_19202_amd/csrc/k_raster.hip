@@ -348,14 +348,18 @@ __device__ __forceinline__ void project_pair(
 
 // Projection over the cull/MLP work items: a work-group takes one 256-
 // Gaussian chunk of an asset and a run of its segments (camera x instance),
-// stages the chunk's geometry records and SH rows in LDS once, and then
-// projects the kept pairs of all those segments with one thread per pair, so
-// that a Gaussian kept by several instances is read from memory once and
-// every lane has a pair whatever the keep rate.  A pair's output slot is its
-// segment-chunk's offset (exclusive scan of the chunks' keep counts) plus its
-// rank among the chunk's kept pairs, as in the ordered compaction.
-constexpr int kPjSegs = 32;       // segments staged at a time
-constexpr int kPjRow = 13;        // float4 per staged SH row (48 floats + padding)
+// stages half of the chunk's geometry records and SH rows in LDS at a time,
+// and projects the kept pairs of all those segments in that half with one
+// thread per pair, so that a Gaussian kept by several instances is read from
+// memory once and every lane has a pair whatever the keep rate (half chunks
+// keep the staging to ~40 KB: four work-groups per compute unit).  A pair's
+// output slot is its segment-chunk's offset (exclusive scan of the chunks'
+// keep counts) plus its rank among the chunk's kept pairs, as in the ordered
+// compaction.
+constexpr int kPjSegs = 32;        // segments staged at a time
+constexpr int kPjRow = 13;         // float4 per staged SH row (48 floats + padding)
+constexpr int kPjHalf = kChunk / 2;  // Gaussians staged at a time
+constexpr int kPjWords = kPjHalf / 32;
 __global__ __launch_bounds__(256) void k_project(
     const AssetDev* __restrict__ assets, const WorkItem* __restrict__ items, const int32_t* __restrict__ seglist,
     const SegRec* __restrict__ segs, const uint32_t* __restrict__ mask, const uint32_t* __restrict__ chunk_off,
@@ -363,105 +367,109 @@ __global__ __launch_bounds__(256) void k_project(
     float det_clip, float4* __restrict__ splat, float4* __restrict__ rec_a, float4* __restrict__ rec_b,
     float4* __restrict__ rec_c, float2* __restrict__ rec_d, uint4* __restrict__ rect_dbg, uint2* __restrict__ rect,
     uint32_t* __restrict__ depth_key, uint32_t* __restrict__ pair_of, uint32_t* __restrict__ overflow) {
-  __shared__ float4 s_geo[3 * kChunk];
-  __shared__ float4 s_sh[kChunk * kPjRow];
+  __shared__ float4 s_geo[3 * kPjHalf];
+  __shared__ float4 s_sh[kPjHalf * kPjRow];
   __shared__ SegRec s_seg[kPjSegs];
   __shared__ uint32_t s_mask[kPjSegs][kChunk / 32];
-  __shared__ uint32_t s_base[kPjSegs + 1];  // exclusive scan of the segments' kept counts in this chunk
-  __shared__ uint32_t s_slot[kPjSegs];      // output slot of each segment's first kept pair
+  __shared__ uint32_t s_base[kPjSegs + 1];  // exclusive scan of the segments' kept counts in this half
+  __shared__ uint32_t s_slot[kPjSegs];      // output slot of each segment's first kept pair in this half
   const int t = threadIdx.x;
   if (blockIdx.x == 0 && t == 0 && (int64_t)*n_splats > cap) atomicOr(overflow, 1u);
   const WorkItem it = items[blockIdx.x];
   const AssetDev& A = assets[it.asset];
   const int64_t n = A.n;
-  const int64_t g0 = (int64_t)it.chunk * kChunk;
   const int64_t words = (n + 31) >> 5;
   constexpr int RW = sizeof(SegRec) / 4;
   static_assert(sizeof(SegRec) % 4 == 0, "segment records are copied word by word");
-  bool staged = false;
-  for (int sb = it.seg_begin; sb < it.seg_end; sb += kPjSegs) {
-    const int ns = min(kPjSegs, it.seg_end - sb);
-    __syncthreads();  // the previous batch's reads of the segment records and masks are done
-    for (int i = t; i < ns * RW; i += 256)
-      reinterpret_cast<uint32_t*>(s_seg)[i] = reinterpret_cast<const uint32_t*>(segs + seglist[sb + i / RW])[i % RW];
-    for (int i = t; i < ns * (kChunk / 32); i += 256) {
-      const int j = i / (kChunk / 32), w = i % (kChunk / 32);
-      const int64_t wi = (int64_t)it.chunk * (kChunk / 32) + w;
-      s_mask[j][w] = wi < words ? mask[segs[seglist[sb + j]].word_base + wi] : 0u;
-    }
-    __syncthreads();
-    if (t < 64) {  // one wave: kept counts, their scan, the slot bases
-      uint32_t c = 0;
-      if (t < ns)
-        for (int w = 0; w < kChunk / 32; ++w) c += (uint32_t)__popc(s_mask[t][w]);
-      uint32_t x = c;
-#pragma unroll
-      for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t y = __shfl_up(x, o);
-        if (t >= o) x += y;
+  for (int h = 0; h < 2; ++h) {
+    const int64_t g0 = (int64_t)it.chunk * kChunk + h * kPjHalf;
+    bool staged = false;
+    for (int sb = it.seg_begin; sb < it.seg_end; sb += kPjSegs) {
+      const int ns = min(kPjSegs, it.seg_end - sb);
+      __syncthreads();  // the previous batch's reads of the segment records and masks are done
+      for (int i = t; i < ns * RW; i += 256)
+        reinterpret_cast<uint32_t*>(s_seg)[i] = reinterpret_cast<const uint32_t*>(segs + seglist[sb + i / RW])[i % RW];
+      for (int i = t; i < ns * (kChunk / 32); i += 256) {
+        const int j = i / (kChunk / 32), w = i % (kChunk / 32);
+        const int64_t wi = (int64_t)it.chunk * (kChunk / 32) + w;
+        s_mask[j][w] = wi < words ? mask[segs[seglist[sb + j]].word_base + wi] : 0u;
       }
-      if (t == 0) s_base[0] = 0;
-      if (t < ns) {
-        s_base[t + 1] = x;
-        s_slot[t] = chunk_off[s_seg[t].chunk_base + it.chunk];
-      }
-    }
-    __syncthreads();
-    const uint32_t K = s_base[ns];
-    if (K == 0) continue;
-    if (!staged) {
-      const int q4 = A.sh_stride / 4;
-      for (int i = t; i < 3 * kChunk; i += 256)
-        s_geo[i] = g0 + i / 3 < n ? ld_global(A.geo, 3 * g0 + i) : make_float4(0.f, 0.f, 0.f, 0.f);
-      const float4* shp = reinterpret_cast<const float4*>(A.shp);
-      for (int i = t; i < kChunk * q4; i += 256) {
-        const int gi = i / q4, q = i % q4;
-        s_sh[gi * kPjRow + q] = g0 + gi < n ? ld_global(shp, (g0 + gi) * q4 + q) : make_float4(0.f, 0.f, 0.f, 0.f);
-      }
-      staged = true;
       __syncthreads();
-    }
-    for (uint32_t p = (uint32_t)t; p < K; p += 256) {
-      // segment: the last j with s_base[j] <= p
-      int j = 0;
-#pragma unroll
-      for (int step = kPjSegs / 2; step > 0; step >>= 1)
-        if (j + step < ns && s_base[j + step] <= p) j += step;
-      // rank among the segment's kept pairs of this chunk -> mask word and bit
-      const uint32_t r = p - s_base[j];
-      uint32_t cum = 0, below = 0, x = 0;
-      int wsel = 0;
-      bool found = false;
-#pragma unroll
-      for (int w = 0; w < kChunk / 32; ++w) {
-        const uint32_t m = s_mask[j][w];
-        const uint32_t pc = (uint32_t)__popc(m);
-        if (!found && r < cum + pc) {
-          found = true;
-          wsel = w;
-          below = cum;
-          x = m;
+      if (t < 64) {  // one wave: kept counts of this half, their scan, the slot bases
+        uint32_t c = 0, before = 0;
+        if (t < ns) {
+          for (int w = 0; w < kPjWords; ++w) c += (uint32_t)__popc(s_mask[t][h * kPjWords + w]);
+          for (int w = 0; w < h * kPjWords; ++w) before += (uint32_t)__popc(s_mask[t][w]);
         }
-        cum += pc;
-      }
-      uint32_t rr = r - below;
-      int pos = 0;
+        uint32_t x = c;
 #pragma unroll
-      for (int half = 16; half > 0; half >>= 1) {
-        const uint32_t low = (uint32_t)__popc(x & ((1u << half) - 1u));
-        if (rr >= low) {
-          rr -= low;
-          x >>= half;
-          pos += half;
+        for (int o = 1; o < 64; o <<= 1) {
+          const uint32_t y = __shfl_up(x, o);
+          if (t >= o) x += y;
+        }
+        if (t == 0) s_base[0] = 0;
+        if (t < ns) {
+          s_base[t + 1] = x;
+          s_slot[t] = chunk_off[s_seg[t].chunk_base + it.chunk] + before;
         }
       }
-      const int gl = wsel * 32 + pos;
-      const uint32_t slot = s_slot[j] + r;
-      if ((int64_t)slot >= cap) continue;  // flagged above
-      const SegRec& R = s_seg[j];
-      project_pair(R, s_geo[3 * gl], s_geo[3 * gl + 1], s_geo[3 * gl + 2], s_sh + gl * kPjRow, A.sh_degree,
-                   (uint32_t)(R.pair_base + g0 + gl), slot, tile, tiles_x, n_tiles, keep_debug, det_clip, splat,
-                   rec_a, rec_b, rec_c, rec_d, rect_dbg, rect, depth_key, pair_of);
+      __syncthreads();
+      const uint32_t K = s_base[ns];
+      if (K == 0) continue;
+      if (!staged) {
+        const int q4 = A.sh_stride / 4;
+        for (int i = t; i < 3 * kPjHalf; i += 256)
+          s_geo[i] = g0 + i / 3 < n ? ld_global(A.geo, 3 * g0 + i) : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float4* shp = reinterpret_cast<const float4*>(A.shp);
+        for (int i = t; i < kPjHalf * q4; i += 256) {
+          const int gi = i / q4, q = i % q4;
+          s_sh[gi * kPjRow + q] = g0 + gi < n ? ld_global(shp, (g0 + gi) * q4 + q) : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        staged = true;
+        __syncthreads();
+      }
+      for (uint32_t p = (uint32_t)t; p < K; p += 256) {
+        // segment: the last j with s_base[j] <= p
+        int j = 0;
+#pragma unroll
+        for (int step = kPjSegs / 2; step > 0; step >>= 1)
+          if (j + step < ns && s_base[j + step] <= p) j += step;
+        // rank among the segment's kept pairs of this half -> mask word and bit
+        const uint32_t r = p - s_base[j];
+        uint32_t cum = 0, below = 0, x = 0;
+        int wsel = 0;
+        bool found = false;
+#pragma unroll
+        for (int w = 0; w < kPjWords; ++w) {
+          const uint32_t m = s_mask[j][h * kPjWords + w];
+          const uint32_t pc = (uint32_t)__popc(m);
+          if (!found && r < cum + pc) {
+            found = true;
+            wsel = w;
+            below = cum;
+            x = m;
+          }
+          cum += pc;
+        }
+        uint32_t rr = r - below;
+        int pos = 0;
+#pragma unroll
+        for (int half = 16; half > 0; half >>= 1) {
+          const uint32_t low = (uint32_t)__popc(x & ((1u << half) - 1u));
+          if (rr >= low) {
+            rr -= low;
+            x >>= half;
+            pos += half;
+          }
+        }
+        const int gl = wsel * 32 + pos;
+        const uint32_t slot = s_slot[j] + r;
+        if ((int64_t)slot >= cap) continue;  // flagged above
+        const SegRec& R = s_seg[j];
+        project_pair(R, s_geo[3 * gl], s_geo[3 * gl + 1], s_geo[3 * gl + 2], s_sh + gl * kPjRow, A.sh_degree,
+                     (uint32_t)(R.pair_base + g0 + gl), slot, tile, tiles_x, n_tiles, keep_debug, det_clip, splat,
+                     rec_a, rec_b, rec_c, rec_d, rect_dbg, rect, depth_key, pair_of);
+      }
     }
   }
 }
