@@ -510,6 +510,8 @@ def main():
         "in_frustum": st_c["in_frustum"], "queried": st_c["queried"], "kept": st_c["kept"],
         "duplicates": st_c["duplicates"], "duplicates_unculled": st_u["duplicates"],
         "blend_tests": st_c["blend_tests"], "blend_tests_unculled": st_u["blend_tests"],
+        "compositing_items": st_c["blend_items"], "compositing_items_unculled": st_u["blend_items"],
+        "chunk_len": st_c["chunk_len"], "chunk_len_unculled": st_u["chunk_len"],
         "ms_stage": stage_c, "ms_stage_unculled": stage_u,
         "dominant_kernel": dom,
         "roofline": roof,
