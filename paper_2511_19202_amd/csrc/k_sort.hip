@@ -21,12 +21,14 @@ namespace nvgs {
 
 constexpr int kSortThreads = 256;
 constexpr int kSortWaves = kSortThreads / 64;
-constexpr int kPerWave = kSortBlock / kSortWaves;  // 512 keys per wave
-constexpr int kRounds = kPerWave / 64;             // 8 rounds of 64
 static_assert(kSortThreads == 256, "the scatter gives one thread to each of the 256 digits");
-// work-groups per pass (they loop over the live blocks); 2048-key blocks and
-// these grids were the fastest of 1024-8192 keys and 1024-4096 groups for
-// 6-100M keys
+// keys per block: kSortBlock (2,048) below kSortBigKeys keys, twice that from
+// there on (measured for 6.4M-661M keys: 2,048 is the fastest at 6.4M,
+// 4,096 from 25M on, 35 % faster at 400M-1G; 8,192 never)
+constexpr int kSortBlockBig = 2 * kSortBlock;
+constexpr int64_t kSortBigKeys = (int64_t)24 << 20;
+// work-groups per pass (they loop over the live blocks); these grids were
+// the fastest of 1024-4096 groups for 6-100M keys
 constexpr int64_t kSortGrid = 2048;  // scatter: 8 per CU
 constexpr int64_t kHistGrid = 4096;  // histogram: 16 per CU
 
@@ -34,23 +36,26 @@ __device__ __forceinline__ int64_t live_n(const uint32_t* n_dev, int64_t cap) {
   return n_dev ? (int64_t)min((uint64_t)*n_dev, (uint64_t)cap) : cap;
 }
 
-// blocks of kSortBlock keys holding live keys (the launches are sized by the
+// blocks of `block` keys holding live keys (the launches are sized by the
 // capacity; work-groups loop over the live blocks only)
-__device__ __forceinline__ int64_t live_blocks(const uint32_t* n_dev, int64_t cap) {
-  return (live_n(n_dev, cap) + kSortBlock - 1) / kSortBlock;
+__device__ __forceinline__ int64_t live_blocks(const uint32_t* n_dev, int64_t cap, int block) {
+  return (live_n(n_dev, cap) + block - 1) / block;
 }
 
+template <int BLOCK>
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t* __restrict__ keys,
                                                              const uint32_t* __restrict__ n_dev, int64_t cap, int shift,
                                                              uint32_t dmask, uint32_t* __restrict__ hist, int64_t nblocks) {
+  constexpr int kPerWave = BLOCK / kSortWaves;  // 512 or 1024 keys per wave
+  constexpr int kRounds = kPerWave / 64;
   __shared__ uint32_t s_h[kSortWaves][256];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t n = live_n(n_dev, cap);
-  const int64_t nbl = live_blocks(n_dev, cap);
+  const int64_t nbl = live_blocks(n_dev, cap, BLOCK);
   // the wave's keys of a block (beyond the live keys: none); the next block's
   // are loaded while this one is counted
   auto load = [&](int64_t blk, uint32_t* kv) {
-    const int64_t base = blk * kSortBlock + wave * kPerWave;
+    const int64_t base = blk * BLOCK + wave * kPerWave;
 #pragma unroll
     for (int r = 0; r < kRounds; ++r) {
       const int64_t idx = base + r * 64 + lane;
@@ -64,7 +69,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t* __r
     load(blk + gridDim.x, kn);
     for (int d = threadIdx.x; d < kSortWaves * 256; d += kSortThreads) (&s_h[0][0])[d] = 0;
     __syncthreads();
-    const int64_t base = blk * kSortBlock + wave * kPerWave;
+    const int64_t base = blk * BLOCK + wave * kPerWave;
 #pragma unroll
     for (int r = 0; r < kRounds; ++r)
       if (base + r * 64 + lane < n) atomicAdd(&s_h[wave][(kv[r] >> shift) & dmask], 1u);
@@ -90,12 +95,12 @@ __device__ __forceinline__ int row_pad(int i) { return i + (i >> 4); }
 
 __global__ __launch_bounds__(kSortThreads) void k_radix_rowscan(uint32_t* __restrict__ hist, int64_t nblocks,
                                                                 const uint32_t* __restrict__ n_dev, int64_t cap,
-                                                                uint32_t* __restrict__ tot) {
+                                                                int block, uint32_t* __restrict__ tot) {
   __shared__ uint32_t s_w[kSortWaves];
   __shared__ uint32_t s_x[kRowTile + kRowTile / 16];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t* row = hist + (int64_t)blockIdx.x * nblocks;
-  const int64_t nbl = live_blocks(n_dev, cap);  // the row's live entries
+  const int64_t nbl = live_blocks(n_dev, cap, block);  // the row's live entries
   uint32_t carry = 0;
   // a tile's entries, coalesced; the next tile's are loaded while this one is scanned
   auto load = [&](int64_t off, uint32_t* v) {
@@ -154,6 +159,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_rowscan(uint32_t* __rest
   if (threadIdx.x == 0) tot[blockIdx.x] = carry;
 }
 
+template <int BLOCK>
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, uint32_t* __restrict__ keys_out,
     uint32_t* __restrict__ vals_out, const uint32_t* __restrict__ n_dev, int64_t cap, int shift, uint32_t dmask,
@@ -164,15 +170,17 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
   __shared__ uint32_t s_glob[256];             // global position of each digit's first key of this block
   __shared__ uint32_t s_wsum[kSortWaves];
   __shared__ uint32_t s_gsum[kSortWaves];
-  __shared__ uint32_t s_k[kSortBlock];
-  __shared__ uint32_t s_v[kSortBlock];
+  constexpr int kPerWave = BLOCK / kSortWaves;
+  constexpr int kRounds = kPerWave / 64;
+  __shared__ uint32_t s_k[BLOCK];
+  __shared__ uint32_t s_v[BLOCK];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t n = live_n(n_dev, cap);
-  const int64_t nbl = live_blocks(n_dev, cap);
+  const int64_t nbl = live_blocks(n_dev, cap, BLOCK);
   // the wave's keys and values of a block; the next block's are loaded while
   // this one is ranked and written
   auto load = [&](int64_t blk, uint32_t* k, uint32_t* v) {
-    const int64_t base = blk * kSortBlock + wave * kPerWave;
+    const int64_t base = blk * BLOCK + wave * kPerWave;
 #pragma unroll
     for (int r = 0; r < kRounds; ++r) {
       const int64_t idx = base + r * 64 + lane;
@@ -188,7 +196,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     load(blk + gridDim.x, nkey, nval);
     for (int d = threadIdx.x; d < kSortWaves * 256; d += kSortThreads) (&s_cnt[0][0])[d] = 0;
     __syncthreads();
-    const int64_t block0 = blk * kSortBlock;
+    const int64_t block0 = blk * BLOCK;
     const int64_t base = block0 + wave * kPerWave;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     uint32_t local[kRounds];
@@ -259,7 +267,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     }
     __syncthreads();
     // phase 4: consecutive threads write consecutive positions of each digit run
-    const int cnt = (int)min<int64_t>(kSortBlock, n - block0);
+    const int cnt = (int)min<int64_t>(BLOCK, n - block0);
     for (int p = threadIdx.x; p < cnt; p += kSortThreads) {
       const uint32_t k = s_k[p];
       const uint32_t dg = (k >> shift) & dmask;
@@ -276,7 +284,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
   }
 }
 
-// digit-major block counts, then the 256 digit totals
+// digit-major block counts, then the 256 digit totals (sized for the
+// smaller block, an upper bound for both)
 size_t radix_hist_words(int64_t cap) {
   int64_t nb = (cap + kSortBlock - 1) / kSortBlock;
   return (size_t)(256 * ((nb > 0 ? nb : 1) + 1));
@@ -288,7 +297,9 @@ size_t radix_hist_words(int64_t cap) {
 hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint32_t* vals_tmp,
                              const uint32_t* n_dev, int64_t cap, int begin_bit, int end_bit, int iota_vals,
                              uint32_t* hist, uint32_t* partials, bool* result_in_tmp, hipStream_t st) {
-  const int64_t nb = (cap + kSortBlock - 1) / kSortBlock;
+  const bool big = cap >= kSortBigKeys;
+  const int block = big ? kSortBlockBig : kSortBlock;
+  const int64_t nb = (cap + block - 1) / block;
   bool in_tmp = false;
   if (nb == 0 || end_bit <= begin_bit) {
     *result_in_tmp = false;
@@ -306,10 +317,19 @@ hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp,
     const int nbits = min(8, end_bit - shift);
     const uint32_t dmask = (1u << nbits) - 1u;
     uint32_t* tot = hist + 256 * nb;
-    hipLaunchKernelGGL(k_radix_hist, dim3(hgrid), dim3(kSortThreads), 0, st, kin, n_dev, cap, shift, dmask, hist, nb);
-    hipLaunchKernelGGL(k_radix_rowscan, dim3(256), dim3(kSortThreads), 0, st, hist, nb, n_dev, cap, tot);
-    hipLaunchKernelGGL(k_radix_scatter, dim3(grid), dim3(kSortThreads), 0, st, kin, vin, kout, vout, n_dev, cap, shift,
-                       dmask, nbits, hist, nb, tot, (first && iota_vals) ? 1 : 0);
+    if (big)
+      hipLaunchKernelGGL(k_radix_hist<kSortBlockBig>, dim3(hgrid), dim3(kSortThreads), 0, st, kin, n_dev, cap, shift,
+                         dmask, hist, nb);
+    else
+      hipLaunchKernelGGL(k_radix_hist<kSortBlock>, dim3(hgrid), dim3(kSortThreads), 0, st, kin, n_dev, cap, shift,
+                         dmask, hist, nb);
+    hipLaunchKernelGGL(k_radix_rowscan, dim3(256), dim3(kSortThreads), 0, st, hist, nb, n_dev, cap, block, tot);
+    if (big)
+      hipLaunchKernelGGL(k_radix_scatter<kSortBlockBig>, dim3(grid), dim3(kSortThreads), 0, st, kin, vin, kout, vout,
+                         n_dev, cap, shift, dmask, nbits, hist, nb, tot, (first && iota_vals) ? 1 : 0);
+    else
+      hipLaunchKernelGGL(k_radix_scatter<kSortBlock>, dim3(grid), dim3(kSortThreads), 0, st, kin, vin, kout, vout,
+                         n_dev, cap, shift, dmask, nbits, hist, nb, tot, (first && iota_vals) ? 1 : 0);
     first = false;
     std::swap(kin, kout);
     std::swap(vin, vout);

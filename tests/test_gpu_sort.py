@@ -88,6 +88,19 @@ def test_sort_pairs_full_size(env, n, kind, bits):
     _check(env, keys, 0, bits, n)
 
 
+@pytest.mark.parametrize("n,kind,bits", [((24 << 20) - 1, "depth", 32), ((24 << 20) + 4097, "depth", 32),
+                                         ((24 << 20) + 4097, "few", 18)])
+def test_sort_pairs_block_size_switch(env, n, kind, bits):
+    """From 24Mi keys on the sort uses 4,096-key blocks instead of 2,048:
+    just below and just above the switch, with a ragged last block."""
+    log(f"[sort] block switch n={n} kind={kind} bits={bits}")
+    rng = np.random.default_rng(n + bits)
+    keys = _keys(kind, n, rng)
+    if bits < 32:
+        keys = (keys ^ rng.integers(0, 1 << 32, n, dtype=np.uint64).astype(np.uint32)) & np.uint32((1 << bits) - 1)
+    _check(env, keys, 0, bits, n)
+
+
 def test_sort_pairs_empty_and_invalid(env):
     nvgs, torch, ctx = env
     e = torch.empty(0, dtype=torch.int32, device="cuda")
@@ -103,8 +116,8 @@ def test_sort_pairs_empty_and_invalid(env):
 
 
 def test_sort_pairs_repeated_calls_reuse_the_workspace(env):
-    """A smaller sort after a larger one: stale look-back words of the larger
-    one's tiles must not leak into the smaller one."""
+    """A smaller sort after a larger one: stale histogram words of the larger
+    one's blocks must not leak into the smaller one."""
     rng = np.random.default_rng(5)
     for n in (500_000, 70_000, 2049, 500_000):
         _check(env, _keys("uniform", n, rng), 0, 32, n)
