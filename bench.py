@@ -184,16 +184,17 @@ def implementation_bytes(stage, st, sh_degree, n_keys_tiles):
     """Bytes the kernels as built move: the projection's 48 B geometry record
     + SH row (rounded to 16 B) read and its 64 B compositing record, 8 B tile
     rectangle and 4 B depth key written; a radix pass 4 B histogram + 8 B read
-    + 8 B written per key; binning 52 B per splat (gather: id, rectangle,
-    depth-ordered rectangle and count; in-place count scan; emission: id,
+    + 8 B written per key, the depth sort's last pass writing the 8 B
+    rectangle and 4 B tile count it reads by id instead of the 4 B key (+16 B
+    per splat); binning 28 B per splat (in-place count scan; emission: id,
     rectangle, offset) + 8 B per entry; the tile stage its radix passes + 4 B
     per entry for the ranges."""
     if stage == "project":
         return st["kept"] * (48 + 4 * (-(-3 * (sh_degree + 1) ** 2 // 4) * 4) + 76)
     if stage == "depth_sort":
-        return st["kept"] * 4 * 20
+        return st["kept"] * (4 * 20 + 16)
     if stage == "bin":
-        return st["kept"] * 52 + st["duplicates"] * 8
+        return st["kept"] * 28 + st["duplicates"] * 8
     if stage == "tile_sort":
         passes = max(1, -(-max(1, int(n_keys_tiles - 1).bit_length()) // 8))
         return st["duplicates"] * (20 * passes + 4)

@@ -732,17 +732,18 @@ nvgs_status enqueue_frame(nvgs_ctx* ctx, hipStream_t st, const Frame& f, bool ea
   // depth order of the splats (stable: equal depths keep id order)
   STAGE_BEGIN(NVGS_STAGE_DEPTH_SORT);
   bool in_tmp = false;
+  // the sort also writes each splat's tile rectangle and tile count in depth
+  // order (the sorted depth keys themselves are not read afterwards)
+  const SortGather gather{P_<uint2>(ctx->rect), P_<uint2>(ctx->rect_sorted), P_<uint32_t>(ctx->cnt)};
   CK(launch_radix_sort(P_<uint32_t>(ctx->depth_key), P_<uint32_t>(ctx->ids), P_<uint32_t>(ctx->keys_tmp),
                        P_<uint32_t>(ctx->vals_tmp), n_splats_dev, ns_bound, 0, 32, 1, P_<uint32_t>(ctx->hist),
-                       P_<uint32_t>(ctx->hist_part), &in_tmp, st));
+                       P_<uint32_t>(ctx->hist_part), &in_tmp, st, &gather));
   // four passes: the order ends in ids, and the ping-pong pair, which the
   // entry sizing below may reallocate, is free again for the tile sort
   if (in_tmp) return fail(ctx, NVGS_E_DEVICE, "depth sort: the order must end in the id buffer");
   const uint32_t* depth_ids = P_<uint32_t>(ctx->ids);
   STAGE_END(NVGS_STAGE_DEPTH_SORT);
   STAGE_BEGIN(NVGS_STAGE_BIN);
-  CK(launch_gather_tiles(depth_ids, P_<uint2>(ctx->rect), n_splats_dev, ns_bound, P_<uint32_t>(ctx->cnt),
-                         P_<uint2>(ctx->rect_sorted), st));
   // tile counts -> entry offsets, in place
   CK(launch_scan_u32_dev(P_<uint32_t>(ctx->cnt), P_<uint32_t>(ctx->cnt), ns_bound, n_splats_dev, counters + 1,
                          P_<uint32_t>(ctx->hist_part), st, counters + 2));

@@ -147,13 +147,21 @@ hipError_t launch_project(const AssetDev* assets, const WorkItem* items, int64_t
                           float4* splat, float4* rec_a, float4* rec_b, float4* rec_c, float2* rec_d, uint4* rect_dbg,
                           uint2* rect, uint32_t* depth_key, uint32_t* pair_of, uint32_t* overflow, hipStream_t st);
 
+// Optional output of a sort: for each sorted value v (in sorted order),
+// rect_out = rect[v] and count_out = the rectangle's width x height (the
+// splats' tile rectangles and tile counts in depth order); the sorted keys
+// may then be left unwritten.
+struct SortGather {
+  const uint2* rect;
+  uint2* rect_out;
+  uint32_t* count_out;
+};
 hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint32_t* vals_tmp,
                              const uint32_t* n_dev, int64_t cap, int begin_bit, int end_bit, int iota_vals,
-                             uint32_t* hist, uint32_t* partials, bool* result_in_tmp, hipStream_t st);
+                             uint32_t* hist, uint32_t* partials, bool* result_in_tmp, hipStream_t st,
+                             const SortGather* gather = nullptr);
 size_t radix_hist_words(int64_t cap);  // sort workspace (32-bit words) for up to cap keys
 
-hipError_t launch_gather_tiles(const uint32_t* sorted_ids, const uint2* rect, const uint32_t* n_dev, int64_t cap,
-                               uint32_t* out, uint2* rect_sorted, hipStream_t st);
 hipError_t launch_emit(const uint32_t* sorted_ids, const uint2* rect_sorted, const uint32_t* dup_off, const uint32_t* n_dev,
                        int64_t cap, const uint32_t* n_dup_dev, int64_t cap_dup, int tiles_x, int n_tiles,
                        uint32_t* keys, uint32_t* vals, uint32_t* overflow, hipStream_t st);

@@ -493,27 +493,6 @@ __device__ __forceinline__ int64_t live(const uint32_t* n_dev, int64_t cap) {
   return n_dev ? (int64_t)min((uint64_t)*n_dev, (uint64_t)cap) : cap;
 }
 
-// tile counts of the splats in depth order, and their rectangles copied into
-// depth order so that the emission reads them sequentially
-__global__ void k_gather_tiles(const uint32_t* __restrict__ ids, const uint2* __restrict__ rect,
-                               const uint32_t* __restrict__ n_dev, int64_t cap, uint32_t* __restrict__ out,
-                               uint2* __restrict__ rect_sorted) {
-  const int64_t n = live(n_dev, cap);
-  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
-    const uint2 r = rect[ids[j]];
-    out[j] = (r.y & 0xffffu) * (r.y >> 16);  // tiles: width x height
-    rect_sorted[j] = r;
-  }
-}
-
-hipError_t launch_gather_tiles(const uint32_t* sorted_ids, const uint2* rect, const uint32_t* n_dev, int64_t cap,
-                               uint32_t* out, uint2* rect_sorted, hipStream_t st) {
-  if (cap == 0) return hipSuccess;
-  unsigned grid = (unsigned)std::min<int64_t>((cap + 255) / 256, 65536);
-  hipLaunchKernelGGL(k_gather_tiles, dim3(grid), dim3(256), 0, st, sorted_ids, rect, n_dev, cap, out, rect_sorted);
-  return hipGetLastError();
-}
-
 // One (tile key, splat id) entry per overlapped tile of each splat, in depth
 // order: splat j's entries occupy [off[j], off[j] + ntiles_j), its tiles in
 // row-major order.  A wave takes 64 consecutive splats and its lanes write

@@ -159,12 +159,12 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_rowscan(uint32_t* __rest
   if (threadIdx.x == 0) tot[blockIdx.x] = carry;
 }
 
-template <int BLOCK>
+template <int BLOCK, bool GATHER>
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, uint32_t* __restrict__ keys_out,
     uint32_t* __restrict__ vals_out, const uint32_t* __restrict__ n_dev, int64_t cap, int shift, uint32_t dmask,
     int nbits, const uint32_t* __restrict__ offs, int64_t nblocks, const uint32_t* __restrict__ digit_tot,
-    int iota_vals) {
+    int iota_vals, SortGather gather) {
   __shared__ uint32_t s_cnt[kSortWaves][256];  // per-wave digit counts, then per-wave digit bases in the block
   __shared__ uint32_t s_start[256];            // first block-local position of each digit
   __shared__ uint32_t s_glob[256];             // global position of each digit's first key of this block
@@ -268,12 +268,37 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     __syncthreads();
     // phase 4: consecutive threads write consecutive positions of each digit run
     const int cnt = (int)min<int64_t>(BLOCK, n - block0);
-    for (int p = threadIdx.x; p < cnt; p += kSortThreads) {
-      const uint32_t k = s_k[p];
-      const uint32_t dg = (k >> shift) & dmask;
-      const uint32_t pos = s_glob[dg] + (uint32_t)p - s_start[dg];
-      keys_out[pos] = k;
-      vals_out[pos] = s_v[p];
+    if constexpr (GATHER) {
+      // every rectangle read of the thread is issued before the first write
+      constexpr int PER = BLOCK / kSortThreads;
+      uint32_t pos[PER], v[PER];
+      uint2 r[PER];
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int p = (int)threadIdx.x + i * kSortThreads;
+        if (p < cnt) {
+          const uint32_t dg = (s_k[p] >> shift) & dmask;
+          pos[i] = s_glob[dg] + (uint32_t)p - s_start[dg];
+          v[i] = s_v[p];
+          r[i] = gather.rect[v[i]];
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        if ((int)threadIdx.x + i * kSortThreads < cnt) {
+          vals_out[pos[i]] = v[i];
+          gather.rect_out[pos[i]] = r[i];
+          gather.count_out[pos[i]] = (r[i].y & 0xffffu) * (r[i].y >> 16);
+        }
+      }
+    } else {
+      for (int p = threadIdx.x; p < cnt; p += kSortThreads) {
+        const uint32_t k = s_k[p];
+        const uint32_t dg = (k >> shift) & dmask;
+        const uint32_t pos = s_glob[dg] + (uint32_t)p - s_start[dg];
+        keys_out[pos] = k;
+        vals_out[pos] = s_v[p];
+      }
     }
     __syncthreads();  // LDS is reused by the next block
 #pragma unroll
@@ -281,6 +306,21 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
       key[r] = nkey[r];
       val[r] = nval[r];
     }
+  }
+}
+
+// The rectangles and counts of a sort with SortGather below kSortBigKeys
+// keys: a pass of its own after the sort, one sorted value per thread (the
+// scatter's last pass holds too few reads in flight at these sizes; from
+// kSortBigKeys keys on it does the gather itself, which saves reading the
+// sorted values and writing the sorted keys again)
+__global__ void k_sort_gather(const uint32_t* __restrict__ vals, const uint32_t* __restrict__ n_dev, int64_t cap,
+                              SortGather g) {
+  const int64_t n = live_n(n_dev, cap);
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+    const uint2 r = g.rect[vals[j]];
+    g.count_out[j] = (r.y & 0xffffu) * (r.y >> 16);
+    g.rect_out[j] = r;
   }
 }
 
@@ -294,9 +334,13 @@ size_t radix_hist_words(int64_t cap) {
 // Sorts keys[0..n) (n = *n_dev, at most cap) by bits [begin_bit, end_bit).
 // Buffers ping-pong between (keys, vals) and (keys_tmp, vals_tmp); the result
 // ends in the tmp pair when the number of passes is odd (*result_in_tmp).
+// With `gather` the sorted values' rectangles and counts are written too: by
+// the last pass, in place of the sorted keys (the output key buffer is then
+// left as it was), from kSortBigKeys keys on, else by a pass after the sort.
 hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint32_t* vals_tmp,
                              const uint32_t* n_dev, int64_t cap, int begin_bit, int end_bit, int iota_vals,
-                             uint32_t* hist, uint32_t* partials, bool* result_in_tmp, hipStream_t st) {
+                             uint32_t* hist, uint32_t* partials, bool* result_in_tmp, hipStream_t st,
+                             const SortGather* gather) {
   const bool big = cap >= kSortBigKeys;
   const int block = big ? kSortBlockBig : kSortBlock;
   const int64_t nb = (cap + block - 1) / block;
@@ -324,18 +368,28 @@ hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp,
       hipLaunchKernelGGL(k_radix_hist<kSortBlock>, dim3(hgrid), dim3(kSortThreads), 0, st, kin, n_dev, cap, shift,
                          dmask, hist, nb);
     hipLaunchKernelGGL(k_radix_rowscan, dim3(256), dim3(kSortThreads), 0, st, hist, nb, n_dev, cap, block, tot);
-    if (big)
-      hipLaunchKernelGGL(k_radix_scatter<kSortBlockBig>, dim3(grid), dim3(kSortThreads), 0, st, kin, vin, kout, vout,
-                         n_dev, cap, shift, dmask, nbits, hist, nb, tot, (first && iota_vals) ? 1 : 0);
-    else
-      hipLaunchKernelGGL(k_radix_scatter<kSortBlock>, dim3(grid), dim3(kSortThreads), 0, st, kin, vin, kout, vout,
-                         n_dev, cap, shift, dmask, nbits, hist, nb, tot, (first && iota_vals) ? 1 : 0);
+    const bool g = big && gather && shift + 8 >= end_bit;  // the last pass of a large sort
+    const SortGather ga = g ? *gather : SortGather{nullptr, nullptr, nullptr};
+    const int iv = (first && iota_vals) ? 1 : 0;
+#define NVGS_SCATTER(B, G)                                                                                         \
+  hipLaunchKernelGGL((k_radix_scatter<B, G>), dim3(grid), dim3(kSortThreads), 0, st, kin, vin, kout, vout, n_dev, cap, \
+                     shift, dmask, nbits, hist, nb, tot, iv, ga)
+    if (big) {
+      if (g) NVGS_SCATTER(kSortBlockBig, true); else NVGS_SCATTER(kSortBlockBig, false);
+    } else {
+      if (g) NVGS_SCATTER(kSortBlock, true); else NVGS_SCATTER(kSortBlock, false);
+    }
+#undef NVGS_SCATTER
     first = false;
     std::swap(kin, kout);
     std::swap(vin, vout);
     in_tmp = !in_tmp;
   }
   *result_in_tmp = in_tmp;
+  if (gather && !big) {
+    const unsigned ggrid = (unsigned)std::min<int64_t>((cap + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_sort_gather, dim3(ggrid), dim3(256), 0, st, in_tmp ? vals_tmp : vals, n_dev, cap, *gather);
+  }
   return hipGetLastError();
 }
 

@@ -34,6 +34,10 @@ def test_sort_and_binning_bytes():
     assert abs(bench.stage_roof("depth_sort", 1.0, st, 64, "fp32", 3, 1)["achieved"] - 64e6 / 1e-3 / 1e9) < 1e-6
     assert abs(bench.stage_roof("bin", 1.0, st, 64, "fp32", 3, 1)["achieved"] - 24e6 / 1e-3 / 1e9) < 1e-6
     assert abs(bench.stage_roof("tile_sort", 1.0, st, 64, "fp32", 3, 1)["achieved"] - 96e6 / 1e-3 / 1e9) < 1e-6
+    # as built: four radix passes, the last also moving the rectangle and count (96 B per splat);
+    # binning: the count scan and the emitter (28 B per splat) + 8 B per entry
+    assert abs(bench.stage_roof("depth_sort", 1.0, st, 64, "fp32", 3, 1)["impl_achieved"] - 96e6 / 1e-3 / 1e9) < 1e-6
+    assert abs(bench.stage_roof("bin", 1.0, st, 64, "fp32", 3, 1)["impl_achieved"] - 52e6 / 1e-3 / 1e9) < 1e-6
 
 
 @pytest.mark.parametrize("keys,passes", [(255, 1), (256, 1), (257, 2), (32400, 2), (65536, 2), (65537, 3),
