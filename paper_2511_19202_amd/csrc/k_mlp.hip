@@ -480,10 +480,7 @@ struct Mfma<NVGS_PREC_FP8> {
     Op r;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      // the first conversion fills the low half of the word and keeps the
-      // high half of its third operand, which the second one overwrites: any
-      // live register serves there (a constant 0 would cost a move)
-      int w = __builtin_amdgcn_cvt_pk_fp8_f32(v[4 * q], v[4 * q + 1], __float_as_int(v[4 * q]), false);
+      int w = __builtin_amdgcn_cvt_pk_fp8_f32(v[4 * q], v[4 * q + 1], 0, false);
       r[q] = __builtin_amdgcn_cvt_pk_fp8_f32(v[4 * q + 2], v[4 * q + 3], w, true);
     }
     return r;
